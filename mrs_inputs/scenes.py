@@ -1,0 +1,414 @@
+"""Seeded synthetic scene generators.
+
+These produce the inputs shared by the GPU renderer and the FP64 reference
+renderer: triangle soups with per-corner shading normals, a material table,
+quad area lights, a constant environment and a pinhole camera.  Nothing here
+computes light transport; the module only builds geometry and draws scene
+parameters from numpy's seeded PCG64 generator.
+
+The paper renders Blender community scenes with Cycles (Sec. 3.1, 3.2); those
+assets are not available, so procedural scenes with the same kind of content
+(closed rooms, curved displaced objects, boxes, area lights, an environment)
+stand in for them.
+"""
+from __future__ import annotations
+
+import hashlib
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# Material kinds (mirrors the C ABI enum mrs_material_kind).
+LAMBERT = 0
+GGX = 1
+EMITTER = 2  # pure emitter: no BSDF, the path ends on it
+
+# Per-triangle flags.
+FLAG_SMOOTH = 1  # use the interpolated per-corner normals for shading
+
+MATERIAL_DTYPE = np.dtype(
+    [("kind", "<i4"), ("color", "<f4", (3,)), ("alpha", "<f4"), ("emission", "<f4", (3,))],
+    align=True,
+)
+LIGHT_DTYPE = np.dtype(
+    [
+        ("corner", "<f4", (3,)),
+        ("edge_u", "<f4", (3,)),
+        ("edge_v", "<f4", (3,)),
+        ("emission", "<f4", (3,)),
+        ("tri", "<i4", (2,)),
+    ],
+    align=True,
+)
+assert MATERIAL_DTYPE.itemsize == 32
+assert LIGHT_DTYPE.itemsize == 56
+
+
+@dataclass
+class Camera:
+    pos: tuple
+    look_at: tuple
+    up: tuple = (0.0, 1.0, 0.0)
+    vfov_deg: float = 40.0
+
+
+@dataclass
+class Scene:
+    vertices: np.ndarray  # float32 [N, 3, 3]  (triangle, corner, xyz)
+    normals: np.ndarray  # float32 [N, 3, 3]  per-corner shading normals
+    tri_material: np.ndarray  # uint32 [N]
+    tri_flags: np.ndarray  # uint32 [N]
+    materials: np.ndarray  # MATERIAL_DTYPE [M]
+    lights: np.ndarray  # LIGHT_DTYPE [L]
+    env: np.ndarray  # float32 [3]
+    camera: Camera
+    name: str = "scene"
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def num_tris(self) -> int:
+        return int(self.vertices.shape[0])
+
+    def content_hash(self) -> str:
+        h = hashlib.sha256()
+        for a in (self.vertices, self.normals, self.tri_material, self.tri_flags,
+                  self.materials, self.lights, self.env):
+            h.update(np.ascontiguousarray(a).tobytes())
+        c = self.camera
+        h.update(np.asarray(list(c.pos) + list(c.look_at) + list(c.up) + [c.vfov_deg],
+                            dtype=np.float32).tobytes())
+        return h.hexdigest()
+
+
+class _Builder:
+    """Accumulates triangles, materials and lights."""
+
+    def __init__(self):
+        self.v, self.n, self.m, self.f = [], [], [], []
+        self.mats = []
+        self.lights = []
+
+    def material(self, kind, color=(0, 0, 0), alpha=0.0, emission=(0, 0, 0)) -> int:
+        self.mats.append((kind, tuple(float(x) for x in color), float(alpha),
+                          tuple(float(x) for x in emission)))
+        return len(self.mats) - 1
+
+    @property
+    def ntris(self):
+        return sum(len(x) for x in self.v)
+
+    def add_tris(self, verts, mat, normals=None):
+        verts = np.asarray(verts, dtype=np.float32).reshape(-1, 3, 3)
+        first = self.ntris
+        self.v.append(verts)
+        if normals is None:
+            self.n.append(np.zeros_like(verts))
+            self.f.append(np.zeros(len(verts), np.uint32))
+        else:
+            self.n.append(np.asarray(normals, np.float32).reshape(-1, 3, 3))
+            self.f.append(np.full(len(verts), FLAG_SMOOTH, np.uint32))
+        self.m.append(np.full(len(verts), mat, np.uint32))
+        return first
+
+    def add_quad(self, corner, eu, ev, mat):
+        """Two triangles (c, c+eu, c+eu+ev), (c, c+eu+ev, c+ev); front face along eu x ev."""
+        c = np.asarray(corner, np.float64)
+        eu = np.asarray(eu, np.float64)
+        ev = np.asarray(ev, np.float64)
+        t = np.array([[c, c + eu, c + eu + ev], [c, c + eu + ev, c + ev]])
+        return self.add_tris(t, mat)
+
+    def add_light(self, corner, eu, ev, emission):
+        mat = self.material(EMITTER, emission=emission)
+        # Store the light exactly as the float32 values of its geometry.
+        c32 = np.asarray(corner, np.float32)
+        eu32 = np.asarray(eu, np.float32)
+        ev32 = np.asarray(ev, np.float32)
+        t0 = self.add_quad(c32, eu32, ev32, mat)
+        self.lights.append((c32, eu32, ev32, np.asarray(emission, np.float32), (t0, t0 + 1)))
+        return mat
+
+    def add_box(self, center, size, yaw, mat, outward=True):
+        """Axis box of `size` rotated by `yaw` radians about +y, 12 triangles."""
+        sx, sy, sz = (0.5 * float(s) for s in size)
+        corners = np.array([[x, y, z] for x in (-sx, sx) for y in (-sy, sy) for z in (-sz, sz)])
+        cy, sn = np.cos(yaw), np.sin(yaw)
+        rot = np.array([[cy, 0, sn], [0, 1, 0], [-sn, 0, cy]])
+        P = corners @ rot.T + np.asarray(center, np.float64)
+        # index = 4*ix + 2*iy + iz
+        faces = [
+            (0, 1, 3, 2),  # -x
+            (4, 6, 7, 5),  # +x
+            (0, 4, 5, 1),  # -y
+            (2, 3, 7, 6),  # +y
+            (0, 2, 6, 4),  # -z
+            (1, 5, 7, 3),  # +z
+        ]
+        tris = []
+        for a, b, c, d in faces:
+            quad = [(a, b, c), (a, c, d)]
+            for tri in quad:
+                t = P[list(tri)]
+                if not outward:
+                    t = t[[0, 2, 1]]
+                tris.append(t)
+        tris = np.array(tris)
+        # make the winding outward (or inward) by checking against the centre
+        ctr = np.asarray(center, np.float64)
+        for i in range(len(tris)):
+            ng = np.cross(tris[i, 1] - tris[i, 0], tris[i, 2] - tris[i, 0])
+            out = np.dot(ng, tris[i].mean(0) - ctr) > 0
+            if out != outward:
+                tris[i] = tris[i][[0, 2, 1]]
+        return self.add_tris(tris, mat)
+
+    def build(self, env, camera, name, meta=None) -> Scene:
+        if self.v:
+            V = np.concatenate(self.v).astype(np.float32)
+            N = np.concatenate(self.n).astype(np.float32)
+            M = np.concatenate(self.m).astype(np.uint32)
+            F = np.concatenate(self.f).astype(np.uint32)
+        else:
+            V = np.zeros((0, 3, 3), np.float32)
+            N = np.zeros((0, 3, 3), np.float32)
+            M = np.zeros((0,), np.uint32)
+            F = np.zeros((0,), np.uint32)
+        mats = np.zeros(max(len(self.mats), 0), MATERIAL_DTYPE)
+        for i, (k, col, a, e) in enumerate(self.mats):
+            mats[i]["kind"] = k
+            mats[i]["color"] = col
+            mats[i]["alpha"] = a
+            mats[i]["emission"] = e
+        lights = np.zeros(len(self.lights), LIGHT_DTYPE)
+        for i, (c, eu, ev, le, tri) in enumerate(self.lights):
+            lights[i]["corner"] = c
+            lights[i]["edge_u"] = eu
+            lights[i]["edge_v"] = ev
+            lights[i]["emission"] = le
+            lights[i]["tri"] = tri
+        return Scene(V, N, M, F, mats, lights, np.asarray(env, np.float32), camera, name,
+                     meta or {})
+
+
+# --------------------------------------------------------------------------- icospheres
+
+def icosphere(subdiv: int):
+    """Unit icosphere: (vertices [V,3] float64, faces [F,3] int64), outward winding."""
+    t = (1.0 + 5.0 ** 0.5) / 2.0
+    V = np.array([
+        [-1, t, 0], [1, t, 0], [-1, -t, 0], [1, -t, 0],
+        [0, -1, t], [0, 1, t], [0, -1, -t], [0, 1, -t],
+        [t, 0, -1], [t, 0, 1], [-t, 0, -1], [-t, 0, 1],
+    ], dtype=np.float64)
+    V /= np.linalg.norm(V, axis=1, keepdims=True)
+    F = np.array([
+        [0, 11, 5], [0, 5, 1], [0, 1, 7], [0, 7, 10], [0, 10, 11],
+        [1, 5, 9], [5, 11, 4], [11, 10, 2], [10, 7, 6], [7, 1, 8],
+        [3, 9, 4], [3, 4, 2], [3, 2, 6], [3, 6, 8], [3, 8, 9],
+        [4, 9, 5], [2, 4, 11], [6, 2, 10], [8, 6, 7], [9, 8, 1],
+    ], dtype=np.int64)
+    for _ in range(subdiv):
+        a, b, c = F[:, 0], F[:, 1], F[:, 2]
+        edges = np.stack([np.stack([a, b], 1), np.stack([b, c], 1), np.stack([c, a], 1)], 1)
+        es = np.sort(edges.reshape(-1, 2), axis=1)
+        uniq, inv = np.unique(es, axis=0, return_inverse=True)
+        inv = inv.reshape(-1)
+        mid = V[uniq[:, 0]] + V[uniq[:, 1]]
+        mid /= np.linalg.norm(mid, axis=1, keepdims=True)
+        base = len(V)
+        V = np.concatenate([V, mid])
+        m = (inv + base).reshape(-1, 3)
+        mab, mbc, mca = m[:, 0], m[:, 1], m[:, 2]
+        F = np.concatenate([
+            np.stack([a, mab, mca], 1),
+            np.stack([b, mbc, mab], 1),
+            np.stack([c, mca, mbc], 1),
+            np.stack([mab, mbc, mca], 1),
+        ])
+    # ensure outward winding
+    ng = np.cross(V[F[:, 1]] - V[F[:, 0]], V[F[:, 2]] - V[F[:, 0]])
+    flip = np.einsum("ij,ij->i", ng, V[F].mean(1)) < 0
+    F[flip] = F[flip][:, [0, 2, 1]]
+    return V, F
+
+
+def vertex_normals(V, F):
+    """Area-weighted vertex normals of an indexed mesh (float64, unit length)."""
+    ng = np.cross(V[F[:, 1]] - V[F[:, 0]], V[F[:, 2]] - V[F[:, 0]])
+    acc = np.zeros_like(V)
+    for k in range(3):
+        np.add.at(acc, F[:, k], ng)
+    return acc / np.linalg.norm(acc, axis=1, keepdims=True)
+
+
+def _displaced_sphere(rng, subdiv, radius, center_xz):
+    V, F = icosphere(subdiv)
+    k = rng.uniform(2.0, 4.0, 3)
+    ph = rng.uniform(0.0, 2.0 * np.pi, 3)
+    disp = 0.15 * radius * np.prod(np.sin(k[None, :] * V + ph[None, :]), axis=1)
+    P = V * radius + V * disp[:, None]
+    P[:, 1] -= P[:, 1].min()  # rest on the ground y = 0
+    P[:, 0] += center_xz[0]
+    P[:, 2] += center_xz[1]
+    N = vertex_normals(P, F)
+    return P[F], N[F]
+
+
+def _random_material(rng, b: _Builder):
+    if rng.uniform() < 0.5:
+        return b.material(LAMBERT, color=rng.uniform(0.2, 0.8, 3))
+    return b.material(GGX, color=rng.uniform(0.5, 0.95, 3), alpha=rng.uniform(0.05, 0.8))
+
+
+# --------------------------------------------------------------------------- named scenes
+
+def cornell(seed: int = 1) -> Scene:
+    """Cornell-style box: 5 walls (10 tris), two boxes (24 tris), one quad light (2 tris).
+
+    Lambertian albedo is drawn per object and channel from U[0.2, 0.8]; the light
+    has emission 15.  36 triangles in total.
+    """
+    rng = np.random.default_rng(seed)
+    b = _Builder()
+    walls = [
+        # floor y=0 (normal +y), ceiling y=1 (-y), back z=1 (-z), left x=0 (+x), right x=1 (-x)
+        ((0, 0, 0), (0, 0, 1), (1, 0, 0)),
+        ((0, 1, 0), (1, 0, 0), (0, 0, 1)),
+        ((0, 0, 1), (0, 1, 0), (1, 0, 0)),
+        ((0, 0, 0), (0, 1, 0), (0, 0, 1)),
+        ((1, 0, 0), (0, 0, 1), (0, 1, 0)),
+    ]
+    for c, eu, ev in walls:
+        b.add_quad(c, eu, ev, b.material(LAMBERT, color=rng.uniform(0.2, 0.8, 3)))
+    b.add_box((0.68, 0.15, 0.32), (0.3, 0.3, 0.3), np.deg2rad(-18.0),
+              b.material(LAMBERT, color=rng.uniform(0.2, 0.8, 3)))
+    b.add_box((0.32, 0.30, 0.62), (0.3, 0.6, 0.3), np.deg2rad(18.0),
+              b.material(LAMBERT, color=rng.uniform(0.2, 0.8, 3)))
+    b.add_light((0.375, 0.999, 0.375), (0.25, 0.0, 0.0), (0.0, 0.0, 0.25), (15.0, 15.0, 15.0))
+    cam = Camera((0.5, 0.5, -1.2), (0.5, 0.5, 0.5), (0.0, 1.0, 0.0), 40.0)
+    return b.build((0.0, 0.0, 0.0), cam, f"cornell_{seed}", {"seed": seed})
+
+
+def procedural(seed: int = 7, spheres=((4, 5), (3, 4)), n_boxes: int = 20,
+               n_lights: int = 3, env: float = 0.2) -> Scene:
+    """Ground plane, displaced icospheres, boxes and quad lights.
+
+    `spheres` lists (count, subdivision level) groups.  The defaults give
+    2 + 4*20480 + 3*5120 + 20*12 + 3*2 = 97,528 triangles.  Each non-light
+    object is Lambertian (albedo U[0.2, 0.8]^3) or GGX (F0 U[0.5, 0.95]^3,
+    roughness U[0.05, 0.8]) with probability 1/2.
+    """
+    rng = np.random.default_rng(seed)
+    b = _Builder()
+    b.add_quad((-20.0, 0.0, -20.0), (0.0, 0.0, 40.0), (40.0, 0.0, 0.0), _random_material(rng, b))
+    for count, subdiv in spheres:
+        for _ in range(count):
+            r = rng.uniform(0.5, 1.5)
+            cxz = rng.uniform(-4.0, 4.0, 2)
+            P, N = _displaced_sphere(rng, subdiv, r, cxz)
+            b.add_tris(P, _random_material(rng, b), normals=N)
+    for _ in range(n_boxes):
+        size = rng.uniform(0.2, 1.0, 3)
+        cxz = rng.uniform(-4.0, 4.0, 2)
+        b.add_box((cxz[0], size[1] / 2, cxz[1]), size, rng.uniform(0, 2 * np.pi),
+                  _random_material(rng, b))
+    for _ in range(n_lights):
+        a, w = rng.uniform(0.5, 1.5, 2)
+        h = rng.uniform(4.0, 6.0)
+        cxz = rng.uniform(-3.0, 3.0, 2)
+        inten = rng.uniform(10.0, 30.0)
+        col = rng.uniform(0.8, 1.0, 3)
+        b.add_light((cxz[0] - a / 2, h, cxz[1] - w / 2), (a, 0, 0), (0, 0, w), inten * col)
+    cam = Camera((0.0, 3.0, 10.0), (0.0, 0.8, 0.0), (0.0, 1.0, 0.0), 40.0)
+    return b.build((env, env, env), cam, f"procedural_{seed}", {"seed": seed})
+
+
+def sphere_plan(target_tris: int):
+    """(count, level) groups whose icosphere triangles approximate `target_tris`."""
+    budget = max(int(target_tris) - 2 - 20 * 12 - 3 * 2, 320)
+    plan = []
+    for level in (7, 6, 5, 4, 3, 2):
+        nt = 20 * 4 ** level
+        c = 0
+        while budget >= nt and c < 6:
+            c += 1
+            budget -= nt
+        if c:
+            plan.append((c, level))
+    return tuple(plan) or ((1, 2),)
+
+
+def procedural_sized(seed: int, target_tris: int) -> Scene:
+    """Procedural scene whose triangle count approximates `target_tris`."""
+    sc = procedural(seed, spheres=sphere_plan(target_tris))
+    sc.name = f"procedural_sized_{seed}_{target_tris}"
+    sc.meta = {"seed": seed, "target_tris": int(target_tris)}
+    return sc
+
+
+def furnace_sphere(emission: float = 1.0, rho: float = 0.5, subdiv: int = 2) -> Scene:
+    """Closed, inward-facing flat-shaded sphere of emissive Lambertian triangles.
+
+    The emitters are not in the light list, so they are found only by BSDF rays.
+    The camera sits at the centre.
+    """
+    V, F = icosphere(subdiv)
+    tris = V[F][:, [0, 2, 1]] * 2.0  # flip the winding: front faces look inward
+    b = _Builder()
+    m = b.material(LAMBERT, color=(rho, rho, rho), emission=(emission, emission, emission))
+    b.add_tris(tris, m)
+    cam = Camera((0.1, -0.05, 0.07), (0.3, 0.2, 1.0), (0.0, 1.0, 0.0), 60.0)
+    return b.build((0.0, 0.0, 0.0), cam, "furnace", {"E": emission, "rho": rho})
+
+
+def env_only(env=(0.3, 0.5, 0.7)) -> Scene:
+    """No geometry at all: every camera ray misses."""
+    b = _Builder()
+    cam = Camera((0.0, 0.0, 0.0), (0.0, 0.0, 1.0), (0.0, 1.0, 0.0), 50.0)
+    return b.build(env, cam, "env_only")
+
+
+def lambert_plane(rho=(0.25, 0.5, 0.75), env=(1.0, 0.5, 0.25)) -> Scene:
+    """A large Lambertian plane under a constant environment, seen from above."""
+    b = _Builder()
+    b.add_quad((-1000.0, 0.0, -1000.0), (0.0, 0.0, 2000.0), (2000.0, 0.0, 0.0),
+               b.material(LAMBERT, color=rho))
+    cam = Camera((0.0, 1.0, 0.0), (0.0, 0.0, 0.5), (0.0, 1.0, 0.0), 60.0)
+    return b.build(env, cam, "lambert_plane")
+
+
+def nee_config(rho=0.5, le=10.0, a=1.0, bb=2.0, c=1.5) -> Scene:
+    """Floor plus a parallel a x bb rectangular light at height c, one corner above the origin.
+
+    The camera looks straight down at the origin with a tiny field of view.
+    """
+    b = _Builder()
+    b.add_quad((-50.0, 0.0, -50.0), (0.0, 0.0, 100.0), (100.0, 0.0, 0.0),
+               b.material(LAMBERT, color=(rho, rho, rho)))
+    b.add_light((0.0, c, 0.0), (a, 0.0, 0.0), (0.0, 0.0, bb), (le, le, le))
+    cam = Camera((0.0, c * 0.5, 0.0), (0.0, 0.0, 0.0), (0.0, 0.0, 1.0), 0.01)
+    return b.build((0.0, 0.0, 0.0), cam, "nee_config",
+                   {"rho": rho, "le": le, "a": a, "b": bb, "c": c})
+
+
+def random_soup(seed: int, n: int, spread: float = 1.0) -> Scene:
+    """Random triangles in a cube (intersection / BVH tests)."""
+    rng = np.random.default_rng(seed)
+    b = _Builder()
+    centers = rng.uniform(-spread, spread, (n, 1, 3))
+    tris = centers + rng.normal(0, 0.2 * spread, (n, 3, 3))
+    m = b.material(LAMBERT, color=(0.5, 0.5, 0.5))
+    b.add_tris(tris, m)
+    cam = Camera((0.0, 0.0, -4.0 * spread), (0.0, 0.0, 0.0), (0.0, 1.0, 0.0), 45.0)
+    return b.build((0.1, 0.1, 0.1), cam, f"soup_{seed}_{n}")
+
+
+def random_rays(seed: int, n: int, spread: float = 1.0):
+    """Random float32 rays: origins in a cube of side 4*spread, aimed at points of the
+    central cube of side 2*spread (where random_soup puts its triangles)."""
+    rng = np.random.default_rng(seed + 12345)
+    o = rng.uniform(-2 * spread, 2 * spread, (n, 3))
+    tgt = rng.uniform(-spread, spread, (n, 3))
+    d = tgt - o
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    return o.astype(np.float32), d.astype(np.float32)
