@@ -1,0 +1,201 @@
+/*
+ * mrs.h -- C ABI of libmrs, a multi-resolution Monte Carlo renderer for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The library renders the two inputs of the hybrid method of "Fast Monte Carlo
+ * Rendering via Multi-Resolution Sampling" (Sec. 4): a high-resolution,
+ * low-spp image (HRLS) and a low-resolution, high-spp image (LRHS), each with
+ * albedo / normal / depth feature buffers (Sec. 4, first paragraph: HRLS carries
+ * RGB plus extra layers; LRHS carries RGB).  The images are produced by a
+ * Monte Carlo path tracer (Sec. 3.2 renders with one; Sec. 1 motivates the
+ * ray-count cost) that this library implements on the GPU.
+ *
+ * Conventions for every entry point:
+ *  - Pointers named *_dev are device pointers (HBM).  Everything else is host
+ *    memory.  Device outputs are owned by the caller (e.g. torch tensors);
+ *    the library never frees them.  *_create functions copy their host inputs,
+ *    which the caller may free on return.
+ *  - All GPU work is enqueued asynchronously on the stream set with
+ *    mrs_set_stream (default: the null stream).  Results are visible after
+ *    mrs_sync() or any later synchronisation of that stream.
+ *  - Functions return mrs_status and never throw or abort.  On failure,
+ *    mrs_last_error() returns a thread-local message.  Arguments are validated
+ *    before any work is enqueued: a call that fails validation writes nothing.
+ *    Asynchronous device faults are reported by the next call or by mrs_sync.
+ *  - Images are row-major, row 0 at the top, channels interleaved (HWC), FP32.
+ *  - Destroy functions accept NULL.
+ */
+#ifndef MRS_H_
+#define MRS_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum mrs_status {
+  MRS_OK = 0,
+  MRS_ERR_INVALID_ARGUMENT = 1,
+  MRS_ERR_OUT_OF_MEMORY = 2,
+  MRS_ERR_DEVICE = 3,
+  MRS_ERR_NOT_READY = 4,
+  MRS_ERR_UNSUPPORTED = 5
+} mrs_status;
+
+/* ------------------------------------------------------------------ scenes */
+
+typedef enum mrs_material_kind {
+  MRS_LAMBERT = 0, /* f = color / pi */
+  MRS_GGX = 1,     /* GGX microfacet reflection (Walter et al. 2007), F0 = color,
+                      roughness alpha, separable Smith G, Schlick Fresnel */
+  MRS_EMITTER = 2  /* pure emitter: no BSDF; a path ends on it */
+} mrs_material_kind;
+
+/* 32 bytes.  Any kind may also emit `emission` from its front face. */
+typedef struct mrs_material {
+  int32_t kind;
+  float color[3];
+  float alpha;
+  float emission[3];
+} mrs_material;
+
+/* 56 bytes.  Parallelogram light y = corner + u*edge_u + v*edge_v, u,v in
+ * [0,1); it emits from the side edge_u x edge_v points to.  tri[] names the
+ * two scene triangles that carry its geometry; those triangles are excluded
+ * from its shadow rays and do not add emission when reached by a BSDF ray
+ * (next-event estimation accounts for them). */
+typedef struct mrs_quad_light {
+  float corner[3];
+  float edge_u[3];
+  float edge_v[3];
+  float emission[3];
+  int32_t tri[2];
+} mrs_quad_light;
+
+/* Pinhole camera.  Forward f = normalize(look_at - pos), right r =
+ * normalize(f x up), vertical v = r x f, vfov_deg the full vertical angle. */
+typedef struct mrs_camera {
+  float pos[3];
+  float look_at[3];
+  float up[3];
+  float vfov_deg;
+} mrs_camera;
+
+#define MRS_TRI_SMOOTH 1u /* shade with the interpolated per-corner normals */
+
+typedef struct mrs_scene_desc {
+  int32_t num_tris;             /* >= 0; 0 gives an environment-only scene */
+  const float* vertices;        /* host, num_tris*9: v0, v1, v2 (xyz each) */
+  const float* normals;         /* host, num_tris*9 per-corner normals, or NULL */
+  const uint32_t* tri_material; /* host, num_tris indices into materials */
+  const uint32_t* tri_flags;    /* host, num_tris MRS_TRI_* bits, or NULL */
+  int32_t num_materials;
+  const mrs_material* materials;
+  int32_t num_lights; /* 0..255 */
+  const mrs_quad_light* lights;
+  float env[3]; /* constant environment radiance seen by rays that miss */
+  mrs_camera camera;
+} mrs_scene_desc;
+
+typedef struct mrs_scene mrs_scene; /* opaque: device copy of the scene + LBVH */
+
+/* Thread-local message of the last failed call ("" if none). */
+const char* mrs_last_error(void);
+
+/* Stream for all later work of this thread (a hipStream_t; NULL = null stream). */
+mrs_status mrs_set_stream(void* hip_stream);
+
+/* Wait for all work on the current stream; reports asynchronous faults. */
+mrs_status mrs_sync(void);
+
+/* Copies the scene to the device.  Fails with INVALID_ARGUMENT on NULL arrays
+ * (when num_tris > 0), material or light indices out of range, or non-finite
+ * vertices; OUT_OF_MEMORY if device allocation fails. */
+mrs_status mrs_scene_create(const mrs_scene_desc* desc, mrs_scene** out);
+mrs_status mrs_scene_destroy(mrs_scene* scene);
+
+/* Builds the linear BVH of Karras (HPG 2012) on the device: 30-bit Morton codes
+ * of triangle centroids in the centroid bounds, keys (morton << 32 | prim)
+ * sorted by a device radix sort, one internal node per adjacent key pair from
+ * common-prefix lengths, leaf-to-root box refit with atomic visit counters.
+ * Idempotent.  Enqueued on the current stream. */
+mrs_status mrs_build_bvh(mrs_scene* scene);
+
+/* Renders W x H pixels at spp samples each, paths of at most max_depth bounces
+ * (vertex 0 is the camera hit; next-event estimation at vertices
+ * 0..max_depth-1), Russian roulette from vertex 3, Philox4x32-10 random
+ * numbers keyed by seed and counted by (pixel, sample, dimension).
+ *   out_rgb_dev  H*W*3 FP32: per-pixel mean radiance over the samples, summed
+ *                in sample order (FP64 sums when spp >= 1024, FP32 below).
+ *   out_aux_dev  H*W*7 FP32 or NULL: mean first-hit albedo (3), shading normal
+ *                facing the camera (3) and hit distance (1); zeros on a miss.
+ * Limits: 1 <= W, H <= 16384, 1 <= spp <= 2^20, 0 <= max_depth <= 64, outputs
+ * 4-byte aligned.  NOT_READY if the BVH has not been built. */
+mrs_status mrs_render(const mrs_scene* scene, int32_t W, int32_t H, int32_t spp,
+                      int32_t max_depth, uint64_t seed, float* out_rgb_dev, float* out_aux_dev);
+
+typedef struct mrs_render_opts {
+  int32_t rr_start;   /* first vertex with Russian roulette (default 3) */
+  int32_t x0, y0;     /* window origin in the W x H image (default 0, 0) */
+  int32_t win_w;      /* window size; 0 = the whole image */
+  int32_t win_h;
+  int32_t accum_fp64; /* -1 auto (spp >= 1024), 0 FP32 sums, 1 FP64 sums */
+  float* out_sumsq_dev; /* optional win_h*win_w*3: sum over samples of L^2 */
+} mrs_render_opts;
+
+/* Fills `opts` with the defaults listed above. */
+void mrs_render_opts_default(mrs_render_opts* opts);
+
+/* mrs_render with options.  A window renders pixels (x0..x0+win_w-1,
+ * y0..y0+win_h-1) of the W x H image into win_h*win_w outputs; random numbers
+ * use full-image pixel indices, so a window is bitwise a crop of the full
+ * image. */
+mrs_status mrs_render_ex(const mrs_scene* scene, int32_t W, int32_t H, int32_t spp,
+                         int32_t max_depth, uint64_t seed, const mrs_render_opts* opts,
+                         float* out_rgb_dev, float* out_aux_dev);
+
+/* Counters accumulated since the last reset (synchronises the stream):
+ * [0] non-finite samples replaced by 0, [1] closest-hit rays, [2] shadow rays,
+ * [3] traversal stack entries spilled from LDS to global memory,
+ * [4] paths started, [5] stack overflows (must be 0). */
+#define MRS_NUM_COUNTERS 8
+mrs_status mrs_get_counters(int64_t out[MRS_NUM_COUNTERS], int32_t reset);
+
+/* Tuning knobs (performance only; results do not depend on them). */
+typedef struct mrs_tuning {
+  int32_t chunk_paths;  /* paths resident at once (default 1<<22) */
+  int32_t trace_blocks; /* grid size of traversal kernels (default 2048) */
+} mrs_tuning;
+mrs_status mrs_get_tuning(mrs_tuning* out);
+mrs_status mrs_set_tuning(const mrs_tuning* t);
+
+/* ------------------------------------------------------- debug / test hooks */
+
+/* Philox4x32-10 on the device: out_dev[4i..4i+3] = philox(ctr_dev[4i..4i+3],
+ * key_dev[2i..2i+1]) for i < n.  For bitwise checks against the host. */
+mrs_status mrs_debug_philox(int32_t n, const uint32_t* ctr_dev, const uint32_t* key_dev,
+                            uint32_t* out_dev);
+
+/* Closest hit through the LBVH for n rays: origins/directions as xyz float
+ * triples, skip_dev[i] a primitive to exclude (-1 for none) or NULL.
+ * Writes t (inf on a miss), primitive (-1 on a miss) and barycentrics b1, b2. */
+mrs_status mrs_debug_closest_hit(const mrs_scene* scene, int32_t n, const float* o_dev,
+                                 const float* d_dev, const int32_t* skip_dev, float* t_dev,
+                                 int32_t* prim_dev, float* b_dev);
+
+/* Copies the LBVH to host memory for invariant checks.  nodes_host receives
+ * (num_tris-1) records of 16 floats: left box lo xyz, hi xyz, right box lo
+ * xyz, hi xyz, then left/right child references as uint32 bit patterns (bit 31
+ * set = leaf, low bits = leaf slot), 2 pad words.  leaf_prim_host receives
+ * num_tris primitive ids in leaf order; morton_host the sorted Morton codes.
+ * Any pointer may be NULL.  Synchronises. */
+mrs_status mrs_debug_bvh(const mrs_scene* scene, float* nodes_host, int32_t* leaf_prim_host,
+                         uint32_t* morton_host, int32_t* root_ref_host);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MRS_H_ */

@@ -1,0 +1,164 @@
+"""ctypes binding of libmrs (include/mrs.h).
+
+Argument marshalling only: every step of the rendering runs in the library's
+HIP kernels.  torch tensors supply device memory and the stream.  Importing this
+module does not touch the GPU; loading the library fails loudly if it has not
+been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmrs.so")
+
+MRS_OK = 0
+STATUS_NAMES = {0: "OK", 1: "INVALID_ARGUMENT", 2: "OUT_OF_MEMORY", 3: "DEVICE", 4: "NOT_READY",
+                5: "UNSUPPORTED"}
+NUM_COUNTERS = 8
+
+
+class MrsError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Material(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("color", C.c_float * 3), ("alpha", C.c_float),
+                ("emission", C.c_float * 3)]
+
+
+class QuadLight(C.Structure):
+    _fields_ = [("corner", C.c_float * 3), ("edge_u", C.c_float * 3), ("edge_v", C.c_float * 3),
+                ("emission", C.c_float * 3), ("tri", C.c_int32 * 2)]
+
+
+class Camera(C.Structure):
+    _fields_ = [("pos", C.c_float * 3), ("look_at", C.c_float * 3), ("up", C.c_float * 3),
+                ("vfov_deg", C.c_float)]
+
+
+class SceneDesc(C.Structure):
+    _fields_ = [("num_tris", C.c_int32), ("vertices", C.c_void_p), ("normals", C.c_void_p),
+                ("tri_material", C.c_void_p), ("tri_flags", C.c_void_p),
+                ("num_materials", C.c_int32), ("materials", C.c_void_p),
+                ("num_lights", C.c_int32), ("lights", C.c_void_p), ("env", C.c_float * 3),
+                ("camera", Camera)]
+
+
+class RenderOpts(C.Structure):
+    _fields_ = [("rr_start", C.c_int32), ("x0", C.c_int32), ("y0", C.c_int32),
+                ("win_w", C.c_int32), ("win_h", C.c_int32), ("accum_fp64", C.c_int32),
+                ("out_sumsq_dev", C.c_void_p)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("chunk_paths", C.c_int32), ("trace_blocks", C.c_int32)]
+
+
+assert C.sizeof(Material) == 32 and C.sizeof(QuadLight) == 56
+
+_lib = None
+
+
+def lib():
+    """Load libmrs.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libmrs.so not found at {LIB_PATH}: run __graft_entry__.build() "
+                           "(the HIP library is required; there is no fallback)")
+    L = C.CDLL(LIB_PATH)
+    P, I32, U64 = C.c_void_p, C.c_int32, C.c_uint64
+    sigs = {
+        "mrs_last_error": ([], C.c_char_p),
+        "mrs_set_stream": ([P], I32),
+        "mrs_sync": ([], I32),
+        "mrs_scene_create": ([C.POINTER(SceneDesc), C.POINTER(P)], I32),
+        "mrs_scene_destroy": ([P], I32),
+        "mrs_build_bvh": ([P], I32),
+        "mrs_render": ([P, I32, I32, I32, I32, U64, P, P], I32),
+        "mrs_render_opts_default": ([C.POINTER(RenderOpts)], None),
+        "mrs_render_ex": ([P, I32, I32, I32, I32, U64, C.POINTER(RenderOpts), P, P], I32),
+        "mrs_get_counters": ([P, I32], I32),
+        "mrs_get_tuning": ([C.POINTER(Tuning)], I32),
+        "mrs_set_tuning": ([C.POINTER(Tuning)], I32),
+        "mrs_debug_philox": ([I32, P, P, P], I32),
+        "mrs_debug_closest_hit": ([P, I32, P, P, P, P, P, P], I32),
+        "mrs_debug_bvh": ([P, P, P, P, P], I32),
+    }
+    for name, (args, res) in sigs.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = L
+    return L
+
+
+def check(status: int):
+    if status != MRS_OK:
+        msg = lib().mrs_last_error()
+        raise MrsError(status, msg.decode() if msg else "")
+
+
+def exported_symbols():
+    return [
+        "mrs_last_error", "mrs_set_stream", "mrs_sync", "mrs_scene_create", "mrs_scene_destroy",
+        "mrs_build_bvh", "mrs_render", "mrs_render_opts_default", "mrs_render_ex",
+        "mrs_get_counters", "mrs_get_tuning", "mrs_set_tuning", "mrs_debug_philox",
+        "mrs_debug_closest_hit", "mrs_debug_bvh",
+    ]
+
+
+def ptr(t) -> int | None:
+    """Device pointer of a torch tensor (None passes through)."""
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t.data_ptr()
+
+
+def use_current_stream():
+    """Route library work to torch's current stream on the current device."""
+    import torch
+    check(lib().mrs_set_stream(C.c_void_p(torch.cuda.current_stream().cuda_stream)))
+
+
+def scene_desc(scene):
+    """Build a SceneDesc from a scene object (numpy arrays); returns (desc, keepalive)."""
+    keep = []
+
+    def arr(a, dt):
+        a = np.ascontiguousarray(a, dtype=dt)
+        keep.append(a)
+        return a.ctypes.data_as(C.c_void_p) if a.size else None
+
+    d = SceneDesc()
+    n = int(scene.vertices.shape[0])
+    d.num_tris = n
+    d.vertices = arr(scene.vertices.reshape(-1), np.float32)
+    d.normals = arr(scene.normals.reshape(-1), np.float32) if scene.normals is not None else None
+    d.tri_material = arr(scene.tri_material, np.uint32)
+    d.tri_flags = arr(scene.tri_flags, np.uint32) if scene.tri_flags is not None else None
+    mats = np.ascontiguousarray(scene.materials)
+    lights = np.ascontiguousarray(scene.lights)
+    keep += [mats, lights]
+    d.num_materials = len(mats)
+    d.materials = mats.ctypes.data_as(C.c_void_p) if len(mats) else None
+    d.num_lights = len(lights)
+    d.lights = lights.ctypes.data_as(C.c_void_p) if len(lights) else None
+    for i in range(3):
+        d.env[i] = float(scene.env[i])
+    cam = scene.camera
+    for i in range(3):
+        d.camera.pos[i] = cam.pos[i]
+        d.camera.look_at[i] = cam.look_at[i]
+        d.camera.up[i] = cam.up[i]
+    d.camera.vfov_deg = cam.vfov_deg
+    return d, keep

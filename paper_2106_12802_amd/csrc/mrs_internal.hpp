@@ -1,0 +1,114 @@
+// Internal declarations shared by the libmrs translation units (GPU side only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "mrs.h"
+
+namespace mrs {
+
+// ------------------------------------------------------------------ errors
+void set_error(const std::string& msg);
+mrs_status fail(mrs_status st, const std::string& msg);
+mrs_status check_hip(hipError_t e, const char* what);
+hipStream_t current_stream();
+void set_stream(hipStream_t s);
+const std::string& t_error_ref();
+
+#define MRS_TRY_HIP(expr)                                       \
+  do {                                                          \
+    hipError_t e_ = (expr);                                     \
+    if (e_ != hipSuccess) return ::mrs::check_hip(e_, #expr);   \
+  } while (0)
+
+// ------------------------------------------------------------------ device scene
+constexpr uint32_t LEAF_BIT = 0x80000000u;
+constexpr uint32_t NO_PRIM = 0xffffffffu;
+constexpr int MAX_LIGHTS = 255;
+constexpr int MAX_STACK = 64;  // Karras trees over unique 64-bit keys are <= 64 deep
+
+struct DevMaterial {  // 32 B, read through the scalar/vector caches
+  float4 color_alpha; // rgb = albedo or F0, w = GGX roughness
+  float4 emis_kind;   // rgb = emission, w = kind (as float: 0, 1, 2)
+};
+
+struct DevLight {  // 80 B
+  float4 corner;   // xyz
+  float4 eu;       // xyz
+  float4 ev;       // xyz
+  float4 le;       // rgb emission
+  float4 normal;   // xyz unit normal, w = area
+  int32_t tri0, tri1, pad0, pad1;
+};
+
+struct SceneView {  // passed by value to kernels
+  int32_t ntris;
+  int32_t nlights;
+  uint32_t root;           // node index, or LEAF_BIT|0 when ntris == 1
+  const float4* nodes;     // (ntris-1)*4 float4
+  const float4* leaf_tri;  // ntris*3 float4: (v0, prim bits) (e1, -) (e2, -) in leaf order
+  const float4* prim_ng;   // ntris: unit geometric normal, w = bits(material | flags)
+  const float4* prim_n;    // ntris*3: per-corner shading normals (smooth triangles)
+  const DevMaterial* mats;
+  const DevLight* lights;
+  float env_r, env_g, env_b;
+  // camera basis (computed in FP64 on the host, rounded once)
+  float cam_px, cam_py, cam_pz;
+  float cam_fx, cam_fy, cam_fz;
+  float cam_rx, cam_ry, cam_rz;
+  float cam_vx, cam_vy, cam_vz;
+  float cam_tan_half;
+};
+
+// prim_ng.w packs: bits 0..23 material index, bit 24 smooth, bit 25 listed light
+constexpr uint32_t PRIM_SMOOTH = 1u << 24;
+constexpr uint32_t PRIM_LISTED = 1u << 25;
+constexpr uint32_t PRIM_MAT_MASK = 0x00ffffffu;
+
+}  // namespace mrs
+
+struct mrs_scene {
+  int32_t ntris = 0;
+  int32_t nmats = 0;
+  int32_t nlights = 0;
+  bool bvh_built = false;
+  // device buffers
+  float4* d_tri_src = nullptr;  // ntris*3: v0, v1, v2 in primitive order (w unused)
+  float4* d_prim_ng = nullptr;
+  float4* d_prim_n = nullptr;
+  float4* d_leaf_tri = nullptr;
+  float4* d_nodes = nullptr;
+  uint32_t* d_morton = nullptr;     // sorted codes
+  uint32_t* d_leaf_prim = nullptr;  // sorted primitive ids
+  mrs::DevMaterial* d_mats = nullptr;
+  mrs::DevLight* d_lights = nullptr;
+  mrs::SceneView view{};
+  uint32_t root = 0;
+};
+
+namespace mrs {
+// lbvh.hip
+mrs_status lbvh_build(mrs_scene* s, hipStream_t st);
+// trace.hip
+struct RenderArgs {
+  int32_t W, H, spp, max_depth, rr_start;
+  uint64_t seed;
+  int32_t x0, y0, ww, wh;
+  bool fp64;
+  float* out_rgb;
+  float* out_aux;
+  float* out_sumsq;
+};
+mrs_status render(const mrs_scene* s, const RenderArgs& a, hipStream_t st);
+mrs_status debug_closest_hit(const mrs_scene* s, int32_t n, const float* o, const float* d,
+                             const int32_t* skip, float* t, int32_t* prim, float* b,
+                             hipStream_t st);
+mrs_status debug_philox(int32_t n, const uint32_t* ctr, const uint32_t* key, uint32_t* out,
+                        hipStream_t st);
+mrs_status get_counters(int64_t* out, bool reset, hipStream_t st);
+void get_tuning(mrs_tuning* t);
+mrs_status set_tuning(const mrs_tuning* t);
+}  // namespace mrs

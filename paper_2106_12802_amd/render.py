@@ -1,0 +1,133 @@
+"""Rendering front end: device scenes and mrs_render / mrs_render_ex calls."""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib as L
+
+
+class GpuScene:
+    """A scene copied to the GPU with its LBVH built (mrs_scene_create + mrs_build_bvh)."""
+
+    def __init__(self, scene, build_bvh: bool = True):
+        import torch  # noqa: F401  (initialises the HIP runtime through torch)
+        L.use_current_stream()
+        desc, keep = L.scene_desc(scene)
+        h = C.c_void_p()
+        L.check(L.lib().mrs_scene_create(C.byref(desc), C.byref(h)))
+        del keep
+        self.handle = h
+        self.num_tris = int(scene.vertices.shape[0])
+        self.camera = scene.camera
+        if build_bvh:
+            self.build_bvh()
+
+    def build_bvh(self):
+        L.use_current_stream()
+        L.check(L.lib().mrs_build_bvh(self.handle))
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            L.lib().mrs_scene_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- debug hooks (tests)
+    def closest_hit(self, o, d, skip=None):
+        import torch
+        o = torch.as_tensor(np.ascontiguousarray(o, np.float32), device="cuda").reshape(-1, 3)
+        d = torch.as_tensor(np.ascontiguousarray(d, np.float32), device="cuda").reshape(-1, 3)
+        n = o.shape[0]
+        sk = None if skip is None else torch.as_tensor(np.asarray(skip, np.int32), device="cuda")
+        t = torch.empty(n, dtype=torch.float32, device="cuda")
+        prim = torch.empty(n, dtype=torch.int32, device="cuda")
+        b = torch.empty(n, 2, dtype=torch.float32, device="cuda")
+        L.use_current_stream()
+        L.check(L.lib().mrs_debug_closest_hit(self.handle, n, L.ptr(o), L.ptr(d), L.ptr(sk),
+                                              L.ptr(t), L.ptr(prim), L.ptr(b)))
+        torch.cuda.synchronize()
+        return t.cpu().numpy(), prim.cpu().numpy(), b.cpu().numpy()
+
+    def bvh(self):
+        n = self.num_tris
+        nodes = np.zeros((max(n - 1, 0), 16), np.float32)
+        leaf = np.zeros(n, np.int32)
+        morton = np.zeros(n, np.uint32)
+        root = C.c_int32()
+        L.use_current_stream()
+        L.check(L.lib().mrs_debug_bvh(self.handle, nodes.ctypes.data_as(C.c_void_p) if n > 1 else None,
+                                      leaf.ctypes.data_as(C.c_void_p) if n else None,
+                                      morton.ctypes.data_as(C.c_void_p) if n else None,
+                                      C.byref(root)))
+        return nodes, leaf, morton, root.value & 0xFFFFFFFF
+
+
+def render_ex(scene: GpuScene, W, H, spp, max_depth, seed, out_rgb, out_aux=None, rr_start=3,
+              window=None, accum_fp64=-1, out_sumsq=None):
+    """Enqueue mrs_render_ex on torch's current stream.  Outputs are CUDA float32 tensors."""
+    o = L.RenderOpts()
+    L.lib().mrs_render_opts_default(C.byref(o))
+    o.rr_start = rr_start
+    if window is not None:
+        o.x0, o.y0, o.win_w, o.win_h = (int(v) for v in window)
+    o.accum_fp64 = accum_fp64
+    o.out_sumsq_dev = L.ptr(out_sumsq)
+    L.use_current_stream()
+    L.check(L.lib().mrs_render_ex(scene.handle, int(W), int(H), int(spp), int(max_depth),
+                                  C.c_uint64(int(seed)), C.byref(o), L.ptr(out_rgb),
+                                  L.ptr(out_aux)))
+
+
+def render(scene: GpuScene, W, H, spp, max_depth, seed, want_aux=True, **kw):
+    """Allocate outputs and render; returns (rgb [H,W,3], aux [H,W,7] or None) CUDA tensors."""
+    import torch
+    win = kw.get("window")
+    ww, wh = (W, H) if win is None else (win[2], win[3])
+    rgb = torch.empty(wh, ww, 3, dtype=torch.float32, device="cuda")
+    aux = torch.empty(wh, ww, 7, dtype=torch.float32, device="cuda") if want_aux else None
+    render_ex(scene, W, H, spp, max_depth, seed, rgb, aux, **kw)
+    return rgb, aux
+
+
+def counters(reset=False):
+    out = np.zeros(L.NUM_COUNTERS, np.int64)
+    L.use_current_stream()
+    L.check(L.lib().mrs_get_counters(out.ctypes.data_as(C.c_void_p), int(reset)))
+    keys = ["nonfinite", "rays", "shadow_rays", "spills", "paths", "overflows", "r6", "r7"]
+    return dict(zip(keys, (int(x) for x in out)))
+
+
+def get_tuning():
+    t = L.Tuning()
+    L.check(L.lib().mrs_get_tuning(C.byref(t)))
+    return {"chunk_paths": t.chunk_paths, "trace_blocks": t.trace_blocks}
+
+
+def set_tuning(chunk_paths=None, trace_blocks=None):
+    cur = get_tuning()
+    t = L.Tuning()
+    t.chunk_paths = int(chunk_paths if chunk_paths is not None else cur["chunk_paths"])
+    t.trace_blocks = int(trace_blocks if trace_blocks is not None else cur["trace_blocks"])
+    L.check(L.lib().mrs_set_tuning(C.byref(t)))
+
+
+def philox(ctr, key):
+    """Device Philox4x32-10 on n counters [n,4] and keys [n,2] (uint32); returns [n,4]."""
+    import torch
+    c = np.ascontiguousarray(ctr, np.uint32).reshape(-1, 4)
+    k = np.ascontiguousarray(key, np.uint32).reshape(-1, 2)
+    n = c.shape[0]
+    ct = torch.from_numpy(c.view(np.int32)).cuda()
+    kt = torch.from_numpy(k.view(np.int32)).cuda()
+    out = torch.empty(n, 4, dtype=torch.int32, device="cuda")
+    L.use_current_stream()
+    L.check(L.lib().mrs_debug_philox(n, L.ptr(ct), L.ptr(kt), L.ptr(out)))
+    torch.cuda.synchronize()
+    return out.cpu().numpy().view(np.uint32)

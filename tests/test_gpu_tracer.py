@@ -1,0 +1,343 @@
+"""GPU parity of the HIP path tracer against the FP64 oracle (through the C ABI)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from mrs_inputs import scenes as S
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def mrs(torch_cuda):
+    import paper_2106_12802_amd as m
+    return m
+
+
+def rel_ok(g, o):
+    """Per-channel relative closeness, dark pixels judged against 1e-3 of the image mean."""
+    floor = 1e-3 * max(float(np.abs(o).mean()), 1e-30)
+    return np.abs(g - o) <= 1e-4 * np.maximum(np.abs(o), floor)
+
+
+def gpu_render(mrs, scene, W, H, spp, D, seed, **kw):
+    import torch
+    gs = mrs.GpuScene(scene)
+    rgb, aux = mrs.render(gs, W, H, spp, D, seed, **kw)
+    torch.cuda.synchronize()
+    return rgb.cpu().numpy().astype(np.float64), aux.cpu().numpy().astype(np.float64), gs
+
+
+# --------------------------------------------------------------------------- RNG
+
+
+def test_philox_bitwise(mrs, oracle_tracer):
+    from paper_2106_12802_amd.render import philox
+    rng = np.random.default_rng(3)
+    ctr = rng.integers(0, 2 ** 32, (1000, 4), dtype=np.uint64).astype(np.uint32)
+    key = rng.integers(0, 2 ** 32, (1000, 2), dtype=np.uint64).astype(np.uint32)
+    ctr[0] = 0
+    key[0] = 0
+    ctr[1] = 0xFFFFFFFF
+    key[1] = 0xFFFFFFFF
+    got = philox(ctr, key)
+    want = np.stack([oracle_tracer.philox4x32_10(c, k) for c, k in zip(ctr, key)])
+    assert np.array_equal(got, want)
+    assert list(got[0]) == [0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8]
+
+
+# --------------------------------------------------------------------------- LBVH
+
+
+def _check_lbvh(gs, scene):
+    nodes, leaf, morton, root = gs.bvh()
+    n = scene.num_tris
+    assert sorted(leaf.tolist()) == list(range(n))
+    keys = (morton.astype(np.uint64) << np.uint64(32)) | leaf.astype(np.uint64)
+    assert np.all(keys[1:] > keys[:-1])
+    if n < 2:
+        return
+    refs = nodes[:, 12:14].copy().view(np.uint32)
+    V = scene.vertices.astype(np.float32)
+    # every node and leaf reachable exactly once; child boxes bound their subtrees
+    seen_int = np.zeros(n - 1, int)
+    seen_leaf = np.zeros(n, int)
+
+    def subtree_box(ref):
+        stack = [ref]
+        lo = np.full(3, np.inf, np.float32)
+        hi = np.full(3, -np.inf, np.float32)
+        while stack:
+            r = stack.pop()
+            if r & 0x80000000:
+                tri = V[leaf[r & 0x7FFFFFFF]]
+                lo = np.minimum(lo, tri.min(0))
+                hi = np.maximum(hi, tri.max(0))
+            else:
+                stack += list(refs[r])
+        return lo, hi
+
+    stack = [0]
+    while stack:
+        i = stack.pop()
+        seen_int[i] += 1
+        for side in range(2):
+            r = int(refs[i, side])
+            box = nodes[i, 6 * side:6 * side + 6]
+            if r & 0x80000000:
+                seen_leaf[r & 0x7FFFFFFF] += 1
+                tri = V[leaf[r & 0x7FFFFFFF]]
+                assert np.array_equal(box[:3], tri.min(0)) and np.array_equal(box[3:], tri.max(0))
+            else:
+                stack.append(r)
+    assert np.all(seen_int == 1) and np.all(seen_leaf == 1)
+    # spot-check subtree boxes of some internal children (exact min/max)
+    for i in range(0, n - 1, max(1, (n - 1) // 40)):
+        for side in range(2):
+            r = int(refs[i, side])
+            if not r & 0x80000000:
+                lo, hi = subtree_box(r)
+                box = nodes[i, 6 * side:6 * side + 6]
+                assert np.array_equal(box[:3], lo) and np.array_equal(box[3:], hi)
+
+
+@pytest.mark.parametrize("maker", [
+    lambda: S.random_soup(1, 1),
+    lambda: S.random_soup(2, 2),
+    lambda: S.random_soup(3, 777),
+    lambda: S.cornell(1),
+    lambda: S.procedural(7, spheres=((2, 4),), n_boxes=8, n_lights=2),
+])
+def test_lbvh_invariants(mrs, maker):
+    scene = maker()
+    _log("lbvh", scene.name, scene.num_tris)
+    gs = mrs.GpuScene(scene)
+    _check_lbvh(gs, scene)
+
+
+def test_lbvh_identical_centroids(mrs):
+    # all centroids equal: every Morton code ties and the primitive index decides
+    b = S._Builder()
+    m = b.material(S.LAMBERT, (0.5, 0.5, 0.5))
+    rng = np.random.default_rng(0)
+    for _ in range(300):
+        d = rng.normal(size=(3, 3))
+        d -= d.mean(0)
+        b.add_tris([d], m)
+    scene = b.build((0, 0, 0), S.Camera((0, 0, -5), (0, 0, 0)), "ties")
+    gs = mrs.GpuScene(scene)
+    _check_lbvh(gs, scene)
+
+
+# --------------------------------------------------------------------------- traversal
+
+
+@pytest.mark.parametrize("seed,n", [(1, 1), (2, 40), (3, 1500), (4, 20000)])
+def test_closest_hit_vs_oracle_brute_force(mrs, oracle_tracer, seed, n):
+    scene = S.random_soup(seed, n)
+    o, d = S.random_rays(seed, 3000)
+    _log("closest_hit", seed, n)
+    gs = mrs.GpuScene(scene)
+    t_g, p_g, b_g = gs.closest_hit(o, d)
+    t_o, p_o, b_o = oracle_tracer.OracleScene(scene).closest_hit(o, d, use_bvh=n > 2000)
+    same = p_g == p_o
+    # A disagreement is allowed only at a near-tie between two triangles (FP32 vs FP64).
+    bad = np.where(~same)[0]
+    for i in bad:
+        assert p_g[i] >= 0 and p_o[i] >= 0 and abs(t_g[i] - t_o[i]) <= 1e-5 * t_o[i], (i, t_g[i], t_o[i])
+    assert same.mean() >= 0.999
+    hit = same & (p_o >= 0)
+    assert hit.sum() > 0 or n == 1
+    assert np.all(np.abs(t_g[hit] - t_o[hit]) <= 1e-5 * t_o[hit])
+    assert np.all(np.isinf(t_g[p_g < 0]))
+
+
+def test_closest_hit_skip(mrs, oracle_tracer):
+    scene = S.random_soup(5, 500)
+    o, d = S.random_rays(5, 2000)
+    osc = oracle_tracer.OracleScene(scene)
+    _, p0, _ = osc.closest_hit(o, d, use_bvh=False)
+    skip = np.where(p0 >= 0, p0, -1).astype(np.int32)
+    gs = mrs.GpuScene(scene)
+    t_g, p_g, _ = gs.closest_hit(o, d, skip=skip)
+    t_o, p_o, _ = osc.closest_hit(o, d, skip=skip, use_bvh=False)
+    assert (p_g == p_o).mean() >= 0.999
+    assert not np.any((p_g == skip) & (skip >= 0))
+
+
+# --------------------------------------------------------------------------- closed forms
+
+
+def test_env_only_exact(mrs):
+    scene = S.env_only((0.3, 0.5, 0.7))
+    rgb, aux, _ = gpu_render(mrs, scene, 37, 19, 3, 5, 1)
+    assert np.all(rgb == scene.env.astype(np.float64)[None, None])
+    assert np.all(aux == 0)
+
+
+@pytest.mark.parametrize("D", [0, 1, 3])
+def test_lambert_plane_exact(mrs, D):
+    scene = S.lambert_plane()
+    rgb, _, _ = gpu_render(mrs, scene, 32, 24, 8, D, 3)
+    want = 0.0 if D == 0 else (scene.materials[0]["color"] * scene.env).astype(np.float64)
+    assert np.allclose(rgb, want, rtol=2e-7, atol=0)
+
+
+@pytest.mark.parametrize("D", [0, 2, 3])
+def test_furnace_exact(mrs, D):
+    scene = S.furnace_sphere(1.5, 0.6, subdiv=2)
+    rgb, _, _ = gpu_render(mrs, scene, 24, 16, 8, D, 5, rr_start=100)
+    E = float(scene.materials[0]["emission"][0])
+    rho = float(scene.materials[0]["color"][0])
+    want = E * sum(rho ** k for k in range(D + 1))
+    assert np.allclose(rgb, want, rtol=1e-6)
+
+
+# --------------------------------------------------------------------------- full renders
+
+
+def _parity(g_rgb, g_aux, o, label):
+    o_rgb = o["rgb"].reshape(g_rgb.shape)
+    o_aux = o["aux"].reshape(g_aux.shape)
+    ok = np.all(rel_ok(g_rgb, o_rgb), axis=-1)
+    frac = ok.mean()
+    mean_rel = abs(g_rgb.mean() - o_rgb.mean()) / abs(o_rgb.mean())
+    alb_err = np.abs(g_aux[..., 0:3] - o_aux[..., 0:3]).max(-1)
+    nrm_err = np.abs(g_aux[..., 3:6] - o_aux[..., 3:6]).max(-1)
+    dep_err = np.abs(g_aux[..., 6] - o_aux[..., 6]) / np.maximum(o_aux[..., 6], 1e-6)
+    aux_ok = (alb_err <= 1e-6) & (nrm_err <= 1e-6) & (dep_err <= 1e-5)
+    _log(f"{label}: pixels ok {frac:.5f} ({(~ok).sum()} bad), mean rel {mean_rel:.2e}, "
+         f"aux ok {aux_ok.mean():.5f}, max nrm err {nrm_err.max():.2e}, max dep err {dep_err.max():.2e}")
+    return frac, mean_rel, aux_ok.mean()
+
+
+@pytest.mark.parametrize("scene_seed", [1, 2, 3])
+def test_cornell_parity(mrs, oracle_tracer, scene_seed):
+    scene = S.cornell(scene_seed)
+    W = H = 64
+    spp, D, seed = 16, 4, 1000 + scene_seed
+    g_rgb, g_aux, _ = gpu_render(mrs, scene, W, H, spp, D, seed)
+    o = oracle_tracer.OracleScene(scene).render(W, H, spp, D, seed)
+    frac, mean_rel, aux_frac = _parity(g_rgb, g_aux, o, f"cornell {scene_seed}")
+    assert frac >= 0.999
+    assert mean_rel <= 1e-5
+    assert aux_frac >= 0.999
+
+
+def test_procedural_parity_small(mrs, oracle_tracer):
+    scene = S.procedural(7)
+    W, H, spp, D, seed = 96, 54, 4, 8, 2 * 7
+    g_rgb, g_aux, _ = gpu_render(mrs, scene, W, H, spp, D, seed)
+    o = oracle_tracer.OracleScene(scene).render(W, H, spp, D, seed)
+    frac, mean_rel, aux_frac = _parity(g_rgb, g_aux, o, "procedural 96x54x4")
+    assert frac >= 0.999
+    assert mean_rel <= 1e-5
+    assert aux_frac >= 0.999
+
+
+def test_procedural_parity_full_size_sampled(mrs, oracle_tracer, torch_cuda):
+    """HRLS 1280x720 @4 spp and LRHS 320x180 @64 spp, checked on sampled pixels."""
+    scene = S.procedural(7)
+    osc = oracle_tracer.OracleScene(scene)
+    gs = mrs.GpuScene(scene)
+    for (W, H, spp, seed, npx) in [(1280, 720, 4, 14, 3000), (320, 180, 64, 15, 600)]:
+        rgb, aux = mrs.render(gs, W, H, spp, 8, seed)
+        torch_cuda.cuda.synchronize()
+        g_rgb = rgb.cpu().numpy().reshape(-1, 3).astype(np.float64)
+        g_aux = aux.cpu().numpy().reshape(-1, 7).astype(np.float64)
+        pix = np.random.default_rng(W).choice(W * H, npx, replace=False).astype(np.int32)
+        o = osc.render(W, H, spp, 8, seed, pixels=pix)
+        frac, _, aux_frac = _parity(g_rgb[pix], g_aux[pix], o, f"procedural {W}x{H}x{spp} sampled")
+        assert frac >= 0.995  # sampled: a few divergent paths land in the sample
+        assert aux_frac >= 0.995
+
+
+def test_window_is_crop_and_chunking_invariant(mrs, torch_cuda):
+    scene = S.cornell(2)
+    gs = mrs.GpuScene(scene)
+    full, faux = mrs.render(gs, 48, 40, 6, 4, 77)
+    win, waux = mrs.render(gs, 48, 40, 6, 4, 77, window=(8, 12, 17, 9))
+    torch_cuda.cuda.synchronize()
+    assert torch_cuda.equal(win, full[12:21, 8:25])
+    assert torch_cuda.equal(waux, faux[12:21, 8:25])
+    old = mrs.get_tuning()
+    try:
+        for chunk, blocks in [(256, 3), (1000, 7), (48 * 40 * 2 + 5, 64)]:
+            mrs.set_tuning(chunk_paths=chunk, trace_blocks=blocks)
+            again, aaux = mrs.render(gs, 48, 40, 6, 4, 77)
+            torch_cuda.cuda.synchronize()
+            assert torch_cuda.equal(again, full), (chunk, blocks)
+            assert torch_cuda.equal(aaux, faux)
+    finally:
+        mrs.set_tuning(**old)
+    again, _ = mrs.render(gs, 48, 40, 6, 4, 77)
+    torch_cuda.cuda.synchronize()
+    assert torch_cuda.equal(again, full)  # deterministic run to run
+
+
+def test_fp64_accumulation_matches(mrs, oracle_tracer, torch_cuda):
+    scene = S.cornell(3)
+    gs = mrs.GpuScene(scene)
+    r32, _ = mrs.render(gs, 16, 16, 64, 4, 5, accum_fp64=0)
+    r64, _ = mrs.render(gs, 16, 16, 64, 4, 5, accum_fp64=1)
+    torch_cuda.cuda.synchronize()
+    a = r32.cpu().numpy().astype(np.float64)
+    b = r64.cpu().numpy().astype(np.float64)
+    assert np.allclose(a, b, rtol=1e-5, atol=1e-7)
+    o = oracle_tracer.OracleScene(scene).render(16, 16, 64, 4, 5)
+    assert np.mean(np.all(rel_ok(b.reshape(-1, 3), o["rgb"]), -1)) >= 0.99
+
+
+def test_counters_and_no_overflow(mrs, torch_cuda):
+    mrs.counters(reset=True)
+    scene = S.procedural(7, spheres=((2, 4),), n_boxes=10, n_lights=3)
+    gs = mrs.GpuScene(scene)
+    mrs.render(gs, 64, 48, 2, 8, 9)
+    c = mrs.counters(reset=True)
+    _log("counters", c)
+    assert c["paths"] == 64 * 48 * 2
+    assert c["rays"] >= c["paths"]
+    assert c["overflows"] == 0
+    assert c["nonfinite"] == 0
+
+
+def test_unbiased_vs_oracle_high_spp(mrs, oracle_tracer, torch_cuda):
+    """Mean of 64 independent 16-spp GPU renders vs a 4096-spp oracle render."""
+    scene = S.cornell(1)
+    W = H = 12
+    osc = oracle_tracer.OracleScene(scene)
+    ref = osc.render(W, H, 4096, 4, 2 ** 40 + 1, want_sumsq=True)
+    ref_mean = ref["rgb"]
+    ref_var = ref["sumsq"] / 4096 - ref_mean ** 2
+    gs = mrs.GpuScene(scene)
+    imgs = []
+    sq = []
+    for k in range(64):
+        s = torch_cuda.zeros(H, W, 3, device="cuda")
+        rgb, _ = mrs.render(gs, W, H, 16, 4, 5000 + k, want_aux=False, out_sumsq=s)
+        imgs.append(rgb.cpu().numpy().reshape(-1, 3).astype(np.float64))
+        sq.append(s.cpu().numpy().reshape(-1, 3).astype(np.float64))
+    g_mean = np.mean(imgs, 0)
+    g_var = np.sum(sq, 0) / 1024 - g_mean ** 2
+    sigma = np.sqrt(np.maximum(g_var, 0) / 1024 + np.maximum(ref_var, 0) / 4096)
+    z = np.abs(g_mean - ref_mean) / np.maximum(sigma, 1e-12)
+    frac_out = (z > 3).mean()
+    img_sigma = math.sqrt(np.sum(sigma ** 2)) / sigma.size
+    _log(f"unbiased: frac > 3 sigma {frac_out:.4f}, mean diff {g_mean.mean() - ref_mean.mean():.3e} "
+         f"(sigma {img_sigma:.3e})")
+    assert abs(g_mean.mean() - ref_mean.mean()) <= 3 * img_sigma
+    assert frac_out <= 0.01
