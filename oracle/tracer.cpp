@@ -22,6 +22,8 @@
 //   E10 GGX microfacet BRDF (Walter et al., EGSR 2007), separable Smith G,
 //       Schlick Fresnel, sampling of the half vector from D(h)(n.h)
 //   E11 Russian roulette
+//   (offset) rays leave a vertex from a point lifted off the surface along the
+//       geometric normal (Wachter & Binder, Ray Tracing Gems ch. 6)
 //   E12 per-pixel accumulation in sample order
 // Arithmetic is FP64 throughout; the scene's FP32 values are promoted.
 //
@@ -460,6 +462,14 @@ PathOut trace_path(const Scene& sc, bool use_bvh, int W, int H, int px, int py, 
       ng = neg(ng);
       ns = neg(ns);
     }
+    // Origin of the rays leaving this vertex: the hit point lifted along the
+    // geometric normal on the arrival side by 2^-16 * max(1, |x|_inf), the
+    // scale-aware ray offset of Wachter & Binder (Ray Tracing Gems, ch. 6).
+    // Every ray that leaves (NEE and BSDF) has n_g . wi > 0, so it starts on
+    // the correct side of the surface.
+    const double lift = std::ldexp(std::max(1.0, std::max(std::fabs(x.x), std::max(std::fabs(x.y),
+                                                                       std::fabs(x.z)))), -16);
+    const V3 xo = x + ng * lift;
     if (b == 0) {  // E6: first-hit feature buffers
       V3 alb = m.kind == 2 ? mk(0, 0, 0) : m.color;
       out.aux[0] = alb.x;
@@ -487,13 +497,13 @@ PathOut trace_path(const Scene& sc, bool use_bvh, int W, int H, int px, int py, 
       const Light& lt = sc.lights[li];
       double u1 = to_unit(bl.w[1]), u2 = to_unit(bl.w[2]);
       V3 y = lt.corner + lt.eu * u1 + lt.ev * u2;
-      V3 dv = y - x;
+      V3 dv = y - xo;
       double r2 = dot(dv, dv);
       double r = std::sqrt(r2);
       V3 wi = dv * (1.0 / r);
       double cs = dot(ns, wi), cg = dot(ng, wi), cl = -dot(lt.normal, wi);
       if (cs > 0.0 && cg > 0.0 && cl > 0.0) {
-        if (!occluded(sc, use_bvh, x, wi, r, h.prim, lt.tri0, lt.tri1)) {
+        if (!occluded(sc, use_bvh, xo, wi, r, h.prim, lt.tri0, lt.tri1)) {
           V3 f = m.kind == 0 ? m.color * (1.0 / M_PI) : ggx_eval(m, ns, wo, wi);
           double pdfA = 1.0 / ((double)nL * lt.area);
           V3 c = mul(mul(beta, f), lt.le) * (cs * cl / (r2 * pdfA));
@@ -528,7 +538,7 @@ PathOut trace_path(const Scene& sc, bool use_bvh, int W, int H, int px, int py, 
       if (!(to_unit(bs.w[2]) < q)) break;
       beta = beta * (1.0 / q);
     }
-    o = x;
+    o = xo;
     d = wi;
     skip = h.prim;
   }
