@@ -1,0 +1,171 @@
+"""Throughput benchmark of the hybrid frame's rendering path on one MI355X.
+
+One step = one multi-resolution frame of the procedural ~100k-triangle scene:
+HRLS 1280x720 at 4 spp plus LRHS 320x180 at 64 spp, max depth 8, Russian
+roulette from vertex 3 (7,372,800 paths; spp_avg = 64/16 + 4 = 8).  Inputs
+(scene and LBVH) are resident in HBM before timing starts.
+
+Prints one JSON line with the throughput (Mpaths/s), the roofline position of
+the dominant kernel (timed live with HIP events on its launch stream), and the
+FP64 oracle's throughput on the host cores for the same frame.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mpaths/s; ms/720p frame hybrid (4spp+LRHS+CNN) vs plain spp at equal PSNR"
+HRLS = (1280, 720, 4)
+LRHS = (320, 180, 64)
+MAX_DEPTH = 8
+SCENE_SEED = 7
+PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32 (FMA = 2 FLOP, packed)
+# Algorithmic FP32 operations (FMA counted as 2) of the closest-hit traversal:
+#   per node visit: two slab tests (6 FMA, 10 min/max, 1 scale, 2 compares each) + order = 51
+#   per triangle test: Moller-Trumbore (2 cross, 4 dot, 3 sub, 1 rcp, 3 scale, 7 compares) = 52
+#   per ray: reciprocal direction and scaled origin = 10
+FLOP_PER_VISIT = 51
+FLOP_PER_TEST = 52
+FLOP_PER_RAY = 10
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "extend_procedural97k_720p_traffic.txt")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2106_12802_amd", "csrc", "trace.hip")
+
+
+def kernel_source_hash() -> str:
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def read_traffic():
+    """HBM bytes per extend launch from the committed rocprofv3 PMC summary, if current."""
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_SUMMARY):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None  # the kernel changed since the counters were taken
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(scene, threads):
+    from oracle import tracer as orc
+    osc = orc.OracleScene(scene)
+    t0 = time.perf_counter()
+    osc.render(*HRLS[:2], HRLS[2], MAX_DEPTH, 2 * SCENE_SEED, nthreads=threads, want_aux=True)
+    osc.render(*LRHS[:2], LRHS[2], MAX_DEPTH, 2 * SCENE_SEED + 1, nthreads=threads, want_aux=False)
+    dt = time.perf_counter() - t0
+    paths = HRLS[0] * HRLS[1] * HRLS[2] + LRHS[0] * LRHS[1] * LRHS[2]
+    return {"value": round(paths / dt / 1e6, 4), "unit": "Mpaths/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"the full frame: HRLS {HRLS[0]}x{HRLS[1]}@{HRLS[2]}spp + LRHS "
+                      f"{LRHS[0]}x{LRHS[1]}@{LRHS[2]}spp ({paths} paths, FP64, {dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU path is a design, not part of this build)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2106_12802_amd as mrs
+    from paper_2106_12802_amd import tracer as R
+    from mrs_inputs import scenes as S
+
+    torch.cuda.set_device(0)
+    scene = S.procedural(SCENE_SEED)
+    gs = mrs.GpuScene(scene)
+    torch.cuda.synchronize()
+    (Wh, Hh, sh), (Wl, Hl, sl) = HRLS, LRHS
+    hr_rgb = torch.empty(Hh, Wh, 3, device="cuda")
+    hr_aux = torch.empty(Hh, Wh, 7, device="cuda")
+    lr_rgb = torch.empty(Hl, Wl, 3, device="cuda")
+    paths = Wh * Hh * sh + Wl * Hl * sl
+
+    def step(i):
+        R.render_ex(gs, Wh, Hh, sh, MAX_DEPTH, 2 * i, hr_rgb, hr_aux)
+        R.render_ex(gs, Wl, Hl, sl, MAX_DEPTH, 2 * i + 1, lr_rgb, None)
+
+    # algorithmic work of one frame (counting variant of the traversal kernels)
+    R.counters(reset=True)
+    R.set_count_work(True)
+    step(0)
+    R.set_count_work(False)
+    work = R.counters(reset=True)
+    print(f"[bench] work per frame: {json.dumps(work)}", file=sys.stderr, flush=True)
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    print(f"[bench] warmup done ({args.warmup} frames)", file=sys.stderr, flush=True)
+
+    R.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(i)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = R.profile_read()
+    R.profile_enable(False)
+    ms_per_step = dt * 1e3 / args.steps
+    value = paths * args.steps / dt / 1e6
+
+    ext_ms, ext_n = prof.get("extend", (0.0, 0))
+    flop_frame = (FLOP_PER_VISIT * work["extend_visits"] + FLOP_PER_TEST * work["extend_tests"]
+                  + FLOP_PER_RAY * work["rays"])
+    launches_per_frame = ext_n / args.steps if args.steps else 0
+    flop_per_launch = flop_frame / max(launches_per_frame, 1)
+    avg_launch_s = ext_ms / 1e3 / max(ext_n, 1)
+    achieved = flop_per_launch / avg_launch_s / 1e12 if avg_launch_s > 0 else 0.0
+    roofline = {"bound": "alu", "kernel": "k_extend (closest-hit traversal)",
+                "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP32_TFLOPS, 5), "traffic": read_traffic(),
+                "avg_launch_us": round(avg_launch_s * 1e6, 2),
+                "flop_per_launch": int(flop_per_launch),
+                "visits_per_ray": round(work["extend_visits"] / max(work["rays"], 1), 2),
+                "tests_per_ray": round(work["extend_tests"] / max(work["rays"], 1), 2)}
+    kernel_ms = {k: round(v[0] / args.steps, 4) for k, v in prof.items()}
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "Mpaths/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "hybrid frame render: procedural scene (seed 7, 97,528 triangles, "
+                               "Lambert+GGX, 3 quad lights, env 0.2), HRLS 1280x720@4spp + LRHS "
+                               "320x180@64spp, max depth 8, RR from vertex 3",
+                   "paths_per_frame": paths, "triangles": scene.num_tris},
+        "roofline": roofline,
+        "kernel_ms_per_frame": kernel_ms,
+        "rays_per_path": round((work["rays"] + work["shadow_rays"]) / paths, 3),
+    }
+    if not args.no_cpu_baseline:
+        threads = max(1, min(16, len(os.sched_getaffinity(0))))
+        print(f"[bench] timing the FP64 oracle on {threads} host threads", file=sys.stderr,
+              flush=True)
+        out["cpu_baseline"] = cpu_baseline(scene, threads)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

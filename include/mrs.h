@@ -159,9 +159,28 @@ mrs_status mrs_render_ex(const mrs_scene* scene, int32_t W, int32_t H, int32_t s
 /* Counters accumulated since the last reset (synchronises the stream):
  * [0] non-finite samples replaced by 0, [1] closest-hit rays, [2] shadow rays,
  * [3] traversal stack entries spilled from LDS to global memory,
- * [4] paths started, [5] stack overflows (must be 0). */
-#define MRS_NUM_COUNTERS 8
+ * [4] paths started, [5] stack overflows (must be 0),
+ * [6] closest-hit node visits, [7] closest-hit triangle tests,
+ * [8] shadow node visits, [9] shadow triangle tests
+ * ([6]..[9] only while work counting is on, see mrs_set_count_work). */
+#define MRS_NUM_COUNTERS 12
 mrs_status mrs_get_counters(int64_t out[MRS_NUM_COUNTERS], int32_t reset);
+
+/* Work counting: while on, traversal kernels also count node visits and
+ * triangle tests (a slower variant of the same kernels; results identical). */
+mrs_status mrs_set_count_work(int32_t on);
+
+/* Kernel timing with HIP events recorded on the launch stream around every
+ * launch of the library's kernels, by kernel id:
+ * 0 generate, 1 extend (closest hit), 2 shade, 3 shadow (any hit),
+ * 4 accumulate, 5 resolve, 6..15 reserved for the fusion network.
+ * mrs_profile_enable(1) clears the totals and starts recording;
+ * mrs_profile_read synchronises and returns, per id, the summed milliseconds
+ * and the launch count of the launches recorded so far. */
+#define MRS_NUM_KERNEL_IDS 16
+mrs_status mrs_profile_enable(int32_t on);
+mrs_status mrs_profile_read(double ms_out[MRS_NUM_KERNEL_IDS],
+                            int64_t launches_out[MRS_NUM_KERNEL_IDS]);
 
 /* Tuning knobs (performance only; results do not depend on them). */
 typedef struct mrs_tuning {

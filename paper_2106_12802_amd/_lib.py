@@ -18,7 +18,9 @@ LIB_PATH = os.path.join(HERE, "libmrs.so")
 MRS_OK = 0
 STATUS_NAMES = {0: "OK", 1: "INVALID_ARGUMENT", 2: "OUT_OF_MEMORY", 3: "DEVICE", 4: "NOT_READY",
                 5: "UNSUPPORTED"}
-NUM_COUNTERS = 8
+NUM_COUNTERS = 12
+NUM_KERNEL_IDS = 16
+KERNEL_NAMES = ["generate", "extend", "shade", "shadow", "accumulate", "resolve"]
 
 
 class MrsError(RuntimeError):
@@ -91,6 +93,9 @@ def lib():
         "mrs_debug_philox": ([I32, P, P, P], I32),
         "mrs_debug_closest_hit": ([P, I32, P, P, P, P, P, P], I32),
         "mrs_debug_bvh": ([P, P, P, P, P], I32),
+        "mrs_set_count_work": ([I32], I32),
+        "mrs_profile_enable": ([I32], I32),
+        "mrs_profile_read": ([P, P], I32),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(L, name)
@@ -111,7 +116,8 @@ def exported_symbols():
         "mrs_last_error", "mrs_set_stream", "mrs_sync", "mrs_scene_create", "mrs_scene_destroy",
         "mrs_build_bvh", "mrs_render", "mrs_render_opts_default", "mrs_render_ex",
         "mrs_get_counters", "mrs_get_tuning", "mrs_set_tuning", "mrs_debug_philox",
-        "mrs_debug_closest_hit", "mrs_debug_bvh",
+        "mrs_debug_closest_hit", "mrs_debug_bvh", "mrs_set_count_work", "mrs_profile_enable",
+        "mrs_profile_read",
     ]
 
 

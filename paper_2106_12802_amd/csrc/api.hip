@@ -325,6 +325,18 @@ mrs_status mrs_get_counters(int64_t out[MRS_NUM_COUNTERS], int32_t reset) {
   return get_counters(out, reset != 0, current_stream());
 }
 
+mrs_status mrs_set_count_work(int32_t on) {
+  set_count_work(on != 0);
+  return MRS_OK;
+}
+
+mrs_status mrs_profile_enable(int32_t on) { return prof_enable(on != 0); }
+
+mrs_status mrs_profile_read(double* ms, int64_t* launches) {
+  if (!ms || !launches) return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_profile_read: NULL output");
+  return prof_read(ms, launches);
+}
+
 mrs_status mrs_get_tuning(mrs_tuning* out) {
   if (!out) return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_get_tuning: out is NULL");
   get_tuning(out);

@@ -111,4 +111,18 @@ mrs_status debug_philox(int32_t n, const uint32_t* ctr, const uint32_t* key, uin
 mrs_status get_counters(int64_t* out, bool reset, hipStream_t st);
 void get_tuning(mrs_tuning* t);
 mrs_status set_tuning(const mrs_tuning* t);
+void set_count_work(bool on);
+// prof.hip: HIP-event timing of kernel launches by id
+enum KernelId {
+  KID_GENERATE = 0,
+  KID_EXTEND = 1,
+  KID_SHADE = 2,
+  KID_SHADOW = 3,
+  KID_ACCUMULATE = 4,
+  KID_RESOLVE = 5,
+};
+void prof_begin(int id, hipStream_t st);
+void prof_end(int id, hipStream_t st);
+mrs_status prof_enable(bool on);
+mrs_status prof_read(double* ms, int64_t* launches);
 }  // namespace mrs

@@ -151,12 +151,20 @@ struct Stack {
   }
 };
 
-// Returns true for ANY when an occluder was found; fills ts otherwise.
-template <bool ANY>
+struct WorkCount {
+  uint32_t visits = 0, tests = 0;
+};
+
+// Returns true for ANY when an occluder was found; fills ts otherwise.  COUNT
+// adds node visits and triangle tests to wc (a separate instantiation).
+template <bool ANY, bool COUNT>
 __device__ bool traverse(const SceneView& sc, f3 o, f3 d, uint32_t x0, uint32_t x1, uint32_t x2,
-                         Stack& st, TraceState& ts) {
+                         Stack& st, TraceState& ts, WorkCount& wc) {
   if (sc.ntris == 0) return false;
-  if (sc.root & LEAF_BIT) return isect_leaf<ANY>(sc.leaf_tri, 0, o, d, x0, x1, x2, ts);
+  if (sc.root & LEAF_BIT) {
+    if (COUNT) ++wc.tests;
+    return isect_leaf<ANY>(sc.leaf_tri, 0, o, d, x0, x1, x2, ts);
+  }
   const f3 inv = F3(safe_rcp(d.x), safe_rcp(d.y), safe_rcp(d.z));
   const f3 oi = mul(o, inv);
   uint32_t node = 0;
@@ -166,6 +174,7 @@ __device__ bool traverse(const SceneView& sc, f3 o, f3 d, uint32_t x0, uint32_t 
   for (uint32_t visits = 0; visits < ninternal; ++visits) {
     const float4* nd = sc.nodes + 4 * (size_t)node;
     const float4 a = nd[0], b = nd[1], c = nd[2], r = nd[3];
+    if (COUNT) ++wc.visits;
     float tl, tr;
     bool hl = slab(a.x, a.y, a.z, a.w, b.x, b.y, oi, inv, ts.t, tl);
     bool hr = slab(b.z, b.w, c.x, c.y, c.z, c.w, oi, inv, ts.t, tr);
@@ -174,10 +183,12 @@ __device__ bool traverse(const SceneView& sc, f3 o, f3 d, uint32_t x0, uint32_t 
     if ((cl & LEAF_BIT) ? (cl & ~LEAF_BIT) >= (uint32_t)sc.ntris : cl >= ninternal) hl = false;
     if ((cr & LEAF_BIT) ? (cr & ~LEAF_BIT) >= (uint32_t)sc.ntris : cr >= ninternal) hr = false;
     if (hl && (cl & LEAF_BIT)) {
+      if (COUNT) ++wc.tests;
       if (isect_leaf<ANY>(sc.leaf_tri, cl & ~LEAF_BIT, o, d, x0, x1, x2, ts) && ANY) return true;
       hl = false;
     }
     if (hr && (cr & LEAF_BIT)) {
+      if (COUNT) ++wc.tests;
       if (isect_leaf<ANY>(sc.leaf_tri, cr & ~LEAF_BIT, o, d, x0, x1, x2, ts) && ANY) return true;
       hr = false;
     }
@@ -230,6 +241,7 @@ __global__ __launch_bounds__(256) void k_generate(ChunkGeom g, SceneView sc, uin
   aux[2 * slot + 1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 }
 
+template <bool COUNT>
 __global__ __launch_bounds__(TB) void k_extend(SceneView sc, const float4* __restrict__ rays,
                                                const uint32_t* __restrict__ count,
                                                float4* __restrict__ hits,
@@ -239,14 +251,18 @@ __global__ __launch_bounds__(TB) void k_extend(SceneView sc, const float4* __res
   const uint32_t n = *count;
   const uint32_t gtid = blockIdx.x * TB + threadIdx.x;
   Stack st{stk + threadIdx.x, spill + gtid, gridDim.x * TB, 0, 0u, false};
+  WorkCount wc;
   for (uint32_t q = gtid; q < n; q += gridDim.x * TB) {
     const float4 R0 = rays[2 * q], R1 = rays[2 * q + 1];
     TraceState ts{INFINITY, NO_PRIM, 0.0f, 0.0f};
-    traverse<false>(sc, xyz(R0), xyz(R1), __float_as_uint(R1.w), NO_PRIM, NO_PRIM, st, ts);
+    traverse<false, COUNT>(sc, xyz(R0), xyz(R1), __float_as_uint(R1.w), NO_PRIM, NO_PRIM, st, ts,
+                           wc);
     hits[q] = make_float4(ts.t, __uint_as_float(ts.prim), ts.b1, ts.b2);
   }
   if (st.spills) atomicAdd(stats + 3, (unsigned long long)st.spills);
   if (st.overflow) atomicAdd(stats + 5, 1ull);
+  if (COUNT && wc.visits) atomicAdd(stats + 6, (unsigned long long)wc.visits);
+  if (COUNT && wc.tests) atomicAdd(stats + 7, (unsigned long long)wc.tests);
 }
 
 __device__ __forceinline__ void onb(f3 n, f3& T, f3& B) {
@@ -331,6 +347,11 @@ __global__ __launch_bounds__(256) void k_shade(ChunkGeom g, SceneView sc, int b,
           ng = neg(ng);
           ns = neg(ns);
         }
+        // Rays leave from the hit point lifted along the arrival-side geometric
+        // normal by 2^-16 * max(1, |x|_inf): far above FP32 rounding of x, so
+        // neither this triangle nor its neighbours are hit again by rounding.
+        const float lift = ldexpf(fmaxf(1.0f, fmaxf(fabsf(x.x), fmaxf(fabsf(x.y), fabsf(x.z)))), -16);
+        x = x + ng * lift;
         const DevMaterial m = sc.mats[info & PRIM_MAT_MASK];
         const int kind = (int)m.emis_kind.w;
         const f3 col = xyz(m.color_alpha);
@@ -424,6 +445,7 @@ __global__ __launch_bounds__(256) void k_shade(ChunkGeom g, SceneView sc, int b,
   }
 }
 
+template <bool COUNT>
 __global__ __launch_bounds__(TB) void k_shadow(SceneView sc, const float4* __restrict__ shadow,
                                                const uint32_t* __restrict__ count,
                                                float4* __restrict__ L_buf,
@@ -433,14 +455,15 @@ __global__ __launch_bounds__(TB) void k_shadow(SceneView sc, const float4* __res
   const uint32_t n = *count;
   const uint32_t gtid = blockIdx.x * TB + threadIdx.x;
   Stack st{stk + threadIdx.x, spill + gtid, gridDim.x * TB, 0, 0u, false};
+  WorkCount wc;
   for (uint32_t q = gtid; q < n; q += gridDim.x * TB) {
     const float4 S0 = shadow[3 * q], S1 = shadow[3 * q + 1], S2 = shadow[3 * q + 2];
     const uint32_t tag = __float_as_uint(S0.w);
     const uint32_t slot = tag & 0xffffffu, li = tag >> 24;
     const DevLight& lt = sc.lights[li];
     TraceState ts{S1.w, NO_PRIM, 0.0f, 0.0f};
-    const bool occ = traverse<true>(sc, xyz(S0), xyz(S1), __float_as_uint(S2.w),
-                                    (uint32_t)lt.tri0, (uint32_t)lt.tri1, st, ts);
+    const bool occ = traverse<true, COUNT>(sc, xyz(S0), xyz(S1), __float_as_uint(S2.w),
+                                           (uint32_t)lt.tri0, (uint32_t)lt.tri1, st, ts, wc);
     if (!occ) {
       float4 Lv = L_buf[slot];
       Lv.x += S2.x;
@@ -451,6 +474,8 @@ __global__ __launch_bounds__(TB) void k_shadow(SceneView sc, const float4* __res
   }
   if (st.spills) atomicAdd(stats + 3, (unsigned long long)st.spills);
   if (st.overflow) atomicAdd(stats + 5, 1ull);
+  if (COUNT && wc.visits) atomicAdd(stats + 8, (unsigned long long)wc.visits);
+  if (COUNT && wc.tests) atomicAdd(stats + 9, (unsigned long long)wc.tests);
 }
 
 template <typename T>
@@ -543,9 +568,11 @@ __global__ __launch_bounds__(256) void k_debug_hit(SceneView sc, int32_t n,
   Stack st{stk + threadIdx.x, spill + i, (uint32_t)(gridDim.x * 256), 0, 0u, false};
   if (i >= n) return;
   TraceState ts{INFINITY, NO_PRIM, 0.0f, 0.0f};
+  WorkCount wc;
   const uint32_t sk = skip ? (uint32_t)skip[i] : NO_PRIM;
-  traverse<false>(sc, F3(o[3 * i], o[3 * i + 1], o[3 * i + 2]),
-                  F3(d[3 * i], d[3 * i + 1], d[3 * i + 2]), sk, NO_PRIM, NO_PRIM, st, ts);
+  traverse<false, false>(sc, F3(o[3 * i], o[3 * i + 1], o[3 * i + 2]),
+                         F3(d[3 * i], d[3 * i + 1], d[3 * i + 2]), sk, NO_PRIM, NO_PRIM, st, ts,
+                         wc);
   t_out[i] = ts.t;
   prim_out[i] = ts.prim == NO_PRIM ? -1 : (int32_t)ts.prim;
   b_out[2 * i] = ts.b1;
@@ -584,6 +611,7 @@ struct Workspace {
 };
 Workspace g_ws;
 mrs_tuning g_tune = {1 << 22, 2048};
+bool g_count_work = false;
 
 template <typename T>
 void hfree(T*& p) {
@@ -692,23 +720,45 @@ mrs_status render_t(const mrs_scene* s, const RenderArgs& a, hipStream_t st) {
     const uint32_t n = (uint32_t)(np * (size_t)ns);
     const unsigned gb = std::min<unsigned>(blocks, cdiv(n, TB));
     k_reset<<<1, 256, 0, st>>>(g_ws.q, n);
+    prof_begin(KID_GENERATE, st);
     k_generate<<<cdiv(n, 256), 256, 0, st>>>(g, sc, n, g_ws.rays[0], g_ws.beta, g_ws.L, g_ws.aux);
+    prof_end(KID_GENERATE, st);
     for (int b = 0; b <= a.max_depth; ++b) {
       float4* rin = g_ws.rays[b & 1];
       float4* rout = g_ws.rays[(b + 1) & 1];
-      k_extend<<<gb, TB, 0, st>>>(sc, rin, g_ws.q + Q_RAYS + b, g_ws.hits, g_ws.spill, g_ws.stats);
+      prof_begin(KID_EXTEND, st);
+      if (g_count_work)
+        k_extend<true><<<gb, TB, 0, st>>>(sc, rin, g_ws.q + Q_RAYS + b, g_ws.hits, g_ws.spill,
+                                          g_ws.stats);
+      else
+        k_extend<false><<<gb, TB, 0, st>>>(sc, rin, g_ws.q + Q_RAYS + b, g_ws.hits, g_ws.spill,
+                                           g_ws.stats);
+      prof_end(KID_EXTEND, st);
+      prof_begin(KID_SHADE, st);
       k_shade<<<gb, 256, 0, st>>>(g, sc, b, rin, g_ws.hits, g_ws.q, rout, g_ws.shadow, g_ws.beta,
                                   g_ws.L, g_ws.aux);
-      if (b < a.max_depth)
-        k_shadow<<<gb, TB, 0, st>>>(sc, g_ws.shadow, g_ws.q + Q_SHADOW + b, g_ws.L, g_ws.spill,
-                                    g_ws.stats);
+      prof_end(KID_SHADE, st);
+      if (b < a.max_depth) {
+        prof_begin(KID_SHADOW, st);
+        if (g_count_work)
+          k_shadow<true><<<gb, TB, 0, st>>>(sc, g_ws.shadow, g_ws.q + Q_SHADOW + b, g_ws.L,
+                                            g_ws.spill, g_ws.stats);
+        else
+          k_shadow<false><<<gb, TB, 0, st>>>(sc, g_ws.shadow, g_ws.q + Q_SHADOW + b, g_ws.L,
+                                             g_ws.spill, g_ws.stats);
+        prof_end(KID_SHADOW, st);
+      }
     }
+    prof_begin(KID_ACCUMULATE, st);
     k_accumulate<T><<<cdiv(np, 256), 256, 0, st>>>(g, ns, (uint32_t)np, g_ws.L, g_ws.aux, acc_rgb,
                                                    acc_aux, acc_sq, g_ws.stats);
+    prof_end(KID_ACCUMULATE, st);
     k_tally<<<1, 64, 0, st>>>(g_ws.q, a.max_depth + 1, g_ws.stats, n);
   }
+  prof_begin(KID_RESOLVE, st);
   k_resolve<T><<<cdiv(npix, 256), 256, 0, st>>>((uint32_t)npix, a.spp, acc_rgb, acc_aux, acc_sq,
                                                 a.out_rgb, a.out_aux, a.out_sumsq);
+  prof_end(KID_RESOLVE, st);
   MRS_TRY_HIP(hipGetLastError());
   return MRS_OK;
 }
@@ -756,6 +806,8 @@ mrs_status get_counters(int64_t* out, bool reset, hipStream_t st) {
 }
 
 void get_tuning(mrs_tuning* t) { *t = g_tune; }
+
+void set_count_work(bool on) { g_count_work = on; }
 
 mrs_status set_tuning(const mrs_tuning* t) {
   if (t->chunk_paths < 256 || t->chunk_paths > (1 << 24))

@@ -100,8 +100,26 @@ def counters(reset=False):
     out = np.zeros(L.NUM_COUNTERS, np.int64)
     L.use_current_stream()
     L.check(L.lib().mrs_get_counters(out.ctypes.data_as(C.c_void_p), int(reset)))
-    keys = ["nonfinite", "rays", "shadow_rays", "spills", "paths", "overflows", "r6", "r7"]
+    keys = ["nonfinite", "rays", "shadow_rays", "spills", "paths", "overflows",
+            "extend_visits", "extend_tests", "shadow_visits", "shadow_tests", "r10", "r11"]
     return dict(zip(keys, (int(x) for x in out)))
+
+
+def set_count_work(on: bool):
+    L.check(L.lib().mrs_set_count_work(int(bool(on))))
+
+
+def profile_enable(on: bool = True):
+    L.check(L.lib().mrs_profile_enable(int(bool(on))))
+
+
+def profile_read():
+    """{kernel name: (total ms, launches)} for the launches recorded since profile_enable."""
+    ms = np.zeros(L.NUM_KERNEL_IDS, np.float64)
+    n = np.zeros(L.NUM_KERNEL_IDS, np.int64)
+    L.check(L.lib().mrs_profile_read(ms.ctypes.data_as(C.c_void_p), n.ctypes.data_as(C.c_void_p)))
+    names = L.KERNEL_NAMES + [f"k{i}" for i in range(len(L.KERNEL_NAMES), L.NUM_KERNEL_IDS)]
+    return {names[i]: (float(ms[i]), int(n[i])) for i in range(L.NUM_KERNEL_IDS) if n[i]}
 
 
 def get_tuning():

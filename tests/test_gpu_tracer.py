@@ -46,7 +46,7 @@ def gpu_render(mrs, scene, W, H, spp, D, seed, **kw):
 
 
 def test_philox_bitwise(mrs, oracle_tracer):
-    from paper_2106_12802_amd.render import philox
+    from paper_2106_12802_amd.tracer import philox
     rng = np.random.default_rng(3)
     ctr = rng.integers(0, 2 ** 32, (1000, 4), dtype=np.uint64).astype(np.uint32)
     key = rng.integers(0, 2 ** 32, (1000, 2), dtype=np.uint64).astype(np.uint32)
@@ -156,13 +156,17 @@ def test_closest_hit_vs_oracle_brute_force(mrs, oracle_tracer, seed, n):
     t_o, p_o, b_o = oracle_tracer.OracleScene(scene).closest_hit(o, d, use_bvh=n > 2000)
     same = p_g == p_o
     # A disagreement is allowed only at a near-tie between two triangles (FP32 vs FP64).
+    # FP32 rounding of t scales with the size of the hit point's coordinates
+    scale = t_o + np.linalg.norm(o, axis=1)
     bad = np.where(~same)[0]
     for i in bad:
-        assert p_g[i] >= 0 and p_o[i] >= 0 and abs(t_g[i] - t_o[i]) <= 1e-5 * t_o[i], (i, t_g[i], t_o[i])
+        assert p_g[i] >= 0 and p_o[i] >= 0 and abs(t_g[i] - t_o[i]) <= 1e-5 * scale[i], (i, t_g[i], t_o[i])
     assert same.mean() >= 0.999
     hit = same & (p_o >= 0)
     assert hit.sum() > 0 or n == 1
-    assert np.all(np.abs(t_g[hit] - t_o[hit]) <= 1e-5 * t_o[hit])
+    err = np.abs(t_g[hit] - t_o[hit]) / scale[hit]
+    _log(f"closest_hit: {len(bad)} prim mismatches, max |dt|/(t+|o|) {err.max() if err.size else 0:.2e}")
+    assert np.all(err <= 1e-5)
     assert np.all(np.isinf(t_g[p_g < 0]))
 
 
@@ -210,6 +214,14 @@ def test_furnace_exact(mrs, D):
 # --------------------------------------------------------------------------- full renders
 
 
+# Feature-buffer tolerances.  Albedo is a table lookup (exact unless the hit
+# differs).  The smooth shading normal interpolates corner normals with FP32
+# barycentrics, whose error is about eps32 * (|o| + t) / edge: for 0.04-long
+# triangles seen from ~10 units that is ~1e-5, times a corner-normal spread of
+# ~0.1, so 2e-5 absolute.  Depth is FP32 t: 1e-5 relative.
+ALBEDO_TOL, NORMAL_TOL, DEPTH_TOL = 1e-6, 2e-5, 1e-5
+
+
 def _parity(g_rgb, g_aux, o, label):
     o_rgb = o["rgb"].reshape(g_rgb.shape)
     o_aux = o["aux"].reshape(g_aux.shape)
@@ -219,9 +231,10 @@ def _parity(g_rgb, g_aux, o, label):
     alb_err = np.abs(g_aux[..., 0:3] - o_aux[..., 0:3]).max(-1)
     nrm_err = np.abs(g_aux[..., 3:6] - o_aux[..., 3:6]).max(-1)
     dep_err = np.abs(g_aux[..., 6] - o_aux[..., 6]) / np.maximum(o_aux[..., 6], 1e-6)
-    aux_ok = (alb_err <= 1e-6) & (nrm_err <= 1e-6) & (dep_err <= 1e-5)
+    aux_ok = (alb_err <= ALBEDO_TOL) & (nrm_err <= NORMAL_TOL) & (dep_err <= DEPTH_TOL)
     _log(f"{label}: pixels ok {frac:.5f} ({(~ok).sum()} bad), mean rel {mean_rel:.2e}, "
-         f"aux ok {aux_ok.mean():.5f}, max nrm err {nrm_err.max():.2e}, max dep err {dep_err.max():.2e}")
+         f"aux ok {aux_ok.mean():.5f}, normal err median {np.median(nrm_err):.1e} "
+         f"max {nrm_err.max():.2e}, max depth err {dep_err.max():.2e}")
     return frac, mean_rel, aux_ok.mean()
 
 
@@ -238,32 +251,34 @@ def test_cornell_parity(mrs, oracle_tracer, scene_seed):
     assert aux_frac >= 0.999
 
 
-def test_procedural_parity_small(mrs, oracle_tracer):
+def test_procedural_parity_small_ragged(mrs, oracle_tracer):
+    # 97 x 55 at 4 spp: several 256-thread blocks and a ragged tail.  With only
+    # 21k paths one divergent path moves the image mean by ~1e-5 of itself, so
+    # the mean is held to 1e-4 here and to 1e-5 at full size below.
     scene = S.procedural(7)
-    W, H, spp, D, seed = 96, 54, 4, 8, 2 * 7
+    W, H, spp, D, seed = 97, 55, 4, 8, 2 * 7
     g_rgb, g_aux, _ = gpu_render(mrs, scene, W, H, spp, D, seed)
     o = oracle_tracer.OracleScene(scene).render(W, H, spp, D, seed)
-    frac, mean_rel, aux_frac = _parity(g_rgb, g_aux, o, "procedural 96x54x4")
+    frac, mean_rel, aux_frac = _parity(g_rgb, g_aux, o, "procedural 97x55x4")
     assert frac >= 0.999
-    assert mean_rel <= 1e-5
+    assert mean_rel <= 1e-4
     assert aux_frac >= 0.999
 
 
-def test_procedural_parity_full_size_sampled(mrs, oracle_tracer, torch_cuda):
-    """HRLS 1280x720 @4 spp and LRHS 320x180 @64 spp, checked on sampled pixels."""
+@pytest.mark.parametrize("W,H,spp,seed", [(1280, 720, 4, 14), (320, 180, 64, 15)])
+def test_procedural_parity_full_size(mrs, oracle_tracer, torch_cuda, W, H, spp, seed):
+    """HRLS 1280x720 @4 spp and LRHS 320x180 @64 spp, whole images against the oracle."""
     scene = S.procedural(7)
-    osc = oracle_tracer.OracleScene(scene)
     gs = mrs.GpuScene(scene)
-    for (W, H, spp, seed, npx) in [(1280, 720, 4, 14, 3000), (320, 180, 64, 15, 600)]:
-        rgb, aux = mrs.render(gs, W, H, spp, 8, seed)
-        torch_cuda.cuda.synchronize()
-        g_rgb = rgb.cpu().numpy().reshape(-1, 3).astype(np.float64)
-        g_aux = aux.cpu().numpy().reshape(-1, 7).astype(np.float64)
-        pix = np.random.default_rng(W).choice(W * H, npx, replace=False).astype(np.int32)
-        o = osc.render(W, H, spp, 8, seed, pixels=pix)
-        frac, _, aux_frac = _parity(g_rgb[pix], g_aux[pix], o, f"procedural {W}x{H}x{spp} sampled")
-        assert frac >= 0.995  # sampled: a few divergent paths land in the sample
-        assert aux_frac >= 0.995
+    rgb, aux = mrs.render(gs, W, H, spp, 8, seed)
+    torch_cuda.cuda.synchronize()
+    g_rgb = rgb.cpu().numpy().reshape(-1, 3).astype(np.float64)
+    g_aux = aux.cpu().numpy().reshape(-1, 7).astype(np.float64)
+    o = oracle_tracer.OracleScene(scene).render(W, H, spp, 8, seed)
+    frac, mean_rel, aux_frac = _parity(g_rgb, g_aux, o, f"procedural {W}x{H}x{spp}")
+    assert frac >= 0.999
+    assert mean_rel <= 1e-5
+    assert aux_frac >= 0.999
 
 
 def test_window_is_crop_and_chunking_invariant(mrs, torch_cuda):
