@@ -60,6 +60,87 @@ def read_traffic():
         return None
 
 
+COPY_BYTES = 1 << 30  # plain device copy used to calibrate the PMC byte counters
+
+
+def copy_calibration():
+    """One plain 1 GiB device-to-device copy (reads and writes COPY_BYTES)."""
+    import torch
+    src = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
+def _pmc_rows(path):
+    import csv
+    files = [path] if os.path.isfile(path) else [
+        os.path.join(dp, f) for dp, _, fs in os.walk(path) for f in fs
+        if f.endswith("counter_collection.csv")]
+    rows = []
+    for fn in files:
+        with open(fn) as f:
+            rows += list(csv.DictReader(f))
+    return rows
+
+
+def pmc_summary(fetch_path, write_path, out_path):
+    """Turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) into the
+    HBM traffic summary read by read_traffic()."""
+    def per_kernel(path, counter):
+        acc = {}
+        for r in _pmc_rows(path):
+            if r.get("Counter_Name") != counter:
+                continue
+            acc.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return acc
+
+    fetch = per_kernel(fetch_path, "FETCH_SIZE")
+    write = per_kernel(write_path, "WRITE_SIZE")
+
+    def copy_value(d):
+        cands = [(max(v), k) for k, v in d.items() if "copy" in k.lower()]
+        return max(cands)[0] if cands else None
+
+    cf, cw = copy_value(fetch), copy_value(write)
+    fs = COPY_BYTES / (cf * 1024.0) if cf else None
+    ws = COPY_BYTES / (cw * 1024.0) if cw else None
+    ext = [k for k in fetch if "k_extend<false>" in k]
+    if not ext or fs is None or ws is None:
+        raise SystemExit(f"pmc summary: missing kernels (extend {ext}, copy {cf}, {cw})")
+    k = ext[0]
+    f_kib = sum(fetch[k]) / len(fetch[k])
+    w_kib = sum(write.get(k, [0.0])) / max(len(write.get(k, [])), 1)
+    hbm = f_kib * 1024.0 * fs + w_kib * 1024.0 * ws
+    lines = [
+        "# HBM traffic of k_extend<false> (closest-hit traversal), procedural scene seed 7",
+        "# (97,528 triangles), hybrid frame HRLS 1280x720@4 + LRHS 320x180@64, max depth 8.",
+        "# Made by (each pass its own process, run from the repository root):",
+        "#   rocprofv3 --pmc FETCH_SIZE -f csv -d gpurun_out/pmc_fetch -o pmc -- python bench.py "
+        "--steps 1 --warmup 0 --no-cpu-baseline --copy-calibration",
+        "#   rocprofv3 --pmc WRITE_SIZE -f csv -d gpurun_out/pmc_write -o pmc -- python bench.py "
+        "--steps 1 --warmup 0 --no-cpu-baseline --copy-calibration",
+        "#   python bench.py --pmc-summary gpurun_out/pmc_fetch gpurun_out/pmc_write",
+        "# Counters are KiB per dispatch; each is scaled by COPY_BYTES over what the same counter",
+        "# reads for a plain 1 GiB device copy in the same process.",
+        f"copy_bytes = {COPY_BYTES}",
+        f"copy_fetch_kib = {cf:.1f}",
+        f"copy_write_kib = {cw:.1f}",
+        f"fetch_scale = {fs:.4f}",
+        f"write_scale = {ws:.4f}",
+        f"extend_dispatches = {len(fetch[k])}",
+        f"extend_fetch_kib_per_dispatch = {f_kib:.1f}",
+        f"extend_write_kib_per_dispatch = {w_kib:.1f}",
+        f"hbm_bytes_per_launch = {hbm:.0f}",
+        f"kernel_source_sha256_16 = {kernel_source_hash()}",
+    ]
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def cpu_baseline(scene, threads):
     from oracle import tracer as orc
     osc = orc.OracleScene(scene)
@@ -80,7 +161,14 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one plain 1 GiB device copy first (PMC byte-counter calibration)")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="summarise two rocprofv3 --pmc runs into the profiles/ traffic file")
     args = ap.parse_args()
+    if args.pmc_summary:
+        pmc_summary(args.pmc_summary[0], args.pmc_summary[1], TRAFFIC_SUMMARY)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the multi-GPU path is a design, not part of this build)", file=sys.stderr)
@@ -93,6 +181,8 @@ def main():
     from mrs_inputs import scenes as S
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        copy_calibration()
     scene = S.procedural(SCENE_SEED)
     gs = mrs.GpuScene(scene)
     torch.cuda.synchronize()
