@@ -173,7 +173,9 @@ mrs_status mrs_set_count_work(int32_t on);
 /* Kernel timing with HIP events recorded on the launch stream around every
  * launch of the library's kernels, by kernel id:
  * 0 generate, 1 extend (closest hit), 2 shade, 3 shadow (any hit),
- * 4 accumulate, 5 resolve, 6..15 reserved for the fusion network.
+ * 4 accumulate, 5 resolve, 6 network input preparation, 7 network HR input conv,
+ * 8 network LR convs (lrhs, fuse, trunk, up), 9 network HR output conv,
+ * 10..15 reserved.
  * mrs_profile_enable(1) clears the totals and starts recording;
  * mrs_profile_read synchronises and returns, per id, the summed milliseconds
  * and the launch count of the launches recorded so far. */
@@ -190,7 +192,56 @@ typedef struct mrs_tuning {
 mrs_status mrs_get_tuning(mrs_tuning* out);
 mrs_status mrs_set_tuning(const mrs_tuning* t);
 
+/* ------------------------------------------------------------ fusion network */
+
+/* The HRLS + LRHS fusion network of the hybrid method (paper Sec. 4, Fig. 3):
+ *   h0  = ReLU(conv3x3 10->64) on HRLS (rgb, albedo, normal, depth)    HR
+ *   fl  = ReLU(conv3x3 3->64) on LRHS rgb                               LR
+ *   F0  = ReLU(conv1x1 [fl, unshuffle4(h0)] 1088->64)   (deshuffle + fuse)
+ *   r  <- r + 0.1 conv3x3(ReLU(conv3x3(r))) x 16, r_0 = F0   (trunk)
+ *   FDF = r_16 + F0                                      (global residual)
+ *   out = conv3x3 [shuffle4(ReLU(conv3x3 64->256 FDF)), h0] 80->3    HR
+ * Every conv is 3x3 except the 1x1 fuse, ReLU after every conv but the last
+ * (Sec. 4, implementation details).  Inputs are preprocessed on the device:
+ * RGB clipped to [0, 100] (Sec. 3.2) then log1p, depth log1p, albedo and normal
+ * as rendered.  unshuffle by r maps HR pixel (rY+i, rX+j) channel c to LR
+ * channel (i r + j) C + c; shuffle is its inverse.  Convolutions run as BF16
+ * MFMA implicit GEMMs with FP32 accumulation; the residual stream is FP32.
+ * Parameters: MRS_NET_NUM_PARAMS FP32 values, layer by layer (hrls, lrhs, fuse,
+ * res0a, res0b, ..., res15b, up, rec), each weight [C_out][C_in][k][k] then
+ * bias [C_out]. */
+typedef struct mrs_net mrs_net;
+#define MRS_NET_NUM_PARAMS 1408883
+
+int64_t mrs_net_num_params(void);
+mrs_status mrs_net_create(mrs_net** out); /* parameters unset: mrs_fuse is NOT_READY */
+mrs_status mrs_net_destroy(mrs_net* net);
+/* He-uniform weights (bound sqrt(6 / fan_in)) from Philox4x32-10 with key seed,
+ * counter (parameter index lo, hi, 0, 2); zero biases.  On the device. */
+mrs_status mrs_net_init(mrs_net* net, uint64_t seed);
+/* Copies `count` (= MRS_NET_NUM_PARAMS) FP32 masters from host memory and
+ * refreshes the packed BF16 weights; synchronises. */
+mrs_status mrs_net_set_params(mrs_net* net, const float* params_host, int64_t count);
+mrs_status mrs_net_get_params(const mrs_net* net, float* params_host, int64_t count);
+
+/* I_SR = Net(I_LRHS, I_HRLS) for one frame: hrls_rgb_dev H*W*3, hrls_aux_dev
+ * H*W*7 (as written by mrs_render), lrhs_rgb_dev (H/4)*(W/4)*3, out_rgb_dev
+ * H*W*3, all FP32 HWC device buffers.  W, H multiples of 4.  The network's
+ * activations live in a per-net device arena grown on demand; calls on one
+ * net must not overlap.  NOT_READY without parameters. */
+mrs_status mrs_fuse(mrs_net* net, const float* hrls_rgb_dev, const float* hrls_aux_dev,
+                    const float* lrhs_rgb_dev, int32_t W, int32_t H, float* out_rgb_dev);
+/* The same for B frames stored one after the other (NHWC). */
+mrs_status mrs_fuse_batch(mrs_net* net, int32_t B, const float* hrls_rgb_dev,
+                          const float* hrls_aux_dev, const float* lrhs_rgb_dev, int32_t W,
+                          int32_t H, float* out_rgb_dev);
+
 /* ------------------------------------------------------- debug / test hooks */
+
+/* FP32 copy of an activation of the last forward on `net`: which 0 = F0,
+ * 1 = FDF, each B*(H/4)*(W/4)*64 values (count must match).  Synchronises. */
+mrs_status mrs_debug_net_activation(const mrs_net* net, int32_t which, float* out_host,
+                                    int64_t count);
 
 /* Philox4x32-10 on the device: out_dev[4i..4i+3] = philox(ctr_dev[4i..4i+3],
  * key_dev[2i..2i+1]) for i < n.  For bitwise checks against the host. */

@@ -20,7 +20,8 @@ STATUS_NAMES = {0: "OK", 1: "INVALID_ARGUMENT", 2: "OUT_OF_MEMORY", 3: "DEVICE",
                 5: "UNSUPPORTED"}
 NUM_COUNTERS = 12
 NUM_KERNEL_IDS = 16
-KERNEL_NAMES = ["generate", "extend", "shade", "shadow", "accumulate", "resolve"]
+KERNEL_NAMES = ["generate", "extend", "shade", "shadow", "accumulate", "resolve", "cnn_prep",
+                "cnn_hr_in", "cnn_lr", "cnn_hr_out"]
 
 
 class MrsError(RuntimeError):
@@ -96,6 +97,15 @@ def lib():
         "mrs_set_count_work": ([I32], I32),
         "mrs_profile_enable": ([I32], I32),
         "mrs_profile_read": ([P, P], I32),
+        "mrs_net_num_params": ([], C.c_int64),
+        "mrs_net_create": ([C.POINTER(P)], I32),
+        "mrs_net_destroy": ([P], I32),
+        "mrs_net_init": ([P, U64], I32),
+        "mrs_net_set_params": ([P, P, C.c_int64], I32),
+        "mrs_net_get_params": ([P, P, C.c_int64], I32),
+        "mrs_fuse": ([P, P, P, P, I32, I32, P], I32),
+        "mrs_fuse_batch": ([P, I32, P, P, P, I32, I32, P], I32),
+        "mrs_debug_net_activation": ([P, I32, P, C.c_int64], I32),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(L, name)
@@ -117,7 +127,9 @@ def exported_symbols():
         "mrs_build_bvh", "mrs_render", "mrs_render_opts_default", "mrs_render_ex",
         "mrs_get_counters", "mrs_get_tuning", "mrs_set_tuning", "mrs_debug_philox",
         "mrs_debug_closest_hit", "mrs_debug_bvh", "mrs_set_count_work", "mrs_profile_enable",
-        "mrs_profile_read",
+        "mrs_profile_read", "mrs_net_num_params", "mrs_net_create", "mrs_net_destroy",
+        "mrs_net_init", "mrs_net_set_params", "mrs_net_get_params", "mrs_fuse", "mrs_fuse_batch",
+        "mrs_debug_net_activation",
     ]
 
 

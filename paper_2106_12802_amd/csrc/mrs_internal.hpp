@@ -120,6 +120,10 @@ enum KernelId {
   KID_SHADOW = 3,
   KID_ACCUMULATE = 4,
   KID_RESOLVE = 5,
+  KID_CNN_PREP = 6,
+  KID_CNN_HR = 7,
+  KID_CNN_LR = 8,
+  KID_CNN_REC = 9,
 };
 void prof_begin(int id, hipStream_t st);
 void prof_end(int id, hipStream_t st);
