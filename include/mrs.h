@@ -236,6 +236,19 @@ mrs_status mrs_fuse_batch(mrs_net* net, int32_t B, const float* hrls_rgb_dev,
                           const float* hrls_aux_dev, const float* lrhs_rgb_dev, int32_t W,
                           int32_t H, float* out_rgb_dev);
 
+/* ------------------------------------------------------------ metrics */
+
+/* Evaluation metrics of the paper (Sec. 5) between two FP32 device images of
+ * `count` values (pixels x channels, scene-linear):
+ *   out[0] = MSE of the sRGB values (Eq. 3: 0 for l <= 0, 12.92 l up to
+ *            0.0031308, 1.055 l^(1/2.4) - 0.055 below 1, then 1),
+ *   out[1] = PSNR = 10 log10(1 / out[0]) (peak 1; +inf when equal),
+ *   out[2] = RelMSE = mean of lambda1 (img - ref)^2 / (ref^2 + lambda2)
+ *            (the paper uses 0.5 and 0.01 on its dataset).
+ * FP64 accumulation in a fixed order; synchronises the stream. */
+mrs_status mrs_image_metrics(const float* img_dev, const float* ref_dev, int64_t count,
+                             double lambda1, double lambda2, double out[3]);
+
 /* ------------------------------------------------------- debug / test hooks */
 
 /* FP32 copy of an activation of the last forward on `net`: which 0 = F0,

@@ -21,7 +21,7 @@ STATUS_NAMES = {0: "OK", 1: "INVALID_ARGUMENT", 2: "OUT_OF_MEMORY", 3: "DEVICE",
 NUM_COUNTERS = 12
 NUM_KERNEL_IDS = 16
 KERNEL_NAMES = ["generate", "extend", "shade", "shadow", "accumulate", "resolve", "cnn_prep",
-                "cnn_hr_in", "cnn_lr", "cnn_hr_out"]
+                "cnn_hr_in", "cnn_lr", "cnn_hr_out", "train_fwd", "train_bwd", "train_adam"]
 
 
 class MrsError(RuntimeError):
@@ -106,6 +106,11 @@ def lib():
         "mrs_fuse": ([P, P, P, P, I32, I32, P], I32),
         "mrs_fuse_batch": ([P, I32, P, P, P, I32, I32, P], I32),
         "mrs_debug_net_activation": ([P, I32, P, C.c_int64], I32),
+        "mrs_image_metrics": ([P, P, C.c_int64, C.c_double, C.c_double, P], I32),
+        "mrs_net_loss_grad": ([P, I32, P, P, P, P, I32, I32, P, P, P], I32),
+        "mrs_train_step": ([P, I32, P, P, P, P, I32, I32, C.c_float, P], I32),
+        "mrs_net_get_state": ([P, P, P, P, C.c_int64, P], I32),
+        "mrs_net_set_state": ([P, P, P, P, C.c_int64, C.c_int64], I32),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(L, name)
@@ -129,7 +134,8 @@ def exported_symbols():
         "mrs_debug_closest_hit", "mrs_debug_bvh", "mrs_set_count_work", "mrs_profile_enable",
         "mrs_profile_read", "mrs_net_num_params", "mrs_net_create", "mrs_net_destroy",
         "mrs_net_init", "mrs_net_set_params", "mrs_net_get_params", "mrs_fuse", "mrs_fuse_batch",
-        "mrs_debug_net_activation",
+        "mrs_debug_net_activation", "mrs_image_metrics", "mrs_net_loss_grad", "mrs_train_step",
+        "mrs_net_get_state", "mrs_net_set_state",
     ]
 
 

@@ -325,6 +325,25 @@ mrs_status mrs_get_counters(int64_t out[MRS_NUM_COUNTERS], int32_t reset) {
   return get_counters(out, reset != 0, current_stream());
 }
 
+mrs_status mrs_image_metrics(const float* img, const float* ref, int64_t count, double lambda1,
+                             double lambda2, double out[3]) {
+  if (!img || !ref || !out || count <= 0)
+    return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_image_metrics: bad arguments");
+  if (!(lambda2 > 0.0)) return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_image_metrics: lambda2 <= 0");
+  static double* d_out = nullptr;
+  if (!d_out) MRS_TRY_HIP(hipMalloc(&d_out, sizeof(double) * 2));
+  hipStream_t st = current_stream();
+  mrs_status rc = image_metrics(img, ref, count, lambda1, lambda2, d_out, st);
+  if (rc != MRS_OK) return rc;
+  double h[2];
+  MRS_TRY_HIP(hipMemcpyAsync(h, d_out, sizeof h, hipMemcpyDeviceToHost, st));
+  MRS_TRY_HIP(hipStreamSynchronize(st));
+  out[0] = h[0];
+  out[1] = h[0] > 0.0 ? 10.0 * std::log10(1.0 / h[0]) : INFINITY;
+  out[2] = h[1];
+  return MRS_OK;
+}
+
 mrs_status mrs_set_count_work(int32_t on) {
   set_count_work(on != 0);
   return MRS_OK;

@@ -89,14 +89,10 @@ __device__ __forceinline__ bf16x8 load_chunk(const ConvArgs& p, int b, int y, in
   return ld8(ptr);
 }
 
+// Accumulates the 32 x (16 NT) output tile of one wave over the whole K.
 template <int NT>
-__global__ __launch_bounds__(256) void k_conv(ConvArgs p) {
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int M = p.B * p.H * p.W;
-  const int m0 = (blockIdx.x * 4 + wave) * 32;
-  if (m0 >= M) return;
-  const int n0 = blockIdx.y * (NT * 16);
+__device__ __forceinline__ void conv_mainloop(const ConvArgs& p, int M, int m0, int n0, int lane,
+                                              f32x4 (&acc)[2][NT]) {
   const int kq = lane >> 4, li = lane & 15;
   int pb[2], py[2], px[2];
   bool pv[2];
@@ -110,7 +106,6 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs p) {
     py[r] = t % p.H;
     pb[r] = t / p.H;
   }
-  f32x4 acc[2][NT];
 #pragma unroll
   for (int r = 0; r < 2; ++r)
 #pragma unroll
@@ -133,6 +128,19 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs p) {
       for (int j = 0; j < NT; ++j)
         acc[r][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[r], Bv[j], acc[r][j], 0, 0, 0);
   }
+}
+
+template <int NT>
+__global__ __launch_bounds__(256) void k_conv(ConvArgs p) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int M = p.B * p.H * p.W;
+  const int m0 = (blockIdx.x * 4 + wave) * 32;
+  if (m0 >= M) return;
+  const int n0 = blockIdx.y * (NT * 16);
+  f32x4 acc[2][NT];
+  conv_mainloop<NT>(p, M, m0, n0, lane, acc);
+  const int kq = lane >> 4, li = lane & 15;
 #pragma unroll
   for (int r = 0; r < 2; ++r) {
 #pragma unroll
@@ -150,6 +158,71 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs p) {
         if (p.res2) y += p.res2[(size_t)m * p.cout + n];
         if (p.out_f) p.out_f[(size_t)m * p.out_f_stride + n] = y;
         if (p.out_h) p.out_h[(size_t)m * p.out_h_stride + n] = f2bf(y);
+      }
+    }
+  }
+}
+
+// Data gradient of a conv: the same implicit GEMM over dY with the packed
+// transposed, flipped weights; the epilogue applies the backward of what
+// surrounds the conv (ReLU masks, residual sums, the (un)shuffle views).
+__device__ __forceinline__ bool pos_bf(uint16_t h) { return h != 0 && !(h & 0x8000u); }
+
+template <int NT>
+__global__ __launch_bounds__(256) void k_dgrad(ConvArgs p, BwdEpi e) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int M = p.B * p.H * p.W;
+  const int m0 = (blockIdx.x * 4 + wave) * 32;
+  if (m0 >= M) return;
+  const int n0 = blockIdx.y * (NT * 16);
+  f32x4 acc[2][NT];
+  conv_mainloop<NT>(p, M, m0, n0, lane, acc);
+  const int kq = lane >> 4, li = lane & 15;
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+      const int n = n0 + j * 16 + li;
+      if (n >= p.cout) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = m0 + r * 16 + kq * 4 + v;
+        if (m >= M) continue;
+        float y = acc[r][j][v] * e.scale;
+        if (e.mode == EPI_PLAIN) {
+          const size_t idx = (size_t)m * e.stride + n;
+          if (e.add1) y += e.add1[idx];
+          if (e.add2) y += e.add2[idx];
+          if (e.mask && !pos_bf(e.mask[idx])) y = 0.0f;
+          if (e.out_f) e.out_f[idx] = y;
+          if (e.out_h) e.out_h[idx] = f2bf(y * e.out_h_scale);
+        } else if (e.mode == EPI_REC_SPLIT) {  // this conv at HR; [shuffle(U) | h0]
+          const int x = m % p.W, t = m / p.W, yy = t % p.H, b = t / p.H;
+          if (n < e.c_split) {
+            const int hh = p.H / e.r, ww = p.W / e.r;
+            const size_t idx = ((size_t)(b * hh + yy / e.r) * ww + x / e.r) * e.stride2 +
+                               ((yy % e.r) * e.r + (x % e.r)) * e.c_split + n;
+            if (!pos_bf(e.mask[idx])) y = 0.0f;
+            e.out_h[idx] = f2bf(y);
+          } else {
+            e.out_f[(size_t)m * e.stride + (n - e.c_split)] = y;
+          }
+        } else {  // EPI_FUSE_SPLIT: this conv at LR; [fl | unshuffle(h0)]
+          if (n < e.c_split) {
+            const size_t idx = (size_t)m * e.c_split + n;
+            if (!pos_bf(e.mask[idx])) y = 0.0f;
+            e.out_h[idx] = f2bf(y);
+          } else {
+            const int X = m % p.W, t = m / p.W, Y = t % p.H, b = t / p.H;
+            const int cc = n - e.c_split, q = cc / e.stride, ch = cc - q * e.stride;
+            const int hy = Y * e.r + q / e.r, hx = X * e.r + q % e.r;
+            const size_t hidx = ((size_t)(b * p.H * e.r + hy) * (p.W * e.r) + hx) * e.stride + ch;
+            float v2 = y + e.add1[hidx];
+            if (!pos_bf(e.mask2[hidx])) v2 = 0.0f;
+            e.out_h2[hidx] = f2bf(v2);
+          }
+        }
       }
     }
   }
@@ -217,9 +290,242 @@ __global__ __launch_bounds__(256) void k_init(float* __restrict__ dst, int64_t n
   }
 }
 
+// Packed BF16 weights of the data-gradient conv of one layer: wt[c][k'],
+// k' = tap' * cinp_t + n, holding W[n][c][8 - tap'] (W[n][c][0] for 1x1).
+__global__ __launch_bounds__(256) void k_pack_t(const float* __restrict__ wm, int cout, int cin,
+                                                int ksz, int cinp_t, int kp_t, int coutp_t,
+                                                uint16_t* __restrict__ wt) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= (int64_t)coutp_t * kp_t) return;
+  const int c = (int)(i / kp_t), k = (int)(i % kp_t);
+  const int tap = k / cinp_t, n = k % cinp_t;
+  float v = 0.0f;
+  const int taps = ksz * ksz;
+  if (c < cin && n < cout && tap < taps) {
+    const int ft = taps - 1 - tap;
+    const int ky = ft / ksz, kx = ft % ksz;
+    v = wm[((size_t)(n * cin + c) * ksz + ky) * ksz + kx];
+  }
+  wt[i] = f2bf(v);
+}
+
+// Weight gradient, split over pixels: part[s][n][col] = sum over the pixels of
+// split s of dY[p][n] * X[p + off(tap)][c], col = tap * cin_p + c (the packed K
+// layout).  Per 32-pixel step the dY and X tiles are staged in LDS transposed
+// (pixels contiguous) so each MFMA operand is one 16-byte LDS read.
+constexpr int WG_LD = 40;  // LDS row length (32 pixels + 8 pad) in BF16
+
+template <int WNN, int WNC>
+__global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
+  constexpr int NN = 16 * WNN, NC = 64 * WNC;
+  __shared__ __attribute__((aligned(16))) uint16_t sY[NN * WG_LD];
+  __shared__ __attribute__((aligned(16))) uint16_t sX[NC * WG_LD];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int kq = lane >> 4, li = lane & 15;
+  const int wn = wave % WNN, wc = wave / WNN;
+  const int col0 = blockIdx.x * NC, n0 = blockIdx.y * NN;
+  const int p_begin = blockIdx.z * a.chunk;
+  const int p_end = min(a.npix, p_begin + a.chunk);
+  const ConvArgs& x = a.x;
+  const int cpt = x.cin_p >> 3;
+  f32x4 acc[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int pk = p_begin; pk < p_end; pk += 32) {
+    for (int ci = t; ci < 32 * (NN / 8); ci += 256) {
+      const int pix = ci / (NN / 8), cc = ci % (NN / 8);
+      const int pp = pk + pix, n = n0 + 8 * cc;
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (pp < p_end && n < a.dy_stride)
+        v = *reinterpret_cast<const uint4*>(a.dy + (size_t)pp * a.dy_stride + n);
+      const uint16_t* h = reinterpret_cast<const uint16_t*>(&v);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) sY[(8 * cc + e) * WG_LD + pix] = h[e];
+    }
+    for (int ci = t; ci < 32 * (NC / 8); ci += 256) {
+      const int pix = ci / (NC / 8), cc = ci % (NC / 8);
+      const int pp = pk + pix, col = col0 + 8 * cc;
+      bf16x8 v = zero8();
+      if (pp < p_end && col < x.kp) {
+        const int q = col >> 3;
+        const int tap = q / cpt, c = (q - tap * cpt) << 3;
+        const int px = pp % x.W, tt = pp / x.W, py = tt % x.H, pb = tt / x.H;
+        v = load_chunk(x, pb, py, px, tap, c);
+      }
+      const uint4 u = __builtin_bit_cast(uint4, v);
+      const uint16_t* h = reinterpret_cast<const uint16_t*>(&u);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) sX[(8 * cc + e) * WG_LD + pix] = h[e];
+    }
+    __syncthreads();
+    const bf16x8 A = ld8(sY + (wn * 16 + li) * WG_LD + 8 * kq);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const bf16x8 Bv = ld8(sX + (wc * 64 + j * 16 + li) * WG_LD + 8 * kq);
+      acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, Bv, acc[j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  float* out = a.part + (size_t)blockIdx.z * a.cout_p * x.kp;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int col = col0 + wc * 64 + j * 16 + li;
+    if (col >= x.kp) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int n = n0 + wn * 16 + kq * 4 + v;
+      if (n < a.cout_p) out[(size_t)n * x.kp + col] = acc[j][v];
+    }
+  }
+}
+
+// Bias gradient partials: bpart[s][n] = sum over the pixels of split s of dY[p][n].
+__global__ __launch_bounds__(256) void k_bias_partial(const uint16_t* __restrict__ dy,
+                                                      int dy_stride, int cout, int npix, int chunk,
+                                                      float* __restrict__ bpart) {
+  const int n = threadIdx.x;
+  if (n >= cout) return;
+  const int p0 = blockIdx.x * chunk, p1 = min(npix, p0 + chunk);
+  float s = 0.0f;
+  for (int p = p0; p < p1; ++p) {
+    const uint32_t u = (uint32_t)dy[(size_t)p * dy_stride + n] << 16;
+    s += __uint_as_float(u);
+  }
+  bpart[(size_t)blockIdx.x * cout + n] = s;
+}
+
+// Sum the split partials in order and scatter into the master gradient layout
+// [cout][cin][k][k] followed by the bias.
+__global__ __launch_bounds__(256) void k_grad_reduce(const float* __restrict__ part,
+                                                     const float* __restrict__ bpart, int splits,
+                                                     int cout, int cin, int ksz, int cin_p, int kp,
+                                                     int cout_p, float* __restrict__ g) {
+  const int64_t nw = (int64_t)cout * cin * ksz * ksz;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < nw) {
+    const int kx = (int)(i % ksz), ky = (int)((i / ksz) % ksz);
+    const int c = (int)((i / (ksz * ksz)) % cin), n = (int)(i / ((int64_t)ksz * ksz * cin));
+    const int col = (ky * ksz + kx) * cin_p + c;
+    float s = 0.0f;
+    for (int sp = 0; sp < splits; ++sp) s += part[((size_t)sp * cout_p + n) * kp + col];
+    g[i] = s;
+  } else if (i < nw + cout) {
+    const int n = (int)(i - nw);
+    float s = 0.0f;
+    for (int sp = 0; sp < splits; ++sp) s += bpart[(size_t)sp * cout + n];
+    g[i] = s;
+  }
+}
+
+// L1 loss pieces: FP64 partial sums of |y - t| per block; the gradient
+// sign(y - t) / N (sign(0) = 0) as BF16 in an 8-channel padded tensor.
+__global__ __launch_bounds__(256) void k_l1(const float* __restrict__ y,
+                                            const float* __restrict__ tgt, int64_t npix,
+                                            double inv_n, double* __restrict__ part,
+                                            uint16_t* __restrict__ g8) {
+  __shared__ double sh[256];
+  double s = 0.0;
+  for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < npix;
+       p += (int64_t)gridDim.x * 256) {
+    uint32_t w[4] = {0u, 0u, 0u, 0u};
+    for (int c = 0; c < 3; ++c) {
+      const float d = y[3 * p + c] - tgt[3 * p + c];
+      s += fabs((double)d);
+      const float gsgn = d > 0.0f ? 1.0f : (d < 0.0f ? -1.0f : 0.0f);
+      const uint32_t h = f2bf(gsgn * (float)inv_n);
+      w[c >> 1] |= h << (16 * (c & 1));
+    }
+    *reinterpret_cast<uint4*>(g8 + 8 * p) = make_uint4(w[0], w[1], w[2], w[3]);
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(256) void k_l1_final(const double* __restrict__ part, int nparts,
+                                                  double inv_n, double* __restrict__ loss) {
+  __shared__ double sh[256];
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nparts; b += 256) s += part[b];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *loss = sh[0] * inv_n;
+}
+
+// Adam (Kingma & Ba 2015, Algorithm 1) on the FP32 masters; c1 = 1 - b1^t,
+// c2 = 1 - b2^t are the bias corrections of step t.
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ w, const float* __restrict__ g,
+                                              float* __restrict__ m, float* __restrict__ v,
+                                              int64_t n, float lr, float b1, float b2, float eps,
+                                              float c1, float c2) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
 namespace {
 inline unsigned cdiv64(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 }  // namespace
+
+void launch_dgrad(const ConvArgs& a, const BwdEpi& e, int cout_p, hipStream_t st) {
+  const int64_t M = (int64_t)a.B * a.H * a.W;
+  const unsigned gx = cdiv64(M, 128);
+  if (cout_p >= 64) {
+    k_dgrad<4><<<dim3(gx, cout_p / 64), 256, 0, st>>>(a, e);
+  } else {
+    k_dgrad<1><<<dim3(gx, cout_p / 16), 256, 0, st>>>(a, e);
+  }
+}
+
+void launch_wgrad(const WgradArgs& a, int splits, hipStream_t st) {
+  if (a.cout_p >= 64) {
+    k_wgrad<4, 1><<<dim3(cdiv64(a.x.kp, 64), a.cout_p / 64, splits), 256, 0, st>>>(a);
+  } else {
+    k_wgrad<1, 4><<<dim3(cdiv64(a.x.kp, 256), a.cout_p / 16, splits), 256, 0, st>>>(a);
+  }
+}
+
+void launch_bias_partial(const uint16_t* dy, int dy_stride, int cout, int npix, int chunk,
+                         int splits, float* bpart, hipStream_t st) {
+  k_bias_partial<<<splits, 256, 0, st>>>(dy, dy_stride, cout, npix, chunk, bpart);
+}
+
+void launch_grad_reduce(const float* part, const float* bpart, int splits, const NetLayer& L,
+                        float* g, hipStream_t st) {
+  const int64_t n = (int64_t)L.cout * L.cin * L.k * L.k + L.cout;
+  k_grad_reduce<<<cdiv64(n, 256), 256, 0, st>>>(part, bpart, splits, L.cout, L.cin, L.k, L.cin_p,
+                                                 L.kp, L.cout_p, g);
+}
+
+void launch_pack_t(const float* wm, const NetLayer& L, uint16_t* wt, hipStream_t st) {
+  k_pack_t<<<cdiv64((int64_t)L.coutp_t * L.kp_t, 256), 256, 0, st>>>(
+      wm, L.cout, L.cin, L.k, L.cinp_t, L.kp_t, L.coutp_t, wt);
+}
+
+void launch_l1(const float* y, const float* tgt, int64_t npix, double* part, int nparts,
+               double* loss, uint16_t* g8, hipStream_t st) {
+  const double inv_n = 1.0 / (double)(3 * npix);
+  k_l1<<<nparts, 256, 0, st>>>(y, tgt, npix, inv_n, part, g8);
+  k_l1_final<<<1, 256, 0, st>>>(part, nparts, inv_n, loss);
+}
+
+void launch_adam(float* w, const float* g, float* m, float* v, int64_t n, float lr, float b1,
+                 float b2, float eps, float c1, float c2, hipStream_t st) {
+  k_adam<<<cdiv64(n, 256), 256, 0, st>>>(w, g, m, v, n, lr, b1, b2, eps, c1, c2);
+}
 
 void launch_conv(const ConvArgs& a, int cout_p, hipStream_t st) {
   const int64_t M = (int64_t)a.B * a.H * a.W;

@@ -112,6 +112,9 @@ mrs_status get_counters(int64_t* out, bool reset, hipStream_t st);
 void get_tuning(mrs_tuning* t);
 mrs_status set_tuning(const mrs_tuning* t);
 void set_count_work(bool on);
+// metrics.hip: out_dev[0] = sRGB MSE, out_dev[1] = RelMSE (FP64, device)
+mrs_status image_metrics(const float* img, const float* ref, int64_t n, double lam1, double lam2,
+                         double* out_dev, hipStream_t st);
 // prof.hip: HIP-event timing of kernel launches by id
 enum KernelId {
   KID_GENERATE = 0,
@@ -124,6 +127,9 @@ enum KernelId {
   KID_CNN_HR = 7,
   KID_CNN_LR = 8,
   KID_CNN_REC = 9,
+  KID_TRAIN_FWD = 10,
+  KID_TRAIN_BWD = 11,
+  KID_TRAIN_ADAM = 12,
 };
 void prof_begin(int id, hipStream_t st);
 void prof_end(int id, hipStream_t st);

@@ -1,5 +1,6 @@
 // Host side of the fusion network: layer table, parameters, forward pass.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -32,7 +33,7 @@ std::vector<NetLayer> make_layers() {
   specs.push_back({"up", NET_UPCH * NET_SCALE * NET_SCALE, NET_FEAT, 3, NET_FEAT});
   specs.push_back({"rec", 3, NET_UPCH + NET_FEAT, 3, NET_UPCH + NET_FEAT});
   std::vector<NetLayer> L;
-  int64_t off = 0, pk = 0;
+  int64_t off = 0, pk = 0, pkt = 0;
   for (const S& s : specs) {
     NetLayer l;
     l.name = s.name;
@@ -48,6 +49,18 @@ std::vector<NetLayer> make_layers() {
     off += s.cout;
     l.pk_off = pk;
     pk += (int64_t)l.cout_p * l.kp;
+    // data-gradient conv: reads dY with the channel count it is stored with
+    const std::string nm = s.name;
+    if (nm == "hrls" || nm == "lrhs") {
+      l.cinp_t = l.kp_t = l.coutp_t = 0;
+      l.pkt_off = -1;
+    } else {
+      l.cinp_t = nm == "rec" ? 8 : s.cout;
+      l.kp_t = round_up(s.k * s.k * l.cinp_t, 32);
+      l.coutp_t = s.cin >= 64 ? round_up(s.cin, 64) : round_up(s.cin, 16);
+      l.pkt_off = pkt;
+      pkt += (int64_t)l.coutp_t * l.kp_t;
+    }
     L.push_back(l);
   }
   return L;
@@ -233,11 +246,399 @@ mrs_status net_forward(mrs_net* net, int B, int H, int W, const float* hr, const
 }
 
 mrs_status net_refresh_packed(mrs_net* net, hipStream_t st) {
-  for (const NetLayer& L : net->layers)
+  for (const NetLayer& L : net->layers) {
     launch_pack(net->d_master + L.w_off, L, net->d_packed + L.pk_off, st);
+    if (L.pkt_off >= 0 && net->d_packed_t)
+      launch_pack_t(net->d_master + L.w_off, L, net->d_packed_t + L.pkt_off, st);
+  }
   MRS_TRY_HIP(hipGetLastError());
   return MRS_OK;
 }
+
+// ------------------------------------------------------------------ training
+
+namespace {
+
+struct TrainArena {
+  uint16_t *xh, *xl, *h0, *fl, *f0h, *rh[NET_NRES + 1], *th[NET_NRES], *U, *g8, *dU, *drh, *dth,
+      *df0h, *dflh, *dh0h;
+  float *f0f, *rf[2], *out, *dh0a, *dfdf, *drf[2];
+};
+
+constexpr int L1_PARTS = 256;
+
+int wgrad_splits(int64_t npix, int& chunk) {
+  int s = (int)std::min<int64_t>(256, std::max<int64_t>(1, npix / 256));
+  chunk = (int)(((npix + s - 1) / s + 31) / 32 * 32);
+  return (int)((npix + chunk - 1) / chunk);
+}
+
+mrs_status ensure_train(mrs_net* net, int B, int H, int W, TrainArena& A) {
+  const size_t P = (size_t)B * H * W, p = P / 16;
+  std::vector<std::pair<void**, size_t>> plan;
+  auto add = [&](void** ptr, size_t bytes) { plan.push_back({ptr, bytes}); };
+  add((void**)&A.xh, P * 16 * 2);
+  add((void**)&A.xl, p * 8 * 2);
+  add((void**)&A.h0, P * 64 * 2);
+  add((void**)&A.fl, p * 64 * 2);
+  add((void**)&A.f0f, p * 64 * 4);
+  add((void**)&A.f0h, p * 64 * 2);
+  for (int i = 1; i <= NET_NRES; ++i) add((void**)&A.rh[i], p * 64 * 2);
+  for (int i = 0; i < NET_NRES; ++i) add((void**)&A.th[i], p * 64 * 2);
+  add((void**)&A.rf[0], p * 64 * 4);
+  add((void**)&A.rf[1], p * 64 * 4);
+  add((void**)&A.U, p * 256 * 2);
+  add((void**)&A.out, P * 3 * 4);
+  add((void**)&A.g8, P * 8 * 2);
+  add((void**)&A.dU, p * 256 * 2);
+  add((void**)&A.dh0a, P * 64 * 4);
+  add((void**)&A.dfdf, p * 64 * 4);
+  add((void**)&A.drf[0], p * 64 * 4);
+  add((void**)&A.drf[1], p * 64 * 4);
+  add((void**)&A.drh, p * 64 * 2);
+  add((void**)&A.dth, p * 64 * 2);
+  add((void**)&A.df0h, p * 64 * 2);
+  add((void**)&A.dflh, p * 64 * 2);
+  add((void**)&A.dh0h, P * 64 * 2);
+  size_t total = 0;
+  for (auto& e : plan) total += align256(e.second);
+  hipStream_t st = current_stream();
+  if (total > net->train_bytes) {
+    if (net->d_train) {
+      MRS_TRY_HIP(hipStreamSynchronize(st));
+      (void)hipFree(net->d_train);
+    }
+    net->d_train = nullptr;
+    net->train_bytes = 0;
+    if (hipMalloc(&net->d_train, total) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(MRS_ERR_OUT_OF_MEMORY, "mrs_train_step: activation allocation failed");
+    }
+    net->train_bytes = total;
+  }
+  size_t off = 0;
+  for (auto& e : plan) {
+    *e.first = net->d_train + off;
+    off += align256(e.second);
+  }
+  A.rh[0] = A.f0h;
+  // split-K partials: the largest layer x split count at these sizes
+  size_t need_w = 0, need_b = 0;
+  for (const NetLayer& L : net->layers) {
+    const bool hr = !std::strcmp(L.name, "hrls") || !std::strcmp(L.name, "rec");
+    int chunk;
+    const int sp = wgrad_splits(hr ? (int64_t)P : (int64_t)p, chunk);
+    need_w = std::max(need_w, (size_t)sp * L.cout_p * L.kp);
+    need_b = std::max(need_b, (size_t)sp * L.cout);
+  }
+  if (need_w > net->wpart_floats) {
+    if (net->d_wpart) {
+      MRS_TRY_HIP(hipStreamSynchronize(st));
+      (void)hipFree(net->d_wpart);
+      (void)hipFree(net->d_bpart);
+    }
+    net->d_wpart = nullptr;
+    net->d_bpart = nullptr;
+    net->wpart_floats = 0;
+    if (hipMalloc(&net->d_wpart, sizeof(float) * need_w) != hipSuccess ||
+        hipMalloc(&net->d_bpart, sizeof(float) * std::max<size_t>(need_b, 256 * 256)) !=
+            hipSuccess) {
+      (void)hipGetLastError();
+      return fail(MRS_ERR_OUT_OF_MEMORY, "mrs_train_step: gradient scratch allocation failed");
+    }
+    net->wpart_floats = need_w;
+  }
+  return MRS_OK;
+}
+
+mrs_status ensure_train_state(mrs_net* net) {
+  if (net->d_grad) return MRS_OK;
+  const size_t n = (size_t)net->nparams;
+  if (hipMalloc(&net->d_grad, sizeof(float) * n) != hipSuccess ||
+      hipMalloc(&net->d_m, sizeof(float) * n) != hipSuccess ||
+      hipMalloc(&net->d_v, sizeof(float) * n) != hipSuccess ||
+      hipMalloc(&net->d_packed_t, sizeof(uint16_t) * net->npacked_t) != hipSuccess ||
+      hipMalloc(&net->d_loss, sizeof(double)) != hipSuccess ||
+      hipMalloc(&net->d_lpart, sizeof(double) * L1_PARTS) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(MRS_ERR_OUT_OF_MEMORY, "mrs_train_step: optimiser state allocation failed");
+  }
+  hipStream_t st = current_stream();
+  MRS_TRY_HIP(hipMemsetAsync(net->d_m, 0, sizeof(float) * n, st));
+  MRS_TRY_HIP(hipMemsetAsync(net->d_v, 0, sizeof(float) * n, st));
+  net->adam_step = 0;
+  return net_refresh_packed(net, st);
+}
+
+void wgrad(mrs_net* net, const NetLayer& L, const ConvArgs& x, const uint16_t* dy, int dy_stride,
+           hipStream_t st) {
+  WgradArgs w;
+  w.x = x;
+  w.dy = dy;
+  w.dy_stride = dy_stride;
+  w.cout_p = L.cout_p;
+  w.npix = x.B * x.H * x.W;
+  const int splits = wgrad_splits(w.npix, w.chunk);
+  w.part = net->d_wpart;
+  launch_wgrad(w, splits, st);
+  launch_bias_partial(dy, dy_stride, L.cout, w.npix, w.chunk, splits, net->d_bpart, st);
+  launch_grad_reduce(net->d_wpart, net->d_bpart, splits, L, net->d_grad + L.w_off, st);
+}
+
+ConvArgs tconv_args(const mrs_net* net, const NetLayer& L, int B, int H, int W,
+                    const uint16_t* dy) {
+  ConvArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.mode = VIEW_PLAIN;
+  a.a = dy;
+  a.ca = L.cinp_t;
+  a.B = B;
+  a.H = H;
+  a.W = W;
+  a.cin_p = L.cinp_t;
+  a.taps = L.k * L.k;
+  a.kp = L.kp_t;
+  a.w = net->d_packed_t + L.pkt_off;
+  a.bias = net->d_master + L.b_off;  // unused by the data-gradient epilogue
+  a.cout = L.cin;
+  a.res_scale = 1.0f;
+  return a;
+}
+
+BwdEpi plain_epi() {
+  BwdEpi e;
+  std::memset(&e, 0, sizeof e);
+  e.mode = EPI_PLAIN;
+  e.scale = 1.0f;
+  e.stride = NET_FEAT;
+  e.out_h_scale = 1.0f;
+  return e;
+}
+
+// Forward keeping every activation the backward pass reads.
+void forward_train(mrs_net* net, const TrainArena& A, int B, int H, int W, const float* hr,
+                   const float* aux, const float* lr, hipStream_t st) {
+  const std::vector<NetLayer>& Ls = net->layers;
+  const int h = H / NET_SCALE, w = W / NET_SCALE;
+  const int64_t P = (int64_t)B * H * W, p = P / 16;
+  launch_prep(P, p, hr, aux, lr, A.xh, A.xl, st);
+  ConvArgs a = base_args(net, Ls[0], B, H, W);
+  a.a = A.xh;
+  a.ca = 16;
+  a.relu = 1;
+  a.out_h = A.h0;
+  a.out_h_stride = NET_FEAT;
+  launch_conv(a, Ls[0].cout_p, st);
+  a = base_args(net, Ls[1], B, h, w);
+  a.a = A.xl;
+  a.ca = 8;
+  a.relu = 1;
+  a.out_h = A.fl;
+  a.out_h_stride = NET_FEAT;
+  launch_conv(a, Ls[1].cout_p, st);
+  a = base_args(net, Ls[2], B, h, w);
+  a.mode = VIEW_CONCAT_UNSHUFFLE;
+  a.a = A.fl;
+  a.ca = NET_FEAT;
+  a.b = A.h0;
+  a.cb = NET_FEAT;
+  a.r = NET_SCALE;
+  a.relu = 1;
+  a.out_f = A.f0f;
+  a.out_f_stride = NET_FEAT;
+  a.out_h = A.f0h;
+  a.out_h_stride = NET_FEAT;
+  launch_conv(a, Ls[2].cout_p, st);
+  for (int i = 0; i < NET_NRES; ++i) {
+    a = base_args(net, Ls[3 + 2 * i], B, h, w);
+    a.a = A.rh[i];
+    a.ca = NET_FEAT;
+    a.relu = 1;
+    a.out_h = A.th[i];
+    a.out_h_stride = NET_FEAT;
+    launch_conv(a, NET_FEAT, st);
+    a = base_args(net, Ls[4 + 2 * i], B, h, w);
+    a.a = A.th[i];
+    a.ca = NET_FEAT;
+    a.res = i == 0 ? A.f0f : A.rf[(i - 1) & 1];
+    a.res_scale = NET_RES_SCALE;
+    a.res2 = i == NET_NRES - 1 ? A.f0f : nullptr;
+    a.out_f = A.rf[i & 1];
+    a.out_f_stride = NET_FEAT;
+    a.out_h = A.rh[i + 1];
+    a.out_h_stride = NET_FEAT;
+    launch_conv(a, NET_FEAT, st);
+  }
+  const NetLayer& Lu = Ls[3 + 2 * NET_NRES];
+  const NetLayer& Lr = Ls[4 + 2 * NET_NRES];
+  a = base_args(net, Lu, B, h, w);
+  a.a = A.rh[NET_NRES];
+  a.ca = NET_FEAT;
+  a.relu = 1;
+  a.out_h = A.U;
+  a.out_h_stride = Lu.cout;
+  launch_conv(a, Lu.cout_p, st);
+  a = base_args(net, Lr, B, H, W);
+  a.mode = VIEW_SHUFFLE_CONCAT;
+  a.a = A.U;
+  a.ca = Lu.cout;
+  a.c0 = NET_UPCH;
+  a.r = NET_SCALE;
+  a.b = A.h0;
+  a.cb = NET_FEAT;
+  a.out_f = A.out;
+  a.out_f_stride = 3;
+  launch_conv(a, Lr.cout_p, st);
+}
+
+// Backward through the whole network from the BF16 output gradient A.g8;
+// writes every layer's gradient into net->d_grad.
+void backward(mrs_net* net, const TrainArena& A, int B, int H, int W, hipStream_t st) {
+  const std::vector<NetLayer>& Ls = net->layers;
+  const int h = H / NET_SCALE, w = W / NET_SCALE;
+  const NetLayer& Lu = Ls[3 + 2 * NET_NRES];
+  const NetLayer& Lr = Ls[4 + 2 * NET_NRES];
+  // rec: d[shuffle(U), h0] -> dU (masked by U > 0, LR layout) and dh0a (FP32)
+  {
+    ConvArgs a = tconv_args(net, Lr, B, H, W, A.g8);
+    BwdEpi e = plain_epi();
+    e.mode = EPI_REC_SPLIT;
+    e.stride = NET_FEAT;
+    e.out_f = A.dh0a;
+    e.out_h = A.dU;
+    e.mask = A.U;
+    e.c_split = NET_UPCH;
+    e.stride2 = Lu.cout;
+    e.r = NET_SCALE;
+    launch_dgrad(a, e, Lr.coutp_t, st);
+    ConvArgs x = base_args(net, Lr, B, H, W);
+    x.mode = VIEW_SHUFFLE_CONCAT;
+    x.a = A.U;
+    x.ca = Lu.cout;
+    x.c0 = NET_UPCH;
+    x.r = NET_SCALE;
+    x.b = A.h0;
+    x.cb = NET_FEAT;
+    wgrad(net, Lr, x, A.g8, 8, st);
+  }
+  // up: dFDF (FP32) and 0.1 dFDF (BF16) = gradient of the last trunk conv
+  {
+    ConvArgs a = tconv_args(net, Lu, B, h, w, A.dU);
+    BwdEpi e = plain_epi();
+    e.out_f = A.dfdf;
+    e.out_h = A.drh;
+    e.out_h_scale = NET_RES_SCALE;
+    launch_dgrad(a, e, Lu.coutp_t, st);
+    ConvArgs x = base_args(net, Lu, B, h, w);
+    x.a = A.rh[NET_NRES];
+    x.ca = NET_FEAT;
+    wgrad(net, Lu, x, A.dU, Lu.cout, st);
+  }
+  const float* dr = A.dfdf;
+  for (int i = NET_NRES - 1; i >= 0; --i) {
+    const NetLayer& La = Ls[3 + 2 * i];
+    const NetLayer& Lb = Ls[4 + 2 * i];
+    {  // conv b: dt = (W_b^T * 0.1 dr) masked by t > 0
+      ConvArgs a = tconv_args(net, Lb, B, h, w, A.drh);
+      BwdEpi e = plain_epi();
+      e.mask = A.th[i];
+      e.out_h = A.dth;
+      launch_dgrad(a, e, Lb.coutp_t, st);
+      ConvArgs x = base_args(net, Lb, B, h, w);
+      x.a = A.th[i];
+      x.ca = NET_FEAT;
+      wgrad(net, Lb, x, A.drh, NET_FEAT, st);
+    }
+    {  // conv a: dr_i = dr_{i+1} + W_a^T dt; at i = 0 add dFDF and mask by F0 > 0
+      ConvArgs a = tconv_args(net, La, B, h, w, A.dth);
+      BwdEpi e = plain_epi();
+      e.add1 = dr;
+      if (i > 0) {
+        e.out_f = A.drf[i & 1];
+        e.out_h = A.drh;
+        e.out_h_scale = NET_RES_SCALE;
+      } else {
+        e.add2 = A.dfdf;
+        e.mask = A.f0h;
+        e.out_h = A.df0h;
+      }
+      launch_dgrad(a, e, La.coutp_t, st);
+      ConvArgs x = base_args(net, La, B, h, w);
+      x.a = A.rh[i];
+      x.ca = NET_FEAT;
+      wgrad(net, La, x, A.dth, NET_FEAT, st);
+      dr = A.drf[i & 1];
+    }
+  }
+  // fuse: d[fl, unshuffle(h0)] -> dfl (masked) and dh0 = (dh0a + shuffle(.)) masked
+  {
+    const NetLayer& Lf = Ls[2];
+    ConvArgs a = tconv_args(net, Lf, B, h, w, A.df0h);
+    BwdEpi e = plain_epi();
+    e.mode = EPI_FUSE_SPLIT;
+    e.c_split = NET_FEAT;
+    e.stride = NET_FEAT;
+    e.mask = A.fl;
+    e.out_h = A.dflh;
+    e.add1 = A.dh0a;
+    e.mask2 = A.h0;
+    e.out_h2 = A.dh0h;
+    e.r = NET_SCALE;
+    launch_dgrad(a, e, Lf.coutp_t, st);
+    ConvArgs x = base_args(net, Lf, B, h, w);
+    x.mode = VIEW_CONCAT_UNSHUFFLE;
+    x.a = A.fl;
+    x.ca = NET_FEAT;
+    x.b = A.h0;
+    x.cb = NET_FEAT;
+    x.r = NET_SCALE;
+    wgrad(net, Lf, x, A.df0h, NET_FEAT, st);
+  }
+  {  // encoders: weight gradients only
+    ConvArgs x = base_args(net, Ls[1], B, h, w);
+    x.a = A.xl;
+    x.ca = 8;
+    wgrad(net, Ls[1], x, A.dflh, NET_FEAT, st);
+    x = base_args(net, Ls[0], B, H, W);
+    x.a = A.xh;
+    x.ca = 16;
+    wgrad(net, Ls[0], x, A.dh0h, NET_FEAT, st);
+  }
+}
+
+mrs_status check_train_args(mrs_net* n, int B, const float* hr, const float* aux,
+                            const float* lr, const float* tgt, int W, int H) {
+  if (!n) return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_train_step: net is NULL");
+  if (!hr || !aux || !lr || !tgt)
+    return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_train_step: NULL buffer");
+  if (B < 1 || W < 4 || H < 4 || W % 4 || H % 4 || (int64_t)B * W * H > (int64_t)1 << 26)
+    return fail(MRS_ERR_INVALID_ARGUMENT,
+                "mrs_train_step: W, H multiples of 4 (>= 4), B >= 1, B*W*H <= 2^26");
+  if (((uintptr_t)hr | (uintptr_t)aux | (uintptr_t)lr | (uintptr_t)tgt) & 3u)
+    return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_train_step: buffers must be 4-byte aligned");
+  if (!n->has_params) return fail(MRS_ERR_NOT_READY, "mrs_train_step: no parameters");
+  return MRS_OK;
+}
+
+mrs_status loss_and_grad(mrs_net* n, int B, const float* hr, const float* aux, const float* lr,
+                         const float* tgt, int W, int H, hipStream_t st) {
+  mrs_status rc = ensure_train_state(n);
+  if (rc != MRS_OK) return rc;
+  TrainArena A;
+  rc = ensure_train(n, B, H, W, A);
+  if (rc != MRS_OK) return rc;
+  prof_begin(KID_TRAIN_FWD, st);
+  forward_train(n, A, B, H, W, hr, aux, lr, st);
+  prof_end(KID_TRAIN_FWD, st);
+  launch_l1(A.out, tgt, (int64_t)B * H * W, n->d_lpart, L1_PARTS, n->d_loss, A.g8, st);
+  prof_begin(KID_TRAIN_BWD, st);
+  backward(n, A, B, H, W, st);
+  prof_end(KID_TRAIN_BWD, st);
+  MRS_TRY_HIP(hipGetLastError());
+  return MRS_OK;
+}
+
+}  // namespace
 
 }  // namespace mrs
 
@@ -255,6 +656,9 @@ mrs_status mrs_net_create(mrs_net** out) {
   const NetLayer& last = n->layers.back();
   n->nparams = last.b_off + last.cout;
   n->npacked = last.pk_off + (int64_t)last.cout_p * last.kp;
+  n->npacked_t = 0;
+  for (const NetLayer& L : n->layers)
+    if (L.pkt_off >= 0) n->npacked_t = std::max(n->npacked_t, L.pkt_off + (int64_t)L.coutp_t * L.kp_t);
   if (n->nparams != NET_NUM_PARAMS) {
     delete n;
     return fail(MRS_ERR_DEVICE, "mrs_net_create: internal layer table mismatch");
@@ -276,6 +680,10 @@ mrs_status mrs_net_destroy(mrs_net* n) {
   if (n->d_master) (void)hipFree(n->d_master);
   if (n->d_packed) (void)hipFree(n->d_packed);
   if (n->d_arena) (void)hipFree(n->d_arena);
+  for (void* p : {(void*)n->d_packed_t, (void*)n->d_grad, (void*)n->d_m, (void*)n->d_v,
+                  (void*)n->d_train, (void*)n->d_loss, (void*)n->d_lpart, (void*)n->d_wpart,
+                  (void*)n->d_bpart})
+    if (p) (void)hipFree(p);
   delete n;
   return MRS_OK;
 }
@@ -332,6 +740,93 @@ mrs_status mrs_fuse_batch(mrs_net* n, int32_t B, const float* hr, const float* a
 mrs_status mrs_fuse(mrs_net* n, const float* hr, const float* aux, const float* lr, int32_t W,
                     int32_t H, float* out) {
   return mrs_fuse_batch(n, 1, hr, aux, lr, W, H, out);
+}
+
+mrs_status mrs_net_loss_grad(mrs_net* n, int32_t B, const float* hr, const float* aux,
+                            const float* lr, const float* tgt, int32_t W, int32_t H,
+                            float* grad_host, double* loss_host, float* out_dev) {
+  mrs_status rc = check_train_args(n, B, hr, aux, lr, tgt, W, H);
+  if (rc != MRS_OK) return rc;
+  hipStream_t st = current_stream();
+  rc = loss_and_grad(n, B, hr, aux, lr, tgt, W, H, st);
+  if (rc != MRS_OK) return rc;
+  if (out_dev) {
+    const size_t P = (size_t)B * H * W;
+    TrainArena A;
+    rc = ensure_train(n, B, H, W, A);
+    if (rc != MRS_OK) return rc;
+    MRS_TRY_HIP(hipMemcpyAsync(out_dev, A.out, sizeof(float) * 3 * P, hipMemcpyDeviceToDevice, st));
+  }
+  if (grad_host)
+    MRS_TRY_HIP(hipMemcpyAsync(grad_host, n->d_grad, sizeof(float) * n->nparams,
+                               hipMemcpyDeviceToHost, st));
+  if (loss_host) MRS_TRY_HIP(hipMemcpyAsync(loss_host, n->d_loss, sizeof(double), hipMemcpyDeviceToHost, st));
+  MRS_TRY_HIP(hipStreamSynchronize(st));
+  return MRS_OK;
+}
+
+mrs_status mrs_train_step(mrs_net* n, int32_t B, const float* hr, const float* aux,
+                          const float* lr, const float* tgt, int32_t W, int32_t H, float lr_rate,
+                          double* loss_host) {
+  mrs_status rc = check_train_args(n, B, hr, aux, lr, tgt, W, H);
+  if (rc != MRS_OK) return rc;
+  if (!(lr_rate > 0.0f) || !std::isfinite(lr_rate))
+    return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_train_step: learning rate must be positive");
+  hipStream_t st = current_stream();
+  rc = loss_and_grad(n, B, hr, aux, lr, tgt, W, H, st);
+  if (rc != MRS_OK) return rc;
+  n->adam_step += 1;
+  const double t = (double)n->adam_step;
+  const float c1 = (float)(1.0 - std::pow(0.9, t)), c2 = (float)(1.0 - std::pow(0.999, t));
+  prof_begin(KID_TRAIN_ADAM, st);
+  launch_adam(n->d_master, n->d_grad, n->d_m, n->d_v, n->nparams, lr_rate, 0.9f, 0.999f, 1e-8f,
+              c1, c2, st);
+  rc = net_refresh_packed(n, st);
+  prof_end(KID_TRAIN_ADAM, st);
+  if (rc != MRS_OK) return rc;
+  if (loss_host) {
+    MRS_TRY_HIP(hipMemcpyAsync(loss_host, n->d_loss, sizeof(double), hipMemcpyDeviceToHost, st));
+    MRS_TRY_HIP(hipStreamSynchronize(st));
+  }
+  return MRS_OK;
+}
+
+mrs_status mrs_net_get_state(const mrs_net* n, float* params, float* m, float* v, int64_t count,
+                             int64_t* step) {
+  if (!n || !params || !m || !v || !step || count != n->nparams)
+    return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_net_get_state: bad arguments");
+  if (!n->has_params) return fail(MRS_ERR_NOT_READY, "mrs_net_get_state: no parameters");
+  hipStream_t st = current_stream();
+  const size_t b = sizeof(float) * count;
+  MRS_TRY_HIP(hipMemcpyAsync(params, n->d_master, b, hipMemcpyDeviceToHost, st));
+  if (n->d_m) {
+    MRS_TRY_HIP(hipMemcpyAsync(m, n->d_m, b, hipMemcpyDeviceToHost, st));
+    MRS_TRY_HIP(hipMemcpyAsync(v, n->d_v, b, hipMemcpyDeviceToHost, st));
+  } else {
+    std::memset(m, 0, b);
+    std::memset(v, 0, b);
+  }
+  MRS_TRY_HIP(hipStreamSynchronize(st));
+  *step = n->adam_step;
+  return MRS_OK;
+}
+
+mrs_status mrs_net_set_state(mrs_net* n, const float* params, const float* m, const float* v,
+                             int64_t count, int64_t step) {
+  if (!n || !params || !m || !v || count != n->nparams || step < 0)
+    return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_net_set_state: bad arguments");
+  hipStream_t st = current_stream();
+  MRS_TRY_HIP(hipMemcpyAsync(n->d_master, params, sizeof(float) * count, hipMemcpyHostToDevice, st));
+  n->has_params = true;
+  mrs_status rc = ensure_train_state(n);
+  if (rc != MRS_OK) return rc;
+  MRS_TRY_HIP(hipMemcpyAsync(n->d_m, m, sizeof(float) * count, hipMemcpyHostToDevice, st));
+  MRS_TRY_HIP(hipMemcpyAsync(n->d_v, v, sizeof(float) * count, hipMemcpyHostToDevice, st));
+  n->adam_step = step;
+  rc = net_refresh_packed(n, st);
+  if (rc != MRS_OK) return rc;
+  MRS_TRY_HIP(hipStreamSynchronize(st));
+  return MRS_OK;
 }
 
 mrs_status mrs_debug_net_activation(const mrs_net* n, int32_t which, float* out_host,

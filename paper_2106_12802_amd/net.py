@@ -49,6 +49,74 @@ class FusionNet:
                                        L.ptr(lrhs_rgb), W, H, L.ptr(out)))
         return out
 
+    @staticmethod
+    def _dims(hrls_rgb):
+        batched = hrls_rgb.dim() == 4
+        B = hrls_rgb.shape[0] if batched else 1
+        return B, hrls_rgb.shape[-3], hrls_rgb.shape[-2]
+
+    def loss_grad(self, hrls_rgb, hrls_aux, lrhs_rgb, target):
+        """(grad [num_params] float32, L1 loss (FP64), network output tensor); no update."""
+        import torch
+        B, H, W = self._dims(hrls_rgb)
+        g = np.empty(self.num_params, np.float32)
+        loss = C.c_double()
+        out = torch.empty(hrls_rgb.shape, dtype=torch.float32, device=hrls_rgb.device)
+        L.use_current_stream()
+        L.check(L.lib().mrs_net_loss_grad(self.handle, B, L.ptr(hrls_rgb), L.ptr(hrls_aux),
+                                          L.ptr(lrhs_rgb), L.ptr(target), W, H,
+                                          g.ctypes.data_as(C.c_void_p), C.byref(loss),
+                                          L.ptr(out)))
+        return g, loss.value, out
+
+    def train_step(self, hrls_rgb, hrls_aux, lrhs_rgb, target, lr=1e-4, want_loss=False):
+        """One Adam step on the L1 loss; returns the loss (synchronising) if want_loss."""
+        B, H, W = self._dims(hrls_rgb)
+        loss = C.c_double()
+        L.use_current_stream()
+        L.check(L.lib().mrs_train_step(self.handle, B, L.ptr(hrls_rgb), L.ptr(hrls_aux),
+                                       L.ptr(lrhs_rgb), L.ptr(target), W, H, float(lr),
+                                       C.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+    def get_state(self):
+        """(params, adam m, adam v, step) as host arrays: a resumable checkpoint."""
+        n = self.num_params
+        p, m, v = (np.empty(n, np.float32) for _ in range(3))
+        step = C.c_int64()
+        L.use_current_stream()
+        L.check(L.lib().mrs_net_get_state(self.handle, p.ctypes.data_as(C.c_void_p),
+                                          m.ctypes.data_as(C.c_void_p),
+                                          v.ctypes.data_as(C.c_void_p), n, C.byref(step)))
+        return p, m, v, step.value
+
+    def set_state(self, params, m, v, step):
+        arrs = [np.ascontiguousarray(a, np.float32) for a in (params, m, v)]
+        L.use_current_stream()
+        L.check(L.lib().mrs_net_set_state(self.handle, *[a.ctypes.data_as(C.c_void_p) for a in arrs],
+                                          self.num_params, int(step)))
+
+    def save(self, path):
+        """Checkpoint file: versioned header, FP32 params, Adam m and v, step, checksum."""
+        import hashlib
+        p, m, v, step = self.get_state()
+        body = p.tobytes() + m.tobytes() + v.tobytes()
+        header = np.array([0x4D52534E, 1, self.num_params, step], np.int64).tobytes()
+        with open(path, "wb") as f:
+            f.write(header + body + hashlib.sha256(header + body).digest())
+
+    def load(self, path):
+        import hashlib
+        raw = open(path, "rb").read()
+        header, body, digest = raw[:32], raw[32:-32], raw[-32:]
+        magic, version, n, step = np.frombuffer(header, np.int64)
+        if magic != 0x4D52534E or version != 1 or n != self.num_params:
+            raise ValueError("not a checkpoint of this network")
+        if hashlib.sha256(header + body).digest() != digest:
+            raise ValueError("checkpoint checksum mismatch")
+        arr = np.frombuffer(body, np.float32).reshape(3, n)
+        self.set_state(arr[0], arr[1], arr[2], int(step))
+
     def activation(self, which: int, shape):
         a = np.empty(int(np.prod(shape)), np.float32)
         L.check(L.lib().mrs_debug_net_activation(self.handle, which,

@@ -91,3 +91,94 @@ def test_fuse_not_ready_and_validation(torch_cuda):
     n.init(1)
     with pytest.raises(MrsError, match="multiples of 4"):
         n.fuse(torch.zeros(6, 8, 3, device="cuda"), torch.zeros(6, 8, 7, device="cuda"), lr)
+
+
+# --------------------------------------------------------------------------- training
+
+
+def _layer_slices():
+    from oracle import cnn
+    off = 0
+    out = []
+    for name, co, ci, k in cnn.layer_specs():
+        n = co * ci * k * k + co
+        out.append((name, off, off + n))
+        off += n
+    return out
+
+
+@pytest.mark.parametrize("B,H,W", [(2, 16, 24), (1, 32, 32)])
+def test_gradient_parity(torch_cuda, B, H, W):
+    """GPU backward (BF16 MFMA) vs the FP64 hand backward, same output gradient."""
+    import paper_2106_12802_amd as mrs
+    from oracle import cnn
+    torch = torch_cuda
+    net = mrs.FusionNet(seed=77)
+    hr, aux, lr = _inputs(H + W, B, H, W)
+    tgt = np.random.default_rng(B).gamma(1.0, 0.5, (B, H, W, 3)).astype(np.float32)
+    t = [torch.from_numpy(a).cuda() for a in (hr, aux, lr, tgt)]
+    g_gpu, loss_gpu, out_gpu = net.loss_grad(*t)
+    out_gpu = out_gpu.cpu().numpy().astype(np.float64)
+    params = net.get_params().astype(np.float64)
+    o, acts = cnn.forward(params, hr, aux, lr, keep=True)
+    assert loss_gpu == pytest.approx(np.abs(out_gpu - tgt).mean(), rel=1e-6)
+    assert abs(loss_gpu - cnn.l1_loss(o, tgt)) <= 5e-3 * cnn.l1_loss(o, tgt)
+    # the oracle's backward from the output gradient the GPU used (signs of its own output)
+    gout = np.sign(out_gpu - tgt) / out_gpu.size
+    g_ref = cnn.backward(params, acts, gout)
+    # Each BF16-stored gradient tensor adds ~2^-9 sqrt(2) = 2.8e-3 relative error;
+    # the encoders sit ~38 such tensors below the loss (rec, up, 32 trunk convs,
+    # fuse), so ~1.7e-2 in quadrature plus ReLU-mask disagreements between the
+    # BF16 and FP64 forwards: 4e-2 per layer, 1e-2 for the whole gradient.
+    errs = {}
+    for name, a, b in _layer_slices():
+        errs[name] = _rel_l2(g_gpu[a:b].astype(np.float64), g_ref[a:b])
+    e_all = _rel_l2(g_gpu.astype(np.float64), g_ref)
+    worst = max(errs, key=errs.get)
+    _log(f"grad {B}x{H}x{W}: rel L2 all {e_all:.2e}; worst {worst} {errs[worst]:.2e}; " +
+         " ".join(f"{k}:{v:.1e}" for k, v in errs.items() if not k.startswith("res") or k in
+                  ("res0a", "res7b", "res15b")))
+    assert all(v <= 4e-2 for v in errs.values()), errs
+    assert e_all <= 1e-2
+
+
+def test_adam_step_and_loss_decrease(torch_cuda):
+    import paper_2106_12802_amd as mrs
+    from oracle import cnn
+    torch = torch_cuda
+    net = mrs.FusionNet(seed=5)
+    hr, aux, lr = _inputs(1, 4, 32, 32)
+    tgt = (hr * 0.8 + 0.05).astype(np.float32)
+    t = [torch.from_numpy(a).cuda() for a in (hr, aux, lr, tgt)]
+    p0 = net.get_params().astype(np.float64)
+    g, _, _ = net.loss_grad(*t)
+    net.train_step(*t, lr=1e-4)
+    p1 = net.get_params().astype(np.float64)
+    want, _, _ = cnn.adam_step(p0, g.astype(np.float64), np.zeros_like(p0), np.zeros_like(p0), 1)
+    assert np.allclose(p1, want, rtol=1e-5, atol=2e-8)
+    losses = [net.train_step(*t, lr=1e-3, want_loss=True) for _ in range(60)]
+    _log(f"train losses {losses[0]:.4f} -> {losses[-1]:.4f}")
+    assert losses[-1] < 0.5 * losses[0]
+
+
+def test_checkpoint_resume_bitwise(torch_cuda, tmp_path):
+    import paper_2106_12802_amd as mrs
+    torch = torch_cuda
+    hr, aux, lr = _inputs(2, 2, 16, 16)
+    tgt = (hr * 0.5).astype(np.float32)
+    t = [torch.from_numpy(a).cuda() for a in (hr, aux, lr, tgt)]
+    a = mrs.FusionNet(seed=9)
+    for _ in range(6):
+        a.train_step(*t, lr=1e-3)
+    b = mrs.FusionNet(seed=9)
+    for _ in range(3):
+        b.train_step(*t, lr=1e-3)
+    b.save(str(tmp_path / "ck.bin"))
+    c = mrs.FusionNet()
+    c.load(str(tmp_path / "ck.bin"))
+    for _ in range(3):
+        c.train_step(*t, lr=1e-3)
+    pa, ma, va, sa = a.get_state()
+    pc, mc, vc, sc = c.get_state()
+    assert sa == sc == 6
+    assert np.array_equal(pa, pc) and np.array_equal(ma, mc) and np.array_equal(va, vc)
