@@ -152,8 +152,13 @@ def forward(params, hrls_rgb, hrls_aux, lrhs_rgb, keep=False):
     return (out, acts) if keep else out
 
 
+def clip_target(target):
+    """Training targets are clipped to [0, 100] (Sec. 3.2: firefly outliers)."""
+    return np.clip(np.asarray(target, np.float64), 0.0, 100.0)
+
+
 def l1_loss(out, target):
-    return np.abs(out - target).mean()
+    return np.abs(out - clip_target(target)).mean()
 
 
 def backward(params, acts, gout):
@@ -186,8 +191,8 @@ def backward(params, acts, gout):
 
 
 def l1_grad(out, target):
-    """d mean|out - target| / d out with sign(0) = 0."""
-    return np.sign(out - target) / out.size
+    """d mean|out - clip(target)| / d out with sign(0) = 0."""
+    return np.sign(out - clip_target(target)) / out.size
 
 
 def adam_step(params, grads, m, v, step, lr=1e-4, b1=0.9, b2=0.999, eps=1e-8):
