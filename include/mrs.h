@@ -175,7 +175,7 @@ mrs_status mrs_set_count_work(int32_t on);
  * 0 generate, 1 extend (closest hit), 2 shade, 3 shadow (any hit),
  * 4 accumulate, 5 resolve, 6 network input preparation, 7 network HR input conv,
  * 8 network LR convs (lrhs, fuse, trunk, up), 9 network HR output conv,
- * 10..15 reserved.
+ * 10 training forward, 11 training backward, 12 Adam + weight refresh, 13..15 reserved.
  * mrs_profile_enable(1) clears the totals and starts recording;
  * mrs_profile_read synchronises and returns, per id, the summed milliseconds
  * and the launch count of the launches recorded so far. */
@@ -235,6 +235,34 @@ mrs_status mrs_fuse(mrs_net* net, const float* hrls_rgb_dev, const float* hrls_a
 mrs_status mrs_fuse_batch(mrs_net* net, int32_t B, const float* hrls_rgb_dev,
                           const float* hrls_aux_dev, const float* lrhs_rgb_dev, int32_t W,
                           int32_t H, float* out_rgb_dev);
+
+/* One training step: forward on B frames (saving activations), L1 loss
+ * mean |I_SR - clip(target, 0, 100)| reduced in FP64, backward through every
+ * layer (BF16 MFMA data and weight gradients, FP32 accumulation), then Adam
+ * (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) on the FP32 masters and
+ * a refresh of the BF16 copies.  Buffers as for mrs_fuse_batch plus target_dev
+ * B*H*W*3.  If loss_host is not NULL the stream is synchronised and the loss
+ * of this step (before the update) is written there.  B*W*H <= 2^26. */
+mrs_status mrs_train_step(mrs_net* net, int32_t B, const float* hrls_rgb_dev,
+                          const float* hrls_aux_dev, const float* lrhs_rgb_dev,
+                          const float* target_dev, int32_t W, int32_t H, float lr,
+                          double* loss_host);
+
+/* Forward + loss + backward without an update: the FP32 gradient of every
+ * parameter (MRS_NET_NUM_PARAMS, master layout) to grad_host, the loss to
+ * loss_host and the network output to out_dev (each optional).  Synchronises. */
+mrs_status mrs_net_loss_grad(mrs_net* net, int32_t B, const float* hrls_rgb_dev,
+                             const float* hrls_aux_dev, const float* lrhs_rgb_dev,
+                             const float* target_dev, int32_t W, int32_t H, float* grad_host,
+                             double* loss_host, float* out_dev);
+
+/* Checkpoint state: FP32 masters, Adam first and second moments, step count
+ * (host arrays of `count` = MRS_NET_NUM_PARAMS floats).  set_state then
+ * continuing is bitwise the same as never having stopped. */
+mrs_status mrs_net_get_state(const mrs_net* net, float* params, float* adam_m, float* adam_v,
+                             int64_t count, int64_t* step);
+mrs_status mrs_net_set_state(mrs_net* net, const float* params, const float* adam_m,
+                             const float* adam_v, int64_t count, int64_t step);
 
 /* ------------------------------------------------------------ metrics */
 

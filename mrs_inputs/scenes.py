@@ -290,7 +290,7 @@ def cornell(seed: int = 1) -> Scene:
 
 
 def procedural(seed: int = 7, spheres=((4, 5), (3, 4)), n_boxes: int = 20,
-               n_lights: int = 3, env: float = 0.2) -> Scene:
+               n_lights: int = 3, env: float = 0.2, random_camera: bool = False) -> Scene:
     """Ground plane, displaced icospheres, boxes and quad lights.
 
     `spheres` lists (count, subdivision level) groups.  The defaults give
@@ -320,6 +320,13 @@ def procedural(seed: int = 7, spheres=((4, 5), (3, 4)), n_boxes: int = 20,
         col = rng.uniform(0.8, 1.0, 3)
         b.add_light((cxz[0] - a / 2, h, cxz[1] - w / 2), (a, 0, 0), (0, 0, w), inten * col)
     cam = Camera((0.0, 3.0, 10.0), (0.0, 0.8, 0.0), (0.0, 1.0, 0.0), 40.0)
+    if random_camera:  # orbit the scene: azimuth, elevation and distance from the seed
+        az = rng.uniform(0, 2 * np.pi)
+        el = rng.uniform(0.15, 0.6)
+        dist = rng.uniform(7.0, 11.0)
+        pos = (dist * np.cos(el) * np.sin(az), dist * np.sin(el) + 0.5, dist * np.cos(el) * np.cos(az))
+        cam = Camera(tuple(float(v) for v in pos), (0.0, 0.8, 0.0), (0.0, 1.0, 0.0),
+                     float(rng.uniform(35.0, 50.0)))
     return b.build((env, env, env), cam, f"procedural_{seed}", {"seed": seed})
 
 
@@ -338,9 +345,9 @@ def sphere_plan(target_tris: int):
     return tuple(plan) or ((1, 2),)
 
 
-def procedural_sized(seed: int, target_tris: int) -> Scene:
+def procedural_sized(seed: int, target_tris: int, random_camera: bool = True) -> Scene:
     """Procedural scene whose triangle count approximates `target_tris`."""
-    sc = procedural(seed, spheres=sphere_plan(target_tris))
+    sc = procedural(seed, spheres=sphere_plan(target_tris), random_camera=random_camera)
     sc.name = f"procedural_sized_{seed}_{target_tris}"
     sc.meta = {"seed": seed, "target_tris": int(target_tris)}
     return sc
@@ -412,3 +419,18 @@ def random_rays(seed: int, n: int, spread: float = 1.0):
     d = tgt - o
     d /= np.linalg.norm(d, axis=1, keepdims=True)
     return o.astype(np.float32), d.astype(np.float32)
+
+
+def training_scene_specs(first_seed: int, count: int, tri_lo: int = 10_000, tri_hi: int = 200_000):
+    """(seed, triangle budget) pairs, budgets log-uniform in [tri_lo, tri_hi]."""
+    rng = np.random.default_rng(first_seed * 7919 + count)
+    logs = rng.uniform(np.log(tri_lo), np.log(tri_hi), count)
+    return [(first_seed + i, int(np.exp(v))) for i, v in enumerate(logs)]
+
+
+def training_windows(seed: int, count: int, W: int = 1280, H: int = 720, size: int = 128):
+    """`count` window origins (x0, y0), multiples of 4, of size x size windows in W x H."""
+    rng = np.random.default_rng(seed + 99_991)
+    xs = rng.integers(0, (W - size) // 4 + 1, count) * 4
+    ys = rng.integers(0, (H - size) // 4 + 1, count) * 4
+    return list(zip(xs.tolist(), ys.tolist()))

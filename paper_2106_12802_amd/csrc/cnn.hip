@@ -417,7 +417,7 @@ __global__ __launch_bounds__(256) void k_grad_reduce(const float* __restrict__ p
   }
 }
 
-// L1 loss pieces: FP64 partial sums of |y - t| per block; the gradient
+// L1 loss pieces (t clipped to [0, 100]): FP64 partial sums of |y - t| per block; the gradient
 // sign(y - t) / N (sign(0) = 0) as BF16 in an 8-channel padded tensor.
 __global__ __launch_bounds__(256) void k_l1(const float* __restrict__ y,
                                             const float* __restrict__ tgt, int64_t npix,
@@ -429,7 +429,8 @@ __global__ __launch_bounds__(256) void k_l1(const float* __restrict__ y,
        p += (int64_t)gridDim.x * 256) {
     uint32_t w[4] = {0u, 0u, 0u, 0u};
     for (int c = 0; c < 3; ++c) {
-      const float d = y[3 * p + c] - tgt[3 * p + c];
+      // targets are clipped to [0, 100] like the training data (fireflies, Sec. 3.2)
+      const float d = y[3 * p + c] - fminf(fmaxf(tgt[3 * p + c], 0.0f), 100.0f);
       s += fabs((double)d);
       const float gsgn = d > 0.0f ? 1.0f : (d < 0.0f ? -1.0f : 0.0f);
       const uint32_t h = f2bf(gsgn * (float)inv_n);

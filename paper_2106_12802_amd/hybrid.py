@@ -1,0 +1,237 @@
+"""The hybrid multi-resolution frame and the learned part around it.
+
+* hybrid_frame: HRLS (W x H, 4 spp, features) + LRHS (W/4 x H/4, 64 spp) +
+  fusion network -> I_SR (paper Sec. 4), each step a libmrs call.
+* build_dataset / train: training pairs rendered by the tracer itself
+  (HRLS/LRHS windows against 1024-spp FP64-accumulated targets) and Adam on the
+  L1 loss (libmrs mrs_train_step).
+* equal_psnr: the plain-render spp whose PSNR (against an independent-seed
+  reference) equals the hybrid frame's, and the time that render takes.
+
+Seeds: HRLS 2s, LRHS 2s+1 for frame seed s; references and targets use seeds
+at or above 2^40 so that no path is shared with the inputs.
+"""
+from __future__ import annotations
+
+import math
+import time
+
+import numpy as np
+
+from . import tracer as T
+from .metrics import image_metrics
+from .net import FusionNet
+
+SCALE = 4
+DEPTH = 8
+REF_SEED = 1 << 40
+
+
+def _empty(shape):
+    import torch
+    return torch.empty(shape, dtype=torch.float32, device="cuda")
+
+
+def render_inputs(gs, W, H, seed, spp_h=4, spp_l=64, depth=DEPTH, window=None):
+    """HRLS rgb + features and LRHS rgb of one frame (or of a window whose origin and
+    size are multiples of 4; the LRHS window is the corresponding quarter-size one)."""
+    if window is None:
+        x0, y0, w, h = 0, 0, W, H
+    else:
+        x0, y0, w, h = window
+    hr_rgb, hr_aux = _empty((h, w, 3)), _empty((h, w, 7))
+    lr_rgb = _empty((h // SCALE, w // SCALE, 3))
+    T.render_ex(gs, W, H, spp_h, depth, 2 * seed, hr_rgb, hr_aux,
+                window=None if window is None else (x0, y0, w, h))
+    T.render_ex(gs, W // SCALE, H // SCALE, spp_l, depth, 2 * seed + 1, lr_rgb, None,
+                window=None if window is None else
+                (x0 // SCALE, y0 // SCALE, w // SCALE, h // SCALE))
+    return hr_rgb, hr_aux, lr_rgb
+
+
+def hybrid_frame(gs, net: FusionNet, W, H, seed, spp_h=4, spp_l=64, depth=DEPTH, out=None):
+    hr_rgb, hr_aux, lr_rgb = render_inputs(gs, W, H, seed, spp_h, spp_l, depth)
+    out = net.fuse(hr_rgb, hr_aux, lr_rgb, out=out)
+    return out, (hr_rgb, hr_aux, lr_rgb)
+
+
+def reference(gs, W, H, spp=1024, seed=REF_SEED, depth=DEPTH, window=None):
+    """High-spp reference render (FP64 per-pixel sums from 1024 spp)."""
+    if window is None:
+        out = _empty((H, W, 3))
+    else:
+        out = _empty((window[3], window[2], 3))
+    T.render_ex(gs, W, H, spp, depth, seed, out, None, window=window)
+    return out
+
+
+# ---------------------------------------------------------------- training data
+
+
+class PairSet:
+    """Training pairs resident on the GPU: HRLS rgb/features, LRHS rgb, target."""
+
+    def __init__(self, hr_rgb, hr_aux, lr_rgb, target):
+        self.hr_rgb, self.hr_aux, self.lr_rgb, self.target = hr_rgb, hr_aux, lr_rgb, target
+
+    def __len__(self):
+        return self.hr_rgb.shape[0]
+
+    def batch(self, idx):
+        import torch
+        i = torch.as_tensor(idx, device="cuda", dtype=torch.long)
+        return [t.index_select(0, i).contiguous() for t in
+                (self.hr_rgb, self.hr_aux, self.lr_rgb, self.target)]
+
+
+def build_dataset(first_seed=100, n_scenes=64, windows=16, size=128, W=1280, H=720,
+                  spp=(4, 64, 1024), tri_range=(10_000, 200_000), depth=DEPTH, log=print):
+    """Render `n_scenes` x `windows` training pairs of size x size HR pixels."""
+    import torch
+    from mrs_inputs import scenes as S
+    N = n_scenes * windows
+    hr_rgb = _empty((N, size, size, 3))
+    hr_aux = _empty((N, size, size, 7))
+    lr_rgb = _empty((N, size // SCALE, size // SCALE, 3))
+    target = _empty((N, size, size, 3))
+    t0 = time.perf_counter()
+    k = 0
+    for si, (seed, tris) in enumerate(S.training_scene_specs(first_seed, n_scenes, *tri_range)):
+        scene = S.procedural_sized(seed, tris)
+        gs = T.GpuScene(scene)
+        for (x0, y0) in S.training_windows(seed, windows, W, H, size):
+            fseed = seed * 1000 + k % windows
+            win = (x0, y0, size, size)
+            T.render_ex(gs, W, H, spp[0], depth, 2 * fseed, hr_rgb[k], hr_aux[k], window=win)
+            T.render_ex(gs, W // SCALE, H // SCALE, spp[1], depth, 2 * fseed + 1, lr_rgb[k], None,
+                        window=(x0 // SCALE, y0 // SCALE, size // SCALE, size // SCALE))
+            T.render_ex(gs, W, H, spp[2], depth, REF_SEED + fseed, target[k], None, window=win)
+            k += 1
+        torch.cuda.synchronize()
+        gs.close()
+        if log and (si % 8 == 7 or si == n_scenes - 1):
+            log(f"[data] {si + 1}/{n_scenes} scenes, {k} pairs, {time.perf_counter() - t0:.1f} s")
+    return PairSet(hr_rgb, hr_aux, lr_rgb, target)
+
+
+def train(net: FusionNet, data: PairSet, steps: int, batch=16, lr=1e-4, seed=0,
+          log_every=200, log=print, time_limit=None, start_step=0):
+    """Adam on the L1 loss over random batches; the batch order is a pure function of
+    (seed, step), so a run resumed from a checkpoint at step s continues identically."""
+    losses = []
+    t0 = time.perf_counter()
+    done = start_step
+    for step in range(start_step, steps):
+        idx = np.random.default_rng([seed, step]).choice(len(data), batch, replace=False)
+        want = (step + 1) % log_every == 0 or step == steps - 1
+        loss = net.train_step(*data.batch(idx), lr=lr, want_loss=want)
+        done = step + 1
+        if want:
+            losses.append((done, loss))
+            if log:
+                log(f"[train] step {done} loss {loss:.5f} ({time.perf_counter() - t0:.1f} s)")
+        if time_limit is not None and time.perf_counter() - t0 > time_limit:
+            break
+    return losses, done
+
+
+# ---------------------------------------------------------------- equal PSNR
+
+
+def equal_psnr(psnr_target, plain):
+    """plain: [(spp, psnr, ms)] increasing in spp.  Returns (spp*, ms*) where the PSNR
+    interpolated linearly in log2(spp) reaches psnr_target (ms interpolated linearly in
+    spp), or None if the target lies outside the measured range."""
+    for (n0, p0, t0), (n1, p1, t1) in zip(plain, plain[1:]):
+        if (p0 - psnr_target) * (p1 - psnr_target) <= 0 and p1 != p0:
+            a = (psnr_target - p0) / (p1 - p0)
+            n = 2 ** (math.log2(n0) + a * (math.log2(n1) - math.log2(n0)))
+            t = t0 + (n - n0) / (n1 - n0) * (t1 - t0)
+            return n, t
+    return None
+
+
+def time_ms(fn, reps=3):
+    import torch
+    torch.cuda.synchronize()
+    fn()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t) * 1e3 / reps
+
+
+def evaluate_scene(gs, net, W=1280, H=720, seed=0, plain_spp=(4, 8, 16, 32, 64, 128, 256),
+                   ref_spp=1024, reps=3):
+    """PSNR/time of the hybrid frame, its baselines and plain renders for one scene."""
+    import torch
+    ref = reference(gs, W, H, ref_spp, REF_SEED + seed)
+    out = _empty((H, W, 3))
+    res = {}
+    t_h = time_ms(lambda: hybrid_frame(gs, net, W, H, seed, out=out), reps)
+    hybrid_frame(gs, net, W, H, seed, out=out)
+    res["hybrid"] = {"psnr": image_metrics(out, ref)["psnr"], "ms": t_h}
+    hr_rgb, hr_aux, lr_rgb = render_inputs(gs, W, H, seed)
+    up = torch.nn.functional.interpolate(lr_rgb.permute(2, 0, 1)[None], scale_factor=SCALE,
+                                         mode="bilinear", align_corners=False)[0].permute(1, 2, 0)
+    res["hrls_4spp"] = {"psnr": image_metrics(hr_rgb, ref)["psnr"]}
+    res["lrhs_bilinear"] = {"psnr": image_metrics(up.contiguous(), ref)["psnr"]}
+    plain = []
+    img = _empty((H, W, 3))
+    for n in plain_spp:
+        ms = time_ms(lambda: T.render_ex(gs, W, H, n, DEPTH, 2 * seed + 7919, img, None), reps)
+        T.render_ex(gs, W, H, n, DEPTH, 2 * seed + 7919, img, None)
+        plain.append((n, image_metrics(img, ref)["psnr"], ms))
+    res["plain"] = plain
+    eq = equal_psnr(res["hybrid"]["psnr"], plain)
+    res["equal_psnr"] = None if eq is None else {"spp": eq[0], "ms": eq[1],
+                                                 "ratio": t_h / eq[1]}
+    return res
+
+
+def main(argv=None):
+    """Render the training set, train the network, save a checkpoint, evaluate."""
+    import argparse
+    import json
+    import sys
+
+    import torch
+    from mrs_inputs import scenes as S
+
+    ap = argparse.ArgumentParser(description=main.__doc__)
+    ap.add_argument("--scenes", type=int, default=64)
+    ap.add_argument("--windows", type=int, default=16)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--time-limit", type=float, default=None, help="seconds of training at most")
+    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--lr", type=float, default=1e-4)
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--out", default="fusion_checkpoint.bin")
+    ap.add_argument("--eval-scenes", type=int, default=4)
+    ap.add_argument("--eval-size", default="640x360")
+    args = ap.parse_args(argv)
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)
+    torch.cuda.set_device(0)
+    data = build_dataset(n_scenes=args.scenes, windows=args.windows, log=log)
+    net = FusionNet(seed=args.seed)
+    losses, done = train(net, data, args.steps, args.batch, args.lr, seed=args.seed, log=log,
+                         time_limit=args.time_limit)
+    net.save(args.out)
+    log(f"[train] saved {args.out} after {done} steps")
+    del data
+    W, H = (int(v) for v in args.eval_size.split("x"))
+    results = []
+    for seed, tris in S.training_scene_specs(200, args.eval_scenes):
+        gs = T.GpuScene(S.procedural_sized(seed, tris))
+        r = evaluate_scene(gs, net, W, H, seed, plain_spp=(4, 8, 16, 32, 64), reps=1)
+        results.append(r)
+        log(f"[eval] scene {seed}: hybrid {r['hybrid']['psnr']:.2f} dB, "
+            f"hrls {r['hrls_4spp']['psnr']:.2f}, lrhs-bilinear {r['lrhs_bilinear']['psnr']:.2f}, "
+            f"plain " + " ".join(f"{n}:{p:.2f}" for n, p, _ in r["plain"]))
+    print(json.dumps({"steps": done, "losses": losses[-5:], "eval": results}))
+
+
+if __name__ == "__main__":
+    main()
