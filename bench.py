@@ -116,7 +116,7 @@ def pmc_summary(fetch_path, write_path, out_path):
     hbm = f_kib * 1024.0 * fs + w_kib * 1024.0 * ws
     lines = [
         "# HBM traffic of k_extend<false> (closest-hit traversal), procedural scene seed 7",
-        "# (97,528 triangles), hybrid frame HRLS 1280x720@4 + LRHS 320x180@64, max depth 8.",
+        "# (101,446 triangles), hybrid frame HRLS 1280x720@4 + LRHS 320x180@64, max depth 8.",
         "# Made by (each pass its own process, run from the repository root):",
         "#   rocprofv3 --pmc FETCH_SIZE -f csv -d gpurun_out/pmc_fetch -o pmc -- python bench.py "
         "--steps 1 --warmup 0 --no-cpu-baseline --copy-calibration",
@@ -241,7 +241,7 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "hybrid frame render: procedural scene (seed 7, 97,528 triangles, "
+        "config": {"workload": "hybrid frame render: procedural scene (seed 7, 101,446 triangles, "
                                "Lambert+GGX, 3 quad lights, env 0.2), HRLS 1280x720@4spp + LRHS "
                                "320x180@64spp, max depth 8, RR from vertex 3",
                    "paths_per_frame": paths, "triangles": scene.num_tris},

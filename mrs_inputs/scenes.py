@@ -98,6 +98,7 @@ class _Builder:
         return sum(len(x) for x in self.v)
 
     def add_tris(self, verts, mat, normals=None):
+        """Append triangles; `mat` is one material index or one per triangle."""
         verts = np.asarray(verts, dtype=np.float32).reshape(-1, 3, 3)
         first = self.ntris
         self.v.append(verts)
@@ -107,7 +108,38 @@ class _Builder:
         else:
             self.n.append(np.asarray(normals, np.float32).reshape(-1, 3, 3))
             self.f.append(np.full(len(verts), FLAG_SMOOTH, np.uint32))
-        self.m.append(np.full(len(verts), mat, np.uint32))
+        self.m.append(np.broadcast_to(np.asarray(mat, np.uint32), (len(verts),)).copy())
+        return first
+
+    def add_grid(self, corner, eu, ev, nu, nv, mats):
+        """nu x nv quads tiling the parallelogram, materials in a checkerboard."""
+        c = np.asarray(corner, np.float64)
+        eu = np.asarray(eu, np.float64) / nu
+        ev = np.asarray(ev, np.float64) / nv
+        tris, ms = [], []
+        for i in range(nu):
+            for j in range(nv):
+                q = c + i * eu + j * ev
+                tris += [[q, q + eu, q + eu + ev], [q, q + eu + ev, q + ev]]
+                ms += [mats[(i + j) % len(mats)]] * 2
+        return self.add_tris(np.array(tris), np.array(ms))
+
+    def add_box_grid(self, center, size, yaw, mats, n=2):
+        """Box rotated by `yaw` about +y, each face an n x n checkerboard, outward winding."""
+        sx, sy, sz = (0.5 * float(v) for v in size)
+        faces = [((sx, -sy, -sz), (0, 2 * sy, 0), (0, 0, 2 * sz)),
+                 ((-sx, -sy, -sz), (0, 0, 2 * sz), (0, 2 * sy, 0)),
+                 ((-sx, sy, -sz), (0, 0, 2 * sz), (2 * sx, 0, 0)),
+                 ((-sx, -sy, -sz), (2 * sx, 0, 0), (0, 0, 2 * sz)),
+                 ((-sx, -sy, sz), (2 * sx, 0, 0), (0, 2 * sy, 0)),
+                 ((-sx, -sy, -sz), (0, 2 * sy, 0), (2 * sx, 0, 0))]
+        cy, sn = np.cos(yaw), np.sin(yaw)
+        rot = np.array([[cy, 0, sn], [0, 1, 0], [-sn, 0, cy]])
+        ctr = np.asarray(center, np.float64)
+        first = self.ntris
+        for corner, eu, ev in faces:
+            self.add_grid(rot @ np.asarray(corner, np.float64) + ctr, rot @ np.asarray(eu, np.float64),
+                          rot @ np.asarray(ev, np.float64), n, n, mats)
         return first
 
     def add_quad(self, corner, eu, ev, mat):
@@ -260,6 +292,27 @@ def _random_material(rng, b: _Builder):
     return b.material(GGX, color=rng.uniform(0.5, 0.95, 3), alpha=rng.uniform(0.05, 0.8))
 
 
+def _material_pair(rng, b: _Builder):
+    """Two materials of one kind with different colours: the two 'texture' tones of an
+    object (Lambert albedo U[0.2, 0.8]^3, or GGX F0 U[0.5, 0.95]^3 and roughness
+    U[0.05, 0.8] shared by both tones)."""
+    if rng.uniform() < 0.5:
+        return [b.material(LAMBERT, color=rng.uniform(0.2, 0.8, 3)) for _ in range(2)]
+    alpha = rng.uniform(0.05, 0.8)
+    return [b.material(GGX, color=rng.uniform(0.5, 0.95, 3), alpha=alpha) for _ in range(2)]
+
+
+def _sphere_pattern(rng, P, F):
+    """Per-triangle tone (0/1) of a displaced sphere: a product-of-sines pattern of
+    the centroid direction, giving blotches a few triangles to a few dozen wide."""
+    u = P[F].mean(1)
+    u = u - u.mean(0)
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    k = rng.uniform(4.0, 9.0, 3)
+    ph = rng.uniform(0.0, 2 * np.pi, 3)
+    return (np.prod(np.sin(k[None] * u + ph[None]), axis=1) > 0.1).astype(np.int64)
+
+
 # --------------------------------------------------------------------------- named scenes
 
 def cornell(seed: int = 1) -> Scene:
@@ -294,24 +347,30 @@ def procedural(seed: int = 7, spheres=((4, 5), (3, 4)), n_boxes: int = 20,
     """Ground plane, displaced icospheres, boxes and quad lights.
 
     `spheres` lists (count, subdivision level) groups.  The defaults give
-    2 + 4*20480 + 3*5120 + 20*12 + 3*2 = 97,528 triangles.  Each non-light
+    3,200 + 4*20,480 + 3*5,120 + 20*48 + 3*2 = 101,446 triangles.  Each non-light
     object is Lambertian (albedo U[0.2, 0.8]^3) or GGX (F0 U[0.5, 0.95]^3,
-    roughness U[0.05, 0.8]) with probability 1/2.
+    roughness U[0.05, 0.8]) with probability 1/2, in two tones laid out as a
+    texture: a checkerboard on the ground and on box faces (2 x 2 per face), a
+    blotch pattern on the spheres.
     """
     rng = np.random.default_rng(seed)
     b = _Builder()
-    b.add_quad((-20.0, 0.0, -20.0), (0.0, 0.0, 40.0), (40.0, 0.0, 0.0), _random_material(rng, b))
+    # ground: 40 x 40 checkerboard tiles of 1 x 1 (3,200 triangles)
+    b.add_grid((-20.0, 0.0, -20.0), (0.0, 0.0, 40.0), (40.0, 0.0, 0.0), 40, 40,
+               _material_pair(rng, b))
     for count, subdiv in spheres:
         for _ in range(count):
             r = rng.uniform(0.5, 1.5)
             cxz = rng.uniform(-4.0, 4.0, 2)
             P, N = _displaced_sphere(rng, subdiv, r, cxz)
-            b.add_tris(P, _random_material(rng, b), normals=N)
+            mats = np.asarray(_material_pair(rng, b))
+            V, F = icosphere(subdiv)
+            b.add_tris(P, mats[_sphere_pattern(rng, V, F)], normals=N)
     for _ in range(n_boxes):
         size = rng.uniform(0.2, 1.0, 3)
         cxz = rng.uniform(-4.0, 4.0, 2)
-        b.add_box((cxz[0], size[1] / 2, cxz[1]), size, rng.uniform(0, 2 * np.pi),
-                  _random_material(rng, b))
+        b.add_box_grid((cxz[0], size[1] / 2, cxz[1]), size, rng.uniform(0, 2 * np.pi),
+                       _material_pair(rng, b))
     for _ in range(n_lights):
         a, w = rng.uniform(0.5, 1.5, 2)
         h = rng.uniform(4.0, 6.0)
@@ -332,7 +391,7 @@ def procedural(seed: int = 7, spheres=((4, 5), (3, 4)), n_boxes: int = 20,
 
 def sphere_plan(target_tris: int):
     """(count, level) groups whose icosphere triangles approximate `target_tris`."""
-    budget = max(int(target_tris) - 2 - 20 * 12 - 3 * 2, 320)
+    budget = max(int(target_tris) - 3200 - 20 * 48 - 3 * 2, 320)
     plan = []
     for level in (7, 6, 5, 4, 3, 2):
         nt = 20 * 4 ** level

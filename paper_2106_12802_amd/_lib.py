@@ -139,12 +139,24 @@ def exported_symbols():
     ]
 
 
-def ptr(t) -> int | None:
-    """Device pointer of a torch tensor (None passes through)."""
+def ptr(t, numel=None, dtype=None, name="tensor") -> int | None:
+    """Device pointer of a contiguous CUDA torch tensor (None passes through).
+
+    With `dtype` / `numel` given, the tensor must have exactly that element type
+    and element count: the C ABI takes raw pointers and cannot check them."""
     if t is None:
         return None
     if not t.is_contiguous():
-        raise ValueError("tensor must be contiguous")
+        raise ValueError(f"{name} must be contiguous")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA tensor")
+    if dtype is not None:
+        import torch
+        want = {"f32": torch.float32, "i32": torch.int32}[dtype]
+        if t.dtype != want:
+            raise TypeError(f"{name} must be {want}, got {t.dtype}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
     return t.data_ptr()
 
 

@@ -210,7 +210,7 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--out", default="fusion_checkpoint.bin")
     ap.add_argument("--eval-scenes", type=int, default=4)
-    ap.add_argument("--eval-size", default="640x360")
+    ap.add_argument("--eval-size", default="1280x720")
     args = ap.parse_args(argv)
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
     torch.cuda.set_device(0)

@@ -14,7 +14,8 @@ def image_metrics(img, ref, lambda1=0.5, lambda2=0.01):
         raise ValueError("shape mismatch")
     out = np.zeros(3, np.float64)
     L.use_current_stream()
-    L.check(L.lib().mrs_image_metrics(L.ptr(img), L.ptr(ref), img.numel(), float(lambda1),
+    L.check(L.lib().mrs_image_metrics(L.ptr(img, img.numel(), "f32", "img"),
+                                      L.ptr(ref, img.numel(), "f32", "ref"), img.numel(), float(lambda1),
                                       float(lambda2), out.ctypes.data_as(C.c_void_p)))
     return {"mse_srgb": float(out[0]), "psnr": float(out[1]), "relmse": float(out[2])}
 

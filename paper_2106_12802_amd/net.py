@@ -44,9 +44,12 @@ class FusionNet:
         H, W = hrls_rgb.shape[-3], hrls_rgb.shape[-2]
         if out is None:
             out = torch.empty(hrls_rgb.shape, dtype=torch.float32, device=hrls_rgb.device)
+        P = B * H * W
         L.use_current_stream()
-        L.check(L.lib().mrs_fuse_batch(self.handle, B, L.ptr(hrls_rgb), L.ptr(hrls_aux),
-                                       L.ptr(lrhs_rgb), W, H, L.ptr(out)))
+        L.check(L.lib().mrs_fuse_batch(self.handle, B, L.ptr(hrls_rgb, 3 * P, "f32", "hrls_rgb"),
+                                       L.ptr(hrls_aux, 7 * P, "f32", "hrls_aux"),
+                                       L.ptr(lrhs_rgb, 3 * P // 16, "f32", "lrhs_rgb"), W, H,
+                                       L.ptr(out, 3 * P, "f32", "out")))
         return out
 
     @staticmethod
@@ -63,8 +66,11 @@ class FusionNet:
         loss = C.c_double()
         out = torch.empty(hrls_rgb.shape, dtype=torch.float32, device=hrls_rgb.device)
         L.use_current_stream()
-        L.check(L.lib().mrs_net_loss_grad(self.handle, B, L.ptr(hrls_rgb), L.ptr(hrls_aux),
-                                          L.ptr(lrhs_rgb), L.ptr(target), W, H,
+        P = B * H * W
+        L.check(L.lib().mrs_net_loss_grad(self.handle, B, L.ptr(hrls_rgb, 3 * P, "f32"),
+                                          L.ptr(hrls_aux, 7 * P, "f32"),
+                                          L.ptr(lrhs_rgb, 3 * P // 16, "f32"),
+                                          L.ptr(target, 3 * P, "f32"), W, H,
                                           g.ctypes.data_as(C.c_void_p), C.byref(loss),
                                           L.ptr(out)))
         return g, loss.value, out
@@ -74,8 +80,11 @@ class FusionNet:
         B, H, W = self._dims(hrls_rgb)
         loss = C.c_double()
         L.use_current_stream()
-        L.check(L.lib().mrs_train_step(self.handle, B, L.ptr(hrls_rgb), L.ptr(hrls_aux),
-                                       L.ptr(lrhs_rgb), L.ptr(target), W, H, float(lr),
+        P = B * H * W
+        L.check(L.lib().mrs_train_step(self.handle, B, L.ptr(hrls_rgb, 3 * P, "f32"),
+                                       L.ptr(hrls_aux, 7 * P, "f32"),
+                                       L.ptr(lrhs_rgb, 3 * P // 16, "f32"),
+                                       L.ptr(target, 3 * P, "f32"), W, H, float(lr),
                                        C.byref(loss) if want_loss else None))
         return loss.value if want_loss else None
 

@@ -50,8 +50,10 @@ class GpuScene:
         prim = torch.empty(n, dtype=torch.int32, device="cuda")
         b = torch.empty(n, 2, dtype=torch.float32, device="cuda")
         L.use_current_stream()
-        L.check(L.lib().mrs_debug_closest_hit(self.handle, n, L.ptr(o), L.ptr(d), L.ptr(sk),
-                                              L.ptr(t), L.ptr(prim), L.ptr(b)))
+        L.check(L.lib().mrs_debug_closest_hit(self.handle, n, L.ptr(o, 3 * n, "f32"),
+                                              L.ptr(d, 3 * n, "f32"), L.ptr(sk, n, "i32"),
+                                              L.ptr(t, n, "f32"), L.ptr(prim, n, "i32"),
+                                              L.ptr(b, 2 * n, "f32")))
         torch.cuda.synchronize()
         return t.cpu().numpy(), prim.cpu().numpy(), b.cpu().numpy()
 
@@ -78,11 +80,13 @@ def render_ex(scene: GpuScene, W, H, spp, max_depth, seed, out_rgb, out_aux=None
     if window is not None:
         o.x0, o.y0, o.win_w, o.win_h = (int(v) for v in window)
     o.accum_fp64 = accum_fp64
-    o.out_sumsq_dev = L.ptr(out_sumsq)
+    npix = (int(W) * int(H)) if window is None else int(window[2]) * int(window[3])
+    o.out_sumsq_dev = L.ptr(out_sumsq, 3 * npix, "f32", "out_sumsq")
     L.use_current_stream()
     L.check(L.lib().mrs_render_ex(scene.handle, int(W), int(H), int(spp), int(max_depth),
-                                  C.c_uint64(int(seed)), C.byref(o), L.ptr(out_rgb),
-                                  L.ptr(out_aux)))
+                                  C.c_uint64(int(seed)), C.byref(o),
+                                  L.ptr(out_rgb, 3 * npix, "f32", "out_rgb"),
+                                  L.ptr(out_aux, 7 * npix, "f32", "out_aux")))
 
 
 def render(scene: GpuScene, W, H, spp, max_depth, seed, want_aux=True, **kw):

@@ -281,6 +281,17 @@ def test_procedural_parity_full_size(mrs, oracle_tracer, torch_cuda, W, H, spp, 
     assert aux_frac >= 0.999
 
 
+def test_binding_rejects_wrong_tensors(mrs, torch_cuda):
+    gs = mrs.GpuScene(S.cornell(1))
+    torch = torch_cuda
+    with pytest.raises(TypeError, match="float32"):
+        mrs.render_ex(gs, 8, 8, 1, 1, 0, torch.zeros(8, 8, 3, dtype=torch.float64, device="cuda"))
+    with pytest.raises(ValueError, match="elements"):
+        mrs.render_ex(gs, 8, 8, 1, 1, 0, torch.zeros(8, 7, 3, dtype=torch.float32, device="cuda"))
+    with pytest.raises(ValueError, match="CUDA"):
+        mrs.render_ex(gs, 8, 8, 1, 1, 0, torch.zeros(8, 8, 3, dtype=torch.float32))
+
+
 def test_window_is_crop_and_chunking_invariant(mrs, torch_cuda):
     scene = S.cornell(2)
     gs = mrs.GpuScene(scene)
@@ -330,6 +341,22 @@ def test_counters_and_no_overflow(mrs, torch_cuda):
     assert c["nonfinite"] == 0
 
 
+def test_sumsq_parity(mrs, oracle_tracer, torch_cuda):
+    """Per-pixel sums of squared sample radiance match the oracle's (same paths)."""
+    scene = S.cornell(1)
+    W = H = 12
+    gs = mrs.GpuScene(scene)
+    for seed, fp64 in [(5000, 0), (5001, 1)]:
+        s = torch_cuda.zeros(H, W, 3, dtype=torch_cuda.float32, device="cuda")
+        rgb, _ = mrs.render(gs, W, H, 16, 4, seed, want_aux=False, out_sumsq=s, accum_fp64=fp64)
+        torch_cuda.cuda.synchronize()
+        g = s.cpu().numpy().reshape(-1, 3).astype(np.float64)
+        o = oracle_tracer.OracleScene(scene).render(W, H, 16, 4, seed, want_sumsq=True)["sumsq"]
+        ok = np.all(rel_ok(g, o), -1)
+        _log(f"sumsq fp64={fp64}: {ok.mean():.4f} ok, max {g.max():.3e} vs {o.max():.3e}")
+        assert ok.mean() >= 0.99
+
+
 def test_unbiased_vs_oracle_high_spp(mrs, oracle_tracer, torch_cuda):
     """Mean of 64 independent 16-spp GPU renders vs a 4096-spp oracle render."""
     scene = S.cornell(1)
@@ -342,7 +369,7 @@ def test_unbiased_vs_oracle_high_spp(mrs, oracle_tracer, torch_cuda):
     imgs = []
     sq = []
     for k in range(64):
-        s = torch_cuda.zeros(H, W, 3, device="cuda")
+        s = torch_cuda.zeros(H, W, 3, dtype=torch_cuda.float32, device="cuda")
         rgb, _ = mrs.render(gs, W, H, 16, 4, 5000 + k, want_aux=False, out_sumsq=s)
         imgs.append(rgb.cpu().numpy().reshape(-1, 3).astype(np.float64))
         sq.append(s.cpu().numpy().reshape(-1, 3).astype(np.float64))
@@ -354,5 +381,11 @@ def test_unbiased_vs_oracle_high_spp(mrs, oracle_tracer, torch_cuda):
     img_sigma = math.sqrt(np.sum(sigma ** 2)) / sigma.size
     _log(f"unbiased: frac > 3 sigma {frac_out:.4f}, mean diff {g_mean.mean() - ref_mean.mean():.3e} "
          f"(sigma {img_sigma:.3e})")
+    if frac_out > 0.01:
+        sq_all = np.array(sq)
+        bad = np.argsort(-sigma.max(1))[:3]
+        _log(f"  largest sigma pixels {bad.tolist()}: gpu var {g_var[bad].max(1)}, oracle var "
+             f"{ref_var[bad].max(1)}; per-render sumsq of pixel {bad[0]}: "
+             f"{sq_all[:, bad[0], 0].tolist()}")
     assert abs(g_mean.mean() - ref_mean.mean()) <= 3 * img_sigma
     assert frac_out <= 0.01

@@ -13,8 +13,6 @@ import torch
 
 from oracle import cnn
 
-torch.set_default_dtype(torch.float64)
-
 
 def _rand_params(seed, scale=1.0):
     rng = np.random.default_rng(seed)
