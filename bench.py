@@ -1,13 +1,15 @@
-"""Throughput benchmark of the hybrid frame's rendering path on one MI355X.
+"""Throughput benchmark of the hybrid multi-resolution frame on one MI355X.
 
-One step = one multi-resolution frame of the procedural ~100k-triangle scene:
-HRLS 1280x720 at 4 spp plus LRHS 320x180 at 64 spp, max depth 8, Russian
-roulette from vertex 3 (7,372,800 paths; spp_avg = 64/16 + 4 = 8).  Inputs
-(scene and LBVH) are resident in HBM before timing starts.
+One step = one 720p hybrid frame of the textured procedural ~100k-triangle
+scene: HRLS 1280x720 at 4 spp with albedo/normal/depth, LRHS 320x180 at 64 spp
+(max depth 8, Russian roulette from vertex 3; 7,372,800 paths, spp_avg =
+64/16 + 4 = 8) and the BF16 fusion network on both.  Inputs (scene, LBVH,
+weights) are resident in HBM before timing starts.
 
-Prints one JSON line with the throughput (Mpaths/s), the roofline position of
-the dominant kernel (timed live with HIP events on its launch stream), and the
-FP64 oracle's throughput on the host cores for the same frame.
+Prints one JSON line: Mpaths/s of the frame, ms per frame, the roofline
+position of the dominant kernel (timed live with HIP events on its launch
+stream), the equal-PSNR comparison with plain renders (PSNR against an
+independent 1024-spp reference), and the FP64 oracle timed on the host cores.
 """
 from __future__ import annotations
 
@@ -34,7 +36,10 @@ PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32 (FMA = 2 FLOP, packed)
 FLOP_PER_VISIT = 51
 FLOP_PER_TEST = 52
 FLOP_PER_RAY = 10
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "extend_procedural97k_720p_traffic.txt")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "extend_procedural101k_720p_traffic.txt")
+WEIGHTS = os.path.join(ROOT, "paper_2106_12802_amd", "weights", "fusion_l1_textured.bin")
+PEAK_BF16_TFLOPS = 2500.0  # MI355X dense BF16 MFMA
+CNN_FLOP_720P = 175.7e9    # 87.85 GMAC per 720p frame
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2106_12802_amd", "csrc", "trace.hip")
 
 
@@ -116,12 +121,13 @@ def pmc_summary(fetch_path, write_path, out_path):
     hbm = f_kib * 1024.0 * fs + w_kib * 1024.0 * ws
     lines = [
         "# HBM traffic of k_extend<false> (closest-hit traversal), procedural scene seed 7",
-        "# (101,446 triangles), hybrid frame HRLS 1280x720@4 + LRHS 320x180@64, max depth 8.",
+        "# (101,446 triangles, textured), 720p hybrid frame HRLS 1280x720@4 + LRHS 320x180@64",
+        "# (max depth 8) + fusion network.",
         "# Made by (each pass its own process, run from the repository root):",
         "#   rocprofv3 --pmc FETCH_SIZE -f csv -d gpurun_out/pmc_fetch -o pmc -- python bench.py "
-        "--steps 1 --warmup 0 --no-cpu-baseline --copy-calibration",
+        "--steps 1 --warmup 0 --no-cpu-baseline --equal-psnr-scenes 0 --copy-calibration",
         "#   rocprofv3 --pmc WRITE_SIZE -f csv -d gpurun_out/pmc_write -o pmc -- python bench.py "
-        "--steps 1 --warmup 0 --no-cpu-baseline --copy-calibration",
+        "--steps 1 --warmup 0 --no-cpu-baseline --equal-psnr-scenes 0 --copy-calibration",
         "#   python bench.py --pmc-summary gpurun_out/pmc_fetch gpurun_out/pmc_write",
         "# Counters are KiB per dispatch; each is scaled by COPY_BYTES over what the same counter",
         "# reads for a plain 1 GiB device copy in the same process.",
@@ -142,17 +148,67 @@ def pmc_summary(fetch_path, write_path, out_path):
 
 
 def cpu_baseline(scene, threads):
-    from oracle import tracer as orc
+    """The FP64 oracle on the host: the frame's two renders in full, the network on one
+    320x180 HR crop scaled by the 16 crops of a frame."""
+    import numpy as np
+    from oracle import cnn, tracer as orc
     osc = orc.OracleScene(scene)
     t0 = time.perf_counter()
-    osc.render(*HRLS[:2], HRLS[2], MAX_DEPTH, 2 * SCENE_SEED, nthreads=threads, want_aux=True)
+    hr = osc.render(*HRLS[:2], HRLS[2], MAX_DEPTH, 2 * SCENE_SEED, nthreads=threads, want_aux=True)
     osc.render(*LRHS[:2], LRHS[2], MAX_DEPTH, 2 * SCENE_SEED + 1, nthreads=threads, want_aux=False)
-    dt = time.perf_counter() - t0
+    t_render = time.perf_counter() - t0
+    rgb = hr["rgb"].reshape(HRLS[1], HRLS[0], 3)[None, :180, :320]
+    aux = hr["aux"].reshape(HRLS[1], HRLS[0], 7)[None, :180, :320]
+    lr = np.zeros((1, 45, 80, 3))
+    params = np.random.default_rng(0).uniform(-0.05, 0.05, cnn.num_params())
+    t0 = time.perf_counter()
+    cnn.forward(params, rgb, aux, lr)
+    t_cnn = (time.perf_counter() - t0) * 16
     paths = HRLS[0] * HRLS[1] * HRLS[2] + LRHS[0] * LRHS[1] * LRHS[2]
-    return {"value": round(paths / dt / 1e6, 4), "unit": "Mpaths/s", "cores": threads,
+    total = t_render + t_cnn
+    return {"value": round(paths / total / 1e6, 4), "unit": "Mpaths/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"the full frame: HRLS {HRLS[0]}x{HRLS[1]}@{HRLS[2]}spp + LRHS "
-                      f"{LRHS[0]}x{LRHS[1]}@{LRHS[2]}spp ({paths} paths, FP64, {dt:.1f} s)"}
+            "sample": f"renders of the full frame (HRLS {HRLS[0]}x{HRLS[1]}@{HRLS[2]} + LRHS "
+                      f"{LRHS[0]}x{LRHS[1]}@{LRHS[2]}, {paths} paths, FP64: {t_render:.1f} s) + the "
+                      f"FP64 network on one 320x180 crop x 16 ({t_cnn:.1f} s)",
+            "ms_per_frame": round(total * 1e3, 1)}
+
+
+def equal_psnr_block(net, n_scenes, log):
+    """Hybrid vs plain renders at equal PSNR on the bench scene and held-out scenes."""
+    from mrs_inputs import scenes as S
+    from paper_2106_12802_amd import hybrid as HY
+    from paper_2106_12802_amd import tracer as R
+    specs = [("bench", S.procedural(SCENE_SEED))]
+    specs += [(f"heldout_{s}", S.procedural_sized(s, t))
+              for s, t in S.training_scene_specs(200, n_scenes)]
+    rows = []
+    for name, scene in specs:
+        gs = R.GpuScene(scene)
+        r = HY.evaluate_scene(gs, net, HRLS[0], HRLS[1], seed=len(rows),
+                              plain_spp=(4, 8, 16, 32, 64, 128, 256), reps=2)
+        gs.close()
+        row = {"scene": name, "triangles": scene.num_tris,
+               "psnr_hybrid": round(r["hybrid"]["psnr"], 3), "ms_hybrid": round(r["hybrid"]["ms"], 3),
+               "psnr_lrhs_bilinear": round(r["lrhs_bilinear"]["psnr"], 3),
+               "psnr_hrls_4spp": round(r["hrls_4spp"]["psnr"], 3),
+               "plain": [[n, round(p, 3), round(t, 3)] for n, p, t in r["plain"]]}
+        eq = r["equal_psnr"]
+        row["equal_psnr_spp"] = None if eq is None else round(eq["spp"], 2)
+        row["plain_ms_at_equal_psnr"] = None if eq is None else round(eq["ms"], 3)
+        row["ratio"] = None if eq is None else round(eq["ratio"], 4)
+        p64 = [t for n, p, t in r["plain"] if n == 64][0]
+        row["ratio_vs_plain64"] = round(r["hybrid"]["ms"] / p64, 4)
+        rows.append(row)
+        log(f"[bench] {name}: hybrid {row['psnr_hybrid']} dB in {row['ms_hybrid']} ms; "
+            f"equal-PSNR plain spp {row['equal_psnr_spp']} ({row['plain_ms_at_equal_psnr']} ms), "
+            f"ratio {row['ratio']}")
+    ratios = [r["ratio"] for r in rows if r["ratio"] is not None]
+    return {"reference": "1024 spp, independent seed, FP64 pixel sums",
+            "protocol": "PSNR_N of plain renders N in 4..256 spp interpolated linearly in log2 N; "
+                        "time interpolated linearly in N; ratio = hybrid ms / plain ms at equal PSNR",
+            "mean_ratio": round(sum(ratios) / len(ratios), 4) if ratios else None,
+            "scenes": rows}
 
 
 def main():
@@ -161,6 +217,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--equal-psnr-scenes", type=int, default=3,
+                    help="held-out scenes in the equal-PSNR comparison (0: skip it)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 1 GiB device copy first (PMC byte-counter calibration)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -180,21 +238,30 @@ def main():
     from paper_2106_12802_amd import tracer as R
     from mrs_inputs import scenes as S
 
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)
     torch.cuda.set_device(0)
     if args.copy_calibration:
         copy_calibration()
     scene = S.procedural(SCENE_SEED)
     gs = mrs.GpuScene(scene)
+    net = mrs.FusionNet()
+    trained = os.path.exists(WEIGHTS)
+    if trained:
+        net.load_weights(WEIGHTS)
+    else:
+        net.init(1)
     torch.cuda.synchronize()
     (Wh, Hh, sh), (Wl, Hl, sl) = HRLS, LRHS
     hr_rgb = torch.empty(Hh, Wh, 3, device="cuda")
     hr_aux = torch.empty(Hh, Wh, 7, device="cuda")
     lr_rgb = torch.empty(Hl, Wl, 3, device="cuda")
+    out = torch.empty(Hh, Wh, 3, device="cuda")
     paths = Wh * Hh * sh + Wl * Hl * sl
 
     def step(i):
         R.render_ex(gs, Wh, Hh, sh, MAX_DEPTH, 2 * i, hr_rgb, hr_aux)
         R.render_ex(gs, Wl, Hl, sl, MAX_DEPTH, 2 * i + 1, lr_rgb, None)
+        net.fuse(hr_rgb, hr_aux, lr_rgb, out=out)
 
     # algorithmic work of one frame (counting variant of the traversal kernels)
     R.counters(reset=True)
@@ -202,12 +269,12 @@ def main():
     step(0)
     R.set_count_work(False)
     work = R.counters(reset=True)
-    print(f"[bench] work per frame: {json.dumps(work)}", file=sys.stderr, flush=True)
+    log(f"[bench] work per frame: {json.dumps(work)}")
 
     for i in range(args.warmup):
         step(i)
     torch.cuda.synchronize()
-    print(f"[bench] warmup done ({args.warmup} frames)", file=sys.stderr, flush=True)
+    log(f"[bench] warmup done ({args.warmup} frames)")
 
     R.profile_enable(True)
     torch.cuda.synchronize()
@@ -220,6 +287,7 @@ def main():
     R.profile_enable(False)
     ms_per_step = dt * 1e3 / args.steps
     value = paths * args.steps / dt / 1e6
+    log(f"[bench] {args.steps} frames: {ms_per_step:.3f} ms/frame, {value:.1f} Mpaths/s")
 
     ext_ms, ext_n = prof.get("extend", (0.0, 0))
     flop_frame = (FLOP_PER_VISIT * work["extend_visits"] + FLOP_PER_TEST * work["extend_tests"]
@@ -235,26 +303,36 @@ def main():
                 "flop_per_launch": int(flop_per_launch),
                 "visits_per_ray": round(work["extend_visits"] / max(work["rays"], 1), 2),
                 "tests_per_ray": round(work["extend_tests"] / max(work["rays"], 1), 2)}
+    cnn_ms = sum(prof.get(k, (0.0, 0))[0] for k in ("cnn_prep", "cnn_hr_in", "cnn_lr",
+                                                     "cnn_hr_out")) / args.steps
+    cnn_roof = {"bound": "mfma", "achieved": round(CNN_FLOP_720P / (cnn_ms / 1e3) / 1e12, 2)
+                if cnn_ms > 0 else 0.0, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                "ms_per_frame": round(cnn_ms, 4)}
+    cnn_roof["frac"] = round(cnn_roof["achieved"] / PEAK_BF16_TFLOPS, 5)
     kernel_ms = {k: round(v[0] / args.steps, 4) for k, v in prof.items()}
-    out = {
+    result = {
         "metric": METRIC, "value": round(value, 3), "unit": "Mpaths/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+bf16",
         "data": "synthetic",
-        "config": {"workload": "hybrid frame render: procedural scene (seed 7, 101,446 triangles, "
-                               "Lambert+GGX, 3 quad lights, env 0.2), HRLS 1280x720@4spp + LRHS "
-                               "320x180@64spp, max depth 8, RR from vertex 3",
-                   "paths_per_frame": paths, "triangles": scene.num_tris},
+        "config": {"workload": "720p hybrid frame: procedural scene (seed 7, 101,446 triangles, "
+                               "textured Lambert+GGX, 3 quad lights, env 0.2), HRLS 1280x720@4spp "
+                               "+ LRHS 320x180@64spp (max depth 8, RR from vertex 3) + BF16 fusion "
+                               "network (175.7 GFLOP)",
+                   "paths_per_frame": paths, "triangles": scene.num_tris,
+                   "weights": "trained (paper_2106_12802_amd/weights)" if trained else "untrained"},
         "roofline": roofline,
+        "roofline_cnn": cnn_roof,
         "kernel_ms_per_frame": kernel_ms,
         "rays_per_path": round((work["rays"] + work["shadow_rays"]) / paths, 3),
     }
+    if args.equal_psnr_scenes > 0:
+        result["equal_psnr"] = equal_psnr_block(net, args.equal_psnr_scenes, log)
     if not args.no_cpu_baseline:
         threads = max(1, min(16, len(os.sched_getaffinity(0))))
-        print(f"[bench] timing the FP64 oracle on {threads} host threads", file=sys.stderr,
-              flush=True)
-        out["cpu_baseline"] = cpu_baseline(scene, threads)
-    print(json.dumps(out), flush=True)
+        log(f"[bench] timing the FP64 oracle on {threads} host threads")
+        result["cpu_baseline"] = cpu_baseline(scene, threads)
+    print(json.dumps(result), flush=True)
 
 
 if __name__ == "__main__":

@@ -208,7 +208,8 @@ def main(argv=None):
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--lr", type=float, default=1e-4)
     ap.add_argument("--seed", type=int, default=1)
-    ap.add_argument("--out", default="fusion_checkpoint.bin")
+    ap.add_argument("--out", default="fusion_checkpoint.bin", help="resumable checkpoint")
+    ap.add_argument("--weights-out", default=None, help="weights-only file for inference")
     ap.add_argument("--eval-scenes", type=int, default=4)
     ap.add_argument("--eval-size", default="1280x720")
     args = ap.parse_args(argv)
@@ -219,6 +220,8 @@ def main(argv=None):
     losses, done = train(net, data, args.steps, args.batch, args.lr, seed=args.seed, log=log,
                          time_limit=args.time_limit)
     net.save(args.out)
+    if args.weights_out:
+        net.save_weights(args.weights_out)
     log(f"[train] saved {args.out} after {done} steps")
     del data
     W, H = (int(v) for v in args.eval_size.split("x"))

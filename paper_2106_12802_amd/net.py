@@ -126,6 +126,25 @@ class FusionNet:
         arr = np.frombuffer(body, np.float32).reshape(3, n)
         self.set_state(arr[0], arr[1], arr[2], int(step))
 
+    def save_weights(self, path):
+        """Weights file: magic, version, count, FP32 parameters, SHA-256 of all before it."""
+        import hashlib
+        p = self.get_params()
+        head = np.array([0x5753524D, 1, self.num_params], np.int64).tobytes()
+        with open(path, "wb") as f:
+            f.write(head + p.tobytes() + hashlib.sha256(head + p.tobytes()).digest())
+
+    def load_weights(self, path):
+        import hashlib
+        raw = open(path, "rb").read()
+        head, body, digest = raw[:24], raw[24:-32], raw[-32:]
+        magic, version, n = np.frombuffer(head, np.int64)
+        if magic != 0x5753524D or version != 1 or n != self.num_params:
+            raise ValueError("not a weights file of this network")
+        if hashlib.sha256(head + body).digest() != digest:
+            raise ValueError("weights file checksum mismatch")
+        self.set_params(np.frombuffer(body, np.float32))
+
     def activation(self, which: int, shape):
         a = np.empty(int(np.prod(shape)), np.float32)
         L.check(L.lib().mrs_debug_net_activation(self.handle, which,
