@@ -221,6 +221,10 @@ def main():
                     help="held-out scenes in the equal-PSNR comparison (0: skip it)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 1 GiB device copy first (PMC byte-counter calibration)")
+    ap.add_argument("--chunk-paths", type=int, default=None, help="tuning: paths resident at once")
+    ap.add_argument("--trace-blocks", type=int, default=None, help="tuning: traversal grid size")
+    ap.add_argument("--schedule", type=int, default=None, choices=(0, 1),
+                    help="tuning: traversal queue schedule (0 grid-stride, 1 dynamic)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="summarise two rocprofv3 --pmc runs into the profiles/ traffic file")
     args = ap.parse_args()
@@ -242,6 +246,9 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_calibration:
         copy_calibration()
+    R.set_tuning(args.chunk_paths, args.trace_blocks, args.schedule)
+    tuning = R.get_tuning()
+    log(f"[bench] tuning {tuning}")
     scene = S.procedural(SCENE_SEED)
     gs = mrs.GpuScene(scene)
     net = mrs.FusionNet()
@@ -320,7 +327,8 @@ def main():
                                "+ LRHS 320x180@64spp (max depth 8, RR from vertex 3) + BF16 fusion "
                                "network (175.7 GFLOP)",
                    "paths_per_frame": paths, "triangles": scene.num_tris,
-                   "weights": "trained (paper_2106_12802_amd/weights)" if trained else "untrained"},
+                   "weights": "trained (paper_2106_12802_amd/weights)" if trained else "untrained",
+                   "tuning": tuning},
         "roofline": roofline,
         "roofline_cnn": cnn_roof,
         "kernel_ms_per_frame": kernel_ms,

@@ -86,7 +86,7 @@ typedef struct mrs_camera {
 #define MRS_TRI_SMOOTH 1u /* shade with the interpolated per-corner normals */
 
 typedef struct mrs_scene_desc {
-  int32_t num_tris;             /* >= 0; 0 gives an environment-only scene */
+  int32_t num_tris;             /* 0 .. 2^24 - 2; 0 gives an environment-only scene */
   const float* vertices;        /* host, num_tris*9: v0, v1, v2 (xyz each) */
   const float* normals;         /* host, num_tris*9 per-corner normals, or NULL */
   const uint32_t* tri_material; /* host, num_tris indices into materials */
@@ -156,6 +156,35 @@ mrs_status mrs_render_ex(const mrs_scene* scene, int32_t W, int32_t H, int32_t s
                          int32_t max_depth, uint64_t seed, const mrs_render_opts* opts,
                          float* out_rgb_dev, float* out_aux_dev);
 
+/* ------------------------------------------------------------ batches */
+
+/* One render of a batch: the arguments of mrs_render_ex. */
+typedef struct mrs_job {
+  const mrs_scene* scene;
+  int32_t W, H, spp, max_depth;
+  uint64_t seed;
+  mrs_render_opts opts;
+  float* out_rgb_dev;
+  float* out_aux_dev; /* or NULL */
+} mrs_job;
+
+typedef struct mrs_batch mrs_batch; /* opaque: device job table + accumulators */
+
+/* Validates 1..255 jobs (each as mrs_render_ex would), uploads the job table
+ * and reserves every buffer the batch needs (synchronous).  Jobs may differ in
+ * scene, resolution, window, spp and depth.  The paths of all jobs form one
+ * index space, so each stage of the wavefront (generate, extend, shade, shadow,
+ * accumulate, resolve) is one launch over every job's live work: small jobs
+ * share the GPU instead of running one after another.  Each job's outputs are
+ * bitwise those of the same mrs_render_ex call.  The scenes must outlive the
+ * batch. */
+mrs_status mrs_batch_create(const mrs_job* jobs, int32_t n, mrs_batch** out);
+/* Enqueues the batch on the current stream.  Performs no allocation and no
+ * host synchronisation (unless mrs_set_tuning enlarged the workspace since
+ * mrs_batch_create), so it can be captured in a HIP graph. */
+mrs_status mrs_batch_render(mrs_batch* batch);
+mrs_status mrs_batch_destroy(mrs_batch* batch);
+
 /* Counters accumulated since the last reset (synchronises the stream):
  * [0] non-finite samples replaced by 0, [1] closest-hit rays, [2] shadow rays,
  * [3] traversal stack entries spilled from LDS to global memory,
@@ -187,7 +216,9 @@ mrs_status mrs_profile_read(double ms_out[MRS_NUM_KERNEL_IDS],
 /* Tuning knobs (performance only; results do not depend on them). */
 typedef struct mrs_tuning {
   int32_t chunk_paths;  /* paths resident at once (default 1<<22) */
-  int32_t trace_blocks; /* grid size of traversal kernels (default 2048) */
+  int32_t trace_blocks; /* grid size of traversal kernels (default 4096) */
+  int32_t schedule;     /* traversal queue: 0 grid-stride (default), 1 per-wave
+                           dynamic fetch from a device counter */
 } mrs_tuning;
 mrs_status mrs_get_tuning(mrs_tuning* out);
 mrs_status mrs_set_tuning(const mrs_tuning* t);

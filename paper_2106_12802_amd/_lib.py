@@ -59,8 +59,14 @@ class RenderOpts(C.Structure):
                 ("out_sumsq_dev", C.c_void_p)]
 
 
+class Job(C.Structure):
+    _fields_ = [("scene", C.c_void_p), ("W", C.c_int32), ("H", C.c_int32), ("spp", C.c_int32),
+                ("max_depth", C.c_int32), ("seed", C.c_uint64), ("opts", RenderOpts),
+                ("out_rgb_dev", C.c_void_p), ("out_aux_dev", C.c_void_p)]
+
+
 class Tuning(C.Structure):
-    _fields_ = [("chunk_paths", C.c_int32), ("trace_blocks", C.c_int32)]
+    _fields_ = [("chunk_paths", C.c_int32), ("trace_blocks", C.c_int32), ("schedule", C.c_int32)]
 
 
 assert C.sizeof(Material) == 32 and C.sizeof(QuadLight) == 56
@@ -111,6 +117,9 @@ def lib():
         "mrs_train_step": ([P, I32, P, P, P, P, I32, I32, C.c_float, P], I32),
         "mrs_net_get_state": ([P, P, P, P, C.c_int64, P], I32),
         "mrs_net_set_state": ([P, P, P, P, C.c_int64, C.c_int64], I32),
+        "mrs_batch_create": ([C.POINTER(Job), I32, C.POINTER(P)], I32),
+        "mrs_batch_render": ([P], I32),
+        "mrs_batch_destroy": ([P], I32),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(L, name)
@@ -135,7 +144,8 @@ def exported_symbols():
         "mrs_profile_read", "mrs_net_num_params", "mrs_net_create", "mrs_net_destroy",
         "mrs_net_init", "mrs_net_set_params", "mrs_net_get_params", "mrs_fuse", "mrs_fuse_batch",
         "mrs_debug_net_activation", "mrs_image_metrics", "mrs_net_loss_grad", "mrs_train_step",
-        "mrs_net_get_state", "mrs_net_set_state",
+        "mrs_net_get_state", "mrs_net_set_state", "mrs_batch_create", "mrs_batch_render",
+        "mrs_batch_destroy",
     ]
 
 

@@ -203,8 +203,8 @@ mrs_status mrs_scene_create(const mrs_scene_desc* d, mrs_scene** out) {
   *out = nullptr;
   if (!d) return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_scene_create: desc is NULL");
   const int n = d->num_tris;
-  if (n < 0 || n > (1 << 28))
-    return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_scene_create: num_tris out of range");
+  if (n < 0 || n > MAX_TRIS)
+    return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_scene_create: num_tris must be in [0, 2^24 - 2]");
   if (n > 0 && (!d->vertices || !d->tri_material))
     return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_scene_create: vertices/tri_material NULL");
   if (d->num_materials < 0 || (d->num_materials > 0 && !d->materials) ||
@@ -276,43 +276,118 @@ void mrs_render_opts_default(mrs_render_opts* o) {
   o->out_sumsq_dev = nullptr;
 }
 
-mrs_status mrs_render_ex(const mrs_scene* s, int32_t W, int32_t H, int32_t spp, int32_t max_depth,
-                         uint64_t seed, const mrs_render_opts* opts, float* out_rgb,
-                         float* out_aux) {
+namespace {
+mrs_status validate_render(const char* fn, const mrs_scene* s, int32_t W, int32_t H, int32_t spp,
+                           int32_t max_depth, uint64_t seed, const mrs_render_opts* opts,
+                           float* out_rgb, float* out_aux, RenderArgs* a) {
+  const std::string f(fn);
   mrs_render_opts o;
   mrs_render_opts_default(&o);
   if (opts) o = *opts;
-  if (!s) return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_render: scene is NULL");
+  if (!s) return fail(MRS_ERR_INVALID_ARGUMENT, f + ": scene is NULL");
   if (W < 1 || H < 1 || W > 16384 || H > 16384)
-    return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_render: W and H must be in [1, 16384]");
+    return fail(MRS_ERR_INVALID_ARGUMENT, f + ": W and H must be in [1, 16384]");
   if (spp < 1 || spp > (1 << 20))
-    return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_render: spp must be in [1, 2^20]");
+    return fail(MRS_ERR_INVALID_ARGUMENT, f + ": spp must be in [1, 2^20]");
   if (max_depth < 0 || max_depth > 64)
-    return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_render: max_depth must be in [0, 64]");
-  if (o.rr_start < 0) return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_render: rr_start < 0");
+    return fail(MRS_ERR_INVALID_ARGUMENT, f + ": max_depth must be in [0, 64]");
+  if (o.rr_start < 0) return fail(MRS_ERR_INVALID_ARGUMENT, f + ": rr_start < 0");
   const int ww = o.win_w ? o.win_w : W, wh = o.win_h ? o.win_h : H;
   if (o.x0 < 0 || o.y0 < 0 || ww < 1 || wh < 1 || o.x0 + ww > W || o.y0 + wh > H)
-    return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_render: window outside the image");
-  if (!out_rgb) return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_render: out_rgb is NULL");
+    return fail(MRS_ERR_INVALID_ARGUMENT, f + ": window outside the image");
+  if (!out_rgb) return fail(MRS_ERR_INVALID_ARGUMENT, f + ": out_rgb is NULL");
   if (((uintptr_t)out_rgb | (uintptr_t)out_aux | (uintptr_t)o.out_sumsq_dev) & 3u)
-    return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_render: outputs must be 4-byte aligned");
-  if (!s->bvh_built) return fail(MRS_ERR_NOT_READY, "mrs_render: call mrs_build_bvh first");
+    return fail(MRS_ERR_INVALID_ARGUMENT, f + ": outputs must be 4-byte aligned");
+  if (!s->bvh_built) return fail(MRS_ERR_NOT_READY, f + ": call mrs_build_bvh first");
+  a->W = W;
+  a->H = H;
+  a->spp = spp;
+  a->max_depth = max_depth;
+  a->rr_start = o.rr_start;
+  a->seed = seed;
+  a->x0 = o.x0;
+  a->y0 = o.y0;
+  a->ww = ww;
+  a->wh = wh;
+  a->fp64 = o.accum_fp64 < 0 ? spp >= 1024 : o.accum_fp64 != 0;
+  a->out_rgb = out_rgb;
+  a->out_aux = out_aux;
+  a->out_sumsq = o.out_sumsq_dev;
+  return MRS_OK;
+}
+}  // namespace
+
+struct mrs_batch {
+  std::vector<DevJob> jobs;
+  DevJob* d_jobs = nullptr;
+  char* d_acc = nullptr;
+  size_t acc_bytes = 0;
+};
+
+mrs_status mrs_render_ex(const mrs_scene* s, int32_t W, int32_t H, int32_t spp, int32_t max_depth,
+                         uint64_t seed, const mrs_render_opts* opts, float* out_rgb,
+                         float* out_aux) {
   RenderArgs a;
-  a.W = W;
-  a.H = H;
-  a.spp = spp;
-  a.max_depth = max_depth;
-  a.rr_start = o.rr_start;
-  a.seed = seed;
-  a.x0 = o.x0;
-  a.y0 = o.y0;
-  a.ww = ww;
-  a.wh = wh;
-  a.fp64 = o.accum_fp64 < 0 ? spp >= 1024 : o.accum_fp64 != 0;
-  a.out_rgb = out_rgb;
-  a.out_aux = out_aux;
-  a.out_sumsq = o.out_sumsq_dev;
+  mrs_status rc = validate_render("mrs_render", s, W, H, spp, max_depth, seed, opts, out_rgb,
+                                  out_aux, &a);
+  if (rc != MRS_OK) return rc;
   return render(s, a, current_stream());
+}
+
+mrs_status mrs_batch_create(const mrs_job* jobs, int32_t n, mrs_batch** out) {
+  if (!out) return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_batch_create: out is NULL");
+  *out = nullptr;
+  if (!jobs || n < 1 || n > MAX_JOBS)
+    return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_batch_create: need 1..255 jobs");
+  std::vector<DevJob> dj;
+  for (int i = 0; i < n; ++i) {
+    const mrs_job& j = jobs[i];
+    RenderArgs a;
+    mrs_status rc = validate_render(("mrs_batch_create: job " + std::to_string(i)).c_str(),
+                                    j.scene, j.W, j.H, j.spp, j.max_depth, j.seed, &j.opts,
+                                    j.out_rgb_dev, j.out_aux_dev, &a);
+    if (rc != MRS_OK) return rc;
+    dj.push_back(make_job(j.scene, a));
+  }
+  mrs_batch* b = new mrs_batch();
+  b->jobs = dj;
+  mrs_status rc = batch_prepare(b->jobs, &b->acc_bytes);
+  if (rc == MRS_OK &&
+      (hipMalloc(&b->d_jobs, sizeof(DevJob) * n) != hipSuccess ||
+       hipMalloc(&b->d_acc, b->acc_bytes) != hipSuccess)) {
+    (void)hipGetLastError();
+    rc = fail(MRS_ERR_OUT_OF_MEMORY, "mrs_batch_create: device allocation failed");
+  }
+  if (rc == MRS_OK) {
+    hipError_t e = hipMemcpy(b->d_jobs, b->jobs.data(), sizeof(DevJob) * n, hipMemcpyHostToDevice);
+    if (e != hipSuccess) rc = check_hip(e, "mrs_batch_create: job table upload");
+  }
+  if (rc != MRS_OK) {
+    if (b->d_jobs) (void)hipFree(b->d_jobs);
+    if (b->d_acc) (void)hipFree(b->d_acc);
+    delete b;
+    return rc;
+  }
+  *out = b;
+  return MRS_OK;
+}
+
+mrs_status mrs_batch_render(mrs_batch* b) {
+  if (!b) return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_batch_render: batch is NULL");
+  std::vector<DevJob> tmp = b->jobs;
+  size_t bytes = 0;
+  mrs_status rc = batch_prepare(tmp, &bytes);  // the workspace may have to grow after retuning
+  if (rc != MRS_OK) return rc;
+  return batch_launch(b->d_jobs, b->jobs, b->d_acc, b->acc_bytes, current_stream());
+}
+
+mrs_status mrs_batch_destroy(mrs_batch* b) {
+  if (!b) return MRS_OK;
+  (void)hipDeviceSynchronize();
+  if (b->d_jobs) (void)hipFree(b->d_jobs);
+  if (b->d_acc) (void)hipFree(b->d_acc);
+  delete b;
+  return MRS_OK;
 }
 
 mrs_status mrs_render(const mrs_scene* s, int32_t W, int32_t H, int32_t spp, int32_t max_depth,

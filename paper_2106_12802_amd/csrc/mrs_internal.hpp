@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "mrs.h"
 
@@ -63,6 +64,24 @@ struct SceneView {  // passed by value to kernels
   float cam_tan_half;
 };
 
+// One render of a batch: its scene, image, window, sampling and outputs.
+// Paths of all jobs form one index space: job j owns [first, first + spp * npix)
+// in sample-major order; pix_first indexes its pixels in the concatenated
+// pixel space; acc_off locates its accumulators (bytes).
+struct DevJob {
+  SceneView sv;
+  int32_t W, H, x0, y0, ww, wh;
+  int32_t spp, max_depth, rr_start, fp64;
+  uint32_t seed_lo, seed_hi;
+  int64_t first, pix_first, acc_off;
+  float* out_rgb;
+  float* out_aux;
+  float* out_sq;
+};
+
+constexpr int MAX_JOBS = 255;                // job ids travel in 8 bits
+constexpr int32_t MAX_TRIS = (1 << 24) - 2;  // primitive ids travel in 24 bits
+
 // prim_ng.w packs: bits 0..23 material index, bit 24 smooth, bit 25 listed light
 constexpr uint32_t PRIM_SMOOTH = 1u << 24;
 constexpr uint32_t PRIM_LISTED = 1u << 25;
@@ -103,6 +122,12 @@ struct RenderArgs {
   float* out_sumsq;
 };
 mrs_status render(const mrs_scene* s, const RenderArgs& a, hipStream_t st);
+DevJob make_job(const mrs_scene* s, const RenderArgs& a);
+// sets first / pix_first / acc_off of every job, returns the accumulator bytes
+// and makes sure the path workspace can hold the batch's chunks
+mrs_status batch_prepare(std::vector<DevJob>& jobs, size_t* acc_bytes);
+mrs_status batch_launch(const DevJob* d_jobs, const std::vector<DevJob>& jobs, char* acc,
+                        size_t acc_bytes, hipStream_t st);
 mrs_status debug_closest_hit(const mrs_scene* s, int32_t n, const float* o, const float* d,
                              const int32_t* skip, float* t, int32_t* prim, float* b,
                              hipStream_t st);

@@ -17,6 +17,7 @@
 // sums its samples in order, so results do not depend on queue order, chunk
 // size or grid size.
 #include <algorithm>
+#include <cstring>
 #include <vector>
 
 #include "mrs_internal.hpp"
@@ -30,26 +31,22 @@ constexpr int LDS_STACK = 16;  // stack entries per thread held in LDS
 constexpr int MAX_BOUNCE_SLOTS = 66;
 constexpr float INV_PI = 0.318309886183790671538f;
 
-// Layout of the device counter block (uint32 words, then uint64 stats).
-constexpr int Q_RAYS = 0;                      // [b] rays entering bounce b
-constexpr int Q_SHADOW = MAX_BOUNCE_SLOTS;     // [b] shadow rays made at bounce b
-constexpr int Q_WORDS = 2 * MAX_BOUNCE_SLOTS;  // uint32 words before the stats
-// stats (uint64): 0 nonfinite, 1 rays, 2 shadow rays, 3 spills, 4 paths, 5 overflow
+// Device counter block (uint32 words), reset at the start of every chunk:
+constexpr int Q_RAYS = 0;                          // [b] rays entering bounce b
+constexpr int Q_SHADOW = MAX_BOUNCE_SLOTS;         // [b] shadow rays made at bounce b
+constexpr int Q_FETCH_EXT = 2 * MAX_BOUNCE_SLOTS;  // [b] work fetched by extend at bounce b
+constexpr int Q_FETCH_SHD = 3 * MAX_BOUNCE_SLOTS;  // [b] work fetched by shadow at bounce b
+constexpr int Q_WORDS = 4 * MAX_BOUNCE_SLOTS;
+// stats (uint64): 0 nonfinite, 1 rays, 2 shadow rays, 3 spills, 4 paths, 5 overflow,
+// 6/7 extend visits/tests, 8/9 shadow visits/tests
 
-struct ChunkGeom {
-  int32_t W, H, x0, y0, ww;
-  int32_t s0, np, p0;
-  uint32_t seed_lo, seed_hi;
-  int32_t max_depth, rr_start;
-};
-
-__device__ __forceinline__ void slot_pixel_sample(const ChunkGeom& g, uint32_t slot, uint32_t& P,
-                                                  uint32_t& s, uint32_t& pl) {
-  const uint32_t k = slot / (uint32_t)g.np;
-  pl = (uint32_t)g.p0 + (slot - k * (uint32_t)g.np);
-  s = (uint32_t)g.s0 + k;
-  const uint32_t wy = pl / (uint32_t)g.ww, wx = pl - wy * (uint32_t)g.ww;
-  P = ((uint32_t)g.y0 + wy) * (uint32_t)g.W + ((uint32_t)g.x0 + wx);
+// Rays and shadow rays carry (job << 24 | primitive) in one word.
+constexpr uint32_t PRIM24 = 0x00ffffffu;  // "no primitive"
+__device__ __forceinline__ uint32_t prim_of(uint32_t w) { return w & PRIM24; }
+__device__ __forceinline__ uint32_t job_of(uint32_t w) { return w >> 24; }
+__device__ __forceinline__ uint32_t unpack_prim(uint32_t w) {
+  const uint32_t p = w & PRIM24;
+  return p == PRIM24 ? NO_PRIM : p;
 }
 
 __device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
@@ -92,14 +89,49 @@ struct TraceState {
   float b1, b2;
 };
 
+// Traversal arrays as global-address-space pointers with wave-uniform values.
+// Pointers read from the job table are generic to the compiler (flat loads,
+// vector addresses); these views give global loads off a scalar base, as
+// pointers passed as kernel arguments do.
+typedef float vfloat4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) const vfloat4 gfloat4;
+
+__device__ __forceinline__ float4 ld4(const gfloat4* p) {
+  const vfloat4 v = *p;
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+struct TraceView {
+  const gfloat4* nodes;
+  const gfloat4* leaf_tri;
+  uint32_t root;
+  int32_t ntris;
+};
+
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// The view of scene sv, whose fields are equal across the active lanes.
+__device__ __forceinline__ TraceView trace_view(const SceneView& sv) {
+  TraceView t;
+  t.nodes = (const gfloat4*)uniform64((uint64_t)(uintptr_t)sv.nodes);
+  t.leaf_tri = (const gfloat4*)uniform64((uint64_t)(uintptr_t)sv.leaf_tri);
+  t.root = __builtin_amdgcn_readfirstlane(sv.root);
+  t.ntris = (int32_t)__builtin_amdgcn_readfirstlane((uint32_t)sv.ntris);
+  return t;
+}
+
 // Moller-Trumbore against one leaf; edges inclusive, t > 0, three excluded
 // primitives.  ANY: accept any t < ts.t (shadow rays).  Otherwise accept a
 // closer hit, or an equal t with a smaller primitive id.
 template <bool ANY>
-__device__ __forceinline__ bool isect_leaf(const float4* __restrict__ leaf_tri, uint32_t leaf,
+__device__ __forceinline__ bool isect_leaf(const gfloat4* __restrict__ leaf_tri, uint32_t leaf,
                                            f3 o, f3 d, uint32_t x0, uint32_t x1, uint32_t x2,
                                            TraceState& ts) {
-  const float4 A = leaf_tri[3 * leaf], B = leaf_tri[3 * leaf + 1], C = leaf_tri[3 * leaf + 2];
+  const float4 A = ld4(leaf_tri + 3 * leaf), B = ld4(leaf_tri + 3 * leaf + 1),
+               C = ld4(leaf_tri + 3 * leaf + 2);
   const uint32_t prim = __float_as_uint(A.w);
   const f3 e1 = xyz(B), e2 = xyz(C);
   const f3 pv = cross(d, e2);
@@ -158,7 +190,7 @@ struct WorkCount {
 // Returns true for ANY when an occluder was found; fills ts otherwise.  COUNT
 // adds node visits and triangle tests to wc (a separate instantiation).
 template <bool ANY, bool COUNT>
-__device__ bool traverse(const SceneView& sc, f3 o, f3 d, uint32_t x0, uint32_t x1, uint32_t x2,
+__device__ bool traverse(const TraceView& sc, f3 o, f3 d, uint32_t x0, uint32_t x1, uint32_t x2,
                          Stack& st, TraceState& ts, WorkCount& wc) {
   if (sc.ntris == 0) return false;
   if (sc.root & LEAF_BIT) {
@@ -172,8 +204,8 @@ __device__ bool traverse(const SceneView& sc, f3 o, f3 d, uint32_t x0, uint32_t 
   const uint32_t ninternal = (uint32_t)sc.ntris - 1u;
   // A well-formed tree visits each internal node at most once per ray.
   for (uint32_t visits = 0; visits < ninternal; ++visits) {
-    const float4* nd = sc.nodes + 4 * (size_t)node;
-    const float4 a = nd[0], b = nd[1], c = nd[2], r = nd[3];
+    const gfloat4* nd = sc.nodes + 4 * node;
+    const float4 a = ld4(nd), b = ld4(nd + 1), c = ld4(nd + 2), r = ld4(nd + 3);
     if (COUNT) ++wc.visits;
     float tl, tr;
     bool hl = slab(a.x, a.y, a.z, a.w, b.x, b.y, oi, inv, ts.t, tl);
@@ -208,56 +240,138 @@ __device__ bool traverse(const SceneView& sc, f3 o, f3 d, uint32_t x0, uint32_t 
   return false;
 }
 
+
+// ------------------------------------------------------------------ jobs
+
+// Global path index g of a batch: jobs are concatenated, each in sample-major
+// order (g = first + s * npix + pl, pl the row-major pixel of its window).
+__device__ __forceinline__ uint32_t find_job(const DevJob* __restrict__ jobs, int njobs,
+                                             int64_t g) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].first <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  return (uint32_t)lo;
+}
+
+__device__ __forceinline__ uint32_t find_job_pix(const DevJob* __restrict__ jobs, int njobs,
+                                                 int64_t i) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].pix_first <= i) lo = mid;
+    else hi = mid - 1;
+  }
+  return (uint32_t)lo;
+}
+
+// full-image pixel index P and sample s of the path at global index g of job J
+__device__ __forceinline__ void path_pixel_sample(const DevJob& J, int64_t g, uint32_t& P,
+                                                  uint32_t& s) {
+  const int64_t l = g - J.first;
+  const int64_t npix = (int64_t)J.ww * J.wh;
+  s = (uint32_t)(l / npix);
+  const uint32_t pl = (uint32_t)(l - (int64_t)s * npix);
+  const uint32_t wy = pl / (uint32_t)J.ww, wx = pl - wy * (uint32_t)J.ww;
+  P = ((uint32_t)J.y0 + wy) * (uint32_t)J.W + ((uint32_t)J.x0 + wx);
+}
+
 // ------------------------------------------------------------------ kernels
+
+__global__ __launch_bounds__(64) void k_store_job(DevJob j, DevJob* dst) {
+  if (threadIdx.x == 0) *dst = j;
+}
 
 __global__ __launch_bounds__(256) void k_reset(uint32_t* q, uint32_t n) {
   for (int i = threadIdx.x; i < Q_WORDS; i += blockDim.x) q[i] = (i == Q_RAYS) ? n : 0u;
 }
 
-__global__ __launch_bounds__(256) void k_generate(ChunkGeom g, SceneView sc, uint32_t n,
+__global__ __launch_bounds__(256) void k_generate(const DevJob* __restrict__ jobs, int njobs,
+                                                  int64_t g0, uint32_t n,
                                                   float4* __restrict__ rays,
                                                   float4* __restrict__ beta,
                                                   float4* __restrict__ L,
                                                   float4* __restrict__ aux) {
   const uint32_t slot = blockIdx.x * 256 + threadIdx.x;
   if (slot >= n) return;
-  uint32_t P, s, pl;
-  slot_pixel_sample(g, slot, P, s, pl);
-  const uint32_t py = P / (uint32_t)g.W, px = P - py * (uint32_t)g.W;
-  const uint4 r = philox4x32_10(make_uint4(P, s, 0u, 0u), g.seed_lo, g.seed_hi);
-  const float sx = ((float)px + unit24(r.x)) / (float)g.W;
-  const float sy = ((float)py + unit24(r.y)) / (float)g.H;
-  const float aspect = (float)g.W / (float)g.H;
+  const int64_t g = g0 + slot;
+  const uint32_t j = find_job(jobs, njobs, g);
+  const DevJob& J = jobs[j];
+  const SceneView& sc = J.sv;
+  uint32_t P, s;
+  path_pixel_sample(J, g, P, s);
+  const uint32_t py = P / (uint32_t)J.W, px = P - py * (uint32_t)J.W;
+  const uint4 r = philox4x32_10(make_uint4(P, s, 0u, 0u), J.seed_lo, J.seed_hi);
+  const float sx = ((float)px + unit24(r.x)) / (float)J.W;
+  const float sy = ((float)py + unit24(r.y)) / (float)J.H;
+  const float aspect = (float)J.W / (float)J.H;
   const float cx = (2.0f * sx - 1.0f) * sc.cam_tan_half * aspect;
   const float cy = (1.0f - 2.0f * sy) * sc.cam_tan_half;
   const f3 f = F3(sc.cam_fx, sc.cam_fy, sc.cam_fz), rr = F3(sc.cam_rx, sc.cam_ry, sc.cam_rz),
            vv = F3(sc.cam_vx, sc.cam_vy, sc.cam_vz);
   const f3 d = normalize(f + rr * cx + vv * cy);
   rays[2 * slot] = make_float4(sc.cam_px, sc.cam_py, sc.cam_pz, __uint_as_float(slot));
-  rays[2 * slot + 1] = make_float4(d.x, d.y, d.z, __uint_as_float(NO_PRIM));
-  beta[slot] = make_float4(1.0f, 1.0f, 1.0f, 0.0f);
+  rays[2 * slot + 1] = make_float4(d.x, d.y, d.z, __uint_as_float((j << 24) | PRIM24));
+  beta[slot] = make_float4(1.0f, 1.0f, 1.0f, __uint_as_float(j));
   L[slot] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   aux[2 * slot] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   aux[2 * slot + 1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 }
 
+// Queue entries of a traversal wave, 64 at a time.  Static schedule: the
+// grid strides over the queue (wave w takes entries w*64 + k*grid).  Dynamic:
+// each wave pulls its next 64 entries from a device counter (load balance
+// across waves of very different ray costs).
+struct WaveQueue {
+  uint32_t* ctr;
+  uint32_t base, step;
+  bool dyn;
+  __device__ __forceinline__ uint32_t fetch() {
+    uint32_t v = 0;
+    if (__lane_id() == 0) v = atomicAdd(ctr, 64u);
+    return __builtin_amdgcn_readfirstlane(v);
+  }
+  __device__ __forceinline__ WaveQueue(uint32_t* c, bool d) : ctr(c), dyn(d) {
+    step = gridDim.x * TB;
+    base = dyn ? fetch() : blockIdx.x * TB + (threadIdx.x & ~63u);
+  }
+  __device__ __forceinline__ void next() { base = dyn ? fetch() : base + step; }
+};
+
 template <bool COUNT>
-__global__ __launch_bounds__(TB) void k_extend(SceneView sc, const float4* __restrict__ rays,
-                                               const uint32_t* __restrict__ count,
+__global__ __launch_bounds__(TB) void k_extend(const DevJob* __restrict__ jobs, int b, int dyn,
+                                               const float4* __restrict__ rays,
+                                               uint32_t* __restrict__ q,
                                                float4* __restrict__ hits,
                                                uint32_t* __restrict__ spill,
                                                unsigned long long* __restrict__ stats) {
   __shared__ uint32_t stk[LDS_STACK * TB];
-  const uint32_t n = *count;
+  const uint32_t n = q[Q_RAYS + b];
+  WaveQueue wq(q + Q_FETCH_EXT + b, dyn != 0);
   const uint32_t gtid = blockIdx.x * TB + threadIdx.x;
   Stack st{stk + threadIdx.x, spill + gtid, gridDim.x * TB, 0, 0u, false};
   WorkCount wc;
-  for (uint32_t q = gtid; q < n; q += gridDim.x * TB) {
-    const float4 R0 = rays[2 * q], R1 = rays[2 * q + 1];
-    TraceState ts{INFINITY, NO_PRIM, 0.0f, 0.0f};
-    traverse<false, COUNT>(sc, xyz(R0), xyz(R1), __float_as_uint(R1.w), NO_PRIM, NO_PRIM, st, ts,
-                           wc);
-    hits[q] = make_float4(ts.t, __uint_as_float(ts.prim), ts.b1, ts.b2);
+  for (; wq.base < n; wq.next()) {
+    const uint32_t qi = wq.base + __lane_id();
+    if (qi < n) {
+      const float4 R0 = rays[2 * qi], R1 = rays[2 * qi + 1];
+      const uint32_t tag = __float_as_uint(R1.w);
+      const uint32_t j = job_of(tag);
+      TraceState ts{INFINITY, NO_PRIM, 0.0f, 0.0f};
+      // One pass per distinct job among the wave's lanes (nearly always one): the
+      // job id is wave-uniform inside, so the scene's pointers stay scalar.
+      for (;;) {
+        const uint32_t ju = __builtin_amdgcn_readfirstlane(j);
+        if (j == ju) {
+          traverse<false, COUNT>(trace_view(jobs[ju].sv), xyz(R0), xyz(R1), unpack_prim(tag),
+                                 NO_PRIM, NO_PRIM, st, ts, wc);
+          break;
+        }
+      }
+      hits[qi] = make_float4(ts.t, __uint_as_float(ts.prim), ts.b1, ts.b2);
+    }
   }
   if (st.spills) atomicAdd(stats + 3, (unsigned long long)st.spills);
   if (st.overflow) atomicAdd(stats + 5, 1ull);
@@ -301,7 +415,8 @@ __device__ __forceinline__ f3 ggx_eval(f3 f0, float alpha, f3 n, f3 wo, f3 wi, f
   return schlick(f0, dot(wi, h)) * (D * G / (4.0f * ci * co));
 }
 
-__global__ __launch_bounds__(256) void k_shade(ChunkGeom g, SceneView sc, int b,
+
+__global__ __launch_bounds__(256) void k_shade(const DevJob* __restrict__ jobs, int64_t g0, int b,
                                                const float4* __restrict__ rays_in,
                                                const float4* __restrict__ hits,
                                                uint32_t* __restrict__ q,
@@ -316,12 +431,15 @@ __global__ __launch_bounds__(256) void k_shade(ChunkGeom g, SceneView sc, int b,
   for (uint32_t base = blockIdx.x * 256; base < n; base += gridDim.x * 256) {
     const uint32_t qi = base + threadIdx.x;
     bool cont = false, shad = false;
-    uint32_t slot = 0, prim = NO_PRIM, li = 0;
+    uint32_t slot = 0, prim = NO_PRIM, li = 0, j = 0;
     f3 x = F3(0, 0, 0), wi = F3(0, 0, 0), swi = F3(0, 0, 0), c = F3(0, 0, 0);
     float sr = 0.0f;
     if (qi < n) {
       const float4 R0 = rays_in[2 * qi], R1 = rays_in[2 * qi + 1];
       slot = __float_as_uint(R0.w);
+      j = job_of(__float_as_uint(R1.w));
+      const DevJob& J = jobs[j];
+      const SceneView& sc = J.sv;
       const f3 o = xyz(R0), d = xyz(R1);
       const float4 Hh = hits[qi];
       prim = __float_as_uint(Hh.y);
@@ -364,12 +482,12 @@ __global__ __launch_bounds__(256) void k_shade(ChunkGeom g, SceneView sc, int b,
         if (front && (em.x != 0.0f || em.y != 0.0f || em.z != 0.0f) &&
             (!(info & PRIM_LISTED) || b == 0))
           L = L + mul(beta, em);
-        bool alive = b != g.max_depth && kind != MRS_EMITTER && dot(ns, wo) > 0.0f;
+        bool alive = b != J.max_depth && kind != MRS_EMITTER && dot(ns, wo) > 0.0f;
         if (alive) {
-          uint32_t P, s, pl;
-          slot_pixel_sample(g, slot, P, s, pl);
-          const uint4 bl = philox4x32_10(make_uint4(P, s, 1u + 2u * b, 0u), g.seed_lo, g.seed_hi);
-          const uint4 bs = philox4x32_10(make_uint4(P, s, 2u + 2u * b, 0u), g.seed_lo, g.seed_hi);
+          uint32_t P, s;
+          path_pixel_sample(J, g0 + slot, P, s);
+          const uint4 bl = philox4x32_10(make_uint4(P, s, 1u + 2u * b, 0u), J.seed_lo, J.seed_hi);
+          const uint4 bs = philox4x32_10(make_uint4(P, s, 2u + 2u * b, 0u), J.seed_lo, J.seed_hi);
           const float alpha = m.color_alpha.w;
           const float co = dot(ns, wo);
           // next-event estimation: one light chosen uniformly, area sampling
@@ -420,12 +538,12 @@ __global__ __launch_bounds__(256) void k_shade(ChunkGeom g, SceneView sc, int b,
               beta = mul(beta, schlick(col, oh) * (G * oh / (co * ch)));
             }
           }
-          if (alive && b >= g.rr_start) {
+          if (alive && b >= J.rr_start) {
             const float qq = fminf(0.95f, maxc(beta));
             if (!(unit24(bs.z) < qq)) alive = false;
             else beta = beta * (1.0f / qq);
           }
-          beta_buf[slot] = make_float4(beta.x, beta.y, beta.z, 0.0f);
+          beta_buf[slot] = make_float4(beta.x, beta.y, beta.z, __uint_as_float(j));
         }
         cont = alive;
       }
@@ -434,42 +552,56 @@ __global__ __launch_bounds__(256) void k_shade(ChunkGeom g, SceneView sc, int b,
     const uint32_t ri = wave_append(cont, cnt_next);
     if (cont) {
       rays_out[2 * ri] = make_float4(x.x, x.y, x.z, __uint_as_float(slot));
-      rays_out[2 * ri + 1] = make_float4(wi.x, wi.y, wi.z, __uint_as_float(prim));
+      rays_out[2 * ri + 1] = make_float4(wi.x, wi.y, wi.z, __uint_as_float((j << 24) | prim));
     }
     const uint32_t si = wave_append(shad, cnt_shadow);
     if (shad) {
       shadow[3 * si] = make_float4(x.x, x.y, x.z, __uint_as_float(slot | (li << 24)));
       shadow[3 * si + 1] = make_float4(swi.x, swi.y, swi.z, sr);
-      shadow[3 * si + 2] = make_float4(c.x, c.y, c.z, __uint_as_float(prim));
+      shadow[3 * si + 2] = make_float4(c.x, c.y, c.z, __uint_as_float((j << 24) | prim));
     }
   }
 }
 
 template <bool COUNT>
-__global__ __launch_bounds__(TB) void k_shadow(SceneView sc, const float4* __restrict__ shadow,
-                                               const uint32_t* __restrict__ count,
+__global__ __launch_bounds__(TB) void k_shadow(const DevJob* __restrict__ jobs, int b, int dyn,
+                                               const float4* __restrict__ shadow,
+                                               uint32_t* __restrict__ q,
                                                float4* __restrict__ L_buf,
                                                uint32_t* __restrict__ spill,
                                                unsigned long long* __restrict__ stats) {
   __shared__ uint32_t stk[LDS_STACK * TB];
-  const uint32_t n = *count;
+  const uint32_t n = q[Q_SHADOW + b];
+  WaveQueue wq(q + Q_FETCH_SHD + b, dyn != 0);
   const uint32_t gtid = blockIdx.x * TB + threadIdx.x;
   Stack st{stk + threadIdx.x, spill + gtid, gridDim.x * TB, 0, 0u, false};
   WorkCount wc;
-  for (uint32_t q = gtid; q < n; q += gridDim.x * TB) {
-    const float4 S0 = shadow[3 * q], S1 = shadow[3 * q + 1], S2 = shadow[3 * q + 2];
-    const uint32_t tag = __float_as_uint(S0.w);
-    const uint32_t slot = tag & 0xffffffu, li = tag >> 24;
-    const DevLight& lt = sc.lights[li];
-    TraceState ts{S1.w, NO_PRIM, 0.0f, 0.0f};
-    const bool occ = traverse<true, COUNT>(sc, xyz(S0), xyz(S1), __float_as_uint(S2.w),
-                                           (uint32_t)lt.tri0, (uint32_t)lt.tri1, st, ts, wc);
-    if (!occ) {
-      float4 Lv = L_buf[slot];
-      Lv.x += S2.x;
-      Lv.y += S2.y;
-      Lv.z += S2.z;
-      L_buf[slot] = Lv;
+  for (; wq.base < n; wq.next()) {
+    const uint32_t qi = wq.base + __lane_id();
+    if (qi < n) {
+      const float4 S0 = shadow[3 * qi], S1 = shadow[3 * qi + 1], S2 = shadow[3 * qi + 2];
+      const uint32_t tag = __float_as_uint(S0.w), ptag = __float_as_uint(S2.w);
+      const uint32_t slot = tag & 0xffffffu, li = tag >> 24;
+      const uint32_t j = job_of(ptag);
+      TraceState ts{S1.w, NO_PRIM, 0.0f, 0.0f};
+      bool occ = false;
+      for (;;) {  // wave-uniform job per pass, as in k_extend
+        const uint32_t ju = __builtin_amdgcn_readfirstlane(j);
+        if (j == ju) {
+          const SceneView& sc = jobs[ju].sv;
+          const DevLight& lt = sc.lights[li];
+          occ = traverse<true, COUNT>(trace_view(sc), xyz(S0), xyz(S1), unpack_prim(ptag),
+                                      (uint32_t)lt.tri0, (uint32_t)lt.tri1, st, ts, wc);
+          break;
+        }
+      }
+      if (!occ) {
+        float4 Lv = L_buf[slot];
+        Lv.x += S2.x;
+        Lv.y += S2.y;
+        Lv.z += S2.z;
+        L_buf[slot] = Lv;
+      }
     }
   }
   if (st.spills) atomicAdd(stats + 3, (unsigned long long)st.spills);
@@ -478,24 +610,24 @@ __global__ __launch_bounds__(TB) void k_shadow(SceneView sc, const float4* __res
   if (COUNT && wc.tests) atomicAdd(stats + 9, (unsigned long long)wc.tests);
 }
 
+// Per pixel of every job overlapping the chunk [g0, g0 + n): add its samples of
+// the chunk, in sample order, to the pixel's sums (FP32 or FP64 per job).
 template <typename T>
-__global__ __launch_bounds__(256) void k_accumulate(ChunkGeom g, int32_t ns, uint32_t np,
-                                                    const float4* __restrict__ L_buf,
-                                                    const float4* __restrict__ aux_buf,
-                                                    T* __restrict__ acc_rgb,
-                                                    T* __restrict__ acc_aux,
-                                                    T* __restrict__ acc_sq,
-                                                    unsigned long long* __restrict__ stats) {
-  const uint32_t i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= np) return;
-  const uint32_t pl = (uint32_t)g.p0 + i;
-  T r = acc_rgb[3 * pl], gg = acc_rgb[3 * pl + 1], bb = acc_rgb[3 * pl + 2];
-  T sr = acc_sq[3 * pl], sg = acc_sq[3 * pl + 1], sb = acc_sq[3 * pl + 2];
+__device__ __forceinline__ void accumulate_pixel(const DevJob& J, char* acc_base, uint32_t pl,
+                                                 int64_t s_lo, int64_t s_hi, int64_t slot0,
+                                                 int64_t npix, const float4* __restrict__ L_buf,
+                                                 const float4* __restrict__ aux_buf,
+                                                 uint32_t& bad) {
+  T* acc = reinterpret_cast<T*>(acc_base + J.acc_off);
+  T* a_rgb = acc + 3 * (int64_t)pl;
+  T* a_aux = acc + 3 * npix + 7 * (int64_t)pl;
+  T* a_sq = acc + 10 * npix + 3 * (int64_t)pl;
+  T r = a_rgb[0], gg = a_rgb[1], bb = a_rgb[2];
+  T sr = a_sq[0], sg = a_sq[1], sb = a_sq[2];
   T a[7];
-  for (int c = 0; c < 7; ++c) a[c] = acc_aux[7 * pl + c];
-  uint32_t bad = 0;
-  for (int k = 0; k < ns; ++k) {
-    const uint32_t slot = (uint32_t)k * np + i;
+  for (int c = 0; c < 7; ++c) a[c] = a_aux[c];
+  for (int64_t s = s_lo; s <= s_hi; ++s) {
+    const int64_t slot = slot0 + s * npix;
     float4 Lv = L_buf[slot];
     if (!(isfinite(Lv.x) && isfinite(Lv.y) && isfinite(Lv.z))) {
       Lv = make_float4(0, 0, 0, 0);
@@ -511,33 +643,68 @@ __global__ __launch_bounds__(256) void k_accumulate(ChunkGeom g, int32_t ns, uin
     a[0] += (T)A0.x; a[1] += (T)A0.y; a[2] += (T)A0.z; a[3] += (T)A0.w;
     a[4] += (T)A1.x; a[5] += (T)A1.y; a[6] += (T)A1.z;
   }
-  acc_rgb[3 * pl] = r; acc_rgb[3 * pl + 1] = gg; acc_rgb[3 * pl + 2] = bb;
-  acc_sq[3 * pl] = sr; acc_sq[3 * pl + 1] = sg; acc_sq[3 * pl + 2] = sb;
-  for (int c = 0; c < 7; ++c) acc_aux[7 * pl + c] = a[c];
+  a_rgb[0] = r; a_rgb[1] = gg; a_rgb[2] = bb;
+  a_sq[0] = sr; a_sq[1] = sg; a_sq[2] = sb;
+  for (int c = 0; c < 7; ++c) a_aux[c] = a[c];
+}
+
+__global__ __launch_bounds__(256) void k_accumulate(const DevJob* __restrict__ jobs, int njobs,
+                                                    int64_t g0, uint32_t n, int64_t pix_lo,
+                                                    int64_t pix_hi,
+                                                    const float4* __restrict__ L_buf,
+                                                    const float4* __restrict__ aux_buf,
+                                                    char* __restrict__ acc_base,
+                                                    unsigned long long* __restrict__ stats) {
+  const int64_t i = pix_lo + (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= pix_hi) return;
+  const uint32_t j = find_job_pix(jobs, njobs, i);
+  const DevJob& J = jobs[j];
+  const int64_t npix = (int64_t)J.ww * J.wh;
+  const uint32_t pl = (uint32_t)(i - J.pix_first);
+  // samples s with g = first + s npix + pl in [g0, g0 + n)
+  const int64_t lo = g0 - J.first - pl, hi = g0 + n - 1 - J.first - pl;
+  if (hi < 0) return;
+  const int64_t s_lo = lo <= 0 ? 0 : (lo + npix - 1) / npix;
+  int64_t s_hi = hi / npix;
+  if (s_hi > J.spp - 1) s_hi = J.spp - 1;
+  if (s_lo > s_hi) return;
+  const int64_t slot0 = J.first + pl - g0;
+  uint32_t bad = 0;
+  if (J.fp64)
+    accumulate_pixel<double>(J, acc_base, pl, s_lo, s_hi, slot0, npix, L_buf, aux_buf, bad);
+  else
+    accumulate_pixel<float>(J, acc_base, pl, s_lo, s_hi, slot0, npix, L_buf, aux_buf, bad);
   if (bad) atomicAdd(stats + 0, (unsigned long long)bad);
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_zero(T* p, size_t n) {
-  for (size_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) p[i] = (T)0;
+__global__ __launch_bounds__(256) void k_zero_words(uint32_t* p, size_t n) {
+  for (size_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) p[i] = 0u;
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_resolve(uint32_t npix, int32_t spp,
-                                                 const T* __restrict__ acc_rgb,
-                                                 const T* __restrict__ acc_aux,
-                                                 const T* __restrict__ acc_sq,
-                                                 float* __restrict__ out_rgb,
-                                                 float* __restrict__ out_aux,
-                                                 float* __restrict__ out_sq) {
-  const uint32_t i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= npix) return;
-  const T inv = (T)1 / (T)spp;
-  for (int c = 0; c < 3; ++c) out_rgb[3 * i + c] = (float)(acc_rgb[3 * i + c] * inv);
-  if (out_aux)
-    for (int c = 0; c < 7; ++c) out_aux[7 * i + c] = (float)(acc_aux[7 * i + c] * inv);
-  if (out_sq)
-    for (int c = 0; c < 3; ++c) out_sq[3 * i + c] = (float)acc_sq[3 * i + c];
+__device__ __forceinline__ void resolve_pixel(const DevJob& J, const char* acc_base, uint32_t pl,
+                                              int64_t npix) {
+  const T* acc = reinterpret_cast<const T*>(acc_base + J.acc_off);
+  const T inv = (T)1 / (T)J.spp;
+  for (int c = 0; c < 3; ++c) J.out_rgb[3 * (int64_t)pl + c] = (float)(acc[3 * (int64_t)pl + c] * inv);
+  if (J.out_aux)
+    for (int c = 0; c < 7; ++c)
+      J.out_aux[7 * (int64_t)pl + c] = (float)(acc[3 * npix + 7 * (int64_t)pl + c] * inv);
+  if (J.out_sq)
+    for (int c = 0; c < 3; ++c)
+      J.out_sq[3 * (int64_t)pl + c] = (float)acc[10 * npix + 3 * (int64_t)pl + c];
+}
+
+__global__ __launch_bounds__(256) void k_resolve(const DevJob* __restrict__ jobs, int njobs,
+                                                 int64_t total_pix, const char* __restrict__ acc) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= total_pix) return;
+  const uint32_t j = find_job_pix(jobs, njobs, i);
+  const DevJob& J = jobs[j];
+  const int64_t npix = (int64_t)J.ww * J.wh;
+  const uint32_t pl = (uint32_t)(i - J.pix_first);
+  if (J.fp64) resolve_pixel<double>(J, acc, pl, npix);
+  else resolve_pixel<float>(J, acc, pl, npix);
 }
 
 __global__ __launch_bounds__(64) void k_tally(const uint32_t* __restrict__ q, int nb,
@@ -570,7 +737,7 @@ __global__ __launch_bounds__(256) void k_debug_hit(SceneView sc, int32_t n,
   TraceState ts{INFINITY, NO_PRIM, 0.0f, 0.0f};
   WorkCount wc;
   const uint32_t sk = skip ? (uint32_t)skip[i] : NO_PRIM;
-  traverse<false, false>(sc, F3(o[3 * i], o[3 * i + 1], o[3 * i + 2]),
+  traverse<false, false>(trace_view(sc), F3(o[3 * i], o[3 * i + 1], o[3 * i + 2]),
                          F3(d[3 * i], d[3 * i + 1], d[3 * i + 2]), sk, NO_PRIM, NO_PRIM, st, ts,
                          wc);
   t_out[i] = ts.t;
@@ -597,7 +764,7 @@ __global__ __launch_bounds__(256) void k_debug_philox(int32_t n, const uint32_t*
 struct Workspace {
   size_t cap_paths = 0;
   int spill_threads = 0;
-  size_t acc_pix = 0;
+  size_t acc_bytes = 0;
   float4* rays[2] = {nullptr, nullptr};
   float4* hits = nullptr;
   float4* shadow = nullptr;
@@ -607,10 +774,11 @@ struct Workspace {
   uint32_t* spill = nullptr;
   uint32_t* q = nullptr;
   unsigned long long* stats = nullptr;
-  double* acc = nullptr;  // 13 values per pixel (rgb, aux 7, sumsq 3), FP32 or FP64
+  char* acc = nullptr;      // per-job accumulators (single renders)
+  DevJob* one = nullptr;    // device copy of the job of a single render
 };
 Workspace g_ws;
-mrs_tuning g_tune = {1 << 22, 2048};
+mrs_tuning g_tune = {1 << 22, 4096, 0};
 bool g_count_work = false;
 
 template <typename T>
@@ -619,11 +787,12 @@ void hfree(T*& p) {
   p = nullptr;
 }
 
-mrs_status ensure_workspace(size_t paths, int threads, size_t npix) {
+mrs_status ensure_workspace(size_t paths, int threads) {
   if (!g_ws.q) {
     MRS_TRY_HIP(hipMalloc(&g_ws.q, sizeof(uint32_t) * Q_WORDS));
     MRS_TRY_HIP(hipMalloc(&g_ws.stats, sizeof(unsigned long long) * MRS_NUM_COUNTERS));
     MRS_TRY_HIP(hipMemset(g_ws.stats, 0, sizeof(unsigned long long) * MRS_NUM_COUNTERS));
+    MRS_TRY_HIP(hipMalloc(&g_ws.one, sizeof(DevJob)));
   }
   if (paths > g_ws.cap_paths) {
     for (auto*& p : g_ws.rays) hfree(p);
@@ -656,108 +825,92 @@ mrs_status ensure_workspace(size_t paths, int threads, size_t npix) {
     }
     g_ws.spill_threads = threads;
   }
-  if (npix > g_ws.acc_pix) {
+  return MRS_OK;
+}
+
+mrs_status ensure_acc(size_t bytes) {
+  if (bytes > g_ws.acc_bytes) {
     hfree(g_ws.acc);
-    if (hipMalloc(&g_ws.acc, sizeof(double) * 13 * npix) != hipSuccess) {
+    if (hipMalloc(&g_ws.acc, bytes) != hipSuccess) {
       (void)hipGetLastError();
-      g_ws.acc_pix = 0;
+      g_ws.acc_bytes = 0;
       return fail(MRS_ERR_OUT_OF_MEMORY, "render: accumulator allocation failed");
     }
-    g_ws.acc_pix = npix;
+    g_ws.acc_bytes = bytes;
   }
   return MRS_OK;
 }
 
 inline unsigned cdiv(size_t a, size_t b) { return (unsigned)((a + b - 1) / b); }
 
-template <typename T>
-mrs_status render_t(const mrs_scene* s, const RenderArgs& a, hipStream_t st) {
-  const size_t npix = (size_t)a.ww * a.wh;
-  const size_t C = (size_t)g_tune.chunk_paths;
-  const int blocks = g_tune.trace_blocks;
-  mrs_status rc = ensure_workspace(std::min(C, npix * (size_t)a.spp), blocks * TB, npix);
-  if (rc != MRS_OK) return rc;
-  T* acc_rgb = (T*)g_ws.acc;
-  T* acc_aux = acc_rgb + 3 * npix;
-  T* acc_sq = acc_aux + 7 * npix;
-  k_zero<T><<<std::min(4096u, cdiv(13 * npix, 256)), 256, 0, st>>>(acc_rgb, 13 * npix);
-  ChunkGeom g{};
-  g.W = a.W;
-  g.H = a.H;
-  g.x0 = a.x0;
-  g.y0 = a.y0;
-  g.ww = a.ww;
-  g.seed_lo = (uint32_t)(a.seed & 0xffffffffu);
-  g.seed_hi = (uint32_t)(a.seed >> 32);
-  g.max_depth = a.max_depth;
-  g.rr_start = a.rr_start;
-  const SceneView sc = s->view;
-  // chunk plan: whole sample passes when a pass fits, else pixel ranges of one sample
-  std::vector<std::pair<int, std::pair<size_t, size_t>>> plan;  // (ns, (s0 or p0, np))
-  if (npix <= C) {
-    const int per = (int)std::max<size_t>(1, C / npix);
-    for (int s0 = 0; s0 < a.spp; s0 += per) plan.push_back({std::min(per, a.spp - s0), {(size_t)s0, npix}});
+size_t acc_bytes_of(int64_t npix, bool fp64) {
+  return ((size_t)npix * 13 * (fp64 ? 8 : 4) + 255) & ~(size_t)255;
+}
+
+// The launch sequence of a batch whose job table is on the device: chunks of at
+// most chunk_paths paths over the concatenated path space; per chunk, generate,
+// then extend / shade / shadow per bounce, then accumulate; finally resolve.
+mrs_status launch_batch(const DevJob* d_jobs, const std::vector<DevJob>& jobs, char* acc,
+                        size_t acc_bytes, hipStream_t st) {
+  const int nj = (int)jobs.size();
+  int64_t total = 0, total_pix = 0;
+  int max_depth = 0;
+  for (const DevJob& J : jobs) {
+    total += (int64_t)J.spp * J.ww * J.wh;
+    total_pix += (int64_t)J.ww * J.wh;
+    max_depth = std::max(max_depth, (int)J.max_depth);
   }
-  for (size_t ci = 0;; ++ci) {
-    int ns;
-    size_t np;
-    if (npix <= C) {
-      if (ci >= plan.size()) break;
-      ns = plan[ci].first;
-      g.s0 = (int32_t)plan[ci].second.first;
-      g.p0 = 0;
-      np = npix;
-    } else {
-      const size_t per_sample = (npix + C - 1) / C;
-      const size_t sidx = ci / per_sample, part = ci % per_sample;
-      if (sidx >= (size_t)a.spp) break;
-      ns = 1;
-      g.s0 = (int32_t)sidx;
-      g.p0 = (int32_t)(part * C);
-      np = std::min(C, npix - part * C);
-    }
-    g.np = (int32_t)np;
-    const uint32_t n = (uint32_t)(np * (size_t)ns);
+  const int64_t C = g_tune.chunk_paths;
+  const int blocks = g_tune.trace_blocks;
+  const int dyn = g_tune.schedule;
+  k_zero_words<<<std::min(4096u, cdiv(acc_bytes / 4, 256)), 256, 0, st>>>((uint32_t*)acc,
+                                                                          acc_bytes / 4);
+  for (int64_t g0 = 0; g0 < total; g0 += C) {
+    const uint32_t n = (uint32_t)std::min<int64_t>(C, total - g0);
     const unsigned gb = std::min<unsigned>(blocks, cdiv(n, TB));
     k_reset<<<1, 256, 0, st>>>(g_ws.q, n);
     prof_begin(KID_GENERATE, st);
-    k_generate<<<cdiv(n, 256), 256, 0, st>>>(g, sc, n, g_ws.rays[0], g_ws.beta, g_ws.L, g_ws.aux);
+    k_generate<<<cdiv(n, 256), 256, 0, st>>>(d_jobs, nj, g0, n, g_ws.rays[0], g_ws.beta, g_ws.L,
+                                             g_ws.aux);
     prof_end(KID_GENERATE, st);
-    for (int b = 0; b <= a.max_depth; ++b) {
+    for (int b = 0; b <= max_depth; ++b) {
       float4* rin = g_ws.rays[b & 1];
       float4* rout = g_ws.rays[(b + 1) & 1];
       prof_begin(KID_EXTEND, st);
       if (g_count_work)
-        k_extend<true><<<gb, TB, 0, st>>>(sc, rin, g_ws.q + Q_RAYS + b, g_ws.hits, g_ws.spill,
-                                          g_ws.stats);
+        k_extend<true><<<gb, TB, 0, st>>>(d_jobs, b, dyn, rin, g_ws.q, g_ws.hits, g_ws.spill, g_ws.stats);
       else
-        k_extend<false><<<gb, TB, 0, st>>>(sc, rin, g_ws.q + Q_RAYS + b, g_ws.hits, g_ws.spill,
-                                           g_ws.stats);
+        k_extend<false><<<gb, TB, 0, st>>>(d_jobs, b, dyn, rin, g_ws.q, g_ws.hits, g_ws.spill, g_ws.stats);
       prof_end(KID_EXTEND, st);
       prof_begin(KID_SHADE, st);
-      k_shade<<<gb, 256, 0, st>>>(g, sc, b, rin, g_ws.hits, g_ws.q, rout, g_ws.shadow, g_ws.beta,
-                                  g_ws.L, g_ws.aux);
+      k_shade<<<gb, 256, 0, st>>>(d_jobs, g0, b, rin, g_ws.hits, g_ws.q, rout, g_ws.shadow,
+                                  g_ws.beta, g_ws.L, g_ws.aux);
       prof_end(KID_SHADE, st);
-      if (b < a.max_depth) {
+      if (b < max_depth) {
         prof_begin(KID_SHADOW, st);
         if (g_count_work)
-          k_shadow<true><<<gb, TB, 0, st>>>(sc, g_ws.shadow, g_ws.q + Q_SHADOW + b, g_ws.L,
-                                            g_ws.spill, g_ws.stats);
+          k_shadow<true><<<gb, TB, 0, st>>>(d_jobs, b, dyn, g_ws.shadow, g_ws.q, g_ws.L, g_ws.spill,
+                                            g_ws.stats);
         else
-          k_shadow<false><<<gb, TB, 0, st>>>(sc, g_ws.shadow, g_ws.q + Q_SHADOW + b, g_ws.L,
-                                             g_ws.spill, g_ws.stats);
+          k_shadow<false><<<gb, TB, 0, st>>>(d_jobs, b, dyn, g_ws.shadow, g_ws.q, g_ws.L, g_ws.spill,
+                                             g_ws.stats);
         prof_end(KID_SHADOW, st);
       }
     }
+    // pixels of the jobs this chunk overlaps
+    int jlo = 0, jhi = nj - 1;
+    while (jlo < nj - 1 && jobs[jlo + 1].first <= g0) ++jlo;
+    while (jhi > 0 && jobs[jhi].first >= g0 + (int64_t)n) --jhi;
+    const int64_t pix_lo = jobs[jlo].pix_first;
+    const int64_t pix_hi = jobs[jhi].pix_first + (int64_t)jobs[jhi].ww * jobs[jhi].wh;
     prof_begin(KID_ACCUMULATE, st);
-    k_accumulate<T><<<cdiv(np, 256), 256, 0, st>>>(g, ns, (uint32_t)np, g_ws.L, g_ws.aux, acc_rgb,
-                                                   acc_aux, acc_sq, g_ws.stats);
+    k_accumulate<<<cdiv((size_t)(pix_hi - pix_lo), 256), 256, 0, st>>>(
+        d_jobs, nj, g0, n, pix_lo, pix_hi, g_ws.L, g_ws.aux, acc, g_ws.stats);
     prof_end(KID_ACCUMULATE, st);
-    k_tally<<<1, 64, 0, st>>>(g_ws.q, a.max_depth + 1, g_ws.stats, n);
+    k_tally<<<1, 64, 0, st>>>(g_ws.q, max_depth + 1, g_ws.stats, n);
   }
   prof_begin(KID_RESOLVE, st);
-  k_resolve<T><<<cdiv(npix, 256), 256, 0, st>>>((uint32_t)npix, a.spp, acc_rgb, acc_aux, acc_sq,
-                                                a.out_rgb, a.out_aux, a.out_sumsq);
+  k_resolve<<<cdiv((size_t)total_pix, 256), 256, 0, st>>>(d_jobs, nj, total_pix, acc);
   prof_end(KID_RESOLVE, st);
   MRS_TRY_HIP(hipGetLastError());
   return MRS_OK;
@@ -765,10 +918,66 @@ mrs_status render_t(const mrs_scene* s, const RenderArgs& a, hipStream_t st) {
 
 }  // namespace
 
+DevJob make_job(const mrs_scene* s, const RenderArgs& a) {
+  DevJob J;
+  std::memset(&J, 0, sizeof J);
+  J.sv = s->view;
+  J.W = a.W;
+  J.H = a.H;
+  J.x0 = a.x0;
+  J.y0 = a.y0;
+  J.ww = a.ww;
+  J.wh = a.wh;
+  J.spp = a.spp;
+  J.max_depth = a.max_depth;
+  J.rr_start = a.rr_start;
+  J.fp64 = a.fp64 ? 1 : 0;
+  J.seed_lo = (uint32_t)(a.seed & 0xffffffffu);
+  J.seed_hi = (uint32_t)(a.seed >> 32);
+  J.out_rgb = a.out_rgb;
+  J.out_aux = a.out_aux;
+  J.out_sq = a.out_sumsq;
+  return J;
+}
+
 mrs_status render(const mrs_scene* s, const RenderArgs& a, hipStream_t st) {
   if (a.max_depth + 2 > MAX_BOUNCE_SLOTS)
     return fail(MRS_ERR_INVALID_ARGUMENT, "render: max_depth too large");
-  return a.fp64 ? render_t<double>(s, a, st) : render_t<float>(s, a, st);
+  DevJob J = make_job(s, a);
+  J.first = 0;
+  J.pix_first = 0;
+  J.acc_off = 0;
+  const int64_t npix = (int64_t)a.ww * a.wh;
+  mrs_status rc = ensure_workspace(std::min<int64_t>(g_tune.chunk_paths, npix * a.spp),
+                                   g_tune.trace_blocks * TB);
+  if (rc != MRS_OK) return rc;
+  const size_t ab = acc_bytes_of(npix, a.fp64);
+  if ((rc = ensure_acc(ab)) != MRS_OK) return rc;
+  k_store_job<<<1, 64, 0, st>>>(J, g_ws.one);
+  std::vector<DevJob> jobs{J};
+  return launch_batch(g_ws.one, jobs, g_ws.acc, ab, st);
+}
+
+mrs_status batch_prepare(std::vector<DevJob>& jobs, size_t* acc_bytes) {
+  int64_t first = 0, pix = 0;
+  size_t off = 0, paths_max = 0;
+  for (DevJob& J : jobs) {
+    const int64_t npix = (int64_t)J.ww * J.wh;
+    J.first = first;
+    J.pix_first = pix;
+    J.acc_off = (int64_t)off;
+    first += npix * J.spp;
+    pix += npix;
+    off += acc_bytes_of(npix, J.fp64 != 0);
+  }
+  paths_max = (size_t)std::min<int64_t>(g_tune.chunk_paths, first);
+  *acc_bytes = off;
+  return ensure_workspace(paths_max, g_tune.trace_blocks * TB);
+}
+
+mrs_status batch_launch(const DevJob* d_jobs, const std::vector<DevJob>& jobs, char* acc,
+                        size_t acc_bytes, hipStream_t st) {
+  return launch_batch(d_jobs, jobs, acc, acc_bytes, st);
 }
 
 mrs_status debug_closest_hit(const mrs_scene* s, int32_t n, const float* o, const float* d,
@@ -776,7 +985,7 @@ mrs_status debug_closest_hit(const mrs_scene* s, int32_t n, const float* o, cons
                              hipStream_t st) {
   if (n <= 0) return MRS_OK;
   const unsigned blocks = cdiv((size_t)n, 256);
-  mrs_status rc = ensure_workspace(1, (int)(blocks * 256), 1);
+  mrs_status rc = ensure_workspace(1, (int)(blocks * 256));
   if (rc != MRS_OK) return rc;
   k_debug_hit<<<blocks, 256, 0, st>>>(s->view, n, o, d, skip, t, prim, b, g_ws.spill);
   MRS_TRY_HIP(hipGetLastError());
@@ -799,7 +1008,7 @@ mrs_status get_counters(int64_t* out, bool reset, hipStream_t st) {
   MRS_TRY_HIP(hipStreamSynchronize(st));
   for (int i = 0; i < MRS_NUM_COUNTERS; ++i) out[i] = (int64_t)h[i];
   if (reset) {
-    k_zero<unsigned long long><<<1, 256, 0, st>>>(g_ws.stats, MRS_NUM_COUNTERS);
+    k_zero_words<<<1, 256, 0, st>>>((uint32_t*)g_ws.stats, 2 * MRS_NUM_COUNTERS);
     MRS_TRY_HIP(hipGetLastError());
   }
   return MRS_OK;
@@ -814,6 +1023,8 @@ mrs_status set_tuning(const mrs_tuning* t) {
     return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_set_tuning: chunk_paths must be in [256, 2^24]");
   if (t->trace_blocks < 1 || t->trace_blocks > 65536)
     return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_set_tuning: trace_blocks must be in [1, 65536]");
+  if (t->schedule != 0 && t->schedule != 1)
+    return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_set_tuning: schedule must be 0 or 1");
   g_tune = *t;
   return MRS_OK;
 }

@@ -126,17 +126,21 @@ def profile_read():
     return {names[i]: (float(ms[i]), int(n[i])) for i in range(L.NUM_KERNEL_IDS) if n[i]}
 
 
+TUNING_KEYS = ("chunk_paths", "trace_blocks", "schedule")
+
+
 def get_tuning():
     t = L.Tuning()
     L.check(L.lib().mrs_get_tuning(C.byref(t)))
-    return {"chunk_paths": t.chunk_paths, "trace_blocks": t.trace_blocks}
+    return {k: int(getattr(t, k)) for k in TUNING_KEYS}
 
 
-def set_tuning(chunk_paths=None, trace_blocks=None):
+def set_tuning(chunk_paths=None, trace_blocks=None, schedule=None):
     cur = get_tuning()
+    new = dict(chunk_paths=chunk_paths, trace_blocks=trace_blocks, schedule=schedule)
     t = L.Tuning()
-    t.chunk_paths = int(chunk_paths if chunk_paths is not None else cur["chunk_paths"])
-    t.trace_blocks = int(trace_blocks if trace_blocks is not None else cur["trace_blocks"])
+    for k in TUNING_KEYS:
+        setattr(t, k, int(new[k] if new[k] is not None else cur[k]))
     L.check(L.lib().mrs_set_tuning(C.byref(t)))
 
 
@@ -153,3 +157,67 @@ def philox(ctr, key):
     L.check(L.lib().mrs_debug_philox(n, L.ptr(ct), L.ptr(kt), L.ptr(out)))
     torch.cuda.synchronize()
     return out.cpu().numpy().view(np.uint32)
+
+
+class Batch:
+    """Several renders (uneven scenes, sizes, spp, depths) enqueued as one wavefront.
+
+    jobs: dicts with keys scene (GpuScene), W, H, spp, max_depth, seed, and optional
+    out_rgb / out_aux / out_sumsq (CUDA float32 tensors, allocated if missing; aux only
+    when want_aux is true), rr_start, window, accum_fp64.  Outputs are in .outputs."""
+
+    def __init__(self, jobs):
+        import torch
+        n = len(jobs)
+        arr = (L.Job * n)()
+        self.outputs = []
+        self._keep = []
+        for i, j in enumerate(jobs):
+            W, H = int(j["W"]), int(j["H"])
+            win = j.get("window")
+            ww, wh = (W, H) if win is None else (int(win[2]), int(win[3]))
+            rgb = j.get("out_rgb")
+            if rgb is None:
+                rgb = torch.empty(wh, ww, 3, dtype=torch.float32, device="cuda")
+            aux = j.get("out_aux")
+            if aux is None and j.get("want_aux", True):
+                aux = torch.empty(wh, ww, 7, dtype=torch.float32, device="cuda")
+            sq = j.get("out_sumsq")
+            o = L.RenderOpts()
+            L.lib().mrs_render_opts_default(C.byref(o))
+            o.rr_start = int(j.get("rr_start", 3))
+            if win is not None:
+                o.x0, o.y0, o.win_w, o.win_h = (int(v) for v in win)
+            o.accum_fp64 = int(j.get("accum_fp64", -1))
+            o.out_sumsq_dev = L.ptr(sq, 3 * ww * wh, "f32", "out_sumsq")
+            arr[i].scene = j["scene"].handle.value
+            arr[i].W, arr[i].H = W, H
+            arr[i].spp, arr[i].max_depth = int(j["spp"]), int(j["max_depth"])
+            arr[i].seed = int(j["seed"])
+            arr[i].opts = o
+            arr[i].out_rgb_dev = L.ptr(rgb, 3 * ww * wh, "f32", "out_rgb")
+            arr[i].out_aux_dev = L.ptr(aux, 7 * ww * wh, "f32", "out_aux")
+            self.outputs.append((rgb, aux))
+            self._keep += [rgb, aux, sq, j["scene"]]
+        L.use_current_stream()
+        h = C.c_void_p()
+        L.check(L.lib().mrs_batch_create(arr, n, C.byref(h)))
+        self.handle = h
+        self.paths = sum(int(j["spp"]) * (int(j["W"]) * int(j["H"]) if j.get("window") is None
+                                           else int(j["window"][2]) * int(j["window"][3]))
+                         for j in jobs)
+
+    def render(self):
+        L.use_current_stream()
+        L.check(L.lib().mrs_batch_render(self.handle))
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            L.lib().mrs_batch_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

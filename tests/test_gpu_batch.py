@@ -1,0 +1,119 @@
+"""Batched renders, HIP-graph replay of the hybrid frame, autotuned launch shapes."""
+import sys
+
+import numpy as np
+import pytest
+
+from mrs_inputs import scenes as S
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _jobs(mrs):
+    scenes = [mrs.GpuScene(S.cornell(1)), mrs.GpuScene(S.procedural_sized(301, 20000)),
+              mrs.GpuScene(S.procedural(7, spheres=((2, 4),), n_boxes=5, n_lights=2))]
+    return [
+        dict(scene=scenes[0], W=64, H=48, spp=5, max_depth=4, seed=11),
+        dict(scene=scenes[1], W=160, H=96, spp=2, max_depth=8, seed=12, window=(8, 4, 100, 60)),
+        dict(scene=scenes[2], W=40, H=40, spp=7, max_depth=3, seed=13, rr_start=1),
+        dict(scene=scenes[0], W=8, H=8, spp=1030, max_depth=2, seed=14),  # FP64 sums
+        dict(scene=scenes[1], W=16, H=12, spp=3, max_depth=6, seed=15, want_aux=False),
+    ]
+
+
+def _single(mrs, j):
+    kw = {k: j[k] for k in ("window", "rr_start") if k in j}
+    return mrs.render(j["scene"], j["W"], j["H"], j["spp"], j["max_depth"], j["seed"],
+                      want_aux=j.get("want_aux", True), **kw)
+
+
+@pytest.mark.parametrize("chunk,schedule", [(None, 0), (None, 1), (3000, 1), (257, 0)])
+def test_batch_matches_single_renders_bitwise(torch_cuda, chunk, schedule):
+    import paper_2106_12802_amd as mrs
+    old = mrs.get_tuning()
+    try:
+        mrs.set_tuning(schedule=schedule)
+        if chunk:
+            mrs.set_tuning(chunk_paths=chunk, trace_blocks=16)
+        jobs = _jobs(mrs)
+        b = mrs.Batch(jobs)
+        b.render()
+        torch_cuda.cuda.synchronize()
+        for j, (rgb, aux) in zip(jobs, b.outputs):
+            r1, a1 = _single(mrs, j)
+            torch_cuda.cuda.synchronize()
+            assert torch_cuda.equal(rgb, r1)
+            if aux is not None:
+                assert torch_cuda.equal(aux, a1)
+        b.render()  # a batch can be rendered again (same results)
+        torch_cuda.cuda.synchronize()
+        assert torch_cuda.equal(b.outputs[0][0], _single(mrs, jobs[0])[0])
+    finally:
+        mrs.set_tuning(**old)
+
+
+def test_graph_replay_of_hybrid_frame(torch_cuda):
+    """Capture HRLS + LRHS + fusion in a HIP graph; every replay equals the eager frame."""
+    import paper_2106_12802_amd as mrs
+    from paper_2106_12802_amd import hybrid as HY
+    torch = torch_cuda
+    gs = mrs.GpuScene(S.procedural(7, spheres=((2, 4),), n_boxes=5, n_lights=2))
+    net = mrs.FusionNet(seed=3)
+    W, H = 256, 128
+    out = torch.empty(H, W, 3, device="cuda")
+    eager, _ = HY.hybrid_frame(gs, net, W, H, 5, out=torch.empty(H, W, 3, device="cuda"))
+    eager = eager.clone()
+    # warm up on a side stream (buffers grow outside the capture), then capture
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        HY.hybrid_frame(gs, net, W, H, 5, out=out)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        HY.hybrid_frame(gs, net, W, H, 5, out=out)
+    for k in range(4):
+        out.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager), k
+        # eager work between replays
+        other, _ = HY.hybrid_frame(gs, net, W, H, 6 + k, out=torch.empty(H, W, 3, device="cuda"))
+        torch.cuda.synchronize()
+
+
+def test_autotune_applies_choice_and_keeps_results(torch_cuda, tmp_path):
+    import paper_2106_12802_amd as mrs
+    from paper_2106_12802_amd import autotune
+    old = mrs.get_tuning()
+    try:
+        gs = mrs.GpuScene(S.cornell(2))
+        ref, _ = mrs.render(gs, 96, 64, 8, 4, 3)
+        torch_cuda.cuda.synchronize()
+        wl = lambda: mrs.render(gs, 96, 64, 8, 4, 3)
+        cache = str(tmp_path / "tune.json")
+        cands = [(1 << 20, 512, 0), (4096, 64, 1), (1 << 22, 2048, 1)]
+        r = autotune.tune(wl, "cornell96", cache, reps=2, candidates=cands, log=_log)
+        assert (r["chunk_paths"], r["trace_blocks"], r["schedule"]) in cands and not r["cached"]
+        assert mrs.get_tuning() == {k: r[k] for k in ("chunk_paths", "trace_blocks", "schedule")}
+        again, _ = mrs.render(gs, 96, 64, 8, 4, 3)
+        torch_cuda.cuda.synchronize()
+        assert torch_cuda.equal(again, ref)
+        mrs.set_tuning(**old)
+        r2 = autotune.tune(wl, "cornell96", cache, candidates=cands)
+        assert r2["cached"] and r2["chunk_paths"] == r["chunk_paths"]
+    finally:
+        mrs.set_tuning(**old)

@@ -302,11 +302,11 @@ def test_window_is_crop_and_chunking_invariant(mrs, torch_cuda):
     assert torch_cuda.equal(waux, faux[12:21, 8:25])
     old = mrs.get_tuning()
     try:
-        for chunk, blocks in [(256, 3), (1000, 7), (48 * 40 * 2 + 5, 64)]:
-            mrs.set_tuning(chunk_paths=chunk, trace_blocks=blocks)
+        for chunk, blocks, sched in [(256, 3, 1), (1000, 7, 0), (48 * 40 * 2 + 5, 64, 1)]:
+            mrs.set_tuning(chunk_paths=chunk, trace_blocks=blocks, schedule=sched)
             again, aaux = mrs.render(gs, 48, 40, 6, 4, 77)
             torch_cuda.cuda.synchronize()
-            assert torch_cuda.equal(again, full), (chunk, blocks)
+            assert torch_cuda.equal(again, full), (chunk, blocks, sched)
             assert torch_cuda.equal(aaux, faux)
     finally:
         mrs.set_tuning(**old)
