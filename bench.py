@@ -211,6 +211,115 @@ def equal_psnr_block(net, n_scenes, log):
             "scenes": rows}
 
 
+def batched_block(net, log, n_scenes=32, tune=True):
+    """Uneven render+fuse frames (32 seeded scenes, 256x256..1920x1080, 10k..1M
+    triangles, HRLS 1..8 spp, LRHS 16..128 spp) as one batch plus the fusions,
+    captured in a HIP graph; timed against the same frames one call at a time."""
+    import torch
+
+    import paper_2106_12802_amd as mrs
+    from paper_2106_12802_amd import autotune
+    from paper_2106_12802_amd import tracer as R
+    from mrs_inputs import scenes as S
+
+    t0 = time.perf_counter()
+    specs = S.batch_specs(500, n_scenes)
+    scenes, frames, jobs = [], [], []
+    for seed, tris, W, H, sh, sl in specs:
+        gs = mrs.GpuScene(S.procedural_sized(seed, tris))
+        scenes.append(gs)
+        f = dict(W=W, H=H, sh=sh, sl=sl, seed=seed,
+                 hr=torch.empty(H, W, 3, device="cuda"), aux=torch.empty(H, W, 7, device="cuda"),
+                 lr=torch.empty(H // 4, W // 4, 3, device="cuda"),
+                 out=torch.empty(H, W, 3, device="cuda"))
+        frames.append(f)
+        jobs.append(dict(scene=gs, W=W, H=H, spp=sh, max_depth=MAX_DEPTH, seed=2 * seed,
+                         out_rgb=f["hr"], out_aux=f["aux"]))
+        jobs.append(dict(scene=gs, W=W // 4, H=H // 4, spp=sl, max_depth=MAX_DEPTH,
+                         seed=2 * seed + 1, out_rgb=f["lr"], want_aux=False))
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    paths = sum(j["W"] * j["H"] * j["spp"] for j in jobs)
+    log(f"[batch] {n_scenes} scenes, {paths / 1e6:.1f} M paths per batch (setup {setup_s:.1f} s)")
+
+    def sequential():
+        for gs, f in zip(scenes, frames):
+            R.render_ex(gs, f["W"], f["H"], f["sh"], MAX_DEPTH, 2 * f["seed"], f["hr"], f["aux"])
+            R.render_ex(gs, f["W"] // 4, f["H"] // 4, f["sl"], MAX_DEPTH, 2 * f["seed"] + 1,
+                        f["lr"], None)
+            net.fuse(f["hr"], f["aux"], f["lr"], out=f["out"])
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) * 1e3 / reps
+
+    seq_ms = timed(sequential, 2)
+    seq_out = [f["out"].clone() for f in frames]
+    log(f"[batch] one call per render/fuse: {seq_ms:.1f} ms")
+    # autotune the batch's launch shape (each candidate gets its own batch)
+    old = R.get_tuning()
+    made = {}
+
+    def workload():
+        key = tuple(R.get_tuning().values())
+        if key not in made:
+            for b in made.values():
+                b.close()
+            made.clear()
+            made[key] = mrs.Batch(jobs)
+        made[key].render()
+
+    tuned = None
+    if tune:
+        cands = [(c, b, 0) for c in (1 << 22, 1 << 23, 1 << 24, 1 << 25) for b in (4096, 8192)]
+        cands.append((1 << 24, 4096, 1))
+        tuned = autotune.tune(workload, f"batch{n_scenes}", "/tmp/mrs_autotune_bench.json",
+                              reps=2, candidates=cands, force=True, log=log)
+    for b in made.values():
+        b.close()
+    made.clear()
+    batch = mrs.Batch(jobs)  # created under the chosen tuning
+    R.set_tuning(**old)
+    # capture batch + fusions in one graph, on a stream that ran them once
+    st = torch.cuda.Stream()
+    st.wait_stream(torch.cuda.current_stream())
+
+    def frame_all():
+        batch.render()
+        for f in frames:
+            net.fuse(f["hr"], f["aux"], f["lr"], out=f["out"])
+
+    with torch.cuda.stream(st):
+        frame_all()
+    torch.cuda.synchronize()
+    eager = [f["out"].clone() for f in frames]
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=st):
+        frame_all()
+    graph_ms = timed(g.replay, 5)
+    same = all(torch.equal(f["out"], e) for f, e in zip(frames, eager))
+    same_seq = all(torch.equal(f["out"], e) for f, e in zip(frames, seq_out))
+    log(f"[batch] batch + fusions as one HIP graph: {graph_ms:.1f} ms "
+        f"({paths / graph_ms / 1e3:.1f} Mpaths/s), replay == eager: {same}, "
+        f"== one call at a time: {same_seq}")
+    batch.close()
+    return {"workload": f"{n_scenes} procedural scenes (seeds 500.., 10k-1M triangles, "
+                        "256x256-1920x1080), HRLS 1-8 spp + LRHS 16-128 spp at 1/4 size, "
+                        "max depth 8, plus one fusion per frame",
+            "triangles_total": int(sum(gs.num_tris for gs in scenes)), "paths": int(paths),
+            "ms_sequential_calls": round(seq_ms, 3), "ms_batched_graph": round(graph_ms, 3),
+            "mpaths_per_s_batched": round(paths / graph_ms / 1e3, 2),
+            "speedup": round(seq_ms / graph_ms, 4), "replay_equals_eager": bool(same),
+            "equals_one_call_at_a_time": bool(same_seq),
+            "tuning": {k: tuned[k] for k in ("chunk_paths", "trace_blocks", "schedule")}
+            if tuned else None}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -219,6 +328,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--equal-psnr-scenes", type=int, default=3,
                     help="held-out scenes in the equal-PSNR comparison (0: skip it)")
+    ap.add_argument("--batch-scenes", type=int, default=32,
+                    help="scenes in the batched render+fuse measurement (0: skip it)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 1 GiB device copy first (PMC byte-counter calibration)")
     ap.add_argument("--chunk-paths", type=int, default=None, help="tuning: paths resident at once")
@@ -265,7 +376,20 @@ def main():
     out = torch.empty(Hh, Wh, 3, device="cuda")
     paths = Wh * Hh * sh + Wl * Hl * sl
 
+    # HRLS and LRHS go through the wavefront together as one two-job batch
+    # (one launch sequence over both renders); each frame gets new seeds
+    frame_batch = mrs.Batch([
+        dict(scene=gs, W=Wh, H=Hh, spp=sh, max_depth=MAX_DEPTH, seed=0, out_rgb=hr_rgb,
+             out_aux=hr_aux),
+        dict(scene=gs, W=Wl, H=Hl, spp=sl, max_depth=MAX_DEPTH, seed=1, out_rgb=lr_rgb,
+             want_aux=False)])
+
     def step(i):
+        frame_batch.set_seeds([2 * i, 2 * i + 1])
+        frame_batch.render()
+        net.fuse(hr_rgb, hr_aux, lr_rgb, out=out)
+
+    def step_calls(i):
         R.render_ex(gs, Wh, Hh, sh, MAX_DEPTH, 2 * i, hr_rgb, hr_aux)
         R.render_ex(gs, Wl, Hl, sl, MAX_DEPTH, 2 * i + 1, lr_rgb, None)
         net.fuse(hr_rgb, hr_aux, lr_rgb, out=out)
@@ -295,6 +419,15 @@ def main():
     ms_per_step = dt * 1e3 / args.steps
     value = paths * args.steps / dt / 1e6
     log(f"[bench] {args.steps} frames: {ms_per_step:.3f} ms/frame, {value:.1f} Mpaths/s")
+    # the same frames as two separate render calls (for comparison, not timed above)
+    step_calls(0)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for i in range(args.steps):
+        step_calls(i)
+    torch.cuda.synchronize()
+    ms_calls = (time.perf_counter() - t1) * 1e3 / args.steps
+    log(f"[bench] same frames as two render calls: {ms_calls:.3f} ms/frame")
 
     ext_ms, ext_n = prof.get("extend", (0.0, 0))
     flop_frame = (FLOP_PER_VISIT * work["extend_visits"] + FLOP_PER_TEST * work["extend_tests"]
@@ -324,8 +457,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": "720p hybrid frame: procedural scene (seed 7, 101,446 triangles, "
                                "textured Lambert+GGX, 3 quad lights, env 0.2), HRLS 1280x720@4spp "
-                               "+ LRHS 320x180@64spp (max depth 8, RR from vertex 3) + BF16 fusion "
-                               "network (175.7 GFLOP)",
+                               "+ LRHS 320x180@64spp (max depth 8, RR from vertex 3; both renders as one "
+                               "two-job batch, new seeds every frame) + BF16 fusion network "
+                               "(175.7 GFLOP)",
                    "paths_per_frame": paths, "triangles": scene.num_tris,
                    "weights": "trained (paper_2106_12802_amd/weights)" if trained else "untrained",
                    "tuning": tuning},
@@ -333,9 +467,12 @@ def main():
         "roofline_cnn": cnn_roof,
         "kernel_ms_per_frame": kernel_ms,
         "rays_per_path": round((work["rays"] + work["shadow_rays"]) / paths, 3),
+        "ms_per_frame_two_render_calls": round(ms_calls, 4),
     }
     if args.equal_psnr_scenes > 0:
         result["equal_psnr"] = equal_psnr_block(net, args.equal_psnr_scenes, log)
+    if args.batch_scenes > 0:
+        result["batched"] = batched_block(net, log, args.batch_scenes)
     if not args.no_cpu_baseline:
         threads = max(1, min(16, len(os.sched_getaffinity(0))))
         log(f"[bench] timing the FP64 oracle on {threads} host threads")

@@ -168,7 +168,7 @@ typedef struct mrs_job {
   float* out_aux_dev; /* or NULL */
 } mrs_job;
 
-typedef struct mrs_batch mrs_batch; /* opaque: device job table + accumulators */
+typedef struct mrs_batch mrs_batch; /* opaque: job table, accumulators, workspace */
 
 /* Validates 1..255 jobs (each as mrs_render_ex would), uploads the job table
  * and reserves every buffer the batch needs (synchronous).  Jobs may differ in
@@ -179,13 +179,28 @@ typedef struct mrs_batch mrs_batch; /* opaque: device job table + accumulators *
  * bitwise those of the same mrs_render_ex call.  The scenes must outlive the
  * batch. */
 mrs_status mrs_batch_create(const mrs_job* jobs, int32_t n, mrs_batch** out);
-/* Enqueues the batch on the current stream.  Performs no allocation and no
- * host synchronisation (unless mrs_set_tuning enlarged the workspace since
- * mrs_batch_create), so it can be captured in a HIP graph. */
+/* Enqueues the batch on the current stream.  The batch owns its path
+ * workspace, sized with the tuning in force at mrs_batch_create (later
+ * mrs_set_tuning calls do not affect it), so this performs no allocation and
+ * no host synchronisation and can be captured in a HIP graph.  Two renders of
+ * one batch must not overlap (same stream, or ordered by events). */
 mrs_status mrs_batch_render(mrs_batch* batch);
+/* Replaces the seed of every job (seeds[i] for job i, as many as the batch
+ * has jobs): enqueues a small update of the device job table on the current
+ * stream, ordered before later renders of the batch.  No allocation. */
+mrs_status mrs_batch_set_seeds(mrs_batch* batch, const uint64_t* seeds);
+/* Synchronises the device, then frees the batch.  NULL is accepted. */
 mrs_status mrs_batch_destroy(mrs_batch* batch);
 
-/* Counters accumulated since the last reset (synchronises the stream):
+/* Single renders use a path workspace per stream (renders on different
+ * streams run concurrently; a built scene is read-only).  A workspace grows on
+ * the first render that needs more room (hipMalloc, so not under graph
+ * capture: run the same call shapes on the capturing stream once first) and is
+ * kept until this call, which synchronises the device and frees them all. */
+mrs_status mrs_release_workspaces(void);
+
+/* Counters accumulated by every stream since the last reset (synchronises
+ * the current stream):
  * [0] non-finite samples replaced by 0, [1] closest-hit rays, [2] shadow rays,
  * [3] traversal stack entries spilled from LDS to global memory,
  * [4] paths started, [5] stack overflows (must be 0),
@@ -215,7 +230,7 @@ mrs_status mrs_profile_read(double ms_out[MRS_NUM_KERNEL_IDS],
 
 /* Tuning knobs (performance only; results do not depend on them). */
 typedef struct mrs_tuning {
-  int32_t chunk_paths;  /* paths resident at once (default 1<<22) */
+  int32_t chunk_paths;  /* paths resident at once (default 1<<23, at most 1<<26) */
   int32_t trace_blocks; /* grid size of traversal kernels (default 4096) */
   int32_t schedule;     /* traversal queue: 0 grid-stride (default), 1 per-wave
                            dynamic fetch from a device counter */

@@ -493,3 +493,18 @@ def training_windows(seed: int, count: int, W: int = 1280, H: int = 720, size: i
     xs = rng.integers(0, (W - size) // 4 + 1, count) * 4
     ys = rng.integers(0, (H - size) // 4 + 1, count) * 4
     return list(zip(xs.tolist(), ys.tolist()))
+
+
+def batch_specs(first_seed: int = 500, count: int = 32):
+    """Uneven render+fuse jobs: (scene seed, triangle budget, W, H, HRLS spp, LRHS spp).
+
+    W x H between 256 x 256 and 1920 x 1080 (multiples of 8), triangle budgets
+    log-uniform in [10k, 1M], HRLS 1..8 spp, LRHS 16..128 spp at W/4 x H/4."""
+    rng = np.random.default_rng(first_seed * 104_729 + count)
+    out = []
+    for i in range(count):
+        tris = int(np.exp(rng.uniform(np.log(1e4), np.log(1e6))))
+        W = int(rng.integers(256 // 8, 1920 // 8 + 1)) * 8
+        H = int(rng.integers(256 // 8, 1080 // 8 + 1)) * 8
+        out.append((first_seed + i, tris, W, H, int(rng.integers(1, 9)), int(rng.integers(16, 129))))
+    return out

@@ -120,6 +120,8 @@ def lib():
         "mrs_batch_create": ([C.POINTER(Job), I32, C.POINTER(P)], I32),
         "mrs_batch_render": ([P], I32),
         "mrs_batch_destroy": ([P], I32),
+        "mrs_release_workspaces": ([], I32),
+        "mrs_batch_set_seeds": ([P, P], I32),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(L, name)
@@ -145,7 +147,7 @@ def exported_symbols():
         "mrs_net_init", "mrs_net_set_params", "mrs_net_get_params", "mrs_fuse", "mrs_fuse_batch",
         "mrs_debug_net_activation", "mrs_image_metrics", "mrs_net_loss_grad", "mrs_train_step",
         "mrs_net_get_state", "mrs_net_set_state", "mrs_batch_create", "mrs_batch_render",
-        "mrs_batch_destroy",
+        "mrs_batch_destroy", "mrs_release_workspaces", "mrs_batch_set_seeds",
     ]
 
 

@@ -13,7 +13,7 @@ import time
 
 from . import tracer as T
 
-CHUNKS = (1 << 20, 1 << 21, 1 << 22, 1 << 23)
+CHUNKS = (1 << 21, 1 << 22, 1 << 23, 1 << 24, 1 << 25)
 BLOCKS = (512, 1024, 2048, 4096)
 SCHEDULES = (0, 1)
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "mrs_autotune.json")

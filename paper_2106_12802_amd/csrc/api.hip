@@ -317,13 +317,6 @@ mrs_status validate_render(const char* fn, const mrs_scene* s, int32_t W, int32_
 }
 }  // namespace
 
-struct mrs_batch {
-  std::vector<DevJob> jobs;
-  DevJob* d_jobs = nullptr;
-  char* d_acc = nullptr;
-  size_t acc_bytes = 0;
-};
-
 mrs_status mrs_render_ex(const mrs_scene* s, int32_t W, int32_t H, int32_t spp, int32_t max_depth,
                          uint64_t seed, const mrs_render_opts* opts, float* out_rgb,
                          float* out_aux) {
@@ -349,44 +342,26 @@ mrs_status mrs_batch_create(const mrs_job* jobs, int32_t n, mrs_batch** out) {
     if (rc != MRS_OK) return rc;
     dj.push_back(make_job(j.scene, a));
   }
-  mrs_batch* b = new mrs_batch();
-  b->jobs = dj;
-  mrs_status rc = batch_prepare(b->jobs, &b->acc_bytes);
-  if (rc == MRS_OK &&
-      (hipMalloc(&b->d_jobs, sizeof(DevJob) * n) != hipSuccess ||
-       hipMalloc(&b->d_acc, b->acc_bytes) != hipSuccess)) {
-    (void)hipGetLastError();
-    rc = fail(MRS_ERR_OUT_OF_MEMORY, "mrs_batch_create: device allocation failed");
-  }
-  if (rc == MRS_OK) {
-    hipError_t e = hipMemcpy(b->d_jobs, b->jobs.data(), sizeof(DevJob) * n, hipMemcpyHostToDevice);
-    if (e != hipSuccess) rc = check_hip(e, "mrs_batch_create: job table upload");
-  }
-  if (rc != MRS_OK) {
-    if (b->d_jobs) (void)hipFree(b->d_jobs);
-    if (b->d_acc) (void)hipFree(b->d_acc);
-    delete b;
-    return rc;
-  }
-  *out = b;
-  return MRS_OK;
+  return batch_create(dj, out);
 }
 
 mrs_status mrs_batch_render(mrs_batch* b) {
   if (!b) return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_batch_render: batch is NULL");
-  std::vector<DevJob> tmp = b->jobs;
-  size_t bytes = 0;
-  mrs_status rc = batch_prepare(tmp, &bytes);  // the workspace may have to grow after retuning
-  if (rc != MRS_OK) return rc;
-  return batch_launch(b->d_jobs, b->jobs, b->d_acc, b->acc_bytes, current_stream());
+  return batch_render(b, current_stream());
+}
+
+mrs_status mrs_batch_set_seeds(mrs_batch* b, const uint64_t* seeds) {
+  if (!b || !seeds) return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_batch_set_seeds: NULL argument");
+  return batch_set_seeds(b, seeds, current_stream());
 }
 
 mrs_status mrs_batch_destroy(mrs_batch* b) {
-  if (!b) return MRS_OK;
-  (void)hipDeviceSynchronize();
-  if (b->d_jobs) (void)hipFree(b->d_jobs);
-  if (b->d_acc) (void)hipFree(b->d_acc);
-  delete b;
+  batch_destroy(b);
+  return MRS_OK;
+}
+
+mrs_status mrs_release_workspaces(void) {
+  release_workspaces();
   return MRS_OK;
 }
 

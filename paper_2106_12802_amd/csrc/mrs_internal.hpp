@@ -123,11 +123,13 @@ struct RenderArgs {
 };
 mrs_status render(const mrs_scene* s, const RenderArgs& a, hipStream_t st);
 DevJob make_job(const mrs_scene* s, const RenderArgs& a);
-// sets first / pix_first / acc_off of every job, returns the accumulator bytes
-// and makes sure the path workspace can hold the batch's chunks
-mrs_status batch_prepare(std::vector<DevJob>& jobs, size_t* acc_bytes);
-mrs_status batch_launch(const DevJob* d_jobs, const std::vector<DevJob>& jobs, char* acc,
-                        size_t acc_bytes, hipStream_t st);
+// a batch of validated jobs: job table, accumulators and its own workspace
+mrs_status batch_create(const std::vector<DevJob>& jobs, mrs_batch** out);
+mrs_status batch_render(mrs_batch* b, hipStream_t st);
+mrs_status batch_set_seeds(mrs_batch* b, const uint64_t* seeds, hipStream_t st);
+void batch_destroy(mrs_batch* b);
+// frees the per-stream workspaces (synchronises the device)
+void release_workspaces();
 mrs_status debug_closest_hit(const mrs_scene* s, int32_t n, const float* o, const float* d,
                              const int32_t* skip, float* t, int32_t* prim, float* b,
                              hipStream_t st);

@@ -17,7 +17,10 @@
 // sums its samples in order, so results do not depend on queue order, chunk
 // size or grid size.
 #include <algorithm>
+#include <atomic>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "mrs_internal.hpp"
@@ -282,6 +285,19 @@ __device__ __forceinline__ void path_pixel_sample(const DevJob& J, int64_t g, ui
 
 __global__ __launch_bounds__(64) void k_store_job(DevJob j, DevJob* dst) {
   if (threadIdx.x == 0) *dst = j;
+}
+
+struct SeedTable {
+  uint32_t n;
+  uint32_t lo[MAX_JOBS], hi[MAX_JOBS];
+};
+
+__global__ __launch_bounds__(256) void k_set_seeds(DevJob* jobs, SeedTable t) {
+  const uint32_t j = threadIdx.x;
+  if (j < t.n) {
+    jobs[j].seed_lo = t.lo[j];
+    jobs[j].seed_hi = t.hi[j];
+  }
 }
 
 __global__ __launch_bounds__(256) void k_reset(uint32_t* q, uint32_t n) {
@@ -761,6 +777,9 @@ __global__ __launch_bounds__(256) void k_debug_philox(int32_t n, const uint32_t*
 
 // ------------------------------------------------------------------ workspace
 
+// Path state of one stream of renders.  Renders enqueued on one stream share a
+// workspace in stream order; each stream, and each batch, has its own, so
+// renders on different streams can run concurrently.
 struct Workspace {
   size_t cap_paths = 0;
   int spill_threads = 0;
@@ -773,13 +792,15 @@ struct Workspace {
   float4* aux = nullptr;
   uint32_t* spill = nullptr;
   uint32_t* q = nullptr;
-  unsigned long long* stats = nullptr;
-  char* acc = nullptr;      // per-job accumulators (single renders)
-  DevJob* one = nullptr;    // device copy of the job of a single render
+  char* acc = nullptr;    // per-job accumulators (single renders)
+  DevJob* one = nullptr;  // device copy of the job of a single render
 };
-Workspace g_ws;
-mrs_tuning g_tune = {1 << 22, 4096, 0};
-bool g_count_work = false;
+
+std::mutex g_mu;  // guards the tables below and the tuning
+std::map<hipStream_t, Workspace*> g_stream_ws;
+unsigned long long* g_stats = nullptr;  // device counters shared by every stream
+mrs_tuning g_tune = {1 << 23, 4096, 0};
+std::atomic<bool> g_count_work{false};
 
 template <typename T>
 void hfree(T*& p) {
@@ -787,58 +808,96 @@ void hfree(T*& p) {
   p = nullptr;
 }
 
-mrs_status ensure_workspace(size_t paths, int threads) {
-  if (!g_ws.q) {
-    MRS_TRY_HIP(hipMalloc(&g_ws.q, sizeof(uint32_t) * Q_WORDS));
-    MRS_TRY_HIP(hipMalloc(&g_ws.stats, sizeof(unsigned long long) * MRS_NUM_COUNTERS));
-    MRS_TRY_HIP(hipMemset(g_ws.stats, 0, sizeof(unsigned long long) * MRS_NUM_COUNTERS));
-    MRS_TRY_HIP(hipMalloc(&g_ws.one, sizeof(DevJob)));
+void ws_release(Workspace& w) {
+  for (auto*& p : w.rays) hfree(p);
+  hfree(w.hits);
+  hfree(w.shadow);
+  hfree(w.beta);
+  hfree(w.L);
+  hfree(w.aux);
+  hfree(w.spill);
+  hfree(w.q);
+  hfree(w.acc);
+  hfree(w.one);
+  w.cap_paths = 0;
+  w.spill_threads = 0;
+  w.acc_bytes = 0;
+}
+
+mrs_status ensure_stats() {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (g_stats) return MRS_OK;
+  MRS_TRY_HIP(hipMalloc(&g_stats, sizeof(unsigned long long) * MRS_NUM_COUNTERS));
+  MRS_TRY_HIP(hipMemset(g_stats, 0, sizeof(unsigned long long) * MRS_NUM_COUNTERS));
+  return MRS_OK;
+}
+
+// Grows w to hold `paths` path slots and `threads` traversal threads (device
+// allocations happen only here, and only when the workspace grows).
+mrs_status ws_ensure(Workspace& w, size_t paths, int threads) {
+  mrs_status rc = ensure_stats();
+  if (rc != MRS_OK) return rc;
+  if (!w.q) {
+    MRS_TRY_HIP(hipMalloc(&w.q, sizeof(uint32_t) * Q_WORDS));
+    MRS_TRY_HIP(hipMalloc(&w.one, sizeof(DevJob)));
   }
-  if (paths > g_ws.cap_paths) {
-    for (auto*& p : g_ws.rays) hfree(p);
-    hfree(g_ws.hits);
-    hfree(g_ws.shadow);
-    hfree(g_ws.beta);
-    hfree(g_ws.L);
-    hfree(g_ws.aux);
-    g_ws.cap_paths = 0;
-    bool ok = hipMalloc(&g_ws.rays[0], 32 * paths) == hipSuccess &&
-              hipMalloc(&g_ws.rays[1], 32 * paths) == hipSuccess &&
-              hipMalloc(&g_ws.hits, 16 * paths) == hipSuccess &&
-              hipMalloc(&g_ws.shadow, 48 * paths) == hipSuccess &&
-              hipMalloc(&g_ws.beta, 16 * paths) == hipSuccess &&
-              hipMalloc(&g_ws.L, 16 * paths) == hipSuccess &&
-              hipMalloc(&g_ws.aux, 32 * paths) == hipSuccess;
+  if (paths > w.cap_paths) {
+    for (auto*& p : w.rays) hfree(p);
+    hfree(w.hits);
+    hfree(w.shadow);
+    hfree(w.beta);
+    hfree(w.L);
+    hfree(w.aux);
+    w.cap_paths = 0;
+    bool ok = hipMalloc(&w.rays[0], 32 * paths) == hipSuccess &&
+              hipMalloc(&w.rays[1], 32 * paths) == hipSuccess &&
+              hipMalloc(&w.hits, 16 * paths) == hipSuccess &&
+              hipMalloc(&w.shadow, 48 * paths) == hipSuccess &&
+              hipMalloc(&w.beta, 16 * paths) == hipSuccess &&
+              hipMalloc(&w.L, 16 * paths) == hipSuccess &&
+              hipMalloc(&w.aux, 32 * paths) == hipSuccess;
     if (!ok) {
       (void)hipGetLastError();
       return fail(MRS_ERR_OUT_OF_MEMORY, "render: path-state allocation failed");
     }
-    g_ws.cap_paths = paths;
+    w.cap_paths = paths;
   }
-  if (threads > g_ws.spill_threads) {
-    hfree(g_ws.spill);
-    if (hipMalloc(&g_ws.spill, sizeof(uint32_t) * (MAX_STACK - LDS_STACK) * (size_t)threads) !=
+  if (threads > w.spill_threads) {
+    hfree(w.spill);
+    if (hipMalloc(&w.spill, sizeof(uint32_t) * (MAX_STACK - LDS_STACK) * (size_t)threads) !=
         hipSuccess) {
       (void)hipGetLastError();
-      g_ws.spill_threads = 0;
+      w.spill_threads = 0;
       return fail(MRS_ERR_OUT_OF_MEMORY, "render: stack spill allocation failed");
     }
-    g_ws.spill_threads = threads;
+    w.spill_threads = threads;
   }
   return MRS_OK;
 }
 
-mrs_status ensure_acc(size_t bytes) {
-  if (bytes > g_ws.acc_bytes) {
-    hfree(g_ws.acc);
-    if (hipMalloc(&g_ws.acc, bytes) != hipSuccess) {
+mrs_status ws_ensure_acc(Workspace& w, size_t bytes) {
+  if (bytes > w.acc_bytes) {
+    hfree(w.acc);
+    if (hipMalloc(&w.acc, bytes) != hipSuccess) {
       (void)hipGetLastError();
-      g_ws.acc_bytes = 0;
+      w.acc_bytes = 0;
       return fail(MRS_ERR_OUT_OF_MEMORY, "render: accumulator allocation failed");
     }
-    g_ws.acc_bytes = bytes;
+    w.acc_bytes = bytes;
   }
   return MRS_OK;
+}
+
+Workspace* stream_workspace(hipStream_t st) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  Workspace*& w = g_stream_ws[st];
+  if (!w) w = new Workspace();
+  return w;
+}
+
+mrs_tuning tuning_snapshot() {
+  std::lock_guard<std::mutex> lk(g_mu);
+  return g_tune;
 }
 
 inline unsigned cdiv(size_t a, size_t b) { return (unsigned)((a + b - 1) / b); }
@@ -850,8 +909,9 @@ size_t acc_bytes_of(int64_t npix, bool fp64) {
 // The launch sequence of a batch whose job table is on the device: chunks of at
 // most chunk_paths paths over the concatenated path space; per chunk, generate,
 // then extend / shade / shadow per bounce, then accumulate; finally resolve.
-mrs_status launch_batch(const DevJob* d_jobs, const std::vector<DevJob>& jobs, char* acc,
-                        size_t acc_bytes, hipStream_t st) {
+mrs_status launch_batch(Workspace& ws, const mrs_tuning& tu, const DevJob* d_jobs,
+                        const std::vector<DevJob>& jobs, char* acc, size_t acc_bytes,
+                        hipStream_t st) {
   const int nj = (int)jobs.size();
   int64_t total = 0, total_pix = 0;
   int max_depth = 0;
@@ -860,40 +920,42 @@ mrs_status launch_batch(const DevJob* d_jobs, const std::vector<DevJob>& jobs, c
     total_pix += (int64_t)J.ww * J.wh;
     max_depth = std::max(max_depth, (int)J.max_depth);
   }
-  const int64_t C = g_tune.chunk_paths;
-  const int blocks = g_tune.trace_blocks;
-  const int dyn = g_tune.schedule;
+  const int64_t C = tu.chunk_paths;
+  const int blocks = tu.trace_blocks;
+  const int dyn = tu.schedule;
+  const bool count = g_count_work.load();
+  unsigned long long* stats = g_stats;
   k_zero_words<<<std::min(4096u, cdiv(acc_bytes / 4, 256)), 256, 0, st>>>((uint32_t*)acc,
                                                                           acc_bytes / 4);
   for (int64_t g0 = 0; g0 < total; g0 += C) {
     const uint32_t n = (uint32_t)std::min<int64_t>(C, total - g0);
     const unsigned gb = std::min<unsigned>(blocks, cdiv(n, TB));
-    k_reset<<<1, 256, 0, st>>>(g_ws.q, n);
+    k_reset<<<1, 256, 0, st>>>(ws.q, n);
     prof_begin(KID_GENERATE, st);
-    k_generate<<<cdiv(n, 256), 256, 0, st>>>(d_jobs, nj, g0, n, g_ws.rays[0], g_ws.beta, g_ws.L,
-                                             g_ws.aux);
+    k_generate<<<cdiv(n, 256), 256, 0, st>>>(d_jobs, nj, g0, n, ws.rays[0], ws.beta, ws.L,
+                                             ws.aux);
     prof_end(KID_GENERATE, st);
     for (int b = 0; b <= max_depth; ++b) {
-      float4* rin = g_ws.rays[b & 1];
-      float4* rout = g_ws.rays[(b + 1) & 1];
+      float4* rin = ws.rays[b & 1];
+      float4* rout = ws.rays[(b + 1) & 1];
       prof_begin(KID_EXTEND, st);
-      if (g_count_work)
-        k_extend<true><<<gb, TB, 0, st>>>(d_jobs, b, dyn, rin, g_ws.q, g_ws.hits, g_ws.spill, g_ws.stats);
+      if (count)
+        k_extend<true><<<gb, TB, 0, st>>>(d_jobs, b, dyn, rin, ws.q, ws.hits, ws.spill, stats);
       else
-        k_extend<false><<<gb, TB, 0, st>>>(d_jobs, b, dyn, rin, g_ws.q, g_ws.hits, g_ws.spill, g_ws.stats);
+        k_extend<false><<<gb, TB, 0, st>>>(d_jobs, b, dyn, rin, ws.q, ws.hits, ws.spill, stats);
       prof_end(KID_EXTEND, st);
       prof_begin(KID_SHADE, st);
-      k_shade<<<gb, 256, 0, st>>>(d_jobs, g0, b, rin, g_ws.hits, g_ws.q, rout, g_ws.shadow,
-                                  g_ws.beta, g_ws.L, g_ws.aux);
+      k_shade<<<gb, 256, 0, st>>>(d_jobs, g0, b, rin, ws.hits, ws.q, rout, ws.shadow,
+                                  ws.beta, ws.L, ws.aux);
       prof_end(KID_SHADE, st);
       if (b < max_depth) {
         prof_begin(KID_SHADOW, st);
-        if (g_count_work)
-          k_shadow<true><<<gb, TB, 0, st>>>(d_jobs, b, dyn, g_ws.shadow, g_ws.q, g_ws.L, g_ws.spill,
-                                            g_ws.stats);
+        if (count)
+          k_shadow<true><<<gb, TB, 0, st>>>(d_jobs, b, dyn, ws.shadow, ws.q, ws.L, ws.spill,
+                                            stats);
         else
-          k_shadow<false><<<gb, TB, 0, st>>>(d_jobs, b, dyn, g_ws.shadow, g_ws.q, g_ws.L, g_ws.spill,
-                                             g_ws.stats);
+          k_shadow<false><<<gb, TB, 0, st>>>(d_jobs, b, dyn, ws.shadow, ws.q, ws.L, ws.spill,
+                                             stats);
         prof_end(KID_SHADOW, st);
       }
     }
@@ -905,9 +967,9 @@ mrs_status launch_batch(const DevJob* d_jobs, const std::vector<DevJob>& jobs, c
     const int64_t pix_hi = jobs[jhi].pix_first + (int64_t)jobs[jhi].ww * jobs[jhi].wh;
     prof_begin(KID_ACCUMULATE, st);
     k_accumulate<<<cdiv((size_t)(pix_hi - pix_lo), 256), 256, 0, st>>>(
-        d_jobs, nj, g0, n, pix_lo, pix_hi, g_ws.L, g_ws.aux, acc, g_ws.stats);
+        d_jobs, nj, g0, n, pix_lo, pix_hi, ws.L, ws.aux, acc, stats);
     prof_end(KID_ACCUMULATE, st);
-    k_tally<<<1, 64, 0, st>>>(g_ws.q, max_depth + 1, g_ws.stats, n);
+    k_tally<<<1, 64, 0, st>>>(ws.q, max_depth + 1, stats, n);
   }
   prof_begin(KID_RESOLVE, st);
   k_resolve<<<cdiv((size_t)total_pix, 256), 256, 0, st>>>(d_jobs, nj, total_pix, acc);
@@ -948,20 +1010,52 @@ mrs_status render(const mrs_scene* s, const RenderArgs& a, hipStream_t st) {
   J.pix_first = 0;
   J.acc_off = 0;
   const int64_t npix = (int64_t)a.ww * a.wh;
-  mrs_status rc = ensure_workspace(std::min<int64_t>(g_tune.chunk_paths, npix * a.spp),
-                                   g_tune.trace_blocks * TB);
+  const mrs_tuning tu = tuning_snapshot();
+  Workspace& ws = *stream_workspace(st);
+  mrs_status rc = ws_ensure(ws, std::min<int64_t>(tu.chunk_paths, npix * a.spp),
+                            tu.trace_blocks * TB);
   if (rc != MRS_OK) return rc;
   const size_t ab = acc_bytes_of(npix, a.fp64);
-  if ((rc = ensure_acc(ab)) != MRS_OK) return rc;
-  k_store_job<<<1, 64, 0, st>>>(J, g_ws.one);
+  if ((rc = ws_ensure_acc(ws, ab)) != MRS_OK) return rc;
+  k_store_job<<<1, 64, 0, st>>>(J, ws.one);
   std::vector<DevJob> jobs{J};
-  return launch_batch(g_ws.one, jobs, g_ws.acc, ab, st);
+  return launch_batch(ws, tu, ws.one, jobs, ws.acc, ab, st);
 }
 
-mrs_status batch_prepare(std::vector<DevJob>& jobs, size_t* acc_bytes) {
+}  // namespace mrs
+
+// A batch owns its job table, accumulators and path workspace, sized at
+// creation with the tuning current then, so rendering it allocates nothing.
+struct mrs_batch {
+  std::vector<mrs::DevJob> jobs;
+  mrs::DevJob* d_jobs = nullptr;
+  char* d_acc = nullptr;
+  size_t acc_bytes = 0;
+  mrs_tuning tune;
+  mrs::Workspace ws;
+};
+
+namespace mrs {
+
+void batch_destroy(mrs_batch* b) {
+  if (!b) return;
+  (void)hipDeviceSynchronize();
+  hfree(b->d_jobs);
+  hfree(b->d_acc);
+  ws_release(b->ws);
+  delete b;
+}
+
+mrs_status batch_create(const std::vector<DevJob>& jobs, mrs_batch** out) {
+  for (const DevJob& J : jobs)
+    if (J.max_depth + 2 > MAX_BOUNCE_SLOTS)
+      return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_batch_create: max_depth too large");
+  mrs_batch* b = new mrs_batch();
+  b->jobs = jobs;
+  b->tune = tuning_snapshot();
   int64_t first = 0, pix = 0;
-  size_t off = 0, paths_max = 0;
-  for (DevJob& J : jobs) {
+  size_t off = 0;
+  for (DevJob& J : b->jobs) {
     const int64_t npix = (int64_t)J.ww * J.wh;
     J.first = first;
     J.pix_first = pix;
@@ -970,14 +1064,54 @@ mrs_status batch_prepare(std::vector<DevJob>& jobs, size_t* acc_bytes) {
     pix += npix;
     off += acc_bytes_of(npix, J.fp64 != 0);
   }
-  paths_max = (size_t)std::min<int64_t>(g_tune.chunk_paths, first);
-  *acc_bytes = off;
-  return ensure_workspace(paths_max, g_tune.trace_blocks * TB);
+  b->acc_bytes = off;
+  mrs_status rc = ws_ensure(b->ws, (size_t)std::min<int64_t>(b->tune.chunk_paths, first),
+                            b->tune.trace_blocks * TB);
+  if (rc == MRS_OK && (hipMalloc(&b->d_jobs, sizeof(DevJob) * b->jobs.size()) != hipSuccess ||
+                       hipMalloc(&b->d_acc, b->acc_bytes) != hipSuccess)) {
+    (void)hipGetLastError();
+    rc = fail(MRS_ERR_OUT_OF_MEMORY, "mrs_batch_create: device allocation failed");
+  }
+  if (rc == MRS_OK) {
+    hipError_t e = hipMemcpy(b->d_jobs, b->jobs.data(), sizeof(DevJob) * b->jobs.size(),
+                             hipMemcpyHostToDevice);
+    if (e != hipSuccess) rc = check_hip(e, "mrs_batch_create: job table upload");
+  }
+  if (rc != MRS_OK) {
+    batch_destroy(b);
+    return rc;
+  }
+  *out = b;
+  return MRS_OK;
 }
 
-mrs_status batch_launch(const DevJob* d_jobs, const std::vector<DevJob>& jobs, char* acc,
-                        size_t acc_bytes, hipStream_t st) {
-  return launch_batch(d_jobs, jobs, acc, acc_bytes, st);
+mrs_status batch_render(mrs_batch* b, hipStream_t st) {
+  return launch_batch(b->ws, b->tune, b->d_jobs, b->jobs, b->d_acc, b->acc_bytes, st);
+}
+
+mrs_status batch_set_seeds(mrs_batch* b, const uint64_t* seeds, hipStream_t st) {
+  SeedTable t;
+  std::memset(&t, 0, sizeof t);
+  t.n = (uint32_t)b->jobs.size();
+  for (uint32_t j = 0; j < t.n; ++j) {
+    t.lo[j] = (uint32_t)(seeds[j] & 0xffffffffu);
+    t.hi[j] = (uint32_t)(seeds[j] >> 32);
+    b->jobs[j].seed_lo = t.lo[j];
+    b->jobs[j].seed_hi = t.hi[j];
+  }
+  k_set_seeds<<<1, 256, 0, st>>>(b->d_jobs, t);
+  MRS_TRY_HIP(hipGetLastError());
+  return MRS_OK;
+}
+
+void release_workspaces() {
+  (void)hipDeviceSynchronize();
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (auto& kv : g_stream_ws) {
+    ws_release(*kv.second);
+    delete kv.second;
+  }
+  g_stream_ws.clear();
 }
 
 mrs_status debug_closest_hit(const mrs_scene* s, int32_t n, const float* o, const float* d,
@@ -985,9 +1119,10 @@ mrs_status debug_closest_hit(const mrs_scene* s, int32_t n, const float* o, cons
                              hipStream_t st) {
   if (n <= 0) return MRS_OK;
   const unsigned blocks = cdiv((size_t)n, 256);
-  mrs_status rc = ensure_workspace(1, (int)(blocks * 256));
+  Workspace& ws = *stream_workspace(st);
+  mrs_status rc = ws_ensure(ws, 1, (int)(blocks * 256));
   if (rc != MRS_OK) return rc;
-  k_debug_hit<<<blocks, 256, 0, st>>>(s->view, n, o, d, skip, t, prim, b, g_ws.spill);
+  k_debug_hit<<<blocks, 256, 0, st>>>(s->view, n, o, d, skip, t, prim, b, ws.spill);
   MRS_TRY_HIP(hipGetLastError());
   return MRS_OK;
 }
@@ -1002,29 +1137,30 @@ mrs_status debug_philox(int32_t n, const uint32_t* ctr, const uint32_t* key, uin
 
 mrs_status get_counters(int64_t* out, bool reset, hipStream_t st) {
   for (int i = 0; i < MRS_NUM_COUNTERS; ++i) out[i] = 0;
-  if (!g_ws.stats) return MRS_OK;
+  if (!g_stats) return MRS_OK;
   unsigned long long h[MRS_NUM_COUNTERS];
-  MRS_TRY_HIP(hipMemcpyAsync(h, g_ws.stats, sizeof(h), hipMemcpyDeviceToHost, st));
+  MRS_TRY_HIP(hipMemcpyAsync(h, g_stats, sizeof(h), hipMemcpyDeviceToHost, st));
   MRS_TRY_HIP(hipStreamSynchronize(st));
   for (int i = 0; i < MRS_NUM_COUNTERS; ++i) out[i] = (int64_t)h[i];
   if (reset) {
-    k_zero_words<<<1, 256, 0, st>>>((uint32_t*)g_ws.stats, 2 * MRS_NUM_COUNTERS);
+    k_zero_words<<<1, 256, 0, st>>>((uint32_t*)g_stats, 2 * MRS_NUM_COUNTERS);
     MRS_TRY_HIP(hipGetLastError());
   }
   return MRS_OK;
 }
 
-void get_tuning(mrs_tuning* t) { *t = g_tune; }
+void get_tuning(mrs_tuning* t) { *t = tuning_snapshot(); }
 
 void set_count_work(bool on) { g_count_work = on; }
 
 mrs_status set_tuning(const mrs_tuning* t) {
-  if (t->chunk_paths < 256 || t->chunk_paths > (1 << 24))
-    return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_set_tuning: chunk_paths must be in [256, 2^24]");
+  if (t->chunk_paths < 256 || t->chunk_paths > (1 << 26))
+    return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_set_tuning: chunk_paths must be in [256, 2^26]");
   if (t->trace_blocks < 1 || t->trace_blocks > 65536)
     return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_set_tuning: trace_blocks must be in [1, 65536]");
   if (t->schedule != 0 && t->schedule != 1)
     return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_set_tuning: schedule must be 0 or 1");
+  std::lock_guard<std::mutex> lk(g_mu);
   g_tune = *t;
   return MRS_OK;
 }

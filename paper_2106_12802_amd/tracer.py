@@ -169,6 +169,7 @@ class Batch:
     def __init__(self, jobs):
         import torch
         n = len(jobs)
+        self.njobs = n
         arr = (L.Job * n)()
         self.outputs = []
         self._keep = []
@@ -210,6 +211,14 @@ class Batch:
     def render(self):
         L.use_current_stream()
         L.check(L.lib().mrs_batch_render(self.handle))
+
+    def set_seeds(self, seeds):
+        """New seed per job (stream-ordered device update; no allocation)."""
+        arr = np.asarray([int(x) for x in seeds], dtype=np.uint64)
+        if arr.size != self.njobs:
+            raise ValueError(f"set_seeds: need {self.njobs} seeds, got {arr.size}")
+        L.use_current_stream()
+        L.check(L.lib().mrs_batch_set_seeds(self.handle, arr.ctypes.data_as(C.c_void_p)))
 
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:

@@ -64,6 +64,23 @@ def test_batch_matches_single_renders_bitwise(torch_cuda, chunk, schedule):
         mrs.set_tuning(**old)
 
 
+def test_batch_set_seeds_matches_single_renders(torch_cuda):
+    import paper_2106_12802_amd as mrs
+    jobs = _jobs(mrs)[:3]
+    b = mrs.Batch(jobs)
+    with pytest.raises(ValueError):
+        b.set_seeds([1, 2])
+    for seeds in ([101, 102, 103], [7, (1 << 40) + 5, 9]):
+        b.set_seeds(seeds)
+        b.render()
+        torch_cuda.cuda.synchronize()
+        for j, seed, (rgb, aux) in zip(jobs, seeds, b.outputs):
+            r1, a1 = _single(mrs, dict(j, seed=seed))
+            torch_cuda.cuda.synchronize()
+            assert torch_cuda.equal(rgb, r1) and torch_cuda.equal(aux, a1), seed
+    b.close()
+
+
 def test_graph_replay_of_hybrid_frame(torch_cuda):
     """Capture HRLS + LRHS + fusion in a HIP graph; every replay equals the eager frame."""
     import paper_2106_12802_amd as mrs
@@ -75,7 +92,7 @@ def test_graph_replay_of_hybrid_frame(torch_cuda):
     out = torch.empty(H, W, 3, device="cuda")
     eager, _ = HY.hybrid_frame(gs, net, W, H, 5, out=torch.empty(H, W, 3, device="cuda"))
     eager = eager.clone()
-    # warm up on a side stream (buffers grow outside the capture), then capture
+    # warm up on the capturing stream (its workspace grows outside the capture)
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(s):
@@ -83,7 +100,7 @@ def test_graph_replay_of_hybrid_frame(torch_cuda):
     torch.cuda.current_stream().wait_stream(s)
     torch.cuda.synchronize()
     g = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(g):
+    with torch.cuda.graph(g, stream=s):
         HY.hybrid_frame(gs, net, W, H, 5, out=out)
     for k in range(4):
         out.zero_()
@@ -115,5 +132,38 @@ def test_autotune_applies_choice_and_keeps_results(torch_cuda, tmp_path):
         mrs.set_tuning(**old)
         r2 = autotune.tune(wl, "cornell96", cache, candidates=cands)
         assert r2["cached"] and r2["chunk_paths"] == r["chunk_paths"]
+    finally:
+        mrs.set_tuning(**old)
+
+
+def test_concurrent_streams_and_batch_tuning_snapshot(torch_cuda):
+    """Renders on two streams at once equal sequential ones (one workspace per stream);
+    a batch keeps the tuning it was created with."""
+    import paper_2106_12802_amd as mrs
+    torch = torch_cuda
+    gs1 = mrs.GpuScene(S.procedural_sized(302, 30000))
+    gs2 = mrs.GpuScene(S.cornell(4))
+    r1, _ = mrs.render(gs1, 200, 120, 4, 6, 21)
+    r2, _ = mrs.render(gs2, 96, 96, 16, 5, 22)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Stream(), torch.cuda.Stream()
+    outs = []
+    for k in range(3):
+        with torch.cuda.stream(a):
+            x1, _ = mrs.render(gs1, 200, 120, 4, 6, 21)
+        with torch.cuda.stream(b):
+            x2, _ = mrs.render(gs2, 96, 96, 16, 5, 22)
+        outs.append((x1, x2))
+    torch.cuda.synchronize()
+    for x1, x2 in outs:
+        assert torch.equal(x1, r1) and torch.equal(x2, r2)
+    old = mrs.get_tuning()
+    try:
+        bt = mrs.Batch([dict(scene=gs2, W=96, H=96, spp=16, max_depth=5, seed=22)])
+        mrs.set_tuning(chunk_paths=256, trace_blocks=1, schedule=1)
+        bt.render()
+        torch.cuda.synchronize()
+        assert torch.equal(bt.outputs[0][0], r2)
+        bt.close()
     finally:
         mrs.set_tuning(**old)
