@@ -30,10 +30,11 @@ MAX_DEPTH = 8
 SCENE_SEED = 7
 PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32 (FMA = 2 FLOP, packed)
 # Algorithmic FP32 operations (FMA counted as 2) of the closest-hit traversal:
-#   per node visit: two slab tests (6 FMA, 10 min/max, 1 scale, 2 compares each) + order = 51
+#   per BVH4 node visit: four slab tests (6 FMA, 10 min/max, 1 scale, 2 compares each = 25)
+#     + a 5-comparator sorting network on the entry distances = 105
 #   per triangle test: Moller-Trumbore (2 cross, 4 dot, 3 sub, 1 rcp, 3 scale, 7 compares) = 52
 #   per ray: reciprocal direction and scaled origin = 10
-FLOP_PER_VISIT = 51
+FLOP_PER_VISIT = 105
 FLOP_PER_TEST = 52
 FLOP_PER_RAY = 10
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "extend_procedural101k_720p_traffic.txt")
@@ -336,6 +337,8 @@ def main():
     ap.add_argument("--trace-blocks", type=int, default=None, help="tuning: traversal grid size")
     ap.add_argument("--schedule", type=int, default=None, choices=(0, 1),
                     help="tuning: traversal queue schedule (0 grid-stride, 1 dynamic)")
+    ap.add_argument("--leaf-max", type=int, default=None,
+                    help="BVH build: triangles a BVH4 leaf may group (1..4)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="summarise two rocprofv3 --pmc runs into the profiles/ traffic file")
     args = ap.parse_args()
@@ -357,7 +360,7 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_calibration:
         copy_calibration()
-    R.set_tuning(args.chunk_paths, args.trace_blocks, args.schedule)
+    R.set_tuning(args.chunk_paths, args.trace_blocks, args.schedule, args.leaf_max)
     tuning = R.get_tuning()
     log(f"[bench] tuning {tuning}")
     scene = S.procedural(SCENE_SEED)

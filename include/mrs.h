@@ -231,9 +231,11 @@ mrs_status mrs_profile_read(double ms_out[MRS_NUM_KERNEL_IDS],
 /* Tuning knobs (performance only; results do not depend on them). */
 typedef struct mrs_tuning {
   int32_t chunk_paths;  /* paths resident at once (default 1<<23, at most 1<<26) */
-  int32_t trace_blocks; /* grid size of traversal kernels (default 4096) */
+  int32_t trace_blocks; /* grid size of traversal kernels (default 8192) */
   int32_t schedule;     /* traversal queue: 0 grid-stride (default), 1 per-wave
                            dynamic fetch from a device counter */
+  int32_t bvh_leaf_max; /* triangles a BVH4 leaf may group, 1..4 (default 4);
+                           applies to scenes built afterwards */
 } mrs_tuning;
 mrs_status mrs_get_tuning(mrs_tuning* out);
 mrs_status mrs_set_tuning(const mrs_tuning* t);
@@ -350,6 +352,17 @@ mrs_status mrs_debug_closest_hit(const mrs_scene* scene, int32_t n, const float*
  * Any pointer may be NULL.  Synchronises. */
 mrs_status mrs_debug_bvh(const mrs_scene* scene, float* nodes_host, int32_t* leaf_prim_host,
                          uint32_t* morton_host, int32_t* root_ref_host);
+
+/* Copies the four-wide BVH the renderer traverses (collapsed from the LBVH).
+ * nodes_host (NULL to query the count) receives count records of 32 floats:
+ * child boxes lo.x[4], lo.y[4], lo.z[4], hi.x[4], hi.y[4], hi.z[4], then 4
+ * child references as uint32 bit patterns (0xffffffff = no child; bit 31 set
+ * = leaf: bits 24..25 = count - 1, bits 0..23 = first leaf slot, covering
+ * leaf slots first .. first + count - 1; otherwise a node index), 4 pad words.
+ * root_ref is a reference in the same encoding; leaf_max is the grouping
+ * limit the build used.  Synchronises. */
+mrs_status mrs_debug_bvh4(const mrs_scene* scene, float* nodes_host, int32_t* count,
+                          uint32_t* root_ref, int32_t* leaf_max);
 
 #ifdef __cplusplus
 }

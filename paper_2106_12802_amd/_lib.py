@@ -66,7 +66,8 @@ class Job(C.Structure):
 
 
 class Tuning(C.Structure):
-    _fields_ = [("chunk_paths", C.c_int32), ("trace_blocks", C.c_int32), ("schedule", C.c_int32)]
+    _fields_ = [("chunk_paths", C.c_int32), ("trace_blocks", C.c_int32), ("schedule", C.c_int32),
+                ("bvh_leaf_max", C.c_int32)]
 
 
 assert C.sizeof(Material) == 32 and C.sizeof(QuadLight) == 56
@@ -122,6 +123,7 @@ def lib():
         "mrs_batch_destroy": ([P], I32),
         "mrs_release_workspaces": ([], I32),
         "mrs_batch_set_seeds": ([P, P], I32),
+        "mrs_debug_bvh4": ([P, P, P, P, P], I32),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(L, name)
@@ -148,6 +150,7 @@ def exported_symbols():
         "mrs_debug_net_activation", "mrs_image_metrics", "mrs_net_loss_grad", "mrs_train_step",
         "mrs_net_get_state", "mrs_net_set_state", "mrs_batch_create", "mrs_batch_render",
         "mrs_batch_destroy", "mrs_release_workspaces", "mrs_batch_set_seeds",
+        "mrs_debug_bvh4",
     ]
 
 

@@ -81,6 +81,7 @@ void free_scene(mrs_scene* s) {
   dfree(s->d_prim_n);
   dfree(s->d_leaf_tri);
   dfree(s->d_nodes);
+  dfree(s->d_nodes4);
   dfree(s->d_morton);
   dfree(s->d_leaf_prim);
   dfree(s->d_mats);
@@ -162,7 +163,8 @@ mrs_status scene_create_impl(const mrs_scene_desc* d, mrs_scene* s) {
   SceneView& sv = s->view;
   sv.ntris = n;
   sv.nlights = d->num_lights;
-  sv.nodes = s->d_nodes;
+  sv.nodes = nullptr;  // BVH4, set by mrs_build_bvh
+  sv.nnodes = 0;
   sv.leaf_tri = s->d_leaf_tri;
   sv.prim_ng = s->d_prim_ng;
   sv.prim_n = s->d_prim_n;
@@ -261,9 +263,13 @@ mrs_status mrs_scene_destroy(mrs_scene* s) {
 mrs_status mrs_build_bvh(mrs_scene* s) {
   if (!s) return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_build_bvh: scene is NULL");
   if (s->bvh_built) return MRS_OK;
-  mrs_status rc = lbvh_build(s, current_stream());
+  mrs_tuning t;
+  get_tuning(&t);
+  mrs_status rc = lbvh_build(s, current_stream(), t.bvh_leaf_max);
   if (rc != MRS_OK) return rc;
-  s->view.root = s->root;
+  s->view.root = s->root4;
+  s->view.nodes = s->d_nodes4;
+  s->view.nnodes = s->count4;
   return MRS_OK;
 }
 
@@ -441,6 +447,20 @@ mrs_status mrs_debug_bvh(const mrs_scene* s, float* nodes, int32_t* leaf_prim, u
   if (leaf_prim && n > 0) MRS_TRY_HIP(hipMemcpy(leaf_prim, s->d_leaf_prim, sizeof(uint32_t) * n, hipMemcpyDeviceToHost));
   if (morton && n > 0) MRS_TRY_HIP(hipMemcpy(morton, s->d_morton, sizeof(uint32_t) * n, hipMemcpyDeviceToHost));
   if (root_ref) *root_ref = (int32_t)s->root;
+  return MRS_OK;
+}
+
+mrs_status mrs_debug_bvh4(const mrs_scene* s, float* nodes, int32_t* count, uint32_t* root_ref,
+                          int32_t* leaf_max) {
+  if (!s) return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_debug_bvh4: scene is NULL");
+  if (!s->bvh_built) return fail(MRS_ERR_NOT_READY, "mrs_debug_bvh4: BVH not built");
+  MRS_TRY_HIP(hipStreamSynchronize(current_stream()));
+  if (nodes && s->count4 > 0)
+    MRS_TRY_HIP(hipMemcpy(nodes, s->d_nodes4, sizeof(float4) * 8 * (size_t)s->count4,
+                          hipMemcpyDeviceToHost));
+  if (count) *count = (int32_t)s->count4;
+  if (root_ref) *root_ref = s->root4;
+  if (leaf_max) *leaf_max = s->leaf_max;
   return MRS_OK;
 }
 

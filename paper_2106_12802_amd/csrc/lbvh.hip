@@ -11,8 +11,15 @@
 //  5. leaf-to-root refit: each leaf walks up; the second thread to reach a
 //     node (atomic visit counter) unions its children's boxes and continues.
 //
-// Node record (64 B): child boxes as 12 floats (left lo, left hi, right lo,
-// right hi), then two child references (bit 31 = leaf) and 2 pad words.
+//  6. collapse to a four-wide BVH, top down one level per launch: a node
+//     starts from its two binary children and twice opens the child of
+//     largest surface area; binary subtrees of at most leaf_max triangles
+//     become leaves (their leaf records are contiguous); nodes are then
+//     renumbered densely in binary-node order.
+//
+// Binary node record (64 B): child boxes as 12 floats (left lo, left hi, right
+// lo, right hi), two child references (bit 31 = leaf) and the node's range of
+// leaf records (first, last).
 #include "mrs_internal.hpp"
 #include "devmath.hpp"
 
@@ -236,7 +243,8 @@ __global__ __launch_bounds__(256) void k_hierarchy(const uint32_t* __restrict__ 
     right = (uint32_t)(g + 1);
     parent_int[g + 1] = (uint32_t)i;
   }
-  nodes[4 * i + 3] = make_float4(__uint_as_float(left), __uint_as_float(right), 0.0f, 0.0f);
+  nodes[4 * i + 3] = make_float4(__uint_as_float(left), __uint_as_float(right),
+                                 __uint_as_float((uint32_t)lo), __uint_as_float((uint32_t)hi));
 }
 
 __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* p, int n, uint32_t v) {
@@ -292,15 +300,200 @@ __global__ __launch_bounds__(256) void k_leaves_refit(const float4* __restrict__
   }
 }
 
+// ---------------------------------------------------------------- BVH4 collapse
+struct Cand {
+  uint32_t ref;
+  float lo[3], hi[3];
+};
+
+__device__ __forceinline__ void binary_children(const float* __restrict__ nf, Cand& l, Cand& r) {
+  for (int a = 0; a < 3; ++a) {
+    l.lo[a] = nf[a];
+    l.hi[a] = nf[3 + a];
+    r.lo[a] = nf[6 + a];
+    r.hi[a] = nf[9 + a];
+  }
+  l.ref = __float_as_uint(nf[12]);
+  r.ref = __float_as_uint(nf[13]);
+}
+
+__device__ __forceinline__ float half_area(const Cand& c) {
+  const float dx = c.hi[0] - c.lo[0], dy = c.hi[1] - c.lo[1], dz = c.hi[2] - c.lo[2];
+  return dx * dy + dy * dz + dz * dx;
+}
+
+// leaf-record range of a binary reference
+__device__ __forceinline__ void ref_range(const float* __restrict__ nodes_f, uint32_t ref,
+                                          uint32_t& first, uint32_t& last) {
+  if (ref & LEAF_BIT) {
+    first = last = ref & ~LEAF_BIT;
+  } else {
+    first = __float_as_uint(nodes_f[16 * (size_t)ref + 14]);
+    last = __float_as_uint(nodes_f[16 * (size_t)ref + 15]);
+  }
+}
+
+// One level: each queued binary node b becomes BVH4 node b (sparse numbering).
+__global__ __launch_bounds__(256) void k_collapse(const float* __restrict__ nodes_f,
+                                                  const uint32_t* __restrict__ q_in,
+                                                  const uint32_t* __restrict__ cnt_in,
+                                                  uint32_t* __restrict__ q_out,
+                                                  uint32_t* __restrict__ cnt_out,
+                                                  float4* __restrict__ sparse4,
+                                                  uint32_t* __restrict__ is4, int leaf_max) {
+  const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= *cnt_in) return;
+  const uint32_t b = q_in[i];
+  Cand c[4];
+  binary_children(nodes_f + 16 * (size_t)b, c[0], c[1]);
+  int nc = 2;
+  for (int open = 0; open < 2; ++open) {
+    int best = -1;
+    float best_area = -1.0f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (k >= nc || (c[k].ref & LEAF_BIT)) continue;
+      uint32_t f, l;
+      ref_range(nodes_f, c[k].ref, f, l);
+      if (l - f + 1 <= (uint32_t)leaf_max) continue;
+      const float a = half_area(c[k]);
+      if (a > best_area) {
+        best_area = a;
+        best = k;
+      }
+    }
+    if (best < 0) break;
+    Cand l, r;
+    uint32_t opened = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (k == best) opened = c[k].ref;
+    binary_children(nodes_f + 16 * (size_t)opened, l, r);
+    // c[best] <- l, c[best + 1] <- r, later children shift right by one
+#pragma unroll
+    for (int k = 3; k >= 1; --k)
+      if (k > best + 1 && k <= nc) c[k] = c[k - 1];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (k == best) c[k] = l;
+      if (k == best + 1) c[k] = r;
+    }
+    ++nc;
+  }
+  float box[6][4];
+  uint32_t refs[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (k < nc) {
+      uint32_t f, l;
+      ref_range(nodes_f, c[k].ref, f, l);
+      if ((c[k].ref & LEAF_BIT) || l - f + 1 <= (uint32_t)leaf_max) {
+        refs[k] = leaf4_ref(f, l - f + 1);
+      } else {
+        refs[k] = c[k].ref;
+        q_out[atomicAdd(cnt_out, 1u)] = c[k].ref;
+      }
+      for (int a = 0; a < 3; ++a) {
+        box[a][k] = c[k].lo[a];
+        box[3 + a][k] = c[k].hi[a];
+      }
+    } else {
+      refs[k] = EMPTY4;
+      for (int a = 0; a < 3; ++a) {
+        box[a][k] = INFINITY;
+        box[3 + a][k] = -INFINITY;
+      }
+    }
+  }
+  float4* o = sparse4 + 8 * (size_t)b;
+  for (int a = 0; a < 6; ++a) o[a] = make_float4(box[a][0], box[a][1], box[a][2], box[a][3]);
+  o[6] = make_float4(__uint_as_float(refs[0]), __uint_as_float(refs[1]),
+                     __uint_as_float(refs[2]), __uint_as_float(refs[3]));
+  o[7] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  is4[b] = 1u;
+}
+
+// Dense renumbering (binary-node order): node b moves to idx[b]; internal
+// references are renumbered the same way.
+__global__ __launch_bounds__(256) void k_compact4(const float4* __restrict__ sparse4,
+                                                  const uint32_t* __restrict__ is4,
+                                                  const uint32_t* __restrict__ idx, int nint,
+                                                  float4* __restrict__ dense4) {
+  const int b = blockIdx.x * 256 + threadIdx.x;
+  if (b >= nint || !is4[b]) return;
+  const float4* src = sparse4 + 8 * (size_t)b;
+  float4* dst = dense4 + 8 * (size_t)idx[b];
+  for (int a = 0; a < 6; ++a) dst[a] = src[a];
+  const float4 r = src[6];
+  uint32_t refs[4] = {__float_as_uint(r.x), __float_as_uint(r.y), __float_as_uint(r.z),
+                      __float_as_uint(r.w)};
+  for (int k = 0; k < 4; ++k)
+    if (refs[k] != EMPTY4 && !(refs[k] & LEAF_BIT)) refs[k] = idx[refs[k]];
+  dst[6] = make_float4(__uint_as_float(refs[0]), __uint_as_float(refs[1]),
+                       __uint_as_float(refs[2]), __uint_as_float(refs[3]));
+  dst[7] = src[7];
+}
+
 inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
+
+// Top-down collapse of the binary tree (one launch per BVH4 level; the level
+// size is read back to size the next launch), then dense renumbering.
+mrs_status collapse4(mrs_scene* s, hipStream_t st, int leaf_max, char* scratch, size_t o_q0,
+                     size_t o_q1, size_t o_qc, size_t o_is4, size_t o_idx, size_t o_sp4) {
+  const int n = s->ntris;
+  uint32_t* q[2] = {(uint32_t*)(scratch + o_q0), (uint32_t*)(scratch + o_q1)};
+  uint32_t* qc = (uint32_t*)(scratch + o_qc);
+  uint32_t* is4 = (uint32_t*)(scratch + o_is4);
+  uint32_t* idx = (uint32_t*)(scratch + o_idx);
+  float4* sparse4 = (float4*)(scratch + o_sp4);
+  k_fill_u32<<<cdiv(n - 1, 256), 256, 0, st>>>(is4, n - 1, 0u);
+  k_fill_u32<<<1, 256, 0, st>>>(q[0], 1, 0u);  // the root is the one item of level 0
+  k_fill_u32<<<1, 256, 0, st>>>(qc, 1, 1u);
+  uint32_t items = 1;
+  int cur = 0;
+  for (int level = 0; items > 0; ++level) {
+    if (level > 4 * MAX_STACK) return fail(MRS_ERR_DEVICE, "mrs_build_bvh: BVH4 collapse does not end");
+    k_fill_u32<<<1, 256, 0, st>>>(qc + (1 - cur), 1, 0u);
+    k_collapse<<<cdiv(items, 256), 256, 0, st>>>((const float*)s->d_nodes, q[cur], qc + cur,
+                                                  q[1 - cur], qc + (1 - cur), sparse4, is4,
+                                                  leaf_max);
+    MRS_TRY_HIP(hipGetLastError());
+    MRS_TRY_HIP(hipMemcpyAsync(&items, qc + (1 - cur), sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    MRS_TRY_HIP(hipStreamSynchronize(st));
+    cur = 1 - cur;
+  }
+  MRS_TRY_HIP(hipMemcpyAsync(idx, is4, sizeof(uint32_t) * (n - 1), hipMemcpyDeviceToDevice, st));
+  k_rs_scan<<<1, 1024, 0, st>>>(idx, n - 1);
+  uint32_t last_idx = 0, last_is = 0;
+  MRS_TRY_HIP(hipMemcpyAsync(&last_idx, idx + (n - 2), sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  MRS_TRY_HIP(hipMemcpyAsync(&last_is, is4 + (n - 2), sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  MRS_TRY_HIP(hipStreamSynchronize(st));
+  const uint32_t count4 = last_idx + last_is;
+  if (s->d_nodes4) {
+    (void)hipFree(s->d_nodes4);
+    s->d_nodes4 = nullptr;
+  }
+  if (hipMalloc(&s->d_nodes4, sizeof(float4) * 8 * (size_t)count4) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(MRS_ERR_OUT_OF_MEMORY, "mrs_build_bvh: BVH4 allocation failed");
+  }
+  k_compact4<<<cdiv(n - 1, 256), 256, 0, st>>>(sparse4, is4, idx, n - 1, s->d_nodes4);
+  MRS_TRY_HIP(hipGetLastError());
+  s->count4 = count4;
+  s->root4 = 0u;  // binary root 0 is the first BVH4 node
+  return MRS_OK;
+}
 
 }  // namespace
 
-mrs_status lbvh_build(mrs_scene* s, hipStream_t st) {
+mrs_status lbvh_build(mrs_scene* s, hipStream_t st, int leaf_max) {
   const int n = s->ntris;
   s->bvh_built = false;
+  s->leaf_max = leaf_max;
   if (n == 0) {
     s->root = 0;
+    s->root4 = EMPTY4;
+    s->count4 = 0;
     s->bvh_built = true;
     return MRS_OK;
   }
@@ -324,6 +517,12 @@ mrs_status lbvh_build(mrs_scene* s, hipStream_t st) {
   const size_t o_pi = carve(sizeof(uint32_t) * n);
   const size_t o_pl = carve(sizeof(uint32_t) * n);
   const size_t o_vis = carve(sizeof(uint32_t) * n);
+  const size_t o_q0 = carve(sizeof(uint32_t) * n);
+  const size_t o_q1 = carve(sizeof(uint32_t) * n);
+  const size_t o_qc = carve(sizeof(uint32_t) * 2);
+  const size_t o_is4 = carve(sizeof(uint32_t) * n);
+  const size_t o_idx = carve(sizeof(uint32_t) * n);
+  const size_t o_sp4 = carve(sizeof(float4) * 8 * (size_t)std::max(n - 1, 1));
   char* scratch = nullptr;
   if (hipMalloc(&scratch, bytes) != hipSuccess) {
     (void)hipGetLastError();
@@ -362,10 +561,17 @@ mrs_status lbvh_build(mrs_scene* s, hipStream_t st) {
   k_leaves_refit<<<cdiv(n, 256), 256, 0, st>>>(s->d_tri_src, s->d_leaf_prim, n, s->d_leaf_tri,
                                                (float*)s->d_nodes, pint, pleaf, visits);
   MRS_TRY_HIP(hipGetLastError());
+  mrs_status rc = MRS_OK;
+  if (n >= 2) rc = collapse4(s, st, leaf_max, scratch, o_q0, o_q1, o_qc, o_is4, o_idx, o_sp4);
   // The scratch must outlive the kernels: wait, then free.
   MRS_TRY_HIP(hipStreamSynchronize(st));
   MRS_TRY_HIP(hipFree(scratch));
+  if (rc != MRS_OK) return rc;
   s->root = n >= 2 ? 0u : LEAF_BIT;
+  if (n < 2) {
+    s->root4 = leaf4_ref(0, 1);
+    s->count4 = 0;
+  }
   s->bvh_built = true;
   return MRS_OK;
 }

@@ -31,6 +31,17 @@ constexpr uint32_t NO_PRIM = 0xffffffffu;
 constexpr int MAX_LIGHTS = 255;
 constexpr int MAX_STACK = 64;  // Karras trees over unique 64-bit keys are <= 64 deep
 
+// Four-wide BVH collapsed from the binary LBVH (128 B per node, one cache
+// line): child boxes as structure-of-arrays float4s (lo.x, lo.y, lo.z, hi.x,
+// hi.y, hi.z of children 0..3), then the 4 child references and 4 pad words.
+// Reference: EMPTY4 (no child), LEAF_BIT | (count - 1) << 24 | first (leaf
+// records first .. first + count - 1, count <= 4), or a node index.
+constexpr uint32_t EMPTY4 = 0xffffffffu;
+constexpr int LEAF4_MAX = 4;
+__host__ __device__ constexpr uint32_t leaf4_ref(uint32_t first, uint32_t count) {
+  return LEAF_BIT | ((count - 1u) << 24) | first;
+}
+
 struct DevMaterial {  // 32 B, read through the scalar/vector caches
   float4 color_alpha; // rgb = albedo or F0, w = GGX roughness
   float4 emis_kind;   // rgb = emission, w = kind (as float: 0, 1, 2)
@@ -48,8 +59,9 @@ struct DevLight {  // 80 B
 struct SceneView {  // passed by value to kernels
   int32_t ntris;
   int32_t nlights;
-  uint32_t root;           // node index, or LEAF_BIT|0 when ntris == 1
-  const float4* nodes;     // (ntris-1)*4 float4
+  uint32_t root;           // BVH4 reference of the root
+  uint32_t nnodes;         // BVH4 nodes
+  const float4* nodes;     // nnodes * 8 float4 (BVH4)
   const float4* leaf_tri;  // ntris*3 float4: (v0, prim bits) (e1, -) (e2, -) in leaf order
   const float4* prim_ng;   // ntris: unit geometric normal, w = bits(material | flags)
   const float4* prim_n;    // ntris*3: per-corner shading normals (smooth triangles)
@@ -99,7 +111,11 @@ struct mrs_scene {
   float4* d_prim_ng = nullptr;
   float4* d_prim_n = nullptr;
   float4* d_leaf_tri = nullptr;
-  float4* d_nodes = nullptr;
+  float4* d_nodes = nullptr;   // binary LBVH: (ntris-1) * 4 float4
+  float4* d_nodes4 = nullptr;  // BVH4: count4 * 8 float4
+  uint32_t count4 = 0;
+  uint32_t root4 = 0;
+  int32_t leaf_max = mrs::LEAF4_MAX;  // triangles per BVH4 leaf the build may group
   uint32_t* d_morton = nullptr;     // sorted codes
   uint32_t* d_leaf_prim = nullptr;  // sorted primitive ids
   mrs::DevMaterial* d_mats = nullptr;
@@ -110,7 +126,7 @@ struct mrs_scene {
 
 namespace mrs {
 // lbvh.hip
-mrs_status lbvh_build(mrs_scene* s, hipStream_t st);
+mrs_status lbvh_build(mrs_scene* s, hipStream_t st, int leaf_max);
 // trace.hip
 struct RenderArgs {
   int32_t W, H, spp, max_depth, rr_start;

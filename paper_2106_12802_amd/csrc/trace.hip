@@ -31,6 +31,9 @@ namespace {
 
 constexpr int TB = 256;        // threads per block of the traversal kernels
 constexpr int LDS_STACK = 16;  // stack entries per thread held in LDS
+// A BVH4 node pushes at most 3 entries and the collapsed tree is no deeper
+// than the binary one; entries beyond MAX_STACK4 are counted as overflows.
+constexpr int MAX_STACK4 = 128;
 constexpr int MAX_BOUNCE_SLOTS = 66;
 constexpr float INV_PI = 0.318309886183790671538f;
 
@@ -92,10 +95,9 @@ struct TraceState {
   float b1, b2;
 };
 
-// Traversal arrays as global-address-space pointers with wave-uniform values.
-// Pointers read from the job table are generic to the compiler (flat loads,
-// vector addresses); these views give global loads off a scalar base, as
-// pointers passed as kernel arguments do.
+// Traversal arrays as global-address-space pointers: pointers read from the
+// job table are generic to the compiler (flat loads); these views give global
+// loads.
 typedef float vfloat4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(1))) const vfloat4 gfloat4;
 
@@ -104,27 +106,12 @@ __device__ __forceinline__ float4 ld4(const gfloat4* p) {
   return make_float4(v.x, v.y, v.z, v.w);
 }
 struct TraceView {
-  const gfloat4* nodes;
+  const gfloat4* nodes;  // BVH4, 8 float4 per node
   const gfloat4* leaf_tri;
   uint32_t root;
+  uint32_t nnodes;
   int32_t ntris;
 };
-
-__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
-  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-  return ((uint64_t)hi << 32) | lo;
-}
-
-// The view of scene sv, whose fields are equal across the active lanes.
-__device__ __forceinline__ TraceView trace_view(const SceneView& sv) {
-  TraceView t;
-  t.nodes = (const gfloat4*)uniform64((uint64_t)(uintptr_t)sv.nodes);
-  t.leaf_tri = (const gfloat4*)uniform64((uint64_t)(uintptr_t)sv.leaf_tri);
-  t.root = __builtin_amdgcn_readfirstlane(sv.root);
-  t.ntris = (int32_t)__builtin_amdgcn_readfirstlane((uint32_t)sv.ntris);
-  return t;
-}
 
 // Moller-Trumbore against one leaf; edges inclusive, t > 0, three excluded
 // primitives.  ANY: accept any t < ts.t (shadow rays).  Otherwise accept a
@@ -171,7 +158,7 @@ struct Stack {
   __device__ __forceinline__ void push(uint32_t v) {
     if (sp < LDS_STACK) {
       lds[sp * TB] = v;
-    } else if (sp < MAX_STACK) {
+    } else if (sp < MAX_STACK4) {
       spill[(size_t)(sp - LDS_STACK) * stride] = v;
       ++spills;
     } else {
@@ -190,57 +177,149 @@ struct WorkCount {
   uint32_t visits = 0, tests = 0;
 };
 
-// Returns true for ANY when an occluder was found; fills ts otherwise.  COUNT
-// adds node visits and triangle tests to wc (a separate instantiation).
-template <bool ANY, bool COUNT>
-__device__ bool traverse(const TraceView& sc, f3 o, f3 d, uint32_t x0, uint32_t x1, uint32_t x2,
-                         Stack& st, TraceState& ts, WorkCount& wc) {
-  if (sc.ntris == 0) return false;
-  if (sc.root & LEAF_BIT) {
-    if (COUNT) ++wc.tests;
-    return isect_leaf<ANY>(sc.leaf_tri, 0, o, d, x0, x1, x2, ts);
+__device__ __forceinline__ void cswap(float& ta, uint32_t& ra, float& tb, uint32_t& rb) {
+  const bool sw = tb < ta;
+  const float t = sw ? tb : ta;
+  const uint32_t r = sw ? rb : ra;
+  tb = sw ? ta : tb;
+  rb = sw ? ra : rb;
+  ta = t;
+  ra = r;
+}
+
+// Per-lane scene view (lanes of a wave may trace different scenes).
+__device__ __forceinline__ TraceView lane_view(const SceneView& sv) {
+  TraceView t;
+  t.nodes = (const gfloat4*)(uintptr_t)sv.nodes;
+  t.leaf_tri = (const gfloat4*)(uintptr_t)sv.leaf_tri;
+  t.root = sv.root;
+  t.nnodes = sv.nnodes;
+  t.ntris = sv.ntris;
+  return t;
+}
+
+// One ray as handed to the traversal.
+struct RayIn {
+  TraceView sc;
+  f3 o, d;
+  uint32_t x0, x1, x2;  // excluded primitives
+  float tmax;           // shadow rays: distance to the light point; else infinity
+};
+
+// Streaming four-wide BVH traversal.  Each lane walks its own sequence of
+// queue entries first, first + stride, ... < n and starts its next ray as soon
+// as the current one is finished, so lanes do not wait for the slowest ray of
+// their wave.  Within a ray: leaf postponing (the "while-while" loop of Aila &
+// Laine, HPG 2009) -- a lane that reaches a leaf parks it and keeps descending
+// until every active lane of the wave has a leaf, then the wave intersects the
+// parked leaves together.  Children are visited nearest first for closest hits
+// (sorting network on the entry distances); shadow rays (ANY) take them in
+// any order and stop at the first occluder.  IO supplies load(qi, RayIn&) and
+// store(qi, const TraceState&, bool occluded).  COUNT adds node visits and
+// triangle tests to wc (a separate instantiation).
+template <bool ANY, bool COUNT, class IO>
+__device__ void trace_stream(IO& io, uint32_t first, uint32_t stride, uint32_t n, Stack& st,
+                             WorkCount& wc) {
+  uint32_t qi = first;
+  bool live = qi < n;
+  RayIn r;
+  TraceState ts;
+  f3 inv, oi;
+  uint32_t node = EMPTY4, leaf = EMPTY4;  // next reference to visit; parked leaf
+  int32_t budget = 0;
+  bool occluded = false;
+  auto start = [&]() {
+    io.load(qi, r);
+    ts = TraceState{r.tmax, NO_PRIM, 0.0f, 0.0f};
+    inv = F3(safe_rcp(r.d.x), safe_rcp(r.d.y), safe_rcp(r.d.z));
+    oi = mul(r.o, inv);
+    st.sp = 0;
+    occluded = false;
+    // every node and leaf is visited at most once per ray in a well-formed tree
+    budget = (int32_t)r.sc.nnodes + r.sc.ntris + 2;
+    node = leaf = EMPTY4;
+    if (r.sc.ntris > 0) {
+      if (r.sc.root & LEAF_BIT) leaf = r.sc.root;
+      else node = r.sc.root;
+    }
+  };
+  if (live) start();
+  while (live) {
+    // ---- internal nodes (EMPTY4 has the leaf bit set)
+    while (!(node & LEAF_BIT) && --budget > 0) {
+      if (node >= r.sc.nnodes) {  // keeps a corrupt reference harmless
+        node = st.sp ? st.pop() : EMPTY4;
+        continue;
+      }
+      const gfloat4* nd = r.sc.nodes + 8 * node;
+      const float4 lx = ld4(nd), ly = ld4(nd + 1), lz = ld4(nd + 2);
+      const float4 hx = ld4(nd + 3), hy = ld4(nd + 4), hz = ld4(nd + 5);
+      const float4 rf = ld4(nd + 6);
+      if (COUNT) ++wc.visits;
+      float t0, t1, t2, t3;
+      uint32_t r0 = __float_as_uint(rf.x), r1 = __float_as_uint(rf.y), r2 = __float_as_uint(rf.z),
+               r3 = __float_as_uint(rf.w);
+      if (r0 == EMPTY4 || !slab(lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, oi, inv, ts.t, t0)) {
+        r0 = EMPTY4;
+        t0 = INFINITY;
+      }
+      if (r1 == EMPTY4 || !slab(lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, oi, inv, ts.t, t1)) {
+        r1 = EMPTY4;
+        t1 = INFINITY;
+      }
+      if (r2 == EMPTY4 || !slab(lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, oi, inv, ts.t, t2)) {
+        r2 = EMPTY4;
+        t2 = INFINITY;
+      }
+      if (r3 == EMPTY4 || !slab(lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, oi, inv, ts.t, t3)) {
+        r3 = EMPTY4;
+        t3 = INFINITY;
+      }
+      // hits to the front, nearest first for closest hits (misses sort last)
+      cswap(t0, r0, t1, r1);
+      cswap(t2, r2, t3, r3);
+      cswap(t0, r0, t2, r2);
+      cswap(t1, r1, t3, r3);
+      if (!ANY) cswap(t1, r1, t2, r2);
+      if (r3 != EMPTY4) st.push(r3);
+      if (r2 != EMPTY4) st.push(r2);
+      if (r1 != EMPTY4) st.push(r1);
+      node = r0 != EMPTY4 ? r0 : (st.sp ? st.pop() : EMPTY4);
+      if ((node & LEAF_BIT) && node != EMPTY4 && leaf == EMPTY4) {
+        leaf = node;
+        node = st.sp ? st.pop() : EMPTY4;
+      }
+      if (__all(leaf != EMPTY4)) break;
+    }
+    // ---- the parked leaf, then leaves that follow on the stack
+    while (leaf != EMPTY4 && --budget > 0) {
+      const uint32_t f = leaf & 0x00ffffffu, cnt = ((leaf >> 24) & 3u) + 1u;
+      if (f + cnt <= (uint32_t)r.sc.ntris) {  // keeps a corrupt reference harmless
+        for (uint32_t k = 0; k < cnt; ++k) {
+          if (COUNT) ++wc.tests;
+          if (isect_leaf<ANY>(r.sc.leaf_tri, f + k, r.o, r.d, r.x0, r.x1, r.x2, ts) && ANY) {
+            occluded = true;
+            break;
+          }
+        }
+      }
+      leaf = EMPTY4;
+      if (occluded) {
+        node = EMPTY4;
+        break;
+      }
+      if ((node & LEAF_BIT) && node != EMPTY4) {
+        leaf = node;
+        node = st.sp ? st.pop() : EMPTY4;
+      }
+    }
+    if ((node == EMPTY4 && leaf == EMPTY4) || budget <= 0) {  // ray finished
+      io.store(qi, ts, occluded);
+      qi += stride;
+      live = qi < n;
+      if (live) start();
+    }
   }
-  const f3 inv = F3(safe_rcp(d.x), safe_rcp(d.y), safe_rcp(d.z));
-  const f3 oi = mul(o, inv);
-  uint32_t node = 0;
-  st.sp = 0;
-  const uint32_t ninternal = (uint32_t)sc.ntris - 1u;
-  // A well-formed tree visits each internal node at most once per ray.
-  for (uint32_t visits = 0; visits < ninternal; ++visits) {
-    const gfloat4* nd = sc.nodes + 4 * node;
-    const float4 a = ld4(nd), b = ld4(nd + 1), c = ld4(nd + 2), r = ld4(nd + 3);
-    if (COUNT) ++wc.visits;
-    float tl, tr;
-    bool hl = slab(a.x, a.y, a.z, a.w, b.x, b.y, oi, inv, ts.t, tl);
-    bool hr = slab(b.z, b.w, c.x, c.y, c.z, c.w, oi, inv, ts.t, tr);
-    const uint32_t cl = __float_as_uint(r.x), cr = __float_as_uint(r.y);
-    // references always lie inside the tree; the checks keep a corrupt one harmless
-    if ((cl & LEAF_BIT) ? (cl & ~LEAF_BIT) >= (uint32_t)sc.ntris : cl >= ninternal) hl = false;
-    if ((cr & LEAF_BIT) ? (cr & ~LEAF_BIT) >= (uint32_t)sc.ntris : cr >= ninternal) hr = false;
-    if (hl && (cl & LEAF_BIT)) {
-      if (COUNT) ++wc.tests;
-      if (isect_leaf<ANY>(sc.leaf_tri, cl & ~LEAF_BIT, o, d, x0, x1, x2, ts) && ANY) return true;
-      hl = false;
-    }
-    if (hr && (cr & LEAF_BIT)) {
-      if (COUNT) ++wc.tests;
-      if (isect_leaf<ANY>(sc.leaf_tri, cr & ~LEAF_BIT, o, d, x0, x1, x2, ts) && ANY) return true;
-      hr = false;
-    }
-    if (hl && hr) {
-      const bool lfirst = tl <= tr;
-      st.push(lfirst ? cr : cl);
-      node = lfirst ? cl : cr;
-    } else if (hl) {
-      node = cl;
-    } else if (hr) {
-      node = cr;
-    } else {
-      if (st.sp == 0) break;
-      node = st.pop();
-    }
-  }
-  return false;
 }
 
 
@@ -356,6 +435,39 @@ struct WaveQueue {
   __device__ __forceinline__ void next() { base = dyn ? fetch() : base + step; }
 };
 
+struct ExtendIO {
+  const DevJob* __restrict__ jobs;
+  const float4* __restrict__ rays;
+  float4* __restrict__ hits;
+  __device__ __forceinline__ void load(uint32_t qi, RayIn& r) const {
+    const float4 R0 = rays[2 * qi], R1 = rays[2 * qi + 1];
+    const uint32_t tag = __float_as_uint(R1.w);
+    r.sc = lane_view(jobs[job_of(tag)].sv);
+    r.o = xyz(R0);
+    r.d = xyz(R1);
+    r.x0 = unpack_prim(tag);
+    r.x1 = r.x2 = NO_PRIM;
+    r.tmax = INFINITY;
+  }
+  __device__ __forceinline__ void store(uint32_t qi, const TraceState& ts, bool) const {
+    hits[qi] = make_float4(ts.t, __uint_as_float(ts.prim), ts.b1, ts.b2);
+  }
+};
+
+// Static schedule: lane sequences gtid, gtid + threads, ...  Dynamic: a wave
+// takes 64 consecutive entries per fetch from a device counter.
+template <bool ANY, bool COUNT, class IO>
+__device__ __forceinline__ void trace_queue(IO& io, uint32_t n, int dyn, uint32_t* fetch,
+                                            Stack& st, WorkCount& wc) {
+  if (!dyn) {
+    trace_stream<ANY, COUNT>(io, blockIdx.x * TB + threadIdx.x, gridDim.x * TB, n, st, wc);
+    return;
+  }
+  WaveQueue wq(fetch, true);
+  for (; wq.base < n; wq.next())
+    trace_stream<ANY, COUNT>(io, wq.base + __lane_id(), 64u, min(n, wq.base + 64u), st, wc);
+}
+
 template <bool COUNT>
 __global__ __launch_bounds__(TB) void k_extend(const DevJob* __restrict__ jobs, int b, int dyn,
                                                const float4* __restrict__ rays,
@@ -365,30 +477,11 @@ __global__ __launch_bounds__(TB) void k_extend(const DevJob* __restrict__ jobs, 
                                                unsigned long long* __restrict__ stats) {
   __shared__ uint32_t stk[LDS_STACK * TB];
   const uint32_t n = q[Q_RAYS + b];
-  WaveQueue wq(q + Q_FETCH_EXT + b, dyn != 0);
   const uint32_t gtid = blockIdx.x * TB + threadIdx.x;
   Stack st{stk + threadIdx.x, spill + gtid, gridDim.x * TB, 0, 0u, false};
   WorkCount wc;
-  for (; wq.base < n; wq.next()) {
-    const uint32_t qi = wq.base + __lane_id();
-    if (qi < n) {
-      const float4 R0 = rays[2 * qi], R1 = rays[2 * qi + 1];
-      const uint32_t tag = __float_as_uint(R1.w);
-      const uint32_t j = job_of(tag);
-      TraceState ts{INFINITY, NO_PRIM, 0.0f, 0.0f};
-      // One pass per distinct job among the wave's lanes (nearly always one): the
-      // job id is wave-uniform inside, so the scene's pointers stay scalar.
-      for (;;) {
-        const uint32_t ju = __builtin_amdgcn_readfirstlane(j);
-        if (j == ju) {
-          traverse<false, COUNT>(trace_view(jobs[ju].sv), xyz(R0), xyz(R1), unpack_prim(tag),
-                                 NO_PRIM, NO_PRIM, st, ts, wc);
-          break;
-        }
-      }
-      hits[qi] = make_float4(ts.t, __uint_as_float(ts.prim), ts.b1, ts.b2);
-    }
-  }
+  ExtendIO io{jobs, rays, hits};
+  trace_queue<false, COUNT>(io, n, dyn, q + Q_FETCH_EXT + b, st, wc);
   if (st.spills) atomicAdd(stats + 3, (unsigned long long)st.spills);
   if (st.overflow) atomicAdd(stats + 5, 1ull);
   if (COUNT && wc.visits) atomicAdd(stats + 6, (unsigned long long)wc.visits);
@@ -579,6 +672,37 @@ __global__ __launch_bounds__(256) void k_shade(const DevJob* __restrict__ jobs, 
   }
 }
 
+struct ShadowIO {
+  const DevJob* __restrict__ jobs;
+  const float4* __restrict__ shadow;
+  float4* __restrict__ L_buf;
+  __device__ __forceinline__ void load(uint32_t qi, RayIn& r) const {
+    const float4 S0 = shadow[3 * qi], S1 = shadow[3 * qi + 1];
+    const uint32_t li = __float_as_uint(S0.w) >> 24;
+    const uint32_t ptag = __float_as_uint(shadow[3 * qi + 2].w);
+    const SceneView& sv = jobs[job_of(ptag)].sv;
+    const DevLight& lt = sv.lights[li];
+    r.sc = lane_view(sv);
+    r.o = xyz(S0);
+    r.d = xyz(S1);
+    r.x0 = unpack_prim(ptag);
+    r.x1 = (uint32_t)lt.tri0;
+    r.x2 = (uint32_t)lt.tri1;
+    r.tmax = S1.w;
+  }
+  // an unoccluded sample adds its contribution to its own path's radiance
+  __device__ __forceinline__ void store(uint32_t qi, const TraceState&, bool occluded) const {
+    if (occluded) return;
+    const uint32_t slot = __float_as_uint(shadow[3 * qi].w) & 0xffffffu;
+    const float4 S2 = shadow[3 * qi + 2];
+    float4 Lv = L_buf[slot];
+    Lv.x += S2.x;
+    Lv.y += S2.y;
+    Lv.z += S2.z;
+    L_buf[slot] = Lv;
+  }
+};
+
 template <bool COUNT>
 __global__ __launch_bounds__(TB) void k_shadow(const DevJob* __restrict__ jobs, int b, int dyn,
                                                const float4* __restrict__ shadow,
@@ -588,38 +712,11 @@ __global__ __launch_bounds__(TB) void k_shadow(const DevJob* __restrict__ jobs, 
                                                unsigned long long* __restrict__ stats) {
   __shared__ uint32_t stk[LDS_STACK * TB];
   const uint32_t n = q[Q_SHADOW + b];
-  WaveQueue wq(q + Q_FETCH_SHD + b, dyn != 0);
   const uint32_t gtid = blockIdx.x * TB + threadIdx.x;
   Stack st{stk + threadIdx.x, spill + gtid, gridDim.x * TB, 0, 0u, false};
   WorkCount wc;
-  for (; wq.base < n; wq.next()) {
-    const uint32_t qi = wq.base + __lane_id();
-    if (qi < n) {
-      const float4 S0 = shadow[3 * qi], S1 = shadow[3 * qi + 1], S2 = shadow[3 * qi + 2];
-      const uint32_t tag = __float_as_uint(S0.w), ptag = __float_as_uint(S2.w);
-      const uint32_t slot = tag & 0xffffffu, li = tag >> 24;
-      const uint32_t j = job_of(ptag);
-      TraceState ts{S1.w, NO_PRIM, 0.0f, 0.0f};
-      bool occ = false;
-      for (;;) {  // wave-uniform job per pass, as in k_extend
-        const uint32_t ju = __builtin_amdgcn_readfirstlane(j);
-        if (j == ju) {
-          const SceneView& sc = jobs[ju].sv;
-          const DevLight& lt = sc.lights[li];
-          occ = traverse<true, COUNT>(trace_view(sc), xyz(S0), xyz(S1), unpack_prim(ptag),
-                                      (uint32_t)lt.tri0, (uint32_t)lt.tri1, st, ts, wc);
-          break;
-        }
-      }
-      if (!occ) {
-        float4 Lv = L_buf[slot];
-        Lv.x += S2.x;
-        Lv.y += S2.y;
-        Lv.z += S2.z;
-        L_buf[slot] = Lv;
-      }
-    }
-  }
+  ShadowIO io{jobs, shadow, L_buf};
+  trace_queue<true, COUNT>(io, n, dyn, q + Q_FETCH_SHD + b, st, wc);
   if (st.spills) atomicAdd(stats + 3, (unsigned long long)st.spills);
   if (st.overflow) atomicAdd(stats + 5, 1ull);
   if (COUNT && wc.visits) atomicAdd(stats + 8, (unsigned long long)wc.visits);
@@ -738,28 +835,44 @@ __global__ __launch_bounds__(64) void k_tally(const uint32_t* __restrict__ q, in
   }
 }
 
-__global__ __launch_bounds__(256) void k_debug_hit(SceneView sc, int32_t n,
-                                                   const float* __restrict__ o,
-                                                   const float* __restrict__ d,
-                                                   const int32_t* __restrict__ skip,
-                                                   float* __restrict__ t_out,
-                                                   int32_t* __restrict__ prim_out,
-                                                   float* __restrict__ b_out,
-                                                   uint32_t* __restrict__ spill) {
-  __shared__ uint32_t stk[LDS_STACK * 256];
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  Stack st{stk + threadIdx.x, spill + i, (uint32_t)(gridDim.x * 256), 0, 0u, false};
-  if (i >= n) return;
-  TraceState ts{INFINITY, NO_PRIM, 0.0f, 0.0f};
+struct DebugHitIO {
+  SceneView sv;
+  const float* __restrict__ o;
+  const float* __restrict__ d;
+  const int32_t* __restrict__ skip;
+  float* __restrict__ t_out;
+  int32_t* __restrict__ prim_out;
+  float* __restrict__ b_out;
+  __device__ __forceinline__ void load(uint32_t i, RayIn& r) const {
+    r.sc = lane_view(sv);
+    r.o = F3(o[3 * i], o[3 * i + 1], o[3 * i + 2]);
+    r.d = F3(d[3 * i], d[3 * i + 1], d[3 * i + 2]);
+    r.x0 = skip ? (uint32_t)skip[i] : NO_PRIM;
+    r.x1 = r.x2 = NO_PRIM;
+    r.tmax = INFINITY;
+  }
+  __device__ __forceinline__ void store(uint32_t i, const TraceState& ts, bool) const {
+    t_out[i] = ts.t;
+    prim_out[i] = ts.prim == NO_PRIM ? -1 : (int32_t)ts.prim;
+    b_out[2 * i] = ts.b1;
+    b_out[2 * i + 1] = ts.b2;
+  }
+};
+
+__global__ __launch_bounds__(TB) void k_debug_hit(SceneView sc, int32_t n,
+                                                  const float* __restrict__ o,
+                                                  const float* __restrict__ d,
+                                                  const int32_t* __restrict__ skip,
+                                                  float* __restrict__ t_out,
+                                                  int32_t* __restrict__ prim_out,
+                                                  float* __restrict__ b_out,
+                                                  uint32_t* __restrict__ spill) {
+  __shared__ uint32_t stk[LDS_STACK * TB];
+  const uint32_t gtid = blockIdx.x * TB + threadIdx.x;
+  Stack st{stk + threadIdx.x, spill + gtid, gridDim.x * TB, 0, 0u, false};
   WorkCount wc;
-  const uint32_t sk = skip ? (uint32_t)skip[i] : NO_PRIM;
-  traverse<false, false>(trace_view(sc), F3(o[3 * i], o[3 * i + 1], o[3 * i + 2]),
-                         F3(d[3 * i], d[3 * i + 1], d[3 * i + 2]), sk, NO_PRIM, NO_PRIM, st, ts,
-                         wc);
-  t_out[i] = ts.t;
-  prim_out[i] = ts.prim == NO_PRIM ? -1 : (int32_t)ts.prim;
-  b_out[2 * i] = ts.b1;
-  b_out[2 * i + 1] = ts.b2;
+  DebugHitIO io{sc, o, d, skip, t_out, prim_out, b_out};
+  trace_stream<false, false>(io, gtid, gridDim.x * TB, (uint32_t)n, st, wc);
 }
 
 __global__ __launch_bounds__(256) void k_debug_philox(int32_t n, const uint32_t* __restrict__ ctr,
@@ -799,7 +912,7 @@ struct Workspace {
 std::mutex g_mu;  // guards the tables below and the tuning
 std::map<hipStream_t, Workspace*> g_stream_ws;
 unsigned long long* g_stats = nullptr;  // device counters shared by every stream
-mrs_tuning g_tune = {1 << 23, 4096, 0};
+mrs_tuning g_tune = {1 << 23, 8192, 0, LEAF4_MAX};
 std::atomic<bool> g_count_work{false};
 
 template <typename T>
@@ -864,7 +977,7 @@ mrs_status ws_ensure(Workspace& w, size_t paths, int threads) {
   }
   if (threads > w.spill_threads) {
     hfree(w.spill);
-    if (hipMalloc(&w.spill, sizeof(uint32_t) * (MAX_STACK - LDS_STACK) * (size_t)threads) !=
+    if (hipMalloc(&w.spill, sizeof(uint32_t) * (MAX_STACK4 - LDS_STACK) * (size_t)threads) !=
         hipSuccess) {
       (void)hipGetLastError();
       w.spill_threads = 0;
@@ -1118,11 +1231,11 @@ mrs_status debug_closest_hit(const mrs_scene* s, int32_t n, const float* o, cons
                              const int32_t* skip, float* t, int32_t* prim, float* b,
                              hipStream_t st) {
   if (n <= 0) return MRS_OK;
-  const unsigned blocks = cdiv((size_t)n, 256);
+  const unsigned blocks = std::min(cdiv((size_t)n, TB), 1024u);
   Workspace& ws = *stream_workspace(st);
-  mrs_status rc = ws_ensure(ws, 1, (int)(blocks * 256));
+  mrs_status rc = ws_ensure(ws, 1, (int)(blocks * TB));
   if (rc != MRS_OK) return rc;
-  k_debug_hit<<<blocks, 256, 0, st>>>(s->view, n, o, d, skip, t, prim, b, ws.spill);
+  k_debug_hit<<<blocks, TB, 0, st>>>(s->view, n, o, d, skip, t, prim, b, ws.spill);
   MRS_TRY_HIP(hipGetLastError());
   return MRS_OK;
 }
@@ -1160,6 +1273,8 @@ mrs_status set_tuning(const mrs_tuning* t) {
     return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_set_tuning: trace_blocks must be in [1, 65536]");
   if (t->schedule != 0 && t->schedule != 1)
     return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_set_tuning: schedule must be 0 or 1");
+  if (t->bvh_leaf_max < 1 || t->bvh_leaf_max > LEAF4_MAX)
+    return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_set_tuning: bvh_leaf_max must be in [1, 4]");
   std::lock_guard<std::mutex> lk(g_mu);
   g_tune = *t;
   return MRS_OK;

@@ -70,6 +70,18 @@ class GpuScene:
                                       C.byref(root)))
         return nodes, leaf, morton, root.value & 0xFFFFFFFF
 
+    def bvh4(self):
+        """(nodes [count, 32] float32, root ref, leaf_max) of the four-wide BVH."""
+        count, root, lmax = C.c_int32(), C.c_uint32(), C.c_int32()
+        L.use_current_stream()
+        L.check(L.lib().mrs_debug_bvh4(self.handle, None, C.byref(count), C.byref(root),
+                                       C.byref(lmax)))
+        nodes = np.zeros((count.value, 32), np.float32)
+        if count.value:
+            L.check(L.lib().mrs_debug_bvh4(self.handle, nodes.ctypes.data_as(C.c_void_p),
+                                           C.byref(count), C.byref(root), C.byref(lmax)))
+        return nodes, root.value, lmax.value
+
 
 def render_ex(scene: GpuScene, W, H, spp, max_depth, seed, out_rgb, out_aux=None, rr_start=3,
               window=None, accum_fp64=-1, out_sumsq=None):
@@ -126,7 +138,7 @@ def profile_read():
     return {names[i]: (float(ms[i]), int(n[i])) for i in range(L.NUM_KERNEL_IDS) if n[i]}
 
 
-TUNING_KEYS = ("chunk_paths", "trace_blocks", "schedule")
+TUNING_KEYS = ("chunk_paths", "trace_blocks", "schedule", "bvh_leaf_max")
 
 
 def get_tuning():
@@ -135,9 +147,10 @@ def get_tuning():
     return {k: int(getattr(t, k)) for k in TUNING_KEYS}
 
 
-def set_tuning(chunk_paths=None, trace_blocks=None, schedule=None):
+def set_tuning(chunk_paths=None, trace_blocks=None, schedule=None, bvh_leaf_max=None):
     cur = get_tuning()
-    new = dict(chunk_paths=chunk_paths, trace_blocks=trace_blocks, schedule=schedule)
+    new = dict(chunk_paths=chunk_paths, trace_blocks=trace_blocks, schedule=schedule,
+               bvh_leaf_max=bvh_leaf_max)
     t = L.Tuning()
     for k in TUNING_KEYS:
         setattr(t, k, int(new[k] if new[k] is not None else cur[k]))

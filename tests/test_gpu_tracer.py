@@ -115,6 +115,53 @@ def _check_lbvh(gs, scene):
                 assert np.array_equal(box[:3], lo) and np.array_equal(box[3:], hi)
 
 
+def _check_bvh4(gs, scene):
+    """The four-wide BVH: every node reached once, every leaf slot covered once by
+    the leaf ranges (at most leaf_max each), child boxes equal to the exact bounds of
+    their subtrees, at least two children per node."""
+    nodes, root, lmax = gs.bvh4()
+    _, leaf, _, _ = gs.bvh()
+    n = scene.num_tris
+    if n == 0:
+        return
+    V = scene.vertices.astype(np.float32)
+    if n == 1:
+        assert root == 0x80000000 and len(nodes) == 0
+        return
+    assert root == 0
+    refs = nodes[:, 24:28].copy().view(np.uint32)
+    seen_node = np.zeros(len(nodes), int)
+    seen_slot = np.zeros(n, int)
+
+    def bounds(ref):  # exact bounds of a reference's triangles; marks what it reaches
+        if ref & 0x80000000:
+            first, count = ref & 0xFFFFFF, ((ref >> 24) & 3) + 1
+            assert count <= lmax and first + count <= n
+            seen_slot[first:first + count] += 1
+            tri = V[leaf[first:first + count]].reshape(-1, 3)
+            return tri.min(0), tri.max(0)
+        seen_node[ref] += 1
+        lo = np.full(3, np.inf, np.float32)
+        hi = np.full(3, -np.inf, np.float32)
+        kids = 0
+        for k in range(4):
+            r = int(refs[ref, k])
+            if r == 0xFFFFFFFF:
+                continue
+            kids += 1
+            clo, chi = bounds(r)
+            box = nodes[ref, [k, 4 + k, 8 + k, 12 + k, 16 + k, 20 + k]]
+            assert np.array_equal(box[:3], clo) and np.array_equal(box[3:], chi), (ref, k)
+            lo, hi = np.minimum(lo, clo), np.maximum(hi, chi)
+        assert kids >= 2
+        return lo, hi
+
+    import sys
+    sys.setrecursionlimit(10000)
+    bounds(root)
+    assert np.all(seen_node == 1) and np.all(seen_slot == 1)
+
+
 @pytest.mark.parametrize("maker", [
     lambda: S.random_soup(1, 1),
     lambda: S.random_soup(2, 2),
@@ -127,6 +174,26 @@ def test_lbvh_invariants(mrs, maker):
     _log("lbvh", scene.name, scene.num_tris)
     gs = mrs.GpuScene(scene)
     _check_lbvh(gs, scene)
+    _check_bvh4(gs, scene)
+
+
+@pytest.mark.parametrize("leaf_max", [1, 2, 3])
+def test_bvh4_leaf_grouping_and_same_hits(mrs, leaf_max):
+    """Any leaf grouping gives a valid tree and bitwise the same closest hits."""
+    scene = S.random_soup(5, 3000)
+    o, d = S.random_rays(5, 2000)
+    ref = mrs.GpuScene(scene)
+    t_r, p_r, b_r = ref.closest_hit(o, d)
+    old = mrs.get_tuning()
+    try:
+        mrs.set_tuning(bvh_leaf_max=leaf_max)
+        gs = mrs.GpuScene(scene)
+    finally:
+        mrs.set_tuning(**old)
+    assert gs.bvh4()[2] == leaf_max
+    _check_bvh4(gs, scene)
+    t_g, p_g, b_g = gs.closest_hit(o, d)
+    assert np.array_equal(p_g, p_r) and np.array_equal(t_g, t_r) and np.array_equal(b_g, b_r)
 
 
 def test_lbvh_identical_centroids(mrs):
