@@ -337,6 +337,8 @@ def main():
     ap.add_argument("--trace-blocks", type=int, default=None, help="tuning: traversal grid size")
     ap.add_argument("--schedule", type=int, default=None, choices=(0, 1),
                     help="tuning: traversal queue schedule (0 grid-stride, 1 dynamic)")
+    ap.add_argument("--streams", type=int, default=None,
+                    help="tuning: concurrent sub-chunks per render (1..4)")
     ap.add_argument("--leaf-max", type=int, default=None,
                     help="BVH build: triangles a BVH4 leaf may group (1..4)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -360,7 +362,7 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_calibration:
         copy_calibration()
-    R.set_tuning(args.chunk_paths, args.trace_blocks, args.schedule, args.leaf_max)
+    R.set_tuning(args.chunk_paths, args.trace_blocks, args.schedule, args.leaf_max, args.streams)
     tuning = R.get_tuning()
     log(f"[bench] tuning {tuning}")
     scene = S.procedural(SCENE_SEED)

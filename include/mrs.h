@@ -236,6 +236,10 @@ typedef struct mrs_tuning {
                            dynamic fetch from a device counter */
   int32_t bvh_leaf_max; /* triangles a BVH4 leaf may group, 1..4 (default 4);
                            applies to scenes built afterwards */
+  int32_t streams;      /* 1..4 (default 3): a render's resident paths are cut into
+                           this many sub-chunks, traced concurrently on internal
+                           streams shared by the library (joined back into the
+                           caller's stream before the per-pixel sums) */
 } mrs_tuning;
 mrs_status mrs_get_tuning(mrs_tuning* out);
 mrs_status mrs_set_tuning(const mrs_tuning* t);

@@ -34,6 +34,7 @@ constexpr int LDS_STACK = 16;  // stack entries per thread held in LDS
 // A BVH4 node pushes at most 3 entries and the collapsed tree is no deeper
 // than the binary one; entries beyond MAX_STACK4 are counted as overflows.
 constexpr int MAX_STACK4 = 128;
+constexpr int MAX_SUB = 4;  // concurrent sub-chunks of a render
 constexpr int MAX_BOUNCE_SLOTS = 66;
 constexpr float INV_PI = 0.318309886183790671538f;
 
@@ -76,8 +77,11 @@ __device__ __forceinline__ float safe_rcp(float x) {
   return __builtin_amdgcn_rcpf(ax);
 }
 
-// Conservative slab test; the far distance is widened by a few ulp so that
-// rounding never culls a box that the ray touches.
+// Conservative slab test.  The far distance is widened by a few ulp so that
+// rounding never culls a box that the ray touches, and a box counts as nearer
+// than the best hit so far up to a relative 2^-12: far above the rounding of
+// either the box or the triangle distances, so culling never drops a triangle
+// that could tie with or beat the best hit, whatever order boxes are visited in.
 __device__ __forceinline__ bool slab(float lx, float ly, float lz, float hx, float hy, float hz,
                                      f3 oi, f3 inv, float tbest, float& tnear) {
   const float t0x = fmaf(lx, inv.x, -oi.x), t1x = fmaf(hx, inv.x, -oi.x);
@@ -86,7 +90,7 @@ __device__ __forceinline__ bool slab(float lx, float ly, float lz, float hx, flo
   const float tmin = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), 0.0f));
   const float tmax = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fmaxf(t0z, t1z)) * 1.0000005f;
   tnear = tmin;
-  return tmin <= tmax && tmin <= tbest;
+  return tmin <= tmax && tmin <= tbest * 1.000244140625f;
 }
 
 struct TraceState {
@@ -209,12 +213,14 @@ struct RayIn {
 // Streaming four-wide BVH traversal.  Each lane walks its own sequence of
 // queue entries first, first + stride, ... < n and starts its next ray as soon
 // as the current one is finished, so lanes do not wait for the slowest ray of
-// their wave.  Within a ray: leaf postponing (the "while-while" loop of Aila &
-// Laine, HPG 2009) -- a lane that reaches a leaf parks it and keeps descending
+// their wave.  Within a ray: the speculative "while-while" loop of Aila &
+// Laine (HPG 2009) -- a lane that reaches a leaf parks it and keeps descending
 // until every active lane of the wave has a leaf, then the wave intersects the
-// parked leaves together.  Children are visited nearest first for closest hits
-// (sorting network on the entry distances); shadow rays (ANY) take them in
-// any order and stop at the first occluder.  IO supplies load(qi, RayIn&) and
+// parked leaves together.  A ray's visiting order thus depends on the rays
+// sharing its wave; the result does not, because box culling is conservative
+// (see slab).  Children are visited nearest first for closest hits (sorting
+// network on the entry distances); shadow rays (ANY) take them in any order
+// and stop at the first occluder.  IO supplies load(qi, RayIn&) and
 // store(qi, const TraceState&, bool occluded).  COUNT adds node visits and
 // triangle tests to wc (a separate instantiation).
 template <bool ANY, bool COUNT, class IO>
@@ -308,10 +314,11 @@ __device__ void trace_stream(IO& io, uint32_t first, uint32_t stride, uint32_t n
         node = EMPTY4;
         break;
       }
-      if ((node & LEAF_BIT) && node != EMPTY4) {
+      if ((node & LEAF_BIT) && node != EMPTY4 && leaf == EMPTY4) {
         leaf = node;
         node = st.sp ? st.pop() : EMPTY4;
       }
+      if (__all(leaf != EMPTY4)) break;
     }
     if ((node == EMPTY4 && leaf == EMPTY4) || budget <= 0) {  // ray finished
       io.store(qi, ts, occluded);
@@ -904,15 +911,41 @@ struct Workspace {
   float4* L = nullptr;
   float4* aux = nullptr;
   uint32_t* spill = nullptr;
-  uint32_t* q = nullptr;
+  uint32_t* q = nullptr;  // MAX_SUB blocks of Q_WORDS counters
   char* acc = nullptr;    // per-job accumulators (single renders)
   DevJob* one = nullptr;  // device copy of the job of a single render
+  int nsub = 0;           // sub-chunk join events created
+  hipEvent_t ev_fork = nullptr;
+  hipEvent_t ev_join[MAX_SUB] = {};
 };
+
+// How a render's path space is cut: super-chunks of K * Cs paths; the K
+// sub-chunks of Cs paths run concurrently on their own streams, each with
+// grids of at most blocks_k traversal blocks.
+struct Plan {
+  int K;
+  int64_t Cs;
+  int blocks_k;
+};
+
+Plan make_plan(const mrs_tuning& tu, int64_t total) {
+  Plan p;
+  p.K = std::max(1, std::min<int>(tu.streams, (int)(total / 65536)));
+  const int64_t C = std::max<int64_t>(1, std::min<int64_t>(tu.chunk_paths, total));
+  p.Cs = ((C + p.K - 1) / p.K + 255) & ~(int64_t)255;
+  p.blocks_k = std::max(1, (tu.trace_blocks + p.K - 1) / p.K);
+  return p;
+}
 
 std::mutex g_mu;  // guards the tables below and the tuning
 std::map<hipStream_t, Workspace*> g_stream_ws;
+// Sub-chunk streams, shared by every workspace and created once: each takes a
+// hardware queue of its own (the runtime has few), so concurrent sub-chunks do
+// not end up serialised behind one another on a shared queue.
+hipStream_t g_sub[MAX_SUB] = {};
+int g_nsub = 0;
 unsigned long long* g_stats = nullptr;  // device counters shared by every stream
-mrs_tuning g_tune = {1 << 23, 8192, 0, LEAF4_MAX};
+mrs_tuning g_tune = {1 << 23, 8192, 0, LEAF4_MAX, 3};
 std::atomic<bool> g_count_work{false};
 
 template <typename T>
@@ -932,6 +965,10 @@ void ws_release(Workspace& w) {
   hfree(w.q);
   hfree(w.acc);
   hfree(w.one);
+  for (int k = 0; k < w.nsub; ++k) (void)hipEventDestroy(w.ev_join[k]);
+  if (w.ev_fork) (void)hipEventDestroy(w.ev_fork);
+  w.ev_fork = nullptr;
+  w.nsub = 0;
   w.cap_paths = 0;
   w.spill_threads = 0;
   w.acc_bytes = 0;
@@ -945,14 +982,27 @@ mrs_status ensure_stats() {
   return MRS_OK;
 }
 
-// Grows w to hold `paths` path slots and `threads` traversal threads (device
-// allocations happen only here, and only when the workspace grows).
-mrs_status ws_ensure(Workspace& w, size_t paths, int threads) {
+// Grows w to hold `paths` path slots, `threads` traversal threads and `nsub`
+// sub-chunk streams (device allocations happen only here, and only when the
+// workspace grows).
+mrs_status ws_ensure(Workspace& w, size_t paths, int threads, int nsub) {
   mrs_status rc = ensure_stats();
   if (rc != MRS_OK) return rc;
   if (!w.q) {
-    MRS_TRY_HIP(hipMalloc(&w.q, sizeof(uint32_t) * Q_WORDS));
+    MRS_TRY_HIP(hipMalloc(&w.q, sizeof(uint32_t) * Q_WORDS * MAX_SUB));
     MRS_TRY_HIP(hipMalloc(&w.one, sizeof(DevJob)));
+    MRS_TRY_HIP(hipEventCreateWithFlags(&w.ev_fork, hipEventDisableTiming));
+  }
+  if (nsub > 0) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    while (g_nsub < nsub) {
+      MRS_TRY_HIP(hipStreamCreateWithFlags(&g_sub[g_nsub], hipStreamNonBlocking));
+      ++g_nsub;
+    }
+  }
+  while (w.nsub < nsub) {
+    MRS_TRY_HIP(hipEventCreateWithFlags(&w.ev_join[w.nsub], hipEventDisableTiming));
+    ++w.nsub;
   }
   if (paths > w.cap_paths) {
     for (auto*& p : w.rays) hfree(p);
@@ -986,6 +1036,10 @@ mrs_status ws_ensure(Workspace& w, size_t paths, int threads) {
     w.spill_threads = threads;
   }
   return MRS_OK;
+}
+
+mrs_status ws_ensure_plan(Workspace& w, const Plan& p) {
+  return ws_ensure(w, (size_t)p.K * p.Cs, p.K * p.blocks_k * TB, p.K > 1 ? p.K : 0);
 }
 
 mrs_status ws_ensure_acc(Workspace& w, size_t bytes) {
@@ -1033,56 +1087,86 @@ mrs_status launch_batch(Workspace& ws, const mrs_tuning& tu, const DevJob* d_job
     total_pix += (int64_t)J.ww * J.wh;
     max_depth = std::max(max_depth, (int)J.max_depth);
   }
-  const int64_t C = tu.chunk_paths;
-  const int blocks = tu.trace_blocks;
+  const Plan P = make_plan(tu, total);
   const int dyn = tu.schedule;
   const bool count = g_count_work.load();
   unsigned long long* stats = g_stats;
+  const size_t spill_k = (size_t)P.blocks_k * TB * (MAX_STACK4 - LDS_STACK);
   k_zero_words<<<std::min(4096u, cdiv(acc_bytes / 4, 256)), 256, 0, st>>>((uint32_t*)acc,
                                                                           acc_bytes / 4);
-  for (int64_t g0 = 0; g0 < total; g0 += C) {
-    const uint32_t n = (uint32_t)std::min<int64_t>(C, total - g0);
-    const unsigned gb = std::min<unsigned>(blocks, cdiv(n, TB));
-    k_reset<<<1, 256, 0, st>>>(ws.q, n);
-    prof_begin(KID_GENERATE, st);
-    k_generate<<<cdiv(n, 256), 256, 0, st>>>(d_jobs, nj, g0, n, ws.rays[0], ws.beta, ws.L,
-                                             ws.aux);
-    prof_end(KID_GENERATE, st);
-    for (int b = 0; b <= max_depth; ++b) {
-      float4* rin = ws.rays[b & 1];
-      float4* rout = ws.rays[(b + 1) & 1];
-      prof_begin(KID_EXTEND, st);
-      if (count)
-        k_extend<true><<<gb, TB, 0, st>>>(d_jobs, b, dyn, rin, ws.q, ws.hits, ws.spill, stats);
-      else
-        k_extend<false><<<gb, TB, 0, st>>>(d_jobs, b, dyn, rin, ws.q, ws.hits, ws.spill, stats);
-      prof_end(KID_EXTEND, st);
-      prof_begin(KID_SHADE, st);
-      k_shade<<<gb, 256, 0, st>>>(d_jobs, g0, b, rin, ws.hits, ws.q, rout, ws.shadow,
-                                  ws.beta, ws.L, ws.aux);
-      prof_end(KID_SHADE, st);
-      if (b < max_depth) {
-        prof_begin(KID_SHADOW, st);
+  if (P.K > 1) MRS_TRY_HIP(hipEventRecord(ws.ev_fork, st));
+  for (int64_t g0 = 0; g0 < total; g0 += P.K * P.Cs) {
+    int used = 0;
+    int64_t lo_k[MAX_SUB];
+    uint32_t n_k[MAX_SUB];
+    for (int k = 0; k < P.K; ++k) {
+      const int64_t lo = g0 + k * P.Cs;
+      if (lo >= total) break;
+      const uint32_t n = (uint32_t)std::min<int64_t>(P.Cs, total - lo);
+      lo_k[k] = lo;
+      n_k[k] = n;
+      used = k + 1;
+      hipStream_t sk = P.K > 1 ? g_sub[k] : st;
+      if (P.K > 1) MRS_TRY_HIP(hipStreamWaitEvent(sk, ws.ev_fork, 0));
+      // this sub-chunk's slice of the workspace
+      const size_t o = (size_t)k * P.Cs;
+      float4* rays[2] = {ws.rays[0] + 2 * o, ws.rays[1] + 2 * o};
+      float4* hits = ws.hits + o;
+      float4* shadow = ws.shadow + 3 * o;
+      float4* beta = ws.beta + o;
+      float4* L = ws.L + o;
+      float4* aux = ws.aux + 2 * o;
+      uint32_t* spill = ws.spill + k * spill_k;
+      uint32_t* q = ws.q + k * Q_WORDS;
+      const unsigned gb = std::min<unsigned>(P.blocks_k, cdiv(n, TB));
+      k_reset<<<1, 256, 0, sk>>>(q, n);
+      prof_begin(KID_GENERATE, sk);
+      k_generate<<<cdiv(n, 256), 256, 0, sk>>>(d_jobs, nj, lo, n, rays[0], beta, L, aux);
+      prof_end(KID_GENERATE, sk);
+      for (int b = 0; b <= max_depth; ++b) {
+        float4* rin = rays[b & 1];
+        float4* rout = rays[(b + 1) & 1];
+        prof_begin(KID_EXTEND, sk);
         if (count)
-          k_shadow<true><<<gb, TB, 0, st>>>(d_jobs, b, dyn, ws.shadow, ws.q, ws.L, ws.spill,
-                                            stats);
+          k_extend<true><<<gb, TB, 0, sk>>>(d_jobs, b, dyn, rin, q, hits, spill, stats);
         else
-          k_shadow<false><<<gb, TB, 0, st>>>(d_jobs, b, dyn, ws.shadow, ws.q, ws.L, ws.spill,
-                                             stats);
-        prof_end(KID_SHADOW, st);
+          k_extend<false><<<gb, TB, 0, sk>>>(d_jobs, b, dyn, rin, q, hits, spill, stats);
+        prof_end(KID_EXTEND, sk);
+        prof_begin(KID_SHADE, sk);
+        k_shade<<<gb, 256, 0, sk>>>(d_jobs, lo, b, rin, hits, q, rout, shadow, beta, L, aux);
+        prof_end(KID_SHADE, sk);
+        if (b < max_depth) {
+          prof_begin(KID_SHADOW, sk);
+          if (count)
+            k_shadow<true><<<gb, TB, 0, sk>>>(d_jobs, b, dyn, shadow, q, L, spill, stats);
+          else
+            k_shadow<false><<<gb, TB, 0, sk>>>(d_jobs, b, dyn, shadow, q, L, spill, stats);
+          prof_end(KID_SHADOW, sk);
+        }
+      }
+      if (P.K > 1) {
+        MRS_TRY_HIP(hipEventRecord(ws.ev_join[k], sk));
+        MRS_TRY_HIP(hipStreamWaitEvent(st, ws.ev_join[k], 0));
       }
     }
-    // pixels of the jobs this chunk overlaps
-    int jlo = 0, jhi = nj - 1;
-    while (jlo < nj - 1 && jobs[jlo + 1].first <= g0) ++jlo;
-    while (jhi > 0 && jobs[jhi].first >= g0 + (int64_t)n) --jhi;
-    const int64_t pix_lo = jobs[jlo].pix_first;
-    const int64_t pix_hi = jobs[jhi].pix_first + (int64_t)jobs[jhi].ww * jobs[jhi].wh;
-    prof_begin(KID_ACCUMULATE, st);
-    k_accumulate<<<cdiv((size_t)(pix_hi - pix_lo), 256), 256, 0, st>>>(
-        d_jobs, nj, g0, n, pix_lo, pix_hi, ws.L, ws.aux, acc, stats);
-    prof_end(KID_ACCUMULATE, st);
-    k_tally<<<1, 64, 0, st>>>(ws.q, max_depth + 1, stats, n);
+    // per-pixel sums in sample order: sub-chunks in path order, on the caller's stream
+    for (int k = 0; k < used; ++k) {
+      const int64_t lo = lo_k[k];
+      const uint32_t n = n_k[k];
+      const size_t o = (size_t)k * P.Cs;
+      int jlo = 0, jhi = nj - 1;
+      while (jlo < nj - 1 && jobs[jlo + 1].first <= lo) ++jlo;
+      while (jhi > 0 && jobs[jhi].first >= lo + (int64_t)n) --jhi;
+      const int64_t pix_lo = jobs[jlo].pix_first;
+      const int64_t pix_hi = jobs[jhi].pix_first + (int64_t)jobs[jhi].ww * jobs[jhi].wh;
+      prof_begin(KID_ACCUMULATE, st);
+      k_accumulate<<<cdiv((size_t)(pix_hi - pix_lo), 256), 256, 0, st>>>(
+          d_jobs, nj, lo, n, pix_lo, pix_hi, ws.L + o, ws.aux + 2 * o, acc, stats);
+      prof_end(KID_ACCUMULATE, st);
+      k_tally<<<1, 64, 0, st>>>(ws.q + k * Q_WORDS, max_depth + 1, stats, n);
+    }
+    // the next super-chunk reuses the slices once these sums have read them
+    if (P.K > 1) MRS_TRY_HIP(hipEventRecord(ws.ev_fork, st));
   }
   prof_begin(KID_RESOLVE, st);
   k_resolve<<<cdiv((size_t)total_pix, 256), 256, 0, st>>>(d_jobs, nj, total_pix, acc);
@@ -1125,8 +1209,7 @@ mrs_status render(const mrs_scene* s, const RenderArgs& a, hipStream_t st) {
   const int64_t npix = (int64_t)a.ww * a.wh;
   const mrs_tuning tu = tuning_snapshot();
   Workspace& ws = *stream_workspace(st);
-  mrs_status rc = ws_ensure(ws, std::min<int64_t>(tu.chunk_paths, npix * a.spp),
-                            tu.trace_blocks * TB);
+  mrs_status rc = ws_ensure_plan(ws, make_plan(tu, npix * a.spp));
   if (rc != MRS_OK) return rc;
   const size_t ab = acc_bytes_of(npix, a.fp64);
   if ((rc = ws_ensure_acc(ws, ab)) != MRS_OK) return rc;
@@ -1178,8 +1261,7 @@ mrs_status batch_create(const std::vector<DevJob>& jobs, mrs_batch** out) {
     off += acc_bytes_of(npix, J.fp64 != 0);
   }
   b->acc_bytes = off;
-  mrs_status rc = ws_ensure(b->ws, (size_t)std::min<int64_t>(b->tune.chunk_paths, first),
-                            b->tune.trace_blocks * TB);
+  mrs_status rc = ws_ensure_plan(b->ws, make_plan(b->tune, first));
   if (rc == MRS_OK && (hipMalloc(&b->d_jobs, sizeof(DevJob) * b->jobs.size()) != hipSuccess ||
                        hipMalloc(&b->d_acc, b->acc_bytes) != hipSuccess)) {
     (void)hipGetLastError();
@@ -1233,7 +1315,7 @@ mrs_status debug_closest_hit(const mrs_scene* s, int32_t n, const float* o, cons
   if (n <= 0) return MRS_OK;
   const unsigned blocks = std::min(cdiv((size_t)n, TB), 1024u);
   Workspace& ws = *stream_workspace(st);
-  mrs_status rc = ws_ensure(ws, 1, (int)(blocks * TB));
+  mrs_status rc = ws_ensure(ws, 1, (int)(blocks * TB), 0);
   if (rc != MRS_OK) return rc;
   k_debug_hit<<<blocks, TB, 0, st>>>(s->view, n, o, d, skip, t, prim, b, ws.spill);
   MRS_TRY_HIP(hipGetLastError());
@@ -1275,6 +1357,8 @@ mrs_status set_tuning(const mrs_tuning* t) {
     return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_set_tuning: schedule must be 0 or 1");
   if (t->bvh_leaf_max < 1 || t->bvh_leaf_max > LEAF4_MAX)
     return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_set_tuning: bvh_leaf_max must be in [1, 4]");
+  if (t->streams < 1 || t->streams > MAX_SUB)
+    return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_set_tuning: streams must be in [1, 4]");
   std::lock_guard<std::mutex> lk(g_mu);
   g_tune = *t;
   return MRS_OK;

@@ -138,7 +138,7 @@ def profile_read():
     return {names[i]: (float(ms[i]), int(n[i])) for i in range(L.NUM_KERNEL_IDS) if n[i]}
 
 
-TUNING_KEYS = ("chunk_paths", "trace_blocks", "schedule", "bvh_leaf_max")
+TUNING_KEYS = ("chunk_paths", "trace_blocks", "schedule", "bvh_leaf_max", "streams")
 
 
 def get_tuning():
@@ -147,10 +147,11 @@ def get_tuning():
     return {k: int(getattr(t, k)) for k in TUNING_KEYS}
 
 
-def set_tuning(chunk_paths=None, trace_blocks=None, schedule=None, bvh_leaf_max=None):
+def set_tuning(chunk_paths=None, trace_blocks=None, schedule=None, bvh_leaf_max=None,
+               streams=None):
     cur = get_tuning()
     new = dict(chunk_paths=chunk_paths, trace_blocks=trace_blocks, schedule=schedule,
-               bvh_leaf_max=bvh_leaf_max)
+               bvh_leaf_max=bvh_leaf_max, streams=streams)
     t = L.Tuning()
     for k in TUNING_KEYS:
         setattr(t, k, int(new[k] if new[k] is not None else cur[k]))
