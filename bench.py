@@ -126,9 +126,11 @@ def pmc_summary(fetch_path, write_path, out_path):
         "# (max depth 8) + fusion network.",
         "# Made by (each pass its own process, run from the repository root):",
         "#   rocprofv3 --pmc FETCH_SIZE -f csv -d gpurun_out/pmc_fetch -o pmc -- python bench.py "
-        "--steps 1 --warmup 0 --no-cpu-baseline --equal-psnr-scenes 0 --copy-calibration",
+        "--steps 1 --warmup 0 --no-cpu-baseline --equal-psnr-scenes 0 --batch-scenes 0 "
+        "--copy-calibration",
         "#   rocprofv3 --pmc WRITE_SIZE -f csv -d gpurun_out/pmc_write -o pmc -- python bench.py "
-        "--steps 1 --warmup 0 --no-cpu-baseline --equal-psnr-scenes 0 --copy-calibration",
+        "--steps 1 --warmup 0 --no-cpu-baseline --equal-psnr-scenes 0 --batch-scenes 0 "
+        "--copy-calibration",
         "#   python bench.py --pmc-summary gpurun_out/pmc_fetch gpurun_out/pmc_write",
         "# Counters are KiB per dispatch; each is scaled by COPY_BYTES over what the same counter",
         "# reads for a plain 1 GiB device copy in the same process.",
@@ -143,6 +145,41 @@ def pmc_summary(fetch_path, write_path, out_path):
         f"hbm_bytes_per_launch = {hbm:.0f}",
         f"kernel_source_sha256_16 = {kernel_source_hash()}",
     ]
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+STATS_SUMMARY = os.path.join(ROOT, "profiles", "hybrid_frame_procedural101k_720p_kernel_stats.txt")
+STATS_CMD = ("rocprofv3 --kernel-trace --stats -f csv -d gpurun_out/prof -o bench -- python -u "
+             "bench.py --steps 5 --warmup 1 --no-cpu-baseline --equal-psnr-scenes 0 --batch-scenes 0")
+
+
+def stats_summary(prof_dir, out_path):
+    """Short text form of a rocprofv3 --stats run (kernel, calls, total, average, share)."""
+    import csv
+    import glob
+    import re
+    paths = glob.glob(os.path.join(prof_dir, "**", "*kernel_stats.csv"), recursive=True)
+    if not paths:
+        raise SystemExit(f"stats summary: no kernel_stats.csv under {prof_dir}")
+    rows = list(csv.DictReader(open(paths[0])))
+
+    def short(n):
+        n = n.replace("mrs::(anonymous namespace)::", "").replace("void ", "")
+        m = re.match(r"([\w:]+(<[^>]*>)?)", n)
+        return m.group(1) if m else n[:40]
+
+    lines = ["# 720p hybrid frame (procedural 101,446 triangles, textured; HRLS 1280x720@4 + LRHS "
+             "320x180@64 as one two-job batch, depth 8; BF16 fusion network): 1 counting frame "
+             "(k_*<true>) + 1 warmup + 5 timed frames + 6 frames as two render calls",
+             f"# command (from the repository root): {STATS_CMD}",
+             "#   then: python bench.py --stats-summary gpurun_out/prof",
+             "# rocprofv3 kernel stats: name | calls | total ms | average us | percent", ""]
+    for r in rows:
+        lines.append(f"{short(r['Name']):34s} | {int(r['Calls']):5d} | "
+                     f"{int(r['TotalDurationNs']) / 1e6:9.3f} | {float(r['AverageNs']) / 1e3:10.2f} | "
+                     f"{float(r['Percentage']):6.2f}")
     with open(out_path, "w") as f:
         f.write("\n".join(lines) + "\n")
     print("\n".join(lines))
@@ -341,9 +378,14 @@ def main():
                     help="tuning: concurrent sub-chunks per render (1..4)")
     ap.add_argument("--leaf-max", type=int, default=None,
                     help="BVH build: triangles a BVH4 leaf may group (1..4)")
+    ap.add_argument("--stats-summary", metavar="PROF_DIR",
+                    help="summarise a rocprofv3 --stats run into the profiles/ kernel-stats file")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="summarise two rocprofv3 --pmc runs into the profiles/ traffic file")
     args = ap.parse_args()
+    if args.stats_summary:
+        stats_summary(args.stats_summary, STATS_SUMMARY)
+        return
     if args.pmc_summary:
         pmc_summary(args.pmc_summary[0], args.pmc_summary[1], TRAFFIC_SUMMARY)
         return

@@ -1,7 +1,8 @@
 """The hybrid multi-resolution frame and the learned part around it.
 
-* hybrid_frame: HRLS (W x H, 4 spp, features) + LRHS (W/4 x H/4, 64 spp) +
-  fusion network -> I_SR (paper Sec. 4), each step a libmrs call.
+* hybrid_frame / HybridFrame: HRLS (W x H, 4 spp, features) + LRHS (W/4 x H/4,
+  64 spp) + fusion network -> I_SR (paper Sec. 4), each step a libmrs call
+  (HybridFrame renders both as one batch).
 * build_dataset / train: training pairs rendered by the tracer itself
   (HRLS/LRHS windows against 1024-spp FP64-accumulated targets) and Adam on the
   L1 loss (libmrs mrs_train_step).
@@ -49,7 +50,56 @@ def render_inputs(gs, W, H, seed, spp_h=4, spp_l=64, depth=DEPTH, window=None):
     return hr_rgb, hr_aux, lr_rgb
 
 
-def hybrid_frame(gs, net: FusionNet, W, H, seed, spp_h=4, spp_l=64, depth=DEPTH, out=None):
+def fallback_spp(spp_h=4, spp_l=64):
+    """spp of the plain render that traces as many paths as the hybrid frame."""
+    return max(1, spp_h + spp_l // (SCALE * SCALE))
+
+
+class HybridFrame:
+    """Reusable hybrid frame of one scene: HRLS and LRHS rendered as one two-job batch
+    (one wavefront over both renders), then fused.  Buffers and the batch are made
+    once; render(seed) takes seeds 2 seed and 2 seed + 1 as hybrid_frame does.
+    Without a ready network (None, or no parameters) the frame falls back to a plain
+    render with the same number of paths (fallback_spp), seed 2 seed."""
+
+    def __init__(self, gs, net: FusionNet | None, W, H, spp_h=4, spp_l=64, depth=DEPTH):
+        self.net = net
+        self.out = _empty((H, W, 3))
+        self.fallback = net is None or not net.ready
+        if self.fallback:
+            self.batch = T.Batch([dict(scene=gs, W=W, H=H, spp=fallback_spp(spp_h, spp_l),
+                                       max_depth=depth, seed=0, out_rgb=self.out,
+                                       want_aux=False)])
+            return
+        self.hr_rgb, self.hr_aux = _empty((H, W, 3)), _empty((H, W, 7))
+        self.lr_rgb = _empty((H // SCALE, W // SCALE, 3))
+        self.batch = T.Batch([
+            dict(scene=gs, W=W, H=H, spp=spp_h, max_depth=depth, seed=0, out_rgb=self.hr_rgb,
+                 out_aux=self.hr_aux),
+            dict(scene=gs, W=W // SCALE, H=H // SCALE, spp=spp_l, max_depth=depth, seed=1,
+                 out_rgb=self.lr_rgb, want_aux=False)])
+
+    def render(self, seed):
+        if self.fallback:
+            self.batch.set_seeds([2 * seed])
+            self.batch.render()
+            return self.out
+        self.batch.set_seeds([2 * seed, 2 * seed + 1])
+        self.batch.render()
+        return self.net.fuse(self.hr_rgb, self.hr_aux, self.lr_rgb, out=self.out)
+
+    def close(self):
+        self.batch.close()
+
+
+def hybrid_frame(gs, net: FusionNet | None, W, H, seed, spp_h=4, spp_l=64, depth=DEPTH,
+                 out=None):
+    """One hybrid frame by separate calls; a plain render (fallback_spp, seed 2 seed)
+    when the network is missing or has no parameters."""
+    if net is None or not net.ready:
+        out = _empty((H, W, 3)) if out is None else out
+        T.render_ex(gs, W, H, fallback_spp(spp_h, spp_l), depth, 2 * seed, out, None)
+        return out, None
     hr_rgb, hr_aux, lr_rgb = render_inputs(gs, W, H, seed, spp_h, spp_l, depth)
     out = net.fuse(hr_rgb, hr_aux, lr_rgb, out=out)
     return out, (hr_rgb, hr_aux, lr_rgb)
@@ -168,12 +218,12 @@ def evaluate_scene(gs, net, W=1280, H=720, seed=0, plain_spp=(4, 8, 16, 32, 64, 
     """PSNR/time of the hybrid frame, its baselines and plain renders for one scene."""
     import torch
     ref = reference(gs, W, H, ref_spp, REF_SEED + seed)
-    out = _empty((H, W, 3))
     res = {}
-    t_h = time_ms(lambda: hybrid_frame(gs, net, W, H, seed, out=out), reps)
-    hybrid_frame(gs, net, W, H, seed, out=out)
+    frame = HybridFrame(gs, net, W, H)
+    t_h = time_ms(lambda: frame.render(seed), reps)
+    out = frame.render(seed)
     res["hybrid"] = {"psnr": image_metrics(out, ref)["psnr"], "ms": t_h}
-    hr_rgb, hr_aux, lr_rgb = render_inputs(gs, W, H, seed)
+    hr_rgb, hr_aux, lr_rgb = frame.hr_rgb, frame.hr_aux, frame.lr_rgb
     up = torch.nn.functional.interpolate(lr_rgb.permute(2, 0, 1)[None], scale_factor=SCALE,
                                          mode="bilinear", align_corners=False)[0].permute(1, 2, 0)
     res["hrls_4spp"] = {"psnr": image_metrics(hr_rgb, ref)["psnr"]}
@@ -188,6 +238,7 @@ def evaluate_scene(gs, net, W=1280, H=720, seed=0, plain_spp=(4, 8, 16, 32, 64, 
     eq = equal_psnr(res["hybrid"]["psnr"], plain)
     res["equal_psnr"] = None if eq is None else {"spp": eq[0], "ms": eq[1],
                                                  "ratio": t_h / eq[1]}
+    frame.close()
     return res
 
 

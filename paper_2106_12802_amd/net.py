@@ -18,17 +18,20 @@ class FusionNet:
         L.check(L.lib().mrs_net_create(C.byref(h)))
         self.handle = h
         self.num_params = int(L.lib().mrs_net_num_params())
+        self.ready = False  # parameters loaded (mrs_fuse refuses to run before)
         if seed is not None:
             self.init(seed)
 
     def init(self, seed: int):
         L.use_current_stream()
         L.check(L.lib().mrs_net_init(self.handle, C.c_uint64(int(seed))))
+        self.ready = True
 
     def set_params(self, params):
         p = np.ascontiguousarray(params, np.float32)
         L.use_current_stream()
         L.check(L.lib().mrs_net_set_params(self.handle, p.ctypes.data_as(C.c_void_p), p.size))
+        self.ready = True
 
     def get_params(self) -> np.ndarray:
         p = np.empty(self.num_params, np.float32)
@@ -104,6 +107,7 @@ class FusionNet:
         L.use_current_stream()
         L.check(L.lib().mrs_net_set_state(self.handle, *[a.ctypes.data_as(C.c_void_p) for a in arrs],
                                           self.num_params, int(step)))
+        self.ready = True
 
     def save(self, path):
         """Checkpoint file: versioned header, FP32 params, Adam m and v, step, checksum."""

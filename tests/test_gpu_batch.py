@@ -191,3 +191,53 @@ def test_full_size_render_invariant_to_tuning(torch_cuda):
             assert torch.equal(img, ref) and torch.equal(aux, raux), tune
     finally:
         mrs.set_tuning(**old)
+
+
+def test_hybrid_frame_batch_equals_separate_calls(torch_cuda):
+    """HybridFrame (HRLS + LRHS as one batch, reseeded per frame) gives bitwise the
+    frame of hybrid_frame (two render calls), for several seeds, also in a graph."""
+    import paper_2106_12802_amd as mrs
+    from paper_2106_12802_amd import hybrid as HY
+    torch = torch_cuda
+    gs = mrs.GpuScene(S.procedural(7, spheres=((2, 4),), n_boxes=5, n_lights=2))
+    net = mrs.FusionNet(seed=4)
+    W, H = 320, 192
+    fr = HY.HybridFrame(gs, net, W, H)
+    for seed in (3, 11):
+        a = fr.render(seed).clone()
+        b, _ = HY.hybrid_frame(gs, net, W, H, seed, out=torch.empty(H, W, 3, device="cuda"))
+        torch.cuda.synchronize()
+        assert torch.equal(a, b), seed
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        fr.render(7)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        fr.render(7)
+    ref, _ = HY.hybrid_frame(gs, net, W, H, 7, out=torch.empty(H, W, 3, device="cuda"))
+    for _ in range(3):
+        fr.out.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(fr.out, ref)
+        fr.render(12)  # eager work between replays (its own seeds)
+        torch.cuda.synchronize()
+    fr.close()
+
+
+def test_fallback_without_network_is_plain_render(torch_cuda):
+    import paper_2106_12802_amd as mrs
+    from paper_2106_12802_amd import hybrid as HY
+    torch = torch_cuda
+    gs = mrs.GpuScene(S.cornell(2))
+    empty = mrs.FusionNet()  # no parameters
+    plain, _ = mrs.render(gs, 64, 48, HY.fallback_spp(), HY.DEPTH, 2 * 9, want_aux=False)
+    for net in (None, empty):
+        a, _ = HY.hybrid_frame(gs, net, 64, 48, 9)
+        fr = HY.HybridFrame(gs, net, 64, 48)
+        b = fr.render(9)
+        torch.cuda.synchronize()
+        assert torch.equal(a, plain) and torch.equal(b, plain)
+        fr.close()
