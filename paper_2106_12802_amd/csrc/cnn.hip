@@ -112,21 +112,174 @@ __device__ __forceinline__ void conv_mainloop(const ConvArgs& p, int M, int m0, 
     for (int j = 0; j < NT; ++j) acc[r][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   const int cpt = p.cin_p >> 3;  // 8-channel chunks per tap
   const uint16_t* wrow = p.w + (size_t)(n0 + li) * p.kp + kq * 8;
-  for (int ks = 0; ks < p.kp; ks += 32) {
+  // Operands of K step ks; the next step's loads are issued before this step's
+  // MFMAs so that their latency overlaps the matrix work.
+  auto load_step = [&](int ks, bf16x8 (&A)[2], bf16x8 (&Bv)[NT]) {
     const int q = (ks >> 3) + kq;
     const int tap = q / cpt;
     const int c = (q - tap * cpt) << 3;
-    bf16x8 A[2];
 #pragma unroll
     for (int r = 0; r < 2; ++r) A[r] = pv[r] ? load_chunk(p, pb[r], py[r], px[r], tap, c) : zero8();
-    bf16x8 Bv[NT];
 #pragma unroll
     for (int j = 0; j < NT; ++j) Bv[j] = ld8(wrow + (size_t)j * 16 * p.kp + ks);
+  };
+  bf16x8 A[2], Bv[NT];
+  load_step(0, A, Bv);
+  for (int ks = 0; ks < p.kp; ks += 32) {
+    bf16x8 An[2], Bn[NT];
+    if (ks + 32 < p.kp) load_step(ks + 32, An, Bn);
 #pragma unroll
     for (int r = 0; r < 2; ++r)
 #pragma unroll
       for (int j = 0; j < NT; ++j)
         acc[r][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[r], Bv[j], acc[r][j], 0, 0, 0);
+#pragma unroll
+    for (int r = 0; r < 2; ++r) A[r] = An[r];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) Bv[j] = Bn[j];
+  }
+}
+
+// Epilogue of a wave's 32 x (16 NT) tile: bias, ReLU, residuals, FP32 and/or
+// BF16 stores.  m[r][v] is the output pixel of accumulator row v of row tile r
+// (-1: outside the image).  Every load (bias, residuals) is issued before the
+// first store: the output pointers may alias nothing, but the compiler cannot
+// know that, and interleaving would serialise one memory latency per element.
+template <int NT>
+__device__ __forceinline__ void conv_epilogue(const ConvArgs& p, const f32x4 (&acc)[2][NT],
+                                              const int64_t (&m)[2][4], int n0, int li) {
+  float bias[NT];
+  bool nv[NT];
+#pragma unroll
+  for (int j = 0; j < NT; ++j) {
+    const int n = n0 + j * 16 + li;
+    nv[j] = n < p.cout;
+    bias[j] = nv[j] ? p.bias[n] : 0.0f;
+  }
+  float y[2][NT][4];
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int j = 0; j < NT; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        float t = acc[r][j][v] + bias[j];
+        y[r][j][v] = p.relu ? fmaxf(t, 0.0f) : t;
+      }
+  if (p.res) {
+    float rv[2][NT][4];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int j = 0; j < NT; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          rv[r][j][v] = (m[r][v] >= 0 && nv[j])
+                            ? p.res[(size_t)m[r][v] * p.cout + n0 + j * 16 + li] : 0.0f;
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int j = 0; j < NT; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) y[r][j][v] = rv[r][j][v] + p.res_scale * y[r][j][v];
+  }
+  if (p.res2) {
+    float rv[2][NT][4];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int j = 0; j < NT; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          rv[r][j][v] = (m[r][v] >= 0 && nv[j])
+                            ? p.res2[(size_t)m[r][v] * p.cout + n0 + j * 16 + li] : 0.0f;
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int j = 0; j < NT; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) y[r][j][v] += rv[r][j][v];
+  }
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int j = 0; j < NT; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        if (m[r][v] < 0 || !nv[j]) continue;
+        const int n = n0 + j * 16 + li;
+        if (p.out_f) p.out_f[(size_t)m[r][v] * p.out_f_stride + n] = y[r][j][v];
+        if (p.out_h) p.out_h[(size_t)m[r][v] * p.out_h_stride + n] = f2bf(y[r][j][v]);
+      }
+}
+
+// 3x3 convolution of a plain 64-channel NHWC input, operands staged in LDS
+// (gfx950 gives a workgroup up to 160 KB).  A block of 8 waves owns a 16 x 16
+// pixel tile of one image: the (16+2) x (16+2) x 64 input tile with its zero
+// halo (46 KB) and the 576 x 64 BF16 weights of one 64-channel output group
+// (72 KB) are loaded once, coalesced; then every MFMA operand comes from LDS.
+// Wave w computes image rows 2w and 2w+1 of the tile (two 16-pixel row tiles)
+// x 64 channels with v_mfma_f32_16x16x32_bf16.  LDS layouts are chosen for
+// conflict-free 16-byte reads: tile pixels padded to 72 channels (a 36-bank
+// stride), weights chunk-major [k / 8][n][8].
+constexpr int C3_T = 16, C3_CIN = 64, C3_K = 9 * C3_CIN;
+constexpr int C3_PITCH = C3_CIN + 8;
+constexpr int C3_TILE = (C3_T + 2) * (C3_T + 2);
+constexpr int C3_THREADS = 512;
+
+__global__ __launch_bounds__(C3_THREADS) void k_conv3_lds(ConvArgs p, int cout_p) {
+  __shared__ __attribute__((aligned(16))) uint16_t tile[C3_TILE * C3_PITCH];
+  __shared__ __attribute__((aligned(16))) uint16_t wts[C3_K * 64];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int kq = lane >> 4, li = lane & 15;
+  const int x0 = blockIdx.x * C3_T, y0 = blockIdx.y * C3_T, b = blockIdx.z;
+  for (int i = tid; i < C3_TILE * (C3_CIN / 8); i += C3_THREADS) {
+    const int px = i >> 3, ch = (i & 7) * 8;
+    const int ty = px / (C3_T + 2), tx = px - ty * (C3_T + 2);
+    const int gy = y0 - 1 + ty, gx = x0 - 1 + tx;
+    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+    if (gy >= 0 && gy < p.H && gx >= 0 && gx < p.W)
+      v = *reinterpret_cast<const uint4*>(p.a + ((size_t)(b * p.H + gy) * p.W + gx) * C3_CIN + ch);
+    *reinterpret_cast<uint4*>(tile + px * C3_PITCH + ch) = v;
+  }
+  for (int n0 = 0; n0 < cout_p; n0 += 64) {
+    if (n0 > 0) __syncthreads();  // the previous group's weights are no longer read
+    for (int i = tid; i < 64 * (C3_K / 8); i += C3_THREADS) {
+      const int n = i / (C3_K / 8), kc = i - n * (C3_K / 8);
+      *reinterpret_cast<uint4*>(wts + (kc * 64 + n) * 8) =
+          *reinterpret_cast<const uint4*>(p.w + (size_t)(n0 + n) * p.kp + kc * 8);
+    }
+    __syncthreads();
+    f32x4 acc[2][4];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[r][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int ks = 0; ks < C3_K; ks += 32) {
+      const int tap = ks / C3_CIN, c = ks - tap * C3_CIN + kq * 8;
+      const int dy = tap / 3, dx = tap - dy * 3;
+      bf16x8 A[2], Bv[4];
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+        A[r] = ld8(tile + ((2 * wave + r + dy) * (C3_T + 2) + li + dx) * C3_PITCH + c);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) Bv[j] = ld8(wts + (((ks >> 3) + kq) * 64 + j * 16 + li) * 8);
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[r][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[r], Bv[j], acc[r][j], 0, 0, 0);
+    }
+    int64_t m[2][4];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int y = y0 + 2 * wave + r, x = x0 + kq * 4 + v;
+        m[r][v] = (y < p.H && x < p.W) ? ((int64_t)b * p.H + y) * p.W + x : -1;
+      }
+    conv_epilogue<4>(p, acc, m, n0, li);
   }
 }
 
@@ -141,26 +294,15 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs p) {
   f32x4 acc[2][NT];
   conv_mainloop<NT>(p, M, m0, n0, lane, acc);
   const int kq = lane >> 4, li = lane & 15;
+  int64_t m[2][4];
 #pragma unroll
-  for (int r = 0; r < 2; ++r) {
+  for (int r = 0; r < 2; ++r)
 #pragma unroll
-    for (int j = 0; j < NT; ++j) {
-      const int n = n0 + j * 16 + li;
-      if (n >= p.cout) continue;
-      const float bias = p.bias[n];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int m = m0 + r * 16 + kq * 4 + v;
-        if (m >= M) continue;
-        float y = acc[r][j][v] + bias;
-        if (p.relu) y = fmaxf(y, 0.0f);
-        if (p.res) y = p.res[(size_t)m * p.cout + n] + p.res_scale * y;
-        if (p.res2) y += p.res2[(size_t)m * p.cout + n];
-        if (p.out_f) p.out_f[(size_t)m * p.out_f_stride + n] = y;
-        if (p.out_h) p.out_h[(size_t)m * p.out_h_stride + n] = f2bf(y);
-      }
+    for (int v = 0; v < 4; ++v) {
+      const int mm = m0 + r * 16 + kq * 4 + v;
+      m[r][v] = mm < M ? mm : -1;
     }
-  }
+  conv_epilogue<NT>(p, acc, m, n0, li);
 }
 
 // Data gradient of a conv: the same implicit GEMM over dY with the packed
@@ -529,6 +671,11 @@ void launch_adam(float* w, const float* g, float* m, float* v, int64_t n, float 
 }
 
 void launch_conv(const ConvArgs& a, int cout_p, hipStream_t st) {
+  if (a.mode == VIEW_PLAIN && a.taps == 9 && a.cin_p == C3_CIN && a.ca == C3_CIN &&
+      a.kp == C3_K && cout_p % 64 == 0) {
+    k_conv3_lds<<<dim3(cdiv64(a.W, C3_T), cdiv64(a.H, C3_T), a.B), C3_THREADS, 0, st>>>(a, cout_p);
+    return;
+  }
   const int64_t M = (int64_t)a.B * a.H * a.W;
   const unsigned gx = cdiv64(M, 128);
   if (cout_p >= 64) {
