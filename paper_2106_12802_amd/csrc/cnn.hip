@@ -53,13 +53,9 @@ __device__ __forceinline__ bf16x8 ld8(const uint16_t* p) {
 }
 
 // 8 consecutive input channels [c, c+8) of tap `tap` around output pixel (b,y,x).
-__device__ __forceinline__ bf16x8 load_chunk(const ConvArgs& p, int b, int y, int x, int tap,
-                                             int c) {
-  if (tap >= p.taps) return zero8();
-  if (p.taps == 9) {
-    y += tap / 3 - 1;
-    x += tap % 3 - 1;
-  }
+// 8 consecutive channels [c, c+8) of the conv input at pixel (b, y, x) through
+// the view (zero outside the image).
+__device__ __forceinline__ bf16x8 view_chunk(const ConvArgs& p, int b, int y, int x, int c) {
   if (y < 0 || y >= p.H || x < 0 || x >= p.W) return zero8();
   const uint16_t* ptr;
   switch (p.mode) {
@@ -87,6 +83,16 @@ __device__ __forceinline__ bf16x8 load_chunk(const ConvArgs& p, int b, int y, in
       break;
   }
   return ld8(ptr);
+}
+
+__device__ __forceinline__ bf16x8 load_chunk(const ConvArgs& p, int b, int y, int x, int tap,
+                                             int c) {
+  if (tap >= p.taps) return zero8();
+  if (p.taps == 9) {
+    y += tap / 3 - 1;
+    x += tap % 3 - 1;
+  }
+  return view_chunk(p, b, y, x, c);
 }
 
 // Accumulates the 32 x (16 NT) output tile of one wave over the whole K.
@@ -213,62 +219,65 @@ __device__ __forceinline__ void conv_epilogue(const ConvArgs& p, const f32x4 (&a
       }
 }
 
-// 3x3 convolution of a plain 64-channel NHWC input, operands staged in LDS
-// (gfx950 gives a workgroup up to 160 KB).  A block of 8 waves owns a 16 x 16
-// pixel tile of one image: the (16+2) x (16+2) x 64 input tile with its zero
-// halo (46 KB) and the 576 x 64 BF16 weights of one 64-channel output group
-// (72 KB) are loaded once, coalesced; then every MFMA operand comes from LDS.
-// Wave w computes image rows 2w and 2w+1 of the tile (two 16-pixel row tiles)
-// x 64 channels with v_mfma_f32_16x16x32_bf16.  LDS layouts are chosen for
-// conflict-free 16-byte reads: tile pixels padded to 72 channels (a 36-bank
-// stride), weights chunk-major [k / 8][n][8].
-constexpr int C3_T = 16, C3_CIN = 64, C3_K = 9 * C3_CIN;
-constexpr int C3_PITCH = C3_CIN + 8;
+// 3x3 convolution with its operands staged in LDS (gfx950 gives a workgroup up
+// to 160 KB).  A block of 8 waves owns a 16 x 16 pixel tile of one image: the
+// (16+2) x (16+2) x CINP input tile with its zero halo is gathered once through
+// the conv's input view (plain, or shuffle+concat for the reconstruction conv),
+// and the weights of one group of 16 NT output channels (K x 16 NT BF16) are
+// loaded once per group; then every MFMA operand comes from LDS.  Wave w
+// computes image rows 2w and 2w+1 of the tile (two 16-pixel row tiles) x 16 NT
+// channels with v_mfma_f32_16x16x32_bf16; K index k = tap CINP + c as in the
+// packed weights, so with CINP < 32 one K step spans two taps.  LDS layouts are
+// chosen for conflict-free 16-byte reads: tile pixels padded by 8 channels,
+// weights chunk-major [k / 8][n][8].
+constexpr int C3_T = 16, C3_THREADS = 512;
 constexpr int C3_TILE = (C3_T + 2) * (C3_T + 2);
-constexpr int C3_THREADS = 512;
 
+template <int CINP, int NT>
 __global__ __launch_bounds__(C3_THREADS) void k_conv3_lds(ConvArgs p, int cout_p) {
-  __shared__ __attribute__((aligned(16))) uint16_t tile[C3_TILE * C3_PITCH];
-  __shared__ __attribute__((aligned(16))) uint16_t wts[C3_K * 64];
+  constexpr int PITCH = CINP + 8;
+  constexpr int KP = (9 * CINP + 31) / 32 * 32;
+  constexpr int NG = 16 * NT;
+  __shared__ __attribute__((aligned(16))) uint16_t tile[C3_TILE * PITCH];
+  __shared__ __attribute__((aligned(16))) uint16_t wts[KP * NG];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int kq = lane >> 4, li = lane & 15;
   const int x0 = blockIdx.x * C3_T, y0 = blockIdx.y * C3_T, b = blockIdx.z;
-  for (int i = tid; i < C3_TILE * (C3_CIN / 8); i += C3_THREADS) {
-    const int px = i >> 3, ch = (i & 7) * 8;
+  for (int i = tid; i < C3_TILE * (CINP / 8); i += C3_THREADS) {
+    const int px = i / (CINP / 8), c = (i - px * (CINP / 8)) * 8;
     const int ty = px / (C3_T + 2), tx = px - ty * (C3_T + 2);
-    const int gy = y0 - 1 + ty, gx = x0 - 1 + tx;
-    uint4 v = make_uint4(0u, 0u, 0u, 0u);
-    if (gy >= 0 && gy < p.H && gx >= 0 && gx < p.W)
-      v = *reinterpret_cast<const uint4*>(p.a + ((size_t)(b * p.H + gy) * p.W + gx) * C3_CIN + ch);
-    *reinterpret_cast<uint4*>(tile + px * C3_PITCH + ch) = v;
+    const bf16x8 v = view_chunk(p, b, y0 - 1 + ty, x0 - 1 + tx, c);
+    *reinterpret_cast<bf16x8*>(tile + px * PITCH + c) = v;
   }
-  for (int n0 = 0; n0 < cout_p; n0 += 64) {
+  for (int n0 = 0; n0 < cout_p; n0 += NG) {
     if (n0 > 0) __syncthreads();  // the previous group's weights are no longer read
-    for (int i = tid; i < 64 * (C3_K / 8); i += C3_THREADS) {
-      const int n = i / (C3_K / 8), kc = i - n * (C3_K / 8);
-      *reinterpret_cast<uint4*>(wts + (kc * 64 + n) * 8) =
+    for (int i = tid; i < NG * (KP / 8); i += C3_THREADS) {
+      const int n = i / (KP / 8), kc = i - n * (KP / 8);
+      *reinterpret_cast<uint4*>(wts + (kc * NG + n) * 8) =
           *reinterpret_cast<const uint4*>(p.w + (size_t)(n0 + n) * p.kp + kc * 8);
     }
     __syncthreads();
-    f32x4 acc[2][4];
+    f32x4 acc[2][NT];
 #pragma unroll
     for (int r = 0; r < 2; ++r)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc[r][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int ks = 0; ks < C3_K; ks += 32) {
-      const int tap = ks / C3_CIN, c = ks - tap * C3_CIN + kq * 8;
+      for (int j = 0; j < NT; ++j) acc[r][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int ks = 0; ks < KP; ks += 32) {
+      const int k = ks + kq * 8;
+      const int tap = k / CINP, c = k - tap * CINP;
       const int dy = tap / 3, dx = tap - dy * 3;
-      bf16x8 A[2], Bv[4];
+      bf16x8 A[2], Bv[NT];
 #pragma unroll
       for (int r = 0; r < 2; ++r)
-        A[r] = ld8(tile + ((2 * wave + r + dy) * (C3_T + 2) + li + dx) * C3_PITCH + c);
+        A[r] = tap < 9 ? ld8(tile + ((2 * wave + r + dy) * (C3_T + 2) + li + dx) * PITCH + c)
+                       : zero8();
 #pragma unroll
-      for (int j = 0; j < 4; ++j) Bv[j] = ld8(wts + (((ks >> 3) + kq) * 64 + j * 16 + li) * 8);
+      for (int j = 0; j < NT; ++j) Bv[j] = ld8(wts + (((ks >> 3) + kq) * NG + j * 16 + li) * 8);
 #pragma unroll
       for (int r = 0; r < 2; ++r)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < NT; ++j)
           acc[r][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[r], Bv[j], acc[r][j], 0, 0, 0);
     }
     int64_t m[2][4];
@@ -279,8 +288,17 @@ __global__ __launch_bounds__(C3_THREADS) void k_conv3_lds(ConvArgs p, int cout_p
         const int y = y0 + 2 * wave + r, x = x0 + kq * 4 + v;
         m[r][v] = (y < p.H && x < p.W) ? ((int64_t)b * p.H + y) * p.W + x : -1;
       }
-    conv_epilogue<4>(p, acc, m, n0, li);
+    conv_epilogue<NT>(p, acc, m, n0, li);
   }
+}
+
+template <int CINP, int NT>
+bool try_conv3_lds(const ConvArgs& a, int cout_p, hipStream_t st) {
+  constexpr int KP = (9 * CINP + 31) / 32 * 32;
+  if (a.cin_p != CINP || a.kp != KP || cout_p % (16 * NT)) return false;
+  k_conv3_lds<CINP, NT><<<dim3((a.W + C3_T - 1) / C3_T, (a.H + C3_T - 1) / C3_T, a.B),
+                          C3_THREADS, 0, st>>>(a, cout_p);
+  return true;
 }
 
 template <int NT>
@@ -671,10 +689,12 @@ void launch_adam(float* w, const float* g, float* m, float* v, int64_t n, float 
 }
 
 void launch_conv(const ConvArgs& a, int cout_p, hipStream_t st) {
-  if (a.mode == VIEW_PLAIN && a.taps == 9 && a.cin_p == C3_CIN && a.ca == C3_CIN &&
-      a.kp == C3_K && cout_p % 64 == 0) {
-    k_conv3_lds<<<dim3(cdiv64(a.W, C3_T), cdiv64(a.H, C3_T), a.B), C3_THREADS, 0, st>>>(a, cout_p);
-    return;
+  if (a.taps == 9 && a.mode != VIEW_CONCAT_UNSHUFFLE &&
+      (a.mode != VIEW_PLAIN || a.ca == a.cin_p)) {
+    if (cout_p >= 64 ? (try_conv3_lds<64, 4>(a, cout_p, st) || try_conv3_lds<16, 4>(a, cout_p, st) ||
+                        try_conv3_lds<8, 4>(a, cout_p, st))
+                     : try_conv3_lds<80, 1>(a, cout_p, st))
+      return;
   }
   const int64_t M = (int64_t)a.B * a.H * a.W;
   const unsigned gx = cdiv64(M, 128);
