@@ -3,7 +3,7 @@
 //
 // A chunk of paths -- contiguous (sample, pixel) pairs -- is advanced one
 // bounce at a time by separate kernels:
-//   generate   camera rays, path state init                    (per path)
+//   generate   camera rays (the path state starts at its first shade) (per path)
 //   extend     closest-hit LBVH traversal, LDS short stack      (per live ray)
 //   shade      emission, first-hit features, next-event estimation sample,
 //              BSDF sample, Russian roulette; appends the surviving rays and
@@ -392,10 +392,7 @@ __global__ __launch_bounds__(256) void k_reset(uint32_t* q, uint32_t n) {
 
 __global__ __launch_bounds__(256) void k_generate(const DevJob* __restrict__ jobs, int njobs,
                                                   int64_t g0, uint32_t n,
-                                                  float4* __restrict__ rays,
-                                                  float4* __restrict__ beta,
-                                                  float4* __restrict__ L,
-                                                  float4* __restrict__ aux) {
+                                                  float4* __restrict__ rays) {
   const uint32_t slot = blockIdx.x * 256 + threadIdx.x;
   if (slot >= n) return;
   const int64_t g = g0 + slot;
@@ -416,10 +413,6 @@ __global__ __launch_bounds__(256) void k_generate(const DevJob* __restrict__ job
   const f3 d = normalize(f + rr * cx + vv * cy);
   rays[2 * slot] = make_float4(sc.cam_px, sc.cam_py, sc.cam_pz, __uint_as_float(slot));
   rays[2 * slot + 1] = make_float4(d.x, d.y, d.z, __uint_as_float((j << 24) | PRIM24));
-  beta[slot] = make_float4(1.0f, 1.0f, 1.0f, __uint_as_float(j));
-  L[slot] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-  aux[2 * slot] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-  aux[2 * slot + 1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 }
 
 // Queue entries of a traversal wave, 64 at a time.  Static schedule: the
@@ -559,10 +552,16 @@ __global__ __launch_bounds__(256) void k_shade(const DevJob* __restrict__ jobs, 
       const f3 o = xyz(R0), d = xyz(R1);
       const float4 Hh = hits[qi];
       prim = __float_as_uint(Hh.y);
-      f3 beta = xyz(beta_buf[slot]);
-      f3 L = xyz(L_buf[slot]);
+      // a path starts with beta = 1, L = 0 and zero features (nothing is stored
+      // for it before its first vertex)
+      f3 beta = b == 0 ? F3(1.0f, 1.0f, 1.0f) : xyz(beta_buf[slot]);
+      f3 L = b == 0 ? F3(0.0f, 0.0f, 0.0f) : xyz(L_buf[slot]);
       if (prim == NO_PRIM) {
         L = L + mul(beta, F3(sc.env_r, sc.env_g, sc.env_b));
+        if (b == 0) {
+          aux_buf[2 * slot] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+          aux_buf[2 * slot + 1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        }
       } else {
         const float t = Hh.x, b1 = Hh.z, b2 = Hh.w;
         const float4 NG = sc.prim_ng[prim];
@@ -1121,7 +1120,7 @@ mrs_status launch_batch(Workspace& ws, const mrs_tuning& tu, const DevJob* d_job
       const unsigned gb = std::min<unsigned>(P.blocks_k, cdiv(n, TB));
       k_reset<<<1, 256, 0, sk>>>(q, n);
       prof_begin(KID_GENERATE, sk);
-      k_generate<<<cdiv(n, 256), 256, 0, sk>>>(d_jobs, nj, lo, n, rays[0], beta, L, aux);
+      k_generate<<<cdiv(n, 256), 256, 0, sk>>>(d_jobs, nj, lo, n, rays[0]);
       prof_end(KID_GENERATE, sk);
       for (int b = 0; b <= max_depth; ++b) {
         float4* rin = rays[b & 1];
