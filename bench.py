@@ -376,6 +376,8 @@ def main():
                     help="tuning: traversal queue schedule (0 grid-stride, 1 dynamic)")
     ap.add_argument("--streams", type=int, default=None,
                     help="tuning: concurrent sub-chunks per render (1..4)")
+    ap.add_argument("--tail-bounce", type=int, default=None,
+                    help="tuning: first bounce traced path by path in one launch (65: never)")
     ap.add_argument("--leaf-max", type=int, default=None,
                     help="BVH build: triangles a BVH4 leaf may group (1..4)")
     ap.add_argument("--stats-summary", metavar="PROF_DIR",
@@ -404,7 +406,8 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_calibration:
         copy_calibration()
-    R.set_tuning(args.chunk_paths, args.trace_blocks, args.schedule, args.leaf_max, args.streams)
+    R.set_tuning(args.chunk_paths, args.trace_blocks, args.schedule, args.leaf_max, args.streams,
+                 args.tail_bounce)
     tuning = R.get_tuning()
     log(f"[bench] tuning {tuning}")
     scene = S.procedural(SCENE_SEED)

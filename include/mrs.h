@@ -205,9 +205,13 @@ mrs_status mrs_release_workspaces(void);
  * [3] traversal stack entries spilled from LDS to global memory,
  * [4] paths started, [5] stack overflows (must be 0),
  * [6] closest-hit node visits, [7] closest-hit triangle tests,
- * [8] shadow node visits, [9] shadow triangle tests
- * ([6]..[9] only while work counting is on, see mrs_set_count_work). */
-#define MRS_NUM_COUNTERS 12
+ * [8] shadow node visits, [9] shadow triangle tests,
+ * [10] / [11] most node visits + triangle tests of one closest-hit / shadow ray,
+ * [12] / [13] closest-hit / shadow rays traced by the path-tail kernel (also
+ * included in [1] / [2]), [14] / [15] its node visits / triangle tests
+ * ([6]..[11], [14], [15] only while work counting is on, see
+ * mrs_set_count_work; [6]..[9] cover the wavefront kernels only). */
+#define MRS_NUM_COUNTERS 16
 mrs_status mrs_get_counters(int64_t out[MRS_NUM_COUNTERS], int32_t reset);
 
 /* Work counting: while on, traversal kernels also count node visits and
@@ -219,7 +223,8 @@ mrs_status mrs_set_count_work(int32_t on);
  * 0 generate, 1 extend (closest hit), 2 shade, 3 shadow (any hit),
  * 4 accumulate, 5 resolve, 6 network input preparation, 7 network HR input conv,
  * 8 network LR convs (lrhs, fuse, trunk, up), 9 network HR output conv,
- * 10 training forward, 11 training backward, 12 Adam + weight refresh, 13..15 reserved.
+ * 10 training forward, 11 training backward, 12 Adam + weight refresh,
+ * 13 path tail (bounces from mrs_tuning.tail_bounce on), 14..15 reserved.
  * mrs_profile_enable(1) clears the totals and starts recording;
  * mrs_profile_read synchronises and returns, per id, the summed milliseconds
  * and the launch count of the launches recorded so far. */
@@ -240,6 +245,8 @@ typedef struct mrs_tuning {
                            this many sub-chunks, traced concurrently on internal
                            streams shared by the library (joined back into the
                            caller's stream before the per-pixel sums) */
+  int32_t tail_bounce;  /* 1..65 (default 3): bounces from this one on are traced
+                           path by path in one launch (65: never) */
 } mrs_tuning;
 mrs_status mrs_get_tuning(mrs_tuning* out);
 mrs_status mrs_set_tuning(const mrs_tuning* t);

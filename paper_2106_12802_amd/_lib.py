@@ -18,10 +18,10 @@ LIB_PATH = os.path.join(HERE, "libmrs.so")
 MRS_OK = 0
 STATUS_NAMES = {0: "OK", 1: "INVALID_ARGUMENT", 2: "OUT_OF_MEMORY", 3: "DEVICE", 4: "NOT_READY",
                 5: "UNSUPPORTED"}
-NUM_COUNTERS = 12
+NUM_COUNTERS = 16
 NUM_KERNEL_IDS = 16
 KERNEL_NAMES = ["generate", "extend", "shade", "shadow", "accumulate", "resolve", "cnn_prep",
-                "cnn_hr_in", "cnn_lr", "cnn_hr_out", "train_fwd", "train_bwd", "train_adam"]
+                "cnn_hr_in", "cnn_lr", "cnn_hr_out", "train_fwd", "train_bwd", "train_adam", "tail"]
 
 
 class MrsError(RuntimeError):
@@ -67,7 +67,7 @@ class Job(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("chunk_paths", C.c_int32), ("trace_blocks", C.c_int32), ("schedule", C.c_int32),
-                ("bvh_leaf_max", C.c_int32), ("streams", C.c_int32)]
+                ("bvh_leaf_max", C.c_int32), ("streams", C.c_int32), ("tail_bounce", C.c_int32)]
 
 
 assert C.sizeof(Material) == 32 and C.sizeof(QuadLight) == 56

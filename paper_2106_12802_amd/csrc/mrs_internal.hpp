@@ -173,6 +173,7 @@ enum KernelId {
   KID_TRAIN_FWD = 10,
   KID_TRAIN_BWD = 11,
   KID_TRAIN_ADAM = 12,
+  KID_TAIL = 13,
 };
 void prof_begin(int id, hipStream_t st);
 void prof_end(int id, hipStream_t st);

@@ -118,12 +118,11 @@ struct TraceView {
 };
 
 // Moller-Trumbore against one leaf; edges inclusive, t > 0, three excluded
-// primitives.  ANY: accept any t < ts.t (shadow rays).  Otherwise accept a
+// primitives.  any: accept any t < ts.t (shadow rays).  Otherwise accept a
 // closer hit, or an equal t with a smaller primitive id.
-template <bool ANY>
 __device__ __forceinline__ bool isect_leaf(const gfloat4* __restrict__ leaf_tri, uint32_t leaf,
                                            f3 o, f3 d, uint32_t x0, uint32_t x1, uint32_t x2,
-                                           TraceState& ts) {
+                                           bool any, TraceState& ts) {
   const float4 A = ld4(leaf_tri + 3 * leaf), B = ld4(leaf_tri + 3 * leaf + 1),
                C = ld4(leaf_tri + 3 * leaf + 2);
   const uint32_t prim = __float_as_uint(A.w);
@@ -138,7 +137,7 @@ __device__ __forceinline__ bool isect_leaf(const gfloat4* __restrict__ leaf_tri,
   const float t = dot(e2, qv) * inv;
   bool ok = det != 0.0f && u >= 0.0f && v >= 0.0f && u + v <= 1.0f && t > 0.0f && prim != x0 &&
             prim != x1 && prim != x2;
-  if (ANY) {
+  if (any) {
     ok = ok && t < ts.t;
   } else {
     ok = ok && (t < ts.t || (t == ts.t && prim < ts.prim));
@@ -179,6 +178,7 @@ struct Stack {
 
 struct WorkCount {
   uint32_t visits = 0, tests = 0;
+  uint32_t ray_steps = 0, max_steps = 0;  // node visits + triangle tests of the current / worst ray
 };
 
 __device__ __forceinline__ void cswap(float& ta, uint32_t& ra, float& tb, uint32_t& rb) {
@@ -208,7 +208,10 @@ struct RayIn {
   f3 o, d;
   uint32_t x0, x1, x2;  // excluded primitives
   float tmax;           // shadow rays: distance to the light point; else infinity
+  bool any;             // any hit (shadow ray) rather than the closest hit
 };
+
+enum TraceMode { CLOSEST = 0, ANY_HIT = 1, PER_RAY = 2 };
 
 // Streaming four-wide BVH traversal.  Each lane walks its own sequence of
 // queue entries first, first + stride, ... < n and starts its next ray as soon
@@ -218,12 +221,14 @@ struct RayIn {
 // until every active lane of the wave has a leaf, then the wave intersects the
 // parked leaves together.  A ray's visiting order thus depends on the rays
 // sharing its wave; the result does not, because box culling is conservative
-// (see slab).  Children are visited nearest first for closest hits (sorting
-// network on the entry distances); shadow rays (ANY) take them in any order
-// and stop at the first occluder.  IO supplies load(qi, RayIn&) and
-// store(qi, const TraceState&, bool occluded).  COUNT adds node visits and
-// triangle tests to wc (a separate instantiation).
-template <bool ANY, bool COUNT, class IO>
+// (see slab).  Children are visited nearest first (sorting network on the
+// entry distances); shadow rays stop at the first occluder.  MODE fixes the
+// ray kind (CLOSEST, ANY_HIT) or takes it from each ray (PER_RAY).  IO supplies
+// load(qi, RayIn&) and store(qi, const TraceState&, bool occluded, RayIn& next)
+// -> bool: true when the lane goes on with `next` for the same queue entry
+// (the next segment of a path), false to move to its next entry.  COUNT adds
+// node visits and triangle tests to wc (a separate instantiation).
+template <int MODE, bool COUNT, class IO>
 __device__ void trace_stream(IO& io, uint32_t first, uint32_t stride, uint32_t n, Stack& st,
                              WorkCount& wc) {
   uint32_t qi = first;
@@ -234,8 +239,7 @@ __device__ void trace_stream(IO& io, uint32_t first, uint32_t stride, uint32_t n
   uint32_t node = EMPTY4, leaf = EMPTY4;  // next reference to visit; parked leaf
   int32_t budget = 0;
   bool occluded = false;
-  auto start = [&]() {
-    io.load(qi, r);
+  auto begin = [&]() {
     ts = TraceState{r.tmax, NO_PRIM, 0.0f, 0.0f};
     inv = F3(safe_rcp(r.d.x), safe_rcp(r.d.y), safe_rcp(r.d.z));
     oi = mul(r.o, inv);
@@ -249,8 +253,12 @@ __device__ void trace_stream(IO& io, uint32_t first, uint32_t stride, uint32_t n
       else node = r.sc.root;
     }
   };
-  if (live) start();
+  if (live) {
+    io.load(qi, r);
+    begin();
+  }
   while (live) {
+    const bool any = MODE == PER_RAY ? r.any : MODE == ANY_HIT;
     // ---- internal nodes (EMPTY4 has the leaf bit set)
     while (!(node & LEAF_BIT) && --budget > 0) {
       if (node >= r.sc.nnodes) {  // keeps a corrupt reference harmless
@@ -261,7 +269,10 @@ __device__ void trace_stream(IO& io, uint32_t first, uint32_t stride, uint32_t n
       const float4 lx = ld4(nd), ly = ld4(nd + 1), lz = ld4(nd + 2);
       const float4 hx = ld4(nd + 3), hy = ld4(nd + 4), hz = ld4(nd + 5);
       const float4 rf = ld4(nd + 6);
-      if (COUNT) ++wc.visits;
+      if (COUNT) {
+        ++wc.visits;
+        ++wc.ray_steps;
+      }
       float t0, t1, t2, t3;
       uint32_t r0 = __float_as_uint(rf.x), r1 = __float_as_uint(rf.y), r2 = __float_as_uint(rf.z),
                r3 = __float_as_uint(rf.w);
@@ -286,7 +297,7 @@ __device__ void trace_stream(IO& io, uint32_t first, uint32_t stride, uint32_t n
       cswap(t2, r2, t3, r3);
       cswap(t0, r0, t2, r2);
       cswap(t1, r1, t3, r3);
-      if (!ANY) cswap(t1, r1, t2, r2);
+      if (MODE != ANY_HIT) cswap(t1, r1, t2, r2);
       if (r3 != EMPTY4) st.push(r3);
       if (r2 != EMPTY4) st.push(r2);
       if (r1 != EMPTY4) st.push(r1);
@@ -302,8 +313,11 @@ __device__ void trace_stream(IO& io, uint32_t first, uint32_t stride, uint32_t n
       const uint32_t f = leaf & 0x00ffffffu, cnt = ((leaf >> 24) & 3u) + 1u;
       if (f + cnt <= (uint32_t)r.sc.ntris) {  // keeps a corrupt reference harmless
         for (uint32_t k = 0; k < cnt; ++k) {
-          if (COUNT) ++wc.tests;
-          if (isect_leaf<ANY>(r.sc.leaf_tri, f + k, r.o, r.d, r.x0, r.x1, r.x2, ts) && ANY) {
+          if (COUNT) {
+            ++wc.tests;
+            ++wc.ray_steps;
+          }
+          if (isect_leaf(r.sc.leaf_tri, f + k, r.o, r.d, r.x0, r.x1, r.x2, any, ts) && any) {
             occluded = true;
             break;
           }
@@ -314,17 +328,26 @@ __device__ void trace_stream(IO& io, uint32_t first, uint32_t stride, uint32_t n
         node = EMPTY4;
         break;
       }
-      if ((node & LEAF_BIT) && node != EMPTY4 && leaf == EMPTY4) {
+      if ((node & LEAF_BIT) && node != EMPTY4) {
         leaf = node;
         node = st.sp ? st.pop() : EMPTY4;
       }
-      if (__all(leaf != EMPTY4)) break;
     }
     if ((node == EMPTY4 && leaf == EMPTY4) || budget <= 0) {  // ray finished
-      io.store(qi, ts, occluded);
-      qi += stride;
-      live = qi < n;
-      if (live) start();
+      if (COUNT) {
+        wc.max_steps = max(wc.max_steps, wc.ray_steps);
+        wc.ray_steps = 0;
+      }
+      if (io.store(qi, ts, occluded, r)) {
+        begin();
+      } else {
+        qi += stride;
+        live = qi < n;
+        if (live) {
+          io.load(qi, r);
+          begin();
+        }
+      }
     }
   }
 }
@@ -448,24 +471,26 @@ struct ExtendIO {
     r.x0 = unpack_prim(tag);
     r.x1 = r.x2 = NO_PRIM;
     r.tmax = INFINITY;
+    r.any = false;
   }
-  __device__ __forceinline__ void store(uint32_t qi, const TraceState& ts, bool) const {
+  __device__ __forceinline__ bool store(uint32_t qi, const TraceState& ts, bool, RayIn&) const {
     hits[qi] = make_float4(ts.t, __uint_as_float(ts.prim), ts.b1, ts.b2);
+    return false;
   }
 };
 
 // Static schedule: lane sequences gtid, gtid + threads, ...  Dynamic: a wave
 // takes 64 consecutive entries per fetch from a device counter.
-template <bool ANY, bool COUNT, class IO>
+template <int MODE, bool COUNT, class IO>
 __device__ __forceinline__ void trace_queue(IO& io, uint32_t n, int dyn, uint32_t* fetch,
                                             Stack& st, WorkCount& wc) {
   if (!dyn) {
-    trace_stream<ANY, COUNT>(io, blockIdx.x * TB + threadIdx.x, gridDim.x * TB, n, st, wc);
+    trace_stream<MODE, COUNT>(io, blockIdx.x * TB + threadIdx.x, gridDim.x * TB, n, st, wc);
     return;
   }
   WaveQueue wq(fetch, true);
   for (; wq.base < n; wq.next())
-    trace_stream<ANY, COUNT>(io, wq.base + __lane_id(), 64u, min(n, wq.base + 64u), st, wc);
+    trace_stream<MODE, COUNT>(io, wq.base + __lane_id(), 64u, min(n, wq.base + 64u), st, wc);
 }
 
 template <bool COUNT>
@@ -481,11 +506,12 @@ __global__ __launch_bounds__(TB) void k_extend(const DevJob* __restrict__ jobs, 
   Stack st{stk + threadIdx.x, spill + gtid, gridDim.x * TB, 0, 0u, false};
   WorkCount wc;
   ExtendIO io{jobs, rays, hits};
-  trace_queue<false, COUNT>(io, n, dyn, q + Q_FETCH_EXT + b, st, wc);
+  trace_queue<CLOSEST, COUNT>(io, n, dyn, q + Q_FETCH_EXT + b, st, wc);
   if (st.spills) atomicAdd(stats + 3, (unsigned long long)st.spills);
   if (st.overflow) atomicAdd(stats + 5, 1ull);
   if (COUNT && wc.visits) atomicAdd(stats + 6, (unsigned long long)wc.visits);
   if (COUNT && wc.tests) atomicAdd(stats + 7, (unsigned long long)wc.tests);
+  if (COUNT && wc.max_steps) atomicMax(stats + 10, (unsigned long long)wc.max_steps);
 }
 
 __device__ __forceinline__ void onb(f3 n, f3& T, f3& B) {
@@ -525,6 +551,142 @@ __device__ __forceinline__ f3 ggx_eval(f3 f0, float alpha, f3 n, f3 wo, f3 wi, f
 }
 
 
+// The shading of one path vertex (estimator steps E5-E11): emission, the first-hit
+// features (b = 0), next-event estimation sample, BSDF sample and Russian
+// roulette.  Shared by the wavefront shade kernel and the path-tail kernel, so
+// both perform the same arithmetic in the same order.
+struct Vertex {
+  f3 beta, L;    // throughput and radiance after this vertex's emission
+  bool cont;     // the path continues from x along wi
+  bool shad;     // a shadow ray from x along swi, length sr, carries c if unoccluded
+  f3 x, wi, swi, c;
+  float sr;
+  uint32_t li, prim;
+};
+
+__device__ __forceinline__ void shade_vertex(const DevJob& J, int64_t g, int b, f3 o, f3 d,
+                                             float4 Hh, f3 beta, f3 L, float4* aux2, Vertex& v) {
+  const SceneView& sc = J.sv;
+  const uint32_t prim = __float_as_uint(Hh.y);
+  v.cont = false;
+  v.shad = false;
+  v.prim = prim;
+  v.li = 0;
+  v.x = v.wi = v.swi = v.c = F3(0.0f, 0.0f, 0.0f);
+  v.sr = 0.0f;
+  if (prim == NO_PRIM) {
+    L = L + mul(beta, F3(sc.env_r, sc.env_g, sc.env_b));
+    if (aux2) {
+      aux2[0] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      aux2[1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
+    v.beta = beta;
+    v.L = L;
+    return;
+  }
+  const float t = Hh.x, b1 = Hh.z, b2 = Hh.w;
+  const float4 NG = sc.prim_ng[prim];
+  const uint32_t info = __float_as_uint(NG.w);
+  f3 ng = xyz(NG);
+  f3 ns = ng;
+  if (info & PRIM_SMOOTH) {
+    const f3 n0 = xyz(sc.prim_n[3 * prim]), n1 = xyz(sc.prim_n[3 * prim + 1]),
+             n2 = xyz(sc.prim_n[3 * prim + 2]);
+    ns = normalize(n0 * (1.0f - b1 - b2) + n1 * b1 + n2 * b2);
+  }
+  f3 x = o + d * t;
+  const f3 wo = neg(d);
+  const bool front = dot(ng, wo) > 0.0f;
+  if (!front) {
+    ng = neg(ng);
+    ns = neg(ns);
+  }
+  // Rays leave from the hit point lifted along the arrival-side geometric
+  // normal by 2^-16 * max(1, |x|_inf): far above FP32 rounding of x, so
+  // neither this triangle nor its neighbours are hit again by rounding.
+  const float lift = ldexpf(fmaxf(1.0f, fmaxf(fabsf(x.x), fmaxf(fabsf(x.y), fabsf(x.z)))), -16);
+  x = x + ng * lift;
+  v.x = x;
+  const DevMaterial m = sc.mats[info & PRIM_MAT_MASK];
+  const int kind = (int)m.emis_kind.w;
+  const f3 col = xyz(m.color_alpha);
+  if (aux2) {
+    const f3 alb = kind == MRS_EMITTER ? F3(0, 0, 0) : col;
+    aux2[0] = make_float4(alb.x, alb.y, alb.z, ns.x);
+    aux2[1] = make_float4(ns.y, ns.z, t, 0.0f);
+  }
+  const f3 em = xyz(m.emis_kind);
+  if (front && (em.x != 0.0f || em.y != 0.0f || em.z != 0.0f) && (!(info & PRIM_LISTED) || b == 0))
+    L = L + mul(beta, em);
+  bool alive = b != J.max_depth && kind != MRS_EMITTER && dot(ns, wo) > 0.0f;
+  if (alive) {
+    uint32_t P, s;
+    path_pixel_sample(J, g, P, s);
+    const uint4 bl = philox4x32_10(make_uint4(P, s, 1u + 2u * b, 0u), J.seed_lo, J.seed_hi);
+    const uint4 bs = philox4x32_10(make_uint4(P, s, 2u + 2u * b, 0u), J.seed_lo, J.seed_hi);
+    const float alpha = m.color_alpha.w;
+    const float co = dot(ns, wo);
+    // next-event estimation: one light chosen uniformly, area sampling
+    if (sc.nlights > 0) {
+      const uint32_t li = (uint32_t)(((uint64_t)(bl.x >> 8) * (uint64_t)sc.nlights) >> 24);
+      const DevLight& lt = sc.lights[li];
+      const float u1 = unit24(bl.y), u2 = unit24(bl.z);
+      const f3 y = xyz(lt.corner) + xyz(lt.eu) * u1 + xyz(lt.ev) * u2;
+      const f3 dv = y - x;
+      const float r2 = dot(dv, dv);
+      const float r = sqrtf(r2);
+      const f3 w = dv * (1.0f / r);
+      const float cs = dot(ns, w), cg = dot(ng, w), cl = -dot(xyz(lt.normal), w);
+      v.li = li;
+      if (cs > 0.0f && cg > 0.0f && cl > 0.0f) {
+        const f3 f = kind == MRS_LAMBERT ? col * INV_PI : ggx_eval(col, alpha, ns, wo, w, cs, co);
+        const float geo = cs * cl * ((float)sc.nlights * lt.normal.w) / r2;
+        v.c = mul(mul(beta, f), xyz(lt.le)) * geo;
+        v.swi = w;
+        v.sr = r;
+        v.shad = true;
+      }
+    }
+    // BSDF sample
+    f3 T, B, wi;
+    onb(ns, T, B);
+    const float v1 = unit24(bs.x), v2 = unit24(bs.y);
+    float sp, cp;
+    sincospif(2.0f * v2, &sp, &cp);
+    if (kind == MRS_LAMBERT) {
+      const float rr = sqrtf(v1);
+      wi = T * (rr * cp) + B * (rr * sp) + ns * sqrtf(1.0f - v1);
+      if (dot(ng, wi) <= 0.0f) alive = false;
+      beta = mul(beta, col);
+    } else {
+      const float a2 = alpha * alpha;
+      const float den = 1.0f + (a2 - 1.0f) * v1;
+      const float cost = sqrtf((1.0f - v1) / den);
+      const float sint = sqrtf(a2 * v1 / den);
+      const f3 h = T * (sint * cp) + B * (sint * sp) + ns * cost;
+      const float oh = dot(wo, h);
+      wi = h * (2.0f * oh) - wo;
+      const float ci = dot(ns, wi);
+      if (ci <= 0.0f || dot(ng, wi) <= 0.0f) {
+        alive = false;
+      } else {
+        const float ch = dot(ns, h);
+        const float G = ggx_G1(a2, ci) * ggx_G1(a2, co);
+        beta = mul(beta, schlick(col, oh) * (G * oh / (co * ch)));
+      }
+    }
+    if (alive && b >= J.rr_start) {
+      const float qq = fminf(0.95f, maxc(beta));
+      if (!(unit24(bs.z) < qq)) alive = false;
+      else beta = beta * (1.0f / qq);
+    }
+    v.wi = wi;
+  }
+  v.cont = alive;
+  v.beta = beta;
+  v.L = L;
+}
+
 __global__ __launch_bounds__(256) void k_shade(const DevJob* __restrict__ jobs, int64_t g0, int b,
                                                const float4* __restrict__ rays_in,
                                                const float4* __restrict__ hits,
@@ -539,141 +701,32 @@ __global__ __launch_bounds__(256) void k_shade(const DevJob* __restrict__ jobs, 
   uint32_t* cnt_shadow = q + Q_SHADOW + b;
   for (uint32_t base = blockIdx.x * 256; base < n; base += gridDim.x * 256) {
     const uint32_t qi = base + threadIdx.x;
-    bool cont = false, shad = false;
-    uint32_t slot = 0, prim = NO_PRIM, li = 0, j = 0;
-    f3 x = F3(0, 0, 0), wi = F3(0, 0, 0), swi = F3(0, 0, 0), c = F3(0, 0, 0);
-    float sr = 0.0f;
+    Vertex v;
+    v.cont = v.shad = false;
+    uint32_t slot = 0, j = 0;
     if (qi < n) {
       const float4 R0 = rays_in[2 * qi], R1 = rays_in[2 * qi + 1];
       slot = __float_as_uint(R0.w);
       j = job_of(__float_as_uint(R1.w));
-      const DevJob& J = jobs[j];
-      const SceneView& sc = J.sv;
-      const f3 o = xyz(R0), d = xyz(R1);
-      const float4 Hh = hits[qi];
-      prim = __float_as_uint(Hh.y);
       // a path starts with beta = 1, L = 0 and zero features (nothing is stored
       // for it before its first vertex)
-      f3 beta = b == 0 ? F3(1.0f, 1.0f, 1.0f) : xyz(beta_buf[slot]);
-      f3 L = b == 0 ? F3(0.0f, 0.0f, 0.0f) : xyz(L_buf[slot]);
-      if (prim == NO_PRIM) {
-        L = L + mul(beta, F3(sc.env_r, sc.env_g, sc.env_b));
-        if (b == 0) {
-          aux_buf[2 * slot] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-          aux_buf[2 * slot + 1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        }
-      } else {
-        const float t = Hh.x, b1 = Hh.z, b2 = Hh.w;
-        const float4 NG = sc.prim_ng[prim];
-        const uint32_t info = __float_as_uint(NG.w);
-        f3 ng = xyz(NG);
-        f3 ns = ng;
-        if (info & PRIM_SMOOTH) {
-          const f3 n0 = xyz(sc.prim_n[3 * prim]), n1 = xyz(sc.prim_n[3 * prim + 1]),
-                   n2 = xyz(sc.prim_n[3 * prim + 2]);
-          ns = normalize(n0 * (1.0f - b1 - b2) + n1 * b1 + n2 * b2);
-        }
-        x = o + d * t;
-        const f3 wo = neg(d);
-        const bool front = dot(ng, wo) > 0.0f;
-        if (!front) {
-          ng = neg(ng);
-          ns = neg(ns);
-        }
-        // Rays leave from the hit point lifted along the arrival-side geometric
-        // normal by 2^-16 * max(1, |x|_inf): far above FP32 rounding of x, so
-        // neither this triangle nor its neighbours are hit again by rounding.
-        const float lift = ldexpf(fmaxf(1.0f, fmaxf(fabsf(x.x), fmaxf(fabsf(x.y), fabsf(x.z)))), -16);
-        x = x + ng * lift;
-        const DevMaterial m = sc.mats[info & PRIM_MAT_MASK];
-        const int kind = (int)m.emis_kind.w;
-        const f3 col = xyz(m.color_alpha);
-        if (b == 0) {
-          const f3 alb = kind == MRS_EMITTER ? F3(0, 0, 0) : col;
-          aux_buf[2 * slot] = make_float4(alb.x, alb.y, alb.z, ns.x);
-          aux_buf[2 * slot + 1] = make_float4(ns.y, ns.z, t, 0.0f);
-        }
-        const f3 em = xyz(m.emis_kind);
-        if (front && (em.x != 0.0f || em.y != 0.0f || em.z != 0.0f) &&
-            (!(info & PRIM_LISTED) || b == 0))
-          L = L + mul(beta, em);
-        bool alive = b != J.max_depth && kind != MRS_EMITTER && dot(ns, wo) > 0.0f;
-        if (alive) {
-          uint32_t P, s;
-          path_pixel_sample(J, g0 + slot, P, s);
-          const uint4 bl = philox4x32_10(make_uint4(P, s, 1u + 2u * b, 0u), J.seed_lo, J.seed_hi);
-          const uint4 bs = philox4x32_10(make_uint4(P, s, 2u + 2u * b, 0u), J.seed_lo, J.seed_hi);
-          const float alpha = m.color_alpha.w;
-          const float co = dot(ns, wo);
-          // next-event estimation: one light chosen uniformly, area sampling
-          if (sc.nlights > 0) {
-            li = (uint32_t)(((uint64_t)(bl.x >> 8) * (uint64_t)sc.nlights) >> 24);
-            const DevLight& lt = sc.lights[li];
-            const float u1 = unit24(bl.y), u2 = unit24(bl.z);
-            const f3 y = xyz(lt.corner) + xyz(lt.eu) * u1 + xyz(lt.ev) * u2;
-            const f3 dv = y - x;
-            const float r2 = dot(dv, dv);
-            const float r = sqrtf(r2);
-            const f3 w = dv * (1.0f / r);
-            const float cs = dot(ns, w), cg = dot(ng, w), cl = -dot(xyz(lt.normal), w);
-            if (cs > 0.0f && cg > 0.0f && cl > 0.0f) {
-              const f3 f = kind == MRS_LAMBERT ? col * INV_PI : ggx_eval(col, alpha, ns, wo, w, cs, co);
-              const float geo = cs * cl * ((float)sc.nlights * lt.normal.w) / r2;
-              c = mul(mul(beta, f), xyz(lt.le)) * geo;
-              swi = w;
-              sr = r;
-              shad = true;
-            }
-          }
-          // BSDF sample
-          f3 T, B;
-          onb(ns, T, B);
-          const float v1 = unit24(bs.x), v2 = unit24(bs.y);
-          float sp, cp;
-          sincospif(2.0f * v2, &sp, &cp);
-          if (kind == MRS_LAMBERT) {
-            const float rr = sqrtf(v1);
-            wi = T * (rr * cp) + B * (rr * sp) + ns * sqrtf(1.0f - v1);
-            if (dot(ng, wi) <= 0.0f) alive = false;
-            beta = mul(beta, col);
-          } else {
-            const float a2 = alpha * alpha;
-            const float den = 1.0f + (a2 - 1.0f) * v1;
-            const float cost = sqrtf((1.0f - v1) / den);
-            const float sint = sqrtf(a2 * v1 / den);
-            const f3 h = T * (sint * cp) + B * (sint * sp) + ns * cost;
-            const float oh = dot(wo, h);
-            wi = h * (2.0f * oh) - wo;
-            const float ci = dot(ns, wi);
-            if (ci <= 0.0f || dot(ng, wi) <= 0.0f) {
-              alive = false;
-            } else {
-              const float ch = dot(ns, h);
-              const float G = ggx_G1(a2, ci) * ggx_G1(a2, co);
-              beta = mul(beta, schlick(col, oh) * (G * oh / (co * ch)));
-            }
-          }
-          if (alive && b >= J.rr_start) {
-            const float qq = fminf(0.95f, maxc(beta));
-            if (!(unit24(bs.z) < qq)) alive = false;
-            else beta = beta * (1.0f / qq);
-          }
-          beta_buf[slot] = make_float4(beta.x, beta.y, beta.z, __uint_as_float(j));
-        }
-        cont = alive;
-      }
-      L_buf[slot] = make_float4(L.x, L.y, L.z, 0.0f);
+      const f3 beta = b == 0 ? F3(1.0f, 1.0f, 1.0f) : xyz(beta_buf[slot]);
+      const f3 L = b == 0 ? F3(0.0f, 0.0f, 0.0f) : xyz(L_buf[slot]);
+      shade_vertex(jobs[j], g0 + slot, b, xyz(R0), xyz(R1), hits[qi], beta, L,
+                   b == 0 ? aux_buf + 2 * slot : nullptr, v);
+      if (v.cont) beta_buf[slot] = make_float4(v.beta.x, v.beta.y, v.beta.z, 0.0f);
+      L_buf[slot] = make_float4(v.L.x, v.L.y, v.L.z, 0.0f);
     }
-    const uint32_t ri = wave_append(cont, cnt_next);
-    if (cont) {
-      rays_out[2 * ri] = make_float4(x.x, x.y, x.z, __uint_as_float(slot));
-      rays_out[2 * ri + 1] = make_float4(wi.x, wi.y, wi.z, __uint_as_float((j << 24) | prim));
+    const uint32_t ri = wave_append(v.cont, cnt_next);
+    if (v.cont) {
+      rays_out[2 * ri] = make_float4(v.x.x, v.x.y, v.x.z, __uint_as_float(slot));
+      rays_out[2 * ri + 1] = make_float4(v.wi.x, v.wi.y, v.wi.z, __uint_as_float((j << 24) | v.prim));
     }
-    const uint32_t si = wave_append(shad, cnt_shadow);
-    if (shad) {
-      shadow[3 * si] = make_float4(x.x, x.y, x.z, __uint_as_float(slot | (li << 24)));
-      shadow[3 * si + 1] = make_float4(swi.x, swi.y, swi.z, sr);
-      shadow[3 * si + 2] = make_float4(c.x, c.y, c.z, __uint_as_float((j << 24) | prim));
+    const uint32_t si = wave_append(v.shad, cnt_shadow);
+    if (v.shad) {
+      shadow[3 * si] = make_float4(v.x.x, v.x.y, v.x.z, __uint_as_float(slot | (v.li << 24)));
+      shadow[3 * si + 1] = make_float4(v.swi.x, v.swi.y, v.swi.z, v.sr);
+      shadow[3 * si + 2] = make_float4(v.c.x, v.c.y, v.c.z, __uint_as_float((j << 24) | v.prim));
     }
   }
 }
@@ -695,10 +748,12 @@ struct ShadowIO {
     r.x1 = (uint32_t)lt.tri0;
     r.x2 = (uint32_t)lt.tri1;
     r.tmax = S1.w;
+    r.any = true;
   }
   // an unoccluded sample adds its contribution to its own path's radiance
-  __device__ __forceinline__ void store(uint32_t qi, const TraceState&, bool occluded) const {
-    if (occluded) return;
+  __device__ __forceinline__ bool store(uint32_t qi, const TraceState&, bool occluded,
+                                        RayIn&) const {
+    if (occluded) return false;
     const uint32_t slot = __float_as_uint(shadow[3 * qi].w) & 0xffffffu;
     const float4 S2 = shadow[3 * qi + 2];
     float4 Lv = L_buf[slot];
@@ -706,6 +761,7 @@ struct ShadowIO {
     Lv.y += S2.y;
     Lv.z += S2.z;
     L_buf[slot] = Lv;
+    return false;
   }
 };
 
@@ -722,11 +778,135 @@ __global__ __launch_bounds__(TB) void k_shadow(const DevJob* __restrict__ jobs, 
   Stack st{stk + threadIdx.x, spill + gtid, gridDim.x * TB, 0, 0u, false};
   WorkCount wc;
   ShadowIO io{jobs, shadow, L_buf};
-  trace_queue<true, COUNT>(io, n, dyn, q + Q_FETCH_SHD + b, st, wc);
+  trace_queue<ANY_HIT, COUNT>(io, n, dyn, q + Q_FETCH_SHD + b, st, wc);
   if (st.spills) atomicAdd(stats + 3, (unsigned long long)st.spills);
   if (st.overflow) atomicAdd(stats + 5, 1ull);
   if (COUNT && wc.visits) atomicAdd(stats + 8, (unsigned long long)wc.visits);
   if (COUNT && wc.tests) atomicAdd(stats + 9, (unsigned long long)wc.tests);
+  if (COUNT && wc.max_steps) atomicMax(stats + 11, (unsigned long long)wc.max_steps);
+}
+
+// Path tail: the paths still alive at bounce b0 are finished here one by one
+// (closest hit, shading, shadow ray, next segment, ...) in a single launch, so
+// that the last bounces -- few rays, each launch bounded below by its slowest
+// ray -- do not cost a launch sequence per bounce.  Each lane streams over the
+// queue like the traversal kernels and, when a segment ends, goes on with the
+// next segment of the same path.  The arithmetic is the wavefront's
+// (shade_vertex; L += c after an unoccluded shadow ray), so results are
+// bitwise those of the wavefront.
+struct PathIO {
+  const DevJob* __restrict__ jobs;
+  const float4* __restrict__ rays;
+  float4* __restrict__ beta_buf;
+  float4* __restrict__ L_buf;
+  int64_t g0;
+  int b0;
+  uint32_t nrays = 0, nshadow = 0;  // segments traced by this lane
+  // the lane's path
+  uint32_t slot, j;
+  int b;
+  f3 beta, L, c, o, d;
+  f3 next_o, next_d;
+  uint32_t next_prim;
+  bool cont, in_shadow;
+
+  __device__ __forceinline__ void closest(RayIn& r, f3 ro, f3 rd, uint32_t origin) {
+    r.sc = lane_view(jobs[j].sv);
+    r.o = o = ro;
+    r.d = d = rd;
+    r.x0 = origin;
+    r.x1 = r.x2 = NO_PRIM;
+    r.tmax = INFINITY;
+    r.any = false;
+    in_shadow = false;
+    ++nrays;
+  }
+  __device__ __forceinline__ void load(uint32_t qi, RayIn& r) {
+    const float4 R0 = rays[2 * qi], R1 = rays[2 * qi + 1];
+    const uint32_t tag = __float_as_uint(R1.w);
+    slot = __float_as_uint(R0.w);
+    j = job_of(tag);
+    b = b0;
+    beta = xyz(beta_buf[slot]);
+    L = xyz(L_buf[slot]);
+    closest(r, xyz(R0), xyz(R1), unpack_prim(tag));
+  }
+  __device__ __forceinline__ bool store(uint32_t, const TraceState& ts, bool occluded,
+                                        RayIn& r) {
+    if (!in_shadow) {
+      Vertex v;
+      shade_vertex(jobs[j], g0 + slot, b, o, d,
+                   make_float4(ts.t, __uint_as_float(ts.prim), ts.b1, ts.b2), beta, L, nullptr, v);
+      beta = v.beta;
+      L = v.L;
+      cont = v.cont;
+      next_o = v.x;
+      next_d = v.wi;
+      next_prim = v.prim;
+      if (v.shad) {
+        const DevLight& lt = jobs[j].sv.lights[v.li];
+        r.sc = lane_view(jobs[j].sv);
+        r.o = v.x;
+        r.d = v.swi;
+        r.x0 = v.prim;
+        r.x1 = (uint32_t)lt.tri0;
+        r.x2 = (uint32_t)lt.tri1;
+        r.tmax = v.sr;
+        r.any = true;
+        c = v.c;
+        in_shadow = true;
+        ++nshadow;
+        return true;
+      }
+    } else if (!occluded) {
+      L.x += c.x;
+      L.y += c.y;
+      L.z += c.z;
+    }
+    if (cont) {
+      ++b;
+      closest(r, next_o, next_d, next_prim);
+      return true;
+    }
+    L_buf[slot] = make_float4(L.x, L.y, L.z, 0.0f);
+    return false;
+  }
+};
+
+template <bool COUNT>
+__global__ __launch_bounds__(TB) void k_tail(const DevJob* __restrict__ jobs, int64_t g0, int b0,
+                                             const float4* __restrict__ rays,
+                                             const uint32_t* __restrict__ q,
+                                             float4* __restrict__ beta_buf,
+                                             float4* __restrict__ L_buf,
+                                             uint32_t* __restrict__ spill,
+                                             unsigned long long* __restrict__ stats) {
+  __shared__ uint32_t stk[LDS_STACK * TB];
+  const uint32_t n = q[Q_RAYS + b0];
+  const uint32_t gtid = blockIdx.x * TB + threadIdx.x;
+  Stack st{stk + threadIdx.x, spill + gtid, gridDim.x * TB, 0, 0u, false};
+  WorkCount wc;
+  PathIO io;
+  io.jobs = jobs;
+  io.rays = rays;
+  io.beta_buf = beta_buf;
+  io.L_buf = L_buf;
+  io.g0 = g0;
+  io.b0 = b0;
+  trace_stream<PER_RAY, COUNT>(io, gtid, gridDim.x * TB, n, st, wc);
+  if (io.nrays) {
+    atomicAdd(stats + 1, (unsigned long long)io.nrays);
+    atomicAdd(stats + 12, (unsigned long long)io.nrays);
+  }
+  if (io.nshadow) {
+    atomicAdd(stats + 2, (unsigned long long)io.nshadow);
+    atomicAdd(stats + 13, (unsigned long long)io.nshadow);
+  }
+  if (st.spills) atomicAdd(stats + 3, (unsigned long long)st.spills);
+  if (st.overflow) atomicAdd(stats + 5, 1ull);
+  if (COUNT && wc.visits) atomicAdd(stats + 14, (unsigned long long)wc.visits);
+  if (COUNT && wc.tests) atomicAdd(stats + 15, (unsigned long long)wc.tests);
+  if (COUNT && wc.max_steps) atomicMax(stats + 10, (unsigned long long)wc.max_steps);
 }
 
 // Per pixel of every job overlapping the chunk [g0, g0 + n): add its samples of
@@ -835,9 +1015,9 @@ __global__ __launch_bounds__(64) void k_tally(const uint32_t* __restrict__ q, in
       r += q[Q_RAYS + b];
       s += q[Q_SHADOW + b];
     }
-    stats[1] += r;
-    stats[2] += s;
-    stats[4] += paths;
+    atomicAdd(stats + 1, r);
+    atomicAdd(stats + 2, s);
+    atomicAdd(stats + 4, (unsigned long long)paths);
   }
 }
 
@@ -856,12 +1036,14 @@ struct DebugHitIO {
     r.x0 = skip ? (uint32_t)skip[i] : NO_PRIM;
     r.x1 = r.x2 = NO_PRIM;
     r.tmax = INFINITY;
+    r.any = false;
   }
-  __device__ __forceinline__ void store(uint32_t i, const TraceState& ts, bool) const {
+  __device__ __forceinline__ bool store(uint32_t i, const TraceState& ts, bool, RayIn&) const {
     t_out[i] = ts.t;
     prim_out[i] = ts.prim == NO_PRIM ? -1 : (int32_t)ts.prim;
     b_out[2 * i] = ts.b1;
     b_out[2 * i + 1] = ts.b2;
+    return false;
   }
 };
 
@@ -878,7 +1060,7 @@ __global__ __launch_bounds__(TB) void k_debug_hit(SceneView sc, int32_t n,
   Stack st{stk + threadIdx.x, spill + gtid, gridDim.x * TB, 0, 0u, false};
   WorkCount wc;
   DebugHitIO io{sc, o, d, skip, t_out, prim_out, b_out};
-  trace_stream<false, false>(io, gtid, gridDim.x * TB, (uint32_t)n, st, wc);
+  trace_stream<CLOSEST, false>(io, gtid, gridDim.x * TB, (uint32_t)n, st, wc);
 }
 
 __global__ __launch_bounds__(256) void k_debug_philox(int32_t n, const uint32_t* __restrict__ ctr,
@@ -944,7 +1126,7 @@ std::map<hipStream_t, Workspace*> g_stream_ws;
 hipStream_t g_sub[MAX_SUB] = {};
 int g_nsub = 0;
 unsigned long long* g_stats = nullptr;  // device counters shared by every stream
-mrs_tuning g_tune = {1 << 23, 8192, 0, LEAF4_MAX, 3};
+mrs_tuning g_tune = {1 << 23, 8192, 0, LEAF4_MAX, 3, 3};
 std::atomic<bool> g_count_work{false};
 
 template <typename T>
@@ -1087,6 +1269,8 @@ mrs_status launch_batch(Workspace& ws, const mrs_tuning& tu, const DevJob* d_job
     max_depth = std::max(max_depth, (int)J.max_depth);
   }
   const Plan P = make_plan(tu, total);
+  // wavefront bounces 0 .. nwave-1; the path tail takes bounces nwave .. max_depth
+  const int nwave = std::min(tu.tail_bounce, max_depth + 1);
   const int dyn = tu.schedule;
   const bool count = g_count_work.load();
   unsigned long long* stats = g_stats;
@@ -1122,7 +1306,7 @@ mrs_status launch_batch(Workspace& ws, const mrs_tuning& tu, const DevJob* d_job
       prof_begin(KID_GENERATE, sk);
       k_generate<<<cdiv(n, 256), 256, 0, sk>>>(d_jobs, nj, lo, n, rays[0]);
       prof_end(KID_GENERATE, sk);
-      for (int b = 0; b <= max_depth; ++b) {
+      for (int b = 0; b < nwave; ++b) {
         float4* rin = rays[b & 1];
         float4* rout = rays[(b + 1) & 1];
         prof_begin(KID_EXTEND, sk);
@@ -1143,6 +1327,16 @@ mrs_status launch_batch(Workspace& ws, const mrs_tuning& tu, const DevJob* d_job
           prof_end(KID_SHADOW, sk);
         }
       }
+      if (nwave <= max_depth) {  // the remaining bounces, path by path
+        prof_begin(KID_TAIL, sk);
+        if (count)
+          k_tail<true><<<gb, TB, 0, sk>>>(d_jobs, lo, nwave, rays[nwave & 1], q, beta, L, spill,
+                                          stats);
+        else
+          k_tail<false><<<gb, TB, 0, sk>>>(d_jobs, lo, nwave, rays[nwave & 1], q, beta, L, spill,
+                                           stats);
+        prof_end(KID_TAIL, sk);
+      }
       if (P.K > 1) {
         MRS_TRY_HIP(hipEventRecord(ws.ev_join[k], sk));
         MRS_TRY_HIP(hipStreamWaitEvent(st, ws.ev_join[k], 0));
@@ -1162,7 +1356,7 @@ mrs_status launch_batch(Workspace& ws, const mrs_tuning& tu, const DevJob* d_job
       k_accumulate<<<cdiv((size_t)(pix_hi - pix_lo), 256), 256, 0, st>>>(
           d_jobs, nj, lo, n, pix_lo, pix_hi, ws.L + o, ws.aux + 2 * o, acc, stats);
       prof_end(KID_ACCUMULATE, st);
-      k_tally<<<1, 64, 0, st>>>(ws.q + k * Q_WORDS, max_depth + 1, stats, n);
+      k_tally<<<1, 64, 0, st>>>(ws.q + k * Q_WORDS, nwave, stats, n);
     }
     // the next super-chunk reuses the slices once these sums have read them
     if (P.K > 1) MRS_TRY_HIP(hipEventRecord(ws.ev_fork, st));
@@ -1358,6 +1552,8 @@ mrs_status set_tuning(const mrs_tuning* t) {
     return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_set_tuning: bvh_leaf_max must be in [1, 4]");
   if (t->streams < 1 || t->streams > MAX_SUB)
     return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_set_tuning: streams must be in [1, 4]");
+  if (t->tail_bounce < 1 || t->tail_bounce > 65)
+    return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_set_tuning: tail_bounce must be in [1, 65]");
   std::lock_guard<std::mutex> lk(g_mu);
   g_tune = *t;
   return MRS_OK;

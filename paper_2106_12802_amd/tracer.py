@@ -117,7 +117,8 @@ def counters(reset=False):
     L.use_current_stream()
     L.check(L.lib().mrs_get_counters(out.ctypes.data_as(C.c_void_p), int(reset)))
     keys = ["nonfinite", "rays", "shadow_rays", "spills", "paths", "overflows",
-            "extend_visits", "extend_tests", "shadow_visits", "shadow_tests", "r10", "r11"]
+            "extend_visits", "extend_tests", "shadow_visits", "shadow_tests", "extend_max_steps",
+            "shadow_max_steps", "tail_rays", "tail_shadow_rays", "tail_visits", "tail_tests"]
     return dict(zip(keys, (int(x) for x in out)))
 
 
@@ -138,7 +139,7 @@ def profile_read():
     return {names[i]: (float(ms[i]), int(n[i])) for i in range(L.NUM_KERNEL_IDS) if n[i]}
 
 
-TUNING_KEYS = ("chunk_paths", "trace_blocks", "schedule", "bvh_leaf_max", "streams")
+TUNING_KEYS = ("chunk_paths", "trace_blocks", "schedule", "bvh_leaf_max", "streams", "tail_bounce")
 
 
 def get_tuning():
@@ -148,10 +149,10 @@ def get_tuning():
 
 
 def set_tuning(chunk_paths=None, trace_blocks=None, schedule=None, bvh_leaf_max=None,
-               streams=None):
+               streams=None, tail_bounce=None):
     cur = get_tuning()
     new = dict(chunk_paths=chunk_paths, trace_blocks=trace_blocks, schedule=schedule,
-               bvh_leaf_max=bvh_leaf_max, streams=streams)
+               bvh_leaf_max=bvh_leaf_max, streams=streams, tail_bounce=tail_bounce)
     t = L.Tuning()
     for k in TUNING_KEYS:
         setattr(t, k, int(new[k] if new[k] is not None else cur[k]))

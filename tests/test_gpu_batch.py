@@ -172,8 +172,8 @@ def test_concurrent_streams_and_batch_tuning_snapshot(torch_cuda):
 
 def test_full_size_render_invariant_to_tuning(torch_cuda):
     """A 1280x720x4 render of the 101k-triangle scene is bitwise the same for every
-    sub-chunk count, chunk size, grid size and schedule (each ray's traversal order
-    must not depend on which rays share its wave)."""
+    sub-chunk count, chunk size, grid size, schedule and path-tail bounce (the result
+    must not depend on which rays share a wave, nor on which kernel traces a bounce)."""
     import paper_2106_12802_amd as mrs
     torch = torch_cuda
     gs = mrs.GpuScene(S.procedural(7))
@@ -184,7 +184,8 @@ def test_full_size_render_invariant_to_tuning(torch_cuda):
         torch.cuda.synchronize()
         for tune in (dict(streams=3), dict(streams=2, chunk_paths=1 << 20),
                      dict(streams=3, trace_blocks=1000, schedule=1),
-                     dict(streams=1, chunk_paths=777777, trace_blocks=3000)):
+                     dict(streams=1, chunk_paths=777777, trace_blocks=3000),
+                     dict(tail_bounce=1), dict(tail_bounce=2), dict(tail_bounce=65)):
             mrs.set_tuning(**dict(old, **tune))
             img, aux = mrs.render(gs, 1280, 720, 4, 8, 99)
             torch.cuda.synchronize()
