@@ -480,8 +480,9 @@ def main():
     log(f"[bench] same frames as two render calls: {ms_calls:.3f} ms/frame")
 
     ext_ms, ext_n = prof.get("extend", (0.0, 0))
+    ext_rays = max(work["rays"] - work["tail_rays"], 1)  # rays traced by k_extend itself
     flop_frame = (FLOP_PER_VISIT * work["extend_visits"] + FLOP_PER_TEST * work["extend_tests"]
-                  + FLOP_PER_RAY * work["rays"])
+                  + FLOP_PER_RAY * ext_rays)
     launches_per_frame = ext_n / args.steps if args.steps else 0
     flop_per_launch = flop_frame / max(launches_per_frame, 1)
     avg_launch_s = ext_ms / 1e3 / max(ext_n, 1)
@@ -491,8 +492,8 @@ def main():
                 "frac": round(achieved / PEAK_FP32_TFLOPS, 5), "traffic": read_traffic(),
                 "avg_launch_us": round(avg_launch_s * 1e6, 2),
                 "flop_per_launch": int(flop_per_launch),
-                "visits_per_ray": round(work["extend_visits"] / max(work["rays"], 1), 2),
-                "tests_per_ray": round(work["extend_tests"] / max(work["rays"], 1), 2)}
+                "visits_per_ray": round(work["extend_visits"] / ext_rays, 2),
+                "tests_per_ray": round(work["extend_tests"] / ext_rays, 2)}
     cnn_ms = sum(prof.get(k, (0.0, 0))[0] for k in ("cnn_prep", "cnn_hr_in", "cnn_lr",
                                                      "cnn_hr_out")) / args.steps
     cnn_roof = {"bound": "mfma", "achieved": round(CNN_FLOP_720P / (cnn_ms / 1e3) / 1e12, 2)
