@@ -1126,7 +1126,7 @@ std::map<hipStream_t, Workspace*> g_stream_ws;
 hipStream_t g_sub[MAX_SUB] = {};
 int g_nsub = 0;
 unsigned long long* g_stats = nullptr;  // device counters shared by every stream
-mrs_tuning g_tune = {1 << 23, 8192, 0, LEAF4_MAX, 3, 3};
+mrs_tuning g_tune = {1 << 23, 4096, 0, LEAF4_MAX, 3, 3};
 std::atomic<bool> g_count_work{false};
 
 template <typename T>
@@ -1278,85 +1278,111 @@ mrs_status launch_batch(Workspace& ws, const mrs_tuning& tu, const DevJob* d_job
   k_zero_words<<<std::min(4096u, cdiv(acc_bytes / 4, 256)), 256, 0, st>>>((uint32_t*)acc,
                                                                           acc_bytes / 4);
   if (P.K > 1) MRS_TRY_HIP(hipEventRecord(ws.ev_fork, st));
+  // One sub-chunk: its stream and its slice of the workspace.
+  struct Sub {
+    hipStream_t s;
+    int64_t lo;
+    uint32_t n;
+    unsigned gb;
+    size_t o;
+    float4* rays[2];
+    float4 *hits, *shadow, *beta, *L, *aux;
+    uint32_t *spill, *q;
+  };
   for (int64_t g0 = 0; g0 < total; g0 += P.K * P.Cs) {
+    Sub sub[MAX_SUB];
     int used = 0;
-    int64_t lo_k[MAX_SUB];
-    uint32_t n_k[MAX_SUB];
-    for (int k = 0; k < P.K; ++k) {
-      const int64_t lo = g0 + k * P.Cs;
-      if (lo >= total) break;
-      const uint32_t n = (uint32_t)std::min<int64_t>(P.Cs, total - lo);
-      lo_k[k] = lo;
-      n_k[k] = n;
-      used = k + 1;
-      hipStream_t sk = P.K > 1 ? g_sub[k] : st;
-      if (P.K > 1) MRS_TRY_HIP(hipStreamWaitEvent(sk, ws.ev_fork, 0));
-      // this sub-chunk's slice of the workspace
-      const size_t o = (size_t)k * P.Cs;
-      float4* rays[2] = {ws.rays[0] + 2 * o, ws.rays[1] + 2 * o};
-      float4* hits = ws.hits + o;
-      float4* shadow = ws.shadow + 3 * o;
-      float4* beta = ws.beta + o;
-      float4* L = ws.L + o;
-      float4* aux = ws.aux + 2 * o;
-      uint32_t* spill = ws.spill + k * spill_k;
-      uint32_t* q = ws.q + k * Q_WORDS;
-      const unsigned gb = std::min<unsigned>(P.blocks_k, cdiv(n, TB));
-      k_reset<<<1, 256, 0, sk>>>(q, n);
-      prof_begin(KID_GENERATE, sk);
-      k_generate<<<cdiv(n, 256), 256, 0, sk>>>(d_jobs, nj, lo, n, rays[0]);
-      prof_end(KID_GENERATE, sk);
-      for (int b = 0; b < nwave; ++b) {
-        float4* rin = rays[b & 1];
-        float4* rout = rays[(b + 1) & 1];
-        prof_begin(KID_EXTEND, sk);
+    for (int k = 0; k < P.K && g0 + k * P.Cs < total; ++k, ++used) {
+      Sub& u = sub[k];
+      u.s = P.K > 1 ? g_sub[k] : st;
+      u.lo = g0 + k * P.Cs;
+      u.n = (uint32_t)std::min<int64_t>(P.Cs, total - u.lo);
+      u.gb = std::min<unsigned>(P.blocks_k, cdiv(u.n, TB));
+      u.o = (size_t)k * P.Cs;
+      u.rays[0] = ws.rays[0] + 2 * u.o;
+      u.rays[1] = ws.rays[1] + 2 * u.o;
+      u.hits = ws.hits + u.o;
+      u.shadow = ws.shadow + 3 * u.o;
+      u.beta = ws.beta + u.o;
+      u.L = ws.L + u.o;
+      u.aux = ws.aux + 2 * u.o;
+      u.spill = ws.spill + k * spill_k;
+      u.q = ws.q + k * Q_WORDS;
+    }
+    // Launches are enqueued phase by phase across the sub-chunks so that every
+    // stream has work queued early.
+    for (int k = 0; k < used; ++k) {
+      Sub& u = sub[k];
+      if (P.K > 1) MRS_TRY_HIP(hipStreamWaitEvent(u.s, ws.ev_fork, 0));
+      k_reset<<<1, 256, 0, u.s>>>(u.q, u.n);
+      prof_begin(KID_GENERATE, u.s);
+      k_generate<<<cdiv(u.n, 256), 256, 0, u.s>>>(d_jobs, nj, u.lo, u.n, u.rays[0]);
+      prof_end(KID_GENERATE, u.s);
+    }
+    for (int b = 0; b < nwave; ++b) {
+      for (int k = 0; k < used; ++k) {
+        Sub& u = sub[k];
+        prof_begin(KID_EXTEND, u.s);
         if (count)
-          k_extend<true><<<gb, TB, 0, sk>>>(d_jobs, b, dyn, rin, q, hits, spill, stats);
+          k_extend<true><<<u.gb, TB, 0, u.s>>>(d_jobs, b, dyn, u.rays[b & 1], u.q, u.hits, u.spill,
+                                                stats);
         else
-          k_extend<false><<<gb, TB, 0, sk>>>(d_jobs, b, dyn, rin, q, hits, spill, stats);
-        prof_end(KID_EXTEND, sk);
-        prof_begin(KID_SHADE, sk);
-        k_shade<<<gb, 256, 0, sk>>>(d_jobs, lo, b, rin, hits, q, rout, shadow, beta, L, aux);
-        prof_end(KID_SHADE, sk);
-        if (b < max_depth) {
-          prof_begin(KID_SHADOW, sk);
+          k_extend<false><<<u.gb, TB, 0, u.s>>>(d_jobs, b, dyn, u.rays[b & 1], u.q, u.hits,
+                                                 u.spill, stats);
+        prof_end(KID_EXTEND, u.s);
+      }
+      for (int k = 0; k < used; ++k) {
+        Sub& u = sub[k];
+        prof_begin(KID_SHADE, u.s);
+        k_shade<<<u.gb, 256, 0, u.s>>>(d_jobs, u.lo, b, u.rays[b & 1], u.hits, u.q,
+                                       u.rays[(b + 1) & 1], u.shadow, u.beta, u.L, u.aux);
+        prof_end(KID_SHADE, u.s);
+      }
+      if (b < max_depth) {
+        for (int k = 0; k < used; ++k) {
+          Sub& u = sub[k];
+          prof_begin(KID_SHADOW, u.s);
           if (count)
-            k_shadow<true><<<gb, TB, 0, sk>>>(d_jobs, b, dyn, shadow, q, L, spill, stats);
+            k_shadow<true><<<u.gb, TB, 0, u.s>>>(d_jobs, b, dyn, u.shadow, u.q, u.L, u.spill,
+                                                  stats);
           else
-            k_shadow<false><<<gb, TB, 0, sk>>>(d_jobs, b, dyn, shadow, q, L, spill, stats);
-          prof_end(KID_SHADOW, sk);
+            k_shadow<false><<<u.gb, TB, 0, u.s>>>(d_jobs, b, dyn, u.shadow, u.q, u.L, u.spill,
+                                                   stats);
+          prof_end(KID_SHADOW, u.s);
         }
       }
-      if (nwave <= max_depth) {  // the remaining bounces, path by path
-        prof_begin(KID_TAIL, sk);
+    }
+    if (nwave <= max_depth) {  // the remaining bounces, path by path
+      for (int k = 0; k < used; ++k) {
+        Sub& u = sub[k];
+        prof_begin(KID_TAIL, u.s);
         if (count)
-          k_tail<true><<<gb, TB, 0, sk>>>(d_jobs, lo, nwave, rays[nwave & 1], q, beta, L, spill,
-                                          stats);
+          k_tail<true><<<u.gb, TB, 0, u.s>>>(d_jobs, u.lo, nwave, u.rays[nwave & 1], u.q, u.beta,
+                                              u.L, u.spill, stats);
         else
-          k_tail<false><<<gb, TB, 0, sk>>>(d_jobs, lo, nwave, rays[nwave & 1], q, beta, L, spill,
-                                           stats);
-        prof_end(KID_TAIL, sk);
-      }
-      if (P.K > 1) {
-        MRS_TRY_HIP(hipEventRecord(ws.ev_join[k], sk));
-        MRS_TRY_HIP(hipStreamWaitEvent(st, ws.ev_join[k], 0));
+          k_tail<false><<<u.gb, TB, 0, u.s>>>(d_jobs, u.lo, nwave, u.rays[nwave & 1], u.q,
+                                               u.beta, u.L, u.spill, stats);
+        prof_end(KID_TAIL, u.s);
       }
     }
-    // per-pixel sums in sample order: sub-chunks in path order, on the caller's stream
+    // per-pixel sums in sample order: each sub-chunk, in path order, on the
+    // caller's stream as soon as that sub-chunk is done
     for (int k = 0; k < used; ++k) {
-      const int64_t lo = lo_k[k];
-      const uint32_t n = n_k[k];
-      const size_t o = (size_t)k * P.Cs;
+      Sub& u = sub[k];
+      if (P.K > 1) {
+        MRS_TRY_HIP(hipEventRecord(ws.ev_join[k], u.s));
+        MRS_TRY_HIP(hipStreamWaitEvent(st, ws.ev_join[k], 0));
+      }
       int jlo = 0, jhi = nj - 1;
-      while (jlo < nj - 1 && jobs[jlo + 1].first <= lo) ++jlo;
-      while (jhi > 0 && jobs[jhi].first >= lo + (int64_t)n) --jhi;
+      while (jlo < nj - 1 && jobs[jlo + 1].first <= u.lo) ++jlo;
+      while (jhi > 0 && jobs[jhi].first >= u.lo + (int64_t)u.n) --jhi;
       const int64_t pix_lo = jobs[jlo].pix_first;
       const int64_t pix_hi = jobs[jhi].pix_first + (int64_t)jobs[jhi].ww * jobs[jhi].wh;
       prof_begin(KID_ACCUMULATE, st);
       k_accumulate<<<cdiv((size_t)(pix_hi - pix_lo), 256), 256, 0, st>>>(
-          d_jobs, nj, lo, n, pix_lo, pix_hi, ws.L + o, ws.aux + 2 * o, acc, stats);
+          d_jobs, nj, u.lo, u.n, pix_lo, pix_hi, u.L, u.aux, acc, stats);
       prof_end(KID_ACCUMULATE, st);
-      k_tally<<<1, 64, 0, st>>>(ws.q + k * Q_WORDS, nwave, stats, n);
+      k_tally<<<1, 64, 0, st>>>(u.q, nwave, stats, u.n);
     }
     // the next super-chunk reuses the slices once these sums have read them
     if (P.K > 1) MRS_TRY_HIP(hipEventRecord(ws.ev_fork, st));
