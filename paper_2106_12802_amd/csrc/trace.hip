@@ -174,6 +174,21 @@ struct Stack {
     --sp;
     return sp < LDS_STACK ? lds[sp * TB] : spill[(size_t)(sp - LDS_STACK) * stride];
   }
+  // Pushes the first `cnt` (0..3) of c, b, a in that order: far to near, so
+  // that `a` is popped first.  With room in LDS for three entries (nearly
+  // always) the three slots are written unconditionally and sp advances by cnt.
+  __device__ __forceinline__ void push_upto3(uint32_t a, uint32_t b, uint32_t c, uint32_t cnt) {
+    if (sp + 3 <= LDS_STACK) {
+      lds[sp * TB] = cnt == 3 ? c : (cnt == 2 ? b : a);
+      lds[(sp + 1) * TB] = cnt == 3 ? b : a;
+      lds[(sp + 2) * TB] = a;
+      sp += (int)cnt;
+      return;
+    }
+    if (cnt == 3) push(c);
+    if (cnt >= 2) push(b);
+    if (cnt >= 1) push(a);
+  }
 };
 
 struct WorkCount {
@@ -276,32 +291,29 @@ __device__ void trace_stream(IO& io, uint32_t first, uint32_t stride, uint32_t n
       float t0, t1, t2, t3;
       uint32_t r0 = __float_as_uint(rf.x), r1 = __float_as_uint(rf.y), r2 = __float_as_uint(rf.z),
                r3 = __float_as_uint(rf.w);
-      if (r0 == EMPTY4 || !slab(lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, oi, inv, ts.t, t0)) {
-        r0 = EMPTY4;
-        t0 = INFINITY;
-      }
-      if (r1 == EMPTY4 || !slab(lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, oi, inv, ts.t, t1)) {
-        r1 = EMPTY4;
-        t1 = INFINITY;
-      }
-      if (r2 == EMPTY4 || !slab(lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, oi, inv, ts.t, t2)) {
-        r2 = EMPTY4;
-        t2 = INFINITY;
-      }
-      if (r3 == EMPTY4 || !slab(lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, oi, inv, ts.t, t3)) {
-        r3 = EMPTY4;
-        t3 = INFINITY;
-      }
-      // hits to the front, nearest first for closest hits (misses sort last)
+      // branch-free: every slab test is evaluated, misses become (INFINITY, EMPTY4)
+      const bool h0 = slab(lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, oi, inv, ts.t, t0) & (r0 != EMPTY4);
+      const bool h1 = slab(lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, oi, inv, ts.t, t1) & (r1 != EMPTY4);
+      const bool h2 = slab(lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, oi, inv, ts.t, t2) & (r2 != EMPTY4);
+      const bool h3 = slab(lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, oi, inv, ts.t, t3) & (r3 != EMPTY4);
+      t0 = h0 ? t0 : INFINITY;
+      t1 = h1 ? t1 : INFINITY;
+      t2 = h2 ? t2 : INFINITY;
+      t3 = h3 ? t3 : INFINITY;
+      r0 = h0 ? r0 : EMPTY4;
+      r1 = h1 ? r1 : EMPTY4;
+      r2 = h2 ? r2 : EMPTY4;
+      r3 = h3 ? r3 : EMPTY4;
+      const uint32_t nhit = (uint32_t)h0 + (uint32_t)h1 + (uint32_t)h2 + (uint32_t)h3;
+      // sorting network: hits nearest first, misses (INFINITY) last
       cswap(t0, r0, t1, r1);
       cswap(t2, r2, t3, r3);
       cswap(t0, r0, t2, r2);
       cswap(t1, r1, t3, r3);
-      if (MODE != ANY_HIT) cswap(t1, r1, t2, r2);
-      if (r3 != EMPTY4) st.push(r3);
-      if (r2 != EMPTY4) st.push(r2);
-      if (r1 != EMPTY4) st.push(r1);
-      node = r0 != EMPTY4 ? r0 : (st.sp ? st.pop() : EMPTY4);
+      cswap(t1, r1, t2, r2);
+      // go to the nearest hit child, push the others far to near
+      st.push_upto3(r1, r2, r3, nhit > 0 ? nhit - 1 : 0);
+      node = nhit > 0 ? r0 : (st.sp ? st.pop() : EMPTY4);
       if ((node & LEAF_BIT) && node != EMPTY4 && leaf == EMPTY4) {
         leaf = node;
         node = st.sp ? st.pop() : EMPTY4;
