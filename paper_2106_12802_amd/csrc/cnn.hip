@@ -228,8 +228,8 @@ __device__ __forceinline__ void conv_epilogue(const ConvArgs& p, const f32x4 (&a
 // computes image rows 2w and 2w+1 of the tile (two 16-pixel row tiles) x 16 NT
 // channels with v_mfma_f32_16x16x32_bf16; K index k = tap CINP + c as in the
 // packed weights, so with CINP < 32 one K step spans two taps.  LDS layouts are
-// chosen for conflict-free 16-byte reads: tile pixels padded by 8 channels,
-// weights chunk-major [k / 8][n][8].
+// chosen for conflict-free 16-byte accesses: tile pixels padded by 8
+// channels, weights chunk-major [k / 8][n][8] with one pad chunk per k row.
 constexpr int C3_T = 16, C3_THREADS = 512;
 constexpr int C3_TILE = (C3_T + 2) * (C3_T + 2);
 
@@ -238,8 +238,9 @@ __global__ __launch_bounds__(C3_THREADS) void k_conv3_lds(ConvArgs p, int cout_p
   constexpr int PITCH = CINP + 8;
   constexpr int KP = (9 * CINP + 31) / 32 * 32;
   constexpr int NG = 16 * NT;
+  constexpr int WPITCH = NG + 1;  // 16-byte chunks per weight row (pad: conflict-free stores)
   __shared__ __attribute__((aligned(16))) uint16_t tile[C3_TILE * PITCH];
-  __shared__ __attribute__((aligned(16))) uint16_t wts[KP * NG];
+  __shared__ __attribute__((aligned(16))) uint16_t wts[(KP / 8) * WPITCH * 8];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int kq = lane >> 4, li = lane & 15;
@@ -272,7 +273,7 @@ __global__ __launch_bounds__(C3_THREADS) void k_conv3_lds(ConvArgs p, int cout_p
     };
     auto w_store = [&](int i, uint4 v) {
       const int n = i / (KP / 8), kc = i - n * (KP / 8);
-      if (i < WCH) *reinterpret_cast<uint4*>(wts + (kc * NG + n) * 8) = v;
+      if (i < WCH) *reinterpret_cast<uint4*>(wts + (kc * WPITCH + n) * 8) = v;
     };
     for (int i = tid; i < WCH; i += 3 * C3_THREADS) {
       const uint4 v0 = w_load(i), v1 = w_load(i + C3_THREADS), v2 = w_load(i + 2 * C3_THREADS);
@@ -296,7 +297,7 @@ __global__ __launch_bounds__(C3_THREADS) void k_conv3_lds(ConvArgs p, int cout_p
         A[r] = tap < 9 ? ld8(tile + ((2 * wave + r + dy) * (C3_T + 2) + li + dx) * PITCH + c)
                        : zero8();
 #pragma unroll
-      for (int j = 0; j < NT; ++j) Bv[j] = ld8(wts + (((ks >> 3) + kq) * NG + j * 16 + li) * 8);
+      for (int j = 0; j < NT; ++j) Bv[j] = ld8(wts + (((ks >> 3) + kq) * WPITCH + j * 16 + li) * 8);
 #pragma unroll
       for (int r = 0; r < 2; ++r)
 #pragma unroll
