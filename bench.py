@@ -41,6 +41,19 @@ TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "extend_procedural101k_720p_tra
 WEIGHTS = os.path.join(ROOT, "paper_2106_12802_amd", "weights", "fusion_l1_textured.bin")
 PEAK_BF16_TFLOPS = 2500.0  # MI355X dense BF16 MFMA
 CNN_FLOP_720P = 175.7e9    # 87.85 GMAC per 720p frame
+PAPER_TABLE5_X4_S = 0.118  # the paper's network, x4 on a 1024x1024 image (its Table 5; Titan Xp)
+
+
+def rdg_flop(H, W):
+    """Forward FLOP of the paper's network (residual dense groups) on one H x W
+    frame: 2 x sum over convs of pixels x C_out x C_in x k^2."""
+    p = H * W // 16  # LR pixels
+    mac = (16 * p * 64 * 10 * 9 + p * 64 * 3 * 9 + p * 64 * 1088      # encoders, fuse
+           + 15 * p * 64 * 9 * (64 + 128 + 192 + 256)                  # 15 dense blocks
+           + p * 256 * 64 * 9 + 4 * p * 256 * 64 * 9 + 16 * p * 3 * 64 * 9)  # up0, up1, rec
+    return 2 * mac
+
+
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2106_12802_amd", "csrc", "trace.hip")
 
 
@@ -126,10 +139,10 @@ def pmc_summary(fetch_path, write_path, out_path):
         "# (max depth 8) + fusion network.",
         "# Made by (each pass its own process, run from the repository root):",
         "#   rocprofv3 --pmc FETCH_SIZE -f csv -d gpurun_out/pmc_fetch -o pmc -- python bench.py "
-        "--steps 1 --warmup 0 --no-cpu-baseline --equal-psnr-scenes 0 --batch-scenes 0 "
+        "--steps 1 --warmup 0 --no-cpu-baseline --equal-psnr-scenes 0 --batch-scenes 0 --no-paper-net "
         "--copy-calibration",
         "#   rocprofv3 --pmc WRITE_SIZE -f csv -d gpurun_out/pmc_write -o pmc -- python bench.py "
-        "--steps 1 --warmup 0 --no-cpu-baseline --equal-psnr-scenes 0 --batch-scenes 0 "
+        "--steps 1 --warmup 0 --no-cpu-baseline --equal-psnr-scenes 0 --batch-scenes 0 --no-paper-net "
         "--copy-calibration",
         "#   python bench.py --pmc-summary gpurun_out/pmc_fetch gpurun_out/pmc_write",
         "# Counters are KiB per dispatch; each is scaled by COPY_BYTES over what the same counter",
@@ -152,7 +165,7 @@ def pmc_summary(fetch_path, write_path, out_path):
 
 STATS_SUMMARY = os.path.join(ROOT, "profiles", "hybrid_frame_procedural101k_720p_kernel_stats.txt")
 STATS_CMD = ("rocprofv3 --kernel-trace --stats -f csv -d gpurun_out/prof -o bench -- python -u "
-             "bench.py --steps 5 --warmup 1 --no-cpu-baseline --equal-psnr-scenes 0 --batch-scenes 0")
+             "bench.py --steps 5 --warmup 1 --no-cpu-baseline --equal-psnr-scenes 0 --batch-scenes 0 --no-paper-net")
 
 
 def stats_summary(prof_dir, out_path):
@@ -358,6 +371,51 @@ def batched_block(net, log, n_scenes=32, tune=True):
             if tuned else None}
 
 
+def paper_net_block(log, reps=10, train_steps=10):
+    """The paper's own network (three residual dense groups, Sec. 4): fuse time
+    on the 720p hybrid frame and at the paper's runtime-table size (one
+    1024 x 1024 image, x4), and the training step (batch 16 of 128 x 128 HR
+    crops, robust loss, SGD) -- random weights and inputs of those shapes."""
+    import torch
+    import paper_2106_12802_amd as mrs
+    net = mrs.FusionNet(seed=1, arch="rdg")
+    g = torch.Generator(device="cuda").manual_seed(5)
+    res = {"params": net.num_params}
+    for tag, (H, W) in (("720p", (720, 1280)), ("1024x1024", (1024, 1024))):
+        hr = torch.rand(H, W, 3, device="cuda", generator=g)
+        aux = torch.rand(H, W, 7, device="cuda", generator=g)
+        lr = torch.rand(H // 4, W // 4, 3, device="cuda", generator=g)
+        out = torch.empty_like(hr)
+        net.fuse(hr, aux, lr, out=out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            net.fuse(hr, aux, lr, out=out)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+        flop = rdg_flop(H, W)
+        res[f"fuse_ms_{tag}"] = round(ms, 4)
+        res[f"tflops_{tag}"] = round(flop / (ms / 1e3) / 1e12, 2)
+        log(f"[bench] paper network {tag}: {ms:.3f} ms ({flop / 1e9:.1f} GFLOP)")
+    res["gflop_720p"] = round(rdg_flop(720, 1280) / 1e9, 2)
+    res["frac_720p"] = round(res["tflops_720p"] / PEAK_BF16_TFLOPS, 5)
+    res["paper_table5_x4_1024sq_ms"] = PAPER_TABLE5_X4_S * 1e3
+    B, H, W = 16, 128, 128
+    t = [torch.rand(B, H, W, c, device="cuda", generator=g) for c in (3, 7)]
+    t.insert(2, torch.rand(B, H // 4, W // 4, 3, device="cuda", generator=g))
+    t.append(torch.rand(B, H, W, 3, device="cuda", generator=g))
+    net.train_step(*t, lr=1e-4, loss="robust", beta=0.1, optimizer="sgd")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(train_steps):
+        net.train_step(*t, lr=1e-4, loss="robust", beta=0.1, optimizer="sgd")
+    torch.cuda.synchronize()
+    res["train_step_ms_b16_128"] = round((time.perf_counter() - t0) * 1e3 / train_steps, 3)
+    log(f"[bench] paper network training step: {res['train_step_ms_b16_128']} ms")
+    net.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -368,6 +426,8 @@ def main():
                     help="held-out scenes in the equal-PSNR comparison (0: skip it)")
     ap.add_argument("--batch-scenes", type=int, default=32,
                     help="scenes in the batched render+fuse measurement (0: skip it)")
+    ap.add_argument("--no-paper-net", action="store_true",
+                    help="skip timing the paper's own network (residual dense groups)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 1 GiB device copy first (PMC byte-counter calibration)")
     ap.add_argument("--chunk-paths", type=int, default=None, help="tuning: paths resident at once")
@@ -524,6 +584,8 @@ def main():
         result["equal_psnr"] = equal_psnr_block(net, args.equal_psnr_scenes, log)
     if args.batch_scenes > 0:
         result["batched"] = batched_block(net, log, args.batch_scenes)
+    if not args.no_paper_net:
+        result["paper_net"] = paper_net_block(log)
     if not args.no_cpu_baseline:
         threads = max(1, min(16, len(os.sched_getaffinity(0))))
         log(f"[bench] timing the FP64 oracle on {threads} host threads")

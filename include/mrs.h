@@ -272,8 +272,33 @@ mrs_status mrs_set_tuning(const mrs_tuning* t);
 typedef struct mrs_net mrs_net;
 #define MRS_NET_NUM_PARAMS 1408883
 
-int64_t mrs_net_num_params(void);
-mrs_status mrs_net_create(mrs_net** out); /* parameters unset: mrs_fuse is NOT_READY */
+/* Network architectures:
+ * MRS_NET_RES16  the network above (16 residual blocks).
+ * MRS_NET_RDG    the paper's own network (Sec. 4, Fig. 4):
+ *   h0   = ReLU(conv3x3 10->64) on HRLS                              HR
+ *   fl   = ReLU(conv3x3 3->64) on LRHS                               LR
+ *   F0   = ReLU(conv1x1 [fl, DSF(DSF(h0))] 1088->64)   two stacked stride-2
+ *          deshuffles: HR pixel (4Y+I, 4X+J) channel c -> LR channel
+ *          (2 (I>>1) + (J>>1)) 256 + (2 (I&1) + (J&1)) 64 + c
+ *   RDB: x_c = ReLU(conv3x3 [x_0 .. x_{c-1}] -> 64) for c = 1..3, output
+ *        x_0 + conv3x3 [x_0 .. x_3] 256->64 (no ReLU before the block's skip)
+ *   F_g  = RDB^5(F_{g-1}) + F_{g-1} for g = 1..3 (residual dense groups)
+ *   FDF  = F_3 + F0
+ *   UP   = twice: shuffle2(ReLU(conv3x3 64->256))   (sub-pixel, ESPCN)
+ *   out  = conv3x3 UP(FDF) 64->3                                     HR
+ *   Parameters (MRS_NET_RDG_NUM_PARAMS): hrls, lrhs, fuse, g0b0c0 .. g0b0c3,
+ *   g0b1c0, ..., g2b4c3, up0, up1, rec, each weight [C_out][C_in][k][k] then
+ *   bias [C_out]; conv c of a block reads channels [x_0, .., x_{c}] in that
+ *   order.  mrs_net_init scales the bound of each block's last conv and of rec by 0.1. */
+#define MRS_NET_RES16 0
+#define MRS_NET_RDG 1
+#define MRS_NET_RDG_NUM_PARAMS 5907907
+
+int64_t mrs_net_num_params(void);                 /* MRS_NET_RES16's count */
+int64_t mrs_net_arch_num_params(int32_t arch);     /* -1 for an unknown arch */
+mrs_status mrs_net_create(mrs_net** out); /* MRS_NET_RES16; parameters unset: mrs_fuse is NOT_READY */
+/* A network of the given architecture; INVALID_ARGUMENT for an unknown one. */
+mrs_status mrs_net_create_arch(int32_t arch, mrs_net** out);
 mrs_status mrs_net_destroy(mrs_net* net);
 /* He-uniform weights (bound sqrt(6 / fan_in)) from Philox4x32-10 with key seed,
  * counter (parameter index lo, hi, 0, 2); zero biases.  On the device. */
@@ -315,6 +340,46 @@ mrs_status mrs_net_loss_grad(mrs_net* net, int32_t B, const float* hrls_rgb_dev,
                              const float* target_dev, int32_t W, int32_t H, float* grad_host,
                              double* loss_host, float* out_dev);
 
+/* Forward (saving activations) and backward from a caller-supplied output
+ * gradient dL/dI_SR (grad_out_dev, FP32 B*H*W*3 device buffer, used as BF16)
+ * in place of a built-in loss: for any loss computed outside the library.
+ * Writes the FP32 gradient of every parameter (master layout) to grad_host if
+ * not NULL.  Synchronises. */
+mrs_status mrs_net_backward(mrs_net* net, int32_t B, const float* hrls_rgb_dev,
+                            const float* hrls_aux_dev, const float* lrhs_rgb_dev, int32_t W,
+                            int32_t H, const float* grad_out_dev, float* grad_host);
+
+/* Losses and optimisers of mrs_train_step_ex.
+ * MRS_LOSS_L1      mean |I_SR - t| (t = clip(target, 0, 100)).
+ * MRS_LOSS_ROBUST  the paper's robust loss (Sec. 4): mean |d| / (beta + |d|),
+ *                  d = I_SR - t, beta > 0 (the paper uses 0.1); gradient
+ *                  sign(d) beta / (beta + |d|)^2 / N.  Reduced in FP64.
+ * MRS_OPT_ADAM     Adam as in mrs_train_step (counts its own steps).
+ * MRS_OPT_SGD      w -= lr g (the paper's optimiser). */
+#define MRS_LOSS_L1 0
+#define MRS_LOSS_ROBUST 1
+#define MRS_OPT_ADAM 0
+#define MRS_OPT_SGD 1
+typedef struct mrs_train_opts {
+  int32_t loss;
+  float beta;
+  int32_t optimizer;
+  float lr;
+} mrs_train_opts;
+
+/* mrs_train_step with a choice of loss and optimiser; INVALID_ARGUMENT for an
+ * unknown loss or optimiser, beta <= 0 with the robust loss, or lr <= 0. */
+mrs_status mrs_train_step_ex(mrs_net* net, int32_t B, const float* hrls_rgb_dev,
+                             const float* hrls_aux_dev, const float* lrhs_rgb_dev,
+                             const float* target_dev, int32_t W, int32_t H,
+                             const mrs_train_opts* opts, double* loss_host);
+/* mrs_net_loss_grad with a choice of loss (beta as in mrs_train_opts). */
+mrs_status mrs_net_loss_grad_ex(mrs_net* net, int32_t B, const float* hrls_rgb_dev,
+                                const float* hrls_aux_dev, const float* lrhs_rgb_dev,
+                                const float* target_dev, int32_t W, int32_t H, int32_t loss,
+                                float beta, float* grad_host, double* loss_host,
+                                float* out_dev);
+
 /* Checkpoint state: FP32 masters, Adam first and second moments, step count
  * (host arrays of `count` = MRS_NET_NUM_PARAMS floats).  set_state then
  * continuing is bitwise the same as never having stopped. */
@@ -338,7 +403,7 @@ mrs_status mrs_image_metrics(const float* img_dev, const float* ref_dev, int64_t
 
 /* ------------------------------------------------------- debug / test hooks */
 
-/* FP32 copy of an activation of the last forward on `net`: which 0 = F0,
+/* FP32 copy of an activation of the last mrs_fuse on `net`: which 0 = F0,
  * 1 = FDF, each B*(H/4)*(W/4)*64 values (count must match).  Synchronises. */
 mrs_status mrs_debug_net_activation(const mrs_net* net, int32_t which, float* out_host,
                                     int64_t count);

@@ -53,6 +53,16 @@ class SceneDesc(C.Structure):
                 ("camera", Camera)]
 
 
+NET_ARCHS = {"res16": 0, "rdg": 1}
+LOSSES = {"l1": 0, "robust": 1}
+OPTIMIZERS = {"adam": 0, "sgd": 1}
+
+
+class TrainOpts(C.Structure):
+    _fields_ = [("loss", C.c_int32), ("beta", C.c_float), ("optimizer", C.c_int32),
+                ("lr", C.c_float)]
+
+
 class RenderOpts(C.Structure):
     _fields_ = [("rr_start", C.c_int32), ("x0", C.c_int32), ("y0", C.c_int32),
                 ("win_w", C.c_int32), ("win_h", C.c_int32), ("accum_fp64", C.c_int32),
@@ -124,6 +134,11 @@ def lib():
         "mrs_release_workspaces": ([], I32),
         "mrs_batch_set_seeds": ([P, P], I32),
         "mrs_debug_bvh4": ([P, P, P, P, P], I32),
+        "mrs_net_arch_num_params": ([I32], C.c_int64),
+        "mrs_net_create_arch": ([I32, C.POINTER(P)], I32),
+        "mrs_net_loss_grad_ex": ([P, I32, P, P, P, P, I32, I32, I32, C.c_float, P, P, P], I32),
+        "mrs_train_step_ex": ([P, I32, P, P, P, P, I32, I32, C.POINTER(TrainOpts), P], I32),
+        "mrs_net_backward": ([P, I32, P, P, P, I32, I32, P, P], I32),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(L, name)
@@ -150,7 +165,8 @@ def exported_symbols():
         "mrs_debug_net_activation", "mrs_image_metrics", "mrs_net_loss_grad", "mrs_train_step",
         "mrs_net_get_state", "mrs_net_set_state", "mrs_batch_create", "mrs_batch_render",
         "mrs_batch_destroy", "mrs_release_workspaces", "mrs_batch_set_seeds",
-        "mrs_debug_bvh4",
+        "mrs_debug_bvh4", "mrs_net_arch_num_params", "mrs_net_create_arch",
+        "mrs_net_loss_grad_ex", "mrs_train_step_ex", "mrs_net_backward",
     ]
 
 

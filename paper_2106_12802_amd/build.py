@@ -12,7 +12,7 @@ LIB = os.path.join(HERE, "libmrs.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["api.hip", "lbvh.hip", "trace.hip", "prof.hip", "cnn.hip", "net.hip", "metrics.hip"]
+SOURCES = ["api.hip", "lbvh.hip", "trace.hip", "prof.hip", "cnn.hip", "net.hip", "net_rdg.hip", "metrics.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -52,7 +52,20 @@ __device__ __forceinline__ bf16x8 ld8(const uint16_t* p) {
   return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(p));
 }
 
-// 8 consecutive input channels [c, c+8) of tap `tap` around output pixel (b,y,x).
+// Offset (I, J) inside its r x r block of the HR pixel held by unshuffle slot
+// q.  One stride-r unshuffle: q = I r + J.  Two stacked stride-2 deshuffles
+// (r = 4): the first consumes the low bits, q = 4 (2 (I>>1) + (J>>1)) +
+// 2 (I&1) + (J&1).
+__device__ __forceinline__ void unshuffle_slot(int q, int r, int dsf, int& I, int& J) {
+  if (dsf) {
+    I = ((q >> 3) << 1) | ((q >> 1) & 1);
+    J = (((q >> 2) & 1) << 1) | (q & 1);
+  } else {
+    I = q / r;
+    J = q - I * r;
+  }
+}
+
 // 8 consecutive channels [c, c+8) of the conv input at pixel (b, y, x) through
 // the view (zero outside the image).
 __device__ __forceinline__ bf16x8 view_chunk(const ConvArgs& p, int b, int y, int x, int c) {
@@ -68,7 +81,9 @@ __device__ __forceinline__ bf16x8 view_chunk(const ConvArgs& p, int b, int y, in
       } else {
         const int cc = c - p.ca;
         const int qq = cc / p.cb, ch = cc - qq * p.cb;
-        const int hy = y * p.r + qq / p.r, hx = x * p.r + qq % p.r;
+        int I, J;
+        unshuffle_slot(qq, p.r, p.dsf, I, J);
+        const int hy = y * p.r + I, hx = x * p.r + J;
         ptr = p.b + ((size_t)(b * p.H * p.r + hy) * (p.W * p.r) + hx) * p.cb + ch;
       }
       break;
@@ -206,6 +221,23 @@ __device__ __forceinline__ void conv_epilogue(const ConvArgs& p, const f32x4 (&a
 #pragma unroll
         for (int v = 0; v < 4; ++v) y[r][j][v] += rv[r][j][v];
   }
+  if (p.res3) {
+    float rv[2][NT][4];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int j = 0; j < NT; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          rv[r][j][v] = (m[r][v] >= 0 && nv[j])
+                            ? p.res3[(size_t)m[r][v] * p.cout + n0 + j * 16 + li] : 0.0f;
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int j = 0; j < NT; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) y[r][j][v] += rv[r][j][v];
+  }
 #pragma unroll
   for (int r = 0; r < 2; ++r)
 #pragma unroll
@@ -221,15 +253,18 @@ __device__ __forceinline__ void conv_epilogue(const ConvArgs& p, const f32x4 (&a
 
 // 3x3 convolution with its operands staged in LDS (gfx950 gives a workgroup up
 // to 160 KB).  A block of 8 waves owns a 16 x 16 pixel tile of one image: the
-// (16+2) x (16+2) x CINP input tile with its zero halo is gathered once through
-// the conv's input view (plain, or shuffle+concat for the reconstruction conv),
-// and the weights of one group of 16 NT output channels (K x 16 NT BF16) are
-// loaded once per group; then every MFMA operand comes from LDS.  Wave w
-// computes image rows 2w and 2w+1 of the tile (two 16-pixel row tiles) x 16 NT
-// channels with v_mfma_f32_16x16x32_bf16; K index k = tap CINP + c as in the
-// packed weights, so with CINP < 32 one K step spans two taps.  LDS layouts are
-// chosen for conflict-free 16-byte accesses: tile pixels padded by 8
-// channels, weights chunk-major [k / 8][n][8] with one pad chunk per k row.
+// (16+2) x (16+2) x CINP input tile with its zero halo is gathered through the
+// conv's input view (plain, or shuffle+concat), and the weights of one group
+// of 16 NT output channels (9 CINP x 16 NT BF16) are loaded once per group;
+// then every MFMA operand comes from LDS.  Wave w computes image rows 2w and
+// 2w+1 of the tile (two 16-pixel row tiles) x 16 NT channels with
+// v_mfma_f32_16x16x32_bf16; local K index k = tap CINP + c, so with CINP < 32
+// one K step spans two taps.  Inputs wider than CINP (a multiple of it, CINP =
+// 64: the dense blocks' 128..256-channel convs) are taken CINP channels at a
+// time, tile and weights restaged per channel chunk, the accumulators kept.
+// LDS layouts are chosen for conflict-free 16-byte accesses: tile pixels
+// padded by 8 channels, weights chunk-major [k / 8][n][8] with one pad chunk
+// per k row.
 constexpr int C3_T = 16, C3_THREADS = 512;
 constexpr int C3_TILE = (C3_T + 2) * (C3_T + 2);
 
@@ -245,64 +280,74 @@ __global__ __launch_bounds__(C3_THREADS) void k_conv3_lds(ConvArgs p, int cout_p
   const int lane = tid & 63, wave = tid >> 6;
   const int kq = lane >> 4, li = lane & 15;
   const int x0 = blockIdx.x * C3_T, y0 = blockIdx.y * C3_T, b = blockIdx.z;
+  const int nchunk = p.cin_p / CINP;
   // Loads are issued three at a time before their LDS stores, so that their
   // latencies overlap instead of adding up.
   constexpr int TCH = C3_TILE * (CINP / 8), WCH = NG * (KP / 8);
-  auto tile_load = [&](int i) -> bf16x8 {
-    const int px = i / (CINP / 8), c = (i - px * (CINP / 8)) * 8;
-    const int ty = px / (C3_T + 2), tx = px - ty * (C3_T + 2);
-    return i < TCH ? view_chunk(p, b, y0 - 1 + ty, x0 - 1 + tx, c) : zero8();
-  };
-  auto tile_store = [&](int i, bf16x8 v) {
-    const int px = i / (CINP / 8), c = (i - px * (CINP / 8)) * 8;
-    if (i < TCH) *reinterpret_cast<bf16x8*>(tile + px * PITCH + c) = v;
-  };
-  for (int i = tid; i < TCH; i += 3 * C3_THREADS) {
-    const bf16x8 v0 = tile_load(i), v1 = tile_load(i + C3_THREADS),
-                 v2 = tile_load(i + 2 * C3_THREADS);
-    tile_store(i, v0);
-    tile_store(i + C3_THREADS, v1);
-    tile_store(i + 2 * C3_THREADS, v2);
-  }
   for (int n0 = 0; n0 < cout_p; n0 += NG) {
-    if (n0 > 0) __syncthreads();  // the previous group's weights are no longer read
-    auto w_load = [&](int i) -> uint4 {
-      const int n = i / (KP / 8), kc = i - n * (KP / 8);
-      return i < WCH ? *reinterpret_cast<const uint4*>(p.w + (size_t)(n0 + n) * p.kp + kc * 8)
-                     : make_uint4(0u, 0u, 0u, 0u);
-    };
-    auto w_store = [&](int i, uint4 v) {
-      const int n = i / (KP / 8), kc = i - n * (KP / 8);
-      if (i < WCH) *reinterpret_cast<uint4*>(wts + (kc * WPITCH + n) * 8) = v;
-    };
-    for (int i = tid; i < WCH; i += 3 * C3_THREADS) {
-      const uint4 v0 = w_load(i), v1 = w_load(i + C3_THREADS), v2 = w_load(i + 2 * C3_THREADS);
-      w_store(i, v0);
-      w_store(i + C3_THREADS, v1);
-      w_store(i + 2 * C3_THREADS, v2);
-    }
-    __syncthreads();
     f32x4 acc[2][NT];
 #pragma unroll
     for (int r = 0; r < 2; ++r)
 #pragma unroll
       for (int j = 0; j < NT; ++j) acc[r][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int ks = 0; ks < KP; ks += 32) {
-      const int k = ks + kq * 8;
-      const int tap = k / CINP, c = k - tap * CINP;
-      const int dy = tap / 3, dx = tap - dy * 3;
-      bf16x8 A[2], Bv[NT];
+    for (int ch = 0; ch < nchunk; ++ch) {
+      const int cbase = ch * CINP;
+      if (n0 > 0 || ch > 0) __syncthreads();  // the LDS operands are no longer read
+      if (nchunk > 1 || n0 == 0) {
+        auto tile_load = [&](int i) -> bf16x8 {
+          const int px = i / (CINP / 8), c = (i - px * (CINP / 8)) * 8;
+          const int ty = px / (C3_T + 2), tx = px - ty * (C3_T + 2);
+          return i < TCH ? view_chunk(p, b, y0 - 1 + ty, x0 - 1 + tx, cbase + c) : zero8();
+        };
+        auto tile_store = [&](int i, bf16x8 v) {
+          const int px = i / (CINP / 8), c = (i - px * (CINP / 8)) * 8;
+          if (i < TCH) *reinterpret_cast<bf16x8*>(tile + px * PITCH + c) = v;
+        };
+        for (int i = tid; i < TCH; i += 3 * C3_THREADS) {
+          const bf16x8 v0 = tile_load(i), v1 = tile_load(i + C3_THREADS),
+                       v2 = tile_load(i + 2 * C3_THREADS);
+          tile_store(i, v0);
+          tile_store(i + C3_THREADS, v1);
+          tile_store(i + 2 * C3_THREADS, v2);
+        }
+      }
+      // local k = tap CINP + c holds packed column tap cin_p + cbase + c
+      auto w_load = [&](int i) -> uint4 {
+        const int n = i / (KP / 8), kc = i - n * (KP / 8);
+        const int k = kc * 8, tap = k / CINP;
+        const int kg = tap * p.cin_p + cbase + (k - tap * CINP);
+        return i < WCH ? *reinterpret_cast<const uint4*>(p.w + (size_t)(n0 + n) * p.kp + kg)
+                       : make_uint4(0u, 0u, 0u, 0u);
+      };
+      auto w_store = [&](int i, uint4 v) {
+        const int n = i / (KP / 8), kc = i - n * (KP / 8);
+        if (i < WCH) *reinterpret_cast<uint4*>(wts + (kc * WPITCH + n) * 8) = v;
+      };
+      for (int i = tid; i < WCH; i += 3 * C3_THREADS) {
+        const uint4 v0 = w_load(i), v1 = w_load(i + C3_THREADS), v2 = w_load(i + 2 * C3_THREADS);
+        w_store(i, v0);
+        w_store(i + C3_THREADS, v1);
+        w_store(i + 2 * C3_THREADS, v2);
+      }
+      __syncthreads();
+      for (int ks = 0; ks < KP; ks += 32) {
+        const int k = ks + kq * 8;
+        const int tap = k / CINP, c = k - tap * CINP;
+        const int dy = tap / 3, dx = tap - dy * 3;
+        bf16x8 A[2], Bv[NT];
 #pragma unroll
-      for (int r = 0; r < 2; ++r)
-        A[r] = tap < 9 ? ld8(tile + ((2 * wave + r + dy) * (C3_T + 2) + li + dx) * PITCH + c)
-                       : zero8();
-#pragma unroll
-      for (int j = 0; j < NT; ++j) Bv[j] = ld8(wts + (((ks >> 3) + kq) * WPITCH + j * 16 + li) * 8);
-#pragma unroll
-      for (int r = 0; r < 2; ++r)
+        for (int r = 0; r < 2; ++r)
+          A[r] = tap < 9 ? ld8(tile + ((2 * wave + r + dy) * (C3_T + 2) + li + dx) * PITCH + c)
+                         : zero8();
 #pragma unroll
         for (int j = 0; j < NT; ++j)
-          acc[r][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[r], Bv[j], acc[r][j], 0, 0, 0);
+          Bv[j] = ld8(wts + (((ks >> 3) + kq) * WPITCH + j * 16 + li) * 8);
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+          for (int j = 0; j < NT; ++j)
+            acc[r][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[r], Bv[j], acc[r][j], 0, 0, 0);
+      }
     }
     int64_t m[2][4];
 #pragma unroll
@@ -316,10 +361,15 @@ __global__ __launch_bounds__(C3_THREADS) void k_conv3_lds(ConvArgs p, int cout_p
   }
 }
 
+// Runs the conv on k_conv3_lds<CINP, NT> if its shape fits: cin_p == CINP, or
+// (CINP = 64) a multiple of it taken in chunks; packed K = 9 cin_p rounded up
+// to 32; cout_p a multiple of the channel group.
 template <int CINP, int NT>
 bool try_conv3_lds(const ConvArgs& a, int cout_p, hipStream_t st) {
-  constexpr int KP = (9 * CINP + 31) / 32 * 32;
-  if (a.cin_p != CINP || a.kp != KP || cout_p % (16 * NT)) return false;
+  const bool chunked = CINP == 64 && a.cin_p > CINP && a.cin_p % CINP == 0;
+  if ((a.cin_p != CINP && !chunked) || a.kp != (9 * a.cin_p + 31) / 32 * 32 ||
+      cout_p % (16 * NT))
+    return false;
   k_conv3_lds<CINP, NT><<<dim3((a.W + C3_T - 1) / C3_T, (a.H + C3_T - 1) / C3_T, a.B),
                           C3_THREADS, 0, st>>>(a, cout_p);
   return true;
@@ -392,7 +442,7 @@ __global__ __launch_bounds__(256) void k_dgrad(ConvArgs p, BwdEpi e) {
           } else {
             e.out_f[(size_t)m * e.stride + (n - e.c_split)] = y;
           }
-        } else {  // EPI_FUSE_SPLIT: this conv at LR; [fl | unshuffle(h0)]
+        } else if (e.mode == EPI_FUSE_SPLIT) {  // this conv at LR; [fl | unshuffle(h0)]
           if (n < e.c_split) {
             const size_t idx = (size_t)m * e.c_split + n;
             if (!pos_bf(e.mask[idx])) y = 0.0f;
@@ -400,11 +450,33 @@ __global__ __launch_bounds__(256) void k_dgrad(ConvArgs p, BwdEpi e) {
           } else {
             const int X = m % p.W, t = m / p.W, Y = t % p.H, b = t / p.H;
             const int cc = n - e.c_split, q = cc / e.stride, ch = cc - q * e.stride;
-            const int hy = Y * e.r + q / e.r, hx = X * e.r + q % e.r;
+            int I, J;
+            unshuffle_slot(q, e.r, e.dsf, I, J);
+            const int hy = Y * e.r + I, hx = X * e.r + J;
             const size_t hidx = ((size_t)(b * p.H * e.r + hy) * (p.W * e.r) + hx) * e.stride + ch;
-            float v2 = y + e.add1[hidx];
+            float v2 = e.add1 ? y + e.add1[hidx] : y;
             if (!pos_bf(e.mask2[hidx])) v2 = 0.0f;
             e.out_h2[hidx] = f2bf(v2);
+          }
+        } else {  // EPI_DENSE: input slices 0 .. k-1 of a residual dense block
+          const int sl = n >> 6, ch = n & 63;
+          const size_t gi = (size_t)m * RDG_DENSE + n, i64 = (size_t)m * NET_FEAT + ch;
+          if (e.k == 1) {  // x_0 complete: the gradient of the block input
+            y += e.ga[gi];
+            if (e.add1) y += e.add1[i64];
+            if (e.add2) y += e.add2[i64];
+            if (e.mask0 && !pos_bf(e.dense[gi])) y = 0.0f;
+            if (e.out_f) e.out_f[i64] = y;
+            e.out_h[i64] = f2bf(y);
+          } else if (sl == e.k - 1) {  // x_{k-1} complete: through its ReLU
+            if (!e.fusing) y += e.ga[gi];
+            if (!pos_bf(e.dense[gi])) y = 0.0f;
+            e.dy_next[i64] = f2bf(y);
+          } else if (e.fusing) {
+            if (sl == 0) y += e.ds[i64];
+            e.ga[gi] = y;
+          } else {
+            e.ga[gi] += y;
           }
         }
       }
@@ -601,11 +673,14 @@ __global__ __launch_bounds__(256) void k_grad_reduce(const float* __restrict__ p
   }
 }
 
-// L1 loss pieces (t clipped to [0, 100]): FP64 partial sums of |y - t| per block; the gradient
-// sign(y - t) / N (sign(0) = 0) as BF16 in an 8-channel padded tensor.
+// Loss pieces (t clipped to [0, 100], d = y - t).  beta <= 0: L1, FP64 partial
+// sums of |d| per block and the gradient sign(d) / N.  beta > 0: the robust loss
+// of Sec. 4, partial sums of |d| / (beta + |d|) in FP64 and the gradient
+// sign(d) beta / (beta + |d|)^2 / N.  sign(0) = 0; the gradient is stored as
+// BF16 in an 8-channel padded tensor.
 __global__ __launch_bounds__(256) void k_l1(const float* __restrict__ y,
                                             const float* __restrict__ tgt, int64_t npix,
-                                            double inv_n, double* __restrict__ part,
+                                            double inv_n, float beta, double* __restrict__ part,
                                             uint16_t* __restrict__ g8) {
   __shared__ double sh[256];
   double s = 0.0;
@@ -615,9 +690,18 @@ __global__ __launch_bounds__(256) void k_l1(const float* __restrict__ y,
     for (int c = 0; c < 3; ++c) {
       // targets are clipped to [0, 100] like the training data (fireflies, Sec. 3.2)
       const float d = y[3 * p + c] - fminf(fmaxf(tgt[3 * p + c], 0.0f), 100.0f);
-      s += fabs((double)d);
+      const double ad = fabs((double)d);
       const float gsgn = d > 0.0f ? 1.0f : (d < 0.0f ? -1.0f : 0.0f);
-      const uint32_t h = f2bf(gsgn * (float)inv_n);
+      float gv;
+      if (beta > 0.0f) {
+        s += ad / ((double)beta + ad);
+        const float den = beta + fabsf(d);
+        gv = gsgn * (beta / (den * den)) * (float)inv_n;
+      } else {
+        s += ad;
+        gv = gsgn * (float)inv_n;
+      }
+      const uint32_t h = f2bf(gv);
       w[c >> 1] |= h << (16 * (c & 1));
     }
     *reinterpret_cast<uint4*>(g8 + 8 * p) = make_uint4(w[0], w[1], w[2], w[3]);
@@ -643,6 +727,24 @@ __global__ __launch_bounds__(256) void k_l1_final(const double* __restrict__ par
     __syncthreads();
   }
   if (threadIdx.x == 0) *loss = sh[0] * inv_n;
+}
+
+// A caller-supplied output gradient (FP32 [P][3]) as BF16 in the 8-channel
+// padded layout the backward pass reads.
+__global__ __launch_bounds__(256) void k_grad_in(const float* __restrict__ gout, int64_t npix,
+                                                 uint16_t* __restrict__ g8) {
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= npix) return;
+  const uint32_t w0 = (uint32_t)f2bf(gout[3 * p]) | ((uint32_t)f2bf(gout[3 * p + 1]) << 16);
+  const uint32_t w1 = (uint32_t)f2bf(gout[3 * p + 2]);
+  *reinterpret_cast<uint4*>(g8 + 8 * p) = make_uint4(w0, w1, 0u, 0u);
+}
+
+// Plain SGD on the FP32 masters (the paper's optimiser): w -= lr g.
+__global__ __launch_bounds__(256) void k_sgd(float* __restrict__ w, const float* __restrict__ g,
+                                             int64_t n, float lr) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) w[i] -= lr * g[i];
 }
 
 // Adam (Kingma & Ba 2015, Algorithm 1) on the FP32 masters; c1 = 1 - b1^t,
@@ -700,11 +802,19 @@ void launch_pack_t(const float* wm, const NetLayer& L, uint16_t* wt, hipStream_t
       wm, L.cout, L.cin, L.k, L.cinp_t, L.kp_t, L.coutp_t, wt);
 }
 
-void launch_l1(const float* y, const float* tgt, int64_t npix, double* part, int nparts,
-               double* loss, uint16_t* g8, hipStream_t st) {
-  const double inv_n = 1.0 / (double)(3 * npix);
-  k_l1<<<nparts, 256, 0, st>>>(y, tgt, npix, inv_n, part, g8);
-  k_l1_final<<<1, 256, 0, st>>>(part, nparts, inv_n, loss);
+void launch_out_grad(const OutGrad& o, const float* y, int64_t npix, uint16_t* g8,
+                     hipStream_t st) {
+  if (o.tgt) {
+    const double inv_n = 1.0 / (double)(3 * npix);
+    k_l1<<<o.nparts, 256, 0, st>>>(y, o.tgt, npix, inv_n, o.beta, o.part, g8);
+    k_l1_final<<<1, 256, 0, st>>>(o.part, o.nparts, inv_n, o.loss);
+  } else {
+    k_grad_in<<<cdiv64(npix, 256), 256, 0, st>>>(o.gout, npix, g8);
+  }
+}
+
+void launch_sgd(float* w, const float* g, int64_t n, float lr, hipStream_t st) {
+  k_sgd<<<cdiv64(n, 256), 256, 0, st>>>(w, g, n, lr);
 }
 
 void launch_adam(float* w, const float* g, float* m, float* v, int64_t n, float lr, float b1,
@@ -714,10 +824,10 @@ void launch_adam(float* w, const float* g, float* m, float* v, int64_t n, float 
 
 void launch_conv(const ConvArgs& a, int cout_p, hipStream_t st) {
   if (a.taps == 9 && a.mode != VIEW_CONCAT_UNSHUFFLE &&
-      (a.mode != VIEW_PLAIN || a.ca == a.cin_p)) {
+      (a.mode != VIEW_PLAIN || a.ca >= a.cin_p)) {
     if (cout_p >= 64 ? (try_conv3_lds<64, 4>(a, cout_p, st) || try_conv3_lds<16, 4>(a, cout_p, st) ||
                         try_conv3_lds<8, 4>(a, cout_p, st))
-                     : try_conv3_lds<80, 1>(a, cout_p, st))
+                     : (try_conv3_lds<80, 1>(a, cout_p, st) || try_conv3_lds<64, 1>(a, cout_p, st)))
       return;
   }
   const int64_t M = (int64_t)a.B * a.H * a.W;
@@ -741,7 +851,7 @@ void launch_pack(const float* wm, const NetLayer& L, uint16_t* wp, hipStream_t s
 
 void launch_init(float* dst, const NetLayer& L, uint64_t seed, hipStream_t st) {
   const int64_t nw = (int64_t)L.cout * L.cin * L.k * L.k;
-  const float bound = (float)std::sqrt(6.0 / (double)(L.cin * L.k * L.k));
+  const float bound = (float)(std::sqrt(6.0 / (double)(L.cin * L.k * L.k)) * L.init_scale);
   k_init<<<cdiv64(nw + L.cout, 256), 256, 0, st>>>(dst, nw, L.cout, (int64_t)L.w_off, bound,
                                                    (uint32_t)seed, (uint32_t)(seed >> 32));
 }

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <utility>
 #include <vector>
 
 #include "mrs.h"
@@ -24,6 +25,7 @@ struct ConvArgs {
   int cb;
   int c0;
   int r;
+  int dsf;  // CONCAT_UNSHUFFLE with r = 4: 1 = two stacked stride-2 deshuffles
   int B, H, W;  // output (and input) resolution of this conv
   int cin_p;    // channels per tap as laid out in K (multiple of 8)
   int taps;     // 1 or 9
@@ -35,13 +37,14 @@ struct ConvArgs {
   const float* res;  // optional FP32 [M][cout]: y = res + res_scale * y
   float res_scale;
   const float* res2;  // optional FP32 [M][cout]: y += res2
+  const float* res3;  // optional FP32 [M][cout]: y += res3
   float* out_f;       // optional FP32 output, out_f_stride floats per pixel
   int out_f_stride;
   uint16_t* out_h;  // optional BF16 output, out_h_stride per pixel
   int out_h_stride;
 };
 
-enum EpiMode { EPI_PLAIN = 0, EPI_REC_SPLIT = 1, EPI_FUSE_SPLIT = 2 };
+enum EpiMode { EPI_PLAIN = 0, EPI_REC_SPLIT = 1, EPI_FUSE_SPLIT = 2, EPI_DENSE = 3 };
 
 // Epilogue of a data-gradient conv (output pixel m, channel n, value y).
 struct BwdEpi {
@@ -60,6 +63,17 @@ struct BwdEpi {
   int r;
   const uint16_t* mask2;  // FUSE n >= c_split: mask at the HR index
   uint16_t* out_h2;       // FUSE n >= c_split: BF16 output at the HR index
+  int dsf;                // FUSE: the unshuffle is two stacked stride-2 deshuffles
+  // DENSE: data gradient of the conv of a residual dense block that reads the
+  // first k 64-channel slices of the block's dense tensor [x_0 .. x_3].
+  int k;
+  int fusing;             // the block's last conv: starts the slice gradients
+  float* ga;              // FP32 [M][256] running gradients of slices 0 .. k-2
+  const float* ds;        // fusing: dL/d(block output) [M][64], the local skip's share of x_0
+  const uint16_t* dense;  // the block's dense tensor BF16 [M][256] (ReLU masks)
+  uint16_t* dy_next;      // k >= 2: BF16 [M][64] gradient of x_{k-1} at its conv's output
+  int mask0;              // k == 1: x_0 is a ReLU output (F_0): mask by it
+  // k == 1: dL/dx_0 = ga + acc + add1 + add2 -> out_f (FP32 [M][64], optional), out_h (BF16)
 };
 
 struct WgradArgs {
@@ -72,9 +86,22 @@ struct WgradArgs {
   float* part;           // [splits][cout_p][kp]
 };
 
+// How a backward pass gets its output gradient dL/dI_SR: from a loss of the
+// output against `tgt` (beta 0: L1, > 0: the robust loss; FP64 value in
+// *loss), or (tgt NULL) as given by the caller in `gout` (FP32 [P][3]).
+struct OutGrad {
+  const float* tgt;
+  float beta;
+  const float* gout;
+  double* part;
+  int nparts;
+  double* loss;
+};
 struct NetLayer {
   const char* name;
   int cout, cin, k;
+  int level;         // resolution: 0 HR, 1 HR/2, 2 LR (HR/4)
+  float init_scale;  // multiplies the He-uniform bound
   int cin_p, kp, cout_p;
   int64_t w_off, b_off;  // offsets in the FP32 master vector
   int64_t pk_off;        // offset in the packed BF16 weights
@@ -90,6 +117,38 @@ constexpr int NET_UPCH = 16;
 constexpr float NET_RES_SCALE = 0.1f;
 constexpr int64_t NET_NUM_PARAMS = 1408883;
 
+// The paper's own network (Sec. 4): G residual dense groups of B blocks of 4
+// densely connected convs (growth 64), two stacked stride-2 deshuffles, two
+// stride-2 sub-pixel upscaling steps.
+constexpr int RDG_GROUPS = 3;
+constexpr int RDG_BLOCKS = 5;
+constexpr int RDG_CONVS = 4;
+constexpr int RDG_DENSE = NET_FEAT * RDG_CONVS;  // channels of a block's dense tensor
+constexpr int64_t RDG_NUM_PARAMS = 5907907;
+constexpr int RDG_L_DENSE = 3;                                             // first dense conv
+constexpr int RDG_L_UP = RDG_L_DENSE + RDG_GROUPS * RDG_BLOCKS * RDG_CONVS;  // up0, up1, rec
+
+std::vector<NetLayer> make_layers(int arch);
+size_t align256(size_t v);
+ConvArgs base_args(const mrs_net* net, const NetLayer& L, int B, int H, int W);
+ConvArgs tconv_args(const mrs_net* net, const NetLayer& L, int B, int H, int W,
+                    const uint16_t* dy);
+BwdEpi plain_epi();
+void wgrad(mrs_net* net, const NetLayer& L, const ConvArgs& x, const uint16_t* dy, int dy_stride,
+           hipStream_t st);
+int wgrad_splits(int64_t npix, int& chunk);
+// Split-K partial buffers for the weight gradients at P HR pixels.
+mrs_status ensure_wpart(mrs_net* net, int64_t P, hipStream_t st);
+// The paper's network (net_rdg.hip): forward into out; forward + output
+// gradient + backward into net->d_grad, *out = the network output.
+mrs_status rdg_forward(mrs_net* net, int B, int H, int W, const float* hr, const float* aux,
+                       const float* lr, float* out, hipStream_t st);
+mrs_status rdg_loss_grad(mrs_net* net, int B, int H, int W, const float* hr, const float* aux,
+                         const float* lr, const OutGrad& og, const float** out, hipStream_t st);
+// Carves `plan` (pointer, bytes) out of one device allocation, growing it if needed.
+mrs_status arena_carve(char*& base, size_t& cap, std::vector<std::pair<void**, size_t>>& plan,
+                       hipStream_t st, const char* what);
+
 void launch_conv(const ConvArgs& a, int cout_p, hipStream_t st);
 void launch_prep(int64_t nhr, int64_t nlr, const float* hr, const float* aux, const float* lr,
                  uint16_t* xh, uint16_t* xl, hipStream_t st);
@@ -102,14 +161,16 @@ void launch_bias_partial(const uint16_t* dy, int dy_stride, int cout, int npix, 
 void launch_grad_reduce(const float* part, const float* bpart, int splits, const NetLayer& L,
                         float* g, hipStream_t st);
 void launch_pack_t(const float* wm, const NetLayer& L, uint16_t* wt, hipStream_t st);
-void launch_l1(const float* y, const float* tgt, int64_t npix, double* part, int nparts,
-               double* loss, uint16_t* g8, hipStream_t st);
+void launch_out_grad(const OutGrad& o, const float* y, int64_t npix, uint16_t* g8,
+                     hipStream_t st);
+void launch_sgd(float* w, const float* g, int64_t n, float lr, hipStream_t st);
 void launch_adam(float* w, const float* g, float* m, float* v, int64_t n, float lr, float b1,
                  float b2, float eps, float c1, float c2, hipStream_t st);
 
 }  // namespace mrs
 
 struct mrs_net {
+  int arch = 0;  // MRS_NET_RES16 or MRS_NET_RDG
   std::vector<mrs::NetLayer> layers;
   int64_t nparams = 0;
   int64_t npacked = 0;

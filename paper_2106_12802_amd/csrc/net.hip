@@ -13,33 +13,76 @@ namespace {
 
 int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
-std::vector<NetLayer> make_layers() {
-  struct S {
-    const char* name;
-    int cout, cin, k, cin_p;
-  };
+struct Spec {
+  const char* name;
+  int cout, cin, k, cin_p, level;
+  float init_scale;
+};
+
+// Layer list of the 16-residual-block network.
+std::vector<Spec> specs_res16() {
   static std::vector<std::string> names;
-  std::vector<S> specs = {{"hrls", NET_FEAT, 10, 3, 16},
-                          {"lrhs", NET_FEAT, 3, 3, 8},
-                          {"fuse", NET_FEAT, NET_FEAT + NET_SCALE * NET_SCALE * NET_FEAT, 1,
-                           NET_FEAT + NET_SCALE * NET_SCALE * NET_FEAT}};
+  std::vector<Spec> specs = {{"hrls", NET_FEAT, 10, 3, 16, 0, 1.0f},
+                             {"lrhs", NET_FEAT, 3, 3, 8, 2, 1.0f},
+                             {"fuse", NET_FEAT, NET_FEAT + NET_SCALE * NET_SCALE * NET_FEAT, 1,
+                              NET_FEAT + NET_SCALE * NET_SCALE * NET_FEAT, 2, 1.0f}};
   if (names.empty()) {
     for (int i = 0; i < NET_NRES; ++i) {
       names.push_back("res" + std::to_string(i) + "a");
       names.push_back("res" + std::to_string(i) + "b");
     }
   }
-  for (int i = 0; i < 2 * NET_NRES; ++i) specs.push_back({names[i].c_str(), NET_FEAT, NET_FEAT, 3, NET_FEAT});
-  specs.push_back({"up", NET_UPCH * NET_SCALE * NET_SCALE, NET_FEAT, 3, NET_FEAT});
-  specs.push_back({"rec", 3, NET_UPCH + NET_FEAT, 3, NET_UPCH + NET_FEAT});
+  for (int i = 0; i < 2 * NET_NRES; ++i)
+    specs.push_back({names[i].c_str(), NET_FEAT, NET_FEAT, 3, NET_FEAT, 2, 1.0f});
+  specs.push_back({"up", NET_UPCH * NET_SCALE * NET_SCALE, NET_FEAT, 3, NET_FEAT, 2, 1.0f});
+  specs.push_back({"rec", 3, NET_UPCH + NET_FEAT, 3, NET_UPCH + NET_FEAT, 0, 1.0f});
+  return specs;
+}
+
+// Layer list of the paper's network (Sec. 4): encoders, 1x1 fuse, G x B residual
+// dense blocks of 4 convs (conv c reads 64 (c + 1) channels; the fourth fuses
+// them back to 64 and feeds the block's skip, its initial weights scaled by 0.1
+// so that the chain of 15 skips starts near the identity), two stride-2
+// upscaling convs, reconstruction (also scaled by 0.1, so that the first
+// outputs are near the scale of the images rather than ~10x above it, where
+// the robust loss is flat and training drifts away).
+std::vector<Spec> specs_rdg() {
+  static std::vector<std::string> names;
+  if (names.empty())
+    for (int g = 0; g < RDG_GROUPS; ++g)
+      for (int b = 0; b < RDG_BLOCKS; ++b)
+        for (int c = 0; c < RDG_CONVS; ++c)
+          names.push_back("g" + std::to_string(g) + "b" + std::to_string(b) + "c" +
+                          std::to_string(c));
+  std::vector<Spec> specs = {{"hrls", NET_FEAT, 10, 3, 16, 0, 1.0f},
+                             {"lrhs", NET_FEAT, 3, 3, 8, 2, 1.0f},
+                             {"fuse", NET_FEAT, NET_FEAT + NET_SCALE * NET_SCALE * NET_FEAT, 1,
+                              NET_FEAT + NET_SCALE * NET_SCALE * NET_FEAT, 2, 1.0f}};
+  for (int i = 0; i < RDG_GROUPS * RDG_BLOCKS * RDG_CONVS; ++i) {
+    const int c = i % RDG_CONVS, cin = NET_FEAT * (c + 1);
+    specs.push_back({names[i].c_str(), NET_FEAT, cin, 3, cin, 2,
+                     c == RDG_CONVS - 1 ? 0.1f : 1.0f});
+  }
+  specs.push_back({"up0", 4 * NET_FEAT, NET_FEAT, 3, NET_FEAT, 2, 1.0f});
+  specs.push_back({"up1", 4 * NET_FEAT, NET_FEAT, 3, NET_FEAT, 1, 1.0f});
+  specs.push_back({"rec", 3, NET_FEAT, 3, NET_FEAT, 0, 0.1f});
+  return specs;
+}
+
+}  // namespace
+
+std::vector<NetLayer> make_layers(int arch) {
+  const std::vector<Spec> specs = arch == MRS_NET_RDG ? specs_rdg() : specs_res16();
   std::vector<NetLayer> L;
   int64_t off = 0, pk = 0, pkt = 0;
-  for (const S& s : specs) {
+  for (const Spec& s : specs) {
     NetLayer l;
     l.name = s.name;
     l.cout = s.cout;
     l.cin = s.cin;
     l.k = s.k;
+    l.level = s.level;
+    l.init_scale = s.init_scale;
     l.cin_p = s.cin_p;
     l.kp = round_up(s.k * s.k * s.cin_p, 32);
     l.cout_p = s.cout >= 64 ? round_up(s.cout, 64) : round_up(s.cout, 16);
@@ -68,6 +111,33 @@ std::vector<NetLayer> make_layers() {
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
+mrs_status arena_carve(char*& base, size_t& cap, std::vector<std::pair<void**, size_t>>& plan,
+                       hipStream_t st, const char* what) {
+  size_t total = 0;
+  for (auto& e : plan) total += align256(e.second);
+  if (total > cap) {
+    if (base) {
+      MRS_TRY_HIP(hipStreamSynchronize(st));
+      (void)hipFree(base);
+    }
+    base = nullptr;
+    cap = 0;
+    if (hipMalloc(&base, total) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(MRS_ERR_OUT_OF_MEMORY, std::string(what) + ": device allocation failed");
+    }
+    cap = total;
+  }
+  size_t off = 0;
+  for (auto& e : plan) {
+    *e.first = base + off;
+    off += align256(e.second);
+  }
+  return MRS_OK;
+}
+
+namespace {
+
 struct Arena {
   uint16_t *xh, *xl, *h0, *fl, *f0h, *rh[2], *th, *U;
   float *f0f, *rf[2];
@@ -75,47 +145,16 @@ struct Arena {
 
 mrs_status ensure_arena(mrs_net* net, int B, int H, int W, Arena& A) {
   const size_t P = (size_t)B * H * W, p = P / 16;
-  size_t off = 0;
-  size_t o_xh = off; off += align256(P * 16 * 2);
-  size_t o_xl = off; off += align256(p * 8 * 2);
-  size_t o_h0 = off; off += align256(P * 64 * 2);
-  size_t o_fl = off; off += align256(p * 64 * 2);
-  size_t o_f0f = off; off += align256(p * 64 * 4);
-  size_t o_f0h = off; off += align256(p * 64 * 2);
-  size_t o_rf0 = off; off += align256(p * 64 * 4);
-  size_t o_rf1 = off; off += align256(p * 64 * 4);
-  size_t o_rh0 = off; off += align256(p * 64 * 2);
-  size_t o_rh1 = off; off += align256(p * 64 * 2);
-  size_t o_th = off; off += align256(p * 64 * 2);
-  size_t o_U = off; off += align256(p * 256 * 2);
-  if (off > net->arena_bytes) {
-    if (net->d_arena) {
-      MRS_TRY_HIP(hipStreamSynchronize(current_stream()));
-      (void)hipFree(net->d_arena);
-    }
-    net->d_arena = nullptr;
-    net->arena_bytes = 0;
-    if (hipMalloc(&net->d_arena, off) != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(MRS_ERR_OUT_OF_MEMORY, "mrs_fuse: activation allocation failed");
-    }
-    net->arena_bytes = off;
-  }
-  char* b = net->d_arena;
-  A.xh = (uint16_t*)(b + o_xh);
-  A.xl = (uint16_t*)(b + o_xl);
-  A.h0 = (uint16_t*)(b + o_h0);
-  A.fl = (uint16_t*)(b + o_fl);
-  A.f0f = (float*)(b + o_f0f);
-  A.f0h = (uint16_t*)(b + o_f0h);
-  A.rf[0] = (float*)(b + o_rf0);
-  A.rf[1] = (float*)(b + o_rf1);
-  A.rh[0] = (uint16_t*)(b + o_rh0);
-  A.rh[1] = (uint16_t*)(b + o_rh1);
-  A.th = (uint16_t*)(b + o_th);
-  A.U = (uint16_t*)(b + o_U);
-  return MRS_OK;
+  std::vector<std::pair<void**, size_t>> plan = {
+      {(void**)&A.xh, P * 16 * 2},   {(void**)&A.xl, p * 8 * 2},    {(void**)&A.h0, P * 64 * 2},
+      {(void**)&A.fl, p * 64 * 2},   {(void**)&A.f0f, p * 64 * 4},  {(void**)&A.f0h, p * 64 * 2},
+      {(void**)&A.rf[0], p * 64 * 4}, {(void**)&A.rf[1], p * 64 * 4},
+      {(void**)&A.rh[0], p * 64 * 2}, {(void**)&A.rh[1], p * 64 * 2},
+      {(void**)&A.th, p * 64 * 2},   {(void**)&A.U, p * 256 * 2}};
+  return arena_carve(net->d_arena, net->arena_bytes, plan, current_stream(), "mrs_fuse");
 }
+
+}  // namespace
 
 ConvArgs base_args(const mrs_net* net, const NetLayer& L, int B, int H, int W) {
   ConvArgs a;
@@ -133,8 +172,6 @@ ConvArgs base_args(const mrs_net* net, const NetLayer& L, int B, int H, int W) {
   a.res_scale = 1.0f;
   return a;
 }
-
-}  // namespace
 
 mrs_status net_forward(mrs_net* net, int B, int H, int W, const float* hr, const float* aux,
                        const float* lr, float* out, hipStream_t st) {
@@ -257,77 +294,19 @@ mrs_status net_refresh_packed(mrs_net* net, hipStream_t st) {
 
 // ------------------------------------------------------------------ training
 
-namespace {
-
-struct TrainArena {
-  uint16_t *xh, *xl, *h0, *fl, *f0h, *rh[NET_NRES + 1], *th[NET_NRES], *U, *g8, *dU, *drh, *dth,
-      *df0h, *dflh, *dh0h;
-  float *f0f, *rf[2], *out, *dh0a, *dfdf, *drf[2];
-};
-
-constexpr int L1_PARTS = 256;
-
 int wgrad_splits(int64_t npix, int& chunk) {
   int s = (int)std::min<int64_t>(256, std::max<int64_t>(1, npix / 256));
   chunk = (int)(((npix + s - 1) / s + 31) / 32 * 32);
   return (int)((npix + chunk - 1) / chunk);
 }
 
-mrs_status ensure_train(mrs_net* net, int B, int H, int W, TrainArena& A) {
-  const size_t P = (size_t)B * H * W, p = P / 16;
-  std::vector<std::pair<void**, size_t>> plan;
-  auto add = [&](void** ptr, size_t bytes) { plan.push_back({ptr, bytes}); };
-  add((void**)&A.xh, P * 16 * 2);
-  add((void**)&A.xl, p * 8 * 2);
-  add((void**)&A.h0, P * 64 * 2);
-  add((void**)&A.fl, p * 64 * 2);
-  add((void**)&A.f0f, p * 64 * 4);
-  add((void**)&A.f0h, p * 64 * 2);
-  for (int i = 1; i <= NET_NRES; ++i) add((void**)&A.rh[i], p * 64 * 2);
-  for (int i = 0; i < NET_NRES; ++i) add((void**)&A.th[i], p * 64 * 2);
-  add((void**)&A.rf[0], p * 64 * 4);
-  add((void**)&A.rf[1], p * 64 * 4);
-  add((void**)&A.U, p * 256 * 2);
-  add((void**)&A.out, P * 3 * 4);
-  add((void**)&A.g8, P * 8 * 2);
-  add((void**)&A.dU, p * 256 * 2);
-  add((void**)&A.dh0a, P * 64 * 4);
-  add((void**)&A.dfdf, p * 64 * 4);
-  add((void**)&A.drf[0], p * 64 * 4);
-  add((void**)&A.drf[1], p * 64 * 4);
-  add((void**)&A.drh, p * 64 * 2);
-  add((void**)&A.dth, p * 64 * 2);
-  add((void**)&A.df0h, p * 64 * 2);
-  add((void**)&A.dflh, p * 64 * 2);
-  add((void**)&A.dh0h, P * 64 * 2);
-  size_t total = 0;
-  for (auto& e : plan) total += align256(e.second);
-  hipStream_t st = current_stream();
-  if (total > net->train_bytes) {
-    if (net->d_train) {
-      MRS_TRY_HIP(hipStreamSynchronize(st));
-      (void)hipFree(net->d_train);
-    }
-    net->d_train = nullptr;
-    net->train_bytes = 0;
-    if (hipMalloc(&net->d_train, total) != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(MRS_ERR_OUT_OF_MEMORY, "mrs_train_step: activation allocation failed");
-    }
-    net->train_bytes = total;
-  }
-  size_t off = 0;
-  for (auto& e : plan) {
-    *e.first = net->d_train + off;
-    off += align256(e.second);
-  }
-  A.rh[0] = A.f0h;
-  // split-K partials: the largest layer x split count at these sizes
+// Split-K partial buffers for the weight gradients of every layer at batch
+// size B x H x W (pixel count per layer from its resolution level).
+mrs_status ensure_wpart(mrs_net* net, int64_t P, hipStream_t st) {
   size_t need_w = 0, need_b = 0;
   for (const NetLayer& L : net->layers) {
-    const bool hr = !std::strcmp(L.name, "hrls") || !std::strcmp(L.name, "rec");
     int chunk;
-    const int sp = wgrad_splits(hr ? (int64_t)P : (int64_t)p, chunk);
+    const int sp = wgrad_splits(P >> (2 * L.level), chunk);
     need_w = std::max(need_w, (size_t)sp * L.cout_p * L.kp);
     need_b = std::max(need_b, (size_t)sp * L.cout);
   }
@@ -349,25 +328,6 @@ mrs_status ensure_train(mrs_net* net, int B, int H, int W, TrainArena& A) {
     net->wpart_floats = need_w;
   }
   return MRS_OK;
-}
-
-mrs_status ensure_train_state(mrs_net* net) {
-  if (net->d_grad) return MRS_OK;
-  const size_t n = (size_t)net->nparams;
-  if (hipMalloc(&net->d_grad, sizeof(float) * n) != hipSuccess ||
-      hipMalloc(&net->d_m, sizeof(float) * n) != hipSuccess ||
-      hipMalloc(&net->d_v, sizeof(float) * n) != hipSuccess ||
-      hipMalloc(&net->d_packed_t, sizeof(uint16_t) * net->npacked_t) != hipSuccess ||
-      hipMalloc(&net->d_loss, sizeof(double)) != hipSuccess ||
-      hipMalloc(&net->d_lpart, sizeof(double) * L1_PARTS) != hipSuccess) {
-    (void)hipGetLastError();
-    return fail(MRS_ERR_OUT_OF_MEMORY, "mrs_train_step: optimiser state allocation failed");
-  }
-  hipStream_t st = current_stream();
-  MRS_TRY_HIP(hipMemsetAsync(net->d_m, 0, sizeof(float) * n, st));
-  MRS_TRY_HIP(hipMemsetAsync(net->d_v, 0, sizeof(float) * n, st));
-  net->adam_step = 0;
-  return net_refresh_packed(net, st);
 }
 
 void wgrad(mrs_net* net, const NetLayer& L, const ConvArgs& x, const uint16_t* dy, int dy_stride,
@@ -413,6 +373,69 @@ BwdEpi plain_epi() {
   e.stride = NET_FEAT;
   e.out_h_scale = 1.0f;
   return e;
+}
+
+namespace {
+
+struct TrainArena {
+  uint16_t *xh, *xl, *h0, *fl, *f0h, *rh[NET_NRES + 1], *th[NET_NRES], *U, *g8, *dU, *drh, *dth,
+      *df0h, *dflh, *dh0h;
+  float *f0f, *rf[2], *out, *dh0a, *dfdf, *drf[2];
+};
+
+constexpr int L1_PARTS = 256;
+
+mrs_status ensure_train(mrs_net* net, int B, int H, int W, TrainArena& A) {
+  const size_t P = (size_t)B * H * W, p = P / 16;
+  std::vector<std::pair<void**, size_t>> plan;
+  auto add = [&](void** ptr, size_t bytes) { plan.push_back({ptr, bytes}); };
+  add((void**)&A.xh, P * 16 * 2);
+  add((void**)&A.xl, p * 8 * 2);
+  add((void**)&A.h0, P * 64 * 2);
+  add((void**)&A.fl, p * 64 * 2);
+  add((void**)&A.f0f, p * 64 * 4);
+  add((void**)&A.f0h, p * 64 * 2);
+  for (int i = 1; i <= NET_NRES; ++i) add((void**)&A.rh[i], p * 64 * 2);
+  for (int i = 0; i < NET_NRES; ++i) add((void**)&A.th[i], p * 64 * 2);
+  add((void**)&A.rf[0], p * 64 * 4);
+  add((void**)&A.rf[1], p * 64 * 4);
+  add((void**)&A.U, p * 256 * 2);
+  add((void**)&A.out, P * 3 * 4);
+  add((void**)&A.g8, P * 8 * 2);
+  add((void**)&A.dU, p * 256 * 2);
+  add((void**)&A.dh0a, P * 64 * 4);
+  add((void**)&A.dfdf, p * 64 * 4);
+  add((void**)&A.drf[0], p * 64 * 4);
+  add((void**)&A.drf[1], p * 64 * 4);
+  add((void**)&A.drh, p * 64 * 2);
+  add((void**)&A.dth, p * 64 * 2);
+  add((void**)&A.df0h, p * 64 * 2);
+  add((void**)&A.dflh, p * 64 * 2);
+  add((void**)&A.dh0h, P * 64 * 2);
+  hipStream_t st = current_stream();
+  mrs_status rc = arena_carve(net->d_train, net->train_bytes, plan, st, "mrs_train_step");
+  if (rc != MRS_OK) return rc;
+  A.rh[0] = A.f0h;
+  return ensure_wpart(net, (int64_t)P, st);
+}
+
+mrs_status ensure_train_state(mrs_net* net) {
+  if (net->d_grad) return MRS_OK;
+  const size_t n = (size_t)net->nparams;
+  if (hipMalloc(&net->d_grad, sizeof(float) * n) != hipSuccess ||
+      hipMalloc(&net->d_m, sizeof(float) * n) != hipSuccess ||
+      hipMalloc(&net->d_v, sizeof(float) * n) != hipSuccess ||
+      hipMalloc(&net->d_packed_t, sizeof(uint16_t) * net->npacked_t) != hipSuccess ||
+      hipMalloc(&net->d_loss, sizeof(double)) != hipSuccess ||
+      hipMalloc(&net->d_lpart, sizeof(double) * L1_PARTS) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(MRS_ERR_OUT_OF_MEMORY, "mrs_train_step: optimiser state allocation failed");
+  }
+  hipStream_t st = current_stream();
+  MRS_TRY_HIP(hipMemsetAsync(net->d_m, 0, sizeof(float) * n, st));
+  MRS_TRY_HIP(hipMemsetAsync(net->d_v, 0, sizeof(float) * n, st));
+  net->adam_step = 0;
+  return net_refresh_packed(net, st);
 }
 
 // Forward keeping every activation the backward pass reads.
@@ -620,21 +643,45 @@ mrs_status check_train_args(mrs_net* n, int B, const float* hr, const float* aux
   return MRS_OK;
 }
 
+// Forward, output gradient (a loss against tgt, or the caller's gout when tgt
+// is NULL) and backward into n->d_grad; *out = the network output.
 mrs_status loss_and_grad(mrs_net* n, int B, const float* hr, const float* aux, const float* lr,
-                         const float* tgt, int W, int H, hipStream_t st) {
+                         const float* tgt, const float* gout, int W, int H, float beta,
+                         hipStream_t st, const float** out) {
   mrs_status rc = ensure_train_state(n);
   if (rc != MRS_OK) return rc;
+  OutGrad og;
+  og.tgt = tgt;
+  og.beta = beta;
+  og.gout = gout;
+  og.part = n->d_lpart;
+  og.nparts = L1_PARTS;
+  og.loss = n->d_loss;
+  if (n->arch == MRS_NET_RDG) return rdg_loss_grad(n, B, H, W, hr, aux, lr, og, out, st);
   TrainArena A;
   rc = ensure_train(n, B, H, W, A);
   if (rc != MRS_OK) return rc;
   prof_begin(KID_TRAIN_FWD, st);
   forward_train(n, A, B, H, W, hr, aux, lr, st);
   prof_end(KID_TRAIN_FWD, st);
-  launch_l1(A.out, tgt, (int64_t)B * H * W, n->d_lpart, L1_PARTS, n->d_loss, A.g8, st);
+  launch_out_grad(og, A.out, (int64_t)B * H * W, A.g8, st);
   prof_begin(KID_TRAIN_BWD, st);
   backward(n, A, B, H, W, st);
   prof_end(KID_TRAIN_BWD, st);
   MRS_TRY_HIP(hipGetLastError());
+  *out = A.out;
+  return MRS_OK;
+}
+
+int64_t arch_params(int32_t arch) {
+  return arch == MRS_NET_RES16 ? NET_NUM_PARAMS : arch == MRS_NET_RDG ? RDG_NUM_PARAMS : -1;
+}
+
+mrs_status check_loss(int32_t loss, float beta, const char* who) {
+  if (loss != MRS_LOSS_L1 && loss != MRS_LOSS_ROBUST)
+    return fail(MRS_ERR_INVALID_ARGUMENT, std::string(who) + ": unknown loss");
+  if (loss == MRS_LOSS_ROBUST && !(beta > 0.0f && std::isfinite(beta)))
+    return fail(MRS_ERR_INVALID_ARGUMENT, std::string(who) + ": the robust loss needs beta > 0");
   return MRS_OK;
 }
 
@@ -648,18 +695,22 @@ extern "C" {
 
 int64_t mrs_net_num_params(void) { return NET_NUM_PARAMS; }
 
-mrs_status mrs_net_create(mrs_net** out) {
+int64_t mrs_net_arch_num_params(int32_t arch) { return arch_params(arch); }
+
+mrs_status mrs_net_create_arch(int32_t arch, mrs_net** out) {
   if (!out) return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_net_create: out is NULL");
   *out = nullptr;
+  if (arch_params(arch) < 0) return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_net_create: unknown arch");
   mrs_net* n = new mrs_net();
-  n->layers = make_layers();
+  n->arch = arch;
+  n->layers = make_layers(arch);
   const NetLayer& last = n->layers.back();
   n->nparams = last.b_off + last.cout;
   n->npacked = last.pk_off + (int64_t)last.cout_p * last.kp;
   n->npacked_t = 0;
   for (const NetLayer& L : n->layers)
     if (L.pkt_off >= 0) n->npacked_t = std::max(n->npacked_t, L.pkt_off + (int64_t)L.coutp_t * L.kp_t);
-  if (n->nparams != NET_NUM_PARAMS) {
+  if (n->nparams != arch_params(arch)) {
     delete n;
     return fail(MRS_ERR_DEVICE, "mrs_net_create: internal layer table mismatch");
   }
@@ -673,6 +724,8 @@ mrs_status mrs_net_create(mrs_net** out) {
   *out = n;
   return MRS_OK;
 }
+
+mrs_status mrs_net_create(mrs_net** out) { return mrs_net_create_arch(MRS_NET_RES16, out); }
 
 mrs_status mrs_net_destroy(mrs_net* n) {
   if (!n) return MRS_OK;
@@ -734,6 +787,7 @@ mrs_status mrs_fuse_batch(mrs_net* n, int32_t B, const float* hr, const float* a
   if (((uintptr_t)hr | (uintptr_t)aux | (uintptr_t)lr | (uintptr_t)out) & 3u)
     return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_fuse: buffers must be 4-byte aligned");
   if (!n->has_params) return fail(MRS_ERR_NOT_READY, "mrs_fuse: no network parameters loaded");
+  if (n->arch == MRS_NET_RDG) return rdg_forward(n, B, H, W, hr, aux, lr, out, current_stream());
   return net_forward(n, B, H, W, hr, aux, lr, out, current_stream());
 }
 
@@ -742,21 +796,22 @@ mrs_status mrs_fuse(mrs_net* n, const float* hr, const float* aux, const float* 
   return mrs_fuse_batch(n, 1, hr, aux, lr, W, H, out);
 }
 
-mrs_status mrs_net_loss_grad(mrs_net* n, int32_t B, const float* hr, const float* aux,
-                            const float* lr, const float* tgt, int32_t W, int32_t H,
-                            float* grad_host, double* loss_host, float* out_dev) {
+mrs_status mrs_net_loss_grad_ex(mrs_net* n, int32_t B, const float* hr, const float* aux,
+                                const float* lr, const float* tgt, int32_t W, int32_t H,
+                                int32_t loss, float beta, float* grad_host, double* loss_host,
+                                float* out_dev) {
   mrs_status rc = check_train_args(n, B, hr, aux, lr, tgt, W, H);
   if (rc != MRS_OK) return rc;
-  hipStream_t st = current_stream();
-  rc = loss_and_grad(n, B, hr, aux, lr, tgt, W, H, st);
+  rc = check_loss(loss, beta, "mrs_net_loss_grad");
   if (rc != MRS_OK) return rc;
-  if (out_dev) {
-    const size_t P = (size_t)B * H * W;
-    TrainArena A;
-    rc = ensure_train(n, B, H, W, A);
-    if (rc != MRS_OK) return rc;
-    MRS_TRY_HIP(hipMemcpyAsync(out_dev, A.out, sizeof(float) * 3 * P, hipMemcpyDeviceToDevice, st));
-  }
+  hipStream_t st = current_stream();
+  const float* out = nullptr;
+  rc = loss_and_grad(n, B, hr, aux, lr, tgt, nullptr, W, H, loss == MRS_LOSS_ROBUST ? beta : 0.0f,
+                     st, &out);
+  if (rc != MRS_OK) return rc;
+  if (out_dev)
+    MRS_TRY_HIP(hipMemcpyAsync(out_dev, out, sizeof(float) * 3 * (size_t)B * H * W,
+                               hipMemcpyDeviceToDevice, st));
   if (grad_host)
     MRS_TRY_HIP(hipMemcpyAsync(grad_host, n->d_grad, sizeof(float) * n->nparams,
                                hipMemcpyDeviceToHost, st));
@@ -765,22 +820,56 @@ mrs_status mrs_net_loss_grad(mrs_net* n, int32_t B, const float* hr, const float
   return MRS_OK;
 }
 
-mrs_status mrs_train_step(mrs_net* n, int32_t B, const float* hr, const float* aux,
-                          const float* lr, const float* tgt, int32_t W, int32_t H, float lr_rate,
-                          double* loss_host) {
+mrs_status mrs_net_backward(mrs_net* n, int32_t B, const float* hr, const float* aux,
+                            const float* lr, int32_t W, int32_t H, const float* grad_out_dev,
+                            float* grad_host) {
+  mrs_status rc = check_train_args(n, B, hr, aux, lr, grad_out_dev, W, H);
+  if (rc != MRS_OK) return rc;
+  hipStream_t st = current_stream();
+  const float* out = nullptr;
+  rc = loss_and_grad(n, B, hr, aux, lr, nullptr, grad_out_dev, W, H, 0.0f, st, &out);
+  if (rc != MRS_OK) return rc;
+  if (grad_host)
+    MRS_TRY_HIP(hipMemcpyAsync(grad_host, n->d_grad, sizeof(float) * n->nparams,
+                               hipMemcpyDeviceToHost, st));
+  MRS_TRY_HIP(hipStreamSynchronize(st));
+  return MRS_OK;
+}
+
+mrs_status mrs_net_loss_grad(mrs_net* n, int32_t B, const float* hr, const float* aux,
+                             const float* lr, const float* tgt, int32_t W, int32_t H,
+                             float* grad_host, double* loss_host, float* out_dev) {
+  return mrs_net_loss_grad_ex(n, B, hr, aux, lr, tgt, W, H, MRS_LOSS_L1, 0.0f, grad_host,
+                              loss_host, out_dev);
+}
+
+mrs_status mrs_train_step_ex(mrs_net* n, int32_t B, const float* hr, const float* aux,
+                             const float* lr, const float* tgt, int32_t W, int32_t H,
+                             const mrs_train_opts* opts, double* loss_host) {
   mrs_status rc = check_train_args(n, B, hr, aux, lr, tgt, W, H);
   if (rc != MRS_OK) return rc;
-  if (!(lr_rate > 0.0f) || !std::isfinite(lr_rate))
+  if (!opts) return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_train_step: opts is NULL");
+  rc = check_loss(opts->loss, opts->beta, "mrs_train_step");
+  if (rc != MRS_OK) return rc;
+  if (opts->optimizer != MRS_OPT_ADAM && opts->optimizer != MRS_OPT_SGD)
+    return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_train_step: unknown optimizer");
+  if (!(opts->lr > 0.0f) || !std::isfinite(opts->lr))
     return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_train_step: learning rate must be positive");
   hipStream_t st = current_stream();
-  rc = loss_and_grad(n, B, hr, aux, lr, tgt, W, H, st);
+  const float* out = nullptr;
+  rc = loss_and_grad(n, B, hr, aux, lr, tgt, nullptr, W, H,
+                     opts->loss == MRS_LOSS_ROBUST ? opts->beta : 0.0f, st, &out);
   if (rc != MRS_OK) return rc;
-  n->adam_step += 1;
-  const double t = (double)n->adam_step;
-  const float c1 = (float)(1.0 - std::pow(0.9, t)), c2 = (float)(1.0 - std::pow(0.999, t));
   prof_begin(KID_TRAIN_ADAM, st);
-  launch_adam(n->d_master, n->d_grad, n->d_m, n->d_v, n->nparams, lr_rate, 0.9f, 0.999f, 1e-8f,
-              c1, c2, st);
+  if (opts->optimizer == MRS_OPT_ADAM) {
+    n->adam_step += 1;
+    const double t = (double)n->adam_step;
+    const float c1 = (float)(1.0 - std::pow(0.9, t)), c2 = (float)(1.0 - std::pow(0.999, t));
+    launch_adam(n->d_master, n->d_grad, n->d_m, n->d_v, n->nparams, opts->lr, 0.9f, 0.999f,
+                1e-8f, c1, c2, st);
+  } else {
+    launch_sgd(n->d_master, n->d_grad, n->nparams, opts->lr, st);
+  }
   rc = net_refresh_packed(n, st);
   prof_end(KID_TRAIN_ADAM, st);
   if (rc != MRS_OK) return rc;
@@ -789,6 +878,17 @@ mrs_status mrs_train_step(mrs_net* n, int32_t B, const float* hr, const float* a
     MRS_TRY_HIP(hipStreamSynchronize(st));
   }
   return MRS_OK;
+}
+
+mrs_status mrs_train_step(mrs_net* n, int32_t B, const float* hr, const float* aux,
+                          const float* lr, const float* tgt, int32_t W, int32_t H, float lr_rate,
+                          double* loss_host) {
+  mrs_train_opts o;
+  o.loss = MRS_LOSS_L1;
+  o.beta = 0.0f;
+  o.optimizer = MRS_OPT_ADAM;
+  o.lr = lr_rate;
+  return mrs_train_step_ex(n, B, hr, aux, lr, tgt, W, H, &o, loss_host);
 }
 
 mrs_status mrs_net_get_state(const mrs_net* n, float* params, float* m, float* v, int64_t count,

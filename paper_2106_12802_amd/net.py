@@ -9,15 +9,21 @@ from . import _lib as L
 
 
 class FusionNet:
-    """The HRLS + LRHS fusion network; parameters live on the GPU (FP32 masters + BF16)."""
+    """The HRLS + LRHS fusion network; parameters live on the GPU (FP32 masters + BF16).
 
-    def __init__(self, seed: int | None = None):
+    arch "res16": 16 residual blocks; "rdg": the paper's network of residual
+    dense groups (include/mrs.h documents both)."""
+
+    def __init__(self, seed: int | None = None, arch: str = "res16"):
         import torch  # noqa: F401  (initialises the HIP runtime through torch)
+        if arch not in L.NET_ARCHS:
+            raise ValueError(f"unknown arch {arch!r}")
+        self.arch = arch
         L.use_current_stream()
         h = C.c_void_p()
-        L.check(L.lib().mrs_net_create(C.byref(h)))
+        L.check(L.lib().mrs_net_create_arch(L.NET_ARCHS[arch], C.byref(h)))
         self.handle = h
-        self.num_params = int(L.lib().mrs_net_num_params())
+        self.num_params = int(L.lib().mrs_net_arch_num_params(L.NET_ARCHS[arch]))
         self.ready = False  # parameters loaded (mrs_fuse refuses to run before)
         if seed is not None:
             self.init(seed)
@@ -61,35 +67,54 @@ class FusionNet:
         B = hrls_rgb.shape[0] if batched else 1
         return B, hrls_rgb.shape[-3], hrls_rgb.shape[-2]
 
-    def loss_grad(self, hrls_rgb, hrls_aux, lrhs_rgb, target):
-        """(grad [num_params] float32, L1 loss (FP64), network output tensor); no update."""
+    def loss_grad(self, hrls_rgb, hrls_aux, lrhs_rgb, target, loss="l1", beta=0.1):
+        """(grad [num_params] float32, loss (FP64), network output tensor); no update.
+
+        loss "l1" or "robust" (the paper's l_r with robust factor beta)."""
         import torch
         B, H, W = self._dims(hrls_rgb)
         g = np.empty(self.num_params, np.float32)
-        loss = C.c_double()
+        value = C.c_double()
         out = torch.empty(hrls_rgb.shape, dtype=torch.float32, device=hrls_rgb.device)
         L.use_current_stream()
         P = B * H * W
-        L.check(L.lib().mrs_net_loss_grad(self.handle, B, L.ptr(hrls_rgb, 3 * P, "f32"),
-                                          L.ptr(hrls_aux, 7 * P, "f32"),
-                                          L.ptr(lrhs_rgb, 3 * P // 16, "f32"),
-                                          L.ptr(target, 3 * P, "f32"), W, H,
-                                          g.ctypes.data_as(C.c_void_p), C.byref(loss),
-                                          L.ptr(out)))
-        return g, loss.value, out
+        L.check(L.lib().mrs_net_loss_grad_ex(self.handle, B, L.ptr(hrls_rgb, 3 * P, "f32"),
+                                             L.ptr(hrls_aux, 7 * P, "f32"),
+                                             L.ptr(lrhs_rgb, 3 * P // 16, "f32"),
+                                             L.ptr(target, 3 * P, "f32"), W, H,
+                                             L.LOSSES[loss], float(beta),
+                                             g.ctypes.data_as(C.c_void_p), C.byref(value),
+                                             L.ptr(out)))
+        return g, value.value, out
 
-    def train_step(self, hrls_rgb, hrls_aux, lrhs_rgb, target, lr=1e-4, want_loss=False):
-        """One Adam step on the L1 loss; returns the loss (synchronising) if want_loss."""
+    def backward(self, hrls_rgb, hrls_aux, lrhs_rgb, grad_out):
+        """Parameter gradient [num_params] float32 for a given dL/dI_SR (CUDA fp32)."""
         B, H, W = self._dims(hrls_rgb)
-        loss = C.c_double()
+        g = np.empty(self.num_params, np.float32)
         L.use_current_stream()
         P = B * H * W
-        L.check(L.lib().mrs_train_step(self.handle, B, L.ptr(hrls_rgb, 3 * P, "f32"),
-                                       L.ptr(hrls_aux, 7 * P, "f32"),
-                                       L.ptr(lrhs_rgb, 3 * P // 16, "f32"),
-                                       L.ptr(target, 3 * P, "f32"), W, H, float(lr),
-                                       C.byref(loss) if want_loss else None))
-        return loss.value if want_loss else None
+        L.check(L.lib().mrs_net_backward(self.handle, B, L.ptr(hrls_rgb, 3 * P, "f32"),
+                                         L.ptr(hrls_aux, 7 * P, "f32"),
+                                         L.ptr(lrhs_rgb, 3 * P // 16, "f32"), W, H,
+                                         L.ptr(grad_out, 3 * P, "f32"),
+                                         g.ctypes.data_as(C.c_void_p)))
+        return g
+
+    def train_step(self, hrls_rgb, hrls_aux, lrhs_rgb, target, lr=1e-4, want_loss=False,
+                   loss="l1", beta=0.1, optimizer="adam"):
+        """One optimiser step ("adam" or "sgd") on the loss ("l1" or "robust");
+        returns the loss of this step (synchronising) if want_loss."""
+        B, H, W = self._dims(hrls_rgb)
+        value = C.c_double()
+        opts = L.TrainOpts(L.LOSSES[loss], float(beta), L.OPTIMIZERS[optimizer], float(lr))
+        L.use_current_stream()
+        P = B * H * W
+        L.check(L.lib().mrs_train_step_ex(self.handle, B, L.ptr(hrls_rgb, 3 * P, "f32"),
+                                          L.ptr(hrls_aux, 7 * P, "f32"),
+                                          L.ptr(lrhs_rgb, 3 * P // 16, "f32"),
+                                          L.ptr(target, 3 * P, "f32"), W, H, C.byref(opts),
+                                          C.byref(value) if want_loss else None))
+        return value.value if want_loss else None
 
     def get_state(self):
         """(params, adam m, adam v, step) as host arrays: a resumable checkpoint."""

@@ -83,3 +83,20 @@ def test_missing_library_fails_loudly(monkeypatch):
     monkeypatch.setattr(_lib, "LIB_PATH", "/nonexistent/libmrs.so")
     with pytest.raises(RuntimeError, match="no fallback"):
         _lib.lib()
+
+
+def test_net_arch_and_training_option_validation():
+    from oracle import cnn, cnn_rdg
+    from paper_2106_12802_amd import _lib
+    L = _lib.lib()
+    assert L.mrs_net_arch_num_params(_lib.NET_ARCHS["res16"]) == cnn.num_params()
+    assert L.mrs_net_arch_num_params(_lib.NET_ARCHS["rdg"]) == cnn_rdg.num_params()
+    assert L.mrs_net_arch_num_params(7) == -1
+    h = C.c_void_p()
+    assert L.mrs_net_create_arch(7, C.byref(h)) == 1 and not h.value
+    assert b"arch" in L.mrs_last_error()
+    assert C.sizeof(_lib.TrainOpts) == 16
+    opts = _lib.TrainOpts(_lib.LOSSES["robust"], 0.1, _lib.OPTIMIZERS["sgd"], 1e-4)
+    assert L.mrs_train_step_ex(None, 1, None, None, None, None, 4, 4, C.byref(opts), None) == 1
+    assert L.mrs_net_loss_grad_ex(None, 1, None, None, None, None, 4, 4, 1, 0.1, None, None,
+                                  None) == 1

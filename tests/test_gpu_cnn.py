@@ -123,15 +123,20 @@ def test_gradient_parity(torch_cuda, B, H, W):
     hr, aux, lr = _inputs(H + W, B, H, W)
     tgt = np.random.default_rng(B).gamma(1.0, 0.5, (B, H, W, 3)).astype(np.float32)
     t = [torch.from_numpy(a).cuda() for a in (hr, aux, lr, tgt)]
-    g_gpu, loss_gpu, out_gpu = net.loss_grad(*t)
+    g_loss, loss_gpu, out_gpu = net.loss_grad(*t)
     out_gpu = out_gpu.cpu().numpy().astype(np.float64)
     params = net.get_params().astype(np.float64)
     o, acts = cnn.forward(params, hr, aux, lr, keep=True)
     assert loss_gpu == pytest.approx(np.abs(out_gpu - tgt).mean(), rel=1e-6)
     assert abs(loss_gpu - cnn.l1_loss(o, tgt)) <= 5e-3 * cnn.l1_loss(o, tgt)
-    # the oracle's backward from the output gradient the GPU used (signs of its own output)
-    gout = np.sign(out_gpu - tgt) / out_gpu.size
+    # the built-in L1 gradient is the caller-supplied one of the same value
+    gl = (np.sign(out_gpu - tgt) / np.float32(out_gpu.size)).astype(np.float32)
+    g_in = net.backward(*t[:3], torch.from_numpy(gl).cuda())
+    assert np.array_equal(g_in, g_loss)
+    # the oracle's output gradient, from its own output, through the GPU backward
+    gout = cnn.l1_grad(o, tgt)
     g_ref = cnn.backward(params, acts, gout)
+    g_gpu = net.backward(*t[:3], torch.from_numpy(gout.astype(np.float32)).cuda())
     # Each BF16-stored gradient tensor adds ~2^-9 sqrt(2) = 2.8e-3 relative error;
     # the encoders sit ~38 such tensors below the loss (rec, up, 32 trunk convs,
     # fuse), so ~1.7e-2 in quadrature, plus ReLU-mask disagreements between the
