@@ -17,7 +17,9 @@
 //       triangles, ties to the smaller primitive id
 //   E5  shading frame, orthonormal basis of Duff et al. (JCGT 2017)
 //   E7  path loop with pbrt-style depth counting
-//   E8  next-event estimation on quad lights, area sampling
+//   E8  next-event estimation on quad lights, area sampling; optionally (mis)
+//       combined with BSDF sampling of the same lights by multiple importance
+//       sampling with the power heuristic (Veach & Guibas, SIGGRAPH 1995)
 //   E9  Lambert BRDF, cosine-weighted sampling
 //   E10 GGX microfacet BRDF (Walter et al., EGSR 2007), separable Smith G,
 //       Schlick Fresnel, sampling of the half vector from D(h)(n.h)
@@ -397,6 +399,14 @@ V3 sample_ggx_h(double alpha, double u1, double u2) {
   double phi = 2.0 * M_PI * u2;
   return mk(sint * std::cos(phi), sint * std::sin(phi), cost);
 }
+// Density (solid angle) of the reflected direction wi when the half vector is
+// sampled with density D(h)(n.h): D(h)(n.h) / (4 wo.h).
+double ggx_pdf(double alpha, V3 n, V3 wo, V3 wi) {
+  V3 h = normalize(wi + wo);
+  double ch = dot(n, h), oh = dot(wo, h);
+  if (ch <= 0.0 || oh <= 0.0) return 0.0;
+  return ggx_D(alpha, ch) * ch / (4.0 * oh);
+}
 // f(wo, wi) for the GGX lobe; n is the shading normal.
 V3 ggx_eval(const MatD& m, V3 n, V3 wo, V3 wi) {
   double cos_i = dot(n, wi), cos_o = dot(n, wo);
@@ -428,8 +438,18 @@ struct PathOut {
   int64_t segments;
 };
 
+// Power-heuristic weight (exponent 2) of a strategy with density a against one
+// with density b.
+double power_weight(double a, double b) { return a * a / (a * a + b * b); }
+
+// Density (solid angle, from the NEE strategy) of reaching light `lt` along a
+// direction that meets it at distance t with cosine cl at the light.
+double light_pdf(const Scene& sc, const Light& lt, double t, double cl) {
+  return t * t / ((double)sc.lights.size() * lt.area * cl);
+}
+
 PathOut trace_path(const Scene& sc, bool use_bvh, int W, int H, int px, int py, int s,
-                   int max_depth, int rr_start, uint64_t seed) {
+                   int max_depth, int rr_start, uint64_t seed, bool mis) {
   PathOut out;
   out.L = mk(0, 0, 0);
   for (int i = 0; i < 7; ++i) out.aux[i] = 0.0;
@@ -440,6 +460,7 @@ PathOut trace_path(const Scene& sc, bool use_bvh, int W, int H, int px, int py, 
   V3 o, d;
   camera_ray(sc.cam, W, H, px + to_unit(b0.w[0]), py + to_unit(b0.w[1]), &o, &d);
   V3 beta = mk(1, 1, 1), L = mk(0, 0, 0);
+  double bsdf_pdf = 0.0;  // density of the BSDF sample that led to this vertex (mis)
   int32_t skip = -1;
   const int nL = (int)sc.lights.size();
   for (int b = 0;; ++b) {
@@ -481,9 +502,25 @@ PathOut trace_path(const Scene& sc, bool use_bvh, int W, int H, int px, int py, 
       out.aux[6] = h.t;
     }
     // Emission from front faces.  Listed quad lights count only when seen
-    // directly (b = 0): afterwards next-event estimation accounts for them.
+    // directly (b = 0): afterwards next-event estimation accounts for them --
+    // or, with mis, BSDF sampling shares them with next-event estimation,
+    // weighted by the power heuristic against the light-sampling density.
     if (front && (m.emission.x != 0.0 || m.emission.y != 0.0 || m.emission.z != 0.0)) {
-      if (!tr.listed_light || b == 0) L = L + mul(beta, m.emission);
+      if (!tr.listed_light || b == 0) {
+        L = L + mul(beta, m.emission);
+      } else if (mis) {
+        const Light* lt = nullptr;
+        for (const Light& l : sc.lights)
+          if (l.tri0 == h.prim || l.tri1 == h.prim) {
+            lt = &l;
+            break;
+          }
+        const double cl = dot(lt->normal, wo);
+        if (cl > 0.0) {
+          const double w = power_weight(bsdf_pdf, light_pdf(sc, *lt, h.t, cl));
+          L = L + mul(beta, m.emission) * w;
+        }
+      }
     }
     if (b == max_depth || m.kind == 2) break;
     if (dot(ns, wo) <= 0.0) break;  // shading normal faces away from the viewer
@@ -507,6 +544,10 @@ PathOut trace_path(const Scene& sc, bool use_bvh, int W, int H, int px, int py, 
           V3 f = m.kind == 0 ? m.color * (1.0 / M_PI) : ggx_eval(m, ns, wo, wi);
           double pdfA = 1.0 / ((double)nL * lt.area);
           V3 c = mul(mul(beta, f), lt.le) * (cs * cl / (r2 * pdfA));
+          if (mis) {
+            const double pb = m.kind == 0 ? cs / M_PI : ggx_pdf(m.alpha, ns, wo, wi);
+            c = c * power_weight(light_pdf(sc, lt, r, cl), pb);
+          }
           L = L + c;
         }
         out.segments++;
@@ -521,6 +562,7 @@ PathOut trace_path(const Scene& sc, bool use_bvh, int W, int H, int px, int py, 
       wi = to_world(sample_cosine(v1, v2), T, B, ns);
       if (dot(ng, wi) <= 0.0) break;
       beta = mul(beta, m.color);
+      bsdf_pdf = dot(ns, wi) / M_PI;
     } else {
       V3 hh = to_world(sample_ggx_h(m.alpha, v1, v2), T, B, ns);
       double oh = dot(wo, hh);
@@ -531,6 +573,7 @@ PathOut trace_path(const Scene& sc, bool use_bvh, int W, int H, int px, int py, 
       double G = ggx_G1(m.alpha, ci) * ggx_G1(m.alpha, co);
       V3 F = schlick(m.color, oh);
       beta = mul(beta, F * (G * oh / (co * ch)));
+      bsdf_pdf = ggx_D(m.alpha, ch) * ch / (4.0 * oh);
     }
     // ---- E11: Russian roulette from vertex rr_start on
     if (b >= rr_start) {
@@ -682,13 +725,14 @@ void orc_ggx_eval(double alpha, const double* f0, const double* n, const double*
 // Render: for each requested pixel (all W*H when pixels == NULL), the mean over
 // spp samples of the path radiance (E12: summed in sample order) and of the
 // first-hit features.  out_sumsq (optional) receives sum_s L^2 per channel.
+// mis = 1 combines next-event estimation and BSDF sampling of the quad lights.
 // counters[0] = non-finite samples replaced by 0, counters[1] = rays traced.
 int32_t orc_render(void* s, int32_t W, int32_t H, int32_t spp, int32_t max_depth,
                    int32_t rr_start, uint64_t seed, int32_t npix, const int32_t* pixels,
                    double* out_rgb, double* out_aux, double* out_sumsq, int32_t nthreads,
-                   int32_t use_bvh, int64_t* counters) {
+                   int32_t use_bvh, int32_t mis, int64_t* counters) {
   const Scene& sc = *(const Scene*)s;
-  if (W <= 0 || H <= 0 || spp <= 0 || max_depth < 0) return 1;
+  if (W <= 0 || H <= 0 || spp <= 0 || max_depth < 0 || (mis != 0 && mis != 1)) return 1;
   int64_t n = pixels ? npix : (int64_t)W * H;
   std::atomic<int64_t> next(0), nonfinite(0), segs(0);
   auto work = [&]() {
@@ -702,7 +746,8 @@ int32_t orc_render(void* s, int32_t W, int32_t H, int32_t spp, int32_t max_depth
         double sum[3] = {0, 0, 0}, sq[3] = {0, 0, 0}, aux[7] = {0, 0, 0, 0, 0, 0, 0};
         int64_t lseg = 0;
         for (int si = 0; si < spp; ++si) {
-          PathOut po = trace_path(sc, use_bvh != 0, W, H, px, py, si, max_depth, rr_start, seed);
+          PathOut po = trace_path(sc, use_bvh != 0, W, H, px, py, si, max_depth, rr_start, seed,
+                                  mis != 0);
           lseg += po.segments;
           double l[3] = {po.L.x, po.L.y, po.L.z};
           if (!(std::isfinite(l[0]) && std::isfinite(l[1]) && std::isfinite(l[2]))) {

@@ -38,7 +38,8 @@ def lib():
         L.orc_ggx_eval.argtypes = [C.c_double, P, P, P, P, P]
         L.orc_philox4x32_10.argtypes = [P, P, P]
         L.orc_render.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
-                                 C.c_uint64, C.c_int32, P, P, P, P, C.c_int32, C.c_int32, P]
+                                 C.c_uint64, C.c_int32, P, P, P, P, C.c_int32, C.c_int32,
+                                 C.c_int32, P]
         L.orc_render.restype = C.c_int32
         _lib = L
     return _lib
@@ -110,10 +111,12 @@ class OracleScene:
         return o, d
 
     def render(self, W, H, spp, max_depth, seed, rr_start=3, pixels=None, nthreads=None,
-               use_bvh=True, want_aux=True, want_sumsq=False):
+               use_bvh=True, want_aux=True, want_sumsq=False, mis=False):
         """FP64 render.  Returns dict(rgb [n,3], aux [n,7], sumsq [n,3], nonfinite, rays).
 
         `pixels` (flat indices y*W+x) selects a subset; default all pixels, row-major.
+        `mis` combines next-event estimation and BSDF sampling of the quad lights
+        (power heuristic).
         """
         if nthreads is None:
             nthreads = os.cpu_count() or 1
@@ -125,7 +128,7 @@ class OracleScene:
         cnt = np.zeros(2, np.int64)
         rc = lib().orc_render(self.h, W, H, spp, max_depth, rr_start, C.c_uint64(seed), n,
                               _p(pix), _p(rgb), _p(aux), _p(sq), int(nthreads), int(use_bvh),
-                              _p(cnt))
+                              int(bool(mis)), _p(cnt))
         if rc != 0:
             raise ValueError("oracle render: invalid arguments")
         return {"rgb": rgb, "aux": aux, "sumsq": sq, "nonfinite": int(cnt[0]),
