@@ -142,6 +142,13 @@ typedef struct mrs_render_opts {
   int32_t win_w;      /* window size; 0 = the whole image */
   int32_t win_h;
   int32_t accum_fp64; /* -1 auto (spp >= 1024), 0 FP32 sums, 1 FP64 sums */
+  int32_t mis;        /* 0 (default): quad lights by next-event estimation only (E8);
+                         1: next-event estimation and BSDF sampling of the quad lights
+                         combined by multiple importance sampling, power heuristic
+                         (Veach & Guibas 1995): a BSDF ray that reaches a listed light
+                         at vertex b >= 1 adds its emission weighted against the
+                         light-sampling density.  Finding that light scans the scene's
+                         light list. */
   float* out_sumsq_dev; /* optional win_h*win_w*3: sum over samples of L^2 */
 } mrs_render_opts;
 

@@ -66,7 +66,7 @@ class TrainOpts(C.Structure):
 class RenderOpts(C.Structure):
     _fields_ = [("rr_start", C.c_int32), ("x0", C.c_int32), ("y0", C.c_int32),
                 ("win_w", C.c_int32), ("win_h", C.c_int32), ("accum_fp64", C.c_int32),
-                ("out_sumsq_dev", C.c_void_p)]
+                ("mis", C.c_int32), ("out_sumsq_dev", C.c_void_p)]
 
 
 class Job(C.Structure):

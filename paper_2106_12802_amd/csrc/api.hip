@@ -279,6 +279,7 @@ void mrs_render_opts_default(mrs_render_opts* o) {
   o->x0 = o->y0 = 0;
   o->win_w = o->win_h = 0;
   o->accum_fp64 = -1;
+  o->mis = 0;
   o->out_sumsq_dev = nullptr;
 }
 
@@ -298,6 +299,7 @@ mrs_status validate_render(const char* fn, const mrs_scene* s, int32_t W, int32_
   if (max_depth < 0 || max_depth > 64)
     return fail(MRS_ERR_INVALID_ARGUMENT, f + ": max_depth must be in [0, 64]");
   if (o.rr_start < 0) return fail(MRS_ERR_INVALID_ARGUMENT, f + ": rr_start < 0");
+  if (o.mis != 0 && o.mis != 1) return fail(MRS_ERR_INVALID_ARGUMENT, f + ": mis must be 0 or 1");
   const int ww = o.win_w ? o.win_w : W, wh = o.win_h ? o.win_h : H;
   if (o.x0 < 0 || o.y0 < 0 || ww < 1 || wh < 1 || o.x0 + ww > W || o.y0 + wh > H)
     return fail(MRS_ERR_INVALID_ARGUMENT, f + ": window outside the image");
@@ -316,6 +318,7 @@ mrs_status validate_render(const char* fn, const mrs_scene* s, int32_t W, int32_
   a->ww = ww;
   a->wh = wh;
   a->fp64 = o.accum_fp64 < 0 ? spp >= 1024 : o.accum_fp64 != 0;
+  a->mis = o.mis != 0;
   a->out_rgb = out_rgb;
   a->out_aux = out_aux;
   a->out_sumsq = o.out_sumsq_dev;

@@ -549,17 +549,38 @@ __device__ __forceinline__ f3 schlick(f3 f0, float c) {
 // GGX BRDF value (Walter et al. 2007).  The denominator of D is written as
 // a^2 cos^2 + |n x h|^2, which equals cos^2 (a^2 - 1) + 1 for unit h but keeps
 // full FP32 accuracy when h is close to n.
+// GGX D(h) for n.h = ch, with 1 - ch^2 taken as |n x h|^2 (no cancellation
+// near the peak of a sharp lobe).
+__device__ __forceinline__ float ggx_D(float a2, f3 n, f3 h, float ch) {
+  const f3 nh = cross(n, h);
+  const float den = a2 * ch * ch + dot(nh, nh);
+  return a2 / (3.14159265358979323846f * den * den);
+}
+
 __device__ __forceinline__ f3 ggx_eval(f3 f0, float alpha, f3 n, f3 wo, f3 wi, float ci,
                                        float co) {
   const f3 h = normalize(wi + wo);
   const float ch = dot(n, h);
   if (ch <= 0.0f) return F3(0.0f, 0.0f, 0.0f);
-  const f3 nh = cross(n, h);
   const float a2 = alpha * alpha;
-  const float den = a2 * ch * ch + dot(nh, nh);
-  const float D = a2 / (3.14159265358979323846f * den * den);
+  const float D = ggx_D(a2, n, h, ch);
   const float G = ggx_G1(a2, ci) * ggx_G1(a2, co);
   return schlick(f0, dot(wi, h)) * (D * G / (4.0f * ci * co));
+}
+
+// Solid-angle density of reflecting wo into wi when h is drawn with density
+// D(h)(n.h): D(h)(n.h) / (4 wo.h).
+__device__ __forceinline__ float ggx_pdf(float a2, f3 n, f3 wo, f3 wi) {
+  const f3 h = normalize(wi + wo);
+  const float ch = dot(n, h), oh = dot(wo, h);
+  if (ch <= 0.0f || oh <= 0.0f) return 0.0f;
+  return ggx_D(a2, n, h, ch) * ch / (4.0f * oh);
+}
+
+// Power-heuristic weight (exponent 2) of a strategy with density a against b
+// (Veach & Guibas 1995).
+__device__ __forceinline__ float power_weight(float a, float b) {
+  return a * a / (a * a + b * b);
 }
 
 
@@ -569,6 +590,7 @@ __device__ __forceinline__ f3 ggx_eval(f3 f0, float alpha, f3 n, f3 wo, f3 wi, f
 // both perform the same arithmetic in the same order.
 struct Vertex {
   f3 beta, L;    // throughput and radiance after this vertex's emission
+  float pdf;     // solid-angle density of the BSDF sample wi (multiple importance sampling)
   bool cont;     // the path continues from x along wi
   bool shad;     // a shadow ray from x along swi, length sr, carries c if unoccluded
   f3 x, wi, swi, c;
@@ -576,12 +598,15 @@ struct Vertex {
   uint32_t li, prim;
 };
 
+// pdf_in: the density of the BSDF sample that led here (0 for camera rays).
 __device__ __forceinline__ void shade_vertex(const DevJob& J, int64_t g, int b, f3 o, f3 d,
-                                             float4 Hh, f3 beta, f3 L, float4* aux2, Vertex& v) {
+                                             float4 Hh, f3 beta, f3 L, float pdf_in,
+                                             float4* aux2, Vertex& v) {
   const SceneView& sc = J.sv;
   const uint32_t prim = __float_as_uint(Hh.y);
   v.cont = false;
   v.shad = false;
+  v.pdf = 0.0f;
   v.prim = prim;
   v.li = 0;
   v.x = v.wi = v.swi = v.c = F3(0.0f, 0.0f, 0.0f);
@@ -628,8 +653,26 @@ __device__ __forceinline__ void shade_vertex(const DevJob& J, int64_t g, int b, 
     aux2[1] = make_float4(ns.y, ns.z, t, 0.0f);
   }
   const f3 em = xyz(m.emis_kind);
-  if (front && (em.x != 0.0f || em.y != 0.0f || em.z != 0.0f) && (!(info & PRIM_LISTED) || b == 0))
-    L = L + mul(beta, em);
+  if (front && (em.x != 0.0f || em.y != 0.0f || em.z != 0.0f)) {
+    if (!(info & PRIM_LISTED) || b == 0) {
+      L = L + mul(beta, em);
+    } else if (J.mis) {
+      // a listed light reached by a BSDF sample: weighted against the density
+      // with which next-event estimation would have chosen this direction
+      // (the light is found by its triangle ids; scenes list few lights)
+      for (int i = 0; i < sc.nlights; ++i) {
+        const DevLight& lt = sc.lights[i];
+        if (lt.tri0 == (int32_t)prim || lt.tri1 == (int32_t)prim) {
+          const float cl = dot(xyz(lt.normal), wo);
+          if (cl > 0.0f) {
+            const float pl = t * t / ((float)sc.nlights * lt.normal.w * cl);
+            L = L + mul(beta, em) * power_weight(pdf_in, pl);
+          }
+          break;
+        }
+      }
+    }
+  }
   bool alive = b != J.max_depth && kind != MRS_EMITTER && dot(ns, wo) > 0.0f;
   if (alive) {
     uint32_t P, s;
@@ -654,6 +697,11 @@ __device__ __forceinline__ void shade_vertex(const DevJob& J, int64_t g, int b, 
         const f3 f = kind == MRS_LAMBERT ? col * INV_PI : ggx_eval(col, alpha, ns, wo, w, cs, co);
         const float geo = cs * cl * ((float)sc.nlights * lt.normal.w) / r2;
         v.c = mul(mul(beta, f), xyz(lt.le)) * geo;
+        if (J.mis) {
+          const float pl = r2 / ((float)sc.nlights * lt.normal.w * cl);
+          const float pb = kind == MRS_LAMBERT ? cs * INV_PI : ggx_pdf(alpha * alpha, ns, wo, w);
+          v.c = v.c * power_weight(pl, pb);
+        }
         v.swi = w;
         v.sr = r;
         v.shad = true;
@@ -670,6 +718,7 @@ __device__ __forceinline__ void shade_vertex(const DevJob& J, int64_t g, int b, 
       wi = T * (rr * cp) + B * (rr * sp) + ns * sqrtf(1.0f - v1);
       if (dot(ng, wi) <= 0.0f) alive = false;
       beta = mul(beta, col);
+      v.pdf = dot(ns, wi) * INV_PI;
     } else {
       const float a2 = alpha * alpha;
       const float den = 1.0f + (a2 - 1.0f) * v1;
@@ -685,6 +734,7 @@ __device__ __forceinline__ void shade_vertex(const DevJob& J, int64_t g, int b, 
         const float ch = dot(ns, h);
         const float G = ggx_G1(a2, ci) * ggx_G1(a2, co);
         beta = mul(beta, schlick(col, oh) * (G * oh / (co * ch)));
+        v.pdf = ggx_D(a2, ns, h, ch) * ch / (4.0f * oh);
       }
     }
     if (alive && b >= J.rr_start) {
@@ -722,11 +772,11 @@ __global__ __launch_bounds__(256) void k_shade(const DevJob* __restrict__ jobs, 
       j = job_of(__float_as_uint(R1.w));
       // a path starts with beta = 1, L = 0 and zero features (nothing is stored
       // for it before its first vertex)
-      const f3 beta = b == 0 ? F3(1.0f, 1.0f, 1.0f) : xyz(beta_buf[slot]);
+      const float4 Bt = b == 0 ? make_float4(1.0f, 1.0f, 1.0f, 0.0f) : beta_buf[slot];
       const f3 L = b == 0 ? F3(0.0f, 0.0f, 0.0f) : xyz(L_buf[slot]);
-      shade_vertex(jobs[j], g0 + slot, b, xyz(R0), xyz(R1), hits[qi], beta, L,
+      shade_vertex(jobs[j], g0 + slot, b, xyz(R0), xyz(R1), hits[qi], xyz(Bt), L, Bt.w,
                    b == 0 ? aux_buf + 2 * slot : nullptr, v);
-      if (v.cont) beta_buf[slot] = make_float4(v.beta.x, v.beta.y, v.beta.z, 0.0f);
+      if (v.cont) beta_buf[slot] = make_float4(v.beta.x, v.beta.y, v.beta.z, v.pdf);
       L_buf[slot] = make_float4(v.L.x, v.L.y, v.L.z, 0.0f);
     }
     const uint32_t ri = wave_append(v.cont, cnt_next);
@@ -818,6 +868,7 @@ struct PathIO {
   uint32_t slot, j;
   int b;
   f3 beta, L, c, o, d;
+  float pdf;  // density of the BSDF sample that led to the next vertex
   f3 next_o, next_d;
   uint32_t next_prim;
   bool cont, in_shadow;
@@ -839,7 +890,9 @@ struct PathIO {
     slot = __float_as_uint(R0.w);
     j = job_of(tag);
     b = b0;
-    beta = xyz(beta_buf[slot]);
+    const float4 Bt = beta_buf[slot];
+    beta = xyz(Bt);
+    pdf = Bt.w;
     L = xyz(L_buf[slot]);
     closest(r, xyz(R0), xyz(R1), unpack_prim(tag));
   }
@@ -848,8 +901,10 @@ struct PathIO {
     if (!in_shadow) {
       Vertex v;
       shade_vertex(jobs[j], g0 + slot, b, o, d,
-                   make_float4(ts.t, __uint_as_float(ts.prim), ts.b1, ts.b2), beta, L, nullptr, v);
+                   make_float4(ts.t, __uint_as_float(ts.prim), ts.b1, ts.b2), beta, L, pdf,
+                   nullptr, v);
       beta = v.beta;
+      pdf = v.pdf;
       L = v.L;
       cont = v.cont;
       next_o = v.x;
@@ -1422,6 +1477,7 @@ DevJob make_job(const mrs_scene* s, const RenderArgs& a) {
   J.max_depth = a.max_depth;
   J.rr_start = a.rr_start;
   J.fp64 = a.fp64 ? 1 : 0;
+  J.mis = a.mis ? 1 : 0;
   J.seed_lo = (uint32_t)(a.seed & 0xffffffffu);
   J.seed_hi = (uint32_t)(a.seed >> 32);
   J.out_rgb = a.out_rgb;

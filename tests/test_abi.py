@@ -100,3 +100,14 @@ def test_net_arch_and_training_option_validation():
     assert L.mrs_train_step_ex(None, 1, None, None, None, None, 4, 4, C.byref(opts), None) == 1
     assert L.mrs_net_loss_grad_ex(None, 1, None, None, None, None, 4, 4, 1, 0.1, None, None,
                                   None) == 1
+
+
+def test_render_opts_layout_matches_the_header():
+    """mrs_render_opts_default writes each documented default into its own field
+    (a layout mismatch between the header and the binding would misplace them)."""
+    from paper_2106_12802_amd import _lib
+    o = _lib.RenderOpts(7, 7, 7, 7, 7, 7, 7, 12345)
+    _lib.lib().mrs_render_opts_default(C.byref(o))
+    assert (o.rr_start, o.x0, o.y0, o.win_w, o.win_h, o.accum_fp64, o.mis) == (3, 0, 0, 0, 0, -1, 0)
+    assert not o.out_sumsq_dev
+    assert C.sizeof(_lib.Job) == 88
