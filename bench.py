@@ -139,10 +139,10 @@ def pmc_summary(fetch_path, write_path, out_path):
         "# (max depth 8) + fusion network.",
         "# Made by (each pass its own process, run from the repository root):",
         "#   rocprofv3 --pmc FETCH_SIZE -f csv -d gpurun_out/pmc_fetch -o pmc -- python bench.py "
-        "--steps 1 --warmup 0 --no-cpu-baseline --equal-psnr-scenes 0 --batch-scenes 0 --no-paper-net "
+        "--steps 1 --warmup 0 --no-cpu-baseline --equal-psnr-scenes 0 --batch-scenes 0 --no-paper-net --no-mis "
         "--copy-calibration",
         "#   rocprofv3 --pmc WRITE_SIZE -f csv -d gpurun_out/pmc_write -o pmc -- python bench.py "
-        "--steps 1 --warmup 0 --no-cpu-baseline --equal-psnr-scenes 0 --batch-scenes 0 --no-paper-net "
+        "--steps 1 --warmup 0 --no-cpu-baseline --equal-psnr-scenes 0 --batch-scenes 0 --no-paper-net --no-mis "
         "--copy-calibration",
         "#   python bench.py --pmc-summary gpurun_out/pmc_fetch gpurun_out/pmc_write",
         "# Counters are KiB per dispatch; each is scaled by COPY_BYTES over what the same counter",
@@ -165,7 +165,7 @@ def pmc_summary(fetch_path, write_path, out_path):
 
 STATS_SUMMARY = os.path.join(ROOT, "profiles", "hybrid_frame_procedural101k_720p_kernel_stats.txt")
 STATS_CMD = ("rocprofv3 --kernel-trace --stats -f csv -d gpurun_out/prof -o bench -- python -u "
-             "bench.py --steps 5 --warmup 1 --no-cpu-baseline --equal-psnr-scenes 0 --batch-scenes 0 --no-paper-net")
+             "bench.py --steps 5 --warmup 1 --no-cpu-baseline --equal-psnr-scenes 0 --batch-scenes 0 --no-paper-net --no-mis")
 
 
 def stats_summary(prof_dir, out_path):
@@ -371,6 +371,40 @@ def batched_block(net, log, n_scenes=32, tune=True):
             if tuned else None}
 
 
+def mis_block(gs, log, reps=5):
+    """Multiple importance sampling of the quad lights (render option mis) on the
+    bench scene: time of the two renders of the hybrid frame with and without it,
+    and the PSNR of the 4-spp HRLS image against a 1024-spp reference (MIS, FP64
+    pixel sums, independent seed) with and without it."""
+    import torch
+    from paper_2106_12802_amd import metrics as M
+    from paper_2106_12802_amd import tracer as R
+    (Wh, Hh, sh), (Wl, Hl, sl) = HRLS, LRHS
+    ref, _ = R.render(gs, Wh, Hh, 1024, MAX_DEPTH, 1 << 41, want_aux=False, mis=True)
+    res = {"reference": "1280x720 at 1024 spp with mis, FP64 pixel sums, seed 2^41"}
+    for mis in (False, True):
+        hr = torch.empty(Hh, Wh, 3, device="cuda")
+        lr = torch.empty(Hl, Wl, 3, device="cuda")
+
+        def frame(i):
+            R.render_ex(gs, Wh, Hh, sh, MAX_DEPTH, 2 * i, hr, None, mis=mis)
+            R.render_ex(gs, Wl, Hl, sl, MAX_DEPTH, 2 * i + 1, lr, None, mis=mis)
+        frame(0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(reps):
+            frame(i)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+        psnr = [M.image_metrics(R.render(gs, Wh, Hh, sh, MAX_DEPTH, 100 + k, want_aux=False,
+                                          mis=mis)[0], ref)["psnr"] for k in range(4)]
+        key = "mis" if mis else "nee"
+        res[f"ms_two_renders_{key}"] = round(ms, 4)
+        res[f"psnr_hrls_4spp_{key}"] = round(sum(psnr) / len(psnr), 3)
+        log(f"[bench] {key}: two renders {ms:.3f} ms, HRLS 4 spp PSNR {res[f'psnr_hrls_4spp_{key}']} dB")
+    return res
+
+
 def paper_net_block(log, reps=10, train_steps=10):
     """The paper's own network (three residual dense groups, Sec. 4): fuse time
     on the 720p hybrid frame and at the paper's runtime-table size (one
@@ -426,6 +460,8 @@ def main():
                     help="held-out scenes in the equal-PSNR comparison (0: skip it)")
     ap.add_argument("--batch-scenes", type=int, default=32,
                     help="scenes in the batched render+fuse measurement (0: skip it)")
+    ap.add_argument("--no-mis", action="store_true",
+                    help="skip the multiple-importance-sampling comparison")
     ap.add_argument("--no-paper-net", action="store_true",
                     help="skip timing the paper's own network (residual dense groups)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -586,6 +622,8 @@ def main():
         result["batched"] = batched_block(net, log, args.batch_scenes)
     if not args.no_paper_net:
         result["paper_net"] = paper_net_block(log)
+    if not args.no_mis:
+        result["mis"] = mis_block(gs, log)
     if not args.no_cpu_baseline:
         threads = max(1, min(16, len(os.sched_getaffinity(0))))
         log(f"[bench] timing the FP64 oracle on {threads} host threads")
