@@ -12,7 +12,8 @@
 // (Kajiya 1986; Cook 1984 -- both cited in Sec. 1-2), with each mapping from
 // uniforms to geometry taken from the published method named at its use:
 //   E1  Philox4x32-10 counter-based RNG (Salmon et al., SC'11)
-//   E3  pinhole camera, box pixel filter
+//   E3  pinhole camera, box pixel filter; optionally a thin lens (depth of
+//       field) and a camera translated over the shutter (motion blur)
 //   E4  Moller-Trumbore ray/triangle test (JGT 1997), closest hit over all
 //       triangles, ties to the smaller primitive id
 //   E5  shading frame, orthonormal basis of Duff et al. (JCGT 2017)
@@ -431,6 +432,32 @@ void camera_ray(const Cam& c, int W, int H, double x, double y, V3* o, V3* d) {
   *d = normalize(f + r * ((2.0 * sx - 1.0) * th * aspect) + v * ((1.0 - 2.0 * sy) * th));
 }
 
+// Camera effects of one render: a thin lens of radius lens_r focused on the
+// plane at distance focus along the view axis (the pinhole ray through the
+// pixel point meets that plane at F; the ray leaves from a point of the lens
+// disk towards F), and a camera translated by motion * tau, tau in [0, 1) the
+// shutter time of the sample.  Zero radius and zero motion give the pinhole.
+struct CamFx {
+  double lens_r, focus;
+  V3 motion;
+};
+
+void camera_ray_fx(const Cam& c, const CamFx& fx, int W, int H, double x, double y, double ul0,
+                   double ul1, double tau, V3* o, V3* d) {
+  camera_ray(c, W, H, x, y, o, d);
+  *o = *o + fx.motion * tau;
+  if (fx.lens_r > 0.0) {
+    V3 f = normalize(c.look_at - c.pos);
+    V3 r = normalize(cross(f, c.up));
+    V3 v = cross(r, f);
+    V3 F = *o + *d * (fx.focus / dot(*d, f));
+    double rho = fx.lens_r * std::sqrt(ul0), phi = 2.0 * M_PI * ul1;
+    V3 lens = *o + r * (rho * std::cos(phi)) + v * (rho * std::sin(phi));
+    *o = lens;
+    *d = normalize(F - lens);
+  }
+}
+
 // ----------------------------------------------------------------- E7: one path
 struct PathOut {
   V3 L;
@@ -449,16 +476,21 @@ double light_pdf(const Scene& sc, const Light& lt, double t, double cl) {
 }
 
 PathOut trace_path(const Scene& sc, bool use_bvh, int W, int H, int px, int py, int s,
-                   int max_depth, int rr_start, uint64_t seed, bool mis) {
+                   int max_depth, int rr_start, uint64_t seed, bool mis, const CamFx& fx) {
   PathOut out;
   out.L = mk(0, 0, 0);
   for (int i = 0; i < 7; ++i) out.aux[i] = 0.0;
   out.segments = 0;
   const uint32_t p = (uint32_t)(py * W + px);
-  // d0, d1: pixel jitter (box filter); d2, d3 reserved.
+  // d0, d1: pixel jitter (box filter); d2, d3: lens sample; the shutter time
+  // is word 0 of the block with counter (p, s, 0, 4) (drawn only for a moving
+  // camera).
   Block b0 = rng_block(seed, p, (uint32_t)s, 0, 0);
+  const bool moving = fx.motion.x != 0.0 || fx.motion.y != 0.0 || fx.motion.z != 0.0;
+  const double tau = moving ? to_unit(rng_block(seed, p, (uint32_t)s, 0, 4).w[0]) : 0.0;
   V3 o, d;
-  camera_ray(sc.cam, W, H, px + to_unit(b0.w[0]), py + to_unit(b0.w[1]), &o, &d);
+  camera_ray_fx(sc.cam, fx, W, H, px + to_unit(b0.w[0]), py + to_unit(b0.w[1]), to_unit(b0.w[2]),
+                to_unit(b0.w[3]), tau, &o, &d);
   V3 beta = mk(1, 1, 1), L = mk(0, 0, 0);
   double bsdf_pdf = 0.0;  // density of the BSDF sample that led to this vertex (mis)
   int32_t skip = -1;
@@ -691,6 +723,23 @@ void orc_camera_ray(void* s, int32_t W, int32_t H, double x, double y, double* o
   d[0] = dd.x; d[1] = dd.y; d[2] = dd.z;
 }
 
+// camfx: lens radius, focus distance, motion xyz (NULL: pinhole, no motion).
+static CamFx make_fx(const double* camfx) {
+  CamFx fx;
+  fx.lens_r = camfx ? camfx[0] : 0.0;
+  fx.focus = camfx ? camfx[1] : 0.0;
+  fx.motion = camfx ? mk(camfx[2], camfx[3], camfx[4]) : mk(0, 0, 0);
+  return fx;
+}
+
+void orc_camera_ray_fx(void* s, int32_t W, int32_t H, double x, double y, double ul0, double ul1,
+                       double tau, const double* camfx, double* o, double* d) {
+  V3 oo, dd;
+  camera_ray_fx(((Scene*)s)->cam, make_fx(camfx), W, H, x, y, ul0, ul1, tau, &oo, &dd);
+  o[0] = oo.x; o[1] = oo.y; o[2] = oo.z;
+  d[0] = dd.x; d[1] = dd.y; d[2] = dd.z;
+}
+
 void orc_onb(const double* n, double* T, double* B) {
   V3 t, b;
   onb(mk(n[0], n[1], n[2]), &t, &b);
@@ -725,14 +774,17 @@ void orc_ggx_eval(double alpha, const double* f0, const double* n, const double*
 // Render: for each requested pixel (all W*H when pixels == NULL), the mean over
 // spp samples of the path radiance (E12: summed in sample order) and of the
 // first-hit features.  out_sumsq (optional) receives sum_s L^2 per channel.
-// mis = 1 combines next-event estimation and BSDF sampling of the quad lights.
+// mis = 1 combines next-event estimation and BSDF sampling of the quad lights;
+// camfx (or NULL) = lens radius, focus distance, camera motion xyz.
 // counters[0] = non-finite samples replaced by 0, counters[1] = rays traced.
 int32_t orc_render(void* s, int32_t W, int32_t H, int32_t spp, int32_t max_depth,
                    int32_t rr_start, uint64_t seed, int32_t npix, const int32_t* pixels,
                    double* out_rgb, double* out_aux, double* out_sumsq, int32_t nthreads,
-                   int32_t use_bvh, int32_t mis, int64_t* counters) {
+                   int32_t use_bvh, int32_t mis, const double* camfx, int64_t* counters) {
   const Scene& sc = *(const Scene*)s;
   if (W <= 0 || H <= 0 || spp <= 0 || max_depth < 0 || (mis != 0 && mis != 1)) return 1;
+  const CamFx fx = make_fx(camfx);
+  if (fx.lens_r < 0.0 || (fx.lens_r > 0.0 && !(fx.focus > 0.0))) return 1;
   int64_t n = pixels ? npix : (int64_t)W * H;
   std::atomic<int64_t> next(0), nonfinite(0), segs(0);
   auto work = [&]() {
@@ -747,7 +799,7 @@ int32_t orc_render(void* s, int32_t W, int32_t H, int32_t spp, int32_t max_depth
         int64_t lseg = 0;
         for (int si = 0; si < spp; ++si) {
           PathOut po = trace_path(sc, use_bvh != 0, W, H, px, py, si, max_depth, rr_start, seed,
-                                  mis != 0);
+                                  mis != 0, fx);
           lseg += po.segments;
           double l[3] = {po.L.x, po.L.y, po.L.z};
           if (!(std::isfinite(l[0]) && std::isfinite(l[1]) && std::isfinite(l[2]))) {

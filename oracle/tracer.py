@@ -39,7 +39,9 @@ def lib():
         L.orc_philox4x32_10.argtypes = [P, P, P]
         L.orc_render.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                  C.c_uint64, C.c_int32, P, P, P, P, C.c_int32, C.c_int32,
-                                 C.c_int32, P]
+                                 C.c_int32, P, P]
+        L.orc_camera_ray_fx.argtypes = [P, C.c_int32, C.c_int32, C.c_double, C.c_double,
+                                        C.c_double, C.c_double, C.c_double, P, P, P]
         L.orc_render.restype = C.c_int32
         _lib = L
     return _lib
@@ -104,6 +106,19 @@ class OracleScene:
                               _p(b))
         return t, prim, b
 
+    @staticmethod
+    def _fx(lens_radius, focus_dist, cam_motion):
+        return np.array([lens_radius, focus_dist, *cam_motion], np.float64)
+
+    def camera_ray_fx(self, W, H, x, y, ul0, ul1, tau, lens_radius=0.0, focus_dist=0.0,
+                      cam_motion=(0.0, 0.0, 0.0)):
+        o = np.zeros(3)
+        d = np.zeros(3)
+        fx = self._fx(lens_radius, focus_dist, cam_motion)
+        lib().orc_camera_ray_fx(self.h, W, H, float(x), float(y), float(ul0), float(ul1),
+                                float(tau), _p(fx), _p(o), _p(d))
+        return o, d
+
     def camera_ray(self, W, H, x, y):
         o = np.zeros(3)
         d = np.zeros(3)
@@ -111,12 +126,14 @@ class OracleScene:
         return o, d
 
     def render(self, W, H, spp, max_depth, seed, rr_start=3, pixels=None, nthreads=None,
-               use_bvh=True, want_aux=True, want_sumsq=False, mis=False):
+               use_bvh=True, want_aux=True, want_sumsq=False, mis=False, lens_radius=0.0,
+               focus_dist=0.0, cam_motion=(0.0, 0.0, 0.0)):
         """FP64 render.  Returns dict(rgb [n,3], aux [n,7], sumsq [n,3], nonfinite, rays).
 
         `pixels` (flat indices y*W+x) selects a subset; default all pixels, row-major.
         `mis` combines next-event estimation and BSDF sampling of the quad lights
-        (power heuristic).
+        (power heuristic).  `lens_radius` / `focus_dist`: thin lens; `cam_motion`:
+        camera translation over the shutter.
         """
         if nthreads is None:
             nthreads = os.cpu_count() or 1
@@ -128,7 +145,8 @@ class OracleScene:
         cnt = np.zeros(2, np.int64)
         rc = lib().orc_render(self.h, W, H, spp, max_depth, rr_start, C.c_uint64(seed), n,
                               _p(pix), _p(rgb), _p(aux), _p(sq), int(nthreads), int(use_bvh),
-                              int(bool(mis)), _p(cnt))
+                              int(bool(mis)), _p(self._fx(lens_radius, focus_dist, cam_motion)),
+                              _p(cnt))
         if rc != 0:
             raise ValueError("oracle render: invalid arguments")
         return {"rgb": rgb, "aux": aux, "sumsq": sq, "nonfinite": int(cnt[0]),

@@ -61,6 +61,88 @@ def test_camera_corner_angles(oracle_tracer):
     assert np.allclose(ctr, f, atol=1e-12)
 
 
+def test_thin_lens_rays_meet_on_the_focal_plane(oracle_tracer):
+    """Every lens sample of a pixel point leaves from the lens disk (radius R,
+    across the view axis) and passes through the point where the pinhole ray
+    meets the focal plane (distance `focus` along the view axis)."""
+    sc = oracle_tracer.OracleScene(S.cornell(1))
+    W, H, R, focus = 64, 48, 0.05, 1.3
+    pos = np.array([0.5, 0.5, -1.2], np.float32).astype(np.float64)  # the camera is FP32
+    f = np.array([0.0, 0.0, 1.0])
+    rng = np.random.default_rng(5)
+    for x, y in [(W / 2, H / 2), (3.25, 40.5), (60.0, 1.0)]:
+        o0, d0 = sc.camera_ray(W, H, x, y)
+        F = o0 + d0 * (focus / (d0 @ f))
+        for u0, u1 in rng.random((8, 2)):
+            o, d = sc.camera_ray_fx(W, H, x, y, u0, u1, 0.0, lens_radius=R, focus_dist=focus)
+            off = o - pos
+            assert abs(off @ f) < 1e-15 and np.linalg.norm(off) <= R * (1 + 1e-12)
+            assert np.linalg.norm(off) == pytest.approx(R * math.sqrt(u0), rel=1e-12)
+            t = (F - o) @ f / (d @ f)
+            assert np.allclose(o + t * d, F, atol=1e-12)
+        # radius 0 is the pinhole exactly
+        o, d = sc.camera_ray_fx(W, H, x, y, 0.3, 0.7, 0.0, focus_dist=focus)
+        assert np.array_equal(o, o0) and np.array_equal(d, d0)
+
+
+def test_circle_of_confusion(oracle_tracer):
+    """On a plane at distance z across the axis, the centre pixel's lens samples
+    land on a disk of radius R |z - focus| / focus around the pinhole hit."""
+    sc = oracle_tracer.OracleScene(S.cornell(1))
+    W, H, R, focus = 64, 48, 0.05, 1.3
+    pos = np.array([0.5, 0.5, -1.2], np.float32).astype(np.float64)  # the camera is FP32
+    for z in (0.6, 2.5):
+        pts = []
+        for k in range(64):
+            u0, u1 = (k + 0.5) / 64, (k * 0.618034) % 1.0
+            o, d = sc.camera_ray_fx(W, H, W / 2, H / 2, 1.0 if k % 2 else u0, u1, 0.0,
+                                    lens_radius=R, focus_dist=focus)
+            pts.append(o + d * ((pos[2] + z - o[2]) / d[2]))
+        rad = np.linalg.norm(np.array(pts)[:, :2] - pos[:2], axis=1)
+        assert rad.max() == pytest.approx(R * abs(z - focus) / focus, rel=1e-12)
+
+
+def test_camera_motion_translates_the_ray(oracle_tracer):
+    sc = oracle_tracer.OracleScene(S.cornell(1))
+    m = (0.2, -0.1, 0.05)
+    o0, d0 = sc.camera_ray(32, 32, 10.5, 20.25)
+    for tau in (0.0, 0.37, 0.999):
+        o, d = sc.camera_ray_fx(32, 32, 10.5, 20.25, 0.5, 0.5, tau, cam_motion=m)
+        assert np.allclose(o, o0 + tau * np.array(m), atol=1e-15) and np.array_equal(d, d0)
+
+
+@pytest.mark.parametrize("max_depth", [1, 3])
+def test_lens_and_motion_keep_lambert_plane_exact(oracle_tracer, max_depth):
+    """A Lambert plane under a constant environment is rho * env from any point of
+    view: it stays exact with a lens and a moving camera (which do draw their
+    random numbers)."""
+    scene = S.lambert_plane()
+    r = oracle_tracer.OracleScene(scene).render(8, 8, 16, max_depth, 3, lens_radius=0.2,
+                                                focus_dist=3.0, cam_motion=(0.5, 0.0, 0.2))
+    want = scene.materials[0]["color"].astype(np.float64) * scene.env.astype(np.float64)
+    assert np.allclose(r["rgb"], want[None], rtol=1e-14, atol=0)
+
+
+def test_in_focus_plane_matches_pinhole(oracle_tracer):
+    """A textured Lambert plane on the focal plane, lit by the environment: every
+    lens sample of a pixel point hits the point the pinhole ray hits, so the image
+    is the pinhole image (to rounding of the hit points)."""
+    b = S._Builder()
+    mats = [b.material(S.LAMBERT, color=(0.8, 0.2, 0.1)), b.material(S.LAMBERT, color=(0.1, 0.3, 0.9))]
+    for i in range(8):
+        for j in range(8):
+            b.add_quad((-2.0 + 0.5 * i, -2.0 + 0.5 * j, 3.0), (0.5, 0.0, 0.0), (0.0, 0.5, 0.0),
+                       mats[(i + j) % 2])
+    cam = S.Camera((0.0, 0.0, 0.0), (0.0, 0.0, 1.0), (0.0, 1.0, 0.0), 50.0)
+    scene = b.build((1.0, 1.0, 1.0), cam, "focal_checker")
+    sc = oracle_tracer.OracleScene(scene)
+    pin = sc.render(24, 24, 8, 1, 9)
+    dof = sc.render(24, 24, 8, 1, 9, lens_radius=0.1, focus_dist=3.0)
+    assert np.allclose(dof["rgb"], pin["rgb"], rtol=1e-9, atol=1e-12)
+    blur = sc.render(24, 24, 8, 1, 9, lens_radius=0.1, focus_dist=1.5)
+    assert not np.allclose(blur["rgb"], pin["rgb"], atol=1e-3)  # out of focus: checker edges blur
+
+
 # --------------------------------------------------------------------------- E4 intersection
 
 
