@@ -149,6 +149,14 @@ typedef struct mrs_render_opts {
                          at vertex b >= 1 adds its emission weighted against the
                          light-sampling density.  Finding that light scans the scene's
                          light list. */
+  float lens_radius;  /* thin lens (depth of field): radius of the lens disk; 0 = pinhole */
+  float focus_dist;   /* distance of the focal plane along the view axis (> 0 with a lens) */
+  float cam_motion[3]; /* camera translation over the shutter (motion blur); 0 = still.
+                         A sample's ray leaves from pos + tau * cam_motion + a point of
+                         the lens disk (uniforms d2, d3: radius R sqrt(u2), angle
+                         2 pi u3) towards the point where the pinhole ray of its pixel
+                         point meets the focal plane; tau = word 0 of Philox with
+                         counter (p, s, 0, 4), drawn only for a moving camera. */
   float* out_sumsq_dev; /* optional win_h*win_w*3: sum over samples of L^2 */
 } mrs_render_opts;
 

@@ -280,6 +280,9 @@ void mrs_render_opts_default(mrs_render_opts* o) {
   o->win_w = o->win_h = 0;
   o->accum_fp64 = -1;
   o->mis = 0;
+  o->lens_radius = 0.0f;
+  o->focus_dist = 0.0f;
+  o->cam_motion[0] = o->cam_motion[1] = o->cam_motion[2] = 0.0f;
   o->out_sumsq_dev = nullptr;
 }
 
@@ -291,6 +294,15 @@ mrs_status validate_render(const char* fn, const mrs_scene* s, int32_t W, int32_
   mrs_render_opts o;
   mrs_render_opts_default(&o);
   if (opts) o = *opts;
+  if (o.rr_start < 0) return fail(MRS_ERR_INVALID_ARGUMENT, f + ": rr_start < 0");
+  if (o.mis != 0 && o.mis != 1) return fail(MRS_ERR_INVALID_ARGUMENT, f + ": mis must be 0 or 1");
+  if (!(o.lens_radius >= 0.0f) || !std::isfinite(o.lens_radius) ||
+      (o.lens_radius > 0.0f && !(o.focus_dist > 0.0f && std::isfinite(o.focus_dist))))
+    return fail(MRS_ERR_INVALID_ARGUMENT,
+                f + ": lens_radius must be >= 0, with a positive finite focus_dist");
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(o.cam_motion[k]))
+      return fail(MRS_ERR_INVALID_ARGUMENT, f + ": cam_motion must be finite");
   if (!s) return fail(MRS_ERR_INVALID_ARGUMENT, f + ": scene is NULL");
   if (W < 1 || H < 1 || W > 16384 || H > 16384)
     return fail(MRS_ERR_INVALID_ARGUMENT, f + ": W and H must be in [1, 16384]");
@@ -298,8 +310,7 @@ mrs_status validate_render(const char* fn, const mrs_scene* s, int32_t W, int32_
     return fail(MRS_ERR_INVALID_ARGUMENT, f + ": spp must be in [1, 2^20]");
   if (max_depth < 0 || max_depth > 64)
     return fail(MRS_ERR_INVALID_ARGUMENT, f + ": max_depth must be in [0, 64]");
-  if (o.rr_start < 0) return fail(MRS_ERR_INVALID_ARGUMENT, f + ": rr_start < 0");
-  if (o.mis != 0 && o.mis != 1) return fail(MRS_ERR_INVALID_ARGUMENT, f + ": mis must be 0 or 1");
+
   const int ww = o.win_w ? o.win_w : W, wh = o.win_h ? o.win_h : H;
   if (o.x0 < 0 || o.y0 < 0 || ww < 1 || wh < 1 || o.x0 + ww > W || o.y0 + wh > H)
     return fail(MRS_ERR_INVALID_ARGUMENT, f + ": window outside the image");
@@ -319,6 +330,9 @@ mrs_status validate_render(const char* fn, const mrs_scene* s, int32_t W, int32_
   a->wh = wh;
   a->fp64 = o.accum_fp64 < 0 ? spp >= 1024 : o.accum_fp64 != 0;
   a->mis = o.mis != 0;
+  a->lens_r = o.lens_radius;
+  a->focus = o.focus_dist;
+  for (int k = 0; k < 3; ++k) a->motion[k] = o.cam_motion[k];
   a->out_rgb = out_rgb;
   a->out_aux = out_aux;
   a->out_sumsq = o.out_sumsq_dev;

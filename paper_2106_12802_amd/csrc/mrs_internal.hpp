@@ -84,7 +84,8 @@ struct DevJob {
   SceneView sv;
   int32_t W, H, x0, y0, ww, wh;
   int32_t spp, max_depth, rr_start, fp64;
-  int32_t mis, pad0;
+  int32_t mis, moving;
+  float lens_r, focus, motion_x, motion_y, motion_z, pad0;
   uint32_t seed_lo, seed_hi;
   int64_t first, pix_first, acc_off;
   float* out_rgb;
@@ -135,6 +136,7 @@ struct RenderArgs {
   int32_t x0, y0, ww, wh;
   bool fp64;
   bool mis;
+  float lens_r, focus, motion[3];
   float* out_rgb;
   float* out_aux;
   float* out_sumsq;

@@ -445,8 +445,25 @@ __global__ __launch_bounds__(256) void k_generate(const DevJob* __restrict__ job
   const float cy = (1.0f - 2.0f * sy) * sc.cam_tan_half;
   const f3 f = F3(sc.cam_fx, sc.cam_fy, sc.cam_fz), rr = F3(sc.cam_rx, sc.cam_ry, sc.cam_rz),
            vv = F3(sc.cam_vx, sc.cam_vy, sc.cam_vz);
-  const f3 d = normalize(f + rr * cx + vv * cy);
-  rays[2 * slot] = make_float4(sc.cam_px, sc.cam_py, sc.cam_pz, __uint_as_float(slot));
+  f3 d = normalize(f + rr * cx + vv * cy);
+  f3 o = F3(sc.cam_px, sc.cam_py, sc.cam_pz);
+  // camera effects: translation over the shutter (time from its own Philox
+  // block), thin lens (lens sample from words 2, 3, aimed at the point where
+  // the pinhole ray meets the focal plane)
+  if (J.moving) {
+    const uint4 rt = philox4x32_10(make_uint4(P, s, 0u, 4u), J.seed_lo, J.seed_hi);
+    const float tau = unit24(rt.x);
+    o = o + F3(J.motion_x, J.motion_y, J.motion_z) * tau;
+  }
+  if (J.lens_r > 0.0f) {
+    const f3 Fp = o + d * (J.focus / dot(d, f));
+    const float rho = J.lens_r * sqrtf(unit24(r.z));
+    float sp, cp;
+    sincospif(2.0f * unit24(r.w), &sp, &cp);
+    o = o + rr * (rho * cp) + vv * (rho * sp);
+    d = normalize(Fp - o);
+  }
+  rays[2 * slot] = make_float4(o.x, o.y, o.z, __uint_as_float(slot));
   rays[2 * slot + 1] = make_float4(d.x, d.y, d.z, __uint_as_float((j << 24) | PRIM24));
 }
 
@@ -1478,6 +1495,12 @@ DevJob make_job(const mrs_scene* s, const RenderArgs& a) {
   J.rr_start = a.rr_start;
   J.fp64 = a.fp64 ? 1 : 0;
   J.mis = a.mis ? 1 : 0;
+  J.lens_r = a.lens_r;
+  J.focus = a.focus;
+  J.motion_x = a.motion[0];
+  J.motion_y = a.motion[1];
+  J.motion_z = a.motion[2];
+  J.moving = (a.motion[0] != 0.0f || a.motion[1] != 0.0f || a.motion[2] != 0.0f) ? 1 : 0;
   J.seed_lo = (uint32_t)(a.seed & 0xffffffffu);
   J.seed_hi = (uint32_t)(a.seed >> 32);
   J.out_rgb = a.out_rgb;

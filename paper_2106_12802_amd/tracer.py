@@ -84,14 +84,19 @@ class GpuScene:
 
 
 def render_ex(scene: GpuScene, W, H, spp, max_depth, seed, out_rgb, out_aux=None, rr_start=3,
-              window=None, accum_fp64=-1, out_sumsq=None, mis=False):
+              window=None, accum_fp64=-1, out_sumsq=None, mis=False, lens_radius=0.0,
+              focus_dist=0.0, cam_motion=(0.0, 0.0, 0.0)):
     """Enqueue mrs_render_ex on torch's current stream.  Outputs are CUDA float32 tensors.
 
-    mis: combine next-event estimation and BSDF sampling of the quad lights."""
+    mis: combine next-event estimation and BSDF sampling of the quad lights;
+    lens_radius / focus_dist: thin lens; cam_motion: camera translation over the shutter."""
     o = L.RenderOpts()
     L.lib().mrs_render_opts_default(C.byref(o))
     o.rr_start = rr_start
     o.mis = int(bool(mis))
+    o.lens_radius = float(lens_radius)
+    o.focus_dist = float(focus_dist)
+    o.cam_motion[:] = [float(v) for v in cam_motion]
     if window is not None:
         o.x0, o.y0, o.win_w, o.win_h = (int(v) for v in window)
     o.accum_fp64 = accum_fp64
@@ -182,7 +187,8 @@ class Batch:
 
     jobs: dicts with keys scene (GpuScene), W, H, spp, max_depth, seed, and optional
     out_rgb / out_aux / out_sumsq (CUDA float32 tensors, allocated if missing; aux only
-    when want_aux is true), rr_start, window, accum_fp64, mis.  Outputs are in .outputs."""
+    when want_aux is true), rr_start, window, accum_fp64, mis, lens_radius, focus_dist,
+    cam_motion.  Outputs are in .outputs."""
 
     def __init__(self, jobs):
         import torch
@@ -209,6 +215,9 @@ class Batch:
                 o.x0, o.y0, o.win_w, o.win_h = (int(v) for v in win)
             o.accum_fp64 = int(j.get("accum_fp64", -1))
             o.mis = int(bool(j.get("mis", False)))
+            o.lens_radius = float(j.get("lens_radius", 0.0))
+            o.focus_dist = float(j.get("focus_dist", 0.0))
+            o.cam_motion[:] = [float(v) for v in j.get("cam_motion", (0.0, 0.0, 0.0))]
             o.out_sumsq_dev = L.ptr(sq, 3 * ww * wh, "f32", "out_sumsq")
             arr[i].scene = j["scene"].handle.value
             arr[i].W, arr[i].H = W, H

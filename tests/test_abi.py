@@ -106,8 +106,23 @@ def test_render_opts_layout_matches_the_header():
     """mrs_render_opts_default writes each documented default into its own field
     (a layout mismatch between the header and the binding would misplace them)."""
     from paper_2106_12802_amd import _lib
-    o = _lib.RenderOpts(7, 7, 7, 7, 7, 7, 7, 12345)
+    o = _lib.RenderOpts(7, 7, 7, 7, 7, 7, 7, 7.0, 7.0, (C.c_float * 3)(7, 7, 7), 12345)
     _lib.lib().mrs_render_opts_default(C.byref(o))
     assert (o.rr_start, o.x0, o.y0, o.win_w, o.win_h, o.accum_fp64, o.mis) == (3, 0, 0, 0, 0, -1, 0)
+    assert (o.lens_radius, o.focus_dist, list(o.cam_motion)) == (0.0, 0.0, [0.0, 0.0, 0.0])
     assert not o.out_sumsq_dev
-    assert C.sizeof(_lib.Job) == 88
+    assert C.sizeof(_lib.Job) == 104
+    # a lens needs a positive focus distance; motion must be finite (rejected on the host)
+    from mrs_inputs import scenes as S
+    L = _lib.lib()
+    for kw in (dict(lens_radius=0.1), dict(lens_radius=-1.0),
+               dict(cam_motion=(float("nan"), 0.0, 0.0))):
+        bad = _lib.RenderOpts()
+        L.mrs_render_opts_default(C.byref(bad))
+        for k, v in kw.items():
+            if k == "cam_motion":
+                bad.cam_motion[:] = list(v)
+            else:
+                setattr(bad, k, v)
+        assert L.mrs_render_ex(None, 4, 4, 1, 1, 0, C.byref(bad), None, None) == 1
+        assert b"lens_radius" in L.mrs_last_error() or b"cam_motion" in L.mrs_last_error()
