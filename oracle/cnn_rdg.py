@@ -5,13 +5,14 @@ Plain numpy, float64, written from the network description of paper Sec. 4
 
   F_LRHS   = ReLU(H_lrhs(I_LRHS))                 3x3, 3 -> 64         @LR
   F^0_HRLS = ReLU(H_hrls(I_HRLS))                 3x3, 10 -> 64        @HR
-  F_HRLS   = DSF(DSF(F^0_HRLS))                   two stride-2 deshuffles (D = 2, alpha = 2)
-  F_0      = ReLU(fuse([F_LRHS, F_HRLS]))         1x1, 64 + 1024 -> 64 @LR
+  F_HRLS   = DSF^D(F^0_HRLS)                      D stacked stride-2 deshuffles (alpha = 2;
+                                                  scale 2^D: x2, x4 (the default), x8)
+  F_0      = ReLU(fuse([F_LRHS, F_HRLS]))         1x1, 64 + 64 4^D -> 64 @LR
   RDB:  x_0 = input; x_c = ReLU(conv3x3([x_0 .. x_{c-1}])) for c = 1..3 (64 each);
         output = x_0 + conv3x3([x_0 .. x_3]) (256 -> 64)
   F_g      = RDB_5(...RDB_1(F_{g-1})...) + F_{g-1},   g = 1..3
   F_DF     = F_3 + F_0
-  UP       = twice: ReLU(conv3x3 64 -> 256) then shuffle by 2 (sub-pixel conv)
+  UP       = D times: ReLU(conv3x3 64 -> 256) then shuffle by 2 (sub-pixel conv)
   I_SR     = H_rec(UP(F_DF))                      3x3, 64 -> 3, no ReLU  @HR
 
 Readings where the paper is silent (each one is listed with its reason in the
@@ -21,10 +22,10 @@ design notes of the repository):
     and feeds the block's local residual, so it has no ReLU (as in the
     residual dense blocks the paper follows); growth rate 64;
   * the equation for F_DF adds F_0 (the text names F_LRHS);
-  * UP mirrors the deshuffle: two stride-2 sub-pixel steps, each conv
+  * UP mirrors the deshuffle: D stride-2 sub-pixel steps, each conv
     followed by ReLU (every conv but the last has one);
   * the stride-2 deshuffle uses the channel convention of oracle/cnn.py
-    (HR pixel (2Y+i, 2X+j), channel c -> channel (2i+j) C + c), applied twice;
+    (HR pixel (2Y+i, 2X+j), channel c -> channel (2i+j) C + c), applied D times;
   * inputs, preprocessing and parameter layout are those of oracle/cnn.py.
 
 The robust loss is the paper's l_r with robust factor beta (Sec. 4, loss
@@ -44,38 +45,44 @@ N_BLOCKS = 5      # B, RDBs per group
 N_CONVS = 4       # convs per RDB
 GROWTH = 64
 ALPHA = 2         # deshuffle / shuffle stride
-N_DSF = 2         # D, stacked deshuffles (total factor ALPHA ** N_DSF = 4)
-SCALE = ALPHA ** N_DSF
+SCALES = (2, 4, 8)
+
+
+def n_dsf(scale):
+    """D, the stacked stride-2 deshuffles (and upscaling steps) of a scale."""
+    if scale not in SCALES:
+        raise ValueError(f"scale {scale} not in {SCALES}")
+    return {2: 1, 4: 2, 8: 3}[scale]
 
 
 def rdb_name(g, b, c):
     return f"g{g}b{b}c{c}"
 
 
-def layer_specs():
+def layer_specs(scale=4):
     """[(name, c_out, c_in, k)] in parameter order."""
     specs = [("hrls", FEAT, 10, 3), ("lrhs", FEAT, 3, 3),
-             ("fuse", FEAT, FEAT + SCALE * SCALE * FEAT, 1)]
+             ("fuse", FEAT, FEAT + scale * scale * FEAT, 1)]
     for g in range(N_GROUPS):
         for b in range(N_BLOCKS):
             for c in range(N_CONVS):
                 cout = GROWTH if c < N_CONVS - 1 else FEAT
                 specs.append((rdb_name(g, b, c), cout, FEAT + c * GROWTH, 3))
-    for i in range(N_DSF):
+    for i in range(n_dsf(scale)):
         specs.append((f"up{i}", ALPHA * ALPHA * FEAT, FEAT, 3))
     specs.append(("rec", 3, FEAT, 3))
     return specs
 
 
-def num_params():
-    return sum(co * ci * k * k + co for _, co, ci, k in layer_specs())
+def num_params(scale=4):
+    return sum(co * ci * k * k + co for _, co, ci, k in layer_specs(scale))
 
 
-def unpack(params):
+def unpack(params, scale=4):
     params = np.asarray(params, np.float64)
     out = {}
     off = 0
-    for name, co, ci, k in layer_specs():
+    for name, co, ci, k in layer_specs(scale):
         nw = co * ci * k * k
         out[name] = (params[off:off + nw].reshape(co, ci, k, k), params[off + nw:off + nw + co])
         off += nw + co
@@ -83,9 +90,9 @@ def unpack(params):
     return out
 
 
-def deshuffle_stack(x):
+def deshuffle_stack(x, scale=4):
     """F_HRLS = DSF^D(...DSF^1(x)...): D stride-ALPHA deshuffles."""
-    for _ in range(N_DSF):
+    for _ in range(n_dsf(scale)):
         x = unshuffle(x, ALPHA)
     return x
 
@@ -98,13 +105,13 @@ def rdb(x0, L, g, b):
     return x0 + conv(np.concatenate(xs, -1), *L[rdb_name(g, b, N_CONVS - 1)]), xs
 
 
-def forward(params, hrls_rgb, hrls_aux, lrhs_rgb, keep=False):
-    """I_SR [B,H,W,3] from HRLS rgb [B,H,W,3], aux [B,H,W,7], LRHS rgb [B,H/4,W/4,3]."""
-    L = unpack(params)
+def forward(params, hrls_rgb, hrls_aux, lrhs_rgb, keep=False, scale=4):
+    """I_SR [B,H,W,3] from HRLS rgb [B,H,W,3], aux [B,H,W,7], LRHS rgb [B,H/s,W/s,3]."""
+    L = unpack(params, scale)
     xh, xl = preprocess(hrls_rgb, hrls_aux, lrhs_rgb)
     h0 = relu(conv(xh, *L["hrls"]))                   # F^0_HRLS
     fl = relu(conv(xl, *L["lrhs"]))                   # F_LRHS
-    cat = np.concatenate([fl, deshuffle_stack(h0)], -1)
+    cat = np.concatenate([fl, deshuffle_stack(h0, scale)], -1)
     f0 = relu(conv(cat, *L["fuse"]))                  # F_0
     acts = {"xh": xh, "xl": xl, "h0": h0, "fl": fl, "cat": cat, "f0": f0, "dense": {}}
     F = f0
@@ -118,7 +125,7 @@ def forward(params, hrls_rgb, hrls_aux, lrhs_rgb, keep=False):
     acts["fdf"] = fdf
     u = fdf
     acts["up_in"], acts["up_act"] = [], []
-    for i in range(N_DSF):
+    for i in range(n_dsf(scale)):
         a = relu(conv(u, *L[f"up{i}"]))
         acts["up_in"].append(u)
         acts["up_act"].append(a)
@@ -129,12 +136,12 @@ def forward(params, hrls_rgb, hrls_aux, lrhs_rgb, keep=False):
     return (out, acts) if keep else out
 
 
-def backward(params, acts, gout):
+def backward(params, acts, gout, scale=4):
     """dL/dparams (flat, float64) given dL/dI_SR, by hand through forward()."""
-    L = unpack(params)
+    L = unpack(params, scale)
     g = {}
     du, g["rec_w"], g["rec_b"] = conv_backward(acts["u"], L["rec"][0], gout)
-    for i in reversed(range(N_DSF)):
+    for i in reversed(range(n_dsf(scale))):
         da = unshuffle(du, ALPHA) * (acts["up_act"][i] > 0)
         du, g[f"up{i}_w"], g[f"up{i}_b"] = conv_backward(acts["up_in"][i], L[f"up{i}"][0], da)
     dfdf = du
@@ -163,13 +170,13 @@ def backward(params, acts, gout):
     dcat, g["fuse_w"], g["fuse_b"] = conv_backward(acts["cat"], L["fuse"][0], df0)
     dfl = dcat[..., :FEAT] * (acts["fl"] > 0)
     dfh = dcat[..., FEAT:]
-    for _ in range(N_DSF):                            # adjoint of the stacked deshuffle
+    for _ in range(n_dsf(scale)):                     # adjoint of the stacked deshuffle
         dfh = shuffle(dfh, ALPHA)
     dh0 = dfh * (acts["h0"] > 0)
     _, g["lrhs_w"], g["lrhs_b"] = conv_backward(acts["xl"], L["lrhs"][0], dfl)
     _, g["hrls_w"], g["hrls_b"] = conv_backward(acts["xh"], L["hrls"][0], dh0)
     return np.concatenate([np.concatenate([g[f"{n}_w"].ravel(), g[f"{n}_b"].ravel()])
-                           for n, *_ in layer_specs()])
+                           for n, *_ in layer_specs(scale)])
 
 
 def robust_loss(out, target, beta=0.1):

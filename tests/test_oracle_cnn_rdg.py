@@ -15,10 +15,10 @@ import torch
 from oracle import cnn, cnn_rdg as rdg
 
 
-def _rand_params(seed, scale=1.0, branch_scale=0.1):
+def _rand_params(seed, scale=1.0, branch_scale=0.1, sr=4):
     rng = np.random.default_rng(seed)
     out = []
-    for name, co, ci, k in rdg.layer_specs():
+    for name, co, ci, k in rdg.layer_specs(sr):
         bound = math.sqrt(6.0 / (ci * k * k)) * scale
         if name.endswith(f"c{rdg.N_CONVS - 1}"):
             bound *= branch_scale  # keep the 15-block residual chain at its input's scale
@@ -27,14 +27,14 @@ def _rand_params(seed, scale=1.0, branch_scale=0.1):
     return np.concatenate(out)
 
 
-def _inputs(seed, B, H, W):
+def _inputs(seed, B, H, W, sr=4):
     rng = np.random.default_rng(seed)
     hr = rng.gamma(1.0, 0.5, (B, H, W, 3))
     hr[rng.random((B, H, W)) < 0.01] *= 300.0
     aux = np.concatenate([rng.uniform(0, 1, (B, H, W, 3)),
                           rng.normal(0, 1, (B, H, W, 3)),
                           rng.uniform(0, 20, (B, H, W, 1))], -1)
-    lr = rng.gamma(1.0, 0.5, (B, H // 4, W // 4, 3))
+    lr = rng.gamma(1.0, 0.5, (B, H // sr, W // sr, 3))
     return hr, aux, lr
 
 
@@ -45,6 +45,12 @@ def test_param_count():
     assert rdg.num_params() == 5_907_907
     names = [s[0] for s in rdg.layer_specs()]
     assert len(names) == 3 + 60 + 3 and len(set(names)) == len(names)
+    # x2: fuse 64*(64 + 256) + 64 = 20,544, one upscale conv 147,712
+    assert rdg.num_params(2) == 5_824 + 1_792 + 20_544 + 5_533_440 + 147_712 + 1_731
+    # x8: fuse 64*(64 + 4096) + 64 = 266,304, three upscale convs 443,136
+    assert rdg.num_params(8) == 5_824 + 1_792 + 266_304 + 5_533_440 + 443_136 + 1_731
+    with pytest.raises(ValueError):
+        rdg.layer_specs(3)
 
 
 def test_deshuffle_stack_index_map():
@@ -88,13 +94,14 @@ def test_branches_off_leave_the_residual_skeleton():
             assert np.array_equal(nxt, acts["dense"][g, b][0])
 
 
-def _torch_forward(flat, hr, aux, lr):
+def _torch_forward(flat, hr, aux, lr, sr=4):
     """Independent float64 torch implementation of the same architecture, NCHW,
     with torch's pixel (un)shuffle and the channel permutations between its
     convention and the oracle's."""
+    D = {2: 1, 4: 2, 8: 3}[sr]
     offs = {}
     off = 0
-    for name, co, ci, k in rdg.layer_specs():
+    for name, co, ci, k in rdg.layer_specs(sr):
         offs[name] = (off, co, ci, k)
         off += co * ci * k * k + co
 
@@ -111,7 +118,7 @@ def _torch_forward(flat, hr, aux, lr):
     h0 = torch.relu(conv(xh, "hrls"))
     fl = torch.relu(conv(xl, "lrhs"))
     fh = h0
-    for _ in range(2):  # torch: channel c*4 + q; oracle: q*C + c
+    for _ in range(D):  # torch: channel c*4 + q; oracle: q*C + c
         C = fh.shape[1]
         fh = torch.nn.functional.pixel_unshuffle(fh, 2)
         fh = fh[:, torch.tensor([c * 4 + q for q in range(4) for c in range(C)])]
@@ -126,7 +133,7 @@ def _torch_forward(flat, hr, aux, lr):
             s = s + conv(torch.cat(xs, 1), f"g{g}b{b}c3")
         F = s + F
     u = F + f0
-    for i in range(2):
+    for i in range(D):
         a = torch.relu(conv(u, f"up{i}"))
         C = a.shape[1] // 4
         a = a[:, torch.tensor([q * C + c for c in range(C) for q in range(4)])]
@@ -143,6 +150,25 @@ def test_forward_cross_check_torch():
     scale = np.abs(ref).max()
     assert scale > 1e-3
     assert np.allclose(out, ref, rtol=1e-10, atol=1e-12 * scale)
+
+
+@pytest.mark.parametrize("sr", [2, 8])
+def test_other_scales_cross_check_torch(sr):
+    """x2 (one deshuffle, one upscaling step) and x8 (three of each): forward
+    against the torch implementation, backward against torch autograd."""
+    params = _rand_params(20 + sr, sr=sr)
+    hr, aux, lr = _inputs(21 + sr, 1, 16, 24, sr=sr)
+    target = np.random.default_rng(22).gamma(1.0, 0.5, (1, 16, 24, 3))
+    out, acts = rdg.forward(params, hr, aux, lr, keep=True, scale=sr)
+    p = torch.from_numpy(params.copy()).requires_grad_(True)
+    y = _torch_forward(p, hr, aux, lr, sr=sr)
+    assert out.shape == (1, 16, 24, 3)
+    assert np.allclose(out, y.detach().numpy(), rtol=1e-10, atol=1e-12 * np.abs(out).max())
+    g = rdg.backward(params, acts, rdg.robust_grad(out, target, 0.1), scale=sr)
+    d = (y - torch.from_numpy(target).clamp(0, 100)).abs()
+    (d / (0.1 + d)).mean().backward()
+    ref = p.grad.numpy()
+    assert np.allclose(g, ref, rtol=1e-8, atol=1e-12 * np.abs(ref).max())
 
 
 def test_backward_cross_check_autograd_robust_loss():
