@@ -308,6 +308,12 @@ typedef struct mrs_net mrs_net;
 #define MRS_NET_RES16 0
 #define MRS_NET_RDG 1
 #define MRS_NET_RDG_NUM_PARAMS 5907907
+/* The paper's network at x2 and x8 (Sec. 4: D stacked stride-2 deshuffles for
+ * scale 2^D, as many upscaling steps; the fuse conv reads 64 + 64 4^D
+ * channels): 5,711,043 and 6,252,227 parameters (up0..up{D-1}).  W and H (and
+ * the LRHS image, W/s x H/s) must be multiples of the scale s. */
+#define MRS_NET_RDG_X2 2
+#define MRS_NET_RDG_X8 3
 
 int64_t mrs_net_num_params(void);                 /* MRS_NET_RES16's count */
 int64_t mrs_net_arch_num_params(int32_t arch);     /* -1 for an unknown arch */

@@ -53,7 +53,8 @@ class SceneDesc(C.Structure):
                 ("camera", Camera)]
 
 
-NET_ARCHS = {"res16": 0, "rdg": 1}
+NET_ARCHS = {"res16": 0, "rdg": 1, "rdg_x2": 2, "rdg_x8": 3}
+NET_SCALES = {"res16": 4, "rdg": 4, "rdg_x2": 2, "rdg_x8": 8}
 LOSSES = {"l1": 0, "robust": 1}
 OPTIMIZERS = {"adam": 0, "sgd": 1}
 

@@ -53,13 +53,16 @@ __device__ __forceinline__ bf16x8 ld8(const uint16_t* p) {
 }
 
 // Offset (I, J) inside its r x r block of the HR pixel held by unshuffle slot
-// q.  One stride-r unshuffle: q = I r + J.  Two stacked stride-2 deshuffles
-// (r = 4): the first consumes the low bits, q = 4 (2 (I>>1) + (J>>1)) +
-// 2 (I&1) + (J&1).
+// q.  One stride-r unshuffle (dsf = 0): q = I r + J.  dsf stacked stride-2
+// deshuffles (r = 2^dsf), the first consuming the low bits: base-4 digit k of
+// q is 2 (bit k of I) + (bit k of J).
 __device__ __forceinline__ void unshuffle_slot(int q, int r, int dsf, int& I, int& J) {
   if (dsf) {
-    I = ((q >> 3) << 1) | ((q >> 1) & 1);
-    J = (((q >> 2) & 1) << 1) | (q & 1);
+    I = J = 0;
+    for (int k = 0; k < dsf; ++k) {
+      J |= ((q >> (2 * k)) & 1) << k;
+      I |= ((q >> (2 * k + 1)) & 1) << k;
+    }
   } else {
     I = q / r;
     J = q - I * r;

@@ -25,7 +25,7 @@ struct ConvArgs {
   int cb;
   int c0;
   int r;
-  int dsf;  // CONCAT_UNSHUFFLE with r = 4: 1 = two stacked stride-2 deshuffles
+  int dsf;  // CONCAT_UNSHUFFLE: 0 = one stride-r unshuffle, D = D stacked stride-2 (r = 2^D)
   int B, H, W;  // output (and input) resolution of this conv
   int cin_p;    // channels per tap as laid out in K (multiple of 8)
   int taps;     // 1 or 9
@@ -63,7 +63,7 @@ struct BwdEpi {
   int r;
   const uint16_t* mask2;  // FUSE n >= c_split: mask at the HR index
   uint16_t* out_h2;       // FUSE n >= c_split: BF16 output at the HR index
-  int dsf;                // FUSE: the unshuffle is two stacked stride-2 deshuffles
+  int dsf;                // FUSE: as ConvArgs::dsf
   // DENSE: data gradient of the conv of a residual dense block that reads the
   // first k 64-channel slices of the block's dense tensor [x_0 .. x_3].
   int k;
@@ -124,9 +124,13 @@ constexpr int RDG_GROUPS = 3;
 constexpr int RDG_BLOCKS = 5;
 constexpr int RDG_CONVS = 4;
 constexpr int RDG_DENSE = NET_FEAT * RDG_CONVS;  // channels of a block's dense tensor
-constexpr int64_t RDG_NUM_PARAMS = 5907907;
 constexpr int RDG_L_DENSE = 3;                                             // first dense conv
-constexpr int RDG_L_UP = RDG_L_DENSE + RDG_GROUPS * RDG_BLOCKS * RDG_CONVS;  // up0, up1, rec
+constexpr int RDG_L_UP = RDG_L_DENSE + RDG_GROUPS * RDG_BLOCKS * RDG_CONVS;  // up0.., rec
+constexpr int RDG_MAX_DSF = 3;
+// scale (2, 4 or 8) of an architecture; D = log2(scale) for the dense-group nets
+int arch_scale(int arch);
+int arch_dsf(int arch);
+bool arch_is_rdg(int arch);
 
 std::vector<NetLayer> make_layers(int arch);
 size_t align256(size_t v);

@@ -46,33 +46,49 @@ std::vector<Spec> specs_res16() {
 // upscaling convs, reconstruction (also scaled by 0.1, so that the first
 // outputs are near the scale of the images rather than ~10x above it, where
 // the robust loss is flat and training drifts away).
-std::vector<Spec> specs_rdg() {
+// D = log2(scale) stacked stride-2 deshuffles and as many upscaling steps.
+std::vector<Spec> specs_rdg(int D) {
   static std::vector<std::string> names;
-  if (names.empty())
+  if (names.empty()) {
     for (int g = 0; g < RDG_GROUPS; ++g)
       for (int b = 0; b < RDG_BLOCKS; ++b)
         for (int c = 0; c < RDG_CONVS; ++c)
           names.push_back("g" + std::to_string(g) + "b" + std::to_string(b) + "c" +
                           std::to_string(c));
+    for (int k = 0; k < RDG_MAX_DSF; ++k) names.push_back("up" + std::to_string(k));
+  }
+  const int fuse_in = NET_FEAT + (1 << (2 * D)) * NET_FEAT;
   std::vector<Spec> specs = {{"hrls", NET_FEAT, 10, 3, 16, 0, 1.0f},
-                             {"lrhs", NET_FEAT, 3, 3, 8, 2, 1.0f},
-                             {"fuse", NET_FEAT, NET_FEAT + NET_SCALE * NET_SCALE * NET_FEAT, 1,
-                              NET_FEAT + NET_SCALE * NET_SCALE * NET_FEAT, 2, 1.0f}};
-  for (int i = 0; i < RDG_GROUPS * RDG_BLOCKS * RDG_CONVS; ++i) {
+                             {"lrhs", NET_FEAT, 3, 3, 8, D, 1.0f},
+                             {"fuse", NET_FEAT, fuse_in, 1, fuse_in, D, 1.0f}};
+  const int ndense = RDG_GROUPS * RDG_BLOCKS * RDG_CONVS;
+  for (int i = 0; i < ndense; ++i) {
     const int c = i % RDG_CONVS, cin = NET_FEAT * (c + 1);
-    specs.push_back({names[i].c_str(), NET_FEAT, cin, 3, cin, 2,
+    specs.push_back({names[i].c_str(), NET_FEAT, cin, 3, cin, D,
                      c == RDG_CONVS - 1 ? 0.1f : 1.0f});
   }
-  specs.push_back({"up0", 4 * NET_FEAT, NET_FEAT, 3, NET_FEAT, 2, 1.0f});
-  specs.push_back({"up1", 4 * NET_FEAT, NET_FEAT, 3, NET_FEAT, 1, 1.0f});
+  for (int k = 0; k < D; ++k)  // step k runs at HR / 2^(D - k)
+    specs.push_back({names[ndense + k].c_str(), 4 * NET_FEAT, NET_FEAT, 3, NET_FEAT, D - k, 1.0f});
   specs.push_back({"rec", 3, NET_FEAT, 3, NET_FEAT, 0, 0.1f});
   return specs;
 }
 
 }  // namespace
 
+int arch_scale(int arch) {
+  return arch == MRS_NET_RDG_X2 ? 2 : arch == MRS_NET_RDG_X8 ? 8 : 4;
+}
+
+int arch_dsf(int arch) {
+  return arch == MRS_NET_RDG_X2 ? 1 : arch == MRS_NET_RDG_X8 ? 3 : 2;
+}
+
+bool arch_is_rdg(int arch) {
+  return arch == MRS_NET_RDG || arch == MRS_NET_RDG_X2 || arch == MRS_NET_RDG_X8;
+}
+
 std::vector<NetLayer> make_layers(int arch) {
-  const std::vector<Spec> specs = arch == MRS_NET_RDG ? specs_rdg() : specs_res16();
+  const std::vector<Spec> specs = arch_is_rdg(arch) ? specs_rdg(arch_dsf(arch)) : specs_res16();
   std::vector<NetLayer> L;
   int64_t off = 0, pk = 0, pkt = 0;
   for (const Spec& s : specs) {
@@ -634,9 +650,11 @@ mrs_status check_train_args(mrs_net* n, int B, const float* hr, const float* aux
   if (!n) return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_train_step: net is NULL");
   if (!hr || !aux || !lr || !tgt)
     return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_train_step: NULL buffer");
-  if (B < 1 || W < 4 || H < 4 || W % 4 || H % 4 || (int64_t)B * W * H > (int64_t)1 << 26)
+  const int sc = arch_scale(n->arch);
+  if (B < 1 || W < sc || H < sc || W % sc || H % sc || (int64_t)B * W * H > (int64_t)1 << 26)
     return fail(MRS_ERR_INVALID_ARGUMENT,
-                "mrs_train_step: W, H multiples of 4 (>= 4), B >= 1, B*W*H <= 2^26");
+                "mrs_train_step: W, H multiples of the net's scale (" + std::to_string(sc) +
+                    "), B >= 1, B*W*H <= 2^26");
   if (((uintptr_t)hr | (uintptr_t)aux | (uintptr_t)lr | (uintptr_t)tgt) & 3u)
     return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_train_step: buffers must be 4-byte aligned");
   if (!n->has_params) return fail(MRS_ERR_NOT_READY, "mrs_train_step: no parameters");
@@ -657,7 +675,7 @@ mrs_status loss_and_grad(mrs_net* n, int B, const float* hr, const float* aux, c
   og.part = n->d_lpart;
   og.nparts = L1_PARTS;
   og.loss = n->d_loss;
-  if (n->arch == MRS_NET_RDG) return rdg_loss_grad(n, B, H, W, hr, aux, lr, og, out, st);
+  if (arch_is_rdg(n->arch)) return rdg_loss_grad(n, B, H, W, hr, aux, lr, og, out, st);
   TrainArena A;
   rc = ensure_train(n, B, H, W, A);
   if (rc != MRS_OK) return rc;
@@ -674,7 +692,11 @@ mrs_status loss_and_grad(mrs_net* n, int B, const float* hr, const float* aux, c
 }
 
 int64_t arch_params(int32_t arch) {
-  return arch == MRS_NET_RES16 ? NET_NUM_PARAMS : arch == MRS_NET_RDG ? RDG_NUM_PARAMS : -1;
+  if (arch == MRS_NET_RES16) return NET_NUM_PARAMS;
+  if (!arch_is_rdg(arch)) return -1;
+  int64_t n = 0;
+  for (const NetLayer& L : make_layers(arch)) n += (int64_t)L.cout * L.cin * L.k * L.k + L.cout;
+  return n;
 }
 
 mrs_status check_loss(int32_t loss, float beta, const char* who) {
@@ -780,14 +802,16 @@ mrs_status mrs_fuse_batch(mrs_net* n, int32_t B, const float* hr, const float* a
                           const float* lr, int32_t W, int32_t H, float* out) {
   if (!n) return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_fuse: net is NULL");
   if (!hr || !aux || !lr || !out) return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_fuse: NULL buffer");
-  if (B < 1 || W < 4 || H < 4 || W % 4 || H % 4 || W > 16384 || H > 16384 ||
+  const int sc = arch_scale(n->arch);
+  if (B < 1 || W < sc || H < sc || W % sc || H % sc || W > 16384 || H > 16384 ||
       (int64_t)B * W * H > (int64_t)1 << 30)
     return fail(MRS_ERR_INVALID_ARGUMENT,
-                "mrs_fuse: W and H must be multiples of 4 in [4, 16384], B >= 1, B*W*H <= 2^30");
+                "mrs_fuse: W and H must be multiples of the net's scale (" + std::to_string(sc) +
+                    ") in [scale, 16384], B >= 1, B*W*H <= 2^30");
   if (((uintptr_t)hr | (uintptr_t)aux | (uintptr_t)lr | (uintptr_t)out) & 3u)
     return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_fuse: buffers must be 4-byte aligned");
   if (!n->has_params) return fail(MRS_ERR_NOT_READY, "mrs_fuse: no network parameters loaded");
-  if (n->arch == MRS_NET_RDG) return rdg_forward(n, B, H, W, hr, aux, lr, out, current_stream());
+  if (arch_is_rdg(n->arch)) return rdg_forward(n, B, H, W, hr, aux, lr, out, current_stream());
   return net_forward(n, B, H, W, hr, aux, lr, out, current_stream());
 }
 
@@ -933,7 +957,8 @@ mrs_status mrs_debug_net_activation(const mrs_net* n, int32_t which, float* out_
                                     int64_t count) {
   if (!n || !out_host) return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_debug_net_activation: NULL");
   if (!n->last_f0) return fail(MRS_ERR_NOT_READY, "mrs_debug_net_activation: no forward yet");
-  const int64_t want = (int64_t)n->last_B * (n->last_H / 4) * (n->last_W / 4) * NET_FEAT;
+  const int sc = arch_scale(n->arch);
+  const int64_t want = (int64_t)n->last_B * (n->last_H / sc) * (n->last_W / sc) * NET_FEAT;
   if (count != want || (which != 0 && which != 1))
     return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_debug_net_activation: bad which/count");
   hipStream_t st = current_stream();

@@ -37,22 +37,25 @@ const NetLayer& dense_layer(const mrs_net* net, int g, int b, int c) {
 // Activations of a forward pass.  Inference keeps two dense tensors (the
 // current block's and the next one's slot 0); training keeps one per block.
 struct RdgActs {
-  uint16_t *xh, *xl, *h0, *fl, *fdfh, *U0, *U1;
+  uint16_t *xh, *xl, *h0, *fl, *fdfh;
+  uint16_t* U[RDG_MAX_DSF];  // upscaling step k's ReLU output, 256 channels at LR 2^k
   uint16_t* D[NB];
   float *f0f, *S[2], *F[2], *fdf, *out;
 };
 
-void plan_acts(std::vector<std::pair<void**, size_t>>& plan, RdgActs& A, size_t P, int ndense,
-               bool out) {
-  const size_t p = P / 16;
+// Pixels of the LR image of a net with D stacked deshuffles.
+size_t lr_pixels(size_t P, int D) { return P >> (2 * D); }
+
+void plan_acts(std::vector<std::pair<void**, size_t>>& plan, RdgActs& A, size_t P, int D,
+               int ndense, bool out) {
+  const size_t p = lr_pixels(P, D);
   auto add = [&](void** ptr, size_t bytes) { plan.push_back({ptr, bytes}); };
   add((void**)&A.xh, P * 16 * 2);
   add((void**)&A.xl, p * 8 * 2);
   add((void**)&A.h0, P * NET_FEAT * 2);
   add((void**)&A.fl, p * NET_FEAT * 2);
   add((void**)&A.fdfh, p * NET_FEAT * 2);
-  add((void**)&A.U0, p * 4 * NET_FEAT * 2);
-  add((void**)&A.U1, 4 * p * 4 * NET_FEAT * 2);
+  for (int k = 0; k < D; ++k) add((void**)&A.U[k], (p << (2 * k)) * 4 * NET_FEAT * 2);
   for (int i = 0; i < ndense; ++i) add((void**)&A.D[i], p * RDG_DENSE * 2);
   add((void**)&A.f0f, p * NET_FEAT * 4);
   for (int i = 0; i < 2; ++i) add((void**)&A.S[i], p * NET_FEAT * 4);
@@ -66,8 +69,9 @@ void plan_acts(std::vector<std::pair<void**, size_t>>& plan, RdgActs& A, size_t 
 void forward(mrs_net* net, const RdgActs& A, bool keep, int B, int H, int W, const float* hr,
              const float* aux, const float* lr, float* out, hipStream_t st) {
   const std::vector<NetLayer>& Ls = net->layers;
-  const int h = H / NET_SCALE, w = W / NET_SCALE;
-  const int64_t P = (int64_t)B * H * W, p = P / 16;
+  const int Dn = arch_dsf(net->arch), sc = 1 << Dn;
+  const int h = H / sc, w = W / sc;
+  const int64_t P = (int64_t)B * H * W, p = (int64_t)lr_pixels(P, Dn);
   prof_begin(KID_CNN_PREP, st);
   launch_prep(P, p, hr, aux, lr, A.xh, A.xl, st);
   prof_end(KID_CNN_PREP, st);
@@ -92,15 +96,15 @@ void forward(mrs_net* net, const RdgActs& A, bool keep, int B, int H, int W, con
     a.out_h_stride = NET_FEAT;
     launch_conv(a, Ls[1].cout_p, st);
   }
-  {  // F0 = ReLU(fuse [F_LRHS, DSF(DSF(F^0_HRLS))]) -> FP32 and slot 0 of the first block
+  {  // F0 = ReLU(fuse [F_LRHS, DSF^D(F^0_HRLS)]) -> FP32 and slot 0 of the first block
     ConvArgs a = base_args(net, Ls[2], B, h, w);
     a.mode = VIEW_CONCAT_UNSHUFFLE;
     a.a = A.fl;
     a.ca = NET_FEAT;
     a.b = A.h0;
     a.cb = NET_FEAT;
-    a.r = NET_SCALE;
-    a.dsf = 1;
+    a.r = sc;
+    a.dsf = Dn;
     a.relu = 1;
     a.out_f = A.f0f;
     a.out_f_stride = NET_FEAT;
@@ -150,37 +154,32 @@ void forward(mrs_net* net, const RdgActs& A, bool keep, int B, int H, int W, con
       if (last) Fprev = of;
     }
   }
-  const NetLayer& Lu0 = Ls[RDG_L_UP];
-  const NetLayer& Lu1 = Ls[RDG_L_UP + 1];
-  const NetLayer& Lr = Ls[RDG_L_UP + 2];
-  {  // U0 = ReLU(conv FDF), 256 channels at LR
-    ConvArgs a = base_args(net, Lu0, B, h, w);
-    a.a = A.fdfh;
-    a.ca = NET_FEAT;
+  for (int k = 0; k < Dn; ++k) {  // U_k = ReLU(conv (k ? shuffle2(U_{k-1}) : FDF)), 256 ch
+    const NetLayer& Lu = Ls[RDG_L_UP + k];
+    ConvArgs a = base_args(net, Lu, B, h << k, w << k);
+    if (k == 0) {
+      a.a = A.fdfh;
+      a.ca = NET_FEAT;
+    } else {
+      a.mode = VIEW_SHUFFLE_CONCAT;
+      a.a = A.U[k - 1];
+      a.ca = 4 * NET_FEAT;
+      a.c0 = NET_FEAT;
+      a.r = 2;
+    }
     a.relu = 1;
-    a.out_h = A.U0;
-    a.out_h_stride = Lu0.cout;
-    launch_conv(a, Lu0.cout_p, st);
-  }
-  {  // U1 = ReLU(conv shuffle2(U0)), 256 channels at HR/2
-    ConvArgs a = base_args(net, Lu1, B, 2 * h, 2 * w);
-    a.mode = VIEW_SHUFFLE_CONCAT;
-    a.a = A.U0;
-    a.ca = Lu0.cout;
-    a.c0 = NET_FEAT;
-    a.r = 2;
-    a.relu = 1;
-    a.out_h = A.U1;
-    a.out_h_stride = Lu1.cout;
-    launch_conv(a, Lu1.cout_p, st);
+    a.out_h = A.U[k];
+    a.out_h_stride = Lu.cout;
+    launch_conv(a, Lu.cout_p, st);
   }
   prof_end(KID_CNN_LR, st);
   prof_begin(KID_CNN_REC, st);
-  {  // I_SR = conv shuffle2(U1)
+  {  // I_SR = conv shuffle2(U_{D-1})
+    const NetLayer& Lr = Ls[RDG_L_UP + Dn];
     ConvArgs a = base_args(net, Lr, B, H, W);
     a.mode = VIEW_SHUFFLE_CONCAT;
-    a.a = A.U1;
-    a.ca = Lu1.cout;
+    a.a = A.U[Dn - 1];
+    a.ca = 4 * NET_FEAT;
     a.c0 = NET_FEAT;
     a.r = 2;
     a.out_f = out;
@@ -192,16 +191,16 @@ void forward(mrs_net* net, const RdgActs& A, bool keep, int B, int H, int W, con
 
 // Gradient buffers of the backward pass.
 struct RdgGrads {
-  uint16_t *g8, *dU0, *dU1, *dfdfh, *dFh[2], *dsh[2], *dy[2], *df0h, *dflh, *dh0h;
+  uint16_t *g8, *dfdfh, *dFh[2], *dsh[2], *dy[2], *df0h, *dflh, *dh0h;
+  uint16_t* dU[RDG_MAX_DSF];
   float *dfdf, *dF[2], *dsf[2], *ga;
 };
 
-void plan_grads(std::vector<std::pair<void**, size_t>>& plan, RdgGrads& G, size_t P) {
-  const size_t p = P / 16;
+void plan_grads(std::vector<std::pair<void**, size_t>>& plan, RdgGrads& G, size_t P, int D) {
+  const size_t p = lr_pixels(P, D);
   auto add = [&](void** ptr, size_t bytes) { plan.push_back({ptr, bytes}); };
   add((void**)&G.g8, P * 8 * 2);
-  add((void**)&G.dU0, p * 4 * NET_FEAT * 2);
-  add((void**)&G.dU1, 4 * p * 4 * NET_FEAT * 2);
+  for (int k = 0; k < D; ++k) add((void**)&G.dU[k], (p << (2 * k)) * 4 * NET_FEAT * 2);
   add((void**)&G.dfdfh, p * NET_FEAT * 2);
   for (int i = 0; i < 2; ++i) {
     add((void**)&G.dFh[i], p * NET_FEAT * 2);
@@ -225,51 +224,45 @@ ConvArgs dense_view(const mrs_net* net, const NetLayer& L, int B, int h, int w,
   return x;
 }
 
+// The input view of upscaling step k (k >= 1) or of the reconstruction conv
+// (k = D): shuffle2 of U_{k-1}, at LR resolution x 2^k.
+ConvArgs shuffle_view(const mrs_net* net, const NetLayer& L, int B, int hk, int wk,
+                      const uint16_t* U) {
+  ConvArgs x = base_args(net, L, B, hk, wk);
+  x.mode = VIEW_SHUFFLE_CONCAT;
+  x.a = U;
+  x.ca = 4 * NET_FEAT;
+  x.c0 = NET_FEAT;
+  x.r = 2;
+  return x;
+}
+
 void backward(mrs_net* net, const RdgActs& A, const RdgGrads& G, int B, int H, int W,
               hipStream_t st) {
   const std::vector<NetLayer>& Ls = net->layers;
-  const int h = H / NET_SCALE, w = W / NET_SCALE;
-  const NetLayer& Lu0 = Ls[RDG_L_UP];
-  const NetLayer& Lu1 = Ls[RDG_L_UP + 1];
-  const NetLayer& Lr = Ls[RDG_L_UP + 2];
-  {  // rec: d shuffle2(U1) -> dU1 (masked by U1 > 0, stored as U1)
-    ConvArgs a = tconv_args(net, Lr, B, H, W, G.g8);
+  const int Dn = arch_dsf(net->arch), sc = 1 << Dn;
+  const int h = H / sc, w = W / sc;
+  // rec (k = D) and upscaling steps D-1 .. 1: d shuffle2(U_{k-1}) -> dU_{k-1}
+  // (masked by U_{k-1} > 0, stored like U_{k-1})
+  for (int k = Dn; k >= 1; --k) {
+    const NetLayer& L = Ls[RDG_L_UP + k];
+    const int hk = h << k, wk = w << k;
+    const uint16_t* dy = k == Dn ? G.g8 : G.dU[k];
+    const int dy_stride = k == Dn ? 8 : L.cout;
+    ConvArgs a = tconv_args(net, L, B, hk, wk, dy);
     BwdEpi e = plain_epi();
     e.mode = EPI_REC_SPLIT;
-    e.out_h = G.dU1;
-    e.mask = A.U1;
+    e.out_h = G.dU[k - 1];
+    e.mask = A.U[k - 1];
     e.c_split = NET_FEAT;
-    e.stride2 = Lu1.cout;
+    e.stride2 = 4 * NET_FEAT;
     e.r = 2;
-    launch_dgrad(a, e, Lr.coutp_t, st);
-    ConvArgs x = base_args(net, Lr, B, H, W);
-    x.mode = VIEW_SHUFFLE_CONCAT;
-    x.a = A.U1;
-    x.ca = Lu1.cout;
-    x.c0 = NET_FEAT;
-    x.r = 2;
-    wgrad(net, Lr, x, G.g8, 8, st);
-  }
-  {  // up1: d shuffle2(U0) -> dU0
-    ConvArgs a = tconv_args(net, Lu1, B, 2 * h, 2 * w, G.dU1);
-    BwdEpi e = plain_epi();
-    e.mode = EPI_REC_SPLIT;
-    e.out_h = G.dU0;
-    e.mask = A.U0;
-    e.c_split = NET_FEAT;
-    e.stride2 = Lu0.cout;
-    e.r = 2;
-    launch_dgrad(a, e, Lu1.coutp_t, st);
-    ConvArgs x = base_args(net, Lu1, B, 2 * h, 2 * w);
-    x.mode = VIEW_SHUFFLE_CONCAT;
-    x.a = A.U0;
-    x.ca = Lu0.cout;
-    x.c0 = NET_FEAT;
-    x.r = 2;
-    wgrad(net, Lu1, x, G.dU1, Lu1.cout, st);
+    launch_dgrad(a, e, L.coutp_t, st);
+    wgrad(net, L, shuffle_view(net, L, B, hk, wk, A.U[k - 1]), dy, dy_stride, st);
   }
   {  // up0: dFDF (FP32 + BF16)
-    ConvArgs a = tconv_args(net, Lu0, B, h, w, G.dU0);
+    const NetLayer& Lu0 = Ls[RDG_L_UP];
+    ConvArgs a = tconv_args(net, Lu0, B, h, w, G.dU[0]);
     BwdEpi e = plain_epi();
     e.out_f = G.dfdf;
     e.out_h = G.dfdfh;
@@ -277,7 +270,7 @@ void backward(mrs_net* net, const RdgActs& A, const RdgGrads& G, int B, int H, i
     ConvArgs x = base_args(net, Lu0, B, h, w);
     x.a = A.fdfh;
     x.ca = NET_FEAT;
-    wgrad(net, Lu0, x, G.dU0, Lu0.cout, st);
+    wgrad(net, Lu0, x, G.dU[0], Lu0.cout, st);
   }
   // groups, last to first; dF = gradient of F_g (the group's output)
   const float* dFf = G.dfdf;
@@ -332,7 +325,7 @@ void backward(mrs_net* net, const RdgActs& A, const RdgGrads& G, int B, int H, i
       dFh = G.dFh[g & 1];
     }
   }
-  {  // fuse: d[fl, DSF(DSF(h0))] -> dfl (masked) and dh0 (masked), no other use of h0
+  {  // fuse: d[fl, DSF^D(h0)] -> dfl (masked) and dh0 (masked), no other use of h0
     const NetLayer& Lf = Ls[2];
     ConvArgs a = tconv_args(net, Lf, B, h, w, G.df0h);
     BwdEpi e = plain_epi();
@@ -343,8 +336,8 @@ void backward(mrs_net* net, const RdgActs& A, const RdgGrads& G, int B, int H, i
     e.out_h = G.dflh;
     e.mask2 = A.h0;
     e.out_h2 = G.dh0h;
-    e.r = NET_SCALE;
-    e.dsf = 1;
+    e.r = sc;
+    e.dsf = Dn;
     launch_dgrad(a, e, Lf.coutp_t, st);
     ConvArgs x = base_args(net, Lf, B, h, w);
     x.mode = VIEW_CONCAT_UNSHUFFLE;
@@ -352,8 +345,8 @@ void backward(mrs_net* net, const RdgActs& A, const RdgGrads& G, int B, int H, i
     x.ca = NET_FEAT;
     x.b = A.h0;
     x.cb = NET_FEAT;
-    x.r = NET_SCALE;
-    x.dsf = 1;
+    x.r = sc;
+    x.dsf = Dn;
     wgrad(net, Lf, x, G.df0h, NET_FEAT, st);
   }
   {  // encoders: weight gradients only
@@ -375,7 +368,7 @@ mrs_status rdg_forward(mrs_net* net, int B, int H, int W, const float* hr, const
   RdgActs A;
   std::memset(&A, 0, sizeof A);
   std::vector<std::pair<void**, size_t>> plan;
-  plan_acts(plan, A, (size_t)B * H * W, 2, false);
+  plan_acts(plan, A, (size_t)B * H * W, arch_dsf(net->arch), 2, false);
   mrs_status rc = arena_carve(net->d_arena, net->arena_bytes, plan, st, "mrs_fuse");
   if (rc != MRS_OK) return rc;
   forward(net, A, false, B, H, W, hr, aux, lr, out, st);
@@ -396,8 +389,8 @@ mrs_status rdg_loss_grad(mrs_net* net, int B, int H, int W, const float* hr, con
   std::memset(&G, 0, sizeof G);
   const size_t P = (size_t)B * H * W;
   std::vector<std::pair<void**, size_t>> plan;
-  plan_acts(plan, A, P, NB, true);
-  plan_grads(plan, G, P);
+  plan_acts(plan, A, P, arch_dsf(net->arch), NB, true);
+  plan_grads(plan, G, P, arch_dsf(net->arch));
   mrs_status rc = arena_carve(net->d_train, net->train_bytes, plan, st, "mrs_train_step");
   if (rc != MRS_OK) return rc;
   rc = ensure_wpart(net, (int64_t)P, st);

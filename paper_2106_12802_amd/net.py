@@ -12,13 +12,15 @@ class FusionNet:
     """The HRLS + LRHS fusion network; parameters live on the GPU (FP32 masters + BF16).
 
     arch "res16": 16 residual blocks; "rdg": the paper's network of residual
-    dense groups (include/mrs.h documents both)."""
+    dense groups, x4 ("rdg_x2", "rdg_x8": the same at x2 and x8; include/mrs.h
+    documents them).  .scale is the HR / LR size ratio."""
 
     def __init__(self, seed: int | None = None, arch: str = "res16"):
         import torch  # noqa: F401  (initialises the HIP runtime through torch)
         if arch not in L.NET_ARCHS:
             raise ValueError(f"unknown arch {arch!r}")
         self.arch = arch
+        self.scale = L.NET_SCALES[arch]
         L.use_current_stream()
         h = C.c_void_p()
         L.check(L.lib().mrs_net_create_arch(L.NET_ARCHS[arch], C.byref(h)))
@@ -46,7 +48,7 @@ class FusionNet:
         return p
 
     def fuse(self, hrls_rgb, hrls_aux, lrhs_rgb, out=None):
-        """hrls_rgb [B,H,W,3] or [H,W,3], hrls_aux [...,7], lrhs_rgb [..,H/4,W/4,3] (CUDA fp32)."""
+        """hrls_rgb [B,H,W,3] or [H,W,3], hrls_aux [...,7], lrhs_rgb [..,H/s,W/s,3] (CUDA fp32)."""
         import torch
         batched = hrls_rgb.dim() == 4
         B = hrls_rgb.shape[0] if batched else 1
@@ -57,7 +59,7 @@ class FusionNet:
         L.use_current_stream()
         L.check(L.lib().mrs_fuse_batch(self.handle, B, L.ptr(hrls_rgb, 3 * P, "f32", "hrls_rgb"),
                                        L.ptr(hrls_aux, 7 * P, "f32", "hrls_aux"),
-                                       L.ptr(lrhs_rgb, 3 * P // 16, "f32", "lrhs_rgb"), W, H,
+                                       L.ptr(lrhs_rgb, 3 * P // self.scale ** 2, "f32", "lrhs_rgb"), W, H,
                                        L.ptr(out, 3 * P, "f32", "out")))
         return out
 
@@ -80,7 +82,7 @@ class FusionNet:
         P = B * H * W
         L.check(L.lib().mrs_net_loss_grad_ex(self.handle, B, L.ptr(hrls_rgb, 3 * P, "f32"),
                                              L.ptr(hrls_aux, 7 * P, "f32"),
-                                             L.ptr(lrhs_rgb, 3 * P // 16, "f32"),
+                                             L.ptr(lrhs_rgb, 3 * P // self.scale ** 2, "f32"),
                                              L.ptr(target, 3 * P, "f32"), W, H,
                                              L.LOSSES[loss], float(beta),
                                              g.ctypes.data_as(C.c_void_p), C.byref(value),
@@ -95,7 +97,7 @@ class FusionNet:
         P = B * H * W
         L.check(L.lib().mrs_net_backward(self.handle, B, L.ptr(hrls_rgb, 3 * P, "f32"),
                                          L.ptr(hrls_aux, 7 * P, "f32"),
-                                         L.ptr(lrhs_rgb, 3 * P // 16, "f32"), W, H,
+                                         L.ptr(lrhs_rgb, 3 * P // self.scale ** 2, "f32"), W, H,
                                          L.ptr(grad_out, 3 * P, "f32"),
                                          g.ctypes.data_as(C.c_void_p)))
         return g
@@ -111,7 +113,7 @@ class FusionNet:
         P = B * H * W
         L.check(L.lib().mrs_train_step_ex(self.handle, B, L.ptr(hrls_rgb, 3 * P, "f32"),
                                           L.ptr(hrls_aux, 7 * P, "f32"),
-                                          L.ptr(lrhs_rgb, 3 * P // 16, "f32"),
+                                          L.ptr(lrhs_rgb, 3 * P // self.scale ** 2, "f32"),
                                           L.ptr(target, 3 * P, "f32"), W, H, C.byref(opts),
                                           C.byref(value) if want_loss else None))
         return value.value if want_loss else None

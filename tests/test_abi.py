@@ -91,6 +91,8 @@ def test_net_arch_and_training_option_validation():
     L = _lib.lib()
     assert L.mrs_net_arch_num_params(_lib.NET_ARCHS["res16"]) == cnn.num_params()
     assert L.mrs_net_arch_num_params(_lib.NET_ARCHS["rdg"]) == cnn_rdg.num_params()
+    assert L.mrs_net_arch_num_params(_lib.NET_ARCHS["rdg_x2"]) == cnn_rdg.num_params(2)
+    assert L.mrs_net_arch_num_params(_lib.NET_ARCHS["rdg_x8"]) == cnn_rdg.num_params(8)
     assert L.mrs_net_arch_num_params(7) == -1
     h = C.c_void_p()
     assert L.mrs_net_create_arch(7, C.byref(h)) == 1 and not h.value
