@@ -165,24 +165,120 @@ def build_dataset(first_seed=100, n_scenes=64, windows=16, size=128, W=1280, H=7
 
 
 def train(net: FusionNet, data: PairSet, steps: int, batch=16, lr=1e-4, seed=0,
-          log_every=200, log=print, time_limit=None, start_step=0):
-    """Adam on the L1 loss over random batches; the batch order is a pure function of
-    (seed, step), so a run resumed from a checkpoint at step s continues identically."""
+          log_every=200, log=print, time_limit=None, start_step=0, loss="l1",
+          optimizer="adam"):
+    """Optimiser steps (Adam on L1 by default; the paper's setting is
+    loss="robust", optimizer="sgd") over random batches; the batch order is a pure
+    function of (seed, step), so a run resumed from a checkpoint at step s
+    continues identically."""
     losses = []
     t0 = time.perf_counter()
     done = start_step
     for step in range(start_step, steps):
         idx = np.random.default_rng([seed, step]).choice(len(data), batch, replace=False)
         want = (step + 1) % log_every == 0 or step == steps - 1
-        loss = net.train_step(*data.batch(idx), lr=lr, want_loss=want)
+        value = net.train_step(*data.batch(idx), lr=lr, want_loss=want, loss=loss,
+                               optimizer=optimizer)
         done = step + 1
         if want:
-            losses.append((done, loss))
+            losses.append((done, value))
             if log:
-                log(f"[train] step {done} loss {loss:.5f} ({time.perf_counter() - t0:.1f} s)")
+                log(f"[train] step {done} loss {value:.5f} ({time.perf_counter() - t0:.1f} s)")
         if time_limit is not None and time.perf_counter() - t0 > time_limit:
             break
     return losses, done
+
+
+# ------------------------------------------------- random spp pairs (Sec. 4)
+
+# The spp sets the paper draws from at every training iteration (Sec. 4,
+# implementation details); the HRLS spp is kept below the LRHS spp.
+SPP_HRLS = (1, 2, 3, 4, 5, 6, 7, 8, 12, 16, 32)
+SPP_LRHS = (2, 3, 4, 5, 6, 7, 8, 12, 16, 32, 64, 128, 250, 1000, 4000)
+
+
+def sample_spp_pair(rng):
+    """(spp_hrls, spp_lrhs): HRLS uniform over SPP_HRLS, then LRHS uniform over the
+    values of SPP_LRHS above it."""
+    h = int(rng.choice(SPP_HRLS))
+    lo = [v for v in SPP_LRHS if v > h]
+    return h, int(rng.choice(lo))
+
+
+class OnlinePairs:
+    """Training windows whose inputs are re-rendered at every iteration, at that
+    iteration's spp pair and with fresh seeds; the 1024-spp targets (FP64 sums,
+    seeds >= 2^40) are rendered once.  Window origins and sizes are multiples of
+    the network's scale."""
+
+    def __init__(self, specs, windows=16, size=128, W=1280, H=720, scale=SCALE,
+                 target_spp=1024, depth=DEPTH, log=print):
+        import torch
+        from mrs_inputs import scenes as S
+        self.scale, self.size, self.W, self.H, self.depth = scale, size, W, H, depth
+        self.scenes = []
+        self.wins = []
+        for seed, tris in specs:
+            gs = T.GpuScene(S.procedural_sized(seed, tris))
+            self.scenes.append(gs)
+            for (x0, y0) in S.training_windows(seed, windows, W, H, size):
+                x0 -= x0 % scale
+                y0 -= y0 % scale
+                self.wins.append((len(self.scenes) - 1, x0, y0, seed))
+        self.target = _empty((len(self.wins), size, size, 3))
+        for k, (si, x0, y0, seed) in enumerate(self.wins):
+            T.render_ex(self.scenes[si], W, H, target_spp, depth, REF_SEED + seed * 1000 + k,
+                        self.target[k], None, window=(x0, y0, size, size))
+        torch.cuda.synchronize()
+        if log:
+            log(f"[data] {len(self.wins)} windows of {len(self.scenes)} scenes, targets rendered")
+
+    def __len__(self):
+        return len(self.wins)
+
+    def batch(self, idx, spp_h, spp_l, seed):
+        """HRLS rgb/features, LRHS rgb and targets of windows idx, inputs rendered
+        now at (spp_h, spp_l) with frame seeds derived from `seed`."""
+        import torch
+        n, z, s = len(idx), self.size, self.scale
+        hr_rgb, hr_aux = _empty((n, z, z, 3)), _empty((n, z, z, 7))
+        lr_rgb = _empty((n, z // s, z // s, 3))
+        for b, k in enumerate(idx):
+            si, x0, y0, _ = self.wins[k]
+            fseed = (seed << 20) + int(k)
+            gs = self.scenes[si]
+            T.render_ex(gs, self.W, self.H, spp_h, self.depth, 2 * fseed, hr_rgb[b], hr_aux[b],
+                        window=(x0, y0, z, z))
+            T.render_ex(gs, self.W // s, self.H // s, spp_l, self.depth, 2 * fseed + 1, lr_rgb[b],
+                        None, window=(x0 // s, y0 // s, z // s, z // s))
+        i = torch.as_tensor(list(idx), device="cuda", dtype=torch.long)
+        return hr_rgb, hr_aux, lr_rgb, self.target.index_select(0, i).contiguous()
+
+    def close(self):
+        for gs in self.scenes:
+            gs.close()
+        self.scenes = []
+
+
+def train_random_spp(net: FusionNet, data: OnlinePairs, steps: int, batch=16, lr=1e-4,
+                     seed=0, loss="robust", optimizer="sgd", log_every=100, log=print):
+    """The paper's training loop: every iteration draws an spp pair
+    (sample_spp_pair) and a batch of windows, renders the inputs at that pair and
+    takes one optimiser step.  Returns [(step, spp_h, spp_l, loss or None)]."""
+    out = []
+    t0 = time.perf_counter()
+    for step in range(steps):
+        rng = np.random.default_rng([seed, step])
+        h, l = sample_spp_pair(rng)
+        idx = rng.choice(len(data), batch, replace=False)
+        want = (step + 1) % log_every == 0 or step == steps - 1
+        value = net.train_step(*data.batch(idx, h, l, seed * 1000003 + step), lr=lr,
+                               want_loss=want, loss=loss, optimizer=optimizer)
+        out.append((step + 1, h, l, value))
+        if want and log:
+            log(f"[train] step {step + 1} spp {h}/{l} loss {value:.5f} "
+                f"({time.perf_counter() - t0:.1f} s)")
+    return out
 
 
 # ---------------------------------------------------------------- equal PSNR

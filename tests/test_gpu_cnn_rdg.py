@@ -332,3 +332,34 @@ def test_checkpoint_resume_bitwise(torch_cuda, tmp_path):
     assert np.array_equal(pa, pc) and np.array_equal(ma, mc) and np.array_equal(va, vc)
     with pytest.raises(ValueError):
         mrs.FusionNet().load(str(tmp_path / "ck.bin"))  # another architecture's checkpoint
+
+
+@pytest.mark.parametrize("arch", ["rdg", "rdg_x8"])
+def test_training_with_random_spp_pairs(torch_cuda, arch):
+    """The paper's loop: every iteration draws an spp pair, re-renders the batch's
+    inputs at it and takes an SGD step on the robust loss.  The rendered inputs
+    are those of a direct window render at that pair."""
+    import paper_2106_12802_amd as mrs
+    from paper_2106_12802_amd import hybrid as HY
+    from paper_2106_12802_amd import tracer as T
+    torch = torch_cuda
+    _log(f"{arch} random spp pairs")
+    sr = SCALE[arch]
+    data = HY.OnlinePairs([(401, 12_000), (402, 20_000)], windows=4, size=64, scale=sr,
+                          target_spp=256, log=None)
+    net = mrs.FusionNet(seed=3, arch=arch)
+    hist = HY.train_random_spp(net, data, 6, batch=4, lr=1e-4, seed=5, log_every=1, log=None)
+    assert len({(h, l) for _, h, l, _ in hist}) > 1
+    assert all(h < l and 0.0 < v < 1.0 for _, h, l, v in hist)
+    hr, aux, lr, tgt = data.batch([2, 5], 3, 12, seed=9)
+    si, x0, y0, _ = data.wins[5]
+    ref = torch.empty(64, 64, 3, device="cuda")
+    T.render_ex(data.scenes[si], 1280, 720, 3, HY.DEPTH, 2 * ((9 << 20) + 5), ref, None,
+                window=(x0, y0, 64, 64))
+    ref_l = torch.empty(64 // sr, 64 // sr, 3, device="cuda")
+    T.render_ex(data.scenes[si], 1280 // sr, 720 // sr, 12, HY.DEPTH, 2 * ((9 << 20) + 5) + 1,
+                ref_l, None, window=(x0 // sr, y0 // sr, 64 // sr, 64 // sr))
+    torch.cuda.synchronize()
+    assert torch.equal(hr[1], ref) and torch.equal(lr[1], ref_l)
+    assert torch.equal(tgt[1], data.target[5])
+    data.close()

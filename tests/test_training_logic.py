@@ -1,0 +1,25 @@
+"""Host logic of the paper's training loop: the per-iteration spp pair sampler."""
+import collections
+
+import numpy as np
+
+
+def test_spp_pairs_follow_the_paper_sets():
+    from paper_2106_12802_amd import hybrid as HY
+    # the sets of Sec. 4 (implementation details)
+    assert HY.SPP_HRLS == (1, 2, 3, 4, 5, 6, 7, 8, 12, 16, 32)
+    assert HY.SPP_LRHS == (2, 3, 4, 5, 6, 7, 8, 12, 16, 32, 64, 128, 250, 1000, 4000)
+    rng = np.random.default_rng(0)
+    pairs = [HY.sample_spp_pair(rng) for _ in range(20000)]
+    assert all(h < l for h, l in pairs)
+    hs = collections.Counter(h for h, _ in pairs)
+    ls = collections.Counter(l for _, l in pairs)
+    assert set(hs) == set(HY.SPP_HRLS) and set(ls) == set(HY.SPP_LRHS)
+    # HRLS uniform over its set (11 values): each ~1/11 of the draws
+    assert max(abs(c / 20000 - 1 / 11) for c in hs.values()) < 0.01
+    # given HRLS = 32 the LRHS is uniform over the five larger values
+    big = collections.Counter(l for h, l in pairs if h == 32)
+    assert set(big) == {64, 128, 250, 1000, 4000}
+    # a pure function of the generator state
+    assert HY.sample_spp_pair(np.random.default_rng([3, 7])) == \
+        HY.sample_spp_pair(np.random.default_rng([3, 7]))
