@@ -41,16 +41,19 @@ TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "extend_procedural101k_720p_tra
 WEIGHTS = os.path.join(ROOT, "paper_2106_12802_amd", "weights", "fusion_l1_textured.bin")
 PEAK_BF16_TFLOPS = 2500.0  # MI355X dense BF16 MFMA
 CNN_FLOP_720P = 175.7e9    # 87.85 GMAC per 720p frame
-PAPER_TABLE5_X4_S = 0.118  # the paper's network, x4 on a 1024x1024 image (its Table 5; Titan Xp)
+# the paper's network on a 1024x1024 image, seconds (its runtime table; Titan Xp)
+PAPER_TABLE5_S = {2: 0.362, 4: 0.118, 8: 0.052}
 
 
-def rdg_flop(H, W):
-    """Forward FLOP of the paper's network (residual dense groups) on one H x W
-    frame: 2 x sum over convs of pixels x C_out x C_in x k^2."""
-    p = H * W // 16  # LR pixels
-    mac = (16 * p * 64 * 10 * 9 + p * 64 * 3 * 9 + p * 64 * 1088      # encoders, fuse
+def rdg_flop(H, W, scale=4):
+    """Forward FLOP of the paper's network (residual dense groups) at x`scale` on
+    one H x W frame: 2 x sum over convs of pixels x C_out x C_in x k^2."""
+    D = {2: 1, 4: 2, 8: 3}[scale]
+    p = H * W // scale ** 2  # LR pixels
+    mac = (scale ** 2 * p * 64 * 10 * 9 + p * 64 * 3 * 9 + p * 64 * (64 + 64 * 4 ** D)
            + 15 * p * 64 * 9 * (64 + 128 + 192 + 256)                  # 15 dense blocks
-           + p * 256 * 64 * 9 + 4 * p * 256 * 64 * 9 + 16 * p * 3 * 64 * 9)  # up0, up1, rec
+           + sum(4 ** k * p * 256 * 64 * 9 for k in range(D))          # upscaling steps
+           + scale ** 2 * p * 3 * 64 * 9)                              # reconstruction
     return 2 * mac
 
 
@@ -382,6 +385,17 @@ def mis_block(gs, log, reps=5):
     (Wh, Hh, sh), (Wl, Hl, sl) = HRLS, LRHS
     ref, _ = R.render(gs, Wh, Hh, 1024, MAX_DEPTH, 1 << 41, want_aux=False, mis=True)
     res = {"reference": "1280x720 at 1024 spp with mis, FP64 pixel sums, seed 2^41"}
+    # a glossy floor mirroring three quad lights: where the two strategies differ most
+    from mrs_inputs import scenes as S
+    glossy = R.GpuScene(S.glossy_lights(0.05))
+    gref, _ = R.render(glossy, 512, 288, 4096, MAX_DEPTH, 1 << 41, want_aux=False, mis=True)
+    for mis in (False, True):
+        p = [M.image_metrics(R.render(glossy, 512, 288, 4, MAX_DEPTH, 200 + k, want_aux=False,
+                                      mis=mis)[0], gref)["psnr"] for k in range(4)]
+        res[f"glossy_psnr_4spp_{'mis' if mis else 'nee'}"] = round(sum(p) / len(p), 3)
+    glossy.close()
+    log(f"[bench] glossy floor 512x288 at 4 spp: NEE {res['glossy_psnr_4spp_nee']} dB, "
+        f"MIS {res['glossy_psnr_4spp_mis']} dB")
     for mis in (False, True):
         hr = torch.empty(Hh, Wh, 3, device="cuda")
         lr = torch.empty(Hl, Wl, 3, device="cuda")
@@ -412,28 +426,37 @@ def paper_net_block(log, reps=10, train_steps=10):
     crops, robust loss, SGD) -- random weights and inputs of those shapes."""
     import torch
     import paper_2106_12802_amd as mrs
-    net = mrs.FusionNet(seed=1, arch="rdg")
     g = torch.Generator(device="cuda").manual_seed(5)
-    res = {"params": net.num_params}
-    for tag, (H, W) in (("720p", (720, 1280)), ("1024x1024", (1024, 1024))):
-        hr = torch.rand(H, W, 3, device="cuda", generator=g)
-        aux = torch.rand(H, W, 7, device="cuda", generator=g)
-        lr = torch.rand(H // 4, W // 4, 3, device="cuda", generator=g)
-        out = torch.empty_like(hr)
-        net.fuse(hr, aux, lr, out=out)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(reps):
+    res = {}
+    for arch, sc in (("rdg", 4), ("rdg_x2", 2), ("rdg_x8", 8)):
+        net = mrs.FusionNet(seed=1, arch=arch)
+        sizes = (("720p", (720, 1280)), ("1024x1024", (1024, 1024)))
+        for tag, (H, W) in sizes if sc == 4 else sizes[1:]:
+            hr = torch.rand(H, W, 3, device="cuda", generator=g)
+            aux = torch.rand(H, W, 7, device="cuda", generator=g)
+            lr = torch.rand(H // sc, W // sc, 3, device="cuda", generator=g)
+            out = torch.empty_like(hr)
             net.fuse(hr, aux, lr, out=out)
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1e3 / reps
-        flop = rdg_flop(H, W)
-        res[f"fuse_ms_{tag}"] = round(ms, 4)
-        res[f"tflops_{tag}"] = round(flop / (ms / 1e3) / 1e12, 2)
-        log(f"[bench] paper network {tag}: {ms:.3f} ms ({flop / 1e9:.1f} GFLOP)")
-    res["gflop_720p"] = round(rdg_flop(720, 1280) / 1e9, 2)
-    res["frac_720p"] = round(res["tflops_720p"] / PEAK_BF16_TFLOPS, 5)
-    res["paper_table5_x4_1024sq_ms"] = PAPER_TABLE5_X4_S * 1e3
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                net.fuse(hr, aux, lr, out=out)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / reps
+            flop = rdg_flop(H, W, sc)
+            key = f"x{sc}_{tag}"
+            res[f"fuse_ms_{key}"] = round(ms, 4)
+            res[f"tflops_{key}"] = round(flop / (ms / 1e3) / 1e12, 2)
+            log(f"[bench] paper network x{sc} {tag}: {ms:.3f} ms ({flop / 1e9:.1f} GFLOP)")
+        res[f"params_x{sc}"] = net.num_params
+        res[f"paper_table5_x{sc}_1024sq_ms"] = PAPER_TABLE5_S[sc] * 1e3
+        if sc != 4:
+            net.close()
+        else:
+            keep = net
+    net = keep
+    res["gflop_x4_720p"] = round(rdg_flop(720, 1280) / 1e9, 2)
+    res["frac_x4_720p"] = round(res["tflops_x4_720p"] / PEAK_BF16_TFLOPS, 5)
     B, H, W = 16, 128, 128
     t = [torch.rand(B, H, W, c, device="cuda", generator=g) for c in (3, 7)]
     t.insert(2, torch.rand(B, H // 4, W // 4, 3, device="cuda", generator=g))

@@ -457,6 +457,20 @@ def nee_config(rho=0.5, le=10.0, a=1.0, bb=2.0, c=1.5) -> Scene:
                    {"rho": rho, "le": le, "a": a, "b": bb, "c": c})
 
 
+def glossy_lights(alpha: float = 0.05) -> Scene:
+    """A glossy GGX floor (roughness alpha) under three quad lights of different
+    sizes, seen at a grazing angle: the floor mirrors the lights, the case where
+    light sampling alone is noisy (the MIS comparison scene)."""
+    b = _Builder()
+    b.add_quad((-20.0, 0.0, -20.0), (0.0, 0.0, 40.0), (40.0, 0.0, 0.0),
+               b.material(GGX, color=(0.9, 0.85, 0.8), alpha=alpha))
+    for x, size, le in ((-2.0, 0.4, 40.0), (0.0, 1.0, 8.0), (2.5, 2.0, 2.0)):
+        b.add_light((x - size / 2, 2.0, 4.0 - size / 2), (size, 0.0, 0.0), (0.0, 0.0, size),
+                    (le, le, le))
+    cam = Camera((0.0, 1.0, -4.0), (0.0, 0.3, 2.0), (0.0, 1.0, 0.0), 50.0)
+    return b.build((0.05, 0.05, 0.05), cam, f"glossy_lights_{alpha}")
+
+
 def random_soup(seed: int, n: int, spread: float = 1.0) -> Scene:
     """Random triangles in a cube (intersection / BVH tests)."""
     rng = np.random.default_rng(seed)
