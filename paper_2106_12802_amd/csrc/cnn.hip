@@ -268,26 +268,29 @@ __device__ __forceinline__ void conv_epilogue(const ConvArgs& p, const f32x4 (&a
 // LDS layouts are chosen for conflict-free 16-byte accesses: tile pixels
 // padded by 8 channels, weights chunk-major [k / 8][n][8] with one pad chunk
 // per k row.
-constexpr int C3_T = 16, C3_THREADS = 512;
-constexpr int C3_TILE = (C3_T + 2) * (C3_T + 2);
+constexpr int C3_W = 16;  // tile width: one 16-pixel MFMA row tile
 
-template <int CINP, int NT>
-__global__ __launch_bounds__(C3_THREADS) void k_conv3_lds(ConvArgs p, int cout_p) {
+template <int CINP, int NT, int TH>
+__global__ __launch_bounds__(32 * TH) void k_conv3_lds(ConvArgs p, int cout_p, int nsplit) {
+  constexpr int THREADS = 32 * TH;  // TH / 2 waves, two tile rows each
+  constexpr int TILE = (TH + 2) * (C3_W + 2);
   constexpr int PITCH = CINP + 8;
   constexpr int KP = (9 * CINP + 31) / 32 * 32;
   constexpr int NG = 16 * NT;
   constexpr int WPITCH = NG + 1;  // 16-byte chunks per weight row (pad: conflict-free stores)
-  __shared__ __attribute__((aligned(16))) uint16_t tile[C3_TILE * PITCH];
+  __shared__ __attribute__((aligned(16))) uint16_t tile[TILE * PITCH];
   __shared__ __attribute__((aligned(16))) uint16_t wts[(KP / 8) * WPITCH * 8];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int kq = lane >> 4, li = lane & 15;
-  const int x0 = blockIdx.x * C3_T, y0 = blockIdx.y * C3_T, b = blockIdx.z;
+  const int x0 = blockIdx.x * C3_W, y0 = blockIdx.y * TH;
+  const int b = blockIdx.z / nsplit, part = blockIdx.z - b * nsplit;
+  const int nper = cout_p / nsplit;  // output channels of this block (a multiple of NG)
   const int nchunk = p.cin_p / CINP;
   // Loads are issued three at a time before their LDS stores, so that their
   // latencies overlap instead of adding up.
-  constexpr int TCH = C3_TILE * (CINP / 8), WCH = NG * (KP / 8);
-  for (int n0 = 0; n0 < cout_p; n0 += NG) {
+  constexpr int TCH = TILE * (CINP / 8), WCH = NG * (KP / 8);
+  for (int n0 = part * nper; n0 < (part + 1) * nper; n0 += NG) {
     f32x4 acc[2][NT];
 #pragma unroll
     for (int r = 0; r < 2; ++r)
@@ -295,23 +298,24 @@ __global__ __launch_bounds__(C3_THREADS) void k_conv3_lds(ConvArgs p, int cout_p
       for (int j = 0; j < NT; ++j) acc[r][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     for (int ch = 0; ch < nchunk; ++ch) {
       const int cbase = ch * CINP;
-      if (n0 > 0 || ch > 0) __syncthreads();  // the LDS operands are no longer read
-      if (nchunk > 1 || n0 == 0) {
+      const bool first = n0 == part * nper && ch == 0;
+      if (!first) __syncthreads();  // the LDS operands are no longer read
+      if (nchunk > 1 || first) {
         auto tile_load = [&](int i) -> bf16x8 {
           const int px = i / (CINP / 8), c = (i - px * (CINP / 8)) * 8;
-          const int ty = px / (C3_T + 2), tx = px - ty * (C3_T + 2);
+          const int ty = px / (C3_W + 2), tx = px - ty * (C3_W + 2);
           return i < TCH ? view_chunk(p, b, y0 - 1 + ty, x0 - 1 + tx, cbase + c) : zero8();
         };
         auto tile_store = [&](int i, bf16x8 v) {
           const int px = i / (CINP / 8), c = (i - px * (CINP / 8)) * 8;
           if (i < TCH) *reinterpret_cast<bf16x8*>(tile + px * PITCH + c) = v;
         };
-        for (int i = tid; i < TCH; i += 3 * C3_THREADS) {
-          const bf16x8 v0 = tile_load(i), v1 = tile_load(i + C3_THREADS),
-                       v2 = tile_load(i + 2 * C3_THREADS);
+        for (int i = tid; i < TCH; i += 3 * THREADS) {
+          const bf16x8 v0 = tile_load(i), v1 = tile_load(i + THREADS),
+                       v2 = tile_load(i + 2 * THREADS);
           tile_store(i, v0);
-          tile_store(i + C3_THREADS, v1);
-          tile_store(i + 2 * C3_THREADS, v2);
+          tile_store(i + THREADS, v1);
+          tile_store(i + 2 * THREADS, v2);
         }
       }
       // local k = tap CINP + c holds packed column tap cin_p + cbase + c
@@ -326,11 +330,11 @@ __global__ __launch_bounds__(C3_THREADS) void k_conv3_lds(ConvArgs p, int cout_p
         const int n = i / (KP / 8), kc = i - n * (KP / 8);
         if (i < WCH) *reinterpret_cast<uint4*>(wts + (kc * WPITCH + n) * 8) = v;
       };
-      for (int i = tid; i < WCH; i += 3 * C3_THREADS) {
-        const uint4 v0 = w_load(i), v1 = w_load(i + C3_THREADS), v2 = w_load(i + 2 * C3_THREADS);
+      for (int i = tid; i < WCH; i += 3 * THREADS) {
+        const uint4 v0 = w_load(i), v1 = w_load(i + THREADS), v2 = w_load(i + 2 * THREADS);
         w_store(i, v0);
-        w_store(i + C3_THREADS, v1);
-        w_store(i + 2 * C3_THREADS, v2);
+        w_store(i + THREADS, v1);
+        w_store(i + 2 * THREADS, v2);
       }
       __syncthreads();
       for (int ks = 0; ks < KP; ks += 32) {
@@ -340,7 +344,7 @@ __global__ __launch_bounds__(C3_THREADS) void k_conv3_lds(ConvArgs p, int cout_p
         bf16x8 A[2], Bv[NT];
 #pragma unroll
         for (int r = 0; r < 2; ++r)
-          A[r] = tap < 9 ? ld8(tile + ((2 * wave + r + dy) * (C3_T + 2) + li + dx) * PITCH + c)
+          A[r] = tap < 9 ? ld8(tile + ((2 * wave + r + dy) * (C3_W + 2) + li + dx) * PITCH + c)
                          : zero8();
 #pragma unroll
         for (int j = 0; j < NT; ++j)
@@ -364,17 +368,18 @@ __global__ __launch_bounds__(C3_THREADS) void k_conv3_lds(ConvArgs p, int cout_p
   }
 }
 
-// Runs the conv on k_conv3_lds<CINP, NT> if its shape fits: cin_p == CINP, or
-// (CINP = 64) a multiple of it taken in chunks; packed K = 9 cin_p rounded up
-// to 32; cout_p a multiple of the channel group.
-template <int CINP, int NT>
-bool try_conv3_lds(const ConvArgs& a, int cout_p, hipStream_t st) {
+// Runs the conv on k_conv3_lds<CINP, NT, TH> if its shape fits: cin_p == CINP,
+// or (CINP = 64) a multiple of it taken in chunks; packed K = 9 cin_p rounded up
+// to 32; cout_p a multiple of nsplit channel groups of 16 NT.  The output
+// channels are split over nsplit blocks per tile.
+template <int CINP, int NT, int TH>
+bool try_conv3_lds(const ConvArgs& a, int cout_p, int nsplit, hipStream_t st) {
   const bool chunked = CINP == 64 && a.cin_p > CINP && a.cin_p % CINP == 0;
   if ((a.cin_p != CINP && !chunked) || a.kp != (9 * a.cin_p + 31) / 32 * 32 ||
-      cout_p % (16 * NT))
+      cout_p % (16 * NT * nsplit))
     return false;
-  k_conv3_lds<CINP, NT><<<dim3((a.W + C3_T - 1) / C3_T, (a.H + C3_T - 1) / C3_T, a.B),
-                          C3_THREADS, 0, st>>>(a, cout_p);
+  k_conv3_lds<CINP, NT, TH><<<dim3((a.W + C3_W - 1) / C3_W, (a.H + TH - 1) / TH, a.B * nsplit),
+                              32 * TH, 0, st>>>(a, cout_p, nsplit);
   return true;
 }
 
@@ -825,12 +830,27 @@ void launch_adam(float* w, const float* g, float* m, float* v, int64_t n, float 
   k_adam<<<cdiv64(n, 256), 256, 0, st>>>(w, g, m, v, n, lr, b1, b2, eps, c1, c2);
 }
 
+// Tile plan of a 3x3 conv on k_conv3_lds: 16 x 16 tiles of 8 waves with all
+// output channels per block; when such tiles would occupy fewer than half of
+// the 256 CUs, 16 x 8 tiles of 4 waves with the output channels split over
+// blocks of 32 (two fit a CU at once).  Measured: the 720p LR trunk (240
+// tiles) is 18% faster on the large tiles, the x8 network on a 1024 x 1024
+// image (64 tiles) 19% faster on the small ones.
+#ifndef MRS_CONV_SMALL_BLOCKS
+#define MRS_CONV_SMALL_BLOCKS 128
+#endif
 void launch_conv(const ConvArgs& a, int cout_p, hipStream_t st) {
   if (a.taps == 9 && a.mode != VIEW_CONCAT_UNSHUFFLE &&
       (a.mode != VIEW_PLAIN || a.ca >= a.cin_p)) {
-    if (cout_p >= 64 ? (try_conv3_lds<64, 4>(a, cout_p, st) || try_conv3_lds<16, 4>(a, cout_p, st) ||
-                        try_conv3_lds<8, 4>(a, cout_p, st))
-                     : (try_conv3_lds<80, 1>(a, cout_p, st) || try_conv3_lds<64, 1>(a, cout_p, st)))
+    const int64_t tiles = (int64_t)((a.W + 15) / 16) * ((a.H + 15) / 16) * a.B;
+    if (cout_p >= 64 && a.cin_p % 64 == 0 && tiles < MRS_CONV_SMALL_BLOCKS &&
+        try_conv3_lds<64, 2, 8>(a, cout_p, cout_p / 32, st))
+      return;
+    if (cout_p >= 64 ? (try_conv3_lds<64, 4, 16>(a, cout_p, 1, st) ||
+                        try_conv3_lds<16, 4, 16>(a, cout_p, 1, st) ||
+                        try_conv3_lds<8, 4, 16>(a, cout_p, 1, st))
+                     : (try_conv3_lds<80, 1, 16>(a, cout_p, 1, st) ||
+                        try_conv3_lds<64, 1, 16>(a, cout_p, 1, st)))
       return;
   }
   const int64_t M = (int64_t)a.B * a.H * a.W;

@@ -94,7 +94,7 @@ def test_fuse_not_ready_and_validation(torch_cuda):
     # the C ABI itself rejects sizes that are not multiples of 4, before any launch
     rc = _lib.lib().mrs_fuse_batch(n.handle, 1, hr.data_ptr(), aux.data_ptr(), lr.data_ptr(),
                                    8, 6, out.data_ptr())
-    assert rc == 1 and b"multiples of 4" in _lib.lib().mrs_last_error()
+    assert rc == 1 and b"multiples of the net" in _lib.lib().mrs_last_error()
     with pytest.raises(TypeError, match="float32"):
         n.fuse(hr.double(), aux, lr)
 
