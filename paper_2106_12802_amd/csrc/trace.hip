@@ -391,14 +391,43 @@ __device__ __forceinline__ uint32_t find_job_pix(const DevJob* __restrict__ jobs
   return (uint32_t)lo;
 }
 
+// Within one sample, paths follow the window's pixels in 8 x 8 tiles (tile
+// rows top to bottom, tiles left to right, pixels row-major inside a tile;
+// edge tiles are cut to the window), so that the 64 paths of a wave start in
+// one tile: their camera rays, first hits and shadow rays are coherent.
+constexpr uint32_t PT = 8;
+
+// Window pixel (wx, wy) of path-order index q of a ww x wh window.
+__device__ __forceinline__ void tile_pixel(uint32_t q, uint32_t ww, uint32_t wh, uint32_t& wx,
+                                           uint32_t& wy) {
+  const uint32_t tr = q / (PT * ww);
+  const uint32_t q0 = q - tr * PT * ww;
+  const uint32_t hh = min(PT, wh - PT * tr);
+  const uint32_t tc = q0 / (hh * PT);
+  const uint32_t q1 = q0 - tc * hh * PT;
+  const uint32_t cw = min(PT, ww - PT * tc);
+  const uint32_t dy = q1 / cw;
+  wy = PT * tr + dy;
+  wx = PT * tc + (q1 - dy * cw);
+}
+
+// Its inverse: the path-order index of window pixel (wx, wy).
+__device__ __forceinline__ uint32_t tile_index(uint32_t wx, uint32_t wy, uint32_t ww,
+                                               uint32_t wh) {
+  const uint32_t tr = wy / PT, tc = wx / PT;
+  const uint32_t hh = min(PT, wh - PT * tr), cw = min(PT, ww - PT * tc);
+  return tr * PT * ww + tc * hh * PT + (wy - PT * tr) * cw + (wx - PT * tc);
+}
+
 // full-image pixel index P and sample s of the path at global index g of job J
 __device__ __forceinline__ void path_pixel_sample(const DevJob& J, int64_t g, uint32_t& P,
                                                   uint32_t& s) {
   const int64_t l = g - J.first;
   const int64_t npix = (int64_t)J.ww * J.wh;
   s = (uint32_t)(l / npix);
-  const uint32_t pl = (uint32_t)(l - (int64_t)s * npix);
-  const uint32_t wy = pl / (uint32_t)J.ww, wx = pl - wy * (uint32_t)J.ww;
+  const uint32_t q = (uint32_t)(l - (int64_t)s * npix);
+  uint32_t wx, wy;
+  tile_pixel(q, (uint32_t)J.ww, (uint32_t)J.wh, wx, wy);
   P = ((uint32_t)J.y0 + wy) * (uint32_t)J.W + ((uint32_t)J.x0 + wx);
 }
 
@@ -1043,15 +1072,17 @@ __global__ __launch_bounds__(256) void k_accumulate(const DevJob* __restrict__ j
   const uint32_t j = find_job_pix(jobs, njobs, i);
   const DevJob& J = jobs[j];
   const int64_t npix = (int64_t)J.ww * J.wh;
-  const uint32_t pl = (uint32_t)(i - J.pix_first);
-  // samples s with g = first + s npix + pl in [g0, g0 + n)
-  const int64_t lo = g0 - J.first - pl, hi = g0 + n - 1 - J.first - pl;
+  const uint32_t pl = (uint32_t)(i - J.pix_first);  // row-major window pixel (outputs)
+  const uint32_t wy = pl / (uint32_t)J.ww, wx = pl - wy * (uint32_t)J.ww;
+  const uint32_t q = tile_index(wx, wy, (uint32_t)J.ww, (uint32_t)J.wh);  // its path order
+  // samples s with g = first + s npix + q in [g0, g0 + n)
+  const int64_t lo = g0 - J.first - q, hi = g0 + n - 1 - J.first - q;
   if (hi < 0) return;
   const int64_t s_lo = lo <= 0 ? 0 : (lo + npix - 1) / npix;
   int64_t s_hi = hi / npix;
   if (s_hi > J.spp - 1) s_hi = J.spp - 1;
   if (s_lo > s_hi) return;
-  const int64_t slot0 = J.first + pl - g0;
+  const int64_t slot0 = J.first + q - g0;
   uint32_t bad = 0;
   if (J.fp64)
     accumulate_pixel<double>(J, acc_base, pl, s_lo, s_hi, slot0, npix, L_buf, aux_buf, bad);
