@@ -78,7 +78,7 @@ struct SceneView {  // passed by value to kernels
 
 // One render of a batch: its scene, image, window, sampling and outputs.
 // Paths of all jobs form one index space: job j owns [first, first + spp * npix)
-// in sample-major order; pix_first indexes its pixels in the concatenated
+// pixel-major (each pixel's samples consecutive); pix_first indexes its pixels in the concatenated
 // pixel space; acc_off locates its accumulators (bytes).
 struct DevJob {
   SceneView sv;

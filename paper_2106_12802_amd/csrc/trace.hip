@@ -367,8 +367,9 @@ __device__ void trace_stream(IO& io, uint32_t first, uint32_t stride, uint32_t n
 
 // ------------------------------------------------------------------ jobs
 
-// Global path index g of a batch: jobs are concatenated, each in sample-major
-// order (g = first + s * npix + pl, pl the row-major pixel of its window).
+// Global path index g of a batch: jobs are concatenated, each pixel-major
+// (g = first + q * spp + s, q the pixel's place in the tile order below, s
+// its sample).
 __device__ __forceinline__ uint32_t find_job(const DevJob* __restrict__ jobs, int njobs,
                                              int64_t g) {
   int lo = 0, hi = njobs - 1;
@@ -391,10 +392,11 @@ __device__ __forceinline__ uint32_t find_job_pix(const DevJob* __restrict__ jobs
   return (uint32_t)lo;
 }
 
-// Within one sample, paths follow the window's pixels in 8 x 8 tiles (tile
-// rows top to bottom, tiles left to right, pixels row-major inside a tile;
-// edge tiles are cut to the window), so that the 64 paths of a wave start in
-// one tile: their camera rays, first hits and shadow rays are coherent.
+// Pixels are ordered in 8 x 8 tiles (tile rows top to bottom, tiles left to
+// right, pixels row-major inside a tile; edge tiles are cut to the window) and
+// each pixel's samples are consecutive, so that the 64 paths of a wave start
+// in a few neighbouring pixels (one pixel at 64 spp and more, 16 at 4 spp):
+// their camera rays, first hits and shadow rays are coherent.
 constexpr uint32_t PT = 8;
 
 // Window pixel (wx, wy) of path-order index q of a ww x wh window.
@@ -423,9 +425,8 @@ __device__ __forceinline__ uint32_t tile_index(uint32_t wx, uint32_t wy, uint32_
 __device__ __forceinline__ void path_pixel_sample(const DevJob& J, int64_t g, uint32_t& P,
                                                   uint32_t& s) {
   const int64_t l = g - J.first;
-  const int64_t npix = (int64_t)J.ww * J.wh;
-  s = (uint32_t)(l / npix);
-  const uint32_t q = (uint32_t)(l - (int64_t)s * npix);
+  const uint32_t q = (uint32_t)(l / J.spp);
+  s = (uint32_t)(l - (int64_t)q * J.spp);
   uint32_t wx, wy;
   tile_pixel(q, (uint32_t)J.ww, (uint32_t)J.wh, wx, wy);
   P = ((uint32_t)J.y0 + wy) * (uint32_t)J.W + ((uint32_t)J.x0 + wx);
@@ -1023,7 +1024,8 @@ __global__ __launch_bounds__(TB) void k_tail(const DevJob* __restrict__ jobs, in
 }
 
 // Per pixel of every job overlapping the chunk [g0, g0 + n): add its samples of
-// the chunk, in sample order, to the pixel's sums (FP32 or FP64 per job).
+// the chunk (consecutive slots from slot0 + s_lo), in sample order, to the
+// pixel's sums (FP32 or FP64 per job).
 template <typename T>
 __device__ __forceinline__ void accumulate_pixel(const DevJob& J, char* acc_base, uint32_t pl,
                                                  int64_t s_lo, int64_t s_hi, int64_t slot0,
@@ -1039,7 +1041,7 @@ __device__ __forceinline__ void accumulate_pixel(const DevJob& J, char* acc_base
   T a[7];
   for (int c = 0; c < 7; ++c) a[c] = a_aux[c];
   for (int64_t s = s_lo; s <= s_hi; ++s) {
-    const int64_t slot = slot0 + s * npix;
+    const int64_t slot = slot0 + s;
     float4 Lv = L_buf[slot];
     if (!(isfinite(Lv.x) && isfinite(Lv.y) && isfinite(Lv.z))) {
       Lv = make_float4(0, 0, 0, 0);
@@ -1075,14 +1077,12 @@ __global__ __launch_bounds__(256) void k_accumulate(const DevJob* __restrict__ j
   const uint32_t pl = (uint32_t)(i - J.pix_first);  // row-major window pixel (outputs)
   const uint32_t wy = pl / (uint32_t)J.ww, wx = pl - wy * (uint32_t)J.ww;
   const uint32_t q = tile_index(wx, wy, (uint32_t)J.ww, (uint32_t)J.wh);  // its path order
-  // samples s with g = first + s npix + q in [g0, g0 + n)
-  const int64_t lo = g0 - J.first - q, hi = g0 + n - 1 - J.first - q;
-  if (hi < 0) return;
-  const int64_t s_lo = lo <= 0 ? 0 : (lo + npix - 1) / npix;
-  int64_t s_hi = hi / npix;
-  if (s_hi > J.spp - 1) s_hi = J.spp - 1;
+  // samples s with g = first + q spp + s in [g0, g0 + n)
+  const int64_t base = J.first + (int64_t)q * J.spp;
+  const int64_t s_lo = g0 > base ? g0 - base : 0;
+  const int64_t s_hi = std::min<int64_t>(J.spp - 1, g0 + n - 1 - base);
   if (s_lo > s_hi) return;
-  const int64_t slot0 = J.first + q - g0;
+  const int64_t slot0 = base - g0;
   uint32_t bad = 0;
   if (J.fp64)
     accumulate_pixel<double>(J, acc_base, pl, s_lo, s_hi, slot0, npix, L_buf, aux_buf, bad);
