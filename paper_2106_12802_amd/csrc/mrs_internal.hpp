@@ -86,6 +86,9 @@ struct DevJob {
   int32_t spp, max_depth, rr_start, fp64;
   int32_t mis, moving;
   float lens_r, focus, motion_x, motion_y, motion_z, pad0;
+  // path order of the full 8-pixel tile rows: row position p holds tile row
+  // (p * row_mul) mod rows_full (row_inv is row_mul's inverse mod rows_full)
+  uint32_t rows_full, row_mul, row_inv, pad1;
   uint32_t seed_lo, seed_hi;
   int64_t first, pix_first, acc_off;
   float* out_rgb;

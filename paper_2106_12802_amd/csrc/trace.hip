@@ -392,18 +392,26 @@ __device__ __forceinline__ uint32_t find_job_pix(const DevJob* __restrict__ jobs
   return (uint32_t)lo;
 }
 
-// Pixels are ordered in 8 x 8 tiles (tile rows top to bottom, tiles left to
-// right, pixels row-major inside a tile; edge tiles are cut to the window) and
-// each pixel's samples are consecutive, so that the 64 paths of a wave start
-// in a few neighbouring pixels (one pixel at 64 spp and more, 16 at 4 spp):
-// their camera rays, first hits and shadow rays are coherent.
+// Pixels are ordered in 8 x 8 tiles (tiles left to right within a tile row,
+// pixels row-major inside a tile; edge tiles are cut to the window) and each
+// pixel's samples are consecutive, so that the 64 paths of a wave start in a
+// few neighbouring pixels (one pixel at 64 spp and more, 16 at 4 spp): their
+// camera rays, first hits and shadow rays are coherent.  The full tile rows
+// follow a stride permutation (row position p holds tile row p * row_mul mod
+// rows_full, row_mul coprime with rows_full and near 0.38 rows_full; a cut
+// last row stays last), so that any contiguous range of paths -- a sub-chunk
+// traced on its own stream -- samples the whole image and costs about the
+// same as any other (the sky at the top of an image is cheap, the ground is
+// not).
 constexpr uint32_t PT = 8;
 
-// Window pixel (wx, wy) of path-order index q of a ww x wh window.
-__device__ __forceinline__ void tile_pixel(uint32_t q, uint32_t ww, uint32_t wh, uint32_t& wx,
+// Window pixel (wx, wy) of path-order index q of job J's window.
+__device__ __forceinline__ void tile_pixel(const DevJob& J, uint32_t q, uint32_t& wx,
                                            uint32_t& wy) {
-  const uint32_t tr = q / (PT * ww);
-  const uint32_t q0 = q - tr * PT * ww;
+  const uint32_t ww = (uint32_t)J.ww, wh = (uint32_t)J.wh;
+  const uint32_t rp = q / (PT * ww);
+  const uint32_t q0 = q - rp * PT * ww;
+  const uint32_t tr = rp < J.rows_full ? rp * J.row_mul % J.rows_full : rp;
   const uint32_t hh = min(PT, wh - PT * tr);
   const uint32_t tc = q0 / (hh * PT);
   const uint32_t q1 = q0 - tc * hh * PT;
@@ -414,11 +422,12 @@ __device__ __forceinline__ void tile_pixel(uint32_t q, uint32_t ww, uint32_t wh,
 }
 
 // Its inverse: the path-order index of window pixel (wx, wy).
-__device__ __forceinline__ uint32_t tile_index(uint32_t wx, uint32_t wy, uint32_t ww,
-                                               uint32_t wh) {
+__device__ __forceinline__ uint32_t tile_index(const DevJob& J, uint32_t wx, uint32_t wy) {
+  const uint32_t ww = (uint32_t)J.ww, wh = (uint32_t)J.wh;
   const uint32_t tr = wy / PT, tc = wx / PT;
   const uint32_t hh = min(PT, wh - PT * tr), cw = min(PT, ww - PT * tc);
-  return tr * PT * ww + tc * hh * PT + (wy - PT * tr) * cw + (wx - PT * tc);
+  const uint32_t rp = tr < J.rows_full ? tr * J.row_inv % J.rows_full : tr;
+  return rp * PT * ww + tc * hh * PT + (wy - PT * tr) * cw + (wx - PT * tc);
 }
 
 // full-image pixel index P and sample s of the path at global index g of job J
@@ -428,7 +437,7 @@ __device__ __forceinline__ void path_pixel_sample(const DevJob& J, int64_t g, ui
   const uint32_t q = (uint32_t)(l / J.spp);
   s = (uint32_t)(l - (int64_t)q * J.spp);
   uint32_t wx, wy;
-  tile_pixel(q, (uint32_t)J.ww, (uint32_t)J.wh, wx, wy);
+  tile_pixel(J, q, wx, wy);
   P = ((uint32_t)J.y0 + wy) * (uint32_t)J.W + ((uint32_t)J.x0 + wx);
 }
 
@@ -1076,7 +1085,7 @@ __global__ __launch_bounds__(256) void k_accumulate(const DevJob* __restrict__ j
   const int64_t npix = (int64_t)J.ww * J.wh;
   const uint32_t pl = (uint32_t)(i - J.pix_first);  // row-major window pixel (outputs)
   const uint32_t wy = pl / (uint32_t)J.ww, wx = pl - wy * (uint32_t)J.ww;
-  const uint32_t q = tile_index(wx, wy, (uint32_t)J.ww, (uint32_t)J.wh);  // its path order
+  const uint32_t q = tile_index(J, wx, wy);  // its path order
   // samples s with g = first + q spp + s in [g0, g0 + n)
   const int64_t base = J.first + (int64_t)q * J.spp;
   const int64_t s_lo = g0 > base ? g0 - base : 0;
@@ -1511,9 +1520,41 @@ mrs_status launch_batch(Workspace& ws, const mrs_tuning& tu, const DevJob* d_job
 
 }  // namespace
 
+namespace {
+uint32_t gcd_u(uint32_t a, uint32_t b) {
+  while (b) {
+    const uint32_t t = a % b;
+    a = b;
+    b = t;
+  }
+  return a;
+}
+// x with (a x) mod m == 1 (a coprime with m > 1): extended Euclid.
+uint32_t inverse_mod(uint32_t a, uint32_t m) {
+  int64_t t = 0, nt = 1, r = m, nr = a % m;
+  while (nr) {
+    const int64_t q = r / nr;
+    t -= q * nt;
+    std::swap(t, nt);
+    r -= q * nr;
+    std::swap(r, nr);
+  }
+  return (uint32_t)(t < 0 ? t + m : t);
+}
+}  // namespace
+
 DevJob make_job(const mrs_scene* s, const RenderArgs& a) {
   DevJob J;
   std::memset(&J, 0, sizeof J);
+  // stride permutation of the full tile rows (see tile_pixel)
+  J.rows_full = (uint32_t)a.wh / PT;
+  J.row_mul = J.row_inv = 1;
+  if (J.rows_full > 2) {
+    uint32_t m = (uint32_t)(0.382 * J.rows_full + 0.5);
+    while (gcd_u(m, J.rows_full) != 1) ++m;
+    J.row_mul = m;
+    J.row_inv = inverse_mod(m, J.rows_full);
+  }
   J.sv = s->view;
   J.W = a.W;
   J.H = a.H;
