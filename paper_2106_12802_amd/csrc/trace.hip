@@ -421,15 +421,6 @@ __device__ __forceinline__ void tile_pixel(const DevJob& J, uint32_t q, uint32_t
   wx = PT * tc + (q1 - dy * cw);
 }
 
-// Its inverse: the path-order index of window pixel (wx, wy).
-__device__ __forceinline__ uint32_t tile_index(const DevJob& J, uint32_t wx, uint32_t wy) {
-  const uint32_t ww = (uint32_t)J.ww, wh = (uint32_t)J.wh;
-  const uint32_t tr = wy / PT, tc = wx / PT;
-  const uint32_t hh = min(PT, wh - PT * tr), cw = min(PT, ww - PT * tc);
-  const uint32_t rp = tr < J.rows_full ? tr * J.row_inv % J.rows_full : tr;
-  return rp * PT * ww + tc * hh * PT + (wy - PT * tr) * cw + (wx - PT * tc);
-}
-
 // full-image pixel index P and sample s of the path at global index g of job J
 __device__ __forceinline__ void path_pixel_sample(const DevJob& J, int64_t g, uint32_t& P,
                                                   uint32_t& s) {
@@ -830,8 +821,9 @@ __global__ __launch_bounds__(256) void k_shade(const DevJob* __restrict__ jobs, 
       // for it before its first vertex)
       const float4 Bt = b == 0 ? make_float4(1.0f, 1.0f, 1.0f, 0.0f) : beta_buf[slot];
       const f3 L = b == 0 ? F3(0.0f, 0.0f, 0.0f) : xyz(L_buf[slot]);
+      // first-hit features only for jobs that output them
       shade_vertex(jobs[j], g0 + slot, b, xyz(R0), xyz(R1), hits[qi], xyz(Bt), L, Bt.w,
-                   b == 0 ? aux_buf + 2 * slot : nullptr, v);
+                   (b == 0 && jobs[j].out_aux) ? aux_buf + 2 * slot : nullptr, v);
       if (v.cont) beta_buf[slot] = make_float4(v.beta.x, v.beta.y, v.beta.z, v.pdf);
       L_buf[slot] = make_float4(v.L.x, v.L.y, v.L.z, 0.0f);
     }
@@ -1045,10 +1037,11 @@ __device__ __forceinline__ void accumulate_pixel(const DevJob& J, char* acc_base
   T* a_rgb = acc + 3 * (int64_t)pl;
   T* a_aux = acc + 3 * npix + 7 * (int64_t)pl;
   T* a_sq = acc + 10 * npix + 3 * (int64_t)pl;
+  const bool feats = J.out_aux != nullptr;  // features are only traced for jobs that output them
   T r = a_rgb[0], gg = a_rgb[1], bb = a_rgb[2];
   T sr = a_sq[0], sg = a_sq[1], sb = a_sq[2];
   T a[7];
-  for (int c = 0; c < 7; ++c) a[c] = a_aux[c];
+  for (int c = 0; c < 7; ++c) a[c] = feats ? a_aux[c] : (T)0;
   for (int64_t s = s_lo; s <= s_hi; ++s) {
     const int64_t slot = slot0 + s;
     float4 Lv = L_buf[slot];
@@ -1062,13 +1055,16 @@ __device__ __forceinline__ void accumulate_pixel(const DevJob& J, char* acc_base
     sr += (T)Lv.x * (T)Lv.x;
     sg += (T)Lv.y * (T)Lv.y;
     sb += (T)Lv.z * (T)Lv.z;
-    const float4 A0 = aux_buf[2 * slot], A1 = aux_buf[2 * slot + 1];
-    a[0] += (T)A0.x; a[1] += (T)A0.y; a[2] += (T)A0.z; a[3] += (T)A0.w;
-    a[4] += (T)A1.x; a[5] += (T)A1.y; a[6] += (T)A1.z;
+    if (feats) {
+      const float4 A0 = aux_buf[2 * slot], A1 = aux_buf[2 * slot + 1];
+      a[0] += (T)A0.x; a[1] += (T)A0.y; a[2] += (T)A0.z; a[3] += (T)A0.w;
+      a[4] += (T)A1.x; a[5] += (T)A1.y; a[6] += (T)A1.z;
+    }
   }
   a_rgb[0] = r; a_rgb[1] = gg; a_rgb[2] = bb;
   a_sq[0] = sr; a_sq[1] = sg; a_sq[2] = sb;
-  for (int c = 0; c < 7; ++c) a_aux[c] = a[c];
+  if (feats)
+    for (int c = 0; c < 7; ++c) a_aux[c] = a[c];
 }
 
 __global__ __launch_bounds__(256) void k_accumulate(const DevJob* __restrict__ jobs, int njobs,
@@ -1078,14 +1074,16 @@ __global__ __launch_bounds__(256) void k_accumulate(const DevJob* __restrict__ j
                                                     const float4* __restrict__ aux_buf,
                                                     char* __restrict__ acc_base,
                                                     unsigned long long* __restrict__ stats) {
+  // i runs over pixels in path order (the chunk's pixels are one range of it)
   const int64_t i = pix_lo + (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= pix_hi) return;
   const uint32_t j = find_job_pix(jobs, njobs, i);
   const DevJob& J = jobs[j];
   const int64_t npix = (int64_t)J.ww * J.wh;
-  const uint32_t pl = (uint32_t)(i - J.pix_first);  // row-major window pixel (outputs)
-  const uint32_t wy = pl / (uint32_t)J.ww, wx = pl - wy * (uint32_t)J.ww;
-  const uint32_t q = tile_index(J, wx, wy);  // its path order
+  const uint32_t q = (uint32_t)(i - J.pix_first);  // path order of the pixel
+  uint32_t wx, wy;
+  tile_pixel(J, q, wx, wy);
+  const uint32_t pl = wy * (uint32_t)J.ww + wx;  // row-major window pixel (outputs)
   // samples s with g = first + q spp + s in [g0, g0 + n)
   const int64_t base = J.first + (int64_t)q * J.spp;
   const int64_t s_lo = g0 > base ? g0 - base : 0;
@@ -1497,11 +1495,14 @@ mrs_status launch_batch(Workspace& ws, const mrs_tuning& tu, const DevJob* d_job
         MRS_TRY_HIP(hipEventRecord(ws.ev_join[k], u.s));
         MRS_TRY_HIP(hipStreamWaitEvent(st, ws.ev_join[k], 0));
       }
+      // the chunk's pixels in path order: from the pixel of its first path to
+      // the pixel of its last
       int jlo = 0, jhi = nj - 1;
       while (jlo < nj - 1 && jobs[jlo + 1].first <= u.lo) ++jlo;
       while (jhi > 0 && jobs[jhi].first >= u.lo + (int64_t)u.n) --jhi;
-      const int64_t pix_lo = jobs[jlo].pix_first;
-      const int64_t pix_hi = jobs[jhi].pix_first + (int64_t)jobs[jhi].ww * jobs[jhi].wh;
+      const int64_t pix_lo = jobs[jlo].pix_first + (u.lo - jobs[jlo].first) / jobs[jlo].spp;
+      const int64_t pix_hi =
+          jobs[jhi].pix_first + (u.lo + (int64_t)u.n - 1 - jobs[jhi].first) / jobs[jhi].spp + 1;
       prof_begin(KID_ACCUMULATE, st);
       k_accumulate<<<cdiv((size_t)(pix_hi - pix_lo), 256), 256, 0, st>>>(
           d_jobs, nj, u.lo, u.n, pix_lo, pix_hi, u.L, u.aux, acc, stats);
