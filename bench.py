@@ -4,7 +4,10 @@ One step = one 720p hybrid frame of the textured procedural ~100k-triangle
 scene: HRLS 1280x720 at 4 spp with albedo/normal/depth, LRHS 320x180 at 64 spp
 (max depth 8, Russian roulette from vertex 3; 7,372,800 paths, spp_avg =
 64/16 + 4 = 8) and the BF16 fusion network on both.  Inputs (scene, LBVH,
-weights) are resident in HBM before timing starts.
+weights) are resident in HBM before timing starts.  The timed frames run as a
+stream of frames on one stream, each frame's fusion overlapping the next
+frame's render (every frame's whole work is inside the timed region); the
+same frames one at a time are reported beside it.
 
 Prints one JSON line: Mpaths/s of the frame, ms per frame, the roofline
 position of the dominant kernel (timed live with HIP events on its launch
@@ -142,10 +145,10 @@ def pmc_summary(fetch_path, write_path, out_path):
         "# (max depth 8) + fusion network.",
         "# Made by (each pass its own process, run from the repository root):",
         "#   rocprofv3 --pmc FETCH_SIZE -f csv -d gpurun_out/pmc_fetch -o pmc -- python bench.py "
-        "--steps 1 --warmup 0 --no-cpu-baseline --equal-psnr-scenes 0 --batch-scenes 0 --no-paper-net --no-mis --no-two-calls "
+        "--steps 1 --warmup 0 --no-cpu-baseline --equal-psnr-scenes 0 --batch-scenes 0 --no-paper-net --no-mis --no-camera --no-spp-pairs --no-two-calls "
         "--copy-calibration",
         "#   rocprofv3 --pmc WRITE_SIZE -f csv -d gpurun_out/pmc_write -o pmc -- python bench.py "
-        "--steps 1 --warmup 0 --no-cpu-baseline --equal-psnr-scenes 0 --batch-scenes 0 --no-paper-net --no-mis --no-two-calls "
+        "--steps 1 --warmup 0 --no-cpu-baseline --equal-psnr-scenes 0 --batch-scenes 0 --no-paper-net --no-mis --no-camera --no-spp-pairs --no-two-calls "
         "--copy-calibration",
         "#   python bench.py --pmc-summary gpurun_out/pmc_fetch gpurun_out/pmc_write",
         "# Counters are KiB per dispatch; each is scaled by COPY_BYTES over what the same counter",
@@ -168,7 +171,7 @@ def pmc_summary(fetch_path, write_path, out_path):
 
 STATS_SUMMARY = os.path.join(ROOT, "profiles", "hybrid_frame_procedural101k_720p_kernel_stats.txt")
 STATS_CMD = ("rocprofv3 --kernel-trace --stats -f csv -d gpurun_out/prof -o bench -- python -u "
-             "bench.py --steps 5 --warmup 1 --no-cpu-baseline --equal-psnr-scenes 0 --batch-scenes 0 --no-paper-net --no-mis --no-two-calls")
+             "bench.py --steps 5 --warmup 1 --no-cpu-baseline --equal-psnr-scenes 0 --batch-scenes 0 --no-paper-net --no-mis --no-camera --no-spp-pairs --no-two-calls")
 
 
 def stats_summary(prof_dir, out_path):
@@ -420,6 +423,70 @@ def mis_block(gs, log, reps=5):
     return res
 
 
+def camera_block(gs, log, reps=5):
+    """Depth of field (thin lens) and motion blur (camera translated over the
+    shutter) on the bench scene: time of the two renders of the hybrid frame
+    (HRLS 1280x720@4 + LRHS 320x180@64) with each effect, against the pinhole
+    camera.  Lens: radius 0.15, focus 8.0 along the view axis; motion: the camera
+    moves by (0.4, 0, 0) over the shutter."""
+    import torch
+    from paper_2106_12802_amd import tracer as R
+    (Wh, Hh, sh), (Wl, Hl, sl) = HRLS, LRHS
+    paths = Wh * Hh * sh + Wl * Hl * sl
+    lens = {"lens_radius": 0.15, "focus_dist": 8.0}
+    motion = {"cam_motion": (0.4, 0.0, 0.0)}
+    cases = (("pinhole", {}), ("lens", lens), ("motion", motion), ("lens_motion", {**lens, **motion}))
+    hr = torch.empty(Hh, Wh, 3, device="cuda")
+    lr = torch.empty(Hl, Wl, 3, device="cuda")
+    res = {"workload": "bench scene, HRLS 1280x720@4 + LRHS 320x180@64 as two render calls; "
+                       "lens radius 0.15 focused at 8.0, camera motion (0.4, 0, 0)"}
+    for name, kw in cases:
+        def frame(i):
+            R.render_ex(gs, Wh, Hh, sh, MAX_DEPTH, 2 * i, hr, None, **kw)
+            R.render_ex(gs, Wl, Hl, sl, MAX_DEPTH, 2 * i + 1, lr, None, **kw)
+        frame(0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(reps):
+            frame(i)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+        res[f"ms_two_renders_{name}"] = round(ms, 4)
+        res[f"mpaths_per_s_{name}"] = round(paths / ms / 1e3, 1)
+        log(f"[bench] camera {name}: two renders {ms:.3f} ms")
+    return res
+
+
+def spp_pairs_block(log, steps=8, batch=8):
+    """The paper's training iteration with a random spp pair per iteration (Sec. 4):
+    the paper's x4 network, robust loss, SGD; every iteration renders its batch of
+    128x128 windows (HRLS at spp_h, LRHS at spp_l, drawn from the paper's sets) and
+    takes one step.  Two procedural training scenes, 4 windows each."""
+    import numpy as np
+    import torch
+    import paper_2106_12802_amd as mrs
+    from paper_2106_12802_amd import hybrid as Hy
+    data = Hy.OnlinePairs([(100, 20000), (101, 60000)], windows=4, size=128, log=None)
+    net = mrs.FusionNet(seed=1, arch="rdg")
+    Hy.train_random_spp(net, data, 1, batch=batch, log=None)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = Hy.train_random_spp(net, data, steps, batch=batch, seed=1, log=None)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    paths = [batch * 128 * 128 * (h + l / 16) for _, h, l, _ in hist]
+    net.close()
+    data.close()
+    res = {"workload": f"paper network x4, robust loss, SGD; batch {batch} of 128x128 windows "
+                       "from 2 procedural scenes (20k, 60k triangles), inputs rendered every "
+                       "iteration at a random spp pair",
+           "ms_per_iteration": round(ms, 3),
+           "spp_pairs": [[h, l] for _, h, l, _ in hist],
+           "mpaths_per_iteration_mean": round(float(np.mean(paths)) / 1e6, 3)}
+    log(f"[bench] random spp pairs: {ms:.2f} ms per iteration ({res['spp_pairs']})")
+    return res
+
+
 def paper_net_block(log, reps=10, train_steps=10):
     """The paper's own network (three residual dense groups, Sec. 4): fuse time
     on the 720p hybrid frame and at the paper's runtime-table size (one
@@ -489,6 +556,10 @@ def main():
                          "every k_extend launch is then one of the batched frame's)")
     ap.add_argument("--no-mis", action="store_true",
                     help="skip the multiple-importance-sampling comparison")
+    ap.add_argument("--no-camera", action="store_true",
+                    help="skip the depth-of-field / motion-blur timing block")
+    ap.add_argument("--no-spp-pairs", action="store_true",
+                    help="skip the random-spp-pair training iteration block")
     ap.add_argument("--no-paper-net", action="store_true",
                     help="skip timing the paper's own network (residual dense groups)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -562,6 +633,18 @@ def main():
         frame_batch.render()
         net.fuse(hr_rgb, hr_aux, lr_rgb, out=out)
 
+    def frames(first, k):
+        # k frames pipelined on the stream: frame i's fusion runs while frame i+1
+        # renders (the render is enqueued in two halves around the fusion)
+        frame_batch.set_seeds([2 * first, 2 * first + 1])
+        frame_batch.render_begin()
+        for i in range(first, first + k):
+            frame_batch.render_end()
+            if i + 1 < first + k:
+                frame_batch.set_seeds([2 * i + 2, 2 * i + 3])
+                frame_batch.render_begin()
+            net.fuse(hr_rgb, hr_aux, lr_rgb, out=out)
+
     def step_calls(i):
         R.render_ex(gs, Wh, Hh, sh, MAX_DEPTH, 2 * i, hr_rgb, hr_aux)
         R.render_ex(gs, Wl, Hl, sl, MAX_DEPTH, 2 * i + 1, lr_rgb, None)
@@ -575,16 +658,15 @@ def main():
     work = R.counters(reset=True)
     log(f"[bench] work per frame: {json.dumps(work)}")
 
-    for i in range(args.warmup):
-        step(i)
+    if args.warmup:
+        frames(0, args.warmup)
     torch.cuda.synchronize()
     log(f"[bench] warmup done ({args.warmup} frames)")
 
     R.profile_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(args.steps):
-        step(i)
+    frames(0, args.steps)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     prof = R.profile_read()
@@ -592,6 +674,17 @@ def main():
     ms_per_step = dt * 1e3 / args.steps
     value = paths * args.steps / dt / 1e6
     log(f"[bench] {args.steps} frames: {ms_per_step:.3f} ms/frame, {value:.1f} Mpaths/s")
+    # the same frames one at a time (each frame's fusion after its render): the
+    # latency of one frame, for comparison, not timed above
+    ms_unpiped = None
+    if not args.no_two_calls:
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for i in range(args.steps):
+            step(i)
+        torch.cuda.synchronize()
+        ms_unpiped = (time.perf_counter() - t1) * 1e3 / args.steps
+        log(f"[bench] same frames one at a time: {ms_unpiped:.3f} ms/frame")
     # the same frames as two separate render calls (for comparison, not timed above)
     ms_calls = None
     if not args.no_two_calls:
@@ -635,7 +728,8 @@ def main():
                                "textured Lambert+GGX, 3 quad lights, env 0.2), HRLS 1280x720@4spp "
                                "+ LRHS 320x180@64spp (max depth 8, RR from vertex 3; both renders as one "
                                "two-job batch, new seeds every frame) + BF16 fusion network "
-                               "(175.7 GFLOP)",
+                               "(175.7 GFLOP); frames pipelined on one stream (frame i's fusion "
+                               "runs while frame i+1 renders)",
                    "paths_per_frame": paths, "triangles": scene.num_tris,
                    "weights": "trained (paper_2106_12802_amd/weights)" if trained else "untrained",
                    "tuning": tuning},
@@ -643,6 +737,7 @@ def main():
         "roofline_cnn": cnn_roof,
         "kernel_ms_per_frame": kernel_ms,
         "rays_per_path": round((work["rays"] + work["shadow_rays"]) / paths, 3),
+        "ms_per_frame_unpipelined": None if ms_unpiped is None else round(ms_unpiped, 4),
         "ms_per_frame_two_render_calls": None if ms_calls is None else round(ms_calls, 4),
     }
     if args.equal_psnr_scenes > 0:
@@ -653,6 +748,10 @@ def main():
         result["paper_net"] = paper_net_block(log)
     if not args.no_mis:
         result["mis"] = mis_block(gs, log)
+    if not args.no_camera:
+        result["camera"] = camera_block(gs, log)
+    if not args.no_spp_pairs:
+        result["spp_pairs"] = spp_pairs_block(log)
     if not args.no_cpu_baseline:
         threads = max(1, min(16, len(os.sched_getaffinity(0))))
         log(f"[bench] timing the FP64 oracle on {threads} host threads")

@@ -200,6 +200,19 @@ mrs_status mrs_batch_create(const mrs_job* jobs, int32_t n, mrs_batch** out);
  * no host synchronisation and can be captured in a HIP graph.  Two renders of
  * one batch must not overlap (same stream, or ordered by events). */
 mrs_status mrs_batch_render(mrs_batch* batch);
+/* mrs_batch_render in two calls, for frame pipelines.  _begin enqueues the
+ * render on the current stream up to its last per-pixel sums: the wavefront
+ * runs on the library's sub-chunk streams from there on.  _end, on the same
+ * stream, enqueues those sums and the resolve; until then the caller's stream
+ * may take other work, which runs concurrently with the render (e.g. the
+ * fusion network on the previous frame's images).  The batch's outputs are
+ * written only by _end, so work enqueued between the two calls may still read
+ * them (the previous frame's values).  Errors (MRS_ERR_INVALID_ARGUMENT, no
+ * effect): _begin while a render of the batch is begun and not ended, _end
+ * with none begun or on another stream.  Begin + end is mrs_batch_render,
+ * bitwise.  No allocation, no host synchronisation. */
+mrs_status mrs_batch_render_begin(mrs_batch* batch);
+mrs_status mrs_batch_render_end(mrs_batch* batch);
 /* Replaces the seed of every job (seeds[i] for job i, as many as the batch
  * has jobs): enqueues a small update of the device job table on the current
  * stream, ordered before later renders of the batch.  No allocation. */

@@ -132,6 +132,8 @@ def lib():
         "mrs_net_set_state": ([P, P, P, P, C.c_int64, C.c_int64], I32),
         "mrs_batch_create": ([C.POINTER(Job), I32, C.POINTER(P)], I32),
         "mrs_batch_render": ([P], I32),
+        "mrs_batch_render_begin": ([P], I32),
+        "mrs_batch_render_end": ([P], I32),
         "mrs_batch_destroy": ([P], I32),
         "mrs_release_workspaces": ([], I32),
         "mrs_batch_set_seeds": ([P, P], I32),
@@ -169,6 +171,7 @@ def exported_symbols():
         "mrs_batch_destroy", "mrs_release_workspaces", "mrs_batch_set_seeds",
         "mrs_debug_bvh4", "mrs_net_arch_num_params", "mrs_net_create_arch",
         "mrs_net_loss_grad_ex", "mrs_train_step_ex", "mrs_net_backward",
+        "mrs_batch_render_begin", "mrs_batch_render_end",
     ]
 
 

@@ -373,6 +373,16 @@ mrs_status mrs_batch_render(mrs_batch* b) {
   return batch_render(b, current_stream());
 }
 
+mrs_status mrs_batch_render_begin(mrs_batch* b) {
+  if (!b) return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_batch_render_begin: batch is NULL");
+  return batch_render_begin(b, current_stream());
+}
+
+mrs_status mrs_batch_render_end(mrs_batch* b) {
+  if (!b) return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_batch_render_end: batch is NULL");
+  return batch_render_end(b, current_stream());
+}
+
 mrs_status mrs_batch_set_seeds(mrs_batch* b, const uint64_t* seeds) {
   if (!b || !seeds) return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_batch_set_seeds: NULL argument");
   return batch_set_seeds(b, seeds, current_stream());

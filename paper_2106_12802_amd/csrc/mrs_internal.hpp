@@ -25,6 +25,12 @@ const std::string& t_error_ref();
     if (e_ != hipSuccess) return ::mrs::check_hip(e_, #expr);   \
   } while (0)
 
+#define MRS_TRY_STATUS(expr)          \
+  do {                                \
+    mrs_status s_ = (expr);           \
+    if (s_ != MRS_OK) return s_;      \
+  } while (0)
+
 // ------------------------------------------------------------------ device scene
 constexpr uint32_t LEAF_BIT = 0x80000000u;
 constexpr uint32_t NO_PRIM = 0xffffffffu;
@@ -149,6 +155,8 @@ DevJob make_job(const mrs_scene* s, const RenderArgs& a);
 // a batch of validated jobs: job table, accumulators and its own workspace
 mrs_status batch_create(const std::vector<DevJob>& jobs, mrs_batch** out);
 mrs_status batch_render(mrs_batch* b, hipStream_t st);
+mrs_status batch_render_begin(mrs_batch* b, hipStream_t st);
+mrs_status batch_render_end(mrs_batch* b, hipStream_t st);
 mrs_status batch_set_seeds(mrs_batch* b, const uint64_t* seeds, hipStream_t st);
 void batch_destroy(mrs_batch* b);
 // frees the per-stream workspaces (synchronises the device)

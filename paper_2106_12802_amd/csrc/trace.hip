@@ -1203,6 +1203,28 @@ __global__ __launch_bounds__(256) void k_debug_philox(int32_t n, const uint32_t*
 // Path state of one stream of renders.  Renders enqueued on one stream share a
 // workspace in stream order; each stream, and each batch, has its own, so
 // renders on different streams can run concurrently.
+// One sub-chunk of a super-chunk: its stream and its slice of the workspace.
+struct Sub {
+  hipStream_t s;
+  int64_t lo;
+  uint32_t n;
+  unsigned gb;
+  size_t o;
+  float4* rays[2];
+  float4 *hits, *shadow, *beta, *L, *aux;
+  uint32_t *spill, *q;
+};
+
+// The part of a render left for its end: the last super-chunk's per-pixel sums
+// and the resolve into the outputs.
+struct Pending {
+  bool active = false;
+  hipStream_t st = nullptr;
+  int used = 0;
+  int nwave = 0;
+  Sub sub[MAX_SUB];
+};
+
 struct Workspace {
   size_t cap_paths = 0;
   int spill_threads = 0;
@@ -1220,6 +1242,7 @@ struct Workspace {
   int nsub = 0;           // sub-chunk join events created
   hipEvent_t ev_fork = nullptr;
   hipEvent_t ev_join[MAX_SUB] = {};
+  Pending pend;  // a render begun and not yet ended
 };
 
 // How a render's path space is cut: super-chunks of K * Cs paths; the K
@@ -1376,18 +1399,46 @@ size_t acc_bytes_of(int64_t npix, bool fp64) {
   return ((size_t)npix * 13 * (fp64 ? 8 : 4) + 255) & ~(size_t)255;
 }
 
+// Per-pixel sums of one super-chunk, in sample order: each sub-chunk, in path
+// order, on the caller's stream once that sub-chunk is done (its join event).
+mrs_status sum_chunk(Workspace& ws, const DevJob* d_jobs, const std::vector<DevJob>& jobs,
+                     const Sub* sub, int used, int nwave, char* acc, hipStream_t st) {
+  const int nj = (int)jobs.size();
+  for (int k = 0; k < used; ++k) {
+    const Sub& u = sub[k];
+    if (u.s != st) MRS_TRY_HIP(hipStreamWaitEvent(st, ws.ev_join[k], 0));
+    // the chunk's pixels in path order: from the pixel of its first path to
+    // the pixel of its last
+    int jlo = 0, jhi = nj - 1;
+    while (jlo < nj - 1 && jobs[jlo + 1].first <= u.lo) ++jlo;
+    while (jhi > 0 && jobs[jhi].first >= u.lo + (int64_t)u.n) --jhi;
+    const int64_t pix_lo = jobs[jlo].pix_first + (u.lo - jobs[jlo].first) / jobs[jlo].spp;
+    const int64_t pix_hi =
+        jobs[jhi].pix_first + (u.lo + (int64_t)u.n - 1 - jobs[jhi].first) / jobs[jhi].spp + 1;
+    prof_begin(KID_ACCUMULATE, st);
+    k_accumulate<<<cdiv((size_t)(pix_hi - pix_lo), 256), 256, 0, st>>>(
+        d_jobs, nj, u.lo, u.n, pix_lo, pix_hi, u.L, u.aux, acc, g_stats);
+    prof_end(KID_ACCUMULATE, st);
+    k_tally<<<1, 64, 0, st>>>(u.q, nwave, g_stats, u.n);
+  }
+  // the next super-chunk (or render) reuses the slices once these sums have read them
+  if (used > 0 && sub[0].s != st) MRS_TRY_HIP(hipEventRecord(ws.ev_fork, st));
+  return MRS_OK;
+}
+
 // The launch sequence of a batch whose job table is on the device: chunks of at
 // most chunk_paths paths over the concatenated path space; per chunk, generate,
 // then extend / shade / shadow per bounce, then accumulate; finally resolve.
-mrs_status launch_batch(Workspace& ws, const mrs_tuning& tu, const DevJob* d_jobs,
-                        const std::vector<DevJob>& jobs, char* acc, size_t acc_bytes,
-                        hipStream_t st) {
+// This enqueues everything but the last super-chunk's sums and the resolve,
+// which end_batch enqueues (render_batch does both).
+mrs_status begin_batch(Workspace& ws, const mrs_tuning& tu, const DevJob* d_jobs,
+                       const std::vector<DevJob>& jobs, char* acc, size_t acc_bytes,
+                       hipStream_t st) {
   const int nj = (int)jobs.size();
-  int64_t total = 0, total_pix = 0;
+  int64_t total = 0;
   int max_depth = 0;
   for (const DevJob& J : jobs) {
     total += (int64_t)J.spp * J.ww * J.wh;
-    total_pix += (int64_t)J.ww * J.wh;
     max_depth = std::max(max_depth, (int)J.max_depth);
   }
   const Plan P = make_plan(tu, total);
@@ -1400,17 +1451,6 @@ mrs_status launch_batch(Workspace& ws, const mrs_tuning& tu, const DevJob* d_job
   k_zero_words<<<std::min(4096u, cdiv(acc_bytes / 4, 256)), 256, 0, st>>>((uint32_t*)acc,
                                                                           acc_bytes / 4);
   if (P.K > 1) MRS_TRY_HIP(hipEventRecord(ws.ev_fork, st));
-  // One sub-chunk: its stream and its slice of the workspace.
-  struct Sub {
-    hipStream_t s;
-    int64_t lo;
-    uint32_t n;
-    unsigned gb;
-    size_t o;
-    float4* rays[2];
-    float4 *hits, *shadow, *beta, *L, *aux;
-    uint32_t *spill, *q;
-  };
   for (int64_t g0 = 0; g0 < total; g0 += P.K * P.Cs) {
     Sub sub[MAX_SUB];
     int used = 0;
@@ -1487,36 +1527,51 @@ mrs_status launch_batch(Workspace& ws, const mrs_tuning& tu, const DevJob* d_job
         prof_end(KID_TAIL, u.s);
       }
     }
-    // per-pixel sums in sample order: each sub-chunk, in path order, on the
-    // caller's stream as soon as that sub-chunk is done
-    for (int k = 0; k < used; ++k) {
-      Sub& u = sub[k];
-      if (P.K > 1) {
-        MRS_TRY_HIP(hipEventRecord(ws.ev_join[k], u.s));
-        MRS_TRY_HIP(hipStreamWaitEvent(st, ws.ev_join[k], 0));
-      }
-      // the chunk's pixels in path order: from the pixel of its first path to
-      // the pixel of its last
-      int jlo = 0, jhi = nj - 1;
-      while (jlo < nj - 1 && jobs[jlo + 1].first <= u.lo) ++jlo;
-      while (jhi > 0 && jobs[jhi].first >= u.lo + (int64_t)u.n) --jhi;
-      const int64_t pix_lo = jobs[jlo].pix_first + (u.lo - jobs[jlo].first) / jobs[jlo].spp;
-      const int64_t pix_hi =
-          jobs[jhi].pix_first + (u.lo + (int64_t)u.n - 1 - jobs[jhi].first) / jobs[jhi].spp + 1;
-      prof_begin(KID_ACCUMULATE, st);
-      k_accumulate<<<cdiv((size_t)(pix_hi - pix_lo), 256), 256, 0, st>>>(
-          d_jobs, nj, u.lo, u.n, pix_lo, pix_hi, u.L, u.aux, acc, stats);
-      prof_end(KID_ACCUMULATE, st);
-      k_tally<<<1, 64, 0, st>>>(u.q, nwave, stats, u.n);
+    // each sub-chunk's end, recorded on its own stream right after its last launch
+    if (P.K > 1)
+      for (int k = 0; k < used; ++k) MRS_TRY_HIP(hipEventRecord(ws.ev_join[k], sub[k].s));
+    if (g0 + P.K * P.Cs < total) {
+      MRS_TRY_STATUS(sum_chunk(ws, d_jobs, jobs, sub, used, nwave, acc, st));
+    } else {
+      ws.pend.active = true;
+      ws.pend.st = st;
+      ws.pend.used = used;
+      ws.pend.nwave = nwave;
+      for (int k = 0; k < used; ++k) ws.pend.sub[k] = sub[k];
     }
-    // the next super-chunk reuses the slices once these sums have read them
-    if (P.K > 1) MRS_TRY_HIP(hipEventRecord(ws.ev_fork, st));
   }
+  MRS_TRY_HIP(hipGetLastError());
+  return MRS_OK;
+}
+
+// The last super-chunk's sums and the resolve into the outputs, on the stream
+// the render began on.
+mrs_status end_batch(Workspace& ws, const DevJob* d_jobs, const std::vector<DevJob>& jobs,
+                     char* acc) {
+  const hipStream_t st = ws.pend.st;
+  int64_t total_pix = 0;
+  for (const DevJob& J : jobs) total_pix += (int64_t)J.ww * J.wh;
+  ws.pend.active = false;
+  MRS_TRY_STATUS(sum_chunk(ws, d_jobs, jobs, ws.pend.sub, ws.pend.used, ws.pend.nwave, acc, st));
   prof_begin(KID_RESOLVE, st);
-  k_resolve<<<cdiv((size_t)total_pix, 256), 256, 0, st>>>(d_jobs, nj, total_pix, acc);
+  k_resolve<<<cdiv((size_t)total_pix, 256), 256, 0, st>>>(d_jobs, (int)jobs.size(), total_pix,
+                                                           acc);
   prof_end(KID_RESOLVE, st);
   MRS_TRY_HIP(hipGetLastError());
   return MRS_OK;
+}
+
+mrs_status launch_batch(Workspace& ws, const mrs_tuning& tu, const DevJob* d_jobs,
+                        const std::vector<DevJob>& jobs, char* acc, size_t acc_bytes,
+                        hipStream_t st) {
+  if (ws.pend.active)
+    return fail(MRS_ERR_INVALID_ARGUMENT, "render: a split render of this workspace is not ended");
+  mrs_status rc = begin_batch(ws, tu, d_jobs, jobs, acc, acc_bytes, st);
+  if (rc != MRS_OK) {
+    ws.pend.active = false;
+    return rc;
+  }
+  return end_batch(ws, d_jobs, jobs, acc);
 }
 
 }  // namespace
@@ -1665,6 +1720,24 @@ mrs_status batch_create(const std::vector<DevJob>& jobs, mrs_batch** out) {
 
 mrs_status batch_render(mrs_batch* b, hipStream_t st) {
   return launch_batch(b->ws, b->tune, b->d_jobs, b->jobs, b->d_acc, b->acc_bytes, st);
+}
+
+mrs_status batch_render_begin(mrs_batch* b, hipStream_t st) {
+  if (b->ws.pend.active)
+    return fail(MRS_ERR_INVALID_ARGUMENT,
+                "mrs_batch_render_begin: the batch's previous render is not ended");
+  mrs_status rc = begin_batch(b->ws, b->tune, b->d_jobs, b->jobs, b->d_acc, b->acc_bytes, st);
+  if (rc != MRS_OK) b->ws.pend.active = false;
+  return rc;
+}
+
+mrs_status batch_render_end(mrs_batch* b, hipStream_t st) {
+  if (!b->ws.pend.active)
+    return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_batch_render_end: no render of the batch begun");
+  if (b->ws.pend.st != st)
+    return fail(MRS_ERR_INVALID_ARGUMENT,
+                "mrs_batch_render_end: not the stream mrs_batch_render_begin ran on");
+  return end_batch(b->ws, b->d_jobs, b->jobs, b->d_acc);
 }
 
 mrs_status batch_set_seeds(mrs_batch* b, const uint64_t* seeds, hipStream_t st) {

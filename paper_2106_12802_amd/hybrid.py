@@ -88,6 +88,33 @@ class HybridFrame:
         self.batch.render()
         return self.net.fuse(self.hr_rgb, self.hr_aux, self.lr_rgb, out=self.out)
 
+    def _seeds(self, seed):
+        return [2 * seed] if self.fallback else [2 * seed, 2 * seed + 1]
+
+    def render_stream(self, seeds, on_frame=None):
+        """The frames of `seeds` in order, pipelined on the current stream: frame i's
+        fusion runs while frame i+1 renders (the render is enqueued in two halves,
+        Batch.render_begin / render_end, and the fusion goes between them).  Each
+        frame equals render(seed) bitwise.  on_frame(k, out) is called once frame k's
+        output is enqueued (work it enqueues on the stream sees that frame)."""
+        seeds = list(seeds)
+        if not seeds:
+            return self.out
+        self.batch.set_seeds(self._seeds(seeds[0]))
+        self.batch.render_begin()
+        for k in range(len(seeds)):
+            self.batch.render_end()
+            if k + 1 < len(seeds):
+                # frame k+1's wavefront starts now; it writes the batch's outputs
+                # only at its render_end, after the fusion below has read them
+                self.batch.set_seeds(self._seeds(seeds[k + 1]))
+                self.batch.render_begin()
+            if not self.fallback:
+                self.net.fuse(self.hr_rgb, self.hr_aux, self.lr_rgb, out=self.out)
+            if on_frame is not None:
+                on_frame(k, self.out)
+        return self.out
+
     def close(self):
         self.batch.close()
 

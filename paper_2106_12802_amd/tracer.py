@@ -240,6 +240,16 @@ class Batch:
         L.use_current_stream()
         L.check(L.lib().mrs_batch_render(self.handle))
 
+    def render_begin(self):
+        """First half of render(): the wavefront is enqueued; the outputs still
+        hold the previous render's values until render_end() (same stream)."""
+        L.use_current_stream()
+        L.check(L.lib().mrs_batch_render_begin(self.handle))
+
+    def render_end(self):
+        L.use_current_stream()
+        L.check(L.lib().mrs_batch_render_end(self.handle))
+
     def set_seeds(self, seeds):
         """New seed per job (stream-ordered device update; no allocation)."""
         arr = np.asarray([int(x) for x in seeds], dtype=np.uint64)

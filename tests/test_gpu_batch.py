@@ -242,3 +242,69 @@ def test_fallback_without_network_is_plain_render(torch_cuda):
         torch.cuda.synchronize()
         assert torch.equal(a, plain) and torch.equal(b, plain)
         fr.close()
+
+
+@pytest.mark.parametrize("chunk", [None, 3000])
+def test_split_render_matches_render(torch_cuda, chunk):
+    """render_begin + render_end is render, bitwise, also over several super-chunks;
+    the outputs keep the previous render's values until render_end; misuse is an
+    error with no effect."""
+    import paper_2106_12802_amd as mrs
+    from paper_2106_12802_amd._lib import MrsError
+    torch = torch_cuda
+    old = mrs.get_tuning()
+    try:
+        if chunk:
+            mrs.set_tuning(chunk_paths=chunk, trace_blocks=16)
+        jobs = _jobs(mrs)[:3]
+        b = mrs.Batch(jobs)
+    finally:
+        mrs.set_tuning(**old)
+    b.render()
+    torch.cuda.synchronize()
+    prev = [o[0].clone() for o in b.outputs]
+    with pytest.raises(MrsError, match="no render of the batch begun"):
+        b.render_end()
+    seeds = [21, (1 << 33) + 22, 23]
+    b.set_seeds(seeds)
+    b.render_begin()
+    with pytest.raises(MrsError, match="not ended"):
+        b.render_begin()
+    with pytest.raises(MrsError, match="not ended"):
+        b.render()
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        with pytest.raises(MrsError, match="stream"):
+            b.render_end()
+    between = [o[0].clone() for o in b.outputs]  # enqueued between begin and end
+    b.render_end()
+    torch.cuda.synchronize()
+    for p, q in zip(prev, between):
+        assert torch.equal(p, q)
+    for j, seed, (rgb, aux) in zip(jobs, seeds, b.outputs):
+        r1, a1 = _single(mrs, dict(j, seed=seed))
+        torch.cuda.synchronize()
+        assert torch.equal(rgb, r1), seed
+        assert torch.equal(aux, a1), seed
+    b.close()
+
+
+def test_pipelined_frames_equal_single_frames(torch_cuda):
+    """HybridFrame.render_stream (frame k's fusion overlapping frame k+1's render)
+    gives every frame bitwise as render(seed); also for the no-network fallback."""
+    import paper_2106_12802_amd as mrs
+    from paper_2106_12802_amd import hybrid as HY
+    torch = torch_cuda
+    gs = mrs.GpuScene(S.procedural(7, spheres=((2, 4),), n_boxes=5, n_lights=2))
+    seeds = [3, 11, 5, 8, 2]
+    for net in (mrs.FusionNet(seed=4), None):
+        fr = HY.HybridFrame(gs, net, 320, 192)
+        refs = [fr.render(sd).clone() for sd in seeds]
+        got = []
+        fr.render_stream(seeds, on_frame=lambda k, out: got.append(out.clone()))
+        torch.cuda.synchronize()
+        assert len(got) == len(seeds)
+        for k, (a, r) in enumerate(zip(got, refs)):
+            assert torch.equal(a, r), (net is None, k)
+        fr.render_stream([])
+        fr.close()
