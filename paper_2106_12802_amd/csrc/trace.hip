@@ -151,8 +151,10 @@ __device__ __forceinline__ bool isect_leaf(const gfloat4* __restrict__ leaf_tri,
   return ok;
 }
 
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+
 struct Stack {
-  uint32_t* lds;     // this thread's column: entry k at lds[k * TB]
+  lds_u32* lds;      // this thread's column: entry k at lds[k * TB]
   uint32_t* spill;   // this thread's global column: entry k at spill[k * stride]
   uint32_t stride;
   int sp;
@@ -170,9 +172,14 @@ struct Stack {
     }
     ++sp;
   }
+  // The LDS read is unconditional (clamped index) and the global read is a
+  // branch of its own, so the common case is a plain LDS read rather than one
+  // generic load through either address space.
   __device__ __forceinline__ uint32_t pop() {
     --sp;
-    return sp < LDS_STACK ? lds[sp * TB] : spill[(size_t)(sp - LDS_STACK) * stride];
+    const uint32_t top = lds[(sp < LDS_STACK ? sp : LDS_STACK - 1) * TB];
+    if (sp < LDS_STACK) return top;
+    return spill[(size_t)(sp - LDS_STACK) * stride];
   }
   // Pushes the first `cnt` (0..3) of c, b, a in that order: far to near, so
   // that `a` is popped first.  With room in LDS for three entries (nearly
@@ -562,7 +569,7 @@ __global__ __launch_bounds__(TB) void k_extend(const DevJob* __restrict__ jobs, 
   __shared__ uint32_t stk[LDS_STACK * TB];
   const uint32_t n = q[Q_RAYS + b];
   const uint32_t gtid = blockIdx.x * TB + threadIdx.x;
-  Stack st{stk + threadIdx.x, spill + gtid, gridDim.x * TB, 0, 0u, false};
+  Stack st{(lds_u32*)stk + threadIdx.x, spill + gtid, gridDim.x * TB, 0, 0u, false};
   WorkCount wc;
   ExtendIO io{jobs, rays, hits};
   trace_queue<CLOSEST, COUNT>(io, n, dyn, q + Q_FETCH_EXT + b, st, wc);
@@ -885,7 +892,7 @@ __global__ __launch_bounds__(TB) void k_shadow(const DevJob* __restrict__ jobs, 
   __shared__ uint32_t stk[LDS_STACK * TB];
   const uint32_t n = q[Q_SHADOW + b];
   const uint32_t gtid = blockIdx.x * TB + threadIdx.x;
-  Stack st{stk + threadIdx.x, spill + gtid, gridDim.x * TB, 0, 0u, false};
+  Stack st{(lds_u32*)stk + threadIdx.x, spill + gtid, gridDim.x * TB, 0, 0u, false};
   WorkCount wc;
   ShadowIO io{jobs, shadow, L_buf};
   trace_queue<ANY_HIT, COUNT>(io, n, dyn, q + Q_FETCH_SHD + b, st, wc);
@@ -999,7 +1006,7 @@ __global__ __launch_bounds__(TB) void k_tail(const DevJob* __restrict__ jobs, in
   __shared__ uint32_t stk[LDS_STACK * TB];
   const uint32_t n = q[Q_RAYS + b0];
   const uint32_t gtid = blockIdx.x * TB + threadIdx.x;
-  Stack st{stk + threadIdx.x, spill + gtid, gridDim.x * TB, 0, 0u, false};
+  Stack st{(lds_u32*)stk + threadIdx.x, spill + gtid, gridDim.x * TB, 0, 0u, false};
   WorkCount wc;
   PathIO io;
   io.jobs = jobs;
@@ -1179,7 +1186,7 @@ __global__ __launch_bounds__(TB) void k_debug_hit(SceneView sc, int32_t n,
                                                   uint32_t* __restrict__ spill) {
   __shared__ uint32_t stk[LDS_STACK * TB];
   const uint32_t gtid = blockIdx.x * TB + threadIdx.x;
-  Stack st{stk + threadIdx.x, spill + gtid, gridDim.x * TB, 0, 0u, false};
+  Stack st{(lds_u32*)stk + threadIdx.x, spill + gtid, gridDim.x * TB, 0, 0u, false};
   WorkCount wc;
   DebugHitIO io{sc, o, d, skip, t_out, prim_out, b_out};
   trace_stream<CLOSEST, false>(io, gtid, gridDim.x * TB, (uint32_t)n, st, wc);
