@@ -712,11 +712,19 @@ def main():
                 "flop_per_launch": int(flop_per_launch),
                 "visits_per_ray": round(work["extend_visits"] / ext_rays, 2),
                 "tests_per_ray": round(work["extend_tests"] / ext_rays, 2)}
-    cnn_ms = sum(prof.get(k, (0.0, 0))[0] for k in ("cnn_prep", "cnn_hr_in", "cnn_lr",
-                                                     "cnn_hr_out")) / args.steps
+    # the network alone: in the pipelined frames it shares the GPU with the next
+    # frame's render, so its events there also hold the tracer's share
+    R.profile_enable(True)
+    for _ in range(args.steps):
+        net.fuse(hr_rgb, hr_aux, lr_rgb, out=out)
+    torch.cuda.synchronize()
+    prof_cnn = R.profile_read()
+    R.profile_enable(False)
+    cnn_ms = sum(prof_cnn.get(k, (0.0, 0))[0] for k in ("cnn_prep", "cnn_hr_in", "cnn_lr",
+                                                         "cnn_hr_out")) / args.steps
     cnn_roof = {"bound": "mfma", "achieved": round(CNN_FLOP_720P / (cnn_ms / 1e3) / 1e12, 2)
                 if cnn_ms > 0 else 0.0, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
-                "ms_per_frame": round(cnn_ms, 4)}
+                "ms_per_frame": round(cnn_ms, 4), "measured": "the network alone, HIP events"}
     cnn_roof["frac"] = round(cnn_roof["achieved"] / PEAK_BF16_TFLOPS, 5)
     kernel_ms = {k: round(v[0] / args.steps, 4) for k, v in prof.items()}
     result = {
