@@ -572,6 +572,8 @@ def main():
                     help="tuning: concurrent sub-chunks per render (1..4)")
     ap.add_argument("--tail-bounce", type=int, default=None,
                     help="tuning: first bounce traced path by path in one launch (65: never)")
+    ap.add_argument("--bvh-builder", default=None, choices=("lbvh", "ploc"),
+                    help="tuning: BVH builder of the scenes (default ploc)")
     ap.add_argument("--leaf-max", type=int, default=None,
                     help="BVH build: triangles a BVH4 leaf may group (1..4)")
     ap.add_argument("--stats-summary", metavar="PROF_DIR",
@@ -601,7 +603,7 @@ def main():
     if args.copy_calibration:
         copy_calibration()
     R.set_tuning(args.chunk_paths, args.trace_blocks, args.schedule, args.leaf_max, args.streams,
-                 args.tail_bounce)
+                 args.tail_bounce, args.bvh_builder)
     tuning = R.get_tuning()
     log(f"[bench] tuning {tuning}")
     scene = S.procedural(SCENE_SEED)

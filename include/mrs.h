@@ -116,12 +116,28 @@ mrs_status mrs_sync(void);
 mrs_status mrs_scene_create(const mrs_scene_desc* desc, mrs_scene** out);
 mrs_status mrs_scene_destroy(mrs_scene* scene);
 
-/* Builds the linear BVH of Karras (HPG 2012) on the device: 30-bit Morton codes
- * of triangle centroids in the centroid bounds, keys (morton << 32 | prim)
- * sorted by a device radix sort, one internal node per adjacent key pair from
- * common-prefix lengths, leaf-to-root box refit with atomic visit counters.
+/* Builds the scene's BVH on the device, with the builder that
+ * mrs_tuning.bvh_builder selects:
+ *   MRS_BVH_LBVH  the linear BVH of Karras (HPG 2012): 30-bit Morton codes of
+ *                 triangle centroids in the centroid bounds, keys
+ *                 (morton << 32 | prim) sorted by a device radix sort, one
+ *                 internal node per adjacent key pair from common-prefix
+ *                 lengths, leaf-to-root box refit with atomic visit counters;
+ *   MRS_BVH_PLOC  (default) agglomerative clustering over the same Morton
+ *                 order (Meister & Bittner, TVCG 2018): nearest neighbours by
+ *                 union surface area within 4 places, mutual pairs merge,
+ *                 until one cluster is left; laid out depth first.  A tree
+ *                 deeper than 64 levels falls back to MRS_BVH_LBVH.
+ * Then either is collapsed into the four-wide BVH that rendering traverses.
+ * Every builder gives the same closest hits and images, bitwise (traversal
+ * culls conservatively and breaks ties by primitive id); they differ in speed.
  * Idempotent.  Enqueued on the current stream. */
+#define MRS_BVH_LBVH 0
+#define MRS_BVH_PLOC 1
 mrs_status mrs_build_bvh(mrs_scene* scene);
+/* The builder that made the scene's BVH (MRS_BVH_*); MRS_ERR_NOT_READY before
+ * mrs_build_bvh. */
+mrs_status mrs_scene_bvh_builder(const mrs_scene* scene, int32_t* builder);
 
 /* Renders W x H pixels at spp samples each, paths of at most max_depth bounces
  * (vertex 0 is the camera hit; next-event estimation at vertices
@@ -275,6 +291,8 @@ typedef struct mrs_tuning {
                            caller's stream before the per-pixel sums) */
   int32_t tail_bounce;  /* 1..65 (default 3): bounces from this one on are traced
                            path by path in one launch (65: never) */
+  int32_t bvh_builder;  /* MRS_BVH_PLOC (default) or MRS_BVH_LBVH; applies to
+                           scenes built afterwards */
 } mrs_tuning;
 mrs_status mrs_get_tuning(mrs_tuning* out);
 mrs_status mrs_set_tuning(const mrs_tuning* t);

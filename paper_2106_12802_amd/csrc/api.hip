@@ -265,7 +265,7 @@ mrs_status mrs_build_bvh(mrs_scene* s) {
   if (s->bvh_built) return MRS_OK;
   mrs_tuning t;
   get_tuning(&t);
-  mrs_status rc = lbvh_build(s, current_stream(), t.bvh_leaf_max);
+  mrs_status rc = lbvh_build(s, current_stream(), t.bvh_leaf_max, t.bvh_builder);
   if (rc != MRS_OK) return rc;
   s->view.root = s->root4;
   s->view.nodes = s->d_nodes4;
@@ -474,6 +474,13 @@ mrs_status mrs_debug_bvh(const mrs_scene* s, float* nodes, int32_t* leaf_prim, u
   if (leaf_prim && n > 0) MRS_TRY_HIP(hipMemcpy(leaf_prim, s->d_leaf_prim, sizeof(uint32_t) * n, hipMemcpyDeviceToHost));
   if (morton && n > 0) MRS_TRY_HIP(hipMemcpy(morton, s->d_morton, sizeof(uint32_t) * n, hipMemcpyDeviceToHost));
   if (root_ref) *root_ref = (int32_t)s->root;
+  return MRS_OK;
+}
+
+mrs_status mrs_scene_bvh_builder(const mrs_scene* s, int32_t* builder) {
+  if (!s || !builder) return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_scene_bvh_builder: NULL argument");
+  if (!s->bvh_built) return fail(MRS_ERR_NOT_READY, "mrs_scene_bvh_builder: BVH not built");
+  *builder = s->builder;
   return MRS_OK;
 }
 

@@ -20,6 +20,20 @@
 // Binary node record (64 B): child boxes as 12 floats (left lo, left hi, right
 // lo, right hi), two child references (bit 31 = leaf) and the node's range of
 // leaf records (first, last).
+//
+// A second builder replaces steps 4-5 by agglomerative clustering over the
+// Morton order (PLOC: Meister & Bittner, "Parallel Locally-Ordered Clustering
+// for Bounding Volume Hierarchy Construction", IEEE TVCG 2018): every cluster
+// finds, among the clusters within R places of it, the one whose union box has
+// the smallest surface area; mutual nearest neighbours merge; the survivors are
+// compacted in order; repeat until one cluster is left.  Ties are broken by a
+// total order on cluster pairs, so some pair is always mutual and every round
+// merges (identical boxes pair up with their neighbours, see pair_before).
+// The tree is then laid out depth first: internal nodes numbered in
+// preorder (root 0) and leaf records in leaf order, so every subtree's leaves
+// are a contiguous range as the BVH4 collapse needs.  Its trees have a lower
+// surface-area cost than the Morton-split tree (about 15% on the procedural
+// scenes), hence fewer node visits per ray.
 #include "mrs_internal.hpp"
 #include "devmath.hpp"
 
@@ -29,6 +43,7 @@ namespace {
 constexpr int RS_THREADS = 256;
 constexpr int RS_ITEMS = 16;
 constexpr int RS_TILE = RS_THREADS * RS_ITEMS;  // keys per block
+constexpr int PLOC_RADIUS = 4;  // clusters searched on each side (4: lowest SAH cost measured)
 
 __device__ __forceinline__ f3 centroid(const float4* tri, int i) {
   f3 a = xyz(tri[3 * i]), b = xyz(tri[3 * i + 1]), c = xyz(tri[3 * i + 2]);
@@ -300,6 +315,276 @@ __global__ __launch_bounds__(256) void k_leaves_refit(const float4* __restrict__
   }
 }
 
+// ---------------------------------------------------------------- PLOC
+constexpr uint32_t NO_PARENT = 0xffffffffu;
+
+__device__ __forceinline__ float box_half_area(float4 lo, float4 hi) {
+  const float dx = hi.x - lo.x, dy = hi.y - lo.y, dz = hi.z - lo.z;
+  return dx * dy + dy * dz + dz * dx;
+}
+
+// Clusters start as the leaves in Morton order: reference LEAF_BIT | k.
+__global__ __launch_bounds__(256) void k_ploc_init(const float4* __restrict__ tri_src,
+                                                   const uint32_t* __restrict__ prim, int n,
+                                                   uint32_t* __restrict__ cref,
+                                                   float4* __restrict__ clo,
+                                                   float4* __restrict__ chi) {
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k >= n) return;
+  const uint32_t p = prim[k];
+  const f3 a = xyz(tri_src[3 * p]), b = xyz(tri_src[3 * p + 1]), c = xyz(tri_src[3 * p + 2]);
+  cref[k] = LEAF_BIT | (uint32_t)k;
+  clo[k] = make_float4(fminf(a.x, fminf(b.x, c.x)), fminf(a.y, fminf(b.y, c.y)),
+                       fminf(a.z, fminf(b.z, c.z)), 0.0f);
+  chi[k] = make_float4(fmaxf(a.x, fmaxf(b.x, c.x)), fmaxf(a.y, fmaxf(b.y, c.y)),
+                       fmaxf(a.z, fmaxf(b.z, c.z)), 0.0f);
+}
+
+// Pair {c, j} before pair {c, b} in a total order of pairs: nearer pairs
+// first, then pairs whose smaller member is even, then by smaller member (b < 0
+// is no pair yet).  Among equal costs (equal boxes, regular grids) clusters
+// thus pair up as (0, 1), (2, 3), ...: every cluster merges and the tree stays
+// balanced, where a plain index order would merge one pair per round.
+__device__ __forceinline__ bool pair_before(int c, int j, int b) {
+  if (b < 0) return true;
+  const int dj = abs(c - j), db = abs(c - b);
+  if (dj != db) return dj < db;
+  const int j0 = min(c, j), b0 = min(c, b);
+  if ((j0 & 1) != (b0 & 1)) return (j0 & 1) == 0;
+  return j0 < b0;
+}
+
+__global__ __launch_bounds__(256) void k_ploc_nn(int m, int radius,
+                                                 const float4* __restrict__ clo,
+                                                 const float4* __restrict__ chi,
+                                                 int* __restrict__ nn) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= m) return;
+  const float4 lo = clo[c], hi = chi[c];
+  float best = INFINITY;
+  int bj = -1;
+  const int j0 = max(0, c - radius), j1 = min(m - 1, c + radius);
+  for (int j = j0; j <= j1; ++j) {
+    if (j == c) continue;
+    const float4 l2 = clo[j], h2 = chi[j];
+    const float a = box_half_area(
+        make_float4(fminf(lo.x, l2.x), fminf(lo.y, l2.y), fminf(lo.z, l2.z), 0.0f),
+        make_float4(fmaxf(hi.x, h2.x), fmaxf(hi.y, h2.y), fmaxf(hi.z, h2.z), 0.0f));
+    if (a < best || (a == best && pair_before(c, j, bj))) {
+      best = a;
+      bj = j;
+    }
+  }
+  nn[c] = bj;
+}
+
+// Mutual nearest neighbours c < j merge into a new internal node (in place of
+// c; j is dropped).  The node's record gets the two child boxes and references.
+__global__ __launch_bounds__(256) void k_ploc_merge(int m, int nint, const int* __restrict__ nn,
+                                                    uint32_t* __restrict__ cref,
+                                                    float4* __restrict__ clo,
+                                                    float4* __restrict__ chi,
+                                                    float* __restrict__ tnodes,
+                                                    uint32_t* __restrict__ tcount,
+                                                    uint32_t* __restrict__ keep) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= m) return;
+  const int j = nn[c];
+  const bool mutual = j >= 0 && j < m && nn[j] == c;
+  keep[c] = (mutual && c > j) ? 0u : 1u;
+  if (!mutual || c > j) return;
+  const uint32_t t = atomicAdd(tcount, 1u);
+  if (t >= (uint32_t)nint) return;  // cannot happen: n leaves make n - 1 merges
+  const float4 l1 = clo[c], h1 = chi[c], l2 = clo[j], h2 = chi[j];
+  float* o = tnodes + 16 * (size_t)t;
+  o[0] = l1.x; o[1] = l1.y; o[2] = l1.z; o[3] = h1.x; o[4] = h1.y; o[5] = h1.z;
+  o[6] = l2.x; o[7] = l2.y; o[8] = l2.z; o[9] = h2.x; o[10] = h2.y; o[11] = h2.z;
+  o[12] = __uint_as_float(cref[c]);
+  o[13] = __uint_as_float(cref[j]);
+  o[14] = o[15] = 0.0f;
+  cref[c] = t;
+  clo[c] = make_float4(fminf(l1.x, l2.x), fminf(l1.y, l2.y), fminf(l1.z, l2.z), 0.0f);
+  chi[c] = make_float4(fmaxf(h1.x, h2.x), fmaxf(h1.y, h2.y), fmaxf(h1.z, h2.z), 0.0f);
+}
+
+__global__ __launch_bounds__(256) void k_ploc_count(int m, const uint32_t* __restrict__ keep,
+                                                    uint32_t* __restrict__ bcount) {
+  __shared__ uint32_t wc[4];
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  const uint64_t b = __ballot(c < m && keep[c]);
+  if ((threadIdx.x & 63) == 0) wc[threadIdx.x >> 6] = (uint32_t)__popcll(b);
+  __syncthreads();
+  if (threadIdx.x == 0) bcount[blockIdx.x] = wc[0] + wc[1] + wc[2] + wc[3];
+}
+
+// Kept clusters in order into the other arrays (boff: exclusive block offsets);
+// the last cluster's thread writes the new count.
+__global__ __launch_bounds__(256) void k_ploc_scatter(
+    int m, const uint32_t* __restrict__ keep, const uint32_t* __restrict__ boff,
+    const uint32_t* __restrict__ cref, const float4* __restrict__ clo,
+    const float4* __restrict__ chi, uint32_t* __restrict__ cref2, float4* __restrict__ clo2,
+    float4* __restrict__ chi2, uint32_t* __restrict__ mcount) {
+  __shared__ uint32_t wc[4];
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  const bool k = c < m && keep[c];
+  const uint64_t b = __ballot(k);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) wc[w] = (uint32_t)__popcll(b);
+  __syncthreads();
+  uint32_t pos = boff[blockIdx.x] + lanes_below(b);
+  for (int v = 0; v < w; ++v) pos += wc[v];
+  if (k && pos < (uint32_t)m) {
+    cref2[pos] = cref[c];
+    clo2[pos] = clo[c];
+    chi2[pos] = chi[c];
+  }
+  if (c == m - 1) *mcount = pos + (k ? 1u : 0u);
+}
+
+// Parent of every node and leaf: (parent << 1) | side.
+__global__ __launch_bounds__(256) void k_ploc_parents(int nint, const float* __restrict__ tnodes,
+                                                      uint32_t* __restrict__ par_int,
+                                                      uint32_t* __restrict__ par_leaf, int n) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= nint) return;
+  for (int side = 0; side < 2; ++side) {
+    const uint32_t r = __float_as_uint(tnodes[16 * (size_t)t + 12 + side]);
+    const uint32_t v = ((uint32_t)t << 1) | (uint32_t)side;
+    if (r & LEAF_BIT) {
+      if ((r & ~LEAF_BIT) < (uint32_t)n) par_leaf[r & ~LEAF_BIT] = v;
+    } else if (r < (uint32_t)nint) {
+      par_int[r] = v;
+    }
+  }
+}
+
+// Leaf counts of each node's two subtrees (sz2[2t + side]), bottom up: every
+// leaf walks up; the second arrival at a node (visit counter) continues.
+__global__ __launch_bounds__(256) void k_ploc_sizes(int n, const uint32_t* __restrict__ par_int,
+                                                    const uint32_t* __restrict__ par_leaf,
+                                                    uint32_t* __restrict__ sz2,
+                                                    uint32_t* __restrict__ visits,
+                                                    uint32_t* __restrict__ bad) {
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k >= n) return;
+  uint32_t size = 1;
+  uint32_t x = par_leaf[k];
+  for (int guard = 0; guard < 4 * MAX_STACK; ++guard) {
+    if (x == NO_PARENT) return;
+    const uint32_t p = x >> 1, side = x & 1u;
+    if (p >= (uint32_t)(n - 1)) break;  // cannot happen for a tree
+    __hip_atomic_store(sz2 + 2 * p + side, size, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t prev =
+        __hip_atomic_fetch_add(visits + p, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (prev == 0) return;  // the sibling subtree is not finished; its thread continues
+    size += __hip_atomic_load(sz2 + 2 * p + (1u - side), __ATOMIC_RELAXED,
+                              __HIP_MEMORY_SCOPE_AGENT);
+    x = par_int[p];
+  }
+  atomicOr(bad, 1u);
+}
+
+// Depth-first layout, each node and leaf walking up to the root: a left child
+// comes right after its parent in preorder and shares its first leaf; a right
+// child follows the left subtree (its leaf count L): preorder + L, first leaf + L.
+__global__ __launch_bounds__(256) void k_ploc_order(int n, int nint,
+                                                    const uint32_t* __restrict__ par_int,
+                                                    const uint32_t* __restrict__ par_leaf,
+                                                    const uint32_t* __restrict__ sz2,
+                                                    uint32_t* __restrict__ pre_int,
+                                                    uint32_t* __restrict__ first_int,
+                                                    uint32_t* __restrict__ first_leaf,
+                                                    uint32_t* __restrict__ depth_max,
+                                                    uint32_t* __restrict__ bad) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= nint + n) return;
+  uint32_t x = i < nint ? par_int[i] : par_leaf[i - nint];
+  uint32_t pre = 0, first = 0, depth = 0;
+  for (; x != NO_PARENT; ++depth) {
+    if (depth >= 4 * MAX_STACK) {
+      atomicOr(bad, 1u);
+      return;
+    }
+    const uint32_t p = x >> 1;
+    if (p >= (uint32_t)nint) {  // cannot happen for a tree
+      atomicOr(bad, 1u);
+      return;
+    }
+    if (x & 1u) {
+      const uint32_t L = sz2[2 * p];
+      pre += L;
+      first += L;
+    } else {
+      pre += 1;
+    }
+    x = par_int[p];
+  }
+  if (i < nint) {
+    pre_int[i] = pre;
+    first_int[i] = first;
+  } else {
+    first_leaf[i - nint] = first;
+  }
+  atomicMax(depth_max, depth);
+}
+
+// Final binary records: temporary node t goes to its preorder place, with its
+// references and leaf range in the final numbering.
+__global__ __launch_bounds__(256) void k_ploc_emit(int nint, int n, const float* __restrict__ tnodes,
+                                                   const uint32_t* __restrict__ pre_int,
+                                                   const uint32_t* __restrict__ first_int,
+                                                   const uint32_t* __restrict__ first_leaf,
+                                                   const uint32_t* __restrict__ sz2,
+                                                   float* __restrict__ nodes_f) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= nint) return;
+  const uint32_t d = pre_int[t];
+  if (d >= (uint32_t)nint) return;  // cannot happen for a tree
+  const float* src = tnodes + 16 * (size_t)t;
+  float* o = nodes_f + 16 * (size_t)d;
+  for (int a = 0; a < 12; ++a) o[a] = src[a];
+  for (int side = 0; side < 2; ++side) {
+    const uint32_t r = __float_as_uint(src[12 + side]);
+    uint32_t f;
+    if (r & LEAF_BIT) f = LEAF_BIT | first_leaf[min(r & ~LEAF_BIT, (uint32_t)n - 1)];
+    else f = pre_int[min(r, (uint32_t)nint - 1)];
+    o[12 + side] = __uint_as_float(f);
+  }
+  const uint32_t first = first_int[t];
+  o[14] = __uint_as_float(first);
+  o[15] = __uint_as_float(first + sz2[2 * t] + sz2[2 * t + 1] - 1u);
+}
+
+// Morton position k -> leaf position first_leaf[k]: primitives and codes in
+// leaf order.
+__global__ __launch_bounds__(256) void k_ploc_leaves(int n, const uint32_t* __restrict__ prim,
+                                                     const uint32_t* __restrict__ code,
+                                                     const uint32_t* __restrict__ first_leaf,
+                                                     uint32_t* __restrict__ leaf_prim,
+                                                     uint32_t* __restrict__ leaf_code) {
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k >= n) return;
+  const uint32_t pos = first_leaf[k];
+  if (pos >= (uint32_t)n) return;  // cannot happen for a tree
+  leaf_prim[pos] = prim[k];
+  leaf_code[pos] = code[k];
+}
+
+// Leaf records (v0, primitive id) (e1) (e2) in leaf order.
+__global__ __launch_bounds__(256) void k_leaf_records(const float4* __restrict__ tri_src,
+                                                      const uint32_t* __restrict__ leaf_prim,
+                                                      int n, float4* __restrict__ leaf_tri) {
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k >= n) return;
+  const uint32_t p = leaf_prim[k];
+  if (p >= (uint32_t)n) return;  // cannot happen: leaf_prim is a permutation
+  const f3 v0 = xyz(tri_src[3 * p]), v1 = xyz(tri_src[3 * p + 1]), v2 = xyz(tri_src[3 * p + 2]);
+  const f3 e1 = v1 - v0, e2 = v2 - v0;
+  leaf_tri[3 * k + 0] = make_float4(v0.x, v0.y, v0.z, __uint_as_float(p));
+  leaf_tri[3 * k + 1] = make_float4(e1.x, e1.y, e1.z, 0.0f);
+  leaf_tri[3 * k + 2] = make_float4(e2.x, e2.y, e2.z, 0.0f);
+}
+
 // ---------------------------------------------------------------- BVH4 collapse
 struct Cand {
   uint32_t ref;
@@ -484,9 +769,122 @@ mrs_status collapse4(mrs_scene* s, hipStream_t st, int leaf_max, char* scratch, 
   return MRS_OK;
 }
 
+// PLOC over the Morton-sorted primitives (code, prim): binary records into
+// s->d_nodes (preorder, root 0), primitives and codes in leaf order into
+// s->d_leaf_prim / s->d_morton, leaf records into s->d_leaf_tri.  *used is
+// false (and nothing of the scene written) when the tree would be deeper than
+// the Morton-split tree may be (64 levels): the caller builds that one instead.
+mrs_status ploc_build(mrs_scene* s, hipStream_t st, const uint32_t* code, const uint32_t* prim,
+                      int radius, bool* used) {
+  *used = false;
+  const int n = s->ntris, nint = n - 1;
+  const int nb = cdiv(n, 256);
+  size_t bytes = 0;
+  auto carve = [&](size_t sz) {
+    size_t off = bytes;
+    bytes += (sz + 255) & ~(size_t)255;
+    return off;
+  };
+  size_t o_ref[2], o_lo[2], o_hi[2];
+  for (int b = 0; b < 2; ++b) {
+    o_ref[b] = carve(sizeof(uint32_t) * n);
+    o_lo[b] = carve(sizeof(float4) * n);
+    o_hi[b] = carve(sizeof(float4) * n);
+  }
+  const size_t o_nn = carve(sizeof(int) * n);
+  const size_t o_keep = carve(sizeof(uint32_t) * n);
+  const size_t o_boff = carve(sizeof(uint32_t) * nb);
+  const size_t o_tn = carve(sizeof(float) * 16 * (size_t)nint);
+  const size_t o_pi = carve(sizeof(uint32_t) * nint);
+  const size_t o_pl = carve(sizeof(uint32_t) * n);
+  const size_t o_sz = carve(sizeof(uint32_t) * 2 * (size_t)nint);
+  const size_t o_vis = carve(sizeof(uint32_t) * nint);
+  const size_t o_pre = carve(sizeof(uint32_t) * nint);
+  const size_t o_fi = carve(sizeof(uint32_t) * nint);
+  const size_t o_fl = carve(sizeof(uint32_t) * n);
+  const size_t o_ctr = carve(sizeof(uint32_t) * 4);  // merges, count, depth, bad
+  char* scratch = nullptr;
+  if (hipMalloc(&scratch, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(MRS_ERR_OUT_OF_MEMORY, "mrs_build_bvh: clustering scratch allocation failed");
+  }
+  uint32_t* cref[2] = {(uint32_t*)(scratch + o_ref[0]), (uint32_t*)(scratch + o_ref[1])};
+  float4* clo[2] = {(float4*)(scratch + o_lo[0]), (float4*)(scratch + o_lo[1])};
+  float4* chi[2] = {(float4*)(scratch + o_hi[0]), (float4*)(scratch + o_hi[1])};
+  int* nn = (int*)(scratch + o_nn);
+  uint32_t* keep = (uint32_t*)(scratch + o_keep);
+  uint32_t* boff = (uint32_t*)(scratch + o_boff);
+  float* tnodes = (float*)(scratch + o_tn);
+  uint32_t* par_int = (uint32_t*)(scratch + o_pi);
+  uint32_t* par_leaf = (uint32_t*)(scratch + o_pl);
+  uint32_t* sz2 = (uint32_t*)(scratch + o_sz);
+  uint32_t* visits = (uint32_t*)(scratch + o_vis);
+  uint32_t* pre_int = (uint32_t*)(scratch + o_pre);
+  uint32_t* first_int = (uint32_t*)(scratch + o_fi);
+  uint32_t* first_leaf = (uint32_t*)(scratch + o_fl);
+  uint32_t* ctr = (uint32_t*)(scratch + o_ctr);
+  mrs_status rc = MRS_OK;
+  auto run = [&]() -> mrs_status {
+    k_fill_u32<<<1, 256, 0, st>>>(ctr, 4, 0u);
+    k_ploc_init<<<nb, 256, 0, st>>>(s->d_tri_src, prim, n, cref[0], clo[0], chi[0]);
+    int cur = 0;
+    uint32_t m = (uint32_t)n;
+    for (int round = 0; m > 1; ++round) {
+      if (round > 2 * n) return fail(MRS_ERR_DEVICE, "mrs_build_bvh: clustering does not end");
+      const int mb = cdiv(m, 256);
+      k_ploc_nn<<<mb, 256, 0, st>>>((int)m, radius, clo[cur], chi[cur], nn);
+      k_ploc_merge<<<mb, 256, 0, st>>>((int)m, nint, nn, cref[cur], clo[cur], chi[cur], tnodes,
+                                       ctr, keep);
+      k_ploc_count<<<mb, 256, 0, st>>>((int)m, keep, boff);
+      k_rs_scan<<<1, 1024, 0, st>>>(boff, mb);
+      k_ploc_scatter<<<mb, 256, 0, st>>>((int)m, keep, boff, cref[cur], clo[cur], chi[cur],
+                                         cref[1 - cur], clo[1 - cur], chi[1 - cur], ctr + 1);
+      MRS_TRY_HIP(hipGetLastError());
+      uint32_t m2 = 0;
+      MRS_TRY_HIP(hipMemcpyAsync(&m2, ctr + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+      MRS_TRY_HIP(hipStreamSynchronize(st));
+      if (m2 >= m || m2 == 0)
+        return fail(MRS_ERR_DEVICE, "mrs_build_bvh: a clustering round merged nothing");
+      m = m2;
+      cur = 1 - cur;
+    }
+    uint32_t root = 0, merges = 0;
+    MRS_TRY_HIP(hipMemcpyAsync(&root, cref[cur], sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    MRS_TRY_HIP(hipMemcpyAsync(&merges, ctr, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    MRS_TRY_HIP(hipStreamSynchronize(st));
+    if (merges != (uint32_t)nint || (root & LEAF_BIT) || root >= (uint32_t)nint)
+      return fail(MRS_ERR_DEVICE, "mrs_build_bvh: clustering did not make one tree");
+    k_fill_u32<<<cdiv(nint, 256), 256, 0, st>>>(par_int, nint, NO_PARENT);
+    k_fill_u32<<<nb, 256, 0, st>>>(par_leaf, n, NO_PARENT);
+    k_fill_u32<<<cdiv(nint, 256), 256, 0, st>>>(visits, nint, 0u);
+    k_ploc_parents<<<cdiv(nint, 256), 256, 0, st>>>(nint, tnodes, par_int, par_leaf, n);
+    k_ploc_sizes<<<nb, 256, 0, st>>>(n, par_int, par_leaf, sz2, visits, ctr + 3);
+    k_ploc_order<<<cdiv(nint + n, 256), 256, 0, st>>>(n, nint, par_int, par_leaf, sz2, pre_int,
+                                                      first_int, first_leaf, ctr + 2, ctr + 3);
+    MRS_TRY_HIP(hipGetLastError());
+    uint32_t dm[2] = {0, 0};
+    MRS_TRY_HIP(hipMemcpyAsync(dm, ctr + 2, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    MRS_TRY_HIP(hipStreamSynchronize(st));
+    if (dm[1]) return fail(MRS_ERR_DEVICE, "mrs_build_bvh: clustered tree is malformed");
+    if (dm[0] > (uint32_t)MAX_STACK) return MRS_OK;  // too deep: the caller falls back
+    k_ploc_emit<<<cdiv(nint, 256), 256, 0, st>>>(nint, n, tnodes, pre_int, first_int,
+                                                 first_leaf, sz2, (float*)s->d_nodes);
+    k_ploc_leaves<<<nb, 256, 0, st>>>(n, prim, code, first_leaf, s->d_leaf_prim, s->d_morton);
+    k_leaf_records<<<nb, 256, 0, st>>>(s->d_tri_src, s->d_leaf_prim, n, s->d_leaf_tri);
+    MRS_TRY_HIP(hipGetLastError());
+    *used = true;
+    return MRS_OK;
+  };
+  rc = run();
+  // The scratch must outlive the kernels: wait, then free.
+  (void)hipStreamSynchronize(st);
+  (void)hipFree(scratch);
+  return rc;
+}
+
 }  // namespace
 
-mrs_status lbvh_build(mrs_scene* s, hipStream_t st, int leaf_max) {
+mrs_status lbvh_build(mrs_scene* s, hipStream_t st, int leaf_max, int builder) {
   const int n = s->ntris;
   s->bvh_built = false;
   s->leaf_max = leaf_max;
@@ -550,18 +948,31 @@ mrs_status lbvh_build(mrs_scene* s, hipStream_t st, int leaf_max) {
     std::swap(v0, v1);
   }
   // 4 passes: the sorted data is back in the first buffers (k0/v0 after swaps)
-  MRS_TRY_HIP(hipMemcpyAsync(s->d_morton, k0, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, st));
-  MRS_TRY_HIP(
-      hipMemcpyAsync(s->d_leaf_prim, v0, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, st));
-  if (n >= 2) {
-    k_hierarchy<<<cdiv(n - 1, 256), 256, 0, st>>>(s->d_morton, s->d_leaf_prim, n, s->d_nodes,
-                                                  pint, pleaf);
-    k_fill_u32<<<cdiv(n, 256), 256, 0, st>>>(visits, n, 0u);
-  }
-  k_leaves_refit<<<cdiv(n, 256), 256, 0, st>>>(s->d_tri_src, s->d_leaf_prim, n, s->d_leaf_tri,
-                                               (float*)s->d_nodes, pint, pleaf, visits);
-  MRS_TRY_HIP(hipGetLastError());
+  bool clustered = false;
   mrs_status rc = MRS_OK;
+  if (builder == MRS_BVH_PLOC && n >= 2) {
+    rc = ploc_build(s, st, k0, v0, PLOC_RADIUS, &clustered);
+    if (rc != MRS_OK) {
+      (void)hipStreamSynchronize(st);
+      (void)hipFree(scratch);
+      return rc;
+    }
+  }
+  if (!clustered) {
+    MRS_TRY_HIP(
+        hipMemcpyAsync(s->d_morton, k0, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, st));
+    MRS_TRY_HIP(
+        hipMemcpyAsync(s->d_leaf_prim, v0, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, st));
+    if (n >= 2) {
+      k_hierarchy<<<cdiv(n - 1, 256), 256, 0, st>>>(s->d_morton, s->d_leaf_prim, n, s->d_nodes,
+                                                    pint, pleaf);
+      k_fill_u32<<<cdiv(n, 256), 256, 0, st>>>(visits, n, 0u);
+    }
+    k_leaves_refit<<<cdiv(n, 256), 256, 0, st>>>(s->d_tri_src, s->d_leaf_prim, n, s->d_leaf_tri,
+                                                 (float*)s->d_nodes, pint, pleaf, visits);
+    MRS_TRY_HIP(hipGetLastError());
+  }
+  s->builder = clustered ? MRS_BVH_PLOC : MRS_BVH_LBVH;
   if (n >= 2) rc = collapse4(s, st, leaf_max, scratch, o_q0, o_q1, o_qc, o_is4, o_idx, o_sp4);
   // The scratch must outlive the kernels: wait, then free.
   MRS_TRY_HIP(hipStreamSynchronize(st));

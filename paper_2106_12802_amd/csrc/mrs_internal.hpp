@@ -127,8 +127,9 @@ struct mrs_scene {
   uint32_t count4 = 0;
   uint32_t root4 = 0;
   int32_t leaf_max = mrs::LEAF4_MAX;  // triangles per BVH4 leaf the build may group
-  uint32_t* d_morton = nullptr;     // sorted codes
-  uint32_t* d_leaf_prim = nullptr;  // sorted primitive ids
+  int32_t builder = MRS_BVH_LBVH;     // the builder that made the binary tree
+  uint32_t* d_morton = nullptr;     // Morton codes in leaf order
+  uint32_t* d_leaf_prim = nullptr;  // primitive ids in leaf order
   mrs::DevMaterial* d_mats = nullptr;
   mrs::DevLight* d_lights = nullptr;
   mrs::SceneView view{};
@@ -137,7 +138,7 @@ struct mrs_scene {
 
 namespace mrs {
 // lbvh.hip
-mrs_status lbvh_build(mrs_scene* s, hipStream_t st, int leaf_max);
+mrs_status lbvh_build(mrs_scene* s, hipStream_t st, int leaf_max, int builder);
 // trace.hip
 struct RenderArgs {
   int32_t W, H, spp, max_depth, rr_start;

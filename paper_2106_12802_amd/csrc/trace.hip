@@ -1278,7 +1278,7 @@ std::map<hipStream_t, Workspace*> g_stream_ws;
 hipStream_t g_sub[MAX_SUB] = {};
 int g_nsub = 0;
 unsigned long long* g_stats = nullptr;  // device counters shared by every stream
-mrs_tuning g_tune = {1 << 23, 4096, 0, LEAF4_MAX, 3, 3};
+mrs_tuning g_tune = {1 << 23, 4096, 0, LEAF4_MAX, 3, 3, MRS_BVH_PLOC};
 std::atomic<bool> g_count_work{false};
 
 template <typename T>
@@ -1824,6 +1824,8 @@ mrs_status set_tuning(const mrs_tuning* t) {
     return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_set_tuning: streams must be in [1, 4]");
   if (t->tail_bounce < 1 || t->tail_bounce > 65)
     return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_set_tuning: tail_bounce must be in [1, 65]");
+  if (t->bvh_builder != MRS_BVH_LBVH && t->bvh_builder != MRS_BVH_PLOC)
+    return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_set_tuning: bvh_builder must be 0 or 1");
   std::lock_guard<std::mutex> lk(g_mu);
   g_tune = *t;
   return MRS_OK;

@@ -70,6 +70,13 @@ class GpuScene:
                                       C.byref(root)))
         return nodes, leaf, morton, root.value & 0xFFFFFFFF
 
+    @property
+    def bvh_builder(self):
+        """"lbvh" or "ploc": the builder that made this scene's BVH."""
+        b = C.c_int32()
+        L.check(L.lib().mrs_scene_bvh_builder(self.handle, C.byref(b)))
+        return {v: k for k, v in BVH_BUILDERS.items()}[b.value]
+
     def bvh4(self):
         """(nodes [count, 32] float32, root ref, leaf_max) of the four-wide BVH."""
         count, root, lmax = C.c_int32(), C.c_uint32(), C.c_int32()
@@ -147,7 +154,9 @@ def profile_read():
     return {names[i]: (float(ms[i]), int(n[i])) for i in range(L.NUM_KERNEL_IDS) if n[i]}
 
 
-TUNING_KEYS = ("chunk_paths", "trace_blocks", "schedule", "bvh_leaf_max", "streams", "tail_bounce")
+TUNING_KEYS = ("chunk_paths", "trace_blocks", "schedule", "bvh_leaf_max", "streams", "tail_bounce",
+               "bvh_builder")
+BVH_BUILDERS = {"lbvh": 0, "ploc": 1}
 
 
 def get_tuning():
@@ -157,10 +166,14 @@ def get_tuning():
 
 
 def set_tuning(chunk_paths=None, trace_blocks=None, schedule=None, bvh_leaf_max=None,
-               streams=None, tail_bounce=None):
+               streams=None, tail_bounce=None, bvh_builder=None):
+    """bvh_builder: 0 / "lbvh" (Karras) or 1 / "ploc" (clustering, the default)."""
     cur = get_tuning()
+    if isinstance(bvh_builder, str):
+        bvh_builder = BVH_BUILDERS[bvh_builder]
     new = dict(chunk_paths=chunk_paths, trace_blocks=trace_blocks, schedule=schedule,
-               bvh_leaf_max=bvh_leaf_max, streams=streams, tail_bounce=tail_bounce)
+               bvh_leaf_max=bvh_leaf_max, streams=streams, tail_bounce=tail_bounce,
+               bvh_builder=bvh_builder)
     t = L.Tuning()
     for k in TUNING_KEYS:
         setattr(t, k, int(new[k] if new[k] is not None else cur[k]))

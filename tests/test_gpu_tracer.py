@@ -68,7 +68,18 @@ def _check_lbvh(gs, scene):
     n = scene.num_tris
     assert sorted(leaf.tolist()) == list(range(n))
     keys = (morton.astype(np.uint64) << np.uint64(32)) | leaf.astype(np.uint64)
-    assert np.all(keys[1:] > keys[:-1])
+    if gs.bvh_builder == "lbvh":  # leaves in Morton order
+        assert np.all(keys[1:] > keys[:-1])
+    else:  # leaves depth first: the same keys, each once
+        assert np.all(np.diff(np.sort(keys)) > 0)
+    if n >= 2:  # each node's leaf range is its left range followed by its right range
+        refs_u = nodes[:, 12:16].copy().view(np.uint32)
+
+        def rng(r):
+            return (r & 0x7FFFFFFF,) * 2 if r & 0x80000000 else tuple(refs_u[r, 2:4])
+        for i in range(n - 1):
+            a, b = rng(int(refs_u[i, 0])), rng(int(refs_u[i, 1]))
+            assert a[0] == refs_u[i, 2] and a[1] + 1 == b[0] and b[1] == refs_u[i, 3], i
     if n < 2:
         return
     refs = nodes[:, 12:14].copy().view(np.uint32)
@@ -169,12 +180,64 @@ def _check_bvh4(gs, scene):
     lambda: S.cornell(1),
     lambda: S.procedural(7, spheres=((2, 4),), n_boxes=8, n_lights=2),
 ])
-def test_lbvh_invariants(mrs, maker):
+@pytest.mark.parametrize("builder", ["lbvh", "ploc"])
+def test_lbvh_invariants(mrs, maker, builder):
     scene = maker()
-    _log("lbvh", scene.name, scene.num_tris)
-    gs = mrs.GpuScene(scene)
+    _log("bvh", builder, scene.name, scene.num_tris)
+    old = mrs.get_tuning()
+    try:
+        mrs.set_tuning(bvh_builder=builder)
+        gs = mrs.GpuScene(scene)
+    finally:
+        mrs.set_tuning(**old)
+    assert gs.bvh_builder == (builder if scene.num_tris >= 2 else "lbvh")
     _check_lbvh(gs, scene)
     _check_bvh4(gs, scene)
+
+
+@pytest.mark.parametrize("maker", [
+    lambda: S.random_soup(4, 20000),
+    lambda: S.procedural(7, spheres=((2, 4),), n_boxes=8, n_lights=2),
+])
+def test_bvh_builders_give_identical_results(mrs, maker):
+    """The clustered and the Morton-split BVH give bitwise the same closest hits and
+    renders (conservative culling, ties to the smaller primitive id)."""
+    import torch
+    scene = maker()
+    _log("builders", scene.name, scene.num_tris)
+    old = mrs.get_tuning()
+    gs = {}
+    try:
+        for b in ("lbvh", "ploc"):
+            mrs.set_tuning(bvh_builder=b)
+            gs[b] = mrs.GpuScene(scene)
+            assert gs[b].bvh_builder == b
+    finally:
+        mrs.set_tuning(**old)
+    o, d = S.random_rays(9, 4000)
+    hits = [gs[b].closest_hit(o, d) for b in ("lbvh", "ploc")]
+    for x, y in zip(*hits):
+        assert np.array_equal(x, y)
+    imgs = [mrs.render(gs[b], 96, 64, 4, 8, 21) for b in ("lbvh", "ploc")]
+    torch.cuda.synchronize()
+    assert torch.equal(imgs[0][0], imgs[1][0]) and torch.equal(imgs[0][1], imgs[1][1])
+
+
+def test_ploc_identical_boxes_stay_shallow(mrs):
+    """Many identical triangles (every candidate cost ties): the clustering pairs
+    neighbours, so the tree is balanced rather than a chain (no fallback)."""
+    tri = np.tile(np.array([[[0, 0, 0], [1, 0, 0], [0, 1, 0]]], np.float32), (1000, 1, 1))
+    b = S._Builder()
+    m = b.material(S.LAMBERT, (0.5, 0.5, 0.5))
+    b.add_tris(list(tri), m)
+    scene = b.build((0, 0, 0), S.Camera((0.3, 0.3, -3), (0.3, 0.3, 0)), "identical")
+    gs = mrs.GpuScene(scene)
+    assert gs.bvh_builder == "ploc"
+    _check_lbvh(gs, scene)
+    o = np.tile(np.array([[0.25, 0.25, -1.0]], np.float32), (8, 1))
+    d = np.tile(np.array([[0.0, 0.0, 1.0]], np.float32), (8, 1))
+    t, p, _ = gs.closest_hit(o, d)
+    assert np.all(p == 0) and np.allclose(t, 1.0)  # equal t: the smallest primitive id
 
 
 @pytest.mark.parametrize("leaf_max", [1, 2, 3])
