@@ -125,7 +125,7 @@ mrs_status mrs_scene_destroy(mrs_scene* scene);
  *                 lengths, leaf-to-root box refit with atomic visit counters;
  *   MRS_BVH_PLOC  (default) agglomerative clustering over the same Morton
  *                 order (Meister & Bittner, TVCG 2018): nearest neighbours by
- *                 union surface area within 4 places, mutual pairs merge,
+ *                 union surface area within 12 places, mutual pairs merge,
  *                 until one cluster is left; laid out depth first.  A tree
  *                 deeper than 64 levels falls back to MRS_BVH_LBVH.
  * Then either is collapsed into the four-wide BVH that rendering traverses.
