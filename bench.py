@@ -60,12 +60,17 @@ def rdg_flop(H, W, scale=4):
     return 2 * mac
 
 
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2106_12802_amd", "csrc", "trace.hip")
+# the traversal kernel and the BVH builder (the tree decides what a launch reads)
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2106_12802_amd", "csrc", f)
+                  for f in ("trace.hip", "lbvh.hip")]
 
 
 def kernel_source_hash() -> str:
-    with open(KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def read_traffic():
@@ -77,7 +82,7 @@ def read_traffic():
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+    if vals.get("kernel_sources_sha256_16") != kernel_source_hash():
         return None  # the kernel changed since the counters were taken
     try:
         return float(vals["hbm_bytes_per_launch"])
@@ -162,7 +167,7 @@ def pmc_summary(fetch_path, write_path, out_path):
         f"extend_fetch_kib_per_dispatch = {f_kib:.1f}",
         f"extend_write_kib_per_dispatch = {w_kib:.1f}",
         f"hbm_bytes_per_launch = {hbm:.0f}",
-        f"kernel_source_sha256_16 = {kernel_source_hash()}",
+        f"kernel_sources_sha256_16 = {kernel_source_hash()}",
     ]
     with open(out_path, "w") as f:
         f.write("\n".join(lines) + "\n")
