@@ -283,7 +283,7 @@ typedef struct mrs_tuning {
   int32_t trace_blocks; /* grid size of traversal kernels (default 4096) */
   int32_t schedule;     /* traversal queue: 0 grid-stride (default), 1 per-wave
                            dynamic fetch from a device counter */
-  int32_t bvh_leaf_max; /* triangles a BVH4 leaf may group, 1..4 (default 4);
+  int32_t bvh_leaf_max; /* triangles a BVH4 leaf may group, 1..4 (default 3);
                            applies to scenes built afterwards */
   int32_t streams;      /* 1..4 (default 3): a render's resident paths are cut into
                            this many sub-chunks, traced concurrently on internal

@@ -1278,7 +1278,8 @@ std::map<hipStream_t, Workspace*> g_stream_ws;
 hipStream_t g_sub[MAX_SUB] = {};
 int g_nsub = 0;
 unsigned long long* g_stats = nullptr;  // device counters shared by every stream
-mrs_tuning g_tune = {1 << 23, 4096, 0, LEAF4_MAX, 3, 3, MRS_BVH_PLOC};
+// defaults: the fastest hybrid 720p frame measured with the clustered BVH
+mrs_tuning g_tune = {1 << 23, 4096, 0, 3, 3, 3, MRS_BVH_PLOC};
 std::atomic<bool> g_count_work{false};
 
 template <typename T>

@@ -240,7 +240,7 @@ def test_ploc_identical_boxes_stay_shallow(mrs):
     assert np.all(p == 0) and np.allclose(t, 1.0)  # equal t: the smallest primitive id
 
 
-@pytest.mark.parametrize("leaf_max", [1, 2, 3])
+@pytest.mark.parametrize("leaf_max", [1, 2, 4])
 def test_bvh4_leaf_grouping_and_same_hits(mrs, leaf_max):
     """Any leaf grouping gives a valid tree and bitwise the same closest hits."""
     scene = S.random_soup(5, 3000)
