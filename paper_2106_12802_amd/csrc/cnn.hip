@@ -287,9 +287,16 @@ __global__ __launch_bounds__(32 * TH) void k_conv3_lds(ConvArgs p, int cout_p, i
   const int b = blockIdx.z / nsplit, part = blockIdx.z - b * nsplit;
   const int nper = cout_p / nsplit;  // output channels of this block (a multiple of NG)
   const int nchunk = p.cin_p / CINP;
-  // Loads are issued three at a time before their LDS stores, so that their
-  // latencies overlap instead of adding up.
+  // Loads are issued in batches (C3_BATCH_T tile chunks, C3_BATCH_W weight
+  // chunks per thread) before their LDS stores, so that their latencies
+  // overlap instead of adding up.
   constexpr int TCH = TILE * (CINP / 8), WCH = NG * (KP / 8);
+  // A block whose LDS leaves room for no second block on its CU (more than
+  // 80 KB) has 2 waves per SIMD, so registers are plentiful: 6 tile and 9
+  // weight chunks in flight per thread; otherwise 3 and 3.
+  constexpr int LDS_BYTES = 2 * (TILE * PITCH + (KP / 8) * WPITCH * 8);
+  constexpr int C3_BATCH_T = LDS_BYTES > 80 * 1024 ? 6 : 3;
+  constexpr int C3_BATCH_W = LDS_BYTES > 80 * 1024 ? 9 : 3;
   for (int n0 = part * nper; n0 < (part + 1) * nper; n0 += NG) {
     f32x4 acc[2][NT];
 #pragma unroll
@@ -310,12 +317,12 @@ __global__ __launch_bounds__(32 * TH) void k_conv3_lds(ConvArgs p, int cout_p, i
           const int px = i / (CINP / 8), c = (i - px * (CINP / 8)) * 8;
           if (i < TCH) *reinterpret_cast<bf16x8*>(tile + px * PITCH + c) = v;
         };
-        for (int i = tid; i < TCH; i += 3 * THREADS) {
-          const bf16x8 v0 = tile_load(i), v1 = tile_load(i + THREADS),
-                       v2 = tile_load(i + 2 * THREADS);
-          tile_store(i, v0);
-          tile_store(i + THREADS, v1);
-          tile_store(i + 2 * THREADS, v2);
+        for (int i = tid; i < TCH; i += C3_BATCH_T * THREADS) {
+          bf16x8 v[C3_BATCH_T];
+#pragma unroll
+          for (int u = 0; u < C3_BATCH_T; ++u) v[u] = tile_load(i + u * THREADS);
+#pragma unroll
+          for (int u = 0; u < C3_BATCH_T; ++u) tile_store(i + u * THREADS, v[u]);
         }
       }
       // local k = tap CINP + c holds packed column tap cin_p + cbase + c
@@ -330,11 +337,12 @@ __global__ __launch_bounds__(32 * TH) void k_conv3_lds(ConvArgs p, int cout_p, i
         const int n = i / (KP / 8), kc = i - n * (KP / 8);
         if (i < WCH) *reinterpret_cast<uint4*>(wts + (kc * WPITCH + n) * 8) = v;
       };
-      for (int i = tid; i < WCH; i += 3 * THREADS) {
-        const uint4 v0 = w_load(i), v1 = w_load(i + THREADS), v2 = w_load(i + 2 * THREADS);
-        w_store(i, v0);
-        w_store(i + THREADS, v1);
-        w_store(i + 2 * THREADS, v2);
+      for (int i = tid; i < WCH; i += C3_BATCH_W * THREADS) {
+        uint4 v[C3_BATCH_W];
+#pragma unroll
+        for (int u = 0; u < C3_BATCH_W; ++u) v[u] = w_load(i + u * THREADS);
+#pragma unroll
+        for (int u = 0; u < C3_BATCH_W; ++u) w_store(i + u * THREADS, v[u]);
       }
       __syncthreads();
       for (int ks = 0; ks < KP; ks += 32) {
