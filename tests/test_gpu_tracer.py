@@ -198,6 +198,8 @@ def test_lbvh_invariants(mrs, maker, builder):
 @pytest.mark.parametrize("maker", [
     lambda: S.random_soup(4, 20000),
     lambda: S.procedural(7, spheres=((2, 4),), n_boxes=8, n_lights=2),
+    lambda: S.procedural_sized(510, 200000),
+    lambda: S.random_soup(6, 3),
 ])
 def test_bvh_builders_give_identical_results(mrs, maker):
     """The clustered and the Morton-split BVH give bitwise the same closest hits and
