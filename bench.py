@@ -196,8 +196,9 @@ def stats_summary(prof_dir, out_path):
 
     lines = ["# 720p hybrid frame (procedural 101,446 triangles, textured; HRLS 1280x720@4 + LRHS "
              "320x180@64 as one two-job batch, depth 8; BF16 fusion network): 1 counting frame "
-             "(k_*<true>) + 1 warmup + 5 timed frames (k_extend<false>: exactly the launches "
-             "whose average bench.py reports)",
+             "(k_*<true>) + 1 warmup + 5 timed (pipelined) + 5 per-kernel-breakdown frames, "
+             "the network 5 more times alone (k_extend<false>: the launches of the frames "
+             "whose extend average bench.py reports, and of their like)",
              f"# command (from the repository root): {STATS_CMD}",
              "#   then: python bench.py --stats-summary gpurun_out/prof",
              "# rocprofv3 kernel stats: name | calls | total ms | average us | percent", ""]
@@ -550,7 +551,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--equal-psnr-scenes", type=int, default=3,
                     help="held-out scenes in the equal-PSNR comparison (0: skip it)")
@@ -670,19 +671,29 @@ def main():
     torch.cuda.synchronize()
     log(f"[bench] warmup done ({args.warmup} frames)")
 
+    # timed frames, pipelined: HIP events around the roofline kernel's launches only
+    R.profile_select(["extend"])
     R.profile_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     frames(0, args.steps)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    prof = R.profile_read()
+    prof_ext = R.profile_read()
     R.profile_enable(False)
+    R.profile_select(None)
     ms_per_step = dt * 1e3 / args.steps
     value = paths * args.steps / dt / 1e6
     log(f"[bench] {args.steps} frames: {ms_per_step:.3f} ms/frame, {value:.1f} Mpaths/s")
-    # the same frames one at a time (each frame's fusion after its render): the
-    # latency of one frame, for comparison, not timed above
+    # the same frames one at a time with every kernel's events, for the
+    # per-kernel breakdown (not timed)
+    R.profile_enable(True)
+    for i in range(args.steps):
+        step(i)
+    prof = R.profile_read()
+    R.profile_enable(False)
+    # the same frames one at a time (each frame's fusion after its render), no
+    # events: the latency of one frame, for comparison
     ms_unpiped = None
     if not args.no_two_calls:
         torch.cuda.synchronize()
@@ -704,7 +715,7 @@ def main():
         ms_calls = (time.perf_counter() - t1) * 1e3 / args.steps
         log(f"[bench] same frames as two render calls: {ms_calls:.3f} ms/frame")
 
-    ext_ms, ext_n = prof.get("extend", (0.0, 0))
+    ext_ms, ext_n = prof_ext.get("extend", (0.0, 0))
     ext_rays = max(work["rays"] - work["tail_rays"], 1)  # rays traced by k_extend itself
     flop_frame = (FLOP_PER_VISIT * work["extend_visits"] + FLOP_PER_TEST * work["extend_tests"]
                   + FLOP_PER_RAY * ext_rays)

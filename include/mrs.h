@@ -271,9 +271,13 @@ mrs_status mrs_set_count_work(int32_t on);
  * 13 path tail (bounces from mrs_tuning.tail_bounce on), 14..15 reserved.
  * mrs_profile_enable(1) clears the totals and starts recording;
  * mrs_profile_read synchronises and returns, per id, the summed milliseconds
- * and the launch count of the launches recorded so far. */
+ * and the launch count of the launches recorded so far.
+ * mrs_profile_select(mask) limits the recording to the ids whose bit is set
+ * in mask (default: all), so that a timed run pays for the events of the
+ * kernels it reports only. */
 #define MRS_NUM_KERNEL_IDS 16
 mrs_status mrs_profile_enable(int32_t on);
+mrs_status mrs_profile_select(uint32_t mask);
 mrs_status mrs_profile_read(double ms_out[MRS_NUM_KERNEL_IDS],
                             int64_t launches_out[MRS_NUM_KERNEL_IDS]);
 

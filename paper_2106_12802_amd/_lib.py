@@ -117,6 +117,7 @@ def lib():
         "mrs_set_count_work": ([I32], I32),
         "mrs_profile_enable": ([I32], I32),
         "mrs_profile_read": ([P, P], I32),
+        "mrs_profile_select": ([C.c_uint32], I32),
         "mrs_net_num_params": ([], C.c_int64),
         "mrs_net_create": ([C.POINTER(P)], I32),
         "mrs_net_destroy": ([P], I32),
@@ -174,6 +175,7 @@ def exported_symbols():
         "mrs_debug_bvh4", "mrs_net_arch_num_params", "mrs_net_create_arch",
         "mrs_net_loss_grad_ex", "mrs_train_step_ex", "mrs_net_backward",
         "mrs_batch_render_begin", "mrs_batch_render_end", "mrs_scene_bvh_builder",
+        "mrs_profile_select",
     ]
 
 

@@ -433,6 +433,7 @@ mrs_status mrs_set_count_work(int32_t on) {
 }
 
 mrs_status mrs_profile_enable(int32_t on) { return prof_enable(on != 0); }
+mrs_status mrs_profile_select(uint32_t mask) { return prof_select(mask); }
 
 mrs_status mrs_profile_read(double* ms, int64_t* launches) {
   if (!ms || !launches) return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_profile_read: NULL output");

@@ -194,5 +194,6 @@ enum KernelId {
 void prof_begin(int id, hipStream_t st);
 void prof_end(int id, hipStream_t st);
 mrs_status prof_enable(bool on);
+mrs_status prof_select(uint32_t mask);
 mrs_status prof_read(double* ms, int64_t* launches);
 }  // namespace mrs

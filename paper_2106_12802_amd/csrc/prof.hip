@@ -13,6 +13,7 @@ struct Pending {
 };
 
 bool g_on = false;
+uint32_t g_mask = 0xffffffffu;
 std::vector<Pending> g_pending;
 std::vector<hipEvent_t> g_free;
 hipEvent_t g_open[MRS_NUM_KERNEL_IDS] = {};
@@ -51,7 +52,7 @@ void drain() {
 }  // namespace
 
 void prof_begin(int id, hipStream_t st) {
-  if (!g_on || id < 0 || id >= MRS_NUM_KERNEL_IDS) return;
+  if (!g_on || id < 0 || id >= MRS_NUM_KERNEL_IDS || !((g_mask >> id) & 1u)) return;
   hipEvent_t e = take();
   if (e && hipEventRecord(e, st) == hipSuccess) {
     g_open[id] = e;
@@ -90,6 +91,11 @@ mrs_status prof_enable(bool on) {
     g_open[i] = nullptr;
   }
   g_on = on;
+  return MRS_OK;
+}
+
+mrs_status prof_select(uint32_t mask) {
+  g_mask = mask;
   return MRS_OK;
 }
 

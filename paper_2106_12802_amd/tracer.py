@@ -145,6 +145,17 @@ def profile_enable(on: bool = True):
     L.check(L.lib().mrs_profile_enable(int(bool(on))))
 
 
+def profile_select(names=None):
+    """Record only these kernels (names of profile_read's keys); None: all."""
+    if names is None:
+        mask = 0xFFFFFFFF
+    else:
+        mask = 0
+        for n in names:
+            mask |= 1 << L.KERNEL_NAMES.index(n)
+    L.check(L.lib().mrs_profile_select(mask))
+
+
 def profile_read():
     """{kernel name: (total ms, launches)} for the launches recorded since profile_enable."""
     ms = np.zeros(L.NUM_KERNEL_IDS, np.float64)
