@@ -308,3 +308,30 @@ def test_pipelined_frames_equal_single_frames(torch_cuda):
             assert torch.equal(a, r), (net is None, k)
         fr.render_stream([])
         fr.close()
+
+
+def test_profile_records_selected_kernels(torch_cuda):
+    """HIP-event kernel timing: every launch by default, only the selected kernels
+    after profile_select; the counts follow the launch structure of a render."""
+    import paper_2106_12802_amd as mrs
+    from paper_2106_12802_amd import tracer as R
+    torch = torch_cuda
+    gs = mrs.GpuScene(S.procedural(7, spheres=((2, 4),), n_boxes=5, n_lights=2))
+    try:
+        R.profile_select(None)
+        R.profile_enable(True)
+        mrs.render(gs, 128, 96, 4, 8, 3)
+        everything = R.profile_read()
+        R.profile_select(["extend"])
+        R.profile_enable(True)
+        mrs.render(gs, 128, 96, 4, 8, 3)
+        only = R.profile_read()
+    finally:
+        R.profile_enable(False)
+        R.profile_select(None)
+    torch.cuda.synchronize()
+    assert set(only) == {"extend"}
+    assert only["extend"][1] == everything["extend"][1] > 0
+    assert {"generate", "extend", "shade", "shadow", "accumulate", "resolve"} <= set(everything)
+    with pytest.raises(ValueError):
+        R.profile_select(["no_such_kernel"])
