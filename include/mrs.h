@@ -127,7 +127,8 @@ mrs_status mrs_scene_destroy(mrs_scene* scene);
  *                 order (Meister & Bittner, TVCG 2018): nearest neighbours by
  *                 union surface area within 12 places, mutual pairs merge,
  *                 until one cluster is left; laid out depth first.  A tree
- *                 deeper than 64 levels falls back to MRS_BVH_LBVH.
+ *                 deeper than 64 levels, or one that needs more than 256
+ *                 clustering rounds (chains), falls back to MRS_BVH_LBVH.
  * Then either is collapsed into the four-wide BVH that rendering traverses.
  * Every builder gives the same closest hits and images, bitwise (traversal
  * culls conservatively and breaks ties by primitive id); they differ in speed.

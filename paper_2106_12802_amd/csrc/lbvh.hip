@@ -44,6 +44,7 @@ constexpr int RS_THREADS = 256;
 constexpr int RS_ITEMS = 16;
 constexpr int RS_TILE = RS_THREADS * RS_ITEMS;  // keys per block
 constexpr int PLOC_RADIUS = 12;  // clusters searched on each side (fastest frame of 2..24)
+constexpr int PLOC_MAX_ROUNDS = 256;
 
 __device__ __forceinline__ f3 centroid(const float4* tri, int i) {
   f3 a = xyz(tri[3 * i]), b = xyz(tri[3 * i + 1]), c = xyz(tri[3 * i + 2]);
@@ -464,6 +465,7 @@ __global__ __launch_bounds__(256) void k_ploc_sizes(int n, const uint32_t* __res
                                                     const uint32_t* __restrict__ par_leaf,
                                                     uint32_t* __restrict__ sz2,
                                                     uint32_t* __restrict__ visits,
+                                                    uint32_t* __restrict__ deep,
                                                     uint32_t* __restrict__ bad) {
   const int k = blockIdx.x * 256 + threadIdx.x;
   if (k >= n) return;
@@ -472,7 +474,10 @@ __global__ __launch_bounds__(256) void k_ploc_sizes(int n, const uint32_t* __res
   for (int guard = 0; guard < 4 * MAX_STACK; ++guard) {
     if (x == NO_PARENT) return;
     const uint32_t p = x >> 1, side = x & 1u;
-    if (p >= (uint32_t)(n - 1)) break;  // cannot happen for a tree
+    if (p >= (uint32_t)(n - 1)) {  // cannot happen for a tree
+      atomicOr(bad, 1u);
+      return;
+    }
     __hip_atomic_store(sz2 + 2 * p + side, size, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const uint32_t prev =
         __hip_atomic_fetch_add(visits + p, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
@@ -481,7 +486,7 @@ __global__ __launch_bounds__(256) void k_ploc_sizes(int n, const uint32_t* __res
                               __HIP_MEMORY_SCOPE_AGENT);
     x = par_int[p];
   }
-  atomicOr(bad, 1u);
+  atomicMax(deep, (uint32_t)(4 * MAX_STACK));  // deeper than the walk's bound: too deep
 }
 
 // Depth-first layout, each node and leaf walking up to the root: a left child
@@ -501,8 +506,8 @@ __global__ __launch_bounds__(256) void k_ploc_order(int n, int nint,
   uint32_t x = i < nint ? par_int[i] : par_leaf[i - nint];
   uint32_t pre = 0, first = 0, depth = 0;
   for (; x != NO_PARENT; ++depth) {
-    if (depth >= 4 * MAX_STACK) {
-      atomicOr(bad, 1u);
+    if (depth >= 4 * MAX_STACK) {  // too deep (the caller falls back)
+      atomicMax(depth_max, depth);
       return;
     }
     const uint32_t p = x >> 1;
@@ -830,7 +835,8 @@ mrs_status ploc_build(mrs_scene* s, hipStream_t st, const uint32_t* code, const 
     int cur = 0;
     uint32_t m = (uint32_t)n;
     for (int round = 0; m > 1; ++round) {
-      if (round > 2 * n) return fail(MRS_ERR_DEVICE, "mrs_build_bvh: clustering does not end");
+      // a healthy build takes 50-70 rounds; this many means chains (deep trees)
+      if (round >= PLOC_MAX_ROUNDS) return MRS_OK;  // the caller falls back
       const int mb = cdiv(m, 256);
       k_ploc_nn<<<mb, 256, 0, st>>>((int)m, radius, clo[cur], chi[cur], nn);
       k_ploc_merge<<<mb, 256, 0, st>>>((int)m, nint, nn, cref[cur], clo[cur], chi[cur], tnodes,
@@ -858,7 +864,7 @@ mrs_status ploc_build(mrs_scene* s, hipStream_t st, const uint32_t* code, const 
     k_fill_u32<<<nb, 256, 0, st>>>(par_leaf, n, NO_PARENT);
     k_fill_u32<<<cdiv(nint, 256), 256, 0, st>>>(visits, nint, 0u);
     k_ploc_parents<<<cdiv(nint, 256), 256, 0, st>>>(nint, tnodes, par_int, par_leaf, n);
-    k_ploc_sizes<<<nb, 256, 0, st>>>(n, par_int, par_leaf, sz2, visits, ctr + 3);
+    k_ploc_sizes<<<nb, 256, 0, st>>>(n, par_int, par_leaf, sz2, visits, ctr + 2, ctr + 3);
     k_ploc_order<<<cdiv(nint + n, 256), 256, 0, st>>>(n, nint, par_int, par_leaf, sz2, pre_int,
                                                       first_int, first_leaf, ctr + 2, ctr + 3);
     MRS_TRY_HIP(hipGetLastError());

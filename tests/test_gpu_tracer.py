@@ -521,3 +521,22 @@ def test_unbiased_vs_oracle_high_spp(mrs, oracle_tracer, torch_cuda):
              f"{sq_all[:, bad[0], 0].tolist()}")
     assert abs(g_mean.mean() - ref_mean.mean()) <= 3 * img_sigma
     assert frac_out <= 0.01
+
+
+def test_ploc_too_deep_falls_back_to_lbvh(mrs):
+    """Concentric triangles of growing size: the clustering can only chain them
+    (one merge per round), a tree deeper than the traversal stack allows, so the
+    build falls back to the Morton-split tree, with the same hits."""
+    b = S._Builder()
+    m = b.material(S.LAMBERT, (0.5, 0.5, 0.5))
+    base = np.array([[-1.0, -1.0, 0.0], [1.0, -1.0, 0.0], [0.0, 1.0, 0.0]])
+    tris = [base * 1.5 ** k + np.array([0.0, 0.0, 0.01 * k]) for k in range(100)]
+    b.add_tris(tris, m)
+    scene = b.build((0, 0, 0), S.Camera((0, 0, -5), (0, 0, 0)), "concentric")
+    gs = mrs.GpuScene(scene)
+    assert gs.bvh_builder == "lbvh"
+    _check_lbvh(gs, scene)
+    o = np.tile(np.array([[0.0, -0.2, -1.0]], np.float32), (4, 1))
+    d = np.tile(np.array([[0.0, 0.0, 1.0]], np.float32), (4, 1))
+    t, p, _ = gs.closest_hit(o, d)
+    assert np.all(p == 0) and np.allclose(t, 1.0)  # the smallest (nearest) triangle
