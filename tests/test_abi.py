@@ -129,3 +129,26 @@ def test_render_opts_layout_matches_the_header():
                 setattr(bad, k, v)
         assert L.mrs_render_ex(None, 4, 4, 1, 1, 0, C.byref(bad), None, None) == 1
         assert b"lens_radius" in L.mrs_last_error() or b"cam_motion" in L.mrs_last_error()
+
+
+def test_tuning_bvh_builder_by_name():
+    """set_tuning takes the builder by name or number; the library keeps it."""
+    from paper_2106_12802_amd import tracer as R
+    old = R.get_tuning()
+    try:
+        R.set_tuning(bvh_builder="lbvh")
+        assert R.get_tuning()["bvh_builder"] == 0
+        R.set_tuning(bvh_builder=1)
+        assert R.get_tuning()["bvh_builder"] == 1
+        with pytest.raises(KeyError):
+            R.set_tuning(bvh_builder="sah")
+        with pytest.raises(_lib_error()):
+            R.set_tuning(bvh_builder=7)
+    finally:
+        R.set_tuning(**old)
+    assert R.get_tuning() == old
+
+
+def _lib_error():
+    from paper_2106_12802_amd._lib import MrsError
+    return MrsError
