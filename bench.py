@@ -250,7 +250,7 @@ def equal_psnr_block(net, n_scenes, log):
     for name, scene in specs:
         gs = R.GpuScene(scene)
         r = HY.evaluate_scene(gs, net, HRLS[0], HRLS[1], seed=len(rows),
-                              plain_spp=(4, 8, 16, 32, 64, 128, 256), reps=2)
+                              plain_spp=(4, 8, 16, 32, 64, 128, 256, 512), reps=2)
         gs.close()
         row = {"scene": name, "triangles": scene.num_tris,
                "psnr_hybrid": round(r["hybrid"]["psnr"], 3), "ms_hybrid": round(r["hybrid"]["ms"], 3),
@@ -269,7 +269,7 @@ def equal_psnr_block(net, n_scenes, log):
             f"ratio {row['ratio']}")
     ratios = [r["ratio"] for r in rows if r["ratio"] is not None]
     return {"reference": "1024 spp, independent seed, FP64 pixel sums",
-            "protocol": "PSNR_N of plain renders N in 4..256 spp interpolated linearly in log2 N; "
+            "protocol": "PSNR_N of plain renders N in 4..512 spp interpolated linearly in log2 N; "
                         "time interpolated linearly in N; ratio = hybrid ms / plain ms at equal PSNR",
             "mean_ratio": round(sum(ratios) / len(ratios), 4) if ratios else None,
             "scenes": rows}

@@ -384,6 +384,8 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--out", default="fusion_checkpoint.bin", help="resumable checkpoint")
     ap.add_argument("--weights-out", default=None, help="weights-only file for inference")
+    ap.add_argument("--init-weights", default=None,
+                    help="start from these weights (fine-tuning) instead of a fresh init")
     ap.add_argument("--eval-scenes", type=int, default=4)
     ap.add_argument("--eval-size", default="1280x720")
     args = ap.parse_args(argv)
@@ -391,6 +393,8 @@ def main(argv=None):
     torch.cuda.set_device(0)
     data = build_dataset(n_scenes=args.scenes, windows=args.windows, log=log)
     net = FusionNet(seed=args.seed)
+    if args.init_weights:
+        net.load_weights(args.init_weights)
     losses, done = train(net, data, args.steps, args.batch, args.lr, seed=args.seed, log=log,
                          time_limit=args.time_limit)
     net.save(args.out)
