@@ -384,6 +384,10 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--out", default="fusion_checkpoint.bin", help="resumable checkpoint")
     ap.add_argument("--weights-out", default=None, help="weights-only file for inference")
+    ap.add_argument("--arch", default="res16", choices=("res16", "rdg"),
+                    help="network: the configured 16-block trunk or the paper's (x4)")
+    ap.add_argument("--loss", default="l1", choices=("l1", "robust"))
+    ap.add_argument("--optimizer", default="adam", choices=("adam", "sgd"))
     ap.add_argument("--init-weights", default=None,
                     help="start from these weights (fine-tuning) instead of a fresh init")
     ap.add_argument("--eval-scenes", type=int, default=4)
@@ -392,11 +396,11 @@ def main(argv=None):
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
     torch.cuda.set_device(0)
     data = build_dataset(n_scenes=args.scenes, windows=args.windows, log=log)
-    net = FusionNet(seed=args.seed)
+    net = FusionNet(seed=args.seed, arch=args.arch)
     if args.init_weights:
         net.load_weights(args.init_weights)
     losses, done = train(net, data, args.steps, args.batch, args.lr, seed=args.seed, log=log,
-                         time_limit=args.time_limit)
+                         time_limit=args.time_limit, loss=args.loss, optimizer=args.optimizer)
     net.save(args.out)
     if args.weights_out:
         net.save_weights(args.weights_out)
