@@ -42,6 +42,8 @@ FLOP_PER_TEST = 52
 FLOP_PER_RAY = 10
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "extend_procedural101k_720p_traffic.txt")
 WEIGHTS = os.path.join(ROOT, "paper_2106_12802_amd", "weights", "fusion_l1_textured.bin")
+# the paper's own network (x4), trained on the same synthetic pairs
+WEIGHTS_RDG = os.path.join(ROOT, "paper_2106_12802_amd", "weights", "fusion_rdg_l1.bin")
 PEAK_BF16_TFLOPS = 2500.0  # MI355X dense BF16 MFMA
 CNN_FLOP_720P = 175.7e9    # 87.85 GMAC per 720p frame
 # the paper's network on a 1024x1024 image, seconds (its runtime table; Titan Xp)
@@ -239,10 +241,16 @@ def cpu_baseline(scene, threads):
 
 
 def equal_psnr_block(net, n_scenes, log):
-    """Hybrid vs plain renders at equal PSNR on the bench scene and held-out scenes."""
+    """Hybrid vs plain renders at equal PSNR on the bench scene and held-out scenes;
+    the same frames with the paper's own network too when its trained weights exist."""
     from mrs_inputs import scenes as S
     from paper_2106_12802_amd import hybrid as HY
     from paper_2106_12802_amd import tracer as R
+    import paper_2106_12802_amd as mrs
+    extra = {}
+    if os.path.exists(WEIGHTS_RDG):
+        extra["paper_net"] = mrs.FusionNet(arch="rdg")
+        extra["paper_net"].load_weights(WEIGHTS_RDG)
     specs = [("bench", S.procedural(SCENE_SEED))]
     specs += [(f"heldout_{s}", S.procedural_sized(s, t))
               for s, t in S.training_scene_specs(200, n_scenes)]
@@ -250,7 +258,8 @@ def equal_psnr_block(net, n_scenes, log):
     for name, scene in specs:
         gs = R.GpuScene(scene)
         r = HY.evaluate_scene(gs, net, HRLS[0], HRLS[1], seed=len(rows),
-                              plain_spp=(4, 8, 16, 32, 64, 128, 256, 512), reps=2)
+                              plain_spp=(4, 8, 16, 32, 64, 128, 256, 512), reps=2,
+                              extra_nets=extra)
         gs.close()
         row = {"scene": name, "triangles": scene.num_tris,
                "psnr_hybrid": round(r["hybrid"]["psnr"], 3), "ms_hybrid": round(r["hybrid"]["ms"], 3),
@@ -263,12 +272,25 @@ def equal_psnr_block(net, n_scenes, log):
         row["ratio"] = None if eq is None else round(eq["ratio"], 4)
         p64 = [t for n, p, t in r["plain"] if n == 64][0]
         row["ratio_vs_plain64"] = round(r["hybrid"]["ms"] / p64, 4)
+        for k, v in r["extra"].items():
+            e = v["equal_psnr"]
+            row[k] = {"psnr_hybrid": round(v["psnr"], 3), "ms_hybrid": round(v["ms"], 3),
+                      "equal_psnr_spp": None if e is None else round(e["spp"], 2),
+                      "ratio": None if e is None else round(e["ratio"], 4)}
+            log(f"[bench] {name} with the paper's network: {row[k]}")
         rows.append(row)
         log(f"[bench] {name}: hybrid {row['psnr_hybrid']} dB in {row['ms_hybrid']} ms; "
             f"equal-PSNR plain spp {row['equal_psnr_spp']} ({row['plain_ms_at_equal_psnr']} ms), "
             f"ratio {row['ratio']}")
     ratios = [r["ratio"] for r in rows if r["ratio"] is not None]
+    for other in extra.values():
+        other.close()
+    extra_means = {}
+    for k in extra:
+        rk = [r[k]["ratio"] for r in rows if r[k]["ratio"] is not None]
+        extra_means[f"mean_ratio_{k}"] = round(sum(rk) / len(rk), 4) if rk else None
     return {"reference": "1024 spp, independent seed, FP64 pixel sums",
+            **extra_means,
             "protocol": "PSNR_N of plain renders N in 4..512 spp interpolated linearly in log2 N; "
                         "time interpolated linearly in N; ratio = hybrid ms / plain ms at equal PSNR",
             "mean_ratio": round(sum(ratios) / len(ratios), 4) if ratios else None,

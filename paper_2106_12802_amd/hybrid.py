@@ -337,8 +337,10 @@ def time_ms(fn, reps=3):
 
 
 def evaluate_scene(gs, net, W=1280, H=720, seed=0, plain_spp=(4, 8, 16, 32, 64, 128, 256),
-                   ref_spp=1024, reps=3):
-    """PSNR/time of the hybrid frame, its baselines and plain renders for one scene."""
+                   ref_spp=1024, reps=3, extra_nets=None):
+    """PSNR/time of the hybrid frame, its baselines and plain renders for one scene;
+    extra_nets {name: net}: the same frame with other networks, against the same
+    reference and plain renders (res["extra"][name])."""
     import torch
     ref = reference(gs, W, H, ref_spp, REF_SEED + seed)
     res = {}
@@ -362,6 +364,15 @@ def evaluate_scene(gs, net, W=1280, H=720, seed=0, plain_spp=(4, 8, 16, 32, 64, 
     res["equal_psnr"] = None if eq is None else {"spp": eq[0], "ms": eq[1],
                                                  "ratio": t_h / eq[1]}
     frame.close()
+    res["extra"] = {}
+    for name, other in (extra_nets or {}).items():
+        fr = HybridFrame(gs, other, W, H)
+        t_o = time_ms(lambda: fr.render(seed), reps)
+        p_o = image_metrics(fr.render(seed), ref)["psnr"]
+        eq_o = equal_psnr(p_o, plain)
+        res["extra"][name] = {"psnr": p_o, "ms": t_o, "equal_psnr": None if eq_o is None else
+                              {"spp": eq_o[0], "ms": eq_o[1], "ratio": t_o / eq_o[1]}}
+        fr.close()
     return res
 
 
