@@ -198,9 +198,9 @@ def stats_summary(prof_dir, out_path):
 
     lines = ["# 720p hybrid frame (procedural 101,446 triangles, textured; HRLS 1280x720@4 + LRHS "
              "320x180@64 as one two-job batch, depth 8; BF16 fusion network): 1 counting frame "
-             "(k_*<true>) + 1 warmup + 5 timed (pipelined) + 5 per-kernel-breakdown frames, "
-             "the network 5 more times alone (k_extend<false>: the launches of the frames "
-             "whose extend average bench.py reports, and of their like)",
+             "(k_*<true>) + 1 warmup + 5 timed frames, pipelined, then the network 5 times "
+             "alone (k_extend<false>: the launches of the warmup and timed frames, whose "
+             "extend average bench.py reports)",
              f"# command (from the repository root): {STATS_CMD}",
              "#   then: python bench.py --stats-summary gpurun_out/prof",
              "# rocprofv3 kernel stats: name | calls | total ms | average us | percent", ""]
@@ -580,8 +580,9 @@ def main():
     ap.add_argument("--batch-scenes", type=int, default=32,
                     help="scenes in the batched render+fuse measurement (0: skip it)")
     ap.add_argument("--no-two-calls", action="store_true",
-                    help="skip timing the frames as two separate render calls (profiling runs: "
-                         "every k_extend launch is then one of the batched frame's)")
+                    help="skip the comparison runs (one frame at a time, two separate render "
+                         "calls) and the per-kernel breakdown pass (profiling runs: every "
+                         "k_extend launch is then one of the timed kind)")
     ap.add_argument("--no-mis", action="store_true",
                     help="skip the multiple-importance-sampling comparison")
     ap.add_argument("--no-camera", action="store_true",
@@ -708,12 +709,15 @@ def main():
     value = paths * args.steps / dt / 1e6
     log(f"[bench] {args.steps} frames: {ms_per_step:.3f} ms/frame, {value:.1f} Mpaths/s")
     # the same frames one at a time with every kernel's events, for the
-    # per-kernel breakdown (not timed)
-    R.profile_enable(True)
-    for i in range(args.steps):
-        step(i)
-    prof = R.profile_read()
-    R.profile_enable(False)
+    # per-kernel breakdown (not timed; skipped with the comparison runs, so that a
+    # profiled run holds only the timed kind of launch)
+    prof = prof_ext
+    if not args.no_two_calls:
+        R.profile_enable(True)
+        for i in range(args.steps):
+            step(i)
+        prof = R.profile_read()
+        R.profile_enable(False)
     # the same frames one at a time (each frame's fusion after its render), no
     # events: the latency of one frame, for comparison
     ms_unpiped = None
