@@ -44,6 +44,8 @@ TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "extend_procedural101k_720p_tra
 WEIGHTS = os.path.join(ROOT, "paper_2106_12802_amd", "weights", "fusion_l1_textured.bin")
 # the paper's own network (x4), trained on the same synthetic pairs
 WEIGHTS_RDG = os.path.join(ROOT, "paper_2106_12802_amd", "weights", "fusion_rdg_l1.bin")
+# the 16-block trunk trained with a random spp pair per iteration
+WEIGHTS_RSPP = os.path.join(ROOT, "paper_2106_12802_amd", "weights", "fusion_l1_random_spp.bin")
 PEAK_BF16_TFLOPS = 2500.0  # MI355X dense BF16 MFMA
 CNN_FLOP_720P = 175.7e9    # 87.85 GMAC per 720p frame
 # the paper's network on a 1024x1024 image, seconds (its runtime table; Titan Xp)
@@ -512,7 +514,35 @@ def spp_pairs_block(log, steps=8, batch=8):
            "spp_pairs": [[h, l] for _, h, l, _ in hist],
            "mpaths_per_iteration_mean": round(float(np.mean(paths)) / 1e6, 3)}
     log(f"[bench] random spp pairs: {ms:.2f} ms per iteration ({res['spp_pairs']})")
+    if os.path.exists(WEIGHTS):
+        res["spp_sweep"] = spp_sweep(log)
     return res
+
+
+def spp_sweep(log):
+    """The paper's spp-pair table (Table 6) on the bench scene at 1280x720: PSNR of the
+    hybrid frame for HRLS {1, 2, 4, 8} x LRHS {16, 64, 256} spp with the trained trunk
+    (and with a trunk trained on random spp pairs, when such weights are present)."""
+    import paper_2106_12802_amd as mrs
+    from mrs_inputs import scenes as S
+    from paper_2106_12802_amd import hybrid as HY
+    gs = mrs.GpuScene(S.procedural(SCENE_SEED))
+    W, H = HRLS[0], HRLS[1]
+    ref = HY.reference(gs, W, H, 1024, HY.REF_SEED)
+    out = {"reference": "1280x720 at 1024 spp, FP64 pixel sums, independent seed"}
+    nets = [("fixed_4_64", WEIGHTS)]
+    if os.path.exists(WEIGHTS_RSPP):
+        nets.append(("random_spp", WEIGHTS_RSPP))
+    for name, path in nets:
+        net = mrs.FusionNet()
+        net.load_weights(path)
+        table = HY.spp_grid(gs, net, W, H, ref=ref)
+        net.close()
+        out[name] = {f"{h}/{l}": round(p, 2) for (h, l), p in sorted(table.items())}
+        out[name + "_monotone"] = HY.grid_monotone(table)
+        log(f"[bench] spp sweep {name}: {out[name]} monotone {out[name + '_monotone']}")
+    gs.close()
+    return out
 
 
 def paper_net_block(log, reps=10, train_steps=10):

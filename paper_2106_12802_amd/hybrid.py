@@ -288,7 +288,8 @@ class OnlinePairs:
 
 
 def train_random_spp(net: FusionNet, data: OnlinePairs, steps: int, batch=16, lr=1e-4,
-                     seed=0, loss="robust", optimizer="sgd", log_every=100, log=print):
+                     seed=0, loss="robust", optimizer="sgd", log_every=100, log=print,
+                     time_limit=None):
     """The paper's training loop: every iteration draws an spp pair
     (sample_spp_pair) and a batch of windows, renders the inputs at that pair and
     takes one optimiser step.  Returns [(step, spp_h, spp_l, loss or None)]."""
@@ -305,7 +306,33 @@ def train_random_spp(net: FusionNet, data: OnlinePairs, steps: int, batch=16, lr
         if want and log:
             log(f"[train] step {step + 1} spp {h}/{l} loss {value:.5f} "
                 f"({time.perf_counter() - t0:.1f} s)")
+        if time_limit is not None and time.perf_counter() - t0 > time_limit:
+            break
     return out
+
+
+def spp_grid(gs, net, W, H, spp_h=(1, 2, 4, 8), spp_l=(16, 64, 256), seed=0, ref=None):
+    """PSNR of the hybrid frame at each (HRLS spp, LRHS spp) pair with HRLS < LRHS
+    (the paper's spp-pair table, Table 6): {(h, l): dB} against a 1024-spp
+    reference with an independent seed."""
+    if ref is None:
+        ref = reference(gs, W, H, 1024, REF_SEED + seed)
+    table = {}
+    for h in spp_h:
+        for l in spp_l:
+            if l > h:
+                out, _ = hybrid_frame(gs, net, W, H, seed, spp_h=h, spp_l=l)
+                table[(h, l)] = image_metrics(out, ref)["psnr"]
+    return table
+
+
+def grid_monotone(table, tol=0.1):
+    """True when PSNR does not fall (by more than tol dB) as either spp grows."""
+    for (h, l), p in table.items():
+        for (h2, l2), p2 in table.items():
+            if ((h2 == h and l2 > l) or (l2 == l and h2 > h)) and p2 < p - tol:
+                return False
+    return True
 
 
 # ---------------------------------------------------------------- equal PSNR
@@ -399,6 +426,9 @@ def main(argv=None):
                     help="network: the configured 16-block trunk or the paper's (x4)")
     ap.add_argument("--loss", default="l1", choices=("l1", "robust"))
     ap.add_argument("--optimizer", default="adam", choices=("adam", "sgd"))
+    ap.add_argument("--random-spp", action="store_true",
+                    help="the paper's training: inputs re-rendered at a random spp pair per "
+                         "iteration (default: fixed 4 / 64 spp pairs rendered once)")
     ap.add_argument("--init-weights", default=None,
                     help="start from these weights (fine-tuning) instead of a fresh init")
     ap.add_argument("--eval-scenes", type=int, default=4)
@@ -406,16 +436,28 @@ def main(argv=None):
     args = ap.parse_args(argv)
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
     torch.cuda.set_device(0)
-    data = build_dataset(n_scenes=args.scenes, windows=args.windows, log=log)
     net = FusionNet(seed=args.seed, arch=args.arch)
     if args.init_weights:
         net.load_weights(args.init_weights)
-    losses, done = train(net, data, args.steps, args.batch, args.lr, seed=args.seed, log=log,
-                         time_limit=args.time_limit, loss=args.loss, optimizer=args.optimizer)
+    if args.random_spp:
+        data = OnlinePairs(S.training_scene_specs(100, args.scenes), windows=args.windows,
+                           scale=net.scale, log=log)
+        hist = train_random_spp(net, data, args.steps, args.batch, args.lr, seed=args.seed,
+                                loss=args.loss, optimizer=args.optimizer, log_every=200,
+                                log=log, time_limit=args.time_limit)
+        losses = [(s, v) for s, _, _, v in hist if v is not None]
+        done = hist[-1][0] if hist else 0
+    else:
+        data = build_dataset(n_scenes=args.scenes, windows=args.windows, log=log)
+        losses, done = train(net, data, args.steps, args.batch, args.lr, seed=args.seed,
+                             log=log, time_limit=args.time_limit, loss=args.loss,
+                             optimizer=args.optimizer)
     net.save(args.out)
     if args.weights_out:
         net.save_weights(args.weights_out)
     log(f"[train] saved {args.out} after {done} steps")
+    if hasattr(data, "close"):
+        data.close()
     del data
     W, H = (int(v) for v in args.eval_size.split("x"))
     results = []

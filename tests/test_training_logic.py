@@ -23,3 +23,12 @@ def test_spp_pairs_follow_the_paper_sets():
     # a pure function of the generator state
     assert HY.sample_spp_pair(np.random.default_rng([3, 7])) == \
         HY.sample_spp_pair(np.random.default_rng([3, 7]))
+
+
+def test_grid_monotone():
+    from paper_2106_12802_amd.hybrid import grid_monotone
+    t = {(1, 16): 30.0, (1, 64): 31.0, (4, 16): 32.0, (4, 64): 33.0}
+    assert grid_monotone(t)
+    assert grid_monotone({**t, (1, 64): 29.95})  # a 0.05 dB dip is within the tolerance
+    assert not grid_monotone({**t, (1, 64): 29.0})  # falls along the LRHS axis
+    assert not grid_monotone({**t, (4, 16): 29.0})  # falls along the HRLS axis
