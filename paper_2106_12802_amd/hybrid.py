@@ -193,7 +193,7 @@ def build_dataset(first_seed=100, n_scenes=64, windows=16, size=128, W=1280, H=7
 
 def train(net: FusionNet, data: PairSet, steps: int, batch=16, lr=1e-4, seed=0,
           log_every=200, log=print, time_limit=None, start_step=0, loss="l1",
-          optimizer="adam"):
+          optimizer="adam", beta=0.1):
     """Optimiser steps (Adam on L1 by default; the paper's setting is
     loss="robust", optimizer="sgd") over random batches; the batch order is a pure
     function of (seed, step), so a run resumed from a checkpoint at step s
@@ -205,7 +205,7 @@ def train(net: FusionNet, data: PairSet, steps: int, batch=16, lr=1e-4, seed=0,
         idx = np.random.default_rng([seed, step]).choice(len(data), batch, replace=False)
         want = (step + 1) % log_every == 0 or step == steps - 1
         value = net.train_step(*data.batch(idx), lr=lr, want_loss=want, loss=loss,
-                               optimizer=optimizer)
+                               optimizer=optimizer, beta=beta)
         done = step + 1
         if want:
             losses.append((done, value))
@@ -308,6 +308,30 @@ def train_random_spp(net: FusionNet, data: OnlinePairs, steps: int, batch=16, lr
                 f"({time.perf_counter() - t0:.1f} s)")
         if time_limit is not None and time.perf_counter() - t0 > time_limit:
             break
+    return out
+
+
+def loss_ablation(data: PairSet, settings, eval_scenes, seconds, W=1280, H=720, batch=16,
+                  lr=1e-4, seed=1, arch="res16", log=print):
+    """One network per loss setting, each trained from the same init on the same
+    pairs for the same time, then the hybrid frame's PSNR on each evaluation
+    scene: {setting: {"steps": n, scene name: dB}}.  settings: ("l1", None) or
+    ("robust", beta)."""
+    refs = {name: reference(gs, W, H, 1024, REF_SEED + k)
+            for k, (name, gs) in enumerate(eval_scenes)}
+    out = {}
+    for loss, beta in settings:
+        net = FusionNet(seed=seed, arch=arch)
+        _, done = train(net, data, 10 ** 9, batch, lr, seed=seed, log_every=2000, log=log,
+                        time_limit=seconds, loss=loss, beta=0.1 if beta is None else beta)
+        key = loss if beta is None else f"{loss}_beta{beta:g}"
+        out[key] = {"steps": done}
+        for k, (name, gs) in enumerate(eval_scenes):
+            img, _ = hybrid_frame(gs, net, W, H, k)
+            out[key][name] = image_metrics(img, refs[name])["psnr"]
+        if log:
+            log(f"[ablation] {key}: {out[key]}")
+        net.close()
     return out
 
 
@@ -429,6 +453,10 @@ def main(argv=None):
     ap.add_argument("--random-spp", action="store_true",
                     help="the paper's training: inputs re-rendered at a random spp pair per "
                          "iteration (default: fixed 4 / 64 spp pairs rendered once)")
+    ap.add_argument("--ablate-loss", type=float, default=None, metavar="SECONDS",
+                    help="instead of one run: train one network per loss (L1, and the paper's "
+                         "robust loss at beta 0.1 and 1) for SECONDS each from the same init and "
+                         "report the hybrid frame's PSNR on the bench and held-out scenes")
     ap.add_argument("--init-weights", default=None,
                     help="start from these weights (fine-tuning) instead of a fresh init")
     ap.add_argument("--eval-scenes", type=int, default=4)
@@ -436,6 +464,16 @@ def main(argv=None):
     args = ap.parse_args(argv)
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
     torch.cuda.set_device(0)
+    if args.ablate_loss:
+        data = build_dataset(n_scenes=args.scenes, windows=args.windows, log=log)
+        evals = [("bench", T.GpuScene(S.procedural(7)))]
+        evals += [(f"heldout_{sd}", T.GpuScene(S.procedural_sized(sd, tr)))
+                  for sd, tr in S.training_scene_specs(200, args.eval_scenes)]
+        res = loss_ablation(data, (("l1", None), ("robust", 0.1), ("robust", 1.0)), evals,
+                            args.ablate_loss, batch=args.batch, lr=args.lr, seed=args.seed,
+                            arch=args.arch, log=log)
+        print(json.dumps(res))
+        return
     net = FusionNet(seed=args.seed, arch=args.arch)
     if args.init_weights:
         net.load_weights(args.init_weights)
