@@ -463,6 +463,12 @@ struct PathOut {
   V3 L;
   double aux[7];
   int64_t segments;
+  // Render layers (Sec. 3.1, Eqs. 1-2, without subsurface and transmission):
+  // the radiance emitted towards the camera at the first vertex (emission or
+  // environment) and the lobe of that vertex (0 none, 1 Lambert = diffuse,
+  // 2 GGX = glossy), which owns the rest of the path's radiance.
+  V3 le0;
+  int lobe;
 };
 
 // Power-heuristic weight (exponent 2) of a strategy with density a against one
@@ -481,6 +487,8 @@ PathOut trace_path(const Scene& sc, bool use_bvh, int W, int H, int px, int py, 
   out.L = mk(0, 0, 0);
   for (int i = 0; i < 7; ++i) out.aux[i] = 0.0;
   out.segments = 0;
+  out.le0 = mk(0, 0, 0);
+  out.lobe = 0;
   const uint32_t p = (uint32_t)(py * W + px);
   // d0, d1: pixel jitter (box filter); d2, d3: lens sample; the shutter time
   // is word 0 of the block with counter (p, s, 0, 4) (drawn only for a moving
@@ -500,6 +508,7 @@ PathOut trace_path(const Scene& sc, bool use_bvh, int W, int H, int px, int py, 
     out.segments++;
     if (h.prim < 0) {  // miss: constant environment
       L = L + mul(beta, sc.env);
+      if (b == 0) out.le0 = L;
       break;
     }
     const Tri& tr = sc.tris[h.prim];
@@ -553,6 +562,10 @@ PathOut trace_path(const Scene& sc, bool use_bvh, int W, int H, int px, int py, 
           L = L + mul(beta, m.emission) * w;
         }
       }
+    }
+    if (b == 0) {
+      out.le0 = L;
+      out.lobe = m.kind == 0 ? 1 : (m.kind == 1 ? 2 : 0);
     }
     if (b == max_depth || m.kind == 2) break;
     if (dot(ns, wo) <= 0.0) break;  // shading normal faces away from the viewer
@@ -777,10 +790,14 @@ void orc_ggx_eval(double alpha, const double* f0, const double* n, const double*
 // mis = 1 combines next-event estimation and BSDF sampling of the quad lights;
 // camfx (or NULL) = lens radius, focus distance, camera motion xyz.
 // counters[0] = non-finite samples replaced by 0, counters[1] = rays traced.
+// out_layers (optional, 9 per pixel): the means of the emission seen at the
+// first vertex, and of the rest of the radiance of the samples whose first
+// vertex is Lambert (diffuse) and GGX (glossy); the three add up to rgb.
 int32_t orc_render(void* s, int32_t W, int32_t H, int32_t spp, int32_t max_depth,
                    int32_t rr_start, uint64_t seed, int32_t npix, const int32_t* pixels,
                    double* out_rgb, double* out_aux, double* out_sumsq, int32_t nthreads,
-                   int32_t use_bvh, int32_t mis, const double* camfx, int64_t* counters) {
+                   int32_t use_bvh, int32_t mis, const double* camfx, int64_t* counters,
+                   double* out_layers) {
   const Scene& sc = *(const Scene*)s;
   if (W <= 0 || H <= 0 || spp <= 0 || max_depth < 0 || (mis != 0 && mis != 1)) return 1;
   const CamFx fx = make_fx(camfx);
@@ -796,15 +813,23 @@ int32_t orc_render(void* s, int32_t W, int32_t H, int32_t spp, int32_t max_depth
         int64_t pix = pixels ? pixels[k] : k;
         int px = (int)(pix % W), py = (int)(pix / W);
         double sum[3] = {0, 0, 0}, sq[3] = {0, 0, 0}, aux[7] = {0, 0, 0, 0, 0, 0, 0};
+        double lay[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
         int64_t lseg = 0;
         for (int si = 0; si < spp; ++si) {
           PathOut po = trace_path(sc, use_bvh != 0, W, H, px, py, si, max_depth, rr_start, seed,
                                   mis != 0, fx);
           lseg += po.segments;
           double l[3] = {po.L.x, po.L.y, po.L.z};
+          double e[3] = {po.le0.x, po.le0.y, po.le0.z};
           if (!(std::isfinite(l[0]) && std::isfinite(l[1]) && std::isfinite(l[2]))) {
             l[0] = l[1] = l[2] = 0.0;
+            e[0] = e[1] = e[2] = 0.0;
             nonfinite++;
+          }
+          // layers: emission at the first vertex; the rest to its lobe
+          for (int c = 0; c < 3; ++c) {
+            lay[c] += e[c];
+            if (po.lobe > 0) lay[3 * po.lobe + c] += l[c] - e[c];
           }
           for (int c = 0; c < 3; ++c) {
             sum[c] += l[c];
@@ -818,6 +843,8 @@ int32_t orc_render(void* s, int32_t W, int32_t H, int32_t spp, int32_t max_depth
           for (int c = 0; c < 3; ++c) out_sumsq[3 * k + c] = sq[c];
         if (out_aux)
           for (int c = 0; c < 7; ++c) out_aux[7 * k + c] = aux[c] / spp;
+        if (out_layers)
+          for (int c = 0; c < 9; ++c) out_layers[9 * k + c] = lay[c] / spp;
       }
     }
   };

@@ -39,7 +39,7 @@ def lib():
         L.orc_philox4x32_10.argtypes = [P, P, P]
         L.orc_render.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                  C.c_uint64, C.c_int32, P, P, P, P, C.c_int32, C.c_int32,
-                                 C.c_int32, P, P]
+                                 C.c_int32, P, P, P]
         L.orc_camera_ray_fx.argtypes = [P, C.c_int32, C.c_int32, C.c_double, C.c_double,
                                         C.c_double, C.c_double, C.c_double, P, P, P]
         L.orc_render.restype = C.c_int32
@@ -127,13 +127,16 @@ class OracleScene:
 
     def render(self, W, H, spp, max_depth, seed, rr_start=3, pixels=None, nthreads=None,
                use_bvh=True, want_aux=True, want_sumsq=False, mis=False, lens_radius=0.0,
-               focus_dist=0.0, cam_motion=(0.0, 0.0, 0.0)):
-        """FP64 render.  Returns dict(rgb [n,3], aux [n,7], sumsq [n,3], nonfinite, rays).
+               focus_dist=0.0, cam_motion=(0.0, 0.0, 0.0), want_layers=False):
+        """FP64 render.  Returns dict(rgb [n,3], aux [n,7], sumsq [n,3], layers [n,9],
+        nonfinite, rays).
 
         `pixels` (flat indices y*W+x) selects a subset; default all pixels, row-major.
         `mis` combines next-event estimation and BSDF sampling of the quad lights
         (power heuristic).  `lens_radius` / `focus_dist`: thin lens; `cam_motion`:
-        camera translation over the shutter.
+        camera translation over the shutter.  `layers` (Sec. 3.1, Eqs. 1-2 without
+        subsurface and transmission): emission seen at the first vertex, then the rest of
+        the radiance of samples whose first vertex is diffuse (Lambert) or glossy (GGX).
         """
         if nthreads is None:
             nthreads = os.cpu_count() or 1
@@ -142,14 +145,15 @@ class OracleScene:
         rgb = np.zeros((n, 3))
         aux = np.zeros((n, 7)) if want_aux else None
         sq = np.zeros((n, 3)) if want_sumsq else None
+        lay = np.zeros((n, 9)) if want_layers else None
         cnt = np.zeros(2, np.int64)
         rc = lib().orc_render(self.h, W, H, spp, max_depth, rr_start, C.c_uint64(seed), n,
                               _p(pix), _p(rgb), _p(aux), _p(sq), int(nthreads), int(use_bvh),
                               int(bool(mis)), _p(self._fx(lens_radius, focus_dist, cam_motion)),
-                              _p(cnt))
+                              _p(cnt), _p(lay))
         if rc != 0:
             raise ValueError("oracle render: invalid arguments")
-        return {"rgb": rgb, "aux": aux, "sumsq": sq, "nonfinite": int(cnt[0]),
+        return {"rgb": rgb, "aux": aux, "sumsq": sq, "layers": lay, "nonfinite": int(cnt[0]),
                 "rays": int(cnt[1])}
 
 

@@ -525,3 +525,77 @@ def test_render_threads_and_subset_consistent(oracle_tracer):
     assert np.array_equal(sub["aux"], full["aux"][pix])
     bf = sc.render(16, 16, 4, 4, 1002, use_bvh=False)
     assert np.array_equal(bf["rgb"], full["rgb"])
+
+
+# --------------------------------------------------------------------------- render layers
+# Sec. 3.1, Eqs. 1-2: the image is the sum of its layers.  Here: the emission
+# seen at the first vertex (emitters, or the environment for a camera ray that
+# misses), then the rest of each sample's radiance filed under the lobe of its
+# first vertex, diffuse (Lambert) or glossy (GGX).
+
+
+def test_layers_env_only_is_all_emission(oracle_tracer):
+    scene = S.env_only((0.3, 0.5, 0.7))
+    r = oracle_tracer.OracleScene(scene).render(8, 4, 4, 8, 42, want_layers=True)
+    lay = r["layers"]
+    assert np.array_equal(lay[:, 0:3], np.tile(scene.env.astype(np.float64), (32, 1)))
+    assert np.all(lay[:, 3:] == 0)
+
+
+@pytest.mark.parametrize("max_depth", [1, 3])
+def test_layers_lambert_plane_all_diffuse(oracle_tracer, max_depth):
+    scene = S.lambert_plane()
+    r = oracle_tracer.OracleScene(scene).render(8, 8, 8, max_depth, 3, want_layers=True)
+    want = scene.materials[0]["color"].astype(np.float64) * scene.env.astype(np.float64)
+    lay = r["layers"]
+    assert np.all(lay[:, 0:3] == 0) and np.all(lay[:, 6:9] == 0)
+    assert np.allclose(lay[:, 3:6], want[None], rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("max_depth", [0, 1, 3])
+def test_layers_furnace_splits_emission_from_bounces(oracle_tracer, max_depth):
+    # emitting Lambert sphere seen from inside: E directly, E sum_{k=1..D} rho^k after
+    E, rho = 1.5, 0.6
+    scene = S.furnace_sphere(E, rho, subdiv=2)
+    r = oracle_tracer.OracleScene(scene).render(4, 4, 8, max_depth, 5, rr_start=100,
+                                                want_layers=True)
+    E32 = float(scene.materials[0]["emission"][0])
+    rho32 = float(scene.materials[0]["color"][0])
+    lay = r["layers"]
+    assert np.all(lay[:, 0:3] == E32)
+    assert np.allclose(lay[:, 3:6], E32 * sum(rho32 ** k for k in range(1, max_depth + 1)),
+                       rtol=1e-12, atol=0)
+    assert np.all(lay[:, 6:9] == 0)
+
+
+def test_layers_ggx_plane_all_glossy(oracle_tracer):
+    scene = _ggx_plane_scene(0.4, (0.9, 0.6, 0.3), 0.6, (1.0, 1.0, 1.0))
+    r = oracle_tracer.OracleScene(scene).render(2, 2, 64, 2, 11, want_layers=True)
+    lay = r["layers"]
+    assert np.all(lay[:, 0:6] == 0)
+    assert np.allclose(lay[:, 6:9], r["rgb"], rtol=1e-12, atol=0)
+    assert np.all(lay[:, 6:9] > 0)
+
+
+def test_layers_front_light_is_emission(oracle_tracer):
+    b = S._Builder()
+    b.add_light((-1.0, 1.0, -1.0), (2.0, 0, 0), (0, 0, 2.0), (5.0, 5.0, 5.0))
+    cam = S.Camera((0.0, -2.0, 0.0), (0.0, 0.0, 0.0), (0.0, 0.0, 1.0), 10.0)
+    r = oracle_tracer.OracleScene(b.build((0.0, 0.0, 0.0), cam, "front")).render(
+        4, 4, 4, 3, 1, want_layers=True)
+    assert np.all(r["layers"][:, 0:3] == 5.0) and np.all(r["layers"][:, 3:] == 0)
+
+
+@pytest.mark.parametrize("mis", [False, True])
+def test_layers_sum_to_image_on_mixed_scene(oracle_tracer, mis):
+    # Lambert and GGX objects, quad lights, the environment seen past them
+    sc = oracle_tracer.OracleScene(S.procedural(7))
+    r = sc.render(24, 16, 4, 4, 77, want_layers=True, mis=mis)
+    lay = r["layers"]
+    total = lay[:, 0:3] + lay[:, 3:6] + lay[:, 6:9]
+    assert np.allclose(total, r["rgb"], rtol=1e-12, atol=1e-14)
+    assert np.all(lay >= 0)
+    for k in range(3):
+        assert lay[:, 3 * k:3 * k + 3].max() > 0, k  # every layer holds something
+    # same paths as without layers
+    assert np.array_equal(sc.render(24, 16, 4, 4, 77, mis=mis)["rgb"], r["rgb"])
