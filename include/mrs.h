@@ -175,6 +175,15 @@ typedef struct mrs_render_opts {
                          point meets the focal plane; tau = word 0 of Philox with
                          counter (p, s, 0, 4), drawn only for a moving camera. */
   float* out_sumsq_dev; /* optional win_h*win_w*3: sum over samples of L^2 */
+  float* out_layers_dev; /* optional win_h*win_w*9: the render layers of Sec. 3.1
+                         (Eqs. 1-2; no subsurface or transmission lobes here), per
+                         pixel the sample means of (0..2) the radiance emitted towards
+                         the camera at the first vertex (emitters, or the environment
+                         when the camera ray misses), (3..5) the rest of the radiance
+                         of samples whose first vertex is Lambert (diffuse) and (6..8)
+                         GGX (glossy).  The three add up to the rgb output up to
+                         rounding; a non-finite sample counts as zero in all of them.
+                         Uses the accumulation precision of the render. */
 } mrs_render_opts;
 
 /* Fills `opts` with the defaults listed above. */

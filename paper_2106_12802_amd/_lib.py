@@ -68,7 +68,8 @@ class RenderOpts(C.Structure):
     _fields_ = [("rr_start", C.c_int32), ("x0", C.c_int32), ("y0", C.c_int32),
                 ("win_w", C.c_int32), ("win_h", C.c_int32), ("accum_fp64", C.c_int32),
                 ("mis", C.c_int32), ("lens_radius", C.c_float), ("focus_dist", C.c_float),
-                ("cam_motion", C.c_float * 3), ("out_sumsq_dev", C.c_void_p)]
+                ("cam_motion", C.c_float * 3), ("out_sumsq_dev", C.c_void_p),
+                ("out_layers_dev", C.c_void_p)]
 
 
 class Job(C.Structure):

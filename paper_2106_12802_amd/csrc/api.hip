@@ -284,6 +284,7 @@ void mrs_render_opts_default(mrs_render_opts* o) {
   o->focus_dist = 0.0f;
   o->cam_motion[0] = o->cam_motion[1] = o->cam_motion[2] = 0.0f;
   o->out_sumsq_dev = nullptr;
+  o->out_layers_dev = nullptr;
 }
 
 namespace {
@@ -315,7 +316,8 @@ mrs_status validate_render(const char* fn, const mrs_scene* s, int32_t W, int32_
   if (o.x0 < 0 || o.y0 < 0 || ww < 1 || wh < 1 || o.x0 + ww > W || o.y0 + wh > H)
     return fail(MRS_ERR_INVALID_ARGUMENT, f + ": window outside the image");
   if (!out_rgb) return fail(MRS_ERR_INVALID_ARGUMENT, f + ": out_rgb is NULL");
-  if (((uintptr_t)out_rgb | (uintptr_t)out_aux | (uintptr_t)o.out_sumsq_dev) & 3u)
+  if (((uintptr_t)out_rgb | (uintptr_t)out_aux | (uintptr_t)o.out_sumsq_dev |
+       (uintptr_t)o.out_layers_dev) & 3u)
     return fail(MRS_ERR_INVALID_ARGUMENT, f + ": outputs must be 4-byte aligned");
   if (!s->bvh_built) return fail(MRS_ERR_NOT_READY, f + ": call mrs_build_bvh first");
   a->W = W;
@@ -336,6 +338,7 @@ mrs_status validate_render(const char* fn, const mrs_scene* s, int32_t W, int32_
   a->out_rgb = out_rgb;
   a->out_aux = out_aux;
   a->out_sumsq = o.out_sumsq_dev;
+  a->out_layers = o.out_layers_dev;
   return MRS_OK;
 }
 }  // namespace

@@ -100,6 +100,7 @@ struct DevJob {
   float* out_rgb;
   float* out_aux;
   float* out_sq;
+  float* out_layers;  // 9 per pixel: emission, diffuse, glossy (or null)
 };
 
 constexpr int MAX_JOBS = 255;                // job ids travel in 8 bits
@@ -150,6 +151,7 @@ struct RenderArgs {
   float* out_rgb;
   float* out_aux;
   float* out_sumsq;
+  float* out_layers;
 };
 mrs_status render(const mrs_scene* s, const RenderArgs& a, hipStream_t st);
 DevJob make_job(const mrs_scene* s, const RenderArgs& a);

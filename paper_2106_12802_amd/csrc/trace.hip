@@ -650,6 +650,7 @@ struct Vertex {
   f3 x, wi, swi, c;
   float sr;
   uint32_t li, prim;
+  int lobe;      // render layer of this vertex's BSDF: 0 none, 1 Lambert, 2 GGX
 };
 
 // pdf_in: the density of the BSDF sample that led here (0 for camera rays).
@@ -663,6 +664,7 @@ __device__ __forceinline__ void shade_vertex(const DevJob& J, int64_t g, int b, 
   v.pdf = 0.0f;
   v.prim = prim;
   v.li = 0;
+  v.lobe = 0;
   v.x = v.wi = v.swi = v.c = F3(0.0f, 0.0f, 0.0f);
   v.sr = 0.0f;
   if (prim == NO_PRIM) {
@@ -701,6 +703,7 @@ __device__ __forceinline__ void shade_vertex(const DevJob& J, int64_t g, int b, 
   const DevMaterial m = sc.mats[info & PRIM_MAT_MASK];
   const int kind = (int)m.emis_kind.w;
   const f3 col = xyz(m.color_alpha);
+  v.lobe = kind == MRS_LAMBERT ? 1 : (kind == MRS_GGX ? 2 : 0);
   if (aux2) {
     const f3 alb = kind == MRS_EMITTER ? F3(0, 0, 0) : col;
     aux2[0] = make_float4(alb.x, alb.y, alb.z, ns.x);
@@ -811,7 +814,8 @@ __global__ __launch_bounds__(256) void k_shade(const DevJob* __restrict__ jobs, 
                                                float4* __restrict__ shadow,
                                                float4* __restrict__ beta_buf,
                                                float4* __restrict__ L_buf,
-                                               float4* __restrict__ aux_buf) {
+                                               float4* __restrict__ aux_buf,
+                                               float4* __restrict__ lay_buf) {
   const uint32_t n = q[Q_RAYS + b];
   uint32_t* cnt_next = q + Q_RAYS + b + 1;
   uint32_t* cnt_shadow = q + Q_SHADOW + b;
@@ -833,6 +837,10 @@ __global__ __launch_bounds__(256) void k_shade(const DevJob* __restrict__ jobs, 
                    (b == 0 && jobs[j].out_aux) ? aux_buf + 2 * slot : nullptr, v);
       if (v.cont) beta_buf[slot] = make_float4(v.beta.x, v.beta.y, v.beta.z, v.pdf);
       L_buf[slot] = make_float4(v.L.x, v.L.y, v.L.z, 0.0f);
+      // render layers: at the first vertex L holds just the emission seen
+      // there (next-event estimates arrive later through the shadow rays)
+      if (b == 0 && jobs[j].out_layers)
+        lay_buf[slot] = make_float4(v.L.x, v.L.y, v.L.z, (float)v.lobe);
     }
     const uint32_t ri = wave_append(v.cont, cnt_next);
     if (v.cont) {
@@ -1039,22 +1047,45 @@ __device__ __forceinline__ void accumulate_pixel(const DevJob& J, char* acc_base
                                                  int64_t s_lo, int64_t s_hi, int64_t slot0,
                                                  int64_t npix, const float4* __restrict__ L_buf,
                                                  const float4* __restrict__ aux_buf,
+                                                 const float4* __restrict__ lay_buf,
                                                  uint32_t& bad) {
   T* acc = reinterpret_cast<T*>(acc_base + J.acc_off);
   T* a_rgb = acc + 3 * (int64_t)pl;
   T* a_aux = acc + 3 * npix + 7 * (int64_t)pl;
   T* a_sq = acc + 10 * npix + 3 * (int64_t)pl;
   const bool feats = J.out_aux != nullptr;  // features are only traced for jobs that output them
+  const bool lays = J.out_layers != nullptr;
+  T* a_lay = acc + 13 * npix + 9 * (int64_t)pl;
   T r = a_rgb[0], gg = a_rgb[1], bb = a_rgb[2];
   T sr = a_sq[0], sg = a_sq[1], sb = a_sq[2];
   T a[7];
   for (int c = 0; c < 7; ++c) a[c] = feats ? a_aux[c] : (T)0;
+  T ly[9];
+  for (int c = 0; c < 9; ++c) ly[c] = lays ? a_lay[c] : (T)0;
   for (int64_t s = s_lo; s <= s_hi; ++s) {
     const int64_t slot = slot0 + s;
     float4 Lv = L_buf[slot];
+    float4 E = lays ? lay_buf[slot] : make_float4(0, 0, 0, 0);
     if (!(isfinite(Lv.x) && isfinite(Lv.y) && isfinite(Lv.z))) {
       Lv = make_float4(0, 0, 0, 0);
+      E = make_float4(0, 0, 0, E.w);
       ++bad;
+    }
+    if (lays) {
+      // the emission seen at the first vertex, and the rest to that vertex's lobe
+      const int lobe = (int)E.w;
+      ly[0] += (T)E.x;
+      ly[1] += (T)E.y;
+      ly[2] += (T)E.z;
+      if (lobe == 1) {
+        ly[3] += (T)Lv.x - (T)E.x;
+        ly[4] += (T)Lv.y - (T)E.y;
+        ly[5] += (T)Lv.z - (T)E.z;
+      } else if (lobe == 2) {
+        ly[6] += (T)Lv.x - (T)E.x;
+        ly[7] += (T)Lv.y - (T)E.y;
+        ly[8] += (T)Lv.z - (T)E.z;
+      }
     }
     r += (T)Lv.x;
     gg += (T)Lv.y;
@@ -1072,6 +1103,8 @@ __device__ __forceinline__ void accumulate_pixel(const DevJob& J, char* acc_base
   a_sq[0] = sr; a_sq[1] = sg; a_sq[2] = sb;
   if (feats)
     for (int c = 0; c < 7; ++c) a_aux[c] = a[c];
+  if (lays)
+    for (int c = 0; c < 9; ++c) a_lay[c] = ly[c];
 }
 
 __global__ __launch_bounds__(256) void k_accumulate(const DevJob* __restrict__ jobs, int njobs,
@@ -1079,6 +1112,7 @@ __global__ __launch_bounds__(256) void k_accumulate(const DevJob* __restrict__ j
                                                     int64_t pix_hi,
                                                     const float4* __restrict__ L_buf,
                                                     const float4* __restrict__ aux_buf,
+                                                    const float4* __restrict__ lay_buf,
                                                     char* __restrict__ acc_base,
                                                     unsigned long long* __restrict__ stats) {
   // i runs over pixels in path order (the chunk's pixels are one range of it)
@@ -1099,9 +1133,11 @@ __global__ __launch_bounds__(256) void k_accumulate(const DevJob* __restrict__ j
   const int64_t slot0 = base - g0;
   uint32_t bad = 0;
   if (J.fp64)
-    accumulate_pixel<double>(J, acc_base, pl, s_lo, s_hi, slot0, npix, L_buf, aux_buf, bad);
+    accumulate_pixel<double>(J, acc_base, pl, s_lo, s_hi, slot0, npix, L_buf, aux_buf, lay_buf,
+                             bad);
   else
-    accumulate_pixel<float>(J, acc_base, pl, s_lo, s_hi, slot0, npix, L_buf, aux_buf, bad);
+    accumulate_pixel<float>(J, acc_base, pl, s_lo, s_hi, slot0, npix, L_buf, aux_buf, lay_buf,
+                            bad);
   if (bad) atomicAdd(stats + 0, (unsigned long long)bad);
 }
 
@@ -1121,6 +1157,9 @@ __device__ __forceinline__ void resolve_pixel(const DevJob& J, const char* acc_b
   if (J.out_sq)
     for (int c = 0; c < 3; ++c)
       J.out_sq[3 * (int64_t)pl + c] = (float)acc[10 * npix + 3 * (int64_t)pl + c];
+  if (J.out_layers)
+    for (int c = 0; c < 9; ++c)
+      J.out_layers[9 * (int64_t)pl + c] = (float)(acc[13 * npix + 9 * (int64_t)pl + c] * inv);
 }
 
 __global__ __launch_bounds__(256) void k_resolve(const DevJob* __restrict__ jobs, int njobs,
@@ -1218,7 +1257,7 @@ struct Sub {
   unsigned gb;
   size_t o;
   float4* rays[2];
-  float4 *hits, *shadow, *beta, *L, *aux;
+  float4 *hits, *shadow, *beta, *L, *aux, *lay;
   uint32_t *spill, *q;
 };
 
@@ -1242,6 +1281,7 @@ struct Workspace {
   float4* beta = nullptr;
   float4* L = nullptr;
   float4* aux = nullptr;
+  float4* lay = nullptr;  // render layers: first-vertex emission and lobe per path
   uint32_t* spill = nullptr;
   uint32_t* q = nullptr;  // MAX_SUB blocks of Q_WORDS counters
   char* acc = nullptr;    // per-job accumulators (single renders)
@@ -1295,6 +1335,7 @@ void ws_release(Workspace& w) {
   hfree(w.beta);
   hfree(w.L);
   hfree(w.aux);
+  hfree(w.lay);
   hfree(w.spill);
   hfree(w.q);
   hfree(w.acc);
@@ -1345,6 +1386,7 @@ mrs_status ws_ensure(Workspace& w, size_t paths, int threads, int nsub) {
     hfree(w.beta);
     hfree(w.L);
     hfree(w.aux);
+    hfree(w.lay);
     w.cap_paths = 0;
     bool ok = hipMalloc(&w.rays[0], 32 * paths) == hipSuccess &&
               hipMalloc(&w.rays[1], 32 * paths) == hipSuccess &&
@@ -1352,7 +1394,8 @@ mrs_status ws_ensure(Workspace& w, size_t paths, int threads, int nsub) {
               hipMalloc(&w.shadow, 48 * paths) == hipSuccess &&
               hipMalloc(&w.beta, 16 * paths) == hipSuccess &&
               hipMalloc(&w.L, 16 * paths) == hipSuccess &&
-              hipMalloc(&w.aux, 32 * paths) == hipSuccess;
+              hipMalloc(&w.aux, 32 * paths) == hipSuccess &&
+              hipMalloc(&w.lay, 16 * paths) == hipSuccess;
     if (!ok) {
       (void)hipGetLastError();
       return fail(MRS_ERR_OUT_OF_MEMORY, "render: path-state allocation failed");
@@ -1403,8 +1446,9 @@ mrs_tuning tuning_snapshot() {
 
 inline unsigned cdiv(size_t a, size_t b) { return (unsigned)((a + b - 1) / b); }
 
-size_t acc_bytes_of(int64_t npix, bool fp64) {
-  return ((size_t)npix * 13 * (fp64 ? 8 : 4) + 255) & ~(size_t)255;
+// rgb 3, features 7, squares 3, then the 9 render-layer sums when asked for
+size_t acc_bytes_of(int64_t npix, bool fp64, bool layers) {
+  return ((size_t)npix * (layers ? 22 : 13) * (fp64 ? 8 : 4) + 255) & ~(size_t)255;
 }
 
 // Per-pixel sums of one super-chunk, in sample order: each sub-chunk, in path
@@ -1425,7 +1469,7 @@ mrs_status sum_chunk(Workspace& ws, const DevJob* d_jobs, const std::vector<DevJ
         jobs[jhi].pix_first + (u.lo + (int64_t)u.n - 1 - jobs[jhi].first) / jobs[jhi].spp + 1;
     prof_begin(KID_ACCUMULATE, st);
     k_accumulate<<<cdiv((size_t)(pix_hi - pix_lo), 256), 256, 0, st>>>(
-        d_jobs, nj, u.lo, u.n, pix_lo, pix_hi, u.L, u.aux, acc, g_stats);
+        d_jobs, nj, u.lo, u.n, pix_lo, pix_hi, u.L, u.aux, u.lay, acc, g_stats);
     prof_end(KID_ACCUMULATE, st);
     k_tally<<<1, 64, 0, st>>>(u.q, nwave, g_stats, u.n);
   }
@@ -1476,6 +1520,7 @@ mrs_status begin_batch(Workspace& ws, const mrs_tuning& tu, const DevJob* d_jobs
       u.beta = ws.beta + u.o;
       u.L = ws.L + u.o;
       u.aux = ws.aux + 2 * u.o;
+      u.lay = ws.lay + u.o;
       u.spill = ws.spill + k * spill_k;
       u.q = ws.q + k * Q_WORDS;
     }
@@ -1505,7 +1550,8 @@ mrs_status begin_batch(Workspace& ws, const mrs_tuning& tu, const DevJob* d_jobs
         Sub& u = sub[k];
         prof_begin(KID_SHADE, u.s);
         k_shade<<<u.gb, 256, 0, u.s>>>(d_jobs, u.lo, b, u.rays[b & 1], u.hits, u.q,
-                                       u.rays[(b + 1) & 1], u.shadow, u.beta, u.L, u.aux);
+                                       u.rays[(b + 1) & 1], u.shadow, u.beta, u.L, u.aux,
+                                       u.lay);
         prof_end(KID_SHADE, u.s);
       }
       if (b < max_depth) {
@@ -1642,6 +1688,7 @@ DevJob make_job(const mrs_scene* s, const RenderArgs& a) {
   J.out_rgb = a.out_rgb;
   J.out_aux = a.out_aux;
   J.out_sq = a.out_sumsq;
+  J.out_layers = a.out_layers;
   return J;
 }
 
@@ -1657,7 +1704,7 @@ mrs_status render(const mrs_scene* s, const RenderArgs& a, hipStream_t st) {
   Workspace& ws = *stream_workspace(st);
   mrs_status rc = ws_ensure_plan(ws, make_plan(tu, npix * a.spp));
   if (rc != MRS_OK) return rc;
-  const size_t ab = acc_bytes_of(npix, a.fp64);
+  const size_t ab = acc_bytes_of(npix, a.fp64, a.out_layers != nullptr);
   if ((rc = ws_ensure_acc(ws, ab)) != MRS_OK) return rc;
   k_store_job<<<1, 64, 0, st>>>(J, ws.one);
   std::vector<DevJob> jobs{J};
@@ -1704,7 +1751,7 @@ mrs_status batch_create(const std::vector<DevJob>& jobs, mrs_batch** out) {
     J.acc_off = (int64_t)off;
     first += npix * J.spp;
     pix += npix;
-    off += acc_bytes_of(npix, J.fp64 != 0);
+    off += acc_bytes_of(npix, J.fp64 != 0, J.out_layers != nullptr);
   }
   b->acc_bytes = off;
   mrs_status rc = ws_ensure_plan(b->ws, make_plan(b->tune, first));

@@ -92,11 +92,12 @@ class GpuScene:
 
 def render_ex(scene: GpuScene, W, H, spp, max_depth, seed, out_rgb, out_aux=None, rr_start=3,
               window=None, accum_fp64=-1, out_sumsq=None, mis=False, lens_radius=0.0,
-              focus_dist=0.0, cam_motion=(0.0, 0.0, 0.0)):
+              focus_dist=0.0, cam_motion=(0.0, 0.0, 0.0), out_layers=None):
     """Enqueue mrs_render_ex on torch's current stream.  Outputs are CUDA float32 tensors.
 
     mis: combine next-event estimation and BSDF sampling of the quad lights;
-    lens_radius / focus_dist: thin lens; cam_motion: camera translation over the shutter."""
+    lens_radius / focus_dist: thin lens; cam_motion: camera translation over the shutter;
+    out_layers ([.., 9]): emission, diffuse and glossy render layers (Sec. 3.1)."""
     o = L.RenderOpts()
     L.lib().mrs_render_opts_default(C.byref(o))
     o.rr_start = rr_start
@@ -109,6 +110,7 @@ def render_ex(scene: GpuScene, W, H, spp, max_depth, seed, out_rgb, out_aux=None
     o.accum_fp64 = accum_fp64
     npix = (int(W) * int(H)) if window is None else int(window[2]) * int(window[3])
     o.out_sumsq_dev = L.ptr(out_sumsq, 3 * npix, "f32", "out_sumsq")
+    o.out_layers_dev = L.ptr(out_layers, 9 * npix, "f32", "out_layers")
     L.use_current_stream()
     L.check(L.lib().mrs_render_ex(scene.handle, int(W), int(H), int(spp), int(max_depth),
                                   C.c_uint64(int(seed)), C.byref(o),
@@ -210,9 +212,9 @@ class Batch:
     """Several renders (uneven scenes, sizes, spp, depths) enqueued as one wavefront.
 
     jobs: dicts with keys scene (GpuScene), W, H, spp, max_depth, seed, and optional
-    out_rgb / out_aux / out_sumsq (CUDA float32 tensors, allocated if missing; aux only
-    when want_aux is true), rr_start, window, accum_fp64, mis, lens_radius, focus_dist,
-    cam_motion.  Outputs are in .outputs."""
+    out_rgb / out_aux / out_sumsq / out_layers (CUDA float32 tensors; rgb and aux are
+    allocated if missing, aux only when want_aux is true), rr_start, window, accum_fp64,
+    mis, lens_radius, focus_dist, cam_motion.  Outputs are in .outputs."""
 
     def __init__(self, jobs):
         import torch
@@ -232,6 +234,7 @@ class Batch:
             if aux is None and j.get("want_aux", True):
                 aux = torch.empty(wh, ww, 7, dtype=torch.float32, device="cuda")
             sq = j.get("out_sumsq")
+            lay = j.get("out_layers")
             o = L.RenderOpts()
             L.lib().mrs_render_opts_default(C.byref(o))
             o.rr_start = int(j.get("rr_start", 3))
@@ -243,6 +246,7 @@ class Batch:
             o.focus_dist = float(j.get("focus_dist", 0.0))
             o.cam_motion[:] = [float(v) for v in j.get("cam_motion", (0.0, 0.0, 0.0))]
             o.out_sumsq_dev = L.ptr(sq, 3 * ww * wh, "f32", "out_sumsq")
+            o.out_layers_dev = L.ptr(lay, 9 * ww * wh, "f32", "out_layers")
             arr[i].scene = j["scene"].handle.value
             arr[i].W, arr[i].H = W, H
             arr[i].spp, arr[i].max_depth = int(j["spp"]), int(j["max_depth"])
@@ -251,7 +255,7 @@ class Batch:
             arr[i].out_rgb_dev = L.ptr(rgb, 3 * ww * wh, "f32", "out_rgb")
             arr[i].out_aux_dev = L.ptr(aux, 7 * ww * wh, "f32", "out_aux")
             self.outputs.append((rgb, aux))
-            self._keep += [rgb, aux, sq, j["scene"]]
+            self._keep += [rgb, aux, sq, lay, j["scene"]]
         L.use_current_stream()
         h = C.c_void_p()
         L.check(L.lib().mrs_batch_create(arr, n, C.byref(h)))

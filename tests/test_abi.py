@@ -109,12 +109,12 @@ def test_render_opts_layout_matches_the_header():
     """mrs_render_opts_default writes each documented default into its own field
     (a layout mismatch between the header and the binding would misplace them)."""
     from paper_2106_12802_amd import _lib
-    o = _lib.RenderOpts(7, 7, 7, 7, 7, 7, 7, 7.0, 7.0, (C.c_float * 3)(7, 7, 7), 12345)
+    o = _lib.RenderOpts(7, 7, 7, 7, 7, 7, 7, 7.0, 7.0, (C.c_float * 3)(7, 7, 7), 12345, 678)
     _lib.lib().mrs_render_opts_default(C.byref(o))
     assert (o.rr_start, o.x0, o.y0, o.win_w, o.win_h, o.accum_fp64, o.mis) == (3, 0, 0, 0, 0, -1, 0)
     assert (o.lens_radius, o.focus_dist, list(o.cam_motion)) == (0.0, 0.0, [0.0, 0.0, 0.0])
-    assert not o.out_sumsq_dev
-    assert C.sizeof(_lib.Job) == 104
+    assert not o.out_sumsq_dev and not o.out_layers_dev
+    assert C.sizeof(_lib.Job) == 112
     # a lens needs a positive focus distance; motion must be finite (rejected on the host)
     from mrs_inputs import scenes as S
     L = _lib.lib()

@@ -540,3 +540,71 @@ def test_ploc_too_deep_falls_back_to_lbvh(mrs):
     d = np.tile(np.array([[0.0, 0.0, 1.0]], np.float32), (4, 1))
     t, p, _ = gs.closest_hit(o, d)
     assert np.all(p == 0) and np.allclose(t, 1.0)  # the smallest (nearest) triangle
+
+
+# --------------------------------------------------------------------------- render layers
+
+
+def _layers_gpu(mrs, torch_cuda, gs, W, H, spp, D, seed, **kw):
+    lay = torch_cuda.full((H, W, 9), float("nan"), dtype=torch_cuda.float32, device="cuda")
+    rgb, _ = mrs.render(gs, W, H, spp, D, seed, want_aux=False, out_layers=lay, **kw)
+    torch_cuda.cuda.synchronize()
+    return rgb.cpu().numpy().reshape(-1, 3).astype(np.float64), \
+        lay.cpu().numpy().reshape(-1, 9).astype(np.float64)
+
+
+@pytest.mark.parametrize("fp64,mis", [(0, False), (1, True)])
+def test_layers_parity(mrs, oracle_tracer, torch_cuda, fp64, mis):
+    """Emission / diffuse / glossy layers (Sec. 3.1, Eqs. 1-2) against the oracle's, on a
+    Lambert + GGX scene with lights and environment; 97 x 55 ends in ragged tiles.  As
+    for the image (21k paths, mean held to 1e-4), one divergent path moves a layer's mean
+    by as much more as the layer is a smaller share of the image (diffuse: ~5% here)."""
+    scene = S.procedural(7)
+    W, H, spp, D, seed = 97, 55, 4, 4, 4242 + fp64
+    gs = mrs.GpuScene(scene)
+    _log(f"layers parity fp64={fp64} mis={mis}")
+    g_rgb, g_lay = _layers_gpu(mrs, torch_cuda, gs, W, H, spp, D, seed, accum_fp64=fp64, mis=mis)
+    plain, _ = mrs.render(gs, W, H, spp, D, seed, want_aux=False, accum_fp64=fp64, mis=mis)
+    torch_cuda.cuda.synchronize()
+    # the same paths: asking for layers leaves the image bitwise as it was
+    assert np.array_equal(plain.cpu().numpy().reshape(-1, 3).astype(np.float64), g_rgb)
+    o = oracle_tracer.OracleScene(scene).render(W, H, spp, D, seed, mis=mis, want_layers=True)
+    assert np.all(np.isfinite(g_lay))
+    tot = g_lay[:, 0:3] + g_lay[:, 3:6] + g_lay[:, 6:9]
+    assert np.allclose(tot, g_rgb, rtol=1e-5, atol=1e-6 * max(g_rgb.mean(), 1e-30))
+    for k, name in enumerate(("emission", "diffuse", "glossy")):
+        g, ob = g_lay[:, 3 * k:3 * k + 3], o["layers"][:, 3 * k:3 * k + 3]
+        assert ob.max() > 0, name
+        frac = np.all(rel_ok(g, ob), -1).mean()
+        mean_rel = abs(g.mean() - ob.mean()) / abs(ob.mean())
+        share = ob.mean() / o["rgb"].mean()
+        _log(f"  {name}: pixels ok {frac:.5f}, mean rel {mean_rel:.2e}, share {share:.3f}")
+        assert frac >= 0.999, name
+        assert mean_rel <= 1e-4 / min(share, 1.0), name
+
+
+def test_layers_in_a_batch_match_single_renders(mrs, torch_cuda):
+    """Jobs with and without layers share a batch's accumulators (their offsets differ
+    by the layer sums); each job's outputs equal its own render bitwise."""
+    gA = mrs.GpuScene(S.procedural(7, spheres=((2, 4),), n_boxes=5, n_lights=2))
+    gB = mrs.GpuScene(S.cornell(1))
+    mk = lambda h, w: torch_cuda.zeros(h, w, 9, dtype=torch_cuda.float32, device="cuda")
+    jobs = [dict(scene=gA, W=40, H=24, spp=5, max_depth=3, seed=71, out_layers=mk(24, 40)),
+            dict(scene=gB, W=32, H=16, spp=3, max_depth=4, seed=72),
+            dict(scene=gA, W=8, H=8, spp=1030, max_depth=2, seed=73, out_layers=mk(8, 8)),
+            dict(scene=gB, W=64, H=40, spp=2, max_depth=5, seed=74, window=(8, 8, 30, 20),
+                 out_layers=mk(20, 30), mis=True)]
+    _log("layers batch")
+    b = mrs.Batch(jobs)
+    b.render()
+    torch_cuda.cuda.synchronize()
+    for j, (rgb, aux) in zip(jobs, b.outputs):
+        kw = {k: j[k] for k in ("window", "mis") if k in j}
+        lay = mk(*j["out_layers"].shape[:2]) if "out_layers" in j else None
+        r1, a1 = mrs.render(j["scene"], j["W"], j["H"], j["spp"], j["max_depth"], j["seed"],
+                            out_layers=lay, **kw)
+        torch_cuda.cuda.synchronize()
+        assert torch_cuda.equal(rgb, r1) and torch_cuda.equal(aux, a1)
+        if lay is not None:
+            assert torch_cuda.equal(j["out_layers"], lay)
+            assert float(lay.abs().sum()) > 0
