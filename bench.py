@@ -487,6 +487,31 @@ def camera_block(gs, log, reps=5):
     return res
 
 
+def layers_block(gs, log, reps=5):
+    """Render layers (Sec. 3.1, Eqs. 1-2: emission, diffuse, glossy) of the HRLS
+    render (1280x720@4) on the bench scene: its time with the nine layer sums
+    against the plain render."""
+    import torch
+    from paper_2106_12802_amd import tracer as R
+    Wh, Hh, sh = HRLS
+    hr = torch.empty(Hh, Wh, 3, device="cuda")
+    lay = torch.empty(Hh, Wh, 9, device="cuda")
+    res = {"workload": "bench scene, HRLS 1280x720@4 as one render call, with and without "
+                       "the emission / diffuse / glossy layers"}
+    for name, kw in (("plain", {}), ("layers", {"out_layers": lay})):
+        R.render_ex(gs, Wh, Hh, sh, MAX_DEPTH, 0, hr, None, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(reps):
+            R.render_ex(gs, Wh, Hh, sh, MAX_DEPTH, i, hr, None, **kw)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+        res[f"ms_hrls_{name}"] = round(ms, 4)
+        log(f"[bench] layers {name}: HRLS render {ms:.3f} ms")
+    res["overhead"] = round(res["ms_hrls_layers"] / res["ms_hrls_plain"] - 1.0, 4)
+    return res
+
+
 def spp_pairs_block(log, steps=8, batch=8):
     """The paper's training iteration with a random spp pair per iteration (Sec. 4):
     the paper's x4 network, robust loss, SGD; every iteration renders its batch of
@@ -616,7 +641,7 @@ def main():
     ap.add_argument("--no-mis", action="store_true",
                     help="skip the multiple-importance-sampling comparison")
     ap.add_argument("--no-camera", action="store_true",
-                    help="skip the depth-of-field / motion-blur timing block")
+                    help="skip the depth-of-field / motion-blur and render-layer timing blocks")
     ap.add_argument("--no-spp-pairs", action="store_true",
                     help="skip the random-spp-pair training iteration block")
     ap.add_argument("--no-paper-net", action="store_true",
@@ -832,6 +857,7 @@ def main():
         result["mis"] = mis_block(gs, log)
     if not args.no_camera:
         result["camera"] = camera_block(gs, log)
+        result["layers"] = layers_block(gs, log)
     if not args.no_spp_pairs:
         result["spp_pairs"] = spp_pairs_block(log)
     if not args.no_cpu_baseline:
