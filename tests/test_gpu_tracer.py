@@ -583,6 +583,26 @@ def test_layers_parity(mrs, oracle_tracer, torch_cuda, fp64, mis):
         assert mean_rel <= 1e-4 / min(share, 1.0), name
 
 
+def test_layers_parity_full_size_hrls(mrs, oracle_tracer, torch_cuda):
+    """The HRLS render (1280x720 @4 spp, depth 8) with its layers, whole image against the
+    oracle; the image mean bar (1e-5) scaled by each layer's share of the image."""
+    scene = S.procedural(7)
+    W, H, spp, D, seed = 1280, 720, 4, 8, 14
+    _log("layers parity 1280x720x4")
+    g_rgb, g_lay = _layers_gpu(mrs, torch_cuda, mrs.GpuScene(scene), W, H, spp, D, seed)
+    o = oracle_tracer.OracleScene(scene).render(W, H, spp, D, seed, want_aux=False,
+                                                want_layers=True)
+    assert np.all(rel_ok(g_rgb, o["rgb"]).all(-1).mean() >= 0.999)
+    for k, name in enumerate(("emission", "diffuse", "glossy")):
+        g, ob = g_lay[:, 3 * k:3 * k + 3], o["layers"][:, 3 * k:3 * k + 3]
+        frac = np.all(rel_ok(g, ob), -1).mean()
+        mean_rel = abs(g.mean() - ob.mean()) / abs(ob.mean())
+        share = ob.mean() / o["rgb"].mean()
+        _log(f"  {name}: pixels ok {frac:.5f}, mean rel {mean_rel:.2e}, share {share:.3f}")
+        assert frac >= 0.999, name
+        assert mean_rel <= 1e-5 / min(share, 1.0), name
+
+
 def test_layers_in_a_batch_match_single_renders(mrs, torch_cuda):
     """Jobs with and without layers share a batch's accumulators (their offsets differ
     by the layer sums); each job's outputs equal its own render bitwise."""
