@@ -234,7 +234,16 @@ def cpu_baseline(scene, threads):
     t_cnn = (time.perf_counter() - t0) * 16
     paths = HRLS[0] * HRLS[1] * HRLS[2] + LRHS[0] * LRHS[1] * LRHS[2]
     total = t_render + t_cnn
+    # the small case (Cornell box 64x64 @16 spp, depth 4: 65,536 paths) on one thread and on all
+    from mrs_inputs import scenes as S
+    small = orc.OracleScene(S.cornell(1))
+    small_rate = {}
+    for n in (1, threads):
+        t0 = time.perf_counter()
+        small.render(64, 64, 16, 4, 1001, nthreads=n)
+        small_rate[f"threads_{n}"] = round(65536 / (time.perf_counter() - t0) / 1e6, 4)
     return {"value": round(paths / total / 1e6, 4), "unit": "Mpaths/s", "cores": threads,
+            "small_case_mpaths_per_s": small_rate,
             "kind": "oracle",
             "sample": f"renders of the full frame (HRLS {HRLS[0]}x{HRLS[1]}@{HRLS[2]} + LRHS "
                       f"{LRHS[0]}x{LRHS[1]}@{LRHS[2]}, {paths} paths, FP64: {t_render:.1f} s) + the "

@@ -603,6 +603,21 @@ def test_layers_parity_full_size_hrls(mrs, oracle_tracer, torch_cuda):
         assert mean_rel <= 1e-5 / min(share, 1.0), name
 
 
+def test_layers_degenerate_cases(mrs, torch_cuda):
+    """Depth 0 (the first vertex's emission only): the emission layer is the image and the
+    others are zero; one pixel at one sample; a scene with no lights (environment only)."""
+    gs = mrs.GpuScene(S.procedural(7))
+    _log("layers degenerate cases")
+    rgb, lay = _layers_gpu(mrs, torch_cuda, gs, 33, 17, 3, 0, 5)
+    assert np.array_equal(lay[:, 0:3], rgb) and np.all(lay[:, 3:] == 0)
+    rgb, lay = _layers_gpu(mrs, torch_cuda, gs, 1, 1, 1, 8, 6)
+    assert np.allclose(lay[:, 0:3] + lay[:, 3:6] + lay[:, 6:9], rgb, rtol=1e-6, atol=0)
+    env = S.env_only((0.3, 0.5, 0.7))
+    rgb, lay = _layers_gpu(mrs, torch_cuda, mrs.GpuScene(env), 16, 8, 2, 4, 7)
+    assert np.array_equal(lay[:, 0:3], rgb) and np.all(lay[:, 3:] == 0)
+    assert np.allclose(rgb, env.env.astype(np.float64)[None])
+
+
 def test_layers_in_a_batch_match_single_renders(mrs, torch_cuda):
     """Jobs with and without layers share a batch's accumulators (their offsets differ
     by the layer sums); each job's outputs equal its own render bitwise."""
