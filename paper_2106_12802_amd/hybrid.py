@@ -60,9 +60,12 @@ class HybridFrame:
     (one wavefront over both renders), then fused.  Buffers and the batch are made
     once; render(seed) takes seeds 2 seed and 2 seed + 1 as hybrid_frame does.
     Without a ready network (None, or no parameters) the frame falls back to a plain
-    render with the same number of paths (fallback_spp), seed 2 seed."""
+    render with the same number of paths (fallback_spp), seed 2 seed.  layers=True also
+    keeps the HRLS render layers of Sec. 3.1 (hr_layers [H, W, 9]: emission, diffuse,
+    glossy) and its per-pixel sums of squares (hr_sumsq, the variance layer)."""
 
-    def __init__(self, gs, net: FusionNet | None, W, H, spp_h=4, spp_l=64, depth=DEPTH):
+    def __init__(self, gs, net: FusionNet | None, W, H, spp_h=4, spp_l=64, depth=DEPTH,
+                 layers=False):
         self.net = net
         self.out = _empty((H, W, 3))
         self.fallback = net is None or not net.ready
@@ -73,9 +76,13 @@ class HybridFrame:
             return
         self.hr_rgb, self.hr_aux = _empty((H, W, 3)), _empty((H, W, 7))
         self.lr_rgb = _empty((H // SCALE, W // SCALE, 3))
+        extra = {}
+        if layers:
+            self.hr_layers, self.hr_sumsq = _empty((H, W, 9)), _empty((H, W, 3))
+            extra = dict(out_layers=self.hr_layers, out_sumsq=self.hr_sumsq)
         self.batch = T.Batch([
             dict(scene=gs, W=W, H=H, spp=spp_h, max_depth=depth, seed=0, out_rgb=self.hr_rgb,
-                 out_aux=self.hr_aux),
+                 out_aux=self.hr_aux, **extra),
             dict(scene=gs, W=W // SCALE, H=H // SCALE, spp=spp_l, max_depth=depth, seed=1,
                  out_rgb=self.lr_rgb, want_aux=False)])
 

@@ -228,6 +228,32 @@ def test_hybrid_frame_batch_equals_separate_calls(torch_cuda):
     fr.close()
 
 
+def test_hybrid_frame_with_layers(torch_cuda):
+    """A hybrid frame that keeps the HRLS layers fuses bitwise the same frame; its layers
+    and sums of squares equal those of a single HRLS render with the frame's seed."""
+    import paper_2106_12802_amd as mrs
+    from paper_2106_12802_amd import hybrid as HY
+    torch = torch_cuda
+    gs = mrs.GpuScene(S.procedural(7, spheres=((2, 4),), n_boxes=5, n_lights=2))
+    net = mrs.FusionNet(seed=4)
+    W, H = 160, 96
+    _log("hybrid frame with layers")
+    plain = HY.HybridFrame(gs, net, W, H)
+    fr = HY.HybridFrame(gs, net, W, H, layers=True)
+    a = plain.render(5).clone()
+    b = fr.render(5).clone()
+    lay = torch.empty(H, W, 9, device="cuda")
+    sq = torch.empty(H, W, 3, device="cuda")
+    rgb, _ = mrs.render(gs, W, H, 4, HY.DEPTH, 10, want_aux=False, out_layers=lay,
+                        out_sumsq=sq)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    assert torch.equal(fr.hr_rgb, rgb)
+    assert torch.equal(fr.hr_layers, lay) and torch.equal(fr.hr_sumsq, sq)
+    plain.close()
+    fr.close()
+
+
 def test_fallback_without_network_is_plain_render(torch_cuda):
     import paper_2106_12802_amd as mrs
     from paper_2106_12802_amd import hybrid as HY
