@@ -60,16 +60,41 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
-// Dense append: every lane with `pred` gets a unique index in the queue; one
-// atomic per wave.  Must be reached by all lanes of the wave together.
-__device__ __forceinline__ uint32_t wave_append(bool pred, uint32_t* counter) {
-  const uint64_t m = __ballot(pred);
-  if (m == 0) return 0;
-  const int leader = __ffsll((long long)m) - 1;
-  uint32_t base = 0;
-  if ((int)__lane_id() == leader) base = atomicAdd(counter, (uint32_t)__popcll(m));
-  base = __builtin_amdgcn_readlane(base, leader);
-  return base + lanes_below(m);
+// Dense append to two queues for a block of 4 waves: each lane with its
+// predicate gets a unique index; one atomic per queue per block (a per-wave
+// atomic contends on the one counter chip-wide), and the appended entries of a
+// block stay together in the block's order, so a queue keeps the coherence of
+// the order its rays were read in.  Must be reached by every thread of the
+// block together; the LDS record is free again when it returns.
+struct BlockAppend2 {
+  uint32_t cnt[4][2];
+  uint32_t base[2];
+};
+__device__ __forceinline__ void block_append2(bool pa, bool pb, uint32_t* ca, uint32_t* cb,
+                                              uint32_t& ia, uint32_t& ib, BlockAppend2& sh) {
+  const uint64_t ma = __ballot(pa), mb = __ballot(pb);
+  const int wave = threadIdx.x >> 6;
+  if (__lane_id() == 0) {
+    sh.cnt[wave][0] = (uint32_t)__popcll(ma);
+    sh.cnt[wave][1] = (uint32_t)__popcll(mb);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t ta = 0, tb = 0;
+    for (int w = 0; w < 4; ++w) {
+      const uint32_t a = sh.cnt[w][0], b = sh.cnt[w][1];
+      sh.cnt[w][0] = ta;
+      sh.cnt[w][1] = tb;
+      ta += a;
+      tb += b;
+    }
+    sh.base[0] = ta ? atomicAdd(ca, ta) : 0u;
+    sh.base[1] = tb ? atomicAdd(cb, tb) : 0u;
+  }
+  __syncthreads();
+  ia = sh.base[0] + sh.cnt[wave][0] + lanes_below(ma);
+  ib = sh.base[1] + sh.cnt[wave][1] + lanes_below(mb);
+  __syncthreads();
 }
 
 __device__ __forceinline__ float safe_rcp(float x) {
@@ -819,6 +844,7 @@ __global__ __launch_bounds__(256) void k_shade(const DevJob* __restrict__ jobs, 
   const uint32_t n = q[Q_RAYS + b];
   uint32_t* cnt_next = q + Q_RAYS + b + 1;
   uint32_t* cnt_shadow = q + Q_SHADOW + b;
+  __shared__ BlockAppend2 sh_app;
   for (uint32_t base = blockIdx.x * 256; base < n; base += gridDim.x * 256) {
     const uint32_t qi = base + threadIdx.x;
     Vertex v;
@@ -842,12 +868,12 @@ __global__ __launch_bounds__(256) void k_shade(const DevJob* __restrict__ jobs, 
       if (b == 0 && jobs[j].out_layers)
         lay_buf[slot] = make_float4(v.L.x, v.L.y, v.L.z, (float)v.lobe);
     }
-    const uint32_t ri = wave_append(v.cont, cnt_next);
+    uint32_t ri, si;
+    block_append2(v.cont, v.shad, cnt_next, cnt_shadow, ri, si, sh_app);
     if (v.cont) {
       rays_out[2 * ri] = make_float4(v.x.x, v.x.y, v.x.z, __uint_as_float(slot));
       rays_out[2 * ri + 1] = make_float4(v.wi.x, v.wi.y, v.wi.z, __uint_as_float((j << 24) | v.prim));
     }
-    const uint32_t si = wave_append(v.shad, cnt_shadow);
     if (v.shad) {
       shadow[3 * si] = make_float4(v.x.x, v.x.y, v.x.z, __uint_as_float(slot | (v.li << 24)));
       shadow[3 * si + 1] = make_float4(v.swi.x, v.swi.y, v.swi.z, v.sr);
