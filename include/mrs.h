@@ -294,7 +294,7 @@ mrs_status mrs_profile_read(double ms_out[MRS_NUM_KERNEL_IDS],
 /* Tuning knobs (performance only; results do not depend on them). */
 typedef struct mrs_tuning {
   int32_t chunk_paths;  /* paths resident at once (default 1<<23, at most 1<<26) */
-  int32_t trace_blocks; /* grid size of traversal kernels (default 4096) */
+  int32_t trace_blocks; /* grid size of traversal kernels (default 8192) */
   int32_t schedule;     /* traversal queue: 0 grid-stride (default), 1 per-wave
                            dynamic fetch from a device counter */
   int32_t bvh_leaf_max; /* triangles a BVH4 leaf may group, 1..4 (default 3);

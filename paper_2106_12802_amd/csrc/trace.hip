@@ -1345,7 +1345,7 @@ hipStream_t g_sub[MAX_SUB] = {};
 int g_nsub = 0;
 unsigned long long* g_stats = nullptr;  // device counters shared by every stream
 // defaults: the fastest hybrid 720p frame measured with the clustered BVH
-mrs_tuning g_tune = {1 << 23, 4096, 0, 3, 3, 3, MRS_BVH_PLOC};
+mrs_tuning g_tune = {1 << 23, 8192, 0, 3, 3, 3, MRS_BVH_PLOC};
 std::atomic<bool> g_count_work{false};
 
 template <typename T>
