@@ -216,22 +216,23 @@ def stats_summary(prof_dir, out_path):
 
 
 def cpu_baseline(scene, threads):
-    """The FP64 oracle on the host: the frame's two renders in full, the network on one
-    320x180 HR crop scaled by the 16 crops of a frame."""
+    """The FP64 oracle on the host, the whole hybrid frame: its two renders and the
+    FP64 network on the full 1280x720 frame (inputs: the oracle's own renders)."""
     import numpy as np
     from oracle import cnn, tracer as orc
     osc = orc.OracleScene(scene)
     t0 = time.perf_counter()
     hr = osc.render(*HRLS[:2], HRLS[2], MAX_DEPTH, 2 * SCENE_SEED, nthreads=threads, want_aux=True)
-    osc.render(*LRHS[:2], LRHS[2], MAX_DEPTH, 2 * SCENE_SEED + 1, nthreads=threads, want_aux=False)
+    lr = osc.render(*LRHS[:2], LRHS[2], MAX_DEPTH, 2 * SCENE_SEED + 1, nthreads=threads,
+                    want_aux=False)
     t_render = time.perf_counter() - t0
-    rgb = hr["rgb"].reshape(HRLS[1], HRLS[0], 3)[None, :180, :320]
-    aux = hr["aux"].reshape(HRLS[1], HRLS[0], 7)[None, :180, :320]
-    lr = np.zeros((1, 45, 80, 3))
+    rgb = hr["rgb"].reshape(1, HRLS[1], HRLS[0], 3)
+    aux = hr["aux"].reshape(1, HRLS[1], HRLS[0], 7)
+    lrgb = lr["rgb"].reshape(1, LRHS[1], LRHS[0], 3)
     params = np.random.default_rng(0).uniform(-0.05, 0.05, cnn.num_params())
     t0 = time.perf_counter()
-    cnn.forward(params, rgb, aux, lr)
-    t_cnn = (time.perf_counter() - t0) * 16
+    cnn.forward(params, rgb, aux, lrgb)
+    t_cnn = time.perf_counter() - t0
     paths = HRLS[0] * HRLS[1] * HRLS[2] + LRHS[0] * LRHS[1] * LRHS[2]
     total = t_render + t_cnn
     # the small case (Cornell box 64x64 @16 spp, depth 4: 65,536 paths) on one thread and on all
@@ -243,11 +244,13 @@ def cpu_baseline(scene, threads):
         small.render(64, 64, 16, 4, 1001, nthreads=n)
         small_rate[f"threads_{n}"] = round(65536 / (time.perf_counter() - t0) / 1e6, 4)
     return {"value": round(paths / total / 1e6, 4), "unit": "Mpaths/s", "cores": threads,
+            "host_cpus": os.cpu_count(), "affinity_cpus": len(os.sched_getaffinity(0)),
             "small_case_mpaths_per_s": small_rate,
             "kind": "oracle",
-            "sample": f"renders of the full frame (HRLS {HRLS[0]}x{HRLS[1]}@{HRLS[2]} + LRHS "
-                      f"{LRHS[0]}x{LRHS[1]}@{LRHS[2]}, {paths} paths, FP64: {t_render:.1f} s) + the "
-                      f"FP64 network on one 320x180 crop x 16 ({t_cnn:.1f} s)",
+            "sample": f"the whole frame: FP64 renders (HRLS {HRLS[0]}x{HRLS[1]}@{HRLS[2]} + LRHS "
+                      f"{LRHS[0]}x{LRHS[1]}@{LRHS[2]}, {paths} paths: {t_render:.1f} s) and the "
+                      f"FP64 network on the full frame ({t_cnn:.1f} s; numpy BLAS threads)",
+            "render_s": round(t_render, 2), "network_s": round(t_cnn, 2),
             "ms_per_frame": round(total * 1e3, 1)}
 
 
@@ -870,8 +873,10 @@ def main():
     if not args.no_spp_pairs:
         result["spp_pairs"] = spp_pairs_block(log)
     if not args.no_cpu_baseline:
+        # every CPU this process may run on, at most the 16 that a one-GPU machine grants
         threads = max(1, min(16, len(os.sched_getaffinity(0))))
-        log(f"[bench] timing the FP64 oracle on {threads} host threads")
+        log(f"[bench] timing the FP64 oracle on {threads} host threads (nproc "
+            f"{os.cpu_count()}, affinity {len(os.sched_getaffinity(0))})")
         result["cpu_baseline"] = cpu_baseline(scene, threads)
     print(json.dumps(result), flush=True)
 

@@ -307,6 +307,13 @@ typedef struct mrs_tuning {
                            path by path in one launch (65: never) */
   int32_t bvh_builder;  /* MRS_BVH_PLOC (default) or MRS_BVH_LBVH; applies to
                            scenes built afterwards */
+  int32_t conv_small_tiles; /* 0..2^30 (default 128): a 3x3 network conv whose
+                           output has fewer 16x16-pixel tiles than this (over
+                           the batch) runs on 16x8 tiles of 4 waves with its
+                           output channels split over blocks; otherwise on
+                           16x16 tiles of 8 waves (0: always the large tiles).
+                           Both sum in the same order: outputs are bitwise
+                           the same */
 } mrs_tuning;
 mrs_status mrs_get_tuning(mrs_tuning* out);
 mrs_status mrs_set_tuning(const mrs_tuning* t);
@@ -454,6 +461,25 @@ mrs_status mrs_net_get_state(const mrs_net* net, float* params, float* adam_m, f
 mrs_status mrs_net_set_state(mrs_net* net, const float* params, const float* adam_m,
                              const float* adam_v, int64_t count, int64_t step);
 
+/* Checkpoint files (training resume).  mrs_net_save writes the state of
+ * mrs_net_get_state plus a caller-defined data counter (e.g. the position in
+ * the training data order) to `path`: a 48-byte little-endian header -- magic
+ * "MRSCKPT\0", u32 version 1, i32 architecture (MRS_NET_*), i64 parameter
+ * count, i64 Adam step, u64 data counter, u32 CRC-32 (IEEE 802.3) of the body,
+ * u32 CRC-32 of the 44 header bytes before it -- then the body: the FP32
+ * masters, Adam m and Adam v, `count` values each.  It writes `path`.tmp and
+ * renames it over `path`, so a failed save leaves an existing file intact.
+ * Synchronises the current stream.  NOT_READY without parameters; DEVICE if
+ * the file cannot be written.
+ * mrs_net_load reads and checks the whole file (magic, both checksums,
+ * version, the net's architecture and count, exact length) before it changes
+ * anything: any mismatch returns INVALID_ARGUMENT and leaves the net as it
+ * was.  Then it sets the state as mrs_net_set_state does and stores the data
+ * counter in *data_counter (if not NULL).  Save, load and continue training is
+ * bitwise the same as never having stopped. */
+mrs_status mrs_net_save(const mrs_net* net, const char* path, uint64_t data_counter);
+mrs_status mrs_net_load(mrs_net* net, const char* path, uint64_t* data_counter);
+
 /* ------------------------------------------------------------ metrics */
 
 /* Evaluation metrics of the paper (Sec. 5) between two FP32 device images of
@@ -473,6 +499,18 @@ mrs_status mrs_image_metrics(const float* img_dev, const float* ref_dev, int64_t
  * 1 = FDF, each B*(H/4)*(W/4)*64 values (count must match).  Synchronises. */
 mrs_status mrs_debug_net_activation(const mrs_net* net, int32_t which, float* out_host,
                                     int64_t count);
+
+/* Launches of each network conv kernel since the last reset, counted on the
+ * host when enqueued (so a captured graph counts once): [0] 3x3 LDS conv on
+ * 16x8 tiles, 64-channel input chunks, output channels split over blocks;
+ * [1] 3x3 LDS conv on 16x16 tiles, 64-channel chunks; [2] / [3] the same with
+ * 16 / 8 input channels (the HR and LR input convs); [4] / [5] 3x3 LDS convs
+ * with fewer than 64 output channels (80 / 64 input channels: the
+ * reconstruction convs); [6] / [7] the direct implicit-GEMM conv (64 / 16
+ * output channels per block: the 1x1 fuse conv and shapes the LDS kernels do
+ * not take).  reset != 0 clears the counts after reading them. */
+#define MRS_NUM_CONV_KINDS 8
+mrs_status mrs_debug_conv_launches(int64_t out[MRS_NUM_CONV_KINDS], int32_t reset);
 
 /* Philox4x32-10 on the device: out_dev[4i..4i+3] = philox(ctr_dev[4i..4i+3],
  * key_dev[2i..2i+1]) for i < n.  For bitwise checks against the host. */

@@ -78,7 +78,8 @@ def conv(x, w, b):
     out = np.zeros((B, H, W, w.shape[0]))
     for ky in range(k):
         for kx in range(k):
-            out += xp[:, ky:ky + H, kx:kx + W, :] @ w[:, :, ky, kx].T
+            # a contiguous copy of the tap's weights lets numpy hand the product to BLAS
+            out += xp[:, ky:ky + H, kx:kx + W, :] @ np.ascontiguousarray(w[:, :, ky, kx].T)
     return out + b
 
 
@@ -94,7 +95,7 @@ def conv_backward(x, w, gy):
         for kx in range(k):
             win = xp[:, ky:ky + H, kx:kx + W, :]
             dw[:, :, ky, kx] = np.einsum("bhwo,bhwi->oi", gy, win)
-            dxp[:, ky:ky + H, kx:kx + W, :] += gy @ w[:, :, ky, kx]
+            dxp[:, ky:ky + H, kx:kx + W, :] += gy @ np.ascontiguousarray(w[:, :, ky, kx])
     return dxp[:, p:p + H, p:p + W, :], dw, gy.sum(axis=(0, 1, 2))
 
 

@@ -26,7 +26,9 @@
 //       Schlick Fresnel, sampling of the half vector from D(h)(n.h)
 //   E11 Russian roulette
 //   (offset) rays leave a vertex from a point lifted off the surface along the
-//       geometric normal (Wachter & Binder, Ray Tracing Gems ch. 6)
+//       geometric normal by an amount proportional to the point's magnitude
+//       (this project's own simplified rule, inspired by the offsets of Wachter
+//       & Binder, Ray Tracing Gems ch. 6, which switch to integer-ULP steps)
 //   E12 per-pixel accumulation in sample order
 // Arithmetic is FP64 throughout; the scene's FP32 values are promoted.
 //
@@ -525,10 +527,12 @@ PathOut trace_path(const Scene& sc, bool use_bvh, int W, int H, int px, int py, 
       ns = neg(ns);
     }
     // Origin of the rays leaving this vertex: the hit point lifted along the
-    // geometric normal on the arrival side by 2^-16 * max(1, |x|_inf), the
-    // scale-aware ray offset of Wachter & Binder (Ray Tracing Gems, ch. 6).
-    // Every ray that leaves (NEE and BSDF) has n_g . wi > 0, so it starts on
-    // the correct side of the surface.
+    // geometric normal on the arrival side by 2^-16 * max(1, |x|_inf).  This is
+    // the project's own reading (the paper's renderer is not described): a
+    // single offset proportional to the point's magnitude, simpler than the
+    // offsets of Wachter & Binder (Ray Tracing Gems, ch. 6), which move the
+    // point by integer ULPs away from the origin.  Every ray that leaves (NEE
+    // and BSDF) has n_g . wi > 0, so it starts on the correct side.
     const double lift = std::ldexp(std::max(1.0, std::max(std::fabs(x.x), std::max(std::fabs(x.y),
                                                                        std::fabs(x.z)))), -16);
     const V3 xo = x + ng * lift;

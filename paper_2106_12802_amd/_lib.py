@@ -81,7 +81,7 @@ class Job(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [("chunk_paths", C.c_int32), ("trace_blocks", C.c_int32), ("schedule", C.c_int32),
                 ("bvh_leaf_max", C.c_int32), ("streams", C.c_int32), ("tail_bounce", C.c_int32),
-                ("bvh_builder", C.c_int32)]
+                ("bvh_builder", C.c_int32), ("conv_small_tiles", C.c_int32)]
 
 
 assert C.sizeof(Material) == 32 and C.sizeof(QuadLight) == 56
@@ -147,6 +147,9 @@ def lib():
         "mrs_net_loss_grad_ex": ([P, I32, P, P, P, P, I32, I32, I32, C.c_float, P, P, P], I32),
         "mrs_train_step_ex": ([P, I32, P, P, P, P, I32, I32, C.POINTER(TrainOpts), P], I32),
         "mrs_net_backward": ([P, I32, P, P, P, I32, I32, P, P], I32),
+        "mrs_debug_conv_launches": ([P, I32], I32),
+        "mrs_net_save": ([P, C.c_char_p, U64], I32),
+        "mrs_net_load": ([P, C.c_char_p, P], I32),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(L, name)
@@ -176,7 +179,7 @@ def exported_symbols():
         "mrs_debug_bvh4", "mrs_net_arch_num_params", "mrs_net_create_arch",
         "mrs_net_loss_grad_ex", "mrs_train_step_ex", "mrs_net_backward",
         "mrs_batch_render_begin", "mrs_batch_render_end", "mrs_scene_bvh_builder",
-        "mrs_profile_select",
+        "mrs_profile_select", "mrs_debug_conv_launches", "mrs_net_save", "mrs_net_load",
     ]
 
 

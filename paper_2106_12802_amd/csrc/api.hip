@@ -454,6 +454,12 @@ mrs_status mrs_set_tuning(const mrs_tuning* t) {
   return set_tuning(t);
 }
 
+mrs_status mrs_debug_conv_launches(int64_t* out, int32_t reset) {
+  if (!out) return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_debug_conv_launches: out is NULL");
+  conv_launch_counts(out, reset != 0);
+  return MRS_OK;
+}
+
 mrs_status mrs_debug_philox(int32_t n, const uint32_t* ctr, const uint32_t* key, uint32_t* out) {
   if (n < 0 || (n > 0 && (!ctr || !key || !out)))
     return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_debug_philox: bad arguments");

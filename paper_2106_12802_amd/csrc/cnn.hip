@@ -22,6 +22,7 @@
 // loads the 8 consecutive input channels (one 16-byte load) of pixel l%16 of
 // each row tile for K chunk l/16, and the matching 8 weights of output channel
 // l%16 of each column tile.
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -839,34 +840,47 @@ void launch_adam(float* w, const float* g, float* m, float* v, int64_t n, float 
 }
 
 // Tile plan of a 3x3 conv on k_conv3_lds: 16 x 16 tiles of 8 waves with all
-// output channels per block; when such tiles would occupy fewer than half of
-// the 256 CUs, 16 x 8 tiles of 4 waves with the output channels split over
-// blocks of 32 (two fit a CU at once).  Measured: the 720p LR trunk (240
-// tiles) is 18% faster on the large tiles, the x8 network on a 1024 x 1024
-// image (64 tiles) 19% faster on the small ones.
-#ifndef MRS_CONV_SMALL_BLOCKS
-#define MRS_CONV_SMALL_BLOCKS 128
-#endif
+// output channels per block; when such tiles are fewer than
+// mrs_tuning.conv_small_tiles (default 128: half of the 256 CUs), 16 x 8 tiles
+// of 4 waves with the output channels split over blocks of 32 (two fit a CU at
+// once).  Both plans sum every output in the same K order, so the choice
+// changes speed only.  Measured: the 720p LR trunk (240 tiles) is 18% faster
+// on the large tiles, the x8 network on a 1024 x 1024 image (64 tiles) 19%
+// faster on the small ones.
+namespace {
+std::atomic<int64_t> g_conv_launches[MRS_NUM_CONV_KINDS];
+inline void count_conv(int kind) { g_conv_launches[kind].fetch_add(1, std::memory_order_relaxed); }
+}  // namespace
+
+void conv_launch_counts(int64_t* out, bool reset) {
+  for (int i = 0; i < MRS_NUM_CONV_KINDS; ++i)
+    out[i] = reset ? g_conv_launches[i].exchange(0) : g_conv_launches[i].load();
+}
+
 void launch_conv(const ConvArgs& a, int cout_p, hipStream_t st) {
   if (a.taps == 9 && a.mode != VIEW_CONCAT_UNSHUFFLE &&
       (a.mode != VIEW_PLAIN || a.ca >= a.cin_p)) {
     const int64_t tiles = (int64_t)((a.W + 15) / 16) * ((a.H + 15) / 16) * a.B;
-    if (cout_p >= 64 && a.cin_p % 64 == 0 && tiles < MRS_CONV_SMALL_BLOCKS &&
+    if (cout_p >= 64 && a.cin_p % 64 == 0 && tiles < conv_small_tiles() &&
         try_conv3_lds<64, 2, 8>(a, cout_p, cout_p / 32, st))
-      return;
-    if (cout_p >= 64 ? (try_conv3_lds<64, 4, 16>(a, cout_p, 1, st) ||
-                        try_conv3_lds<16, 4, 16>(a, cout_p, 1, st) ||
-                        try_conv3_lds<8, 4, 16>(a, cout_p, 1, st))
-                     : (try_conv3_lds<80, 1, 16>(a, cout_p, 1, st) ||
-                        try_conv3_lds<64, 1, 16>(a, cout_p, 1, st)))
-      return;
+      return count_conv(0);
+    if (cout_p >= 64) {
+      if (try_conv3_lds<64, 4, 16>(a, cout_p, 1, st)) return count_conv(1);
+      if (try_conv3_lds<16, 4, 16>(a, cout_p, 1, st)) return count_conv(2);
+      if (try_conv3_lds<8, 4, 16>(a, cout_p, 1, st)) return count_conv(3);
+    } else {
+      if (try_conv3_lds<80, 1, 16>(a, cout_p, 1, st)) return count_conv(4);
+      if (try_conv3_lds<64, 1, 16>(a, cout_p, 1, st)) return count_conv(5);
+    }
   }
   const int64_t M = (int64_t)a.B * a.H * a.W;
   const unsigned gx = cdiv64(M, 128);
   if (cout_p >= 64) {
     k_conv<4><<<dim3(gx, cout_p / 64), 256, 0, st>>>(a);
+    count_conv(6);
   } else {
     k_conv<1><<<dim3(gx, cout_p / 16), 256, 0, st>>>(a);
+    count_conv(7);
   }
 }
 

@@ -172,6 +172,10 @@ mrs_status debug_philox(int32_t n, const uint32_t* ctr, const uint32_t* key, uin
 mrs_status get_counters(int64_t* out, bool reset, hipStream_t st);
 void get_tuning(mrs_tuning* t);
 mrs_status set_tuning(const mrs_tuning* t);
+int conv_small_tiles();  // mrs_tuning.conv_small_tiles in force
+// Launches of each network conv kernel instance since the last reset (host
+// counters, in the order of mrs_debug_conv_launches).
+void conv_launch_counts(int64_t* out, bool reset);
 void set_count_work(bool on);
 // metrics.hip: out_dev[0] = sRGB MSE, out_dev[1] = RelMSE (FP64, device)
 mrs_status image_metrics(const float* img, const float* ref, int64_t n, double lam1, double lam2,

@@ -1,6 +1,8 @@
 // Host side of the fusion network: layer table, parameters, forward pass.
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
+#include <cstdio>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -950,6 +952,122 @@ mrs_status mrs_net_set_state(mrs_net* n, const float* params, const float* m, co
   rc = net_refresh_packed(n, st);
   if (rc != MRS_OK) return rc;
   MRS_TRY_HIP(hipStreamSynchronize(st));
+  return MRS_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// CRC-32 of IEEE 802.3 (reflected polynomial 0xEDB88320), table driven.
+uint32_t crc32_update(uint32_t crc, const void* data, size_t n) {
+  static uint32_t table[256];
+  static bool ready = [] {
+    for (uint32_t i = 0; i < 256; ++i) {
+      uint32_t c = i;
+      for (int k = 0; k < 8; ++k) c = (c & 1u) ? 0xEDB88320u ^ (c >> 1) : c >> 1;
+      table[i] = c;
+    }
+    return true;
+  }();
+  (void)ready;
+  const uint8_t* p = static_cast<const uint8_t*>(data);
+  crc = ~crc;
+  for (size_t i = 0; i < n; ++i) crc = table[(crc ^ p[i]) & 0xffu] ^ (crc >> 8);
+  return ~crc;
+}
+
+// Checkpoint file layout (little-endian), 48-byte header then the body:
+//   char magic[8] "MRSCKPT\0", u32 version (1), i32 arch, i64 count,
+//   i64 Adam step, u64 data counter, u32 CRC-32 of the body, u32 CRC-32 of
+//   the 44 header bytes before it; body = count FP32 masters, count Adam m,
+//   count Adam v.
+constexpr char CKPT_MAGIC[8] = {'M', 'R', 'S', 'C', 'K', 'P', 'T', '\0'};
+constexpr uint32_t CKPT_VERSION = 1;
+struct CkptHeader {
+  char magic[8];
+  uint32_t version;
+  int32_t arch;
+  int64_t count;
+  int64_t step;
+  uint64_t data_counter;
+  uint32_t body_crc;
+  uint32_t header_crc;
+};
+static_assert(sizeof(CkptHeader) == 48, "checkpoint header layout");
+
+}  // namespace
+
+extern "C" {
+
+mrs_status mrs_net_save(const mrs_net* n, const char* path, uint64_t data_counter) {
+  if (!n || !path) return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_net_save: NULL argument");
+  if (!n->has_params) return fail(MRS_ERR_NOT_READY, "mrs_net_save: no parameters");
+  const int64_t cnt = n->nparams;
+  std::vector<float> body(3 * (size_t)cnt);
+  int64_t step = 0;
+  mrs_status rc = mrs_net_get_state(n, body.data(), body.data() + cnt, body.data() + 2 * cnt, cnt,
+                                    &step);
+  if (rc != MRS_OK) return rc;
+  CkptHeader h;
+  std::memcpy(h.magic, CKPT_MAGIC, 8);
+  h.version = CKPT_VERSION;
+  h.arch = n->arch;
+  h.count = cnt;
+  h.step = step;
+  h.data_counter = data_counter;
+  h.body_crc = crc32_update(0u, body.data(), sizeof(float) * body.size());
+  h.header_crc = crc32_update(0u, &h, offsetof(CkptHeader, header_crc));
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "wb");
+  if (!f) return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_net_save: cannot open " + tmp);
+  const bool ok = std::fwrite(&h, sizeof h, 1, f) == 1 &&
+                  std::fwrite(body.data(), sizeof(float), body.size(), f) == body.size();
+  if (std::fclose(f) != 0 || !ok) {
+    std::remove(tmp.c_str());
+    return fail(MRS_ERR_DEVICE, "mrs_net_save: write to " + tmp + " failed");
+  }
+  if (std::rename(tmp.c_str(), path) != 0) {
+    std::remove(tmp.c_str());
+    return fail(MRS_ERR_DEVICE, std::string("mrs_net_save: cannot rename to ") + path);
+  }
+  return MRS_OK;
+}
+
+mrs_status mrs_net_load(mrs_net* n, const char* path, uint64_t* data_counter) {
+  if (!n || !path) return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_net_load: NULL argument");
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return fail(MRS_ERR_INVALID_ARGUMENT, std::string("mrs_net_load: cannot open ") + path);
+  CkptHeader h;
+  std::vector<float> body;
+  std::string err;
+  if (std::fread(&h, sizeof h, 1, f) != 1 || std::memcmp(h.magic, CKPT_MAGIC, 8) != 0) {
+    err = "not a checkpoint file";
+  } else if (h.header_crc != crc32_update(0u, &h, offsetof(CkptHeader, header_crc))) {
+    err = "header checksum mismatch";
+  } else if (h.version != CKPT_VERSION) {
+    err = "unsupported checkpoint version " + std::to_string(h.version);
+  } else if (h.arch != n->arch || h.count != n->nparams) {
+    err = "checkpoint of another network (arch " + std::to_string(h.arch) + ", " +
+          std::to_string(h.count) + " parameters)";
+  } else if (h.step < 0) {
+    err = "negative step";
+  } else {
+    body.resize(3 * (size_t)h.count);
+    char extra;
+    if (std::fread(body.data(), sizeof(float), body.size(), f) != body.size() ||
+        std::fread(&extra, 1, 1, f) != 0)
+      err = "truncated or oversized file";
+    else if (h.body_crc != crc32_update(0u, body.data(), sizeof(float) * body.size()))
+      err = "body checksum mismatch";
+  }
+  std::fclose(f);
+  if (!err.empty()) return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_net_load: " + err);
+  const int64_t cnt = h.count;
+  mrs_status rc = mrs_net_set_state(n, body.data(), body.data() + cnt, body.data() + 2 * cnt, cnt,
+                                    h.step);
+  if (rc != MRS_OK) return rc;
+  if (data_counter) *data_counter = h.data_counter;
   return MRS_OK;
 }
 

@@ -7,8 +7,9 @@
 //   extend     closest-hit LBVH traversal, LDS short stack      (per live ray)
 //   shade      emission, first-hit features, next-event estimation sample,
 //              BSDF sample, Russian roulette; appends the surviving rays and
-//              the shadow rays to dense queues with one atomic per wave
-//              (ballot + mbcnt prefix)                          (per live ray)
+//              the shadow rays to dense queues with one atomic per queue per
+//              4-wave block (wave ballot + mbcnt prefix, then an LDS prefix
+//              over the block's waves)                          (per live ray)
 //   shadow     any-hit traversal; an unoccluded sample adds its contribution
 //              to its own path's radiance                       (per shadow ray)
 //   accumulate per-pixel sums in sample order                   (per pixel)
@@ -1327,11 +1328,16 @@ struct Plan {
   int blocks_k;
 };
 
+// A shadow ray carries its path slot in the low 24 bits of a word (the light
+// index in the high 8), so a sub-chunk holds at most 2^24 path slots; larger
+// chunk_paths values take more super-chunks instead.
+constexpr int64_t MAX_SUB_PATHS = int64_t(1) << 24;
+
 Plan make_plan(const mrs_tuning& tu, int64_t total) {
   Plan p;
   p.K = std::max(1, std::min<int>(tu.streams, (int)(total / 65536)));
   const int64_t C = std::max<int64_t>(1, std::min<int64_t>(tu.chunk_paths, total));
-  p.Cs = ((C + p.K - 1) / p.K + 255) & ~(int64_t)255;
+  p.Cs = std::min(MAX_SUB_PATHS, ((C + p.K - 1) / p.K + 255) & ~(int64_t)255);
   p.blocks_k = std::max(1, (tu.trace_blocks + p.K - 1) / p.K);
   return p;
 }
@@ -1345,7 +1351,8 @@ hipStream_t g_sub[MAX_SUB] = {};
 int g_nsub = 0;
 unsigned long long* g_stats = nullptr;  // device counters shared by every stream
 // defaults: the fastest hybrid 720p frame measured with the clustered BVH
-mrs_tuning g_tune = {1 << 23, 8192, 0, 3, 3, 3, MRS_BVH_PLOC};
+mrs_tuning g_tune = {1 << 23, 8192, 0, 3, 3, 3, MRS_BVH_PLOC, 128};
+std::atomic<int> g_conv_small{128};  // g_tune.conv_small_tiles, read without the lock
 std::atomic<bool> g_count_work{false};
 
 template <typename T>
@@ -1900,9 +1907,14 @@ mrs_status set_tuning(const mrs_tuning* t) {
     return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_set_tuning: tail_bounce must be in [1, 65]");
   if (t->bvh_builder != MRS_BVH_LBVH && t->bvh_builder != MRS_BVH_PLOC)
     return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_set_tuning: bvh_builder must be 0 or 1");
+  if (t->conv_small_tiles < 0 || t->conv_small_tiles > (1 << 30))
+    return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_set_tuning: conv_small_tiles must be in [0, 2^30]");
   std::lock_guard<std::mutex> lk(g_mu);
   g_tune = *t;
+  g_conv_small = t->conv_small_tiles;
   return MRS_OK;
 }
+
+int conv_small_tiles() { return g_conv_small.load(std::memory_order_relaxed); }
 
 }  // namespace mrs

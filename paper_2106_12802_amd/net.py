@@ -2,6 +2,7 @@
 from __future__ import annotations
 
 import ctypes as C
+import os
 
 import numpy as np
 
@@ -136,26 +137,20 @@ class FusionNet:
                                           self.num_params, int(step)))
         self.ready = True
 
-    def save(self, path):
-        """Checkpoint file: versioned header, FP32 params, Adam m and v, step, checksum."""
-        import hashlib
-        p, m, v, step = self.get_state()
-        body = p.tobytes() + m.tobytes() + v.tobytes()
-        header = np.array([0x4D52534E, 1, self.num_params, step], np.int64).tobytes()
-        with open(path, "wb") as f:
-            f.write(header + body + hashlib.sha256(header + body).digest())
+    def save(self, path, data_counter=0):
+        """Resumable checkpoint file (mrs_net_save): versioned header, FP32 masters,
+        Adam m and v, step, a data counter and CRC-32 checksums."""
+        L.use_current_stream()
+        L.check(L.lib().mrs_net_save(self.handle, os.fsencode(str(path)), int(data_counter)))
 
     def load(self, path):
-        import hashlib
-        raw = open(path, "rb").read()
-        header, body, digest = raw[:32], raw[32:-32], raw[-32:]
-        magic, version, n, step = np.frombuffer(header, np.int64)
-        if magic != 0x4D52534E or version != 1 or n != self.num_params:
-            raise ValueError("not a checkpoint of this network")
-        if hashlib.sha256(header + body).digest() != digest:
-            raise ValueError("checkpoint checksum mismatch")
-        arr = np.frombuffer(body, np.float32).reshape(3, n)
-        self.set_state(arr[0], arr[1], arr[2], int(step))
+        """Restores a checkpoint of this architecture (mrs_net_load); returns its
+        data counter.  A damaged or foreign file raises and changes nothing."""
+        counter = C.c_uint64()
+        L.use_current_stream()
+        L.check(L.lib().mrs_net_load(self.handle, os.fsencode(str(path)), C.byref(counter)))
+        self.ready = True
+        return int(counter.value)
 
     def save_weights(self, path):
         """Weights file: magic, version, count, FP32 parameters, SHA-256 of all before it."""

@@ -129,6 +129,11 @@ def render(scene: GpuScene, W, H, spp, max_depth, seed, want_aux=True, **kw):
     return rgb, aux
 
 
+def release_workspaces():
+    """Free the per-stream render workspaces (mrs_release_workspaces; synchronises)."""
+    L.check(L.lib().mrs_release_workspaces())
+
+
 def counters(reset=False):
     out = np.zeros(L.NUM_COUNTERS, np.int64)
     L.use_current_stream()
@@ -168,7 +173,7 @@ def profile_read():
 
 
 TUNING_KEYS = ("chunk_paths", "trace_blocks", "schedule", "bvh_leaf_max", "streams", "tail_bounce",
-               "bvh_builder")
+               "bvh_builder", "conv_small_tiles")
 BVH_BUILDERS = {"lbvh": 0, "ploc": 1}
 
 
@@ -179,18 +184,31 @@ def get_tuning():
 
 
 def set_tuning(chunk_paths=None, trace_blocks=None, schedule=None, bvh_leaf_max=None,
-               streams=None, tail_bounce=None, bvh_builder=None):
-    """bvh_builder: 0 / "lbvh" (Karras) or 1 / "ploc" (clustering, the default)."""
+               streams=None, tail_bounce=None, bvh_builder=None, conv_small_tiles=None):
+    """bvh_builder: 0 / "lbvh" (Karras) or 1 / "ploc" (clustering, the default);
+    conv_small_tiles: the network's 3x3 convs with fewer 16x16 output tiles than
+    this run on the small-tile plan (0: never)."""
     cur = get_tuning()
     if isinstance(bvh_builder, str):
         bvh_builder = BVH_BUILDERS[bvh_builder]
     new = dict(chunk_paths=chunk_paths, trace_blocks=trace_blocks, schedule=schedule,
                bvh_leaf_max=bvh_leaf_max, streams=streams, tail_bounce=tail_bounce,
-               bvh_builder=bvh_builder)
+               bvh_builder=bvh_builder, conv_small_tiles=conv_small_tiles)
     t = L.Tuning()
     for k in TUNING_KEYS:
         setattr(t, k, int(new[k] if new[k] is not None else cur[k]))
     L.check(L.lib().mrs_set_tuning(C.byref(t)))
+
+
+CONV_KINDS = ("lds64_small", "lds64_large", "lds16", "lds8", "lds80_narrow", "lds64_narrow",
+              "direct64", "direct16")
+
+
+def conv_launches(reset=False):
+    """{conv kernel instance: launches} counted since the last reset (host side)."""
+    out = np.zeros(len(CONV_KINDS), np.int64)
+    L.check(L.lib().mrs_debug_conv_launches(out.ctypes.data_as(C.c_void_p), int(reset)))
+    return dict(zip(CONV_KINDS, out.tolist()))
 
 
 def philox(ctr, key):

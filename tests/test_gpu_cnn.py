@@ -78,6 +78,59 @@ def test_forward_parity(net, torch_cuda, B, H, W):
     assert e_out <= 5e-3
 
 
+@pytest.fixture
+def tuning_restored(torch_cuda):
+    import paper_2106_12802_amd as mrs
+    old = mrs.get_tuning()
+    yield mrs
+    mrs.set_tuning(**old)
+
+
+# (B, H, W, conv_small_tiles): 0 forces the 16x16-tile, 8-wave LDS conv at the
+# small sizes; None keeps the default threshold (128 tiles), which 8 frames of
+# 256x256 (LR 64x64: 8 x 16 = 128 tiles) reach on their own, like the 720p frame
+# (LR 320x180: 240 tiles).
+@pytest.mark.parametrize("B,H,W,small", [(2, 16, 24, 0), (1, 96, 128, 0), (8, 256, 256, None)])
+def test_forward_parity_large_tile_plan(net, tuning_restored, B, H, W, small):
+    """The LR trunk conv that the 720p frame runs (k_conv3_lds on 16x16 tiles of
+    8 waves, ~121 KB of LDS, 6 tile and 9 weight chunks in flight per thread)
+    against the FP64 oracle, and bitwise equal to the small-tile plan."""
+    from oracle import cnn
+    from paper_2106_12802_amd.tracer import conv_launches
+    mrs = tuning_restored
+    import torch
+    if small is not None:
+        mrs.set_tuning(conv_small_tiles=small)
+    lr_tiles = B * ((W // 4 + 15) // 16) * ((H // 4 + 15) // 16)
+    _log(f"cnn large-tile plan {B}x{H}x{W} (LR tiles {lr_tiles}, conv_small_tiles "
+         f"{mrs.get_tuning()['conv_small_tiles']})")
+    hr, aux, lr = _inputs(B * H + W + 7, B, H, W)
+    params = net.get_params().astype(np.float64)
+    t = [torch.from_numpy(a).cuda() for a in (hr, aux, lr)]
+    conv_launches(reset=True)
+    out = net.fuse(*t)
+    torch.cuda.synchronize()
+    ran = conv_launches(reset=True)
+    _log(f"  conv instances: {ran}")
+    # 32 trunk convs + the 64->256 upscaling conv on the large tiles, none on the small
+    assert ran["lds64_large"] == 33 and ran["lds64_small"] == 0, ran
+    g = out.cpu().numpy().astype(np.float64)
+    f0 = net.activation(0, (B, H // 4, W // 4, 64))
+    fdf = net.activation(1, (B, H // 4, W // 4, 64))
+    o, acts = cnn.forward(params, hr, aux, lr, keep=True)
+    e_out, e_f0, e_fdf = _rel_l2(g, o), _rel_l2(f0, acts["f0"]), _rel_l2(fdf, acts["fdf"])
+    _log(f"  rel L2 out {e_out:.2e}, F0 {e_f0:.2e}, FDF {e_fdf:.2e}")
+    assert e_f0 <= 5e-3 and e_fdf <= 5e-3
+    assert e_out <= 5e-3
+    # the tile plan is a tuning choice: the small-tile plan sums in the same order
+    mrs.set_tuning(conv_small_tiles=1 << 30)
+    out_small = net.fuse(*t)
+    torch.cuda.synchronize()
+    ran = conv_launches(reset=True)
+    assert ran["lds64_small"] == 33 and ran["lds64_large"] == 0, ran
+    assert torch.equal(out_small, out)
+
+
 def test_fuse_not_ready_and_validation(torch_cuda):
     import ctypes
     import paper_2106_12802_amd as mrs
@@ -140,8 +193,8 @@ def test_gradient_parity(torch_cuda, B, H, W):
     # Each BF16-stored gradient tensor adds ~2^-9 sqrt(2) = 2.8e-3 relative error;
     # the encoders sit ~38 such tensors below the loss (rec, up, 32 trunk convs,
     # fuse), so ~1.7e-2 in quadrature, plus ReLU-mask disagreements between the
-    # BF16 and FP64 forwards (a few pixels of a small batch): 5e-2 per layer,
-    # 1e-2 for the whole gradient.
+    # BF16 and FP64 forwards (a few pixels of a small batch): 4e-2 per layer
+    # (measured worst 1.9e-2, res1a), 1e-2 for the whole gradient.
     errs = {}
     for name, a, b in _layer_slices():
         errs[name] = _rel_l2(g_gpu[a:b].astype(np.float64), g_ref[a:b])
@@ -150,7 +203,7 @@ def test_gradient_parity(torch_cuda, B, H, W):
     _log(f"grad {B}x{H}x{W}: rel L2 all {e_all:.2e}; worst {worst} {errs[worst]:.2e}; " +
          " ".join(f"{k}:{v:.1e}" for k, v in errs.items() if not k.startswith("res") or k in
                   ("res0a", "res7b", "res15b")))
-    assert all(v <= 5e-2 for v in errs.values()), errs
+    assert all(v <= 4e-2 for v in errs.values()), errs
     assert e_all <= 1e-2
 
 
@@ -185,12 +238,47 @@ def test_checkpoint_resume_bitwise(torch_cuda, tmp_path):
     b = mrs.FusionNet(seed=9)
     for _ in range(3):
         b.train_step(*t, lr=1e-3)
-    b.save(str(tmp_path / "ck.bin"))
+    b.save(str(tmp_path / "ck.bin"), data_counter=12345)
     c = mrs.FusionNet()
-    c.load(str(tmp_path / "ck.bin"))
+    assert c.load(str(tmp_path / "ck.bin")) == 12345
     for _ in range(3):
         c.train_step(*t, lr=1e-3)
     pa, ma, va, sa = a.get_state()
     pc, mc, vc, sc = c.get_state()
     assert sa == sc == 6
     assert np.array_equal(pa, pc) and np.array_equal(ma, mc) and np.array_equal(va, vc)
+
+
+def test_checkpoint_file_checks(torch_cuda, tmp_path):
+    """mrs_net_save / mrs_net_load: the header layout is the documented one; a
+    flipped bit in the body or the header, a truncated or extended file and a
+    missing file are refused, and a refused load leaves the net unchanged."""
+    import struct
+    import zlib
+    import paper_2106_12802_amd as mrs
+    from paper_2106_12802_amd._lib import MrsError
+    net = mrs.FusionNet(seed=3)
+    path = tmp_path / "ck.bin"
+    net.save(str(path), data_counter=7)
+    raw = path.read_bytes()
+    n = net.num_params
+    assert len(raw) == 48 + 12 * n
+    magic, ver, arch, count, step, ctr, body_crc, head_crc = struct.unpack("<8sIiqqQII", raw[:48])
+    assert (magic, ver, arch, count, step, ctr) == (b"MRSCKPT\0", 1, 0, n, 0, 7)
+    assert body_crc == zlib.crc32(raw[48:]) and head_crc == zlib.crc32(raw[:44])
+    assert np.array_equal(np.frombuffer(raw[48:48 + 4 * n], np.float32), net.get_params())
+    other = mrs.FusionNet(seed=4)
+    before = other.get_params()
+    bad = tmp_path / "bad.bin"
+    for what, data in [("body checksum", raw[:100] + bytes([raw[100] ^ 1]) + raw[101:]),
+                       ("header checksum", raw[:30] + bytes([raw[30] ^ 4]) + raw[31:]),
+                       ("truncated", raw[:-4]), ("oversized", raw + b"x"),
+                       ("not a checkpoint", b"MRSWGHT" + raw[7:])]:
+        bad.write_bytes(data)
+        with pytest.raises(MrsError, match=what):
+            other.load(str(bad))
+        assert np.array_equal(other.get_params(), before), what
+    with pytest.raises(MrsError, match="cannot open"):
+        other.load(str(tmp_path / "missing.bin"))
+    assert other.load(str(path)) == 7
+    assert np.array_equal(other.get_params(), net.get_params())

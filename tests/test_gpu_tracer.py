@@ -447,6 +447,27 @@ def test_window_is_crop_and_chunking_invariant(mrs, torch_cuda):
     assert torch_cuda.equal(again, full)  # deterministic run to run
 
 
+def test_sub_chunks_beyond_2_24_paths(mrs, torch_cuda):
+    """A shadow ray carries its path slot in 24 bits next to its light index; a
+    tuning asking for more resident paths per sub-chunk than that (one stream,
+    2^25 paths) is cut into more super-chunks instead, and a multi-light render
+    of 17.8 M paths is bitwise the one of the default tuning."""
+    scene = S.procedural(7, spheres=((2, 3),), n_boxes=6, n_lights=3)
+    gs = mrs.GpuScene(scene)
+    ref, _ = mrs.render(gs, 1024, 1024, 17, 2, 31, want_aux=False)
+    old = mrs.get_tuning()
+    try:
+        mrs.set_tuning(chunk_paths=1 << 25, streams=1)
+        big, _ = mrs.render(gs, 1024, 1024, 17, 2, 31, want_aux=False)
+        mrs.set_tuning(chunk_paths=1 << 26, streams=2)
+        big2, _ = mrs.render(gs, 1024, 1024, 17, 2, 31, want_aux=False)
+        torch_cuda.cuda.synchronize()
+    finally:
+        mrs.set_tuning(**old)
+    mrs.release_workspaces()
+    assert torch_cuda.equal(big, ref) and torch_cuda.equal(big2, ref)
+
+
 def test_fp64_accumulation_matches(mrs, oracle_tracer, torch_cuda):
     scene = S.cornell(3)
     gs = mrs.GpuScene(scene)
@@ -458,6 +479,35 @@ def test_fp64_accumulation_matches(mrs, oracle_tracer, torch_cuda):
     assert np.allclose(a, b, rtol=1e-5, atol=1e-7)
     o = oracle_tracer.OracleScene(scene).render(16, 16, 64, 4, 5)
     assert np.mean(np.all(rel_ok(b.reshape(-1, 3), o["rgb"]), -1)) >= 0.99
+
+
+@pytest.mark.parametrize("case", ["cornell", "procedural"])
+def test_fp64_auto_parity_at_1024_spp(mrs, oracle_tracer, torch_cuda, case):
+    """At spp >= 1024 the pixel sums switch to FP64 by themselves (Q16, the path
+    every reference and training target takes): the automatic choice equals
+    forced FP64 bitwise, and the image holds the parity bar element-wise against
+    the FP64 oracle (99.9% of pixels within 1e-4, mean within 1e-5)."""
+    if case == "cornell":
+        scene, W, H, D, win = S.cornell(1), 32, 32, 4, None
+    else:  # a 40 x 24 window of the 1280 x 720 bench scene (ground, spheres, boxes)
+        scene, W, H, D, win = S.procedural(7), 1280, 720, 8, (600, 330, 40, 24)
+    spp, seed = 1024, 2 ** 40 + 3
+    gs = mrs.GpuScene(scene)
+    auto, aux = mrs.render(gs, W, H, spp, D, seed, window=win)
+    forced, _ = mrs.render(gs, W, H, spp, D, seed, window=win, accum_fp64=1, want_aux=False)
+    torch_cuda.cuda.synchronize()
+    assert torch_cuda.equal(auto, forced)
+    g_rgb = auto.cpu().numpy().reshape(-1, 3).astype(np.float64)
+    g_aux = aux.cpu().numpy().reshape(-1, 7).astype(np.float64)
+    pix = None
+    if win is not None:
+        x0, y0, ww, wh = win
+        pix = ((np.arange(y0, y0 + wh)[:, None] * W) + np.arange(x0, x0 + ww)[None, :]).ravel()
+    o = oracle_tracer.OracleScene(scene).render(W, H, spp, D, seed, pixels=pix)
+    frac, mean_rel, aux_frac = _parity(g_rgb, g_aux, o, f"{case} @1024 spp (FP64 sums)")
+    assert frac >= 0.999
+    assert mean_rel <= 1e-5
+    assert aux_frac >= 0.999
 
 
 def test_counters_and_no_overflow(mrs, torch_cuda):
