@@ -197,6 +197,26 @@ mrs_status mrs_render_ex(const mrs_scene* scene, int32_t W, int32_t H, int32_t s
                          int32_t max_depth, uint64_t seed, const mrs_render_opts* opts,
                          float* out_rgb_dev, float* out_aux_dev);
 
+/* mrs_render_ex for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same arguments, validation and results -- bitwise those of mrs_render_ex --
+ * but the call performs no device allocation.  Its workspace is a fixed array
+ * in the library's device code (each GPU that loads the library holds its own
+ * copy, about 170 MB, until the process ends): at most 2^18 resident paths
+ * (any spp: the render loops over super-chunks), 512 traversal blocks, the
+ * caller's stream only (no internal sub-chunk streams), and 2^19 * 13 * 8
+ * bytes (54.5 MB) of pixel sums: 13 values per window pixel (22 with render
+ * layers) at 8 bytes with FP64 sums (spp >= 1024) or 4 with FP32 sums, i.e.
+ * windows of up to 2^19 pixels with FP64 sums, 2^20 with FP32 sums; a larger
+ * window returns INVALID_ARGUMENT before anything is enqueued (render such
+ * images in windows: a window is bitwise a crop of the full image).  Every call on one GPU shares that GPU's array:
+ * calls that overlap on one GPU (other streams, other threads) race and must
+ * be ordered by the caller.  Its counters are not added to mrs_get_counters
+ * and its kernels are not timed by mrs_profile_*. */
+mrs_status mrs_render_ex_noalloc(const mrs_scene* scene, int32_t W, int32_t H, int32_t spp,
+                                 int32_t max_depth, uint64_t seed, const mrs_render_opts* opts,
+                                 float* out_rgb_dev, float* out_aux_dev);
+
 /* ------------------------------------------------------------ batches */
 
 /* One render of a batch: the arguments of mrs_render_ex. */

@@ -149,6 +149,7 @@ def lib():
         "mrs_net_backward": ([P, I32, P, P, P, I32, I32, P, P], I32),
         "mrs_debug_conv_launches": ([P, I32], I32),
         "mrs_net_save": ([P, C.c_char_p, U64], I32),
+        "mrs_render_ex_noalloc": ([P, I32, I32, I32, I32, U64, C.POINTER(RenderOpts), P, P], I32),
         "mrs_net_load": ([P, C.c_char_p, P], I32),
     }
     for name, (args, res) in sigs.items():
@@ -180,6 +181,7 @@ def exported_symbols():
         "mrs_net_loss_grad_ex", "mrs_train_step_ex", "mrs_net_backward",
         "mrs_batch_render_begin", "mrs_batch_render_end", "mrs_scene_bvh_builder",
         "mrs_profile_select", "mrs_debug_conv_launches", "mrs_net_save", "mrs_net_load",
+        "mrs_render_ex_noalloc",
     ]
 
 

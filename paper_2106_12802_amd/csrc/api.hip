@@ -353,6 +353,16 @@ mrs_status mrs_render_ex(const mrs_scene* s, int32_t W, int32_t H, int32_t spp, 
   return render(s, a, current_stream());
 }
 
+mrs_status mrs_render_ex_noalloc(const mrs_scene* s, int32_t W, int32_t H, int32_t spp,
+                                 int32_t max_depth, uint64_t seed, const mrs_render_opts* opts,
+                                 float* out_rgb, float* out_aux) {
+  RenderArgs a;
+  mrs_status rc = validate_render("mrs_render_ex_noalloc", s, W, H, spp, max_depth, seed, opts,
+                                  out_rgb, out_aux, &a);
+  if (rc != MRS_OK) return rc;
+  return render_noalloc(s, a, current_stream());
+}
+
 mrs_status mrs_batch_create(const mrs_job* jobs, int32_t n, mrs_batch** out) {
   if (!out) return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_batch_create: out is NULL");
   *out = nullptr;

@@ -154,6 +154,8 @@ struct RenderArgs {
   float* out_layers;
 };
 mrs_status render(const mrs_scene* s, const RenderArgs& a, hipStream_t st);
+// The same render with its workspace in a fixed device array (no allocation).
+mrs_status render_noalloc(const mrs_scene* s, const RenderArgs& a, hipStream_t st);
 DevJob make_job(const mrs_scene* s, const RenderArgs& a);
 // a batch of validated jobs: job table, accumulators and its own workspace
 mrs_status batch_create(const std::vector<DevJob>& jobs, mrs_batch** out);
@@ -196,6 +198,13 @@ enum KernelId {
   KID_TRAIN_BWD = 11,
   KID_TRAIN_ADAM = 12,
   KID_TAIL = 13,
+};
+// While a ProfPause is alive on a thread, its launches record no timing events.
+struct ProfPause {
+  ProfPause();
+  ~ProfPause();
+  ProfPause(const ProfPause&) = delete;
+  ProfPause& operator=(const ProfPause&) = delete;
 };
 void prof_begin(int id, hipStream_t st);
 void prof_end(int id, hipStream_t st);

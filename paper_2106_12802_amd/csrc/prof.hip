@@ -13,6 +13,7 @@ struct Pending {
 };
 
 bool g_on = false;
+thread_local int t_paused = 0;  // ProfPause scopes open on this thread
 uint32_t g_mask = 0xffffffffu;
 std::vector<Pending> g_pending;
 std::vector<hipEvent_t> g_free;
@@ -51,8 +52,11 @@ void drain() {
 
 }  // namespace
 
+ProfPause::ProfPause() { ++t_paused; }
+ProfPause::~ProfPause() { --t_paused; }
+
 void prof_begin(int id, hipStream_t st) {
-  if (!g_on || id < 0 || id >= MRS_NUM_KERNEL_IDS || !((g_mask >> id) & 1u)) return;
+  if (!g_on || t_paused || id < 0 || id >= MRS_NUM_KERNEL_IDS || !((g_mask >> id) & 1u)) return;
   hipEvent_t e = take();
   if (e && hipEventRecord(e, st) == hipSuccess) {
     g_open[id] = e;
@@ -64,7 +68,7 @@ void prof_begin(int id, hipStream_t st) {
 }
 
 void prof_end(int id, hipStream_t st) {
-  if (!g_on || id < 0 || id >= MRS_NUM_KERNEL_IDS || !g_open[id]) return;
+  if (!g_on || t_paused || id < 0 || id >= MRS_NUM_KERNEL_IDS || !g_open[id]) return;
   hipEvent_t e = take();
   if (e && hipEventRecord(e, st) == hipSuccess) {
     g_pending.push_back({id, g_open[id], e});

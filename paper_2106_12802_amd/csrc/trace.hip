@@ -1313,6 +1313,7 @@ struct Workspace {
   uint32_t* q = nullptr;  // MAX_SUB blocks of Q_WORDS counters
   char* acc = nullptr;    // per-job accumulators (single renders)
   DevJob* one = nullptr;  // device copy of the job of a single render
+  unsigned long long* stats = nullptr;  // counters the kernels add to (g_stats)
   int nsub = 0;           // sub-chunk join events created
   hipEvent_t ev_fork = nullptr;
   hipEvent_t ev_join[MAX_SUB] = {};
@@ -1396,6 +1397,7 @@ mrs_status ensure_stats() {
 mrs_status ws_ensure(Workspace& w, size_t paths, int threads, int nsub) {
   mrs_status rc = ensure_stats();
   if (rc != MRS_OK) return rc;
+  w.stats = g_stats;
   if (!w.q) {
     MRS_TRY_HIP(hipMalloc(&w.q, sizeof(uint32_t) * Q_WORDS * MAX_SUB));
     MRS_TRY_HIP(hipMalloc(&w.one, sizeof(DevJob)));
@@ -1502,9 +1504,9 @@ mrs_status sum_chunk(Workspace& ws, const DevJob* d_jobs, const std::vector<DevJ
         jobs[jhi].pix_first + (u.lo + (int64_t)u.n - 1 - jobs[jhi].first) / jobs[jhi].spp + 1;
     prof_begin(KID_ACCUMULATE, st);
     k_accumulate<<<cdiv((size_t)(pix_hi - pix_lo), 256), 256, 0, st>>>(
-        d_jobs, nj, u.lo, u.n, pix_lo, pix_hi, u.L, u.aux, u.lay, acc, g_stats);
+        d_jobs, nj, u.lo, u.n, pix_lo, pix_hi, u.L, u.aux, u.lay, acc, ws.stats);
     prof_end(KID_ACCUMULATE, st);
-    k_tally<<<1, 64, 0, st>>>(u.q, nwave, g_stats, u.n);
+    k_tally<<<1, 64, 0, st>>>(u.q, nwave, ws.stats, u.n);
   }
   // the next super-chunk (or render) reuses the slices once these sums have read them
   if (used > 0 && sub[0].s != st) MRS_TRY_HIP(hipEventRecord(ws.ev_fork, st));
@@ -1531,7 +1533,7 @@ mrs_status begin_batch(Workspace& ws, const mrs_tuning& tu, const DevJob* d_jobs
   const int nwave = std::min(tu.tail_bounce, max_depth + 1);
   const int dyn = tu.schedule;
   const bool count = g_count_work.load();
-  unsigned long long* stats = g_stats;
+  unsigned long long* stats = ws.stats;
   const size_t spill_k = (size_t)P.blocks_k * TB * (MAX_STACK4 - LDS_STACK);
   k_zero_words<<<std::min(4096u, cdiv(acc_bytes / 4, 256)), 256, 0, st>>>((uint32_t*)acc,
                                                                           acc_bytes / 4);
@@ -1739,6 +1741,115 @@ mrs_status render(const mrs_scene* s, const RenderArgs& a, hipStream_t st) {
   if (rc != MRS_OK) return rc;
   const size_t ab = acc_bytes_of(npix, a.fp64, a.out_layers != nullptr);
   if ((rc = ws_ensure_acc(ws, ab)) != MRS_OK) return rc;
+  k_store_job<<<1, 64, 0, st>>>(J, ws.one);
+  std::vector<DevJob> jobs{J};
+  return launch_batch(ws, tu, ws.one, jobs, ws.acc, ab, st);
+}
+
+// ------------------------------------------------------------ static workspace
+// mrs_render_ex_noalloc keeps its whole workspace in one file-scope device
+// array: every GPU that loads the library holds its own copy until the process
+// ends, and the call allocates nothing.  Capacity: NOALLOC_PATHS resident path
+// slots (any spp: more super-chunks), NOALLOC_BLOCKS traversal blocks, and
+// NOALLOC_ACC_BYTES of pixel sums (13 FP64 values for each of 2^19 pixels).
+constexpr int64_t NOALLOC_PATHS = int64_t(1) << 18;
+constexpr int NOALLOC_BLOCKS = 512;
+constexpr size_t NOALLOC_ACC_BYTES = size_t(13) * 8 << 19;
+constexpr size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
+// path state per slot: rays 2 x 32 B, hits 16, shadow 48, beta 16, L 16,
+// features 32, layers 16
+constexpr size_t NA_OFF_RAYS0 = 0;
+constexpr size_t NA_OFF_RAYS1 = NA_OFF_RAYS0 + 32 * NOALLOC_PATHS;
+constexpr size_t NA_OFF_HITS = NA_OFF_RAYS1 + 32 * NOALLOC_PATHS;
+constexpr size_t NA_OFF_SHADOW = NA_OFF_HITS + 16 * NOALLOC_PATHS;
+constexpr size_t NA_OFF_BETA = NA_OFF_SHADOW + 48 * NOALLOC_PATHS;
+constexpr size_t NA_OFF_L = NA_OFF_BETA + 16 * NOALLOC_PATHS;
+constexpr size_t NA_OFF_AUX = NA_OFF_L + 16 * NOALLOC_PATHS;
+constexpr size_t NA_OFF_LAY = NA_OFF_AUX + 32 * NOALLOC_PATHS;
+constexpr size_t NA_OFF_SPILL = NA_OFF_LAY + 16 * NOALLOC_PATHS;
+constexpr size_t NA_OFF_Q =
+    NA_OFF_SPILL + al256(sizeof(uint32_t) * (MAX_STACK4 - LDS_STACK) * NOALLOC_BLOCKS * TB);
+constexpr size_t NA_OFF_JOB = NA_OFF_Q + al256(sizeof(uint32_t) * Q_WORDS);
+constexpr size_t NA_OFF_STATS = NA_OFF_JOB + al256(sizeof(DevJob));
+constexpr size_t NA_OFF_ACC = NA_OFF_STATS + al256(sizeof(unsigned long long) * MRS_NUM_COUNTERS);
+constexpr size_t NA_BYTES = NA_OFF_ACC + NOALLOC_ACC_BYTES;
+static_assert(NA_OFF_RAYS1 % 256 == 0 && NA_OFF_SPILL % 256 == 0 && NA_BYTES % 16 == 0,
+              "static workspace layout");
+
+static __device__ __align__(256) uint4 scratch[NA_BYTES / 16];
+
+// Device address of this GPU's copy of `scratch` (host code must never use the
+// array's name as an address: it is a host-side stand-in).  Looked up once per
+// device, with that device current.
+constexpr int NA_MAX_DEVICES = 64;
+char* g_scratch_ptr[NA_MAX_DEVICES] = {};
+
+mrs_status scratch_base(char** out) {
+  int dev = 0;
+  MRS_TRY_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= NA_MAX_DEVICES)
+    return fail(MRS_ERR_UNSUPPORTED, "mrs_render_ex_noalloc: device index beyond 63");
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return fail(MRS_ERR_DEVICE, std::string("mrs_render_ex_noalloc: hipGetSymbolAddress: ") +
+                                      hipGetErrorString(e));
+    }
+    g_scratch_ptr[dev] = static_cast<char*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return MRS_OK;
+}
+
+mrs_status render_noalloc(const mrs_scene* s, const RenderArgs& a, hipStream_t st) {
+  if (a.max_depth + 2 > MAX_BOUNCE_SLOTS)
+    return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_render_ex_noalloc: max_depth too large");
+  const int64_t npix = (int64_t)a.ww * a.wh;
+  const size_t ab = acc_bytes_of(npix, a.fp64, a.out_layers != nullptr);
+  if (ab > NOALLOC_ACC_BYTES)
+    return fail(MRS_ERR_INVALID_ARGUMENT,
+                "mrs_render_ex_noalloc: the window needs " + std::to_string(ab) +
+                    " bytes of pixel sums; the static workspace holds " +
+                    std::to_string(NOALLOC_ACC_BYTES) +
+                    " (2^19 pixels with FP64 sums, 2^20 with FP32 sums, fewer with render "
+                    "layers): render it in windows");
+  char* base = nullptr;
+  mrs_status rc = scratch_base(&base);
+  if (rc != MRS_OK) return rc;
+  mrs_tuning tu = tuning_snapshot();
+  tu.streams = 1;  // the caller's stream only: no internal streams or events
+  tu.chunk_paths = (int32_t)std::min<int64_t>(tu.chunk_paths, NOALLOC_PATHS);
+  tu.trace_blocks = std::min(tu.trace_blocks, NOALLOC_BLOCKS);
+  Workspace ws;
+  ws.cap_paths = (size_t)NOALLOC_PATHS;
+  ws.spill_threads = NOALLOC_BLOCKS * TB;
+  ws.rays[0] = reinterpret_cast<float4*>(base + NA_OFF_RAYS0);
+  ws.rays[1] = reinterpret_cast<float4*>(base + NA_OFF_RAYS1);
+  ws.hits = reinterpret_cast<float4*>(base + NA_OFF_HITS);
+  ws.shadow = reinterpret_cast<float4*>(base + NA_OFF_SHADOW);
+  ws.beta = reinterpret_cast<float4*>(base + NA_OFF_BETA);
+  ws.L = reinterpret_cast<float4*>(base + NA_OFF_L);
+  ws.aux = reinterpret_cast<float4*>(base + NA_OFF_AUX);
+  ws.lay = reinterpret_cast<float4*>(base + NA_OFF_LAY);
+  ws.spill = reinterpret_cast<uint32_t*>(base + NA_OFF_SPILL);
+  ws.q = reinterpret_cast<uint32_t*>(base + NA_OFF_Q);
+  ws.one = reinterpret_cast<DevJob*>(base + NA_OFF_JOB);
+  ws.stats = reinterpret_cast<unsigned long long*>(base + NA_OFF_STATS);
+  ws.acc = base + NA_OFF_ACC;
+  ws.acc_bytes = NOALLOC_ACC_BYTES;
+  const Plan P = make_plan(tu, npix * a.spp);
+  if (P.K != 1 || P.Cs > NOALLOC_PATHS || P.blocks_k > NOALLOC_BLOCKS)
+    return fail(MRS_ERR_DEVICE, "mrs_render_ex_noalloc: internal plan exceeds the workspace");
+  DevJob J = make_job(s, a);
+  J.first = 0;
+  J.pix_first = 0;
+  J.acc_off = 0;
+  ProfPause pause;  // kernel timing would create events
+  // the counters of this call start at zero and are not added to mrs_get_counters
+  k_zero_words<<<1, 64, 0, st>>>(reinterpret_cast<uint32_t*>(ws.stats), 2 * MRS_NUM_COUNTERS);
   k_store_job<<<1, 64, 0, st>>>(J, ws.one);
   std::vector<DevJob> jobs{J};
   return launch_batch(ws, tu, ws.one, jobs, ws.acc, ab, st);
