@@ -178,6 +178,135 @@ def pmc_summary(fetch_path, write_path, out_path):
     print("\n".join(lines))
 
 
+COUNTERS_SUMMARY = os.path.join(ROOT, "profiles", "hybrid_frame_procedural101k_720p_counters.txt")
+# the kernels the counters describe and the sources that make them
+COUNTER_SOURCES = [os.path.join(ROOT, "paper_2106_12802_amd", "csrc", f)
+                   for f in ("trace.hip", "lbvh.hip", "cnn.hip", "net.hip")]
+PROFILE_ARGS = ("--steps 1 --warmup 0 --no-cpu-baseline --equal-psnr-scenes 0 --batch-scenes 0 "
+                "--no-paper-net --no-mis --no-camera --no-spp-pairs --no-two-calls")
+# rocprofv3 --pmc passes (one process each; each within the per-block counter limits)
+COUNTER_PASSES = {
+    "valu": "VALUBusy VALUUtilization SQ_INSTS_VALU SQ_WAVES GRBM_GUI_ACTIVE",
+    "cache": "TCC_HIT_sum TCC_MISS_sum TCP_TOTAL_CACHE_ACCESSES_sum TCP_TCC_READ_REQ_sum "
+             "GRBM_GUI_ACTIVE",
+    "mfma": "MfmaUtil SQ_INSTS_VALU_MFMA_MOPS_BF16 SQ_LDS_BANK_CONFLICT SQ_LDS_IDX_ACTIVE "
+            "SQ_BUSY_CYCLES GRBM_GUI_ACTIVE",
+}
+# kernel (a prefix of its demangled name, after the namespace) -> short name
+COUNTER_KERNELS = [("k_extend<false>", "k_extend"), ("k_shadow<false>", "k_shadow"),
+                   ("k_tail<false>", "k_tail"), ("k_shade", "k_shade"),
+                   ("k_conv3_lds<64, 4, 16>", "k_conv3_lds<64,4,16>"),
+                   ("k_conv3_lds<16, 4, 16>", "k_conv3_lds<16,4,16>"),
+                   ("k_conv3_lds<8, 4, 16>", "k_conv3_lds<8,4,16>"),
+                   ("k_conv3_lds<80, 1, 16>", "k_conv3_lds<80,1,16>"),
+                   ("k_conv<4>", "k_conv<4>")]
+
+
+def counter_source_hash() -> str:
+    h = hashlib.sha256()
+    for path in COUNTER_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def counters_summary(dirs, out_path):
+    """Per-kernel figures from the rocprofv3 --pmc passes of COUNTER_PASSES (their
+    output directories, in that order): each counter summed over a kernel's
+    dispatches, percentages weighted by each dispatch's GRBM_GUI_ACTIVE cycles."""
+    import re
+    vals = {}   # short kernel name -> counter -> [sum over dispatches]
+    gui = {}    # (pass, kernel) -> total active cycles
+    disp = {}
+    for (pname, _), d in zip(COUNTER_PASSES.items(), dirs):
+        per = {}
+        for r in _pmc_rows(d):
+            name = r["Kernel_Name"].replace("void ", "").replace(
+                "(anonymous namespace)::", "").replace("mrs::", "")
+            short = next((sh for pre, sh in COUNTER_KERNELS if name.startswith(pre)), None)
+            if short is None:
+                continue
+            key = (short, r.get("Dispatch_Id") or r.get("Correlation_Id"))
+            cs = per.setdefault(key, {})
+            cs[r["Counter_Name"]] = float(r["Counter_Value"])
+            cs["_ns"] = float(r["End_Timestamp"]) - float(r["Start_Timestamp"])
+        for (short, _), cs in per.items():
+            g = cs.pop("_ns")  # the dispatch's duration (ns) weighs its percentages
+            gui[(pname, short)] = gui.get((pname, short), 0.0) + g
+            disp[(pname, short)] = disp.get((pname, short), 0) + 1
+            v = vals.setdefault(short, {})
+            for c, x in cs.items():
+                if c in ("VALUBusy", "VALUUtilization", "MfmaUtil"):
+                    v[c] = v.get(c, 0.0) + x * g  # weighted, divided below
+                else:
+                    v[c] = v.get(c, 0.0) + x
+    lines = [
+        "# Hardware counters of the 720p hybrid frame's kernels (procedural scene seed 7,",
+        "# 101,446 triangles; HRLS 1280x720@4 + LRHS 320x180@64, depth 8; BF16 fusion network):",
+        "# one counting frame (k_*<true>, not listed), one pipelined frame and the network once",
+        "# alone.  Made by (one process per pass, from the repository root, cd /tmp first):",
+    ]
+    for pname, ctrs in COUNTER_PASSES.items():
+        lines.append(f"#   rocprofv3 --pmc {ctrs} -f csv -d gpurun_out/pmc_{pname} -o pmc -- "
+                     f"python bench.py {PROFILE_ARGS}")
+    lines += ["#   python bench.py --counters-summary gpurun_out/pmc_valu gpurun_out/pmc_cache "
+              "gpurun_out/pmc_mfma",
+              "# Sums over each kernel's dispatches; VALUBusy / VALUUtilization / MfmaUtil are",
+              "# rocprofv3's derived percentages, weighted by each dispatch's duration (its",
+              "# start and end timestamps; counter runs serialise the dispatches).",
+              "# L1 hit = 1 - TCP_TCC_READ_REQ / TCP_TOTAL_CACHE_ACCESSES; L2 hit = TCC_HIT /",
+              "# (TCC_HIT + TCC_MISS); VALU insts per wave = SQ_INSTS_VALU / SQ_WAVES;",
+              "# BF16 TFLOP/s = 512 SQ_INSTS_VALU_MFMA_MOPS_BF16 / the dispatches' duration.",
+              f"kernel_sources_sha256_16 = {counter_source_hash()}", ""]
+    for _, short in COUNTER_KERNELS:
+        v = vals.get(short)
+        if not v:
+            continue
+        out = []
+        gv, gc, gm = (gui.get((p, short), 0.0) for p in COUNTER_PASSES)
+        if gv > 0 and "VALUBusy" in v:
+            out.append(f"valu_busy_pct = {v['VALUBusy'] / gv:.2f}")
+            out.append(f"valu_lane_util_pct = {v['VALUUtilization'] / gv:.2f}")
+            out.append(f"valu_insts_per_wave = {v['SQ_INSTS_VALU'] / max(v['SQ_WAVES'], 1):.1f}")
+        if "TCP_TOTAL_CACHE_ACCESSES_sum" in v:
+            acc, miss = v["TCP_TOTAL_CACHE_ACCESSES_sum"], v["TCP_TCC_READ_REQ_sum"]
+            out.append(f"l1_hit = {1.0 - miss / max(acc, 1):.4f}")
+            h, m = v["TCC_HIT_sum"], v["TCC_MISS_sum"]
+            out.append(f"l2_hit = {h / max(h + m, 1):.4f}")
+        if gm > 0 and "MfmaUtil" in v:
+            out.append(f"mfma_util_pct = {v['MfmaUtil'] / gm:.2f}")
+            tf = 512.0 * v["SQ_INSTS_VALU_MFMA_MOPS_BF16"] / (gm * 1e-9) / 1e12
+            out.append(f"mfma_bf16_tflops = {tf:.1f}")
+            li = v.get("SQ_LDS_IDX_ACTIVE", 0.0)
+            if li > 0:
+                out.append(f"lds_bank_conflict_per_access_cycle = "
+                           f"{v['SQ_LDS_BANK_CONFLICT'] / li:.4f}")
+        out.append(f"dispatches = {max(disp.get((p, short), 0) for p in COUNTER_PASSES)}")
+        out.append(f"us_per_dispatch = {gv / max(disp.get(('valu', short), 1), 1) / 1e3:.1f}")
+        lines += [f"[{short}]"] + out + [""]
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines))
+    print("\n".join(lines))
+
+
+def read_counters():
+    """{kernel: {figure: value}} from the committed counter summary, if it belongs to
+    the current kernel sources (None otherwise)."""
+    if not os.path.exists(COUNTERS_SUMMARY):
+        return None
+    res, cur, sha = {}, None, None
+    for line in open(COUNTERS_SUMMARY):
+        line = line.strip()
+        if line.startswith("kernel_sources_sha256_16"):
+            sha = line.split("=", 1)[1].strip()
+        elif line.startswith("[") and line.endswith("]"):
+            cur = res.setdefault(line[1:-1], {})
+        elif "=" in line and cur is not None and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            cur[k.strip()] = float(v)
+    return res if sha == counter_source_hash() else None
+
+
 STATS_SUMMARY = os.path.join(ROOT, "profiles", "hybrid_frame_procedural101k_720p_kernel_stats.txt")
 STATS_CMD = ("rocprofv3 --kernel-trace --stats -f csv -d gpurun_out/prof -o bench -- python -u "
              "bench.py --steps 5 --warmup 1 --no-cpu-baseline --equal-psnr-scenes 0 --batch-scenes 0 --no-paper-net --no-mis --no-camera --no-spp-pairs --no-two-calls")
@@ -676,7 +805,12 @@ def main():
                     help="summarise a rocprofv3 --stats run into the profiles/ kernel-stats file")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="summarise two rocprofv3 --pmc runs into the profiles/ traffic file")
+    ap.add_argument("--counters-summary", nargs=3, metavar=("VALU_DIR", "CACHE_DIR", "MFMA_DIR"),
+                    help="summarise the three rocprofv3 --pmc counter passes into profiles/")
     args = ap.parse_args()
+    if args.counters_summary:
+        counters_summary(args.counters_summary, COUNTERS_SUMMARY)
+        return
     if args.stats_summary:
         stats_summary(args.stats_summary, STATS_SUMMARY)
         return
@@ -837,6 +971,12 @@ def main():
                 if cnn_ms > 0 else 0.0, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
                 "ms_per_frame": round(cnn_ms, 4), "measured": "the network alone, HIP events"}
     cnn_roof["frac"] = round(cnn_roof["achieved"] / PEAK_BF16_TFLOPS, 5)
+    # hardware counters of the committed profile, if it belongs to these kernel sources
+    ctr = read_counters()
+    roofline["counters"] = None if ctr is None else {
+        k: ctr[k] for k in ("k_extend", "k_shadow", "k_tail") if k in ctr}
+    cnn_roof["counters"] = None if ctr is None else {
+        k: ctr[k] for k in ctr if k.startswith("k_conv")}
     kernel_ms = {k: round(v[0] / args.steps, 4) for k, v in prof.items()}
     result = {
         "metric": METRIC, "value": round(value, 3), "unit": "Mpaths/s", "n_gpus": 1,
