@@ -154,10 +154,10 @@ def pmc_summary(fetch_path, write_path, out_path):
         "# (max depth 8) + fusion network.",
         "# Made by (each pass its own process, run from the repository root):",
         "#   rocprofv3 --pmc FETCH_SIZE -f csv -d gpurun_out/pmc_fetch -o pmc -- python bench.py "
-        "--steps 1 --warmup 0 --no-cpu-baseline --equal-psnr-scenes 0 --batch-scenes 0 --no-paper-net --no-mis --no-camera --no-spp-pairs --no-two-calls "
+        "--steps 1 --warmup 0 --no-cpu-baseline --equal-psnr-scenes 0 --batch-scenes 0 --no-paper-net --no-mis --no-camera --no-spp-pairs --no-two-calls --no-training "
         "--copy-calibration",
         "#   rocprofv3 --pmc WRITE_SIZE -f csv -d gpurun_out/pmc_write -o pmc -- python bench.py "
-        "--steps 1 --warmup 0 --no-cpu-baseline --equal-psnr-scenes 0 --batch-scenes 0 --no-paper-net --no-mis --no-camera --no-spp-pairs --no-two-calls "
+        "--steps 1 --warmup 0 --no-cpu-baseline --equal-psnr-scenes 0 --batch-scenes 0 --no-paper-net --no-mis --no-camera --no-spp-pairs --no-two-calls --no-training "
         "--copy-calibration",
         "#   python bench.py --pmc-summary gpurun_out/pmc_fetch gpurun_out/pmc_write",
         "# Counters are KiB per dispatch; each is scaled by COPY_BYTES over what the same counter",
@@ -183,7 +183,7 @@ COUNTERS_SUMMARY = os.path.join(ROOT, "profiles", "hybrid_frame_procedural101k_7
 COUNTER_SOURCES = [os.path.join(ROOT, "paper_2106_12802_amd", "csrc", f)
                    for f in ("trace.hip", "lbvh.hip", "cnn.hip", "net.hip")]
 PROFILE_ARGS = ("--steps 1 --warmup 0 --no-cpu-baseline --equal-psnr-scenes 0 --batch-scenes 0 "
-                "--no-paper-net --no-mis --no-camera --no-spp-pairs --no-two-calls")
+                "--no-paper-net --no-mis --no-camera --no-spp-pairs --no-two-calls --no-training")
 # rocprofv3 --pmc passes (one process each; each within the per-block counter limits)
 COUNTER_PASSES = {
     "valu": "VALUBusy VALUUtilization SQ_INSTS_VALU SQ_WAVES GRBM_GUI_ACTIVE",
@@ -309,7 +309,7 @@ def read_counters():
 
 STATS_SUMMARY = os.path.join(ROOT, "profiles", "hybrid_frame_procedural101k_720p_kernel_stats.txt")
 STATS_CMD = ("rocprofv3 --kernel-trace --stats -f csv -d gpurun_out/prof -o bench -- python -u "
-             "bench.py --steps 5 --warmup 1 --no-cpu-baseline --equal-psnr-scenes 0 --batch-scenes 0 --no-paper-net --no-mis --no-camera --no-spp-pairs --no-two-calls")
+             "bench.py --steps 5 --warmup 1 --no-cpu-baseline --equal-psnr-scenes 0 --batch-scenes 0 --no-paper-net --no-mis --no-camera --no-spp-pairs --no-two-calls --no-training")
 
 
 def stats_summary(prof_dir, out_path):
@@ -545,8 +545,7 @@ def batched_block(net, log, n_scenes=32, tune=True):
             "mpaths_per_s_batched": round(paths / graph_ms / 1e3, 2),
             "speedup": round(seq_ms / graph_ms, 4), "replay_equals_eager": bool(same),
             "equals_one_call_at_a_time": bool(same_seq),
-            "tuning": {k: tuned[k] for k in ("chunk_paths", "trace_blocks", "schedule")}
-            if tuned else None}
+            "tuning": {k: tuned[k] for k in autotune.KEYS} if tuned else None}
 
 
 def mis_block(gs, log, reps=5):
@@ -711,6 +710,53 @@ def spp_sweep(log):
     return out
 
 
+def res16_flop(B, H, W):
+    """Forward FLOP of the 16-residual-block network on B frames of H x W (x4):
+    2 x sum over convs of output pixels x C_out x C_in x k^2."""
+    hr, lr = B * H * W, B * H * W // 16
+    mac = (hr * 64 * 10 * 9 + lr * 64 * 3 * 9 + lr * 64 * 1088 + 32 * lr * 64 * 64 * 9
+           + lr * 256 * 64 * 9 + hr * 3 * 80 * 9)
+    return 2 * mac
+
+
+def training_block(log, steps=20, warmup=5):
+    """The configured training step (16-residual-block network, batch 16 of 128 x 128
+    HR / 32 x 32 LR crops, L1 loss reduced in FP64, Adam at lr 1e-4, BF16 MFMA with
+    FP32 masters): ms per step and the MFMA rate it reaches.  One step is the
+    forward, the data gradients of every conv but the two input convs, every
+    weight gradient (each as many FLOP as its forward conv) and the update."""
+    import torch
+    import paper_2106_12802_amd as mrs
+    B, H, W = 16, 128, 128
+    g = torch.Generator(device="cuda").manual_seed(11)
+    hr = torch.rand(B, H, W, 3, device="cuda", generator=g) * 2.0
+    aux = torch.rand(B, H, W, 7, device="cuda", generator=g)
+    lr = torch.rand(B, H // 4, W // 4, 3, device="cuda", generator=g) * 2.0
+    tgt = torch.rand(B, H, W, 3, device="cuda", generator=g) * 2.0
+    net = mrs.FusionNet(seed=3)
+    for _ in range(warmup):
+        net.train_step(hr, aux, lr, tgt, lr=1e-4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        net.train_step(hr, aux, lr, tgt, lr=1e-4)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    fwd = res16_flop(B, H, W)
+    in_convs = 2 * (B * H * W * 64 * 10 * 9 + B * H * W // 16 * 64 * 3 * 9)
+    flop = 3 * fwd - in_convs
+    loss = net.train_step(hr, aux, lr, tgt, lr=1e-4, want_loss=True)
+    net.close()
+    res = {"workload": "16-residual-block network, batch 16 of 128x128 HR / 32x32 LR crops, "
+                       "L1 (FP64 reduction) + Adam lr 1e-4, BF16 MFMA with FP32 masters",
+           "ms_per_step": round(ms, 3), "gflop_per_step": round(flop / 1e9, 2),
+           "tflops": round(flop / (ms / 1e3) / 1e12, 2),
+           "frac_of_bf16_peak": round(flop / (ms / 1e3) / 1e12 / PEAK_BF16_TFLOPS, 5),
+           "loss_after_steps": round(float(loss), 5)}
+    log(f"[bench] training step (cfg of 16 x 128^2): {ms:.3f} ms, {res['tflops']} TFLOP/s")
+    return res
+
+
 def paper_net_block(log, reps=10, train_steps=10):
     """The paper's own network (three residual dense groups, Sec. 4): fuse time
     on the 720p hybrid frame and at the paper's runtime-table size (one
@@ -787,6 +833,8 @@ def main():
                     help="skip the random-spp-pair training iteration block")
     ap.add_argument("--no-paper-net", action="store_true",
                     help="skip timing the paper's own network (residual dense groups)")
+    ap.add_argument("--no-training", action="store_true",
+                    help="skip timing the training step of the 16-residual-block network")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 1 GiB device copy first (PMC byte-counter calibration)")
     ap.add_argument("--chunk-paths", type=int, default=None, help="tuning: paths resident at once")
@@ -1003,6 +1051,8 @@ def main():
         result["equal_psnr"] = equal_psnr_block(net, args.equal_psnr_scenes, log)
     if args.batch_scenes > 0:
         result["batched"] = batched_block(net, log, args.batch_scenes)
+    if not args.no_training:
+        result["training"] = training_block(log)
     if not args.no_paper_net:
         result["paper_net"] = paper_net_block(log)
     if not args.no_mis:

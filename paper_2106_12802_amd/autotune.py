@@ -1,9 +1,12 @@
-"""Autotuner of the renderer's launch shape (performance only: results are bitwise
-independent of the tuning, which the tests check).
+"""Autotuner of the renderer's and the network's launch shape (performance only:
+results are bitwise independent of the tuning, which the tests check).
 
-It times a workload under each candidate (chunk_paths, trace_blocks, schedule), keeps the
-fastest, and caches the choice in a JSON file keyed by device and workload so that
-later runs apply it without measuring.
+It times a workload under candidate tunings, keeps the fastest, and caches the
+choice in a JSON file keyed by device and workload so that later runs apply it
+without measuring.  The search is a grid over the primary launch shape
+(resident paths x traversal grid x queue schedule) followed by one pass over
+each secondary knob with the rest held at the best so far: sub-chunk streams,
+the first bounce traced path by path, and the network conv tile plan.
 """
 from __future__ import annotations
 
@@ -14,8 +17,11 @@ import time
 from . import tracer as T
 
 CHUNKS = (1 << 21, 1 << 22, 1 << 23, 1 << 24, 1 << 25)
-BLOCKS = (512, 1024, 2048, 4096)
+BLOCKS = (1024, 2048, 4096, 8192)
 SCHEDULES = (0, 1)
+SECONDARY = (("streams", (1, 2, 3, 4)), ("tail_bounce", (2, 3, 4, 5)),
+             ("conv_small_tiles", (0, 64, 128, 256)))
+KEYS = ("chunk_paths", "trace_blocks", "schedule", "streams", "tail_bounce", "conv_small_tiles")
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "mrs_autotune.json")
 
 
@@ -36,10 +42,28 @@ def choose(timings):
     return best
 
 
+def as_dict(cand):
+    """A candidate as a tuning dict: a (chunk_paths, trace_blocks, schedule) tuple or a dict."""
+    if isinstance(cand, dict):
+        return dict(cand)
+    return dict(zip(("chunk_paths", "trace_blocks", "schedule"), cand))
+
+
+def _apply(base, cand):
+    t = dict(base)
+    t.update(as_dict(cand))
+    T.set_tuning(**{k: t[k] for k in T.TUNING_KEYS})
+    return t
+
+
 def tune(workload, key, cache_path=DEFAULT_CACHE, reps=3, candidates=None, log=None,
-         force=False):
+         force=False, secondary=None):
     """Pick and apply the fastest tuning for `workload` (a callable that enqueues the
-    renders); returns {"chunk_paths", "trace_blocks", "schedule", "ms", "cached"}."""
+    work); returns the chosen tuning fields plus "ms" and "cached".
+
+    candidates: the primary grid (tuples or dicts; default CHUNKS x BLOCKS x
+    SCHEDULES); secondary: [(field, values)] searched one field at a time after
+    it (default SECONDARY; [] to skip)."""
     import torch
     full_key = f"{_device_key()}|{key}"
     cache = {}
@@ -48,31 +72,45 @@ def tune(workload, key, cache_path=DEFAULT_CACHE, reps=3, candidates=None, log=N
             cache = json.load(open(cache_path))
         except (OSError, ValueError):
             cache = {}
+    base = T.get_tuning()
     if not force and full_key in cache:
         c = cache[full_key]
-        T.set_tuning(c["chunk_paths"], c["trace_blocks"], c["schedule"])
+        _apply(base, {k: c[k] for k in KEYS if k in c})
         return dict(c, cached=True)
     if candidates is None:
         candidates = [(c, b, s) for c in CHUNKS for b in BLOCKS for s in SCHEDULES]
-    timings = []
-    for chunk, blocks, sched in candidates:
-        T.set_tuning(chunk, blocks, sched)
-        workload()  # warm-up: grows buffers outside the timing
-        torch.cuda.synchronize()
-        times = []
-        for _ in range(reps):
-            t0 = time.perf_counter()
-            workload()
+    if secondary is None:
+        secondary = SECONDARY
+
+    def measure(cands, cur):
+        timings = []
+        for cand in cands:
+            t = _apply(cur, cand)
+            workload()  # warm-up: grows buffers outside the timing
             torch.cuda.synchronize()
-            times.append((time.perf_counter() - t0) * 1e3)
-        timings.append(((chunk, blocks, sched), times))
-        if log:
-            log(f"[autotune] chunk {chunk} blocks {blocks} schedule {sched}: "
-                f"{sorted(times)[len(times) // 2]:.3f} ms")
-    (chunk, blocks, sched), ms = choose(timings)
-    T.set_tuning(chunk, blocks, sched)
-    cache[full_key] = {"chunk_paths": chunk, "trace_blocks": blocks, "schedule": sched,
-                       "ms": round(ms, 4)}
+            times = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                workload()
+                torch.cuda.synchronize()
+                times.append((time.perf_counter() - t0) * 1e3)
+            timings.append((as_dict(cand), times))
+            if log:
+                shown = {k: t[k] for k in KEYS}
+                log(f"[autotune] {shown}: {sorted(times)[len(times) // 2]:.3f} ms")
+        return choose(timings)
+
+    best, ms = measure(candidates, base)
+    cur = dict(base)
+    cur.update(best)
+    for field, values in secondary:
+        b, m = measure([{field: v} for v in values], cur)
+        if m < ms:
+            cur.update(b)
+            ms = m
+    _apply(base, cur)
+    chosen = {k: int(cur[k]) for k in KEYS}
+    cache[full_key] = dict(chosen, ms=round(ms, 4))
     try:
         os.makedirs(os.path.dirname(cache_path), exist_ok=True)
         with open(cache_path + ".tmp", "w") as f:
