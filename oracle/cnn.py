@@ -22,6 +22,15 @@ Conventions fixed here (the GPU library documents the same ones):
   * parameters: one flat float32 vector, layer by layer, each as the weight
     [C_out, C_in, k, k] followed by the bias [C_out].
 
+With the HRLS render layers (paper Sec. 4, first paragraph: I_HRLS is RGB plus
+albedo, normal, diffuse, specular and variance layers; the layers of Sec. 3.1),
+the HRLS input has 16 channels instead of 10: log1p of the clipped RGB, albedo,
+normal, log1p of the clipped diffuse and glossy (specular) layers, and log1p of
+the per-sample variance averaged over the three colour channels (clamped to
+[0, 1e4]), computed from the per-pixel sums of squares and the sample count.
+Depth is not part of it (the paper's list has none); the emission layer enters
+implicitly as RGB minus the two lobes.  Only the input conv changes (16 -> 64).
+
 Only tests/, the smoke check and the bench's CPU-baseline leg use this module.
 """
 from __future__ import annotations
@@ -33,11 +42,14 @@ FEAT = 64
 N_RES = 16
 RES_SCALE = 0.1
 UP_CH = 16  # channels per HR pixel after the x4 shuffle of 256 channels
+HR_IN = 10          # HRLS input: rgb, albedo, normal, depth
+HR_IN_LAYERS = 16   # with the render layers: rgb, albedo, normal, diffuse, glossy, variance
+VAR_MAX = 1.0e4     # the variance channel's clamp
 
 
-def layer_specs():
+def layer_specs(hr_in=HR_IN):
     """[(name, c_out, c_in, k)] in parameter order."""
-    specs = [("hrls", FEAT, 10, 3), ("lrhs", FEAT, 3, 3),
+    specs = [("hrls", FEAT, hr_in, 3), ("lrhs", FEAT, 3, 3),
              ("fuse", FEAT, FEAT + SCALE * SCALE * FEAT, 1)]
     for i in range(N_RES):
         specs += [(f"res{i}a", FEAT, FEAT, 3), (f"res{i}b", FEAT, FEAT, 3)]
@@ -45,15 +57,24 @@ def layer_specs():
     return specs
 
 
-def num_params():
-    return sum(co * ci * k * k + co for _, co, ci, k in layer_specs())
+def num_params(hr_in=HR_IN):
+    return sum(co * ci * k * k + co for _, co, ci, k in layer_specs(hr_in))
+
+
+def hr_in_of(n_params, count=num_params):
+    """The HRLS input width of a parameter vector of n_params values (count(hr_in)
+    gives the size of each variant)."""
+    for hr_in in (HR_IN, HR_IN_LAYERS):
+        if count(hr_in) == n_params:
+            return hr_in
+    raise ValueError(f"{n_params} parameters fit no variant of the network")
 
 
 def unpack(params):
     params = np.asarray(params, np.float64)
     out = {}
     off = 0
-    for name, co, ci, k in layer_specs():
+    for name, co, ci, k in layer_specs(hr_in_of(params.size)):
         nw = co * ci * k * k
         out[name] = (params[off:off + nw].reshape(co, ci, k, k), params[off + nw:off + nw + co])
         off += nw + co
@@ -62,8 +83,9 @@ def unpack(params):
 
 
 def pack(layers):
+    hr_in = layers["hrls"][0].shape[1]
     return np.concatenate([np.concatenate([layers[n][0].ravel(), layers[n][1].ravel()])
-                           for n, *_ in layer_specs()])
+                           for n, *_ in layer_specs(hr_in)])
 
 
 # ----------------------------------------------------------------- primitives
@@ -125,13 +147,40 @@ def preprocess(hrls_rgb, hrls_aux, lrhs_rgb):
     return np.concatenate([hr, aux], axis=-1), lr
 
 
+def layer_variance(hrls_rgb, hrls_sumsq, spp):
+    """Per-sample variance of each pixel's samples, averaged over the three colour
+    channels: mean_c (sumsq_c / spp - mean_c^2), clamped to [0, VAR_MAX]."""
+    m = np.asarray(hrls_rgb, np.float64)
+    v = np.asarray(hrls_sumsq, np.float64) / spp - m * m
+    return np.clip(v.mean(-1), 0.0, VAR_MAX)
+
+
+def preprocess_layers(hrls_rgb, hrls_aux, hrls_layers, hrls_sumsq, spp, lrhs_rgb):
+    """Network inputs with the render layers: HRLS [B,H,W,16] (rgb, albedo, normal,
+    diffuse, glossy, variance), LRHS [B,H/4,W/4,3] (float64).  hrls_layers [...,9]:
+    emission, diffuse, glossy; hrls_sumsq [...,3]: per-pixel sums of squared samples."""
+    hr = np.log1p(np.clip(np.asarray(hrls_rgb, np.float64), 0.0, 100.0))
+    aux = np.asarray(hrls_aux, np.float64)
+    lay = np.log1p(np.clip(np.asarray(hrls_layers, np.float64)[..., 3:9], 0.0, 100.0))
+    var = np.log1p(layer_variance(hrls_rgb, hrls_sumsq, spp))[..., None]
+    lr = np.log1p(np.clip(np.asarray(lrhs_rgb, np.float64), 0.0, 100.0))
+    return np.concatenate([hr, aux[..., 0:6], lay, var], axis=-1), lr
+
+
 # ----------------------------------------------------------------- network
 
 
-def forward(params, hrls_rgb, hrls_aux, lrhs_rgb, keep=False):
-    """I_SR [B,H,W,3] from HRLS rgb [B,H,W,3], aux [B,H,W,7], LRHS rgb [B,H/4,W/4,3]."""
+def forward(params, hrls_rgb, hrls_aux, lrhs_rgb, keep=False, layers=None):
+    """I_SR [B,H,W,3] from HRLS rgb [B,H,W,3], aux [B,H,W,7], LRHS rgb [B,H/4,W/4,3];
+    layers = (hrls_layers [B,H,W,9], hrls_sumsq [B,H,W,3], spp) for the variant
+    whose HRLS input carries the render layers."""
     L = unpack(params)
-    xh, xl = preprocess(hrls_rgb, hrls_aux, lrhs_rgb)
+    if layers is None:
+        xh, xl = preprocess(hrls_rgb, hrls_aux, lrhs_rgb)
+    else:
+        xh, xl = preprocess_layers(hrls_rgb, hrls_aux, *layers, lrhs_rgb)
+    if xh.shape[-1] != L["hrls"][0].shape[1]:
+        raise ValueError("the parameters and the inputs belong to different variants")
     acts = {"xh": xh, "xl": xl}
     h0 = relu(conv(xh, *L["hrls"]))                   # F^0_HRLS
     fl = relu(conv(xl, *L["lrhs"]))                   # F_LRHS
@@ -188,7 +237,7 @@ def backward(params, acts, gout):
     _, g["lrhs_w"], g["lrhs_b"] = conv_backward(acts["xl"], L["lrhs"][0], dfl)
     _, g["hrls_w"], g["hrls_b"] = conv_backward(acts["xh"], L["hrls"][0], dh0)
     return np.concatenate([np.concatenate([g[f"{n}_w"].ravel(), g[f"{n}_b"].ravel()])
-                           for n, *_ in layer_specs()])
+                           for n, *_ in layer_specs(L["hrls"][0].shape[1])])
 
 
 def l1_grad(out, target):

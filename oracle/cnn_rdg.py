@@ -38,7 +38,8 @@ from __future__ import annotations
 
 import numpy as np
 
-from .cnn import FEAT, clip_target, conv, conv_backward, preprocess, relu, shuffle, unshuffle
+from .cnn import (FEAT, HR_IN, clip_target, conv, conv_backward, hr_in_of, preprocess,
+                  preprocess_layers, relu, shuffle, unshuffle)
 
 N_GROUPS = 3      # G
 N_BLOCKS = 5      # B, RDBs per group
@@ -59,9 +60,10 @@ def rdb_name(g, b, c):
     return f"g{g}b{b}c{c}"
 
 
-def layer_specs(scale=4):
-    """[(name, c_out, c_in, k)] in parameter order."""
-    specs = [("hrls", FEAT, 10, 3), ("lrhs", FEAT, 3, 3),
+def layer_specs(scale=4, hr_in=HR_IN):
+    """[(name, c_out, c_in, k)] in parameter order; hr_in 16 for the variant whose
+    HRLS input carries the render layers (oracle/cnn.py, preprocess_layers)."""
+    specs = [("hrls", FEAT, hr_in, 3), ("lrhs", FEAT, 3, 3),
              ("fuse", FEAT, FEAT + scale * scale * FEAT, 1)]
     for g in range(N_GROUPS):
         for b in range(N_BLOCKS):
@@ -74,15 +76,16 @@ def layer_specs(scale=4):
     return specs
 
 
-def num_params(scale=4):
-    return sum(co * ci * k * k + co for _, co, ci, k in layer_specs(scale))
+def num_params(scale=4, hr_in=HR_IN):
+    return sum(co * ci * k * k + co for _, co, ci, k in layer_specs(scale, hr_in))
 
 
 def unpack(params, scale=4):
     params = np.asarray(params, np.float64)
     out = {}
     off = 0
-    for name, co, ci, k in layer_specs(scale):
+    hr_in = hr_in_of(params.size, lambda h: num_params(scale, h))
+    for name, co, ci, k in layer_specs(scale, hr_in):
         nw = co * ci * k * k
         out[name] = (params[off:off + nw].reshape(co, ci, k, k), params[off + nw:off + nw + co])
         off += nw + co
@@ -105,10 +108,16 @@ def rdb(x0, L, g, b):
     return x0 + conv(np.concatenate(xs, -1), *L[rdb_name(g, b, N_CONVS - 1)]), xs
 
 
-def forward(params, hrls_rgb, hrls_aux, lrhs_rgb, keep=False, scale=4):
-    """I_SR [B,H,W,3] from HRLS rgb [B,H,W,3], aux [B,H,W,7], LRHS rgb [B,H/s,W/s,3]."""
+def forward(params, hrls_rgb, hrls_aux, lrhs_rgb, keep=False, scale=4, layers=None):
+    """I_SR [B,H,W,3] from HRLS rgb [B,H,W,3], aux [B,H,W,7], LRHS rgb [B,H/s,W/s,3];
+    layers = (hrls_layers, hrls_sumsq, spp) for the variant with the render layers."""
     L = unpack(params, scale)
-    xh, xl = preprocess(hrls_rgb, hrls_aux, lrhs_rgb)
+    if layers is None:
+        xh, xl = preprocess(hrls_rgb, hrls_aux, lrhs_rgb)
+    else:
+        xh, xl = preprocess_layers(hrls_rgb, hrls_aux, *layers, lrhs_rgb)
+    if xh.shape[-1] != L["hrls"][0].shape[1]:
+        raise ValueError("the parameters and the inputs belong to different variants")
     h0 = relu(conv(xh, *L["hrls"]))                   # F^0_HRLS
     fl = relu(conv(xl, *L["lrhs"]))                   # F_LRHS
     cat = np.concatenate([fl, deshuffle_stack(h0, scale)], -1)
@@ -176,7 +185,7 @@ def backward(params, acts, gout, scale=4):
     _, g["lrhs_w"], g["lrhs_b"] = conv_backward(acts["xl"], L["lrhs"][0], dfl)
     _, g["hrls_w"], g["hrls_b"] = conv_backward(acts["xh"], L["hrls"][0], dh0)
     return np.concatenate([np.concatenate([g[f"{n}_w"].ravel(), g[f"{n}_b"].ravel()])
-                           for n, *_ in layer_specs(scale)])
+                           for n, *_ in layer_specs(scale, L["hrls"][0].shape[1])])
 
 
 def robust_loss(out, target, beta=0.1):
