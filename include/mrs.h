@@ -386,6 +386,19 @@ typedef struct mrs_net mrs_net;
  * the LRHS image, W/s x H/s) must be multiples of the scale s. */
 #define MRS_NET_RDG_X2 2
 #define MRS_NET_RDG_X8 3
+/* The x4 networks with the HRLS render layers as inputs (Sec. 4, first
+ * paragraph: I_HRLS is RGB plus albedo, normal, diffuse, specular and variance
+ * layers; the layers are those of Sec. 3.1): the HRLS input conv reads 16
+ * channels instead of 10 -- log1p of the clipped RGB, albedo (3), normal (3),
+ * log1p of the clipped diffuse and glossy layers (3 + 3), and log1p of the
+ * per-sample variance averaged over RGB, mean_c(sumsq_c / spp - rgb_c^2)
+ * clamped to [0, 1e4] (1); depth is not an input.  Everything else is the
+ * network of MRS_NET_RES16 / MRS_NET_RDG; 1,412,339 / 5,911,363 parameters.
+ * These networks read the layers from the buffers bound with
+ * mrs_net_bind_layers; every fuse / train / gradient call on them returns
+ * NOT_READY until some are bound. */
+#define MRS_NET_RES16_LAYERS 4
+#define MRS_NET_RDG_LAYERS 5
 
 int64_t mrs_net_num_params(void);                 /* MRS_NET_RES16's count */
 int64_t mrs_net_arch_num_params(int32_t arch);     /* -1 for an unknown arch */
@@ -393,6 +406,17 @@ mrs_status mrs_net_create(mrs_net** out); /* MRS_NET_RES16; parameters unset: mr
 /* A network of the given architecture; INVALID_ARGUMENT for an unknown one. */
 mrs_status mrs_net_create_arch(int32_t arch, mrs_net** out);
 mrs_status mrs_net_destroy(mrs_net* net);
+/* Binds the HRLS render layers that the MRS_NET_*_LAYERS networks read in every
+ * later mrs_fuse / mrs_fuse_batch / mrs_train_step(_ex) / mrs_net_loss_grad(_ex)
+ * / mrs_net_backward call: layers_dev B*H*W*9 FP32 (emission, diffuse, glossy:
+ * a render's out_layers_dev) and sumsq_dev B*H*W*3 FP32 (its out_sumsq_dev),
+ * laid out like hrls_rgb_dev of those calls, and spp the render's samples per
+ * pixel.  The buffers stay owned by the caller and must hold the B, W and H of
+ * each call that reads them.  NULL, NULL, 0 unbinds.  INVALID_ARGUMENT for a
+ * network without layer inputs, NULL or misaligned buffers or spp < 1. */
+mrs_status mrs_net_bind_layers(mrs_net* net, const float* layers_dev, const float* sumsq_dev,
+                               int32_t spp);
+
 /* He-uniform weights (bound sqrt(6 / fan_in)) from Philox4x32-10 with key seed,
  * counter (parameter index lo, hi, 0, 2); zero biases.  On the device. */
 mrs_status mrs_net_init(mrs_net* net, uint64_t seed);

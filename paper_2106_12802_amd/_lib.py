@@ -53,8 +53,8 @@ class SceneDesc(C.Structure):
                 ("camera", Camera)]
 
 
-NET_ARCHS = {"res16": 0, "rdg": 1, "rdg_x2": 2, "rdg_x8": 3}
-NET_SCALES = {"res16": 4, "rdg": 4, "rdg_x2": 2, "rdg_x8": 8}
+NET_ARCHS = {"res16": 0, "rdg": 1, "rdg_x2": 2, "rdg_x8": 3, "res16_layers": 4, "rdg_layers": 5}
+NET_SCALES = {"res16": 4, "rdg": 4, "rdg_x2": 2, "rdg_x8": 8, "res16_layers": 4, "rdg_layers": 4}
 LOSSES = {"l1": 0, "robust": 1}
 OPTIMIZERS = {"adam": 0, "sgd": 1}
 
@@ -150,6 +150,7 @@ def lib():
         "mrs_debug_conv_launches": ([P, I32], I32),
         "mrs_net_save": ([P, C.c_char_p, U64], I32),
         "mrs_render_ex_noalloc": ([P, I32, I32, I32, I32, U64, C.POINTER(RenderOpts), P, P], I32),
+        "mrs_net_bind_layers": ([P, P, P, I32], I32),
         "mrs_net_load": ([P, C.c_char_p, P], I32),
     }
     for name, (args, res) in sigs.items():
@@ -181,7 +182,7 @@ def exported_symbols():
         "mrs_net_loss_grad_ex", "mrs_train_step_ex", "mrs_net_backward",
         "mrs_batch_render_begin", "mrs_batch_render_end", "mrs_scene_bvh_builder",
         "mrs_profile_select", "mrs_debug_conv_launches", "mrs_net_save", "mrs_net_load",
-        "mrs_render_ex_noalloc",
+        "mrs_render_ex_noalloc", "mrs_net_bind_layers",
     ]
 
 

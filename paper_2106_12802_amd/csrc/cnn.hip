@@ -532,6 +532,46 @@ __global__ __launch_bounds__(256) void k_prep(int64_t nhr, int64_t nlr,
   }
 }
 
+// Network inputs with the HRLS render layers: HRLS -> 16 BF16 channels (log1p
+// of clipped RGB, albedo, normal, log1p of the clipped diffuse and glossy
+// layers, log1p of the per-sample variance averaged over RGB, clamped to
+// [0, 1e4]); LRHS as in k_prep.
+__global__ __launch_bounds__(256) void k_prep_layers(int64_t nhr, int64_t nlr,
+                                                     const float* __restrict__ hr,
+                                                     const float* __restrict__ aux,
+                                                     const float* __restrict__ lay,
+                                                     const float* __restrict__ sq, float inv_spp,
+                                                     const float* __restrict__ lr,
+                                                     uint16_t* __restrict__ xh,
+                                                     uint16_t* __restrict__ xl) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < nhr) {
+    float v[16];
+    float var = 0.0f;
+    for (int c = 0; c < 3; ++c) {
+      const float m = hr[3 * i + c];
+      v[c] = log1pf(fminf(fmaxf(m, 0.0f), 100.0f));
+      var += sq[3 * i + c] * inv_spp - m * m;
+    }
+    for (int c = 0; c < 6; ++c) v[3 + c] = aux[7 * i + c];
+    for (int c = 0; c < 6; ++c) v[9 + c] = log1pf(fminf(fmaxf(lay[9 * i + 3 + c], 0.0f), 100.0f));
+    v[15] = log1pf(fminf(fmaxf(var * (1.0f / 3.0f), 0.0f), 1.0e4f));
+    uint32_t w[8];
+    for (int k = 0; k < 8; ++k) w[k] = (uint32_t)f2bf(v[2 * k]) | ((uint32_t)f2bf(v[2 * k + 1]) << 16);
+    uint4* o = reinterpret_cast<uint4*>(xh + 16 * i);
+    o[0] = make_uint4(w[0], w[1], w[2], w[3]);
+    o[1] = make_uint4(w[4], w[5], w[6], w[7]);
+  } else if (i < nhr + nlr) {
+    const int64_t j = i - nhr;
+    float v[8];
+    for (int c = 0; c < 3; ++c) v[c] = log1pf(fminf(fmaxf(lr[3 * j + c], 0.0f), 100.0f));
+    for (int c = 3; c < 8; ++c) v[c] = 0.0f;
+    uint32_t w[4];
+    for (int k = 0; k < 4; ++k) w[k] = (uint32_t)f2bf(v[2 * k]) | ((uint32_t)f2bf(v[2 * k + 1]) << 16);
+    *reinterpret_cast<uint4*>(xl + 8 * j) = make_uint4(w[0], w[1], w[2], w[3]);
+  }
+}
+
 // Packed BF16 weights of one layer: wp[n][k], k = tap * cin_p + c; zero padding
 // for c >= cin, tap >= taps, n >= cout.  Master layout [cout][cin][k][k].
 __global__ __launch_bounds__(256) void k_pack(const float* __restrict__ wm, int cout, int cin,
@@ -884,9 +924,13 @@ void launch_conv(const ConvArgs& a, int cout_p, hipStream_t st) {
   }
 }
 
-void launch_prep(int64_t nhr, int64_t nlr, const float* hr, const float* aux, const float* lr,
-                 uint16_t* xh, uint16_t* xl, hipStream_t st) {
-  k_prep<<<cdiv64(nhr + nlr, 256), 256, 0, st>>>(nhr, nlr, hr, aux, lr, xh, xl);
+void launch_prep(const mrs_net* net, int64_t nhr, int64_t nlr, const float* hr, const float* aux,
+                 const float* lr, uint16_t* xh, uint16_t* xl, hipStream_t st) {
+  if (arch_has_layers(net->arch))
+    k_prep_layers<<<cdiv64(nhr + nlr, 256), 256, 0, st>>>(
+        nhr, nlr, hr, aux, net->in_layers, net->in_sumsq, 1.0f / (float)net->in_spp, lr, xh, xl);
+  else
+    k_prep<<<cdiv64(nhr + nlr, 256), 256, 0, st>>>(nhr, nlr, hr, aux, lr, xh, xl);
 }
 
 void launch_pack(const float* wm, const NetLayer& L, uint16_t* wp, hipStream_t st) {

@@ -131,6 +131,7 @@ constexpr int RDG_MAX_DSF = 3;
 int arch_scale(int arch);
 int arch_dsf(int arch);
 bool arch_is_rdg(int arch);
+bool arch_has_layers(int arch);  // HRLS input with the render layers (16 channels)
 
 std::vector<NetLayer> make_layers(int arch);
 size_t align256(size_t v);
@@ -154,8 +155,8 @@ mrs_status arena_carve(char*& base, size_t& cap, std::vector<std::pair<void**, s
                        hipStream_t st, const char* what);
 
 void launch_conv(const ConvArgs& a, int cout_p, hipStream_t st);
-void launch_prep(int64_t nhr, int64_t nlr, const float* hr, const float* aux, const float* lr,
-                 uint16_t* xh, uint16_t* xl, hipStream_t st);
+void launch_prep(const mrs_net* net, int64_t nhr, int64_t nlr, const float* hr, const float* aux,
+                 const float* lr, uint16_t* xh, uint16_t* xl, hipStream_t st);
 void launch_pack(const float* wm, const NetLayer& L, uint16_t* wp, hipStream_t st);
 void launch_init(float* dst, const NetLayer& L, uint64_t seed, hipStream_t st);
 void launch_dgrad(const ConvArgs& a, const BwdEpi& e, int cout_p, hipStream_t st);
@@ -174,7 +175,11 @@ void launch_adam(float* w, const float* g, float* m, float* v, int64_t n, float 
 }  // namespace mrs
 
 struct mrs_net {
-  int arch = 0;  // MRS_NET_RES16 or MRS_NET_RDG
+  int arch = 0;  // MRS_NET_*
+  // render layers of the HRLS input, bound by mrs_net_bind_layers (layered archs)
+  const float* in_layers = nullptr;
+  const float* in_sumsq = nullptr;
+  int32_t in_spp = 0;
   std::vector<mrs::NetLayer> layers;
   int64_t nparams = 0;
   int64_t npacked = 0;

@@ -21,10 +21,11 @@ struct Spec {
   float init_scale;
 };
 
-// Layer list of the 16-residual-block network.
-std::vector<Spec> specs_res16() {
+// Layer list of the 16-residual-block network; hr_in HRLS input channels (10,
+// or 16 with the render layers), padded to 16.
+std::vector<Spec> specs_res16(int hr_in) {
   static std::vector<std::string> names;
-  std::vector<Spec> specs = {{"hrls", NET_FEAT, 10, 3, 16, 0, 1.0f},
+  std::vector<Spec> specs = {{"hrls", NET_FEAT, hr_in, 3, 16, 0, 1.0f},
                              {"lrhs", NET_FEAT, 3, 3, 8, 2, 1.0f},
                              {"fuse", NET_FEAT, NET_FEAT + NET_SCALE * NET_SCALE * NET_FEAT, 1,
                               NET_FEAT + NET_SCALE * NET_SCALE * NET_FEAT, 2, 1.0f}};
@@ -49,7 +50,7 @@ std::vector<Spec> specs_res16() {
 // outputs are near the scale of the images rather than ~10x above it, where
 // the robust loss is flat and training drifts away).
 // D = log2(scale) stacked stride-2 deshuffles and as many upscaling steps.
-std::vector<Spec> specs_rdg(int D) {
+std::vector<Spec> specs_rdg(int D, int hr_in) {
   static std::vector<std::string> names;
   if (names.empty()) {
     for (int g = 0; g < RDG_GROUPS; ++g)
@@ -60,7 +61,7 @@ std::vector<Spec> specs_rdg(int D) {
     for (int k = 0; k < RDG_MAX_DSF; ++k) names.push_back("up" + std::to_string(k));
   }
   const int fuse_in = NET_FEAT + (1 << (2 * D)) * NET_FEAT;
-  std::vector<Spec> specs = {{"hrls", NET_FEAT, 10, 3, 16, 0, 1.0f},
+  std::vector<Spec> specs = {{"hrls", NET_FEAT, hr_in, 3, 16, 0, 1.0f},
                              {"lrhs", NET_FEAT, 3, 3, 8, D, 1.0f},
                              {"fuse", NET_FEAT, fuse_in, 1, fuse_in, D, 1.0f}};
   const int ndense = RDG_GROUPS * RDG_BLOCKS * RDG_CONVS;
@@ -86,11 +87,20 @@ int arch_dsf(int arch) {
 }
 
 bool arch_is_rdg(int arch) {
-  return arch == MRS_NET_RDG || arch == MRS_NET_RDG_X2 || arch == MRS_NET_RDG_X8;
+  return arch == MRS_NET_RDG || arch == MRS_NET_RDG_X2 || arch == MRS_NET_RDG_X8 ||
+         arch == MRS_NET_RDG_LAYERS;
 }
 
+bool arch_has_layers(int arch) {
+  return arch == MRS_NET_RES16_LAYERS || arch == MRS_NET_RDG_LAYERS;
+}
+
+bool arch_known(int arch) { return arch == MRS_NET_RES16 || arch == MRS_NET_RES16_LAYERS || arch_is_rdg(arch); }
+
 std::vector<NetLayer> make_layers(int arch) {
-  const std::vector<Spec> specs = arch_is_rdg(arch) ? specs_rdg(arch_dsf(arch)) : specs_res16();
+  const int hr_in = arch_has_layers(arch) ? 16 : 10;
+  const std::vector<Spec> specs =
+      arch_is_rdg(arch) ? specs_rdg(arch_dsf(arch), hr_in) : specs_res16(hr_in);
   std::vector<NetLayer> L;
   int64_t off = 0, pk = 0, pkt = 0;
   for (const Spec& s : specs) {
@@ -200,7 +210,7 @@ mrs_status net_forward(mrs_net* net, int B, int H, int W, const float* hr, const
   const int h = H / NET_SCALE, w = W / NET_SCALE;
   const int64_t P = (int64_t)B * H * W, p = P / 16;
   prof_begin(KID_CNN_PREP, st);
-  launch_prep(P, p, hr, aux, lr, A.xh, A.xl, st);
+  launch_prep(net, P, p, hr, aux, lr, A.xh, A.xl, st);
   prof_end(KID_CNN_PREP, st);
   prof_begin(KID_CNN_HR, st);
   {  // h0 = ReLU(conv(xh))
@@ -462,7 +472,7 @@ void forward_train(mrs_net* net, const TrainArena& A, int B, int H, int W, const
   const std::vector<NetLayer>& Ls = net->layers;
   const int h = H / NET_SCALE, w = W / NET_SCALE;
   const int64_t P = (int64_t)B * H * W, p = P / 16;
-  launch_prep(P, p, hr, aux, lr, A.xh, A.xl, st);
+  launch_prep(net, P, p, hr, aux, lr, A.xh, A.xl, st);
   ConvArgs a = base_args(net, Ls[0], B, H, W);
   a.a = A.xh;
   a.ca = 16;
@@ -660,6 +670,9 @@ mrs_status check_train_args(mrs_net* n, int B, const float* hr, const float* aux
   if (((uintptr_t)hr | (uintptr_t)aux | (uintptr_t)lr | (uintptr_t)tgt) & 3u)
     return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_train_step: buffers must be 4-byte aligned");
   if (!n->has_params) return fail(MRS_ERR_NOT_READY, "mrs_train_step: no parameters");
+  if (arch_has_layers(n->arch) && !n->in_layers)
+    return fail(MRS_ERR_NOT_READY, "mrs_train_step: bind the HRLS render layers first "
+                                   "(mrs_net_bind_layers)");
   return MRS_OK;
 }
 
@@ -695,7 +708,7 @@ mrs_status loss_and_grad(mrs_net* n, int B, const float* hr, const float* aux, c
 
 int64_t arch_params(int32_t arch) {
   if (arch == MRS_NET_RES16) return NET_NUM_PARAMS;
-  if (!arch_is_rdg(arch)) return -1;
+  if (!arch_known(arch)) return -1;
   int64_t n = 0;
   for (const NetLayer& L : make_layers(arch)) n += (int64_t)L.cout * L.cin * L.k * L.k + L.cout;
   return n;
@@ -750,6 +763,27 @@ mrs_status mrs_net_create_arch(int32_t arch, mrs_net** out) {
 }
 
 mrs_status mrs_net_create(mrs_net** out) { return mrs_net_create_arch(MRS_NET_RES16, out); }
+
+mrs_status mrs_net_bind_layers(mrs_net* n, const float* layers_dev, const float* sumsq_dev,
+                               int32_t spp) {
+  if (!n) return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_net_bind_layers: net is NULL");
+  if (!arch_has_layers(n->arch))
+    return fail(MRS_ERR_INVALID_ARGUMENT,
+                "mrs_net_bind_layers: this architecture takes no render layers");
+  if (!layers_dev && !sumsq_dev && spp == 0) {  // unbind
+    n->in_layers = n->in_sumsq = nullptr;
+    n->in_spp = 0;
+    return MRS_OK;
+  }
+  if (!layers_dev || !sumsq_dev || spp < 1 || (((uintptr_t)layers_dev | (uintptr_t)sumsq_dev) & 3u))
+    return fail(MRS_ERR_INVALID_ARGUMENT,
+                "mrs_net_bind_layers: layers and sums of squares must be non-NULL, 4-byte "
+                "aligned device buffers and spp >= 1");
+  n->in_layers = layers_dev;
+  n->in_sumsq = sumsq_dev;
+  n->in_spp = spp;
+  return MRS_OK;
+}
 
 mrs_status mrs_net_destroy(mrs_net* n) {
   if (!n) return MRS_OK;
@@ -813,6 +847,9 @@ mrs_status mrs_fuse_batch(mrs_net* n, int32_t B, const float* hr, const float* a
   if (((uintptr_t)hr | (uintptr_t)aux | (uintptr_t)lr | (uintptr_t)out) & 3u)
     return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_fuse: buffers must be 4-byte aligned");
   if (!n->has_params) return fail(MRS_ERR_NOT_READY, "mrs_fuse: no network parameters loaded");
+  if (arch_has_layers(n->arch) && !n->in_layers)
+    return fail(MRS_ERR_NOT_READY, "mrs_fuse: bind the HRLS render layers first "
+                                   "(mrs_net_bind_layers)");
   if (arch_is_rdg(n->arch)) return rdg_forward(n, B, H, W, hr, aux, lr, out, current_stream());
   return net_forward(n, B, H, W, hr, aux, lr, out, current_stream());
 }

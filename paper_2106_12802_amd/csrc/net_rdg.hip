@@ -73,7 +73,7 @@ void forward(mrs_net* net, const RdgActs& A, bool keep, int B, int H, int W, con
   const int h = H / sc, w = W / sc;
   const int64_t P = (int64_t)B * H * W, p = (int64_t)lr_pixels(P, Dn);
   prof_begin(KID_CNN_PREP, st);
-  launch_prep(P, p, hr, aux, lr, A.xh, A.xl, st);
+  launch_prep(net, P, p, hr, aux, lr, A.xh, A.xl, st);
   prof_end(KID_CNN_PREP, st);
   prof_begin(KID_CNN_HR, st);
   {  // F^0_HRLS

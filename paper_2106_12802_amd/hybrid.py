@@ -69,6 +69,9 @@ class HybridFrame:
         self.net = net
         self.out = _empty((H, W, 3))
         self.fallback = net is None or not net.ready
+        self.spp_h = spp_h
+        if not self.fallback and net.has_layers:
+            layers = True  # the network reads them
         if self.fallback:
             self.batch = T.Batch([dict(scene=gs, W=W, H=H, spp=fallback_spp(spp_h, spp_l),
                                        max_depth=depth, seed=0, out_rgb=self.out,
@@ -93,7 +96,11 @@ class HybridFrame:
             return self.out
         self.batch.set_seeds([2 * seed, 2 * seed + 1])
         self.batch.render()
-        return self.net.fuse(self.hr_rgb, self.hr_aux, self.lr_rgb, out=self.out)
+        return self._fuse()
+
+    def _fuse(self):
+        lay = (self.hr_layers, self.hr_sumsq, self.spp_h) if self.net.has_layers else None
+        return self.net.fuse(self.hr_rgb, self.hr_aux, self.lr_rgb, out=self.out, layers=lay)
 
     def _seeds(self, seed):
         return [2 * seed] if self.fallback else [2 * seed, 2 * seed + 1]
@@ -117,7 +124,7 @@ class HybridFrame:
                 self.batch.set_seeds(self._seeds(seeds[k + 1]))
                 self.batch.render_begin()
             if not self.fallback:
-                self.net.fuse(self.hr_rgb, self.hr_aux, self.lr_rgb, out=self.out)
+                self._fuse()
             if on_frame is not None:
                 on_frame(k, self.out)
         return self.out
@@ -134,6 +141,14 @@ def hybrid_frame(gs, net: FusionNet | None, W, H, seed, spp_h=4, spp_l=64, depth
         out = _empty((H, W, 3)) if out is None else out
         T.render_ex(gs, W, H, fallback_spp(spp_h, spp_l), depth, 2 * seed, out, None)
         return out, None
+    if net.has_layers:  # the HRLS render also keeps its layers and sums of squares
+        frame = HybridFrame(gs, net, W, H, spp_h, spp_l, depth)
+        if out is not None:
+            frame.out = out
+        img = frame.render(seed)
+        res = (frame.hr_rgb, frame.hr_aux, frame.lr_rgb)
+        frame.close()
+        return img, res
     hr_rgb, hr_aux, lr_rgb = render_inputs(gs, W, H, seed, spp_h, spp_l, depth)
     out = net.fuse(hr_rgb, hr_aux, lr_rgb, out=out)
     return out, (hr_rgb, hr_aux, lr_rgb)
@@ -153,10 +168,12 @@ def reference(gs, W, H, spp=1024, seed=REF_SEED, depth=DEPTH, window=None):
 
 
 class PairSet:
-    """Training pairs resident on the GPU: HRLS rgb/features, LRHS rgb, target."""
+    """Training pairs resident on the GPU: HRLS rgb/features, LRHS rgb, target, and
+    (for the networks with layer inputs) the HRLS render layers and sums of squares."""
 
-    def __init__(self, hr_rgb, hr_aux, lr_rgb, target):
+    def __init__(self, hr_rgb, hr_aux, lr_rgb, target, hr_layers=None, hr_sumsq=None, spp_h=4):
         self.hr_rgb, self.hr_aux, self.lr_rgb, self.target = hr_rgb, hr_aux, lr_rgb, target
+        self.hr_layers, self.hr_sumsq, self.spp_h = hr_layers, hr_sumsq, spp_h
 
     def __len__(self):
         return self.hr_rgb.shape[0]
@@ -167,10 +184,21 @@ class PairSet:
         return [t.index_select(0, i).contiguous() for t in
                 (self.hr_rgb, self.hr_aux, self.lr_rgb, self.target)]
 
+    def layers(self, idx):
+        """(hr_layers, hr_sumsq, spp) of a batch, for mrs_net_bind_layers."""
+        import torch
+        if self.hr_layers is None:
+            raise ValueError("this pair set was built without render layers")
+        i = torch.as_tensor(idx, device="cuda", dtype=torch.long)
+        return (self.hr_layers.index_select(0, i).contiguous(),
+                self.hr_sumsq.index_select(0, i).contiguous(), self.spp_h)
+
 
 def build_dataset(first_seed=100, n_scenes=64, windows=16, size=128, W=1280, H=720,
-                  spp=(4, 64, 1024), tri_range=(10_000, 200_000), depth=DEPTH, log=print):
-    """Render `n_scenes` x `windows` training pairs of size x size HR pixels."""
+                  spp=(4, 64, 1024), tri_range=(10_000, 200_000), depth=DEPTH, log=print,
+                  layers=False):
+    """Render `n_scenes` x `windows` training pairs of size x size HR pixels
+    (layers: also the HRLS render layers and per-pixel sums of squares)."""
     import torch
     from mrs_inputs import scenes as S
     N = n_scenes * windows
@@ -178,6 +206,8 @@ def build_dataset(first_seed=100, n_scenes=64, windows=16, size=128, W=1280, H=7
     hr_aux = _empty((N, size, size, 7))
     lr_rgb = _empty((N, size // SCALE, size // SCALE, 3))
     target = _empty((N, size, size, 3))
+    hr_lay = _empty((N, size, size, 9)) if layers else None
+    hr_sq = torch.zeros((N, size, size, 3), dtype=torch.float32, device="cuda") if layers else None
     t0 = time.perf_counter()
     k = 0
     for si, (seed, tris) in enumerate(S.training_scene_specs(first_seed, n_scenes, *tri_range)):
@@ -186,7 +216,9 @@ def build_dataset(first_seed=100, n_scenes=64, windows=16, size=128, W=1280, H=7
         for (x0, y0) in S.training_windows(seed, windows, W, H, size):
             fseed = seed * 1000 + k % windows
             win = (x0, y0, size, size)
-            T.render_ex(gs, W, H, spp[0], depth, 2 * fseed, hr_rgb[k], hr_aux[k], window=win)
+            extra = dict(out_layers=hr_lay[k], out_sumsq=hr_sq[k]) if layers else {}
+            T.render_ex(gs, W, H, spp[0], depth, 2 * fseed, hr_rgb[k], hr_aux[k], window=win,
+                        **extra)
             T.render_ex(gs, W // SCALE, H // SCALE, spp[1], depth, 2 * fseed + 1, lr_rgb[k], None,
                         window=(x0 // SCALE, y0 // SCALE, size // SCALE, size // SCALE))
             T.render_ex(gs, W, H, spp[2], depth, REF_SEED + fseed, target[k], None, window=win)
@@ -195,7 +227,7 @@ def build_dataset(first_seed=100, n_scenes=64, windows=16, size=128, W=1280, H=7
         gs.close()
         if log and (si % 8 == 7 or si == n_scenes - 1):
             log(f"[data] {si + 1}/{n_scenes} scenes, {k} pairs, {time.perf_counter() - t0:.1f} s")
-    return PairSet(hr_rgb, hr_aux, lr_rgb, target)
+    return PairSet(hr_rgb, hr_aux, lr_rgb, target, hr_lay, hr_sq, spp[0])
 
 
 def train(net: FusionNet, data: PairSet, steps: int, batch=16, lr=1e-4, seed=0,
@@ -212,7 +244,8 @@ def train(net: FusionNet, data: PairSet, steps: int, batch=16, lr=1e-4, seed=0,
         idx = np.random.default_rng([seed, step]).choice(len(data), batch, replace=False)
         want = (step + 1) % log_every == 0 or step == steps - 1
         value = net.train_step(*data.batch(idx), lr=lr, want_loss=want, loss=loss,
-                               optimizer=optimizer, beta=beta)
+                               optimizer=optimizer, beta=beta,
+                               layers=data.layers(idx) if net.has_layers else None)
         done = step + 1
         if want:
             losses.append((done, value))
@@ -319,25 +352,55 @@ def train_random_spp(net: FusionNet, data: OnlinePairs, steps: int, batch=16, lr
 
 
 def loss_ablation(data: PairSet, settings, eval_scenes, seconds, W=1280, H=720, batch=16,
-                  lr=1e-4, seed=1, arch="res16", log=print):
+                  lr=1e-4, seed=1, arch="res16", log=print, optimizer="adam", weights_out=None):
     """One network per loss setting, each trained from the same init on the same
     pairs for the same time, then the hybrid frame's PSNR on each evaluation
     scene: {setting: {"steps": n, scene name: dB}}.  settings: ("l1", None) or
-    ("robust", beta)."""
+    ("robust", beta).  weights_out {setting key: path} saves the trained weights."""
     refs = {name: reference(gs, W, H, 1024, REF_SEED + k)
             for k, (name, gs) in enumerate(eval_scenes)}
     out = {}
     for loss, beta in settings:
         net = FusionNet(seed=seed, arch=arch)
-        _, done = train(net, data, 10 ** 9, batch, lr, seed=seed, log_every=2000, log=log,
-                        time_limit=seconds, loss=loss, beta=0.1 if beta is None else beta)
+        losses, done = train(net, data, 10 ** 9, batch, lr, seed=seed, log_every=2000, log=log,
+                             time_limit=seconds, loss=loss, beta=0.1 if beta is None else beta,
+                             optimizer=optimizer)
         key = loss if beta is None else f"{loss}_beta{beta:g}"
-        out[key] = {"steps": done}
+        out[key] = {"steps": done, "optimizer": optimizer, "lr": lr,
+                    "last_losses": [round(v, 6) for _, v in losses[-3:]]}
         for k, (name, gs) in enumerate(eval_scenes):
             img, _ = hybrid_frame(gs, net, W, H, k)
             out[key][name] = image_metrics(img, refs[name])["psnr"]
+        if weights_out and key in weights_out:
+            net.save_weights(weights_out[key])
         if log:
             log(f"[ablation] {key}: {out[key]}")
+        net.close()
+    return out
+
+
+def layers_ablation(data: PairSet, eval_scenes, seconds, W=1280, H=720, batch=16, lr=1e-4,
+                    seed=1, archs=("res16", "res16_layers"), log=print, weights_out=None):
+    """The input-layer ablation (Sec. 5, Fig. 9 on synthetic scenes): the network
+    with and without the HRLS render layers as inputs, each trained from the same
+    seed on the same pairs (built with layers=True) with L1 and Adam for the same
+    time, then the hybrid frame's PSNR on each evaluation scene:
+    {arch: {"steps": n, scene name: dB}}.  weights_out {arch: path} saves them."""
+    refs = {name: reference(gs, W, H, 1024, REF_SEED + k)
+            for k, (name, gs) in enumerate(eval_scenes)}
+    out = {}
+    for arch in archs:
+        net = FusionNet(seed=seed, arch=arch)
+        _, done = train(net, data, 10 ** 9, batch, lr, seed=seed, log_every=4000, log=log,
+                        time_limit=seconds)
+        out[arch] = {"steps": done}
+        for k, (name, gs) in enumerate(eval_scenes):
+            img, _ = hybrid_frame(gs, net, W, H, k)
+            out[arch][name] = image_metrics(img, refs[name])["psnr"]
+        if weights_out and arch in weights_out:
+            net.save_weights(weights_out[arch])
+        if log:
+            log(f"[layers ablation] {arch}: {out[arch]}")
         net.close()
     return out
 
@@ -453,8 +516,10 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--out", default="fusion_checkpoint.bin", help="resumable checkpoint")
     ap.add_argument("--weights-out", default=None, help="weights-only file for inference")
-    ap.add_argument("--arch", default="res16", choices=("res16", "rdg"),
-                    help="network: the configured 16-block trunk or the paper's (x4)")
+    ap.add_argument("--arch", default="res16",
+                    choices=("res16", "rdg", "res16_layers", "rdg_layers"),
+                    help="network: the configured 16-block trunk or the paper's (x4); "
+                         "*_layers: with the HRLS render layers as inputs")
     ap.add_argument("--loss", default="l1", choices=("l1", "robust"))
     ap.add_argument("--optimizer", default="adam", choices=("adam", "sgd"))
     ap.add_argument("--random-spp", action="store_true",
@@ -464,6 +529,13 @@ def main(argv=None):
                     help="instead of one run: train one network per loss (L1, and the paper's "
                          "robust loss at beta 0.1 and 1) for SECONDS each from the same init and "
                          "report the hybrid frame's PSNR on the bench and held-out scenes")
+    ap.add_argument("--ablate-layers", type=float, default=None, metavar="SECONDS",
+                    help="instead of one run: the 16-block network without and with the HRLS "
+                         "render layers as inputs, SECONDS of training each from the same seed "
+                         "on the same pairs; the hybrid frame's PSNR on the bench and held-out "
+                         "scenes")
+    ap.add_argument("--ablation-weights", default=None, metavar="PREFIX",
+                    help="save each ablation network's weights to PREFIX<name>.bin")
     ap.add_argument("--init-weights", default=None,
                     help="start from these weights (fine-tuning) instead of a fresh init")
     ap.add_argument("--eval-scenes", type=int, default=4)
@@ -471,14 +543,25 @@ def main(argv=None):
     args = ap.parse_args(argv)
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
     torch.cuda.set_device(0)
-    if args.ablate_loss:
-        data = build_dataset(n_scenes=args.scenes, windows=args.windows, log=log)
+    if args.ablate_loss or args.ablate_layers:
+        data = build_dataset(n_scenes=args.scenes, windows=args.windows, log=log,
+                             layers=bool(args.ablate_layers))
         evals = [("bench", T.GpuScene(S.procedural(7)))]
         evals += [(f"heldout_{sd}", T.GpuScene(S.procedural_sized(sd, tr)))
                   for sd, tr in S.training_scene_specs(200, args.eval_scenes)]
-        res = loss_ablation(data, (("l1", None), ("robust", 0.1), ("robust", 1.0)), evals,
-                            args.ablate_loss, batch=args.batch, lr=args.lr, seed=args.seed,
-                            arch=args.arch, log=log)
+        pre = args.ablation_weights
+        if args.ablate_layers:
+            archs = ("res16", "res16_layers")
+            res = layers_ablation(data, evals, args.ablate_layers, batch=args.batch, lr=args.lr,
+                                  seed=args.seed, archs=archs, log=log,
+                                  weights_out={a: f"{pre}{a}.bin" for a in archs} if pre else None)
+        else:
+            settings = (("l1", None), ("robust", 0.1), ("robust", 1.0))
+            keys = ("l1", "robust_beta0.1", "robust_beta1")
+            res = loss_ablation(data, settings, evals, args.ablate_loss, batch=args.batch,
+                                lr=args.lr, seed=args.seed, arch=args.arch, log=log,
+                                optimizer=args.optimizer,
+                                weights_out={k: f"{pre}{k}.bin" for k in keys} if pre else None)
         print(json.dumps(res))
         return
     net = FusionNet(seed=args.seed, arch=args.arch)

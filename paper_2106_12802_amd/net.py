@@ -14,7 +14,10 @@ class FusionNet:
 
     arch "res16": 16 residual blocks; "rdg": the paper's network of residual
     dense groups, x4 ("rdg_x2", "rdg_x8": the same at x2 and x8; include/mrs.h
-    documents them).  .scale is the HR / LR size ratio."""
+    documents them); "res16_layers" / "rdg_layers": the x4 networks whose HRLS
+    input also carries the render layers (pass layers=(hr_layers, hr_sumsq, spp)
+    to the calls, or bind them once with bind_layers).  .scale is the HR / LR
+    size ratio."""
 
     def __init__(self, seed: int | None = None, arch: str = "res16"):
         import torch  # noqa: F401  (initialises the HIP runtime through torch)
@@ -28,8 +31,25 @@ class FusionNet:
         self.handle = h
         self.num_params = int(L.lib().mrs_net_arch_num_params(L.NET_ARCHS[arch]))
         self.ready = False  # parameters loaded (mrs_fuse refuses to run before)
+        self.has_layers = arch.endswith("_layers")
+        self._bound = None  # keeps the bound layer tensors alive
         if seed is not None:
             self.init(seed)
+
+    def bind_layers(self, hr_layers, hr_sumsq, spp):
+        """The HRLS render layers ([..,9]: emission, diffuse, glossy) and sums of
+        squares ([..,3]) that later calls of a layered network read (mrs_net_bind_layers)."""
+        L.check(L.lib().mrs_net_bind_layers(self.handle, L.ptr(hr_layers, None, "f32", "hr_layers"),
+                                            L.ptr(hr_sumsq, None, "f32", "hr_sumsq"), int(spp)))
+        self._bound = (hr_layers, hr_sumsq)
+
+    def _layers(self, layers, P):
+        if layers is None:
+            return
+        lay, sq, spp = layers
+        if lay.numel() != 9 * P or sq.numel() != 3 * P:
+            raise ValueError(f"layers must hold {9 * P} and {3 * P} values")
+        self.bind_layers(lay, sq, spp)
 
     def init(self, seed: int):
         L.use_current_stream()
@@ -48,8 +68,9 @@ class FusionNet:
         L.check(L.lib().mrs_net_get_params(self.handle, p.ctypes.data_as(C.c_void_p), p.size))
         return p
 
-    def fuse(self, hrls_rgb, hrls_aux, lrhs_rgb, out=None):
-        """hrls_rgb [B,H,W,3] or [H,W,3], hrls_aux [...,7], lrhs_rgb [..,H/s,W/s,3] (CUDA fp32)."""
+    def fuse(self, hrls_rgb, hrls_aux, lrhs_rgb, out=None, layers=None):
+        """hrls_rgb [B,H,W,3] or [H,W,3], hrls_aux [...,7], lrhs_rgb [..,H/s,W/s,3] (CUDA fp32);
+        layers = (hr_layers, hr_sumsq, spp) for the layered networks."""
         import torch
         batched = hrls_rgb.dim() == 4
         B = hrls_rgb.shape[0] if batched else 1
@@ -57,6 +78,7 @@ class FusionNet:
         if out is None:
             out = torch.empty(hrls_rgb.shape, dtype=torch.float32, device=hrls_rgb.device)
         P = B * H * W
+        self._layers(layers, P)
         L.use_current_stream()
         L.check(L.lib().mrs_fuse_batch(self.handle, B, L.ptr(hrls_rgb, 3 * P, "f32", "hrls_rgb"),
                                        L.ptr(hrls_aux, 7 * P, "f32", "hrls_aux"),
@@ -70,12 +92,13 @@ class FusionNet:
         B = hrls_rgb.shape[0] if batched else 1
         return B, hrls_rgb.shape[-3], hrls_rgb.shape[-2]
 
-    def loss_grad(self, hrls_rgb, hrls_aux, lrhs_rgb, target, loss="l1", beta=0.1):
+    def loss_grad(self, hrls_rgb, hrls_aux, lrhs_rgb, target, loss="l1", beta=0.1, layers=None):
         """(grad [num_params] float32, loss (FP64), network output tensor); no update.
 
         loss "l1" or "robust" (the paper's l_r with robust factor beta)."""
         import torch
         B, H, W = self._dims(hrls_rgb)
+        self._layers(layers, B * H * W)
         g = np.empty(self.num_params, np.float32)
         value = C.c_double()
         out = torch.empty(hrls_rgb.shape, dtype=torch.float32, device=hrls_rgb.device)
@@ -90,9 +113,10 @@ class FusionNet:
                                              L.ptr(out)))
         return g, value.value, out
 
-    def backward(self, hrls_rgb, hrls_aux, lrhs_rgb, grad_out):
+    def backward(self, hrls_rgb, hrls_aux, lrhs_rgb, grad_out, layers=None):
         """Parameter gradient [num_params] float32 for a given dL/dI_SR (CUDA fp32)."""
         B, H, W = self._dims(hrls_rgb)
+        self._layers(layers, B * H * W)
         g = np.empty(self.num_params, np.float32)
         L.use_current_stream()
         P = B * H * W
@@ -104,10 +128,11 @@ class FusionNet:
         return g
 
     def train_step(self, hrls_rgb, hrls_aux, lrhs_rgb, target, lr=1e-4, want_loss=False,
-                   loss="l1", beta=0.1, optimizer="adam"):
+                   loss="l1", beta=0.1, optimizer="adam", layers=None):
         """One optimiser step ("adam" or "sgd") on the loss ("l1" or "robust");
         returns the loss of this step (synchronising) if want_loss."""
         B, H, W = self._dims(hrls_rgb)
+        self._layers(layers, B * H * W)
         value = C.c_double()
         opts = L.TrainOpts(L.LOSSES[loss], float(beta), L.OPTIMIZERS[optimizer], float(lr))
         L.use_current_stream()
