@@ -845,6 +845,8 @@ def main():
                     help="tuning: concurrent sub-chunks per render (1..4)")
     ap.add_argument("--tail-bounce", type=int, default=None,
                     help="tuning: first bounce traced path by path in one launch (65: never)")
+    ap.add_argument("--queue-sort", type=int, default=None, choices=(0, 1),
+                    help="tuning: order appended rays by octant / shadow rays by light")
     ap.add_argument("--bvh-builder", default=None, choices=("lbvh", "ploc"),
                     help="tuning: BVH builder of the scenes (default ploc)")
     ap.add_argument("--leaf-max", type=int, default=None,
@@ -881,7 +883,7 @@ def main():
     if args.copy_calibration:
         copy_calibration()
     R.set_tuning(args.chunk_paths, args.trace_blocks, args.schedule, args.leaf_max, args.streams,
-                 args.tail_bounce, args.bvh_builder)
+                 args.tail_bounce, args.bvh_builder, queue_sort=args.queue_sort)
     tuning = R.get_tuning()
     log(f"[bench] tuning {tuning}")
     scene = S.procedural(SCENE_SEED)

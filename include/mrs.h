@@ -334,6 +334,10 @@ typedef struct mrs_tuning {
                            16x16 tiles of 8 waves (0: always the large tiles).
                            Both sum in the same order: outputs are bitwise
                            the same */
+  int32_t queue_sort;   /* 1 (default): the shade kernel orders each block's
+                           appended rays by direction octant and its shadow rays
+                           by light, so that a wave of the next traversal holds
+                           alike rays; 0: in lane order */
 } mrs_tuning;
 mrs_status mrs_get_tuning(mrs_tuning* out);
 mrs_status mrs_set_tuning(const mrs_tuning* t);

@@ -98,6 +98,48 @@ __device__ __forceinline__ void block_append2(bool pa, bool pb, uint32_t* ca, ui
   __syncthreads();
 }
 
+// block_append2 with each entry's place inside its block's segment ordered by
+// a small key (0..7; stable within a key): the rays of a wave of the next
+// kernel then share one or two keys (a direction octant, a light), which keeps
+// their traversals alike.  Same contract as block_append2.
+struct BlockAppendKeyed {
+  uint32_t cnt[2][8][4];  // queue, key, wave: counts, then exclusive offsets
+  uint32_t base[2];
+};
+__device__ __forceinline__ void block_append2_keyed(bool pa, uint32_t ka, bool pb, uint32_t kb,
+                                                    uint32_t* ca, uint32_t* cb, uint32_t& ia,
+                                                    uint32_t& ib, BlockAppendKeyed& sh) {
+  const int wave = threadIdx.x >> 6;
+  uint32_t ra = 0, rb = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < 8; ++k) {
+    const uint64_t ma = __ballot(pa && ka == k), mb = __ballot(pb && kb == k);
+    if (pa && ka == k) ra = lanes_below(ma);
+    if (pb && kb == k) rb = lanes_below(mb);
+    if (__lane_id() == 0) {
+      sh.cnt[0][k][wave] = (uint32_t)__popcll(ma);
+      sh.cnt[1][k][wave] = (uint32_t)__popcll(mb);
+    }
+  }
+  __syncthreads();
+  if (wave == 0) {  // lane l: queue l / 32, entry l % 32 = key * 4 + wave, scanned in order
+    const int lane = __lane_id(), qq = lane >> 5, i = lane & 31;
+    const uint32_t c = sh.cnt[qq][i >> 2][i & 3];
+    uint32_t x = c;
+#pragma unroll
+    for (int d = 1; d < 32; d <<= 1) {
+      const uint32_t y = __shfl_up(x, d, 32);
+      if (i >= d) x += y;
+    }
+    sh.cnt[qq][i >> 2][i & 3] = x - c;
+    if (i == 31) sh.base[qq] = x ? atomicAdd(qq ? cb : ca, x) : 0u;
+  }
+  __syncthreads();
+  ia = pa ? sh.base[0] + sh.cnt[0][ka & 7][wave] + ra : 0u;
+  ib = pb ? sh.base[1] + sh.cnt[1][kb & 7][wave] + rb : 0u;
+  __syncthreads();
+}
+
 __device__ __forceinline__ float safe_rcp(float x) {
   const float ax = fabsf(x) > 1e-20f ? x : copysignf(1e-20f, x);
   return __builtin_amdgcn_rcpf(ax);
@@ -832,6 +874,7 @@ __device__ __forceinline__ void shade_vertex(const DevJob& J, int64_t g, int b, 
   v.L = L;
 }
 
+template <bool SORT>
 __global__ __launch_bounds__(256) void k_shade(const DevJob* __restrict__ jobs, int64_t g0, int b,
                                                const float4* __restrict__ rays_in,
                                                const float4* __restrict__ hits,
@@ -846,10 +889,13 @@ __global__ __launch_bounds__(256) void k_shade(const DevJob* __restrict__ jobs, 
   uint32_t* cnt_next = q + Q_RAYS + b + 1;
   uint32_t* cnt_shadow = q + Q_SHADOW + b;
   __shared__ BlockAppend2 sh_app;
+  __shared__ BlockAppendKeyed sh_key;
   for (uint32_t base = blockIdx.x * 256; base < n; base += gridDim.x * 256) {
     const uint32_t qi = base + threadIdx.x;
     Vertex v;
     v.cont = v.shad = false;
+    v.li = 0;
+    v.wi = F3(0.0f, 0.0f, 0.0f);
     uint32_t slot = 0, j = 0;
     if (qi < n) {
       const float4 R0 = rays_in[2 * qi], R1 = rays_in[2 * qi + 1];
@@ -870,7 +916,11 @@ __global__ __launch_bounds__(256) void k_shade(const DevJob* __restrict__ jobs, 
         lay_buf[slot] = make_float4(v.L.x, v.L.y, v.L.z, (float)v.lobe);
     }
     uint32_t ri, si;
-    block_append2(v.cont, v.shad, cnt_next, cnt_shadow, ri, si, sh_app);
+    if (SORT)  // continuing rays by direction octant, shadow rays by light
+      block_append2_keyed(v.cont, (v.wi.x < 0.0f) | (v.wi.y < 0.0f) << 1 | (v.wi.z < 0.0f) << 2,
+                          v.shad, v.li & 7u, cnt_next, cnt_shadow, ri, si, sh_key);
+    else
+      block_append2(v.cont, v.shad, cnt_next, cnt_shadow, ri, si, sh_app);
     if (v.cont) {
       rays_out[2 * ri] = make_float4(v.x.x, v.x.y, v.x.z, __uint_as_float(slot));
       rays_out[2 * ri + 1] = make_float4(v.wi.x, v.wi.y, v.wi.z, __uint_as_float((j << 24) | v.prim));
@@ -1352,7 +1402,7 @@ hipStream_t g_sub[MAX_SUB] = {};
 int g_nsub = 0;
 unsigned long long* g_stats = nullptr;  // device counters shared by every stream
 // defaults: the fastest hybrid 720p frame measured with the clustered BVH
-mrs_tuning g_tune = {1 << 23, 8192, 0, 3, 3, 3, MRS_BVH_PLOC, 128};
+mrs_tuning g_tune = {1 << 23, 8192, 0, 3, 3, 3, MRS_BVH_PLOC, 128, 1};
 std::atomic<int> g_conv_small{128};  // g_tune.conv_small_tiles, read without the lock
 std::atomic<bool> g_count_work{false};
 
@@ -1584,9 +1634,14 @@ mrs_status begin_batch(Workspace& ws, const mrs_tuning& tu, const DevJob* d_jobs
       for (int k = 0; k < used; ++k) {
         Sub& u = sub[k];
         prof_begin(KID_SHADE, u.s);
-        k_shade<<<u.gb, 256, 0, u.s>>>(d_jobs, u.lo, b, u.rays[b & 1], u.hits, u.q,
-                                       u.rays[(b + 1) & 1], u.shadow, u.beta, u.L, u.aux,
-                                       u.lay);
+        if (tu.queue_sort)
+          k_shade<true><<<u.gb, 256, 0, u.s>>>(d_jobs, u.lo, b, u.rays[b & 1], u.hits, u.q,
+                                               u.rays[(b + 1) & 1], u.shadow, u.beta, u.L,
+                                               u.aux, u.lay);
+        else
+          k_shade<false><<<u.gb, 256, 0, u.s>>>(d_jobs, u.lo, b, u.rays[b & 1], u.hits, u.q,
+                                                u.rays[(b + 1) & 1], u.shadow, u.beta, u.L,
+                                                u.aux, u.lay);
         prof_end(KID_SHADE, u.s);
       }
       if (b < max_depth) {
@@ -2020,6 +2075,8 @@ mrs_status set_tuning(const mrs_tuning* t) {
     return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_set_tuning: bvh_builder must be 0 or 1");
   if (t->conv_small_tiles < 0 || t->conv_small_tiles > (1 << 30))
     return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_set_tuning: conv_small_tiles must be in [0, 2^30]");
+  if (t->queue_sort != 0 && t->queue_sort != 1)
+    return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_set_tuning: queue_sort must be 0 or 1");
   std::lock_guard<std::mutex> lk(g_mu);
   g_tune = *t;
   g_conv_small = t->conv_small_tiles;

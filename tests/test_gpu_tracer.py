@@ -434,17 +434,38 @@ def test_window_is_crop_and_chunking_invariant(mrs, torch_cuda):
     assert torch_cuda.equal(waux, faux[12:21, 8:25])
     old = mrs.get_tuning()
     try:
-        for chunk, blocks, sched in [(256, 3, 1), (1000, 7, 0), (48 * 40 * 2 + 5, 64, 1)]:
-            mrs.set_tuning(chunk_paths=chunk, trace_blocks=blocks, schedule=sched)
+        for chunk, blocks, sched, qs in [(256, 3, 1, 0), (1000, 7, 0, 1), (48 * 40 * 2 + 5, 64, 1, 0),
+                                         (48 * 40 * 2 + 5, 64, 1, 1)]:
+            mrs.set_tuning(chunk_paths=chunk, trace_blocks=blocks, schedule=sched, queue_sort=qs)
             again, aaux = mrs.render(gs, 48, 40, 6, 4, 77)
             torch_cuda.cuda.synchronize()
-            assert torch_cuda.equal(again, full), (chunk, blocks, sched)
+            assert torch_cuda.equal(again, full), (chunk, blocks, sched, qs)
             assert torch_cuda.equal(aaux, faux)
     finally:
         mrs.set_tuning(**old)
     again, _ = mrs.render(gs, 48, 40, 6, 4, 77)
     torch_cuda.cuda.synchronize()
     assert torch_cuda.equal(again, full)  # deterministic run to run
+
+
+def test_queue_order_does_not_change_the_image(mrs, torch_cuda):
+    """Ordering each block's appended rays by direction octant and its shadow rays by
+    light (queue_sort) changes which rays share a wave, not any result: the full HRLS
+    render of the bench scene, with features and render layers, is bitwise the same."""
+    gs = mrs.GpuScene(S.procedural(7))
+    old = mrs.get_tuning()
+    outs = []
+    try:
+        for qs in (0, 1):
+            mrs.set_tuning(queue_sort=qs)
+            lay = torch_cuda.empty(720, 1280, 9, device="cuda")
+            rgb, aux = mrs.render(gs, 1280, 720, 4, 8, 14, out_layers=lay)
+            torch_cuda.cuda.synchronize()
+            outs.append((rgb, aux, lay))
+    finally:
+        mrs.set_tuning(**old)
+    for a, b in zip(*outs):
+        assert torch_cuda.equal(a, b)
 
 
 def test_sub_chunks_beyond_2_24_paths(mrs, torch_cuda):
