@@ -534,6 +534,8 @@ def main(argv=None):
                          "render layers as inputs, SECONDS of training each from the same seed "
                          "on the same pairs; the hybrid frame's PSNR on the bench and held-out "
                          "scenes")
+    ap.add_argument("--loss-settings", default="l1,robust:0.1,robust:1",
+                    help="losses of --ablate-loss: comma-separated l1 or robust:<beta>")
     ap.add_argument("--ablation-weights", default=None, metavar="PREFIX",
                     help="save each ablation network's weights to PREFIX<name>.bin")
     ap.add_argument("--init-weights", default=None,
@@ -556,8 +558,11 @@ def main(argv=None):
                                   seed=args.seed, archs=archs, log=log,
                                   weights_out={a: f"{pre}{a}.bin" for a in archs} if pre else None)
         else:
-            settings = (("l1", None), ("robust", 0.1), ("robust", 1.0))
-            keys = ("l1", "robust_beta0.1", "robust_beta1")
+            settings = []
+            for item in args.loss_settings.split(","):
+                name, _, beta = item.partition(":")
+                settings.append((name, float(beta) if beta else None))
+            keys = [n if b is None else f"{n}_beta{b:g}" for n, b in settings]
             res = loss_ablation(data, settings, evals, args.ablate_loss, batch=args.batch,
                                 lr=args.lr, seed=args.seed, arch=args.arch, log=log,
                                 optimizer=args.optimizer,
