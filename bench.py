@@ -154,10 +154,10 @@ def pmc_summary(fetch_path, write_path, out_path):
         "# (max depth 8) + fusion network.",
         "# Made by (each pass its own process, run from the repository root):",
         "#   rocprofv3 --pmc FETCH_SIZE -f csv -d gpurun_out/pmc_fetch -o pmc -- python bench.py "
-        "--steps 1 --warmup 0 --no-cpu-baseline --equal-psnr-scenes 0 --batch-scenes 0 --no-paper-net --no-mis --no-camera --no-spp-pairs --no-two-calls --no-training "
+        "--steps 1 --warmup 0 --no-cpu-baseline --equal-psnr-scenes 0 --batch-scenes 0 --no-paper-net --no-mis --no-camera --no-spp-pairs --no-two-calls --no-training --no-ablations "
         "--copy-calibration",
         "#   rocprofv3 --pmc WRITE_SIZE -f csv -d gpurun_out/pmc_write -o pmc -- python bench.py "
-        "--steps 1 --warmup 0 --no-cpu-baseline --equal-psnr-scenes 0 --batch-scenes 0 --no-paper-net --no-mis --no-camera --no-spp-pairs --no-two-calls --no-training "
+        "--steps 1 --warmup 0 --no-cpu-baseline --equal-psnr-scenes 0 --batch-scenes 0 --no-paper-net --no-mis --no-camera --no-spp-pairs --no-two-calls --no-training --no-ablations "
         "--copy-calibration",
         "#   python bench.py --pmc-summary gpurun_out/pmc_fetch gpurun_out/pmc_write",
         "# Counters are KiB per dispatch; each is scaled by COPY_BYTES over what the same counter",
@@ -183,7 +183,7 @@ COUNTERS_SUMMARY = os.path.join(ROOT, "profiles", "hybrid_frame_procedural101k_7
 COUNTER_SOURCES = [os.path.join(ROOT, "paper_2106_12802_amd", "csrc", f)
                    for f in ("trace.hip", "lbvh.hip", "cnn.hip", "net.hip")]
 PROFILE_ARGS = ("--steps 1 --warmup 0 --no-cpu-baseline --equal-psnr-scenes 0 --batch-scenes 0 "
-                "--no-paper-net --no-mis --no-camera --no-spp-pairs --no-two-calls --no-training")
+                "--no-paper-net --no-mis --no-camera --no-spp-pairs --no-two-calls --no-training --no-ablations")
 # rocprofv3 --pmc passes (one process each; each within the per-block counter limits)
 COUNTER_PASSES = {
     "valu": "VALUBusy VALUUtilization SQ_INSTS_VALU SQ_WAVES GRBM_GUI_ACTIVE",
@@ -309,7 +309,7 @@ def read_counters():
 
 STATS_SUMMARY = os.path.join(ROOT, "profiles", "hybrid_frame_procedural101k_720p_kernel_stats.txt")
 STATS_CMD = ("rocprofv3 --kernel-trace --stats -f csv -d gpurun_out/prof -o bench -- python -u "
-             "bench.py --steps 5 --warmup 1 --no-cpu-baseline --equal-psnr-scenes 0 --batch-scenes 0 --no-paper-net --no-mis --no-camera --no-spp-pairs --no-two-calls --no-training")
+             "bench.py --steps 5 --warmup 1 --no-cpu-baseline --equal-psnr-scenes 0 --batch-scenes 0 --no-paper-net --no-mis --no-camera --no-spp-pairs --no-two-calls --no-training --no-ablations")
 
 
 def stats_summary(prof_dir, out_path):
@@ -710,6 +710,56 @@ def spp_sweep(log):
     return out
 
 
+ABLATIONS_JSON = os.path.join(ROOT, "paper_2106_12802_amd", "weights", "ablations.json")
+
+
+def ablations_block(log, scenes=((7, None), (200, None))):
+    """The trained ablation networks (paper_2106_12802_amd/weights/ablations.json):
+    with and without the HRLS render layers as inputs, and the paper's network
+    trained with its own recipe (robust loss, SGD) against L1 with the same
+    optimiser: each network's hybrid 720p frame PSNR against an independent
+    1024-spp reference, on the bench scene and a held-out scene, plus the
+    record of its training run."""
+    import torch
+    import paper_2106_12802_amd as mrs
+    from paper_2106_12802_amd import hybrid
+    from paper_2106_12802_amd.metrics import image_metrics
+    from mrs_inputs import scenes as S
+    if not os.path.exists(ABLATIONS_JSON):
+        return None
+    meta = json.load(open(ABLATIONS_JSON))
+    wdir = os.path.dirname(ABLATIONS_JSON)
+    specs = dict(S.training_scene_specs(200, 1))
+    evals = []
+    for seed, _ in scenes:
+        scene = S.procedural(seed) if seed == 7 else S.procedural_sized(seed, specs[seed])
+        gs = mrs.GpuScene(scene)
+        evals.append((f"bench" if seed == 7 else f"heldout_{seed}", gs,
+                      hybrid.reference(gs, 1280, 720, 1024, hybrid.REF_SEED + seed)))
+    out = {}
+    for study, rec in meta.items():
+        res = {"training": rec.get("training"), "psnr_at_training": rec.get("psnr_at_training")}
+        for arch_key, fname in rec["weights"].items():
+            path = os.path.join(wdir, fname)
+            if not os.path.exists(path):
+                continue
+            arch = rec.get("arch", {}).get(arch_key, arch_key)
+            net = mrs.FusionNet(arch=arch)
+            net.load_weights(path)
+            r = {}
+            for k, (name, gs, ref) in enumerate(evals):
+                img, _ = hybrid.hybrid_frame(gs, net, 1280, 720, 1000 + k)
+                torch.cuda.synchronize()
+                r[name] = round(image_metrics(img, ref)["psnr"], 3)
+            net.close()
+            res[arch_key] = r
+            log(f"[bench] ablation {study} {arch_key}: {r}")
+        out[study] = res
+    for _, gs, _ in evals:
+        gs.close()
+    return out
+
+
 def res16_flop(B, H, W):
     """Forward FLOP of the 16-residual-block network on B frames of H x W (x4):
     2 x sum over convs of output pixels x C_out x C_in x k^2."""
@@ -835,6 +885,8 @@ def main():
                     help="skip timing the paper's own network (residual dense groups)")
     ap.add_argument("--no-training", action="store_true",
                     help="skip timing the training step of the 16-residual-block network")
+    ap.add_argument("--no-ablations", action="store_true",
+                    help="skip evaluating the trained ablation networks (input layers, loss)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 1 GiB device copy first (PMC byte-counter calibration)")
     ap.add_argument("--chunk-paths", type=int, default=None, help="tuning: paths resident at once")
@@ -1055,6 +1107,8 @@ def main():
         result["batched"] = batched_block(net, log, args.batch_scenes)
     if not args.no_training:
         result["training"] = training_block(log)
+    if not args.no_ablations:
+        result["ablations"] = ablations_block(log)
     if not args.no_paper_net:
         result["paper_net"] = paper_net_block(log)
     if not args.no_mis:
