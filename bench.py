@@ -897,6 +897,8 @@ def main():
                     help="tuning: concurrent sub-chunks per render (1..4)")
     ap.add_argument("--tail-bounce", type=int, default=None,
                     help="tuning: first bounce traced path by path in one launch (65: never)")
+    ap.add_argument("--bvh-quantized", type=int, default=None, choices=(0, 1),
+                    help="tuning: traverse the quantized 64-byte BVH4 nodes")
     ap.add_argument("--queue-sort", type=int, default=None, choices=(0, 1),
                     help="tuning: order appended rays by octant / shadow rays by light")
     ap.add_argument("--bvh-builder", default=None, choices=("lbvh", "ploc"),
@@ -935,7 +937,8 @@ def main():
     if args.copy_calibration:
         copy_calibration()
     R.set_tuning(args.chunk_paths, args.trace_blocks, args.schedule, args.leaf_max, args.streams,
-                 args.tail_bounce, args.bvh_builder, queue_sort=args.queue_sort)
+                 args.tail_bounce, args.bvh_builder, queue_sort=args.queue_sort,
+                 bvh_quantized=args.bvh_quantized)
     tuning = R.get_tuning()
     log(f"[bench] tuning {tuning}")
     scene = S.procedural(SCENE_SEED)

@@ -338,6 +338,10 @@ typedef struct mrs_tuning {
                            appended rays by direction octant and its shadow rays
                            by light, so that a wave of the next traversal holds
                            alike rays; 0: in lane order */
+  int32_t bvh_quantized; /* 1: traversal reads the 64-byte copy of each BVH4
+                           node whose child boxes are 8-bit steps from the node's
+                           origin, rounded outward with a margin; 0 (default):
+                           the 128-byte nodes with FP32 boxes.  Same hits */
 } mrs_tuning;
 mrs_status mrs_get_tuning(mrs_tuning* out);
 mrs_status mrs_set_tuning(const mrs_tuning* t);

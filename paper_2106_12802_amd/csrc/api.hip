@@ -82,6 +82,7 @@ void free_scene(mrs_scene* s) {
   dfree(s->d_leaf_tri);
   dfree(s->d_nodes);
   dfree(s->d_nodes4);
+  dfree(s->d_nodes4q);
   dfree(s->d_morton);
   dfree(s->d_leaf_prim);
   dfree(s->d_mats);
@@ -164,6 +165,7 @@ mrs_status scene_create_impl(const mrs_scene_desc* d, mrs_scene* s) {
   sv.ntris = n;
   sv.nlights = d->num_lights;
   sv.nodes = nullptr;  // BVH4, set by mrs_build_bvh
+  sv.nodes_q = nullptr;
   sv.nnodes = 0;
   sv.leaf_tri = s->d_leaf_tri;
   sv.prim_ng = s->d_prim_ng;
@@ -269,6 +271,7 @@ mrs_status mrs_build_bvh(mrs_scene* s) {
   if (rc != MRS_OK) return rc;
   s->view.root = s->root4;
   s->view.nodes = s->d_nodes4;
+  s->view.nodes_q = s->d_nodes4q;
   s->view.nnodes = s->count4;
   return MRS_OK;
 }

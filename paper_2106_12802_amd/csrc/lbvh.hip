@@ -724,6 +724,82 @@ __global__ __launch_bounds__(256) void k_compact4(const float4* __restrict__ spa
   dst[7] = src[7];
 }
 
+// Quantized copy of a BVH4 node (64 bytes, 4 float4): the node's box origin p
+// (minus a margin) and per-axis power-of-two steps s = 2^e, then each child's
+// box as 8-bit steps from p, rounded outward, and the child references:
+//   [0] p.x, p.y, p.z, bits(biased e_x | e_y << 8 | e_z << 16)
+//   [1] lo_x, lo_y, lo_z, hi_x  (one byte per child: byte c = child c)
+//   [2] hi_y, hi_z, 0, 0
+//   [3] child references (as in the full node)
+// Every quantized child box contains the exact one with a margin of at least
+// m = 2^-18 max(|node coordinates|, |scene coordinates|) on every side, so the
+// traversal's FP32 rounding never culls a box the full node would keep.
+__global__ __launch_bounds__(256) void k_quantize4(const float4* __restrict__ nodes4, int count,
+                                                   float4* __restrict__ q4) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= count) return;
+  const float4* nd = nodes4 + 8 * (size_t)i;
+  const float4* root = nodes4;
+  const float4 rf = nd[6];
+  const uint32_t ref[4] = {__float_as_uint(rf.x), __float_as_uint(rf.y), __float_as_uint(rf.z),
+                           __float_as_uint(rf.w)};
+  auto comp = [](const float4& v, int c) { return c == 0 ? v.x : c == 1 ? v.y : c == 2 ? v.z : v.w; };
+  double scene = 0.0;  // largest coordinate magnitude of the scene (the root's child boxes)
+  {
+    const uint32_t rr[4] = {__float_as_uint(root[6].x), __float_as_uint(root[6].y),
+                            __float_as_uint(root[6].z), __float_as_uint(root[6].w)};
+    for (int c = 0; c < 4; ++c)
+      if (rr[c] != EMPTY4)
+        for (int a = 0; a < 6; ++a) scene = fmax(scene, fabs((double)comp(root[a], c)));
+  }
+  float P[3];
+  uint32_t E = 0, qlo[3] = {0u, 0u, 0u}, qhi[3] = {0u, 0u, 0u};
+  for (int a = 0; a < 3; ++a) {
+    double lo = INFINITY, hi = -INFINITY, mag = scene;
+    for (int c = 0; c < 4; ++c) {
+      if (ref[c] == EMPTY4) continue;
+      const double l = comp(nd[a], c), h = comp(nd[3 + a], c);
+      lo = fmin(lo, l);
+      hi = fmax(hi, h);
+      mag = fmax(mag, fmax(fabs(l), fabs(h)));
+    }
+    if (!(lo <= hi)) lo = hi = 0.0;  // no child (cannot happen in a built tree)
+    const double m = ldexp(fmax(mag, 1e-30), -18);
+    // origin: an FP32 value at or below lo - m
+    float p = (float)(lo - m);
+    if ((double)p > lo - m) p = nextafterf(p, -INFINITY);
+    // step: the smallest power of two with 255 steps covering [p, hi + m]
+    const double need = (hi + m - (double)p) / 255.0;
+    int e;
+    (void)frexp(fmax(need, 1e-37), &e);  // need <= 2^e
+    e = max(-126, min(127, e));
+    const double sc = ldexp(1.0, e);
+    P[a] = p;
+    E |= (uint32_t)(e + 127) << (8 * a);
+    for (int c = 0; c < 4; ++c) {
+      uint32_t ql = 0u, qh = 0u;
+      if (ref[c] != EMPTY4) {
+        const double l = comp(nd[a], c) - m, h = comp(nd[3 + a], c) + m;
+        int lq = (int)floor((l - (double)p) / sc), hq = (int)ceil((h - (double)p) / sc);
+        lq = max(0, min(255, lq));
+        hq = max(0, min(255, hq));
+        while (lq > 0 && (double)p + lq * sc > l) --lq;   // exact in FP64
+        while (hq < 255 && (double)p + hq * sc < h) ++hq;
+        ql = (uint32_t)lq;
+        qh = (uint32_t)hq;
+      }
+      qlo[a] |= ql << (8 * c);
+      qhi[a] |= qh << (8 * c);
+    }
+  }
+  float4* o = q4 + 4 * (size_t)i;
+  o[0] = make_float4(P[0], P[1], P[2], __uint_as_float(E));
+  o[1] = make_float4(__uint_as_float(qlo[0]), __uint_as_float(qlo[1]), __uint_as_float(qlo[2]),
+                     __uint_as_float(qhi[0]));
+  o[2] = make_float4(__uint_as_float(qhi[1]), __uint_as_float(qhi[2]), 0.0f, 0.0f);
+  o[3] = rf;
+}
+
 inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 
 // Top-down collapse of the binary tree (one launch per BVH4 level; the level
@@ -768,6 +844,16 @@ mrs_status collapse4(mrs_scene* s, hipStream_t st, int leaf_max, char* scratch, 
     return fail(MRS_ERR_OUT_OF_MEMORY, "mrs_build_bvh: BVH4 allocation failed");
   }
   k_compact4<<<cdiv(n - 1, 256), 256, 0, st>>>(sparse4, is4, idx, n - 1, s->d_nodes4);
+  MRS_TRY_HIP(hipGetLastError());
+  if (s->d_nodes4q) {
+    (void)hipFree(s->d_nodes4q);
+    s->d_nodes4q = nullptr;
+  }
+  if (hipMalloc(&s->d_nodes4q, sizeof(float4) * 4 * (size_t)count4) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(MRS_ERR_OUT_OF_MEMORY, "mrs_build_bvh: quantized BVH4 allocation failed");
+  }
+  k_quantize4<<<cdiv(count4, 256), 256, 0, st>>>(s->d_nodes4, (int)count4, s->d_nodes4q);
   MRS_TRY_HIP(hipGetLastError());
   s->count4 = count4;
   s->root4 = 0u;  // binary root 0 is the first BVH4 node

@@ -68,6 +68,7 @@ struct SceneView {  // passed by value to kernels
   uint32_t root;           // BVH4 reference of the root
   uint32_t nnodes;         // BVH4 nodes
   const float4* nodes;     // nnodes * 8 float4 (BVH4)
+  const float4* nodes_q;   // nnodes * 4 float4 (BVH4, quantized child boxes)
   const float4* leaf_tri;  // ntris*3 float4: (v0, prim bits) (e1, -) (e2, -) in leaf order
   const float4* prim_ng;   // ntris: unit geometric normal, w = bits(material | flags)
   const float4* prim_n;    // ntris*3: per-corner shading normals (smooth triangles)
@@ -125,6 +126,7 @@ struct mrs_scene {
   float4* d_leaf_tri = nullptr;
   float4* d_nodes = nullptr;   // binary LBVH: (ntris-1) * 4 float4
   float4* d_nodes4 = nullptr;  // BVH4: count4 * 8 float4
+  float4* d_nodes4q = nullptr; // the same nodes quantized: count4 * 4 float4
   uint32_t count4 = 0;
   uint32_t root4 = 0;
   int32_t leaf_max = mrs::LEAF4_MAX;  // triangles per BVH4 leaf the build may group

@@ -161,6 +161,18 @@ __device__ __forceinline__ bool slab(float lx, float ly, float lz, float hx, flo
   return tmin <= tmax && tmin <= tbest * 1.000244140625f;
 }
 
+// The same test on the six plane distances of a box.
+__device__ __forceinline__ bool slab_t(float t0x, float t1x, float t0y, float t1y, float t0z,
+                                       float t1z, float tbest, float& tnear) {
+  const float tmin = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), 0.0f));
+  const float tmax = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fmaxf(t0z, t1z)) * 1.0000005f;
+  tnear = tmin;
+  return tmin <= tmax && tmin <= tbest * 1.000244140625f;
+}
+
+// Byte c of w as a float (one v_cvt_f32_ubyte).
+__device__ __forceinline__ float ubyte(uint32_t w, int c) { return (float)((w >> (8 * c)) & 0xffu); }
+
 struct TraceState {
   float t;
   uint32_t prim;
@@ -179,6 +191,7 @@ __device__ __forceinline__ float4 ld4(const gfloat4* p) {
 }
 struct TraceView {
   const gfloat4* nodes;  // BVH4, 8 float4 per node
+  const gfloat4* nodes_q;  // the same nodes with quantized child boxes, 4 float4 per node
   const gfloat4* leaf_tri;
   uint32_t root;
   uint32_t nnodes;
@@ -285,6 +298,7 @@ __device__ __forceinline__ void cswap(float& ta, uint32_t& ra, float& tb, uint32
 __device__ __forceinline__ TraceView lane_view(const SceneView& sv) {
   TraceView t;
   t.nodes = (const gfloat4*)(uintptr_t)sv.nodes;
+  t.nodes_q = (const gfloat4*)(uintptr_t)sv.nodes_q;
   t.leaf_tri = (const gfloat4*)(uintptr_t)sv.leaf_tri;
   t.root = sv.root;
   t.nnodes = sv.nnodes;
@@ -318,7 +332,7 @@ enum TraceMode { CLOSEST = 0, ANY_HIT = 1, PER_RAY = 2 };
 // -> bool: true when the lane goes on with `next` for the same queue entry
 // (the next segment of a path), false to move to its next entry.  COUNT adds
 // node visits and triangle tests to wc (a separate instantiation).
-template <int MODE, bool COUNT, class IO>
+template <int MODE, bool COUNT, bool Q, class IO>
 __device__ void trace_stream(IO& io, uint32_t first, uint32_t stride, uint32_t n, Stack& st,
                              WorkCount& wc) {
   uint32_t qi = first;
@@ -355,22 +369,53 @@ __device__ void trace_stream(IO& io, uint32_t first, uint32_t stride, uint32_t n
         node = st.sp ? st.pop() : EMPTY4;
         continue;
       }
-      const gfloat4* nd = r.sc.nodes + 8 * node;
-      const float4 lx = ld4(nd), ly = ld4(nd + 1), lz = ld4(nd + 2);
-      const float4 hx = ld4(nd + 3), hy = ld4(nd + 4), hz = ld4(nd + 5);
-      const float4 rf = ld4(nd + 6);
       if (COUNT) {
         ++wc.visits;
         ++wc.ray_steps;
       }
       float t0, t1, t2, t3;
-      uint32_t r0 = __float_as_uint(rf.x), r1 = __float_as_uint(rf.y), r2 = __float_as_uint(rf.z),
-               r3 = __float_as_uint(rf.w);
+      uint32_t r0, r1, r2, r3;
+      bool h0, h1, h2, h3;
       // branch-free: every slab test is evaluated, misses become (INFINITY, EMPTY4)
-      const bool h0 = slab(lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, oi, inv, ts.t, t0) & (r0 != EMPTY4);
-      const bool h1 = slab(lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, oi, inv, ts.t, t1) & (r1 != EMPTY4);
-      const bool h2 = slab(lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, oi, inv, ts.t, t2) & (r2 != EMPTY4);
-      const bool h3 = slab(lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, oi, inv, ts.t, t3) & (r3 != EMPTY4);
+      if (Q) {  // quantized node: plane distance fma(q, 2^e inv, p inv - o inv)
+        const gfloat4* nd = r.sc.nodes_q + 4 * node;
+        const float4 hd = ld4(nd), qa = ld4(nd + 1), qb = ld4(nd + 2), rf = ld4(nd + 3);
+        const uint32_t ex = __float_as_uint(hd.w);
+        const float ax = __uint_as_float((ex & 0xffu) << 23) * inv.x;
+        const float ay = __uint_as_float(((ex >> 8) & 0xffu) << 23) * inv.y;
+        const float az = __uint_as_float(((ex >> 16) & 0xffu) << 23) * inv.z;
+        const float bx = fmaf(hd.x, inv.x, -oi.x), by = fmaf(hd.y, inv.y, -oi.y),
+                    bz = fmaf(hd.z, inv.z, -oi.z);
+        const uint32_t lxw = __float_as_uint(qa.x), lyw = __float_as_uint(qa.y),
+                       lzw = __float_as_uint(qa.z), hxw = __float_as_uint(qa.w),
+                       hyw = __float_as_uint(qb.x), hzw = __float_as_uint(qb.y);
+        r0 = __float_as_uint(rf.x);
+        r1 = __float_as_uint(rf.y);
+        r2 = __float_as_uint(rf.z);
+        r3 = __float_as_uint(rf.w);
+#define MRS_QSLAB(c, tc)                                                                    \
+  slab_t(fmaf(ubyte(lxw, c), ax, bx), fmaf(ubyte(hxw, c), ax, bx), fmaf(ubyte(lyw, c), ay, by), \
+         fmaf(ubyte(hyw, c), ay, by), fmaf(ubyte(lzw, c), az, bz), fmaf(ubyte(hzw, c), az, bz), \
+         ts.t, tc)
+        h0 = MRS_QSLAB(0, t0) & (r0 != EMPTY4);
+        h1 = MRS_QSLAB(1, t1) & (r1 != EMPTY4);
+        h2 = MRS_QSLAB(2, t2) & (r2 != EMPTY4);
+        h3 = MRS_QSLAB(3, t3) & (r3 != EMPTY4);
+#undef MRS_QSLAB
+      } else {
+        const gfloat4* nd = r.sc.nodes + 8 * node;
+        const float4 lx = ld4(nd), ly = ld4(nd + 1), lz = ld4(nd + 2);
+        const float4 hx = ld4(nd + 3), hy = ld4(nd + 4), hz = ld4(nd + 5);
+        const float4 rf = ld4(nd + 6);
+        r0 = __float_as_uint(rf.x);
+        r1 = __float_as_uint(rf.y);
+        r2 = __float_as_uint(rf.z);
+        r3 = __float_as_uint(rf.w);
+        h0 = slab(lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, oi, inv, ts.t, t0) & (r0 != EMPTY4);
+        h1 = slab(lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, oi, inv, ts.t, t1) & (r1 != EMPTY4);
+        h2 = slab(lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, oi, inv, ts.t, t2) & (r2 != EMPTY4);
+        h3 = slab(lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, oi, inv, ts.t, t3) & (r3 != EMPTY4);
+      }
       t0 = h0 ? t0 : INFINITY;
       t1 = h1 ? t1 : INFINITY;
       t2 = h2 ? t2 : INFINITY;
@@ -615,20 +660,20 @@ struct ExtendIO {
 
 // Static schedule: lane sequences gtid, gtid + threads, ...  Dynamic: a wave
 // takes 64 consecutive entries per fetch from a device counter.
-template <int MODE, bool COUNT, class IO>
+template <int MODE, bool COUNT, bool Q, class IO>
 __device__ __forceinline__ void trace_queue(IO& io, uint32_t n, int dyn, uint32_t* fetch,
                                             Stack& st, WorkCount& wc) {
   if (!dyn) {
-    trace_stream<MODE, COUNT>(io, blockIdx.x * TB + threadIdx.x, gridDim.x * TB, n, st, wc);
+    trace_stream<MODE, COUNT, Q>(io, blockIdx.x * TB + threadIdx.x, gridDim.x * TB, n, st, wc);
     return;
   }
   WaveQueue wq(fetch, true);
   for (; wq.base < n; wq.next())
-    trace_stream<MODE, COUNT>(io, wq.base + __lane_id(), 64u, min(n, wq.base + 64u), st, wc);
+    trace_stream<MODE, COUNT, Q>(io, wq.base + __lane_id(), 64u, min(n, wq.base + 64u), st, wc);
 }
 
-template <bool COUNT>
-__global__ __launch_bounds__(TB) void k_extend(const DevJob* __restrict__ jobs, int b, int dyn,
+template <bool COUNT, bool Q>
+__global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(7))) void k_extend(const DevJob* __restrict__ jobs, int b, int dyn,
                                                const float4* __restrict__ rays,
                                                uint32_t* __restrict__ q,
                                                float4* __restrict__ hits,
@@ -640,7 +685,7 @@ __global__ __launch_bounds__(TB) void k_extend(const DevJob* __restrict__ jobs, 
   Stack st{(lds_u32*)stk + threadIdx.x, spill + gtid, gridDim.x * TB, 0, 0u, false};
   WorkCount wc;
   ExtendIO io{jobs, rays, hits};
-  trace_queue<CLOSEST, COUNT>(io, n, dyn, q + Q_FETCH_EXT + b, st, wc);
+  trace_queue<CLOSEST, COUNT, Q>(io, n, dyn, q + Q_FETCH_EXT + b, st, wc);
   if (st.spills) atomicAdd(stats + 3, (unsigned long long)st.spills);
   if (st.overflow) atomicAdd(stats + 5, 1ull);
   if (COUNT && wc.visits) atomicAdd(stats + 6, (unsigned long long)wc.visits);
@@ -967,8 +1012,8 @@ struct ShadowIO {
   }
 };
 
-template <bool COUNT>
-__global__ __launch_bounds__(TB) void k_shadow(const DevJob* __restrict__ jobs, int b, int dyn,
+template <bool COUNT, bool Q>
+__global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(7))) void k_shadow(const DevJob* __restrict__ jobs, int b, int dyn,
                                                const float4* __restrict__ shadow,
                                                uint32_t* __restrict__ q,
                                                float4* __restrict__ L_buf,
@@ -980,7 +1025,7 @@ __global__ __launch_bounds__(TB) void k_shadow(const DevJob* __restrict__ jobs, 
   Stack st{(lds_u32*)stk + threadIdx.x, spill + gtid, gridDim.x * TB, 0, 0u, false};
   WorkCount wc;
   ShadowIO io{jobs, shadow, L_buf};
-  trace_queue<ANY_HIT, COUNT>(io, n, dyn, q + Q_FETCH_SHD + b, st, wc);
+  trace_queue<ANY_HIT, COUNT, Q>(io, n, dyn, q + Q_FETCH_SHD + b, st, wc);
   if (st.spills) atomicAdd(stats + 3, (unsigned long long)st.spills);
   if (st.overflow) atomicAdd(stats + 5, 1ull);
   if (COUNT && wc.visits) atomicAdd(stats + 8, (unsigned long long)wc.visits);
@@ -1080,7 +1125,7 @@ struct PathIO {
   }
 };
 
-template <bool COUNT>
+template <bool COUNT, bool Q>
 __global__ __launch_bounds__(TB) void k_tail(const DevJob* __restrict__ jobs, int64_t g0, int b0,
                                              const float4* __restrict__ rays,
                                              const uint32_t* __restrict__ q,
@@ -1100,7 +1145,7 @@ __global__ __launch_bounds__(TB) void k_tail(const DevJob* __restrict__ jobs, in
   io.L_buf = L_buf;
   io.g0 = g0;
   io.b0 = b0;
-  trace_stream<PER_RAY, COUNT>(io, gtid, gridDim.x * TB, n, st, wc);
+  trace_stream<PER_RAY, COUNT, Q>(io, gtid, gridDim.x * TB, n, st, wc);
   if (io.nrays) {
     atomicAdd(stats + 1, (unsigned long long)io.nrays);
     atomicAdd(stats + 12, (unsigned long long)io.nrays);
@@ -1292,6 +1337,7 @@ struct DebugHitIO {
   }
 };
 
+template <bool Q>
 __global__ __launch_bounds__(TB) void k_debug_hit(SceneView sc, int32_t n,
                                                   const float* __restrict__ o,
                                                   const float* __restrict__ d,
@@ -1305,7 +1351,7 @@ __global__ __launch_bounds__(TB) void k_debug_hit(SceneView sc, int32_t n,
   Stack st{(lds_u32*)stk + threadIdx.x, spill + gtid, gridDim.x * TB, 0, 0u, false};
   WorkCount wc;
   DebugHitIO io{sc, o, d, skip, t_out, prim_out, b_out};
-  trace_stream<CLOSEST, false>(io, gtid, gridDim.x * TB, (uint32_t)n, st, wc);
+  trace_stream<CLOSEST, false, Q>(io, gtid, gridDim.x * TB, (uint32_t)n, st, wc);
 }
 
 __global__ __launch_bounds__(256) void k_debug_philox(int32_t n, const uint32_t* __restrict__ ctr,
@@ -1402,7 +1448,7 @@ hipStream_t g_sub[MAX_SUB] = {};
 int g_nsub = 0;
 unsigned long long* g_stats = nullptr;  // device counters shared by every stream
 // defaults: the fastest hybrid 720p frame measured with the clustered BVH
-mrs_tuning g_tune = {1 << 23, 8192, 0, 3, 3, 3, MRS_BVH_PLOC, 128, 1};
+mrs_tuning g_tune = {1 << 23, 8192, 0, 3, 3, 3, MRS_BVH_PLOC, 128, 1, 0};
 std::atomic<int> g_conv_small{128};  // g_tune.conv_small_tiles, read without the lock
 std::atomic<bool> g_count_work{false};
 
@@ -1582,6 +1628,7 @@ mrs_status begin_batch(Workspace& ws, const mrs_tuning& tu, const DevJob* d_jobs
   // wavefront bounces 0 .. nwave-1; the path tail takes bounces nwave .. max_depth
   const int nwave = std::min(tu.tail_bounce, max_depth + 1);
   const int dyn = tu.schedule;
+  const bool qn = tu.bvh_quantized != 0;
   const bool count = g_count_work.load();
   unsigned long long* stats = ws.stats;
   const size_t spill_k = (size_t)P.blocks_k * TB * (MAX_STACK4 - LDS_STACK);
@@ -1623,12 +1670,9 @@ mrs_status begin_batch(Workspace& ws, const mrs_tuning& tu, const DevJob* d_jobs
       for (int k = 0; k < used; ++k) {
         Sub& u = sub[k];
         prof_begin(KID_EXTEND, u.s);
-        if (count)
-          k_extend<true><<<u.gb, TB, 0, u.s>>>(d_jobs, b, dyn, u.rays[b & 1], u.q, u.hits, u.spill,
-                                                stats);
-        else
-          k_extend<false><<<u.gb, TB, 0, u.s>>>(d_jobs, b, dyn, u.rays[b & 1], u.q, u.hits,
-                                                 u.spill, stats);
+        auto ext = count ? (qn ? k_extend<true, true> : k_extend<true, false>)
+                         : (qn ? k_extend<false, true> : k_extend<false, false>);
+        ext<<<u.gb, TB, 0, u.s>>>(d_jobs, b, dyn, u.rays[b & 1], u.q, u.hits, u.spill, stats);
         prof_end(KID_EXTEND, u.s);
       }
       for (int k = 0; k < used; ++k) {
@@ -1648,12 +1692,9 @@ mrs_status begin_batch(Workspace& ws, const mrs_tuning& tu, const DevJob* d_jobs
         for (int k = 0; k < used; ++k) {
           Sub& u = sub[k];
           prof_begin(KID_SHADOW, u.s);
-          if (count)
-            k_shadow<true><<<u.gb, TB, 0, u.s>>>(d_jobs, b, dyn, u.shadow, u.q, u.L, u.spill,
-                                                  stats);
-          else
-            k_shadow<false><<<u.gb, TB, 0, u.s>>>(d_jobs, b, dyn, u.shadow, u.q, u.L, u.spill,
-                                                   stats);
+          auto shd = count ? (qn ? k_shadow<true, true> : k_shadow<true, false>)
+                           : (qn ? k_shadow<false, true> : k_shadow<false, false>);
+          shd<<<u.gb, TB, 0, u.s>>>(d_jobs, b, dyn, u.shadow, u.q, u.L, u.spill, stats);
           prof_end(KID_SHADOW, u.s);
         }
       }
@@ -1662,12 +1703,10 @@ mrs_status begin_batch(Workspace& ws, const mrs_tuning& tu, const DevJob* d_jobs
       for (int k = 0; k < used; ++k) {
         Sub& u = sub[k];
         prof_begin(KID_TAIL, u.s);
-        if (count)
-          k_tail<true><<<u.gb, TB, 0, u.s>>>(d_jobs, u.lo, nwave, u.rays[nwave & 1], u.q, u.beta,
-                                              u.L, u.spill, stats);
-        else
-          k_tail<false><<<u.gb, TB, 0, u.s>>>(d_jobs, u.lo, nwave, u.rays[nwave & 1], u.q,
-                                               u.beta, u.L, u.spill, stats);
+        auto tail = count ? (qn ? k_tail<true, true> : k_tail<true, false>)
+                          : (qn ? k_tail<false, true> : k_tail<false, false>);
+        tail<<<u.gb, TB, 0, u.s>>>(d_jobs, u.lo, nwave, u.rays[nwave & 1], u.q, u.beta, u.L,
+                                   u.spill, stats);
         prof_end(KID_TAIL, u.s);
       }
     }
@@ -2027,7 +2066,10 @@ mrs_status debug_closest_hit(const mrs_scene* s, int32_t n, const float* o, cons
   Workspace& ws = *stream_workspace(st);
   mrs_status rc = ws_ensure(ws, 1, (int)(blocks * TB), 0);
   if (rc != MRS_OK) return rc;
-  k_debug_hit<<<blocks, TB, 0, st>>>(s->view, n, o, d, skip, t, prim, b, ws.spill);
+  if (tuning_snapshot().bvh_quantized)
+    k_debug_hit<true><<<blocks, TB, 0, st>>>(s->view, n, o, d, skip, t, prim, b, ws.spill);
+  else
+    k_debug_hit<false><<<blocks, TB, 0, st>>>(s->view, n, o, d, skip, t, prim, b, ws.spill);
   MRS_TRY_HIP(hipGetLastError());
   return MRS_OK;
 }
@@ -2077,6 +2119,8 @@ mrs_status set_tuning(const mrs_tuning* t) {
     return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_set_tuning: conv_small_tiles must be in [0, 2^30]");
   if (t->queue_sort != 0 && t->queue_sort != 1)
     return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_set_tuning: queue_sort must be 0 or 1");
+  if (t->bvh_quantized != 0 && t->bvh_quantized != 1)
+    return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_set_tuning: bvh_quantized must be 0 or 1");
   std::lock_guard<std::mutex> lk(g_mu);
   g_tune = *t;
   g_conv_small = t->conv_small_tiles;

@@ -173,7 +173,7 @@ def profile_read():
 
 
 TUNING_KEYS = ("chunk_paths", "trace_blocks", "schedule", "bvh_leaf_max", "streams", "tail_bounce",
-               "bvh_builder", "conv_small_tiles", "queue_sort")
+               "bvh_builder", "conv_small_tiles", "queue_sort", "bvh_quantized")
 BVH_BUILDERS = {"lbvh": 0, "ploc": 1}
 
 
@@ -185,7 +185,7 @@ def get_tuning():
 
 def set_tuning(chunk_paths=None, trace_blocks=None, schedule=None, bvh_leaf_max=None,
                streams=None, tail_bounce=None, bvh_builder=None, conv_small_tiles=None,
-               queue_sort=None):
+               queue_sort=None, bvh_quantized=None):
     """bvh_builder: 0 / "lbvh" (Karras) or 1 / "ploc" (clustering, the default);
     conv_small_tiles: the network's 3x3 convs with fewer 16x16 output tiles than
     this run on the small-tile plan (0: never)."""
@@ -195,7 +195,7 @@ def set_tuning(chunk_paths=None, trace_blocks=None, schedule=None, bvh_leaf_max=
     new = dict(chunk_paths=chunk_paths, trace_blocks=trace_blocks, schedule=schedule,
                bvh_leaf_max=bvh_leaf_max, streams=streams, tail_bounce=tail_bounce,
                bvh_builder=bvh_builder, conv_small_tiles=conv_small_tiles,
-               queue_sort=queue_sort)
+               queue_sort=queue_sort, bvh_quantized=bvh_quantized)
     t = L.Tuning()
     for k in TUNING_KEYS:
         setattr(t, k, int(new[k] if new[k] is not None else cur[k]))

@@ -448,24 +448,46 @@ def test_window_is_crop_and_chunking_invariant(mrs, torch_cuda):
     assert torch_cuda.equal(again, full)  # deterministic run to run
 
 
-def test_queue_order_does_not_change_the_image(mrs, torch_cuda):
+def test_queue_order_and_node_format_do_not_change_the_image(mrs, torch_cuda):
     """Ordering each block's appended rays by direction octant and its shadow rays by
-    light (queue_sort) changes which rays share a wave, not any result: the full HRLS
-    render of the bench scene, with features and render layers, is bitwise the same."""
+    light (queue_sort) changes which rays share a wave, and the quantized BVH4 nodes
+    (bvh_quantized) which boxes a ray visits, not any result: the full HRLS render of
+    the bench scene, with features and render layers, is bitwise the same."""
     gs = mrs.GpuScene(S.procedural(7))
     old = mrs.get_tuning()
     outs = []
     try:
-        for qs in (0, 1):
-            mrs.set_tuning(queue_sort=qs)
+        for qs, qn in ((0, 0), (1, 0), (0, 1), (1, 1)):
+            mrs.set_tuning(queue_sort=qs, bvh_quantized=qn)
             lay = torch_cuda.empty(720, 1280, 9, device="cuda")
             rgb, aux = mrs.render(gs, 1280, 720, 4, 8, 14, out_layers=lay)
             torch_cuda.cuda.synchronize()
             outs.append((rgb, aux, lay))
     finally:
         mrs.set_tuning(**old)
-    for a, b in zip(*outs):
-        assert torch_cuda.equal(a, b)
+    for other in outs[1:]:
+        for a, b in zip(outs[0], other):
+            assert torch_cuda.equal(a, b)
+
+
+@pytest.mark.parametrize("seed,n", [(2, 40), (3, 1500), (4, 20000)])
+def test_quantized_nodes_closest_hit_vs_oracle_brute_force(mrs, oracle_tracer, seed, n):
+    """Closest hits through the quantized nodes equal the FP32-node traversal's
+    bitwise and the oracle's brute force (same primitive)."""
+    scene = S.random_soup(seed, n)
+    gs = mrs.GpuScene(scene)
+    o, d = S.random_rays(seed + 100, 3000)
+    old = mrs.get_tuning()
+    try:
+        mrs.set_tuning(bvh_quantized=0)
+        t0, p0, b0 = gs.closest_hit(o, d)
+        mrs.set_tuning(bvh_quantized=1)
+        t1, p1, b1 = gs.closest_hit(o, d)
+    finally:
+        mrs.set_tuning(**old)
+    assert np.array_equal(p0, p1) and np.array_equal(t0, t1) and np.array_equal(b0, b1)
+    _, p_o, _ = oracle_tracer.OracleScene(scene).closest_hit(o, d, use_bvh=False)
+    assert (p1 == p_o).mean() >= 0.999
 
 
 def test_sub_chunks_beyond_2_24_paths(mrs, torch_cuda):
