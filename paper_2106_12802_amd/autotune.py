@@ -6,8 +6,8 @@ choice in a JSON file keyed by device and workload so that later runs apply it
 without measuring.  The search is a grid over the primary launch shape
 (resident paths x traversal grid x queue schedule) followed by one pass over
 each secondary knob with the rest held at the best so far: sub-chunk streams,
-the first bounce traced path by path, the ordering of appended rays, and the
-network conv tile plan.
+the first bounce traced path by path, the ordering of appended rays, the BVH
+node format, and the network conv tile plan.
 """
 from __future__ import annotations
 
@@ -21,9 +21,10 @@ CHUNKS = (1 << 21, 1 << 22, 1 << 23, 1 << 24, 1 << 25)
 BLOCKS = (1024, 2048, 4096, 8192)
 SCHEDULES = (0, 1)
 SECONDARY = (("streams", (1, 2, 3, 4)), ("tail_bounce", (2, 3, 4, 5)),
-             ("queue_sort", (0, 1)), ("conv_small_tiles", (0, 64, 128, 256)))
+             ("queue_sort", (0, 1)), ("bvh_quantized", (0, 1)),
+             ("conv_small_tiles", (0, 64, 128, 256)))
 KEYS = ("chunk_paths", "trace_blocks", "schedule", "streams", "tail_bounce", "queue_sort",
-        "conv_small_tiles")
+        "bvh_quantized", "conv_small_tiles")
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "mrs_autotune.json")
 
 
