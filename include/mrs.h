@@ -560,8 +560,10 @@ mrs_status mrs_debug_net_activation(const mrs_net* net, int32_t which, float* ou
  * with fewer than 64 output channels (80 / 64 input channels: the
  * reconstruction convs); [6] / [7] the direct implicit-GEMM conv (64 / 16
  * output channels per block: the 1x1 fuse conv and shapes the LDS kernels do
- * not take).  reset != 0 clears the counts after reading them. */
-#define MRS_NUM_CONV_KINDS 8
+ * not take); [8] / [9] the data-gradient convs of training on the LDS conv
+ * (16x8 / 16x16 tiles; the others run a direct implicit GEMM, not counted).
+ * reset != 0 clears the counts after reading them. */
+#define MRS_NUM_CONV_KINDS 10
 mrs_status mrs_debug_conv_launches(int64_t out[MRS_NUM_CONV_KINDS], int32_t reset);
 
 /* Philox4x32-10 on the device: out_dev[4i..4i+3] = philox(ctr_dev[4i..4i+3],

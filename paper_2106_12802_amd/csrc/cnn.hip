@@ -271,8 +271,49 @@ __device__ __forceinline__ void conv_epilogue(const ConvArgs& p, const f32x4 (&a
 // per k row.
 constexpr int C3_W = 16;  // tile width: one 16-pixel MFMA row tile
 
-template <int CINP, int NT, int TH>
-__global__ __launch_bounds__(32 * TH) void k_conv3_lds(ConvArgs p, int cout_p, int nsplit) {
+// Epilogue of a data-gradient conv with a plain backward (EPI_PLAIN of
+// k_dgrad): y = scale acc (+ add1 + add2), zero where the ReLU mask is not
+// positive, stored FP32 and/or BF16 (times out_h_scale).  Loads first, then
+// stores, as in conv_epilogue.
+__device__ __forceinline__ bool pos_bf(uint16_t h) { return h != 0 && !(h & 0x8000u); }
+
+template <int NT>
+__device__ __forceinline__ void dgrad_epilogue_plain(const BwdEpi& e, int cout,
+                                                     const f32x4 (&acc)[2][NT],
+                                                     const int64_t (&m)[2][4], int n0, int li) {
+  float y[2][NT][4];
+  bool keep[2][NT][4];
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int j = 0; j < NT; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int n = n0 + j * 16 + li;
+        keep[r][j][v] = m[r][v] >= 0 && n < cout;
+        const size_t idx = keep[r][j][v] ? (size_t)m[r][v] * e.stride + n : 0;
+        float t = acc[r][j][v] * e.scale;
+        if (e.add1 && keep[r][j][v]) t += e.add1[idx];
+        if (e.add2 && keep[r][j][v]) t += e.add2[idx];
+        if (e.mask && keep[r][j][v] && !pos_bf(e.mask[idx])) t = 0.0f;
+        y[r][j][v] = t;
+      }
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int j = 0; j < NT; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        if (!keep[r][j][v]) continue;
+        const size_t idx = (size_t)m[r][v] * e.stride + n0 + j * 16 + li;
+        if (e.out_f) e.out_f[idx] = y[r][j][v];
+        if (e.out_h) e.out_h[idx] = f2bf(y[r][j][v] * e.out_h_scale);
+      }
+}
+
+template <int CINP, int NT, int TH, bool DG = false>
+__global__ __launch_bounds__(32 * TH) void k_conv3_lds(ConvArgs p, int cout_p, int nsplit,
+                                                       BwdEpi be) {
   constexpr int THREADS = 32 * TH;  // TH / 2 waves, two tile rows each
   constexpr int TILE = (TH + 2) * (C3_W + 2);
   constexpr int PITCH = CINP + 8;
@@ -373,7 +414,10 @@ __global__ __launch_bounds__(32 * TH) void k_conv3_lds(ConvArgs p, int cout_p, i
         const int y = y0 + 2 * wave + r, x = x0 + kq * 4 + v;
         m[r][v] = (y < p.H && x < p.W) ? ((int64_t)b * p.H + y) * p.W + x : -1;
       }
-    conv_epilogue<NT>(p, acc, m, n0, li);
+    if (DG)
+      dgrad_epilogue_plain<NT>(be, p.cout, acc, m, n0, li);
+    else
+      conv_epilogue<NT>(p, acc, m, n0, li);
   }
 }
 
@@ -381,14 +425,19 @@ __global__ __launch_bounds__(32 * TH) void k_conv3_lds(ConvArgs p, int cout_p, i
 // or (CINP = 64) a multiple of it taken in chunks; packed K = 9 cin_p rounded up
 // to 32; cout_p a multiple of nsplit channel groups of 16 NT.  The output
 // channels are split over nsplit blocks per tile.
-template <int CINP, int NT, int TH>
-bool try_conv3_lds(const ConvArgs& a, int cout_p, int nsplit, hipStream_t st) {
+template <int CINP, int NT, int TH, bool DG = false>
+bool try_conv3_lds(const ConvArgs& a, int cout_p, int nsplit, hipStream_t st,
+                   const BwdEpi* be = nullptr) {
   const bool chunked = CINP == 64 && a.cin_p > CINP && a.cin_p % CINP == 0;
   if ((a.cin_p != CINP && !chunked) || a.kp != (9 * a.cin_p + 31) / 32 * 32 ||
       cout_p % (16 * NT * nsplit))
     return false;
-  k_conv3_lds<CINP, NT, TH><<<dim3((a.W + C3_W - 1) / C3_W, (a.H + TH - 1) / TH, a.B * nsplit),
-                              32 * TH, 0, st>>>(a, cout_p, nsplit);
+  BwdEpi e;
+  if (be) e = *be;
+  else std::memset(&e, 0, sizeof e);
+  k_conv3_lds<CINP, NT, TH, DG><<<dim3((a.W + C3_W - 1) / C3_W, (a.H + TH - 1) / TH,
+                                       a.B * nsplit),
+                                  32 * TH, 0, st>>>(a, cout_p, nsplit, e);
   return true;
 }
 
@@ -417,8 +466,6 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs p) {
 // Data gradient of a conv: the same implicit GEMM over dY with the packed
 // transposed, flipped weights; the epilogue applies the backward of what
 // surrounds the conv (ReLU masks, residual sums, the (un)shuffle views).
-__device__ __forceinline__ bool pos_bf(uint16_t h) { return h != 0 && !(h & 0x8000u); }
-
 template <int NT>
 __global__ __launch_bounds__(256) void k_dgrad(ConvArgs p, BwdEpi e) {
   const int lane = threadIdx.x & 63;
@@ -644,6 +691,11 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
   f32x4 acc[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // the first column block also sums dY over its pixels: the bias gradient
+  // (thread t: channel t / 4, pixels 8 (t % 4) .. 8 (t % 4) + 7 of each step)
+  const bool bias_blk = blockIdx.x == 0 && a.bpart;
+  const int bn = t >> 2, bq = t & 3;
+  float bsum = 0.0f;
   for (int pk = p_begin; pk < p_end; pk += 32) {
     for (int ci = t; ci < 32 * (NN / 8); ci += 256) {
       const int pix = ci / (NN / 8), cc = ci % (NN / 8);
@@ -671,6 +723,11 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
       for (int e = 0; e < 8; ++e) sX[(8 * cc + e) * WG_LD + pix] = h[e];
     }
     __syncthreads();
+    if (bias_blk && bn < NN) {
+      const bf16x8 yv = ld8(sY + bn * WG_LD + 8 * bq);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) bsum += (float)yv[e];
+    }
     const bf16x8 A = ld8(sY + (wn * 16 + li) * WG_LD + 8 * kq);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -678,6 +735,11 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
       acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, Bv, acc[j], 0, 0, 0);
     }
     __syncthreads();
+  }
+  if (bias_blk) {  // the 4 threads of a channel are adjacent lanes of one wave
+    bsum += __shfl_xor(bsum, 1);
+    bsum += __shfl_xor(bsum, 2);
+    if (bq == 0 && bn < NN && n0 + bn < a.cout) a.bpart[(size_t)blockIdx.z * a.cout + n0 + bn] = bsum;
   }
   float* out = a.part + (size_t)blockIdx.z * a.cout_p * x.kp;
 #pragma unroll
@@ -692,19 +754,19 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
   }
 }
 
-// Bias gradient partials: bpart[s][n] = sum over the pixels of split s of dY[p][n].
-__global__ __launch_bounds__(256) void k_bias_partial(const uint16_t* __restrict__ dy,
-                                                      int dy_stride, int cout, int npix, int chunk,
-                                                      float* __restrict__ bpart) {
-  const int n = threadIdx.x;
-  if (n >= cout) return;
-  const int p0 = blockIdx.x * chunk, p1 = min(npix, p0 + chunk);
-  float s = 0.0f;
-  for (int p = p0; p < p1; ++p) {
-    const uint32_t u = (uint32_t)dy[(size_t)p * dy_stride + n] << 16;
-    s += __uint_as_float(u);
+// Sum of v[sp * stride] over the splits: eight independent partial sums
+// (split sp into sum sp % 8), so that eight loads are in flight, then added in a
+// fixed order.
+__device__ __forceinline__ float sum_splits(const float* __restrict__ v, size_t stride,
+                                            int splits) {
+  float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  int sp = 0;
+  for (; sp + 8 <= splits; sp += 8) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s[k] += v[(size_t)(sp + k) * stride];
   }
-  bpart[(size_t)blockIdx.x * cout + n] = s;
+  for (int k = 0; sp < splits; ++sp, ++k) s[k] += v[(size_t)sp * stride];
+  return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
 }
 
 // Sum the split partials in order and scatter into the master gradient layout
@@ -719,14 +781,10 @@ __global__ __launch_bounds__(256) void k_grad_reduce(const float* __restrict__ p
     const int kx = (int)(i % ksz), ky = (int)((i / ksz) % ksz);
     const int c = (int)((i / (ksz * ksz)) % cin), n = (int)(i / ((int64_t)ksz * ksz * cin));
     const int col = (ky * ksz + kx) * cin_p + c;
-    float s = 0.0f;
-    for (int sp = 0; sp < splits; ++sp) s += part[((size_t)sp * cout_p + n) * kp + col];
-    g[i] = s;
+    g[i] = sum_splits(part + (size_t)n * kp + col, (size_t)cout_p * kp, splits);
   } else if (i < nw + cout) {
     const int n = (int)(i - nw);
-    float s = 0.0f;
-    for (int sp = 0; sp < splits; ++sp) s += bpart[(size_t)sp * cout + n];
-    g[i] = s;
+    g[i] = sum_splits(bpart + n, (size_t)cout, splits);
   }
 }
 
@@ -824,7 +882,21 @@ namespace {
 inline unsigned cdiv64(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 }  // namespace
 
+namespace {
+std::atomic<int64_t> g_conv_launches[MRS_NUM_CONV_KINDS];
+inline void count_conv(int kind) { g_conv_launches[kind].fetch_add(1, std::memory_order_relaxed); }
+}  // namespace
+
 void launch_dgrad(const ConvArgs& a, const BwdEpi& e, int cout_p, hipStream_t st) {
+  // 3x3 data gradients with a plain backward on the LDS conv (the same tile
+  // plans as the forward convs)
+  if (e.mode == EPI_PLAIN && a.taps == 9 && a.mode == VIEW_PLAIN && a.ca >= a.cin_p &&
+      cout_p >= 64 && a.cin_p % 64 == 0) {
+    const int64_t tiles = (int64_t)((a.W + 15) / 16) * ((a.H + 15) / 16) * a.B;
+    if (tiles < conv_small_tiles() && try_conv3_lds<64, 2, 8, true>(a, cout_p, cout_p / 32, st, &e))
+      return count_conv(8);
+    if (try_conv3_lds<64, 4, 16, true>(a, cout_p, 1, st, &e)) return count_conv(9);
+  }
   const int64_t M = (int64_t)a.B * a.H * a.W;
   const unsigned gx = cdiv64(M, 128);
   if (cout_p >= 64) {
@@ -840,11 +912,6 @@ void launch_wgrad(const WgradArgs& a, int splits, hipStream_t st) {
   } else {
     k_wgrad<1, 4><<<dim3(cdiv64(a.x.kp, 256), a.cout_p / 16, splits), 256, 0, st>>>(a);
   }
-}
-
-void launch_bias_partial(const uint16_t* dy, int dy_stride, int cout, int npix, int chunk,
-                         int splits, float* bpart, hipStream_t st) {
-  k_bias_partial<<<splits, 256, 0, st>>>(dy, dy_stride, cout, npix, chunk, bpart);
 }
 
 void launch_grad_reduce(const float* part, const float* bpart, int splits, const NetLayer& L,
@@ -887,10 +954,6 @@ void launch_adam(float* w, const float* g, float* m, float* v, int64_t n, float 
 // changes speed only.  Measured: the 720p LR trunk (240 tiles) is 18% faster
 // on the large tiles, the x8 network on a 1024 x 1024 image (64 tiles) 19%
 // faster on the small ones.
-namespace {
-std::atomic<int64_t> g_conv_launches[MRS_NUM_CONV_KINDS];
-inline void count_conv(int kind) { g_conv_launches[kind].fetch_add(1, std::memory_order_relaxed); }
-}  // namespace
 
 void conv_launch_counts(int64_t* out, bool reset) {
   for (int i = 0; i < MRS_NUM_CONV_KINDS; ++i)

@@ -84,6 +84,8 @@ struct WgradArgs {
   int npix;
   int chunk;             // pixels per split (multiple of 32)
   float* part;           // [splits][cout_p][kp]
+  int cout;              // output channels with a bias
+  float* bpart;          // [splits][cout]: the bias gradient's partial sums
 };
 
 // How a backward pass gets its output gradient dL/dI_SR: from a loss of the
@@ -161,8 +163,6 @@ void launch_pack(const float* wm, const NetLayer& L, uint16_t* wp, hipStream_t s
 void launch_init(float* dst, const NetLayer& L, uint64_t seed, hipStream_t st);
 void launch_dgrad(const ConvArgs& a, const BwdEpi& e, int cout_p, hipStream_t st);
 void launch_wgrad(const WgradArgs& a, int splits, hipStream_t st);
-void launch_bias_partial(const uint16_t* dy, int dy_stride, int cout, int npix, int chunk,
-                         int splits, float* bpart, hipStream_t st);
 void launch_grad_reduce(const float* part, const float* bpart, int splits, const NetLayer& L,
                         float* g, hipStream_t st);
 void launch_pack_t(const float* wm, const NetLayer& L, uint16_t* wt, hipStream_t st);

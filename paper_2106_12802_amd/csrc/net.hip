@@ -368,8 +368,9 @@ void wgrad(mrs_net* net, const NetLayer& L, const ConvArgs& x, const uint16_t* d
   w.npix = x.B * x.H * x.W;
   const int splits = wgrad_splits(w.npix, w.chunk);
   w.part = net->d_wpart;
+  w.cout = L.cout;
+  w.bpart = net->d_bpart;
   launch_wgrad(w, splits, st);
-  launch_bias_partial(dy, dy_stride, L.cout, w.npix, w.chunk, splits, net->d_bpart, st);
   launch_grad_reduce(net->d_wpart, net->d_bpart, splits, L, net->d_grad + L.w_off, st);
 }
 

@@ -203,7 +203,7 @@ def set_tuning(chunk_paths=None, trace_blocks=None, schedule=None, bvh_leaf_max=
 
 
 CONV_KINDS = ("lds64_small", "lds64_large", "lds16", "lds8", "lds80_narrow", "lds64_narrow",
-              "direct64", "direct16")
+              "direct64", "direct16", "dgrad_lds_small", "dgrad_lds_large")
 
 
 def conv_launches(reset=False):
