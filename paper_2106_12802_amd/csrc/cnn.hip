@@ -70,38 +70,41 @@ __device__ __forceinline__ void unshuffle_slot(int q, int r, int dsf, int& I, in
   }
 }
 
-// 8 consecutive channels [c, c+8) of the conv input at pixel (b, y, x) through
-// the view (zero outside the image).
-__device__ __forceinline__ bf16x8 view_chunk(const ConvArgs& p, int b, int y, int x, int c) {
-  if (y < 0 || y >= p.H || x < 0 || x >= p.W) return zero8();
-  const uint16_t* ptr;
+// Address of channel c of the conv input at pixel (b, y, x) through the view
+// (nullptr outside the image); channels c .. c+7 are contiguous there when c is
+// a multiple of 8.
+__device__ __forceinline__ const uint16_t* view_ptr(const ConvArgs& p, int b, int y, int x,
+                                                    int c) {
+  if (y < 0 || y >= p.H || x < 0 || x >= p.W) return nullptr;
   switch (p.mode) {
     case VIEW_PLAIN:
-      ptr = p.a + ((size_t)(b * p.H + y) * p.W + x) * p.ca + c;
-      break;
+      return p.a + ((size_t)(b * p.H + y) * p.W + x) * p.ca + c;
     case VIEW_CONCAT_UNSHUFFLE:  // [a (LR, ca ch), unshuffle_r(b (HR, cb ch))]
       if (c < p.ca) {
-        ptr = p.a + ((size_t)(b * p.H + y) * p.W + x) * p.ca + c;
+        return p.a + ((size_t)(b * p.H + y) * p.W + x) * p.ca + c;
       } else {
         const int cc = c - p.ca;
         const int qq = cc / p.cb, ch = cc - qq * p.cb;
         int I, J;
         unshuffle_slot(qq, p.r, p.dsf, I, J);
         const int hy = y * p.r + I, hx = x * p.r + J;
-        ptr = p.b + ((size_t)(b * p.H * p.r + hy) * (p.W * p.r) + hx) * p.cb + ch;
+        return p.b + ((size_t)(b * p.H * p.r + hy) * (p.W * p.r) + hx) * p.cb + ch;
       }
-      break;
     default:  // VIEW_SHUFFLE_CONCAT: [shuffle_r(a (LR, ca = r^2 c0 ch)), b (HR, cb ch)]
       if (c < p.c0) {
         const int qq = (y % p.r) * p.r + (x % p.r);
-        ptr = p.a + ((size_t)(b * (p.H / p.r) + y / p.r) * (p.W / p.r) + x / p.r) * p.ca +
-              qq * p.c0 + c;
-      } else {
-        ptr = p.b + ((size_t)(b * p.H + y) * p.W + x) * p.cb + (c - p.c0);
+        return p.a + ((size_t)(b * (p.H / p.r) + y / p.r) * (p.W / p.r) + x / p.r) * p.ca +
+               qq * p.c0 + c;
       }
-      break;
+      return p.b + ((size_t)(b * p.H + y) * p.W + x) * p.cb + (c - p.c0);
   }
-  return ld8(ptr);
+}
+
+// 8 consecutive channels [c, c+8) of the conv input at pixel (b, y, x) through
+// the view (zero outside the image).
+__device__ __forceinline__ bf16x8 view_chunk(const ConvArgs& p, int b, int y, int x, int c) {
+  const uint16_t* ptr = view_ptr(p, b, y, x, c);
+  return ptr ? ld8(ptr) : zero8();
 }
 
 __device__ __forceinline__ bf16x8 load_chunk(const ConvArgs& p, int b, int y, int x, int tap,
@@ -170,17 +173,41 @@ __device__ __forceinline__ void conv_mainloop(const ConvArgs& p, int M, int m0, 
 // (-1: outside the image).  Every load (bias, residuals) is issued before the
 // first store: the output pointers may alias nothing, but the compiler cannot
 // know that, and interleaving would serialise one memory latency per element.
+// The epilogue's first inputs (bias and the first residual), which a kernel
+// may load before its main loop so that their latency overlaps the MFMAs.
 template <int NT>
-__device__ __forceinline__ void conv_epilogue(const ConvArgs& p, const f32x4 (&acc)[2][NT],
-                                              const int64_t (&m)[2][4], int n0, int li) {
+struct EpiIn {
   float bias[NT];
-  bool nv[NT];
+  float res[2][NT][4];
+};
+
+template <int NT>
+__device__ __forceinline__ void epi_load(const ConvArgs& p, const int64_t (&m)[2][4], int n0,
+                                         int li, EpiIn<NT>& in) {
 #pragma unroll
   for (int j = 0; j < NT; ++j) {
     const int n = n0 + j * 16 + li;
-    nv[j] = n < p.cout;
-    bias[j] = nv[j] ? p.bias[n] : 0.0f;
+    in.bias[j] = n < p.cout ? p.bias[n] : 0.0f;
   }
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int j = 0; j < NT; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int n = n0 + j * 16 + li;
+        in.res[r][j][v] = (p.res && m[r][v] >= 0 && n < p.cout)
+                              ? p.res[(size_t)m[r][v] * p.cout + n] : 0.0f;
+      }
+}
+
+template <int NT>
+__device__ __forceinline__ void conv_epilogue(const ConvArgs& p, const f32x4 (&acc)[2][NT],
+                                              const int64_t (&m)[2][4], int n0, int li,
+                                              const EpiIn<NT>& in) {
+  bool nv[NT];
+#pragma unroll
+  for (int j = 0; j < NT; ++j) nv[j] = n0 + j * 16 + li < p.cout;
   float y[2][NT][4];
 #pragma unroll
   for (int r = 0; r < 2; ++r)
@@ -188,25 +215,16 @@ __device__ __forceinline__ void conv_epilogue(const ConvArgs& p, const f32x4 (&a
     for (int j = 0; j < NT; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        float t = acc[r][j][v] + bias[j];
+        float t = acc[r][j][v] + in.bias[j];
         y[r][j][v] = p.relu ? fmaxf(t, 0.0f) : t;
       }
   if (p.res) {
-    float rv[2][NT][4];
 #pragma unroll
     for (int r = 0; r < 2; ++r)
 #pragma unroll
       for (int j = 0; j < NT; ++j)
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
-          rv[r][j][v] = (m[r][v] >= 0 && nv[j])
-                            ? p.res[(size_t)m[r][v] * p.cout + n0 + j * 16 + li] : 0.0f;
-#pragma unroll
-    for (int r = 0; r < 2; ++r)
-#pragma unroll
-      for (int j = 0; j < NT; ++j)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) y[r][j][v] = rv[r][j][v] + p.res_scale * y[r][j][v];
+        for (int v = 0; v < 4; ++v) y[r][j][v] = in.res[r][j][v] + p.res_scale * y[r][j][v];
   }
   if (p.res2) {
     float rv[2][NT][4];
@@ -417,7 +435,11 @@ __global__ __launch_bounds__(32 * TH) void k_conv3_lds(ConvArgs p, int cout_p, i
     if (DG)
       dgrad_epilogue_plain<NT>(be, p.cout, acc, m, n0, li);
     else
-      conv_epilogue<NT>(p, acc, m, n0, li);
+    {
+      EpiIn<NT> in;
+      epi_load<NT>(p, m, n0, li, in);
+      conv_epilogue<NT>(p, acc, m, n0, li, in);
+    }
   }
 }
 
@@ -460,7 +482,9 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs p) {
       const int mm = m0 + r * 16 + kq * 4 + v;
       m[r][v] = mm < M ? mm : -1;
     }
-  conv_epilogue<NT>(p, acc, m, n0, li);
+  EpiIn<NT> in;
+  epi_load<NT>(p, m, n0, li, in);
+  conv_epilogue<NT>(p, acc, m, n0, li, in);
 }
 
 // Data gradient of a conv: the same implicit GEMM over dY with the packed
@@ -619,21 +643,39 @@ __global__ __launch_bounds__(256) void k_prep_layers(int64_t nhr, int64_t nlr,
   }
 }
 
-// Packed BF16 weights of one layer: wp[n][k], k = tap * cin_p + c; zero padding
-// for c >= cin, tap >= taps, n >= cout.  Master layout [cout][cin][k][k].
-__global__ __launch_bounds__(256) void k_pack(const float* __restrict__ wm, int cout, int cin,
-                                              int ksz, int cin_p, int kp, int cout_p,
-                                              uint16_t* __restrict__ wp) {
+// BF16 weight packing of every layer in one launch (master layout
+// [cout][cin][k][k]).  Element i belongs to the last job whose begin is <= i.
+// t = 0: wp[n][tap cin_p + c] = W[n][c][tap], the forward convs' B operand.
+// t = 1: wt[c][tap' cinp_t + n] = W[n][c][taps - 1 - tap'], the data-gradient
+// conv (flipped taps, input and output channels swapped).  Padding is zero.
+__global__ __launch_bounds__(256) void k_pack_all(const float* __restrict__ wm,
+                                                  const PackJob* __restrict__ jobs, int njobs,
+                                                  int64_t total, uint16_t* __restrict__ packed,
+                                                  uint16_t* __restrict__ packed_t) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= (int64_t)cout_p * kp) return;
-  const int n = (int)(i / kp), k = (int)(i % kp);
-  const int tap = k / cin_p, c = k % cin_p;
-  float v = 0.0f;
-  if (n < cout && c < cin && tap < ksz * ksz) {
-    const int ky = tap / ksz, kx = tap % ksz;
-    v = wm[((size_t)(n * cin + c) * ksz + ky) * ksz + kx];
+  if (i >= total) return;
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].begin <= i) lo = mid;
+    else hi = mid - 1;
   }
-  wp[i] = f2bf(v);
+  const PackJob& J = jobs[lo];
+  const int64_t e = i - J.begin;
+  const int row = (int)(e / J.kp), k = (int)(e % J.kp);
+  const int tap = k / J.cinp, col = k % J.cinp;
+  const int taps = J.ksz * J.ksz;
+  const float* w = wm + J.w_off;
+  float v = 0.0f;
+  if (J.t == 0) {  // row = output channel n, col = input channel c
+    if (row < J.cout && col < J.cin && tap < taps)
+      v = w[((size_t)(row * J.cin + col) * taps) + tap];
+    packed[J.out_off + e] = f2bf(v);
+  } else {  // row = input channel c, col = output channel n, flipped tap
+    if (row < J.cin && col < J.cout && tap < taps)
+      v = w[((size_t)(col * J.cin + row) * taps) + (taps - 1 - tap)];
+    packed_t[J.out_off + e] = f2bf(v);
+  }
 }
 
 // He-uniform initialisation (fan-in), Philox4x32-10 with tag 2; biases 0.
@@ -650,108 +692,211 @@ __global__ __launch_bounds__(256) void k_init(float* __restrict__ dst, int64_t n
   }
 }
 
-// Packed BF16 weights of the data-gradient conv of one layer: wt[c][k'],
-// k' = tap' * cinp_t + n, holding W[n][c][8 - tap'] (W[n][c][0] for 1x1).
-__global__ __launch_bounds__(256) void k_pack_t(const float* __restrict__ wm, int cout, int cin,
-                                                int ksz, int cinp_t, int kp_t, int coutp_t,
-                                                uint16_t* __restrict__ wt) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= (int64_t)coutp_t * kp_t) return;
-  const int c = (int)(i / kp_t), k = (int)(i % kp_t);
-  const int tap = k / cinp_t, n = k % cinp_t;
-  float v = 0.0f;
-  const int taps = ksz * ksz;
-  if (c < cin && n < cout && tap < taps) {
-    const int ft = taps - 1 - tap;
-    const int ky = ft / ksz, kx = ft % ksz;
-    v = wm[((size_t)(n * cin + c) * ksz + ky) * ksz + kx];
+// Weight gradient on the matrix cores, split over pixels: part[s][n][col] = sum
+// over the pixels of split s of dY[p][n] X[p + off(tap)][c], col = tap cin_p + c
+// (the packed K layout).  The pixel is the MFMA's K index: lane (i, kq) of a
+// wave reads, for the pixels p0 + 8 kq + e (e < 8) of each 32-pixel step, RN
+// channels of dY and QX columns of X with one load each, and re-packs the
+// 16-bit halves into operands: dY operand c maps row i to channel n0 + RN i + c
+// (RN = 1: channel n0 + i), X operand d maps column i to col0 + QX i + d.  No LDS
+// staging and no barrier in the loop; the next step's loads are issued before
+// this step's MFMAs.  The 4 waves of a workgroup take consecutive quarters of
+// the split's pixels and their tiles are summed in LDS in wave order
+// (deterministic).  The first column block also sums dY, the bias gradient.
+// FAST: plain view and W % 8 == 0, so a lane's 8 pixels share one image row.
+template <int W>
+struct Dw {
+  uint32_t v[W];
+};
+
+template <int W>
+__device__ __forceinline__ Dw<W> ldw(const uint16_t* p) {
+  Dw<W> r;
+  if constexpr (W == 1) {
+    r.v[0] = *reinterpret_cast<const uint32_t*>(p);
+  } else if constexpr (W == 2) {
+    const uint2 u = *reinterpret_cast<const uint2*>(p);
+    r.v[0] = u.x;
+    r.v[1] = u.y;
+  } else {
+    const uint4 u = *reinterpret_cast<const uint4*>(p);
+    r.v[0] = u.x;
+    r.v[1] = u.y;
+    r.v[2] = u.z;
+    r.v[3] = u.w;
   }
-  wt[i] = f2bf(v);
+  return r;
 }
 
-// Weight gradient, split over pixels: part[s][n][col] = sum over the pixels of
-// split s of dY[p][n] * X[p + off(tap)][c], col = tap * cin_p + c (the packed K
-// layout).  Per 32-pixel step the dY and X tiles are staged in LDS transposed
-// (pixels contiguous) so each MFMA operand is one 16-byte LDS read.
-constexpr int WG_LD = 40;  // LDS row length (32 pixels + 8 pad) in BF16
+template <int W>
+__device__ __forceinline__ Dw<W> zdw() {
+  Dw<W> r;
+#pragma unroll
+  for (int k = 0; k < W; ++k) r.v[k] = 0u;
+  return r;
+}
 
-template <int WNN, int WNC>
+// The 16-bit half at bit `sh` (0 or 16) of word u of pixels 2k and 2k+1, packed
+// into one operand word (pixel 2k low).
+__device__ __forceinline__ uint32_t pair16(uint32_t lo, uint32_t hi, int sh) {
+  return ((lo >> sh) & 0xffffu) | ((hi >> sh) << 16);
+}
+
+template <int RN, int QX, bool FAST>
 __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
-  constexpr int NN = 16 * WNN, NC = 64 * WNC;
-  __shared__ __attribute__((aligned(16))) uint16_t sY[NN * WG_LD];
-  __shared__ __attribute__((aligned(16))) uint16_t sX[NC * WG_LD];
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int kq = lane >> 4, li = lane & 15;
-  const int wn = wave % WNN, wc = wave / WNN;
+  constexpr int NN = 16 * RN, NC = 16 * QX;
+  constexpr int YW = RN == 1 ? 1 : RN / 2, XW = QX / 2;  // dwords per pixel
+  __shared__ __attribute__((aligned(16))) float red[4][NN * NC];
+  __shared__ float bred[4][NN];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = lane & 15, kq = lane >> 4;
   const int col0 = blockIdx.x * NC, n0 = blockIdx.y * NN;
-  const int p_begin = blockIdx.z * a.chunk;
-  const int p_end = min(a.npix, p_begin + a.chunk);
   const ConvArgs& x = a.x;
-  const int cpt = x.cin_p >> 3;
-  f32x4 acc[4];
-#pragma unroll
-  for (int j = 0; j < 4; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  // the first column block also sums dY over its pixels: the bias gradient
-  // (thread t: channel t / 4, pixels 8 (t % 4) .. 8 (t % 4) + 7 of each step)
+  const int quarter = a.chunk >> 2;
+  const int pw0 = blockIdx.z * a.chunk + wave * quarter;
+  const int pw1 = min(a.npix, pw0 + quarter);
+  // this lane's X columns: QX channels cx.. of tap `tap` (one tap: cin_p % 8 == 0)
+  const int colx = col0 + QX * i;
+  const int tapx = colx / x.cin_p, cx = colx - tapx * x.cin_p;
+  const bool xon = colx < x.kp && tapx < x.taps;
+  const int ty = x.taps == 9 ? tapx / 3 - 1 : 0, tx = x.taps == 9 ? tapx % 3 - 1 : 0;
+  // this lane's dY channels (RN = 1: the word holding channel n0 + i)
+  const int ny = RN == 1 ? ((n0 + i) & ~1) : n0 + RN * i;
+  const bool yon = (RN == 1 ? n0 + i : ny) < a.dy_stride;
+  const int ysh = RN == 1 ? 16 * ((n0 + i) & 1) : 0;
   const bool bias_blk = blockIdx.x == 0 && a.bpart;
-  const int bn = t >> 2, bq = t & 3;
-  float bsum = 0.0f;
-  for (int pk = p_begin; pk < p_end; pk += 32) {
-    for (int ci = t; ci < 32 * (NN / 8); ci += 256) {
-      const int pix = ci / (NN / 8), cc = ci % (NN / 8);
-      const int pp = pk + pix, n = n0 + 8 * cc;
-      uint4 v = make_uint4(0u, 0u, 0u, 0u);
-      if (pp < p_end && n < a.dy_stride)
-        v = *reinterpret_cast<const uint4*>(a.dy + (size_t)pp * a.dy_stride + n);
-      const uint16_t* h = reinterpret_cast<const uint16_t*>(&v);
+
+  auto load_step = [&](int pk, Dw<YW>(&yd)[8], Dw<XW>(&xd)[8]) {
+    const int pp0 = pk + 8 * kq;
+    const uint16_t* yp = a.dy + (int64_t)pp0 * a.dy_stride + ny;
+    if constexpr (FAST) {
+      const bool gv = pp0 < pw1;  // W % 8 == 0: the 8 pixels are valid together
+      const int x0 = pp0 % x.W, y0 = (pp0 / x.W) % x.H;
+      const bool rowv = gv && xon && (unsigned)(y0 + ty) < (unsigned)x.H;
+      const uint16_t* xp = x.a + ((int64_t)pp0 + ty * x.W + tx) * x.ca + cx;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) sY[(8 * cc + e) * WG_LD + pix] = h[e];
-    }
-    for (int ci = t; ci < 32 * (NC / 8); ci += 256) {
-      const int pix = ci / (NC / 8), cc = ci % (NC / 8);
-      const int pp = pk + pix, col = col0 + 8 * cc;
-      bf16x8 v = zero8();
-      if (pp < p_end && col < x.kp) {
-        const int q = col >> 3;
-        const int tap = q / cpt, c = (q - tap * cpt) << 3;
-        const int px = pp % x.W, tt = pp / x.W, py = tt % x.H, pb = tt / x.H;
-        v = load_chunk(x, pb, py, px, tap, c);
+      for (int e = 0; e < 8; ++e) {
+        const bool xv = rowv && (unsigned)(x0 + e + tx) < (unsigned)x.W;
+        xd[e] = xv ? ldw<XW>(xp + (int64_t)e * x.ca) : zdw<XW>();
+        yd[e] = (gv && yon) ? ldw<YW>(yp + (int64_t)e * a.dy_stride) : zdw<YW>();
       }
-      const uint4 u = __builtin_bit_cast(uint4, v);
-      const uint16_t* h = reinterpret_cast<const uint16_t*>(&u);
+    } else {
+      int px = pp0 % x.W;
+      const int t = pp0 / x.W;
+      int py = t % x.H, pb = t / x.H;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) sX[(8 * cc + e) * WG_LD + pix] = h[e];
+      for (int e = 0; e < 8; ++e) {
+        const bool v = pp0 + e < pw1;
+        const uint16_t* q = (v && xon) ? view_ptr(x, pb, py + ty, px + tx, cx) : nullptr;
+        xd[e] = q ? ldw<XW>(q) : zdw<XW>();
+        yd[e] = (v && yon) ? ldw<YW>(yp + (int64_t)e * a.dy_stride) : zdw<YW>();
+        ++px;
+        const bool wrap = px == x.W;
+        px = wrap ? 0 : px;
+        py += wrap;
+        const bool wrap2 = py == x.H;
+        py = wrap2 ? 0 : py;
+        pb += wrap2;
+      }
     }
-    __syncthreads();
-    if (bias_blk && bn < NN) {
-      const bf16x8 yv = ld8(sY + bn * WG_LD + 8 * bq);
+  };
+
+  f32x4 acc[RN][QX];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) bsum += (float)yv[e];
-    }
-    const bf16x8 A = ld8(sY + (wn * 16 + li) * WG_LD + 8 * kq);
+  for (int c = 0; c < RN; ++c)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const bf16x8 Bv = ld8(sX + (wc * 64 + j * 16 + li) * WG_LD + 8 * kq);
-      acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, Bv, acc[j], 0, 0, 0);
+    for (int d = 0; d < QX; ++d) acc[c][d] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float bs[RN];
+#pragma unroll
+  for (int c = 0; c < RN; ++c) bs[c] = 0.0f;
+
+  Dw<YW> yd[8];
+  Dw<XW> xd[8];
+  if (pw0 < pw1) load_step(pw0, yd, xd);
+  for (int pk = pw0; pk < pw1; pk += 32) {
+    Dw<YW> yn[8];
+    Dw<XW> xn[8];
+    if (pk + 32 < pw1) load_step(pk + 32, yn, xn);
+    bf16x8 A[RN], Bv[QX];
+#pragma unroll
+    for (int c = 0; c < RN; ++c) {
+      const int u = RN == 1 ? 0 : c >> 1, sh = RN == 1 ? ysh : 16 * (c & 1);
+      uint4 w;
+      w.x = pair16(yd[0].v[u], yd[1].v[u], sh);
+      w.y = pair16(yd[2].v[u], yd[3].v[u], sh);
+      w.z = pair16(yd[4].v[u], yd[5].v[u], sh);
+      w.w = pair16(yd[6].v[u], yd[7].v[u], sh);
+      A[c] = __builtin_bit_cast(bf16x8, w);
+      if (bias_blk) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) bs[c] += __uint_as_float(((yd[e].v[u] >> sh) & 0xffffu) << 16);
+      }
     }
-    __syncthreads();
+#pragma unroll
+    for (int d = 0; d < QX; ++d) {
+      const int u = d >> 1, sh = 16 * (d & 1);
+      uint4 w;
+      w.x = pair16(xd[0].v[u], xd[1].v[u], sh);
+      w.y = pair16(xd[2].v[u], xd[3].v[u], sh);
+      w.z = pair16(xd[4].v[u], xd[5].v[u], sh);
+      w.w = pair16(xd[6].v[u], xd[7].v[u], sh);
+      Bv[d] = __builtin_bit_cast(bf16x8, w);
+    }
+#pragma unroll
+    for (int c = 0; c < RN; ++c)
+#pragma unroll
+      for (int d = 0; d < QX; ++d)
+        acc[c][d] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[c], Bv[d], acc[c][d], 0, 0, 0);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      yd[e] = yn[e];
+      xd[e] = xn[e];
+    }
   }
-  if (bias_blk) {  // the 4 threads of a channel are adjacent lanes of one wave
-    bsum += __shfl_xor(bsum, 1);
-    bsum += __shfl_xor(bsum, 2);
-    if (bq == 0 && bn < NN && n0 + bn < a.cout) a.bpart[(size_t)blockIdx.z * a.cout + n0 + bn] = bsum;
+  // accumulator (c, d) of lane (j, g): rows 4g + v (channel n0 + RN row + c),
+  // column j (col0 + QX j + d)
+  {
+    const int j = lane & 15, g = lane >> 4;
+    float* r = red[wave];
+#pragma unroll
+    for (int c = 0; c < RN; ++c)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        float* row = r + (RN * (4 * g + v) + c) * NC + QX * j;
+#pragma unroll
+        for (int d4 = 0; d4 < QX; d4 += 4)
+          *reinterpret_cast<float4*>(row + d4) =
+              make_float4(acc[c][d4][v], acc[c][d4 + 1][v], acc[c][d4 + 2][v], acc[c][d4 + 3][v]);
+      }
   }
-  float* out = a.part + (size_t)blockIdx.z * a.cout_p * x.kp;
+  if (bias_blk) {  // over kq (lanes 16 apart), then per wave into LDS
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int col = col0 + wc * 64 + j * 16 + li;
-    if (col >= x.kp) continue;
+    for (int c = 0; c < RN; ++c) {
+      bs[c] += __shfl_xor(bs[c], 16);
+      bs[c] += __shfl_xor(bs[c], 32);
+    }
+    if (kq == 0) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int n = n0 + wn * 16 + kq * 4 + v;
-      if (n < a.cout_p) out[(size_t)n * x.kp + col] = acc[j][v];
+      for (int c = 0; c < RN; ++c) bred[wave][RN == 1 ? i : RN * i + c] = bs[c];
     }
   }
+  __syncthreads();
+  const int t = threadIdx.x;
+  float* out = a.part + ((size_t)blockIdx.z * a.cout_p + n0) * x.kp + col0;
+  for (int f = t; f < NN * NC / 4; f += 256) {
+    const int nl = (4 * f) / NC, cl = (4 * f) % NC;
+    if (col0 + cl >= x.kp) continue;
+    const float4 r0 = reinterpret_cast<const float4*>(red[0])[f];
+    const float4 r1 = reinterpret_cast<const float4*>(red[1])[f];
+    const float4 r2 = reinterpret_cast<const float4*>(red[2])[f];
+    const float4 r3 = reinterpret_cast<const float4*>(red[3])[f];
+    *reinterpret_cast<float4*>(out + (size_t)nl * x.kp + cl) =
+        make_float4(((r0.x + r1.x) + r2.x) + r3.x, ((r0.y + r1.y) + r2.y) + r3.y,
+                    ((r0.z + r1.z) + r2.z) + r3.z, ((r0.w + r1.w) + r2.w) + r3.w);
+  }
+  if (bias_blk && t < NN && n0 + t < a.cout)
+    a.bpart[(size_t)blockIdx.z * a.cout + n0 + t] =
+        ((bred[0][t] + bred[1][t]) + bred[2][t]) + bred[3][t];
 }
 
 // Sum of v[sp * stride] over the splits: eight independent partial sums
@@ -770,21 +915,24 @@ __device__ __forceinline__ float sum_splits(const float* __restrict__ v, size_t 
 }
 
 // Sum the split partials in order and scatter into the master gradient layout
-// [cout][cin][k][k] followed by the bias.
+// [cout][cin][k][k] followed by the bias.  Threads walk the packed layout
+// [n][tap cin_p + c], so that the split partials are read coalesced.
 __global__ __launch_bounds__(256) void k_grad_reduce(const float* __restrict__ part,
                                                      const float* __restrict__ bpart, int splits,
                                                      int cout, int cin, int ksz, int cin_p, int kp,
                                                      int cout_p, float* __restrict__ g) {
-  const int64_t nw = (int64_t)cout * cin * ksz * ksz;
+  const int64_t np = (int64_t)cout * kp;
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < nw) {
-    const int kx = (int)(i % ksz), ky = (int)((i / ksz) % ksz);
-    const int c = (int)((i / (ksz * ksz)) % cin), n = (int)(i / ((int64_t)ksz * ksz * cin));
-    const int col = (ky * ksz + kx) * cin_p + c;
-    g[i] = sum_splits(part + (size_t)n * kp + col, (size_t)cout_p * kp, splits);
-  } else if (i < nw + cout) {
-    const int n = (int)(i - nw);
-    g[i] = sum_splits(bpart + n, (size_t)cout, splits);
+  if (i < np) {
+    const int n = (int)(i / kp), col = (int)(i - (int64_t)n * kp);
+    const int tap = col / cin_p, c = col - tap * cin_p;
+    if (c >= cin || tap >= ksz * ksz) return;
+    const int ky = tap / ksz, kx = tap - ky * ksz;
+    g[((size_t)(n * cin + c) * ksz + ky) * ksz + kx] =
+        sum_splits(part + i, (size_t)cout_p * kp, splits);
+  } else if (i < np + cout) {
+    const int n = (int)(i - np);
+    g[(size_t)cout * cin * ksz * ksz + n] = sum_splits(bpart + n, (size_t)cout, splits);
   }
 }
 
@@ -906,24 +1054,44 @@ void launch_dgrad(const ConvArgs& a, const BwdEpi& e, int cout_p, hipStream_t st
   }
 }
 
+// Weight-gradient tile per workgroup: 64 x 64 (RN 4, QX 4) for 64 or more
+// output channels, else 16 x 128 (RN 1, QX 8).
+namespace {
+inline int wgrad_nc(int cout_p) { return cout_p >= 64 ? 64 : 128; }
+inline int wgrad_nn(int cout_p) { return cout_p >= 64 ? 64 : 16; }
+}  // namespace
+
+int wgrad_splits(int64_t npix, int kp, int cout_p, int& chunk) {
+  // about 1024 workgroups over the tiles, at most 128 splits, and at least 4
+  // steps of 32 pixels per wave (512 pixels per workgroup)
+  const int64_t tiles = (int64_t)cdiv64(kp, wgrad_nc(cout_p)) * (cout_p / wgrad_nn(cout_p));
+  const int64_t s = std::max<int64_t>(1, std::min<int64_t>(128, (1024 + tiles - 1) / tiles));
+  const int64_t per = std::max<int64_t>(512, (npix + s - 1) / s);
+  chunk = (int)((per + 127) / 128 * 128);
+  return (int)std::max<int64_t>(1, (npix + chunk - 1) / chunk);
+}
+
 void launch_wgrad(const WgradArgs& a, int splits, hipStream_t st) {
+  const bool fast = a.x.mode == VIEW_PLAIN && a.x.W % 8 == 0;
+  const dim3 grid(cdiv64(a.x.kp, wgrad_nc(a.cout_p)), a.cout_p / wgrad_nn(a.cout_p), splits);
   if (a.cout_p >= 64) {
-    k_wgrad<4, 1><<<dim3(cdiv64(a.x.kp, 64), a.cout_p / 64, splits), 256, 0, st>>>(a);
+    if (fast)
+      k_wgrad<4, 4, true><<<grid, 256, 0, st>>>(a);
+    else
+      k_wgrad<4, 4, false><<<grid, 256, 0, st>>>(a);
   } else {
-    k_wgrad<1, 4><<<dim3(cdiv64(a.x.kp, 256), a.cout_p / 16, splits), 256, 0, st>>>(a);
+    if (fast)
+      k_wgrad<1, 8, true><<<grid, 256, 0, st>>>(a);
+    else
+      k_wgrad<1, 8, false><<<grid, 256, 0, st>>>(a);
   }
 }
 
 void launch_grad_reduce(const float* part, const float* bpart, int splits, const NetLayer& L,
                         float* g, hipStream_t st) {
-  const int64_t n = (int64_t)L.cout * L.cin * L.k * L.k + L.cout;
+  const int64_t n = (int64_t)L.cout * L.kp + L.cout;
   k_grad_reduce<<<cdiv64(n, 256), 256, 0, st>>>(part, bpart, splits, L.cout, L.cin, L.k, L.cin_p,
                                                  L.kp, L.cout_p, g);
-}
-
-void launch_pack_t(const float* wm, const NetLayer& L, uint16_t* wt, hipStream_t st) {
-  k_pack_t<<<cdiv64((int64_t)L.coutp_t * L.kp_t, 256), 256, 0, st>>>(
-      wm, L.cout, L.cin, L.k, L.cinp_t, L.kp_t, L.coutp_t, wt);
 }
 
 void launch_out_grad(const OutGrad& o, const float* y, int64_t npix, uint16_t* g8,
@@ -996,9 +1164,10 @@ void launch_prep(const mrs_net* net, int64_t nhr, int64_t nlr, const float* hr, 
     k_prep<<<cdiv64(nhr + nlr, 256), 256, 0, st>>>(nhr, nlr, hr, aux, lr, xh, xl);
 }
 
-void launch_pack(const float* wm, const NetLayer& L, uint16_t* wp, hipStream_t st) {
-  k_pack<<<cdiv64((int64_t)L.cout_p * L.kp, 256), 256, 0, st>>>(wm, L.cout, L.cin, L.k, L.cin_p,
-                                                                 L.kp, L.cout_p, wp);
+void launch_pack_all(const float* wm, const PackJob* jobs, int njobs, int64_t total,
+                     uint16_t* packed, uint16_t* packed_t, hipStream_t st) {
+  if (total > 0)
+    k_pack_all<<<cdiv64(total, 256), 256, 0, st>>>(wm, jobs, njobs, total, packed, packed_t);
 }
 
 void launch_init(float* dst, const NetLayer& L, uint64_t seed, hipStream_t st) {

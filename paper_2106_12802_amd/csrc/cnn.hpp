@@ -82,7 +82,7 @@ struct WgradArgs {
   int dy_stride;
   int cout_p;
   int npix;
-  int chunk;             // pixels per split (multiple of 32)
+  int chunk;             // pixels per split (multiple of 128)
   float* part;           // [splits][cout_p][kp]
   int cout;              // output channels with a bias
   float* bpart;          // [splits][cout]: the bias gradient's partial sums
@@ -110,6 +110,17 @@ struct NetLayer {
   // data-gradient conv: inputs dY (cinp_t channels stored), outputs cin channels
   int cinp_t, kp_t, coutp_t;
   int64_t pkt_off;       // offset in the packed transposed weights (-1: none)
+};
+
+// One layer's BF16 packing job of k_pack_all: the forward layout (t = 0) or
+// the transposed layout of its data-gradient conv (t = 1).
+struct PackJob {
+  int64_t begin;    // index of the job's first element in the launch
+  int64_t w_off;    // the layer's FP32 master weights
+  int64_t out_off;  // offset in d_packed (t = 0) or d_packed_t (t = 1)
+  int cout, cin, ksz;
+  int cinp, kp, coutp;  // padded layout of the output
+  int t;
 };
 
 constexpr int NET_FEAT = 64;
@@ -143,7 +154,7 @@ ConvArgs tconv_args(const mrs_net* net, const NetLayer& L, int B, int H, int W,
 BwdEpi plain_epi();
 void wgrad(mrs_net* net, const NetLayer& L, const ConvArgs& x, const uint16_t* dy, int dy_stride,
            hipStream_t st);
-int wgrad_splits(int64_t npix, int& chunk);
+int wgrad_splits(int64_t npix, int kp, int cout_p, int& chunk);
 // Split-K partial buffers for the weight gradients at P HR pixels.
 mrs_status ensure_wpart(mrs_net* net, int64_t P, hipStream_t st);
 // The paper's network (net_rdg.hip): forward into out; forward + output
@@ -159,13 +170,13 @@ mrs_status arena_carve(char*& base, size_t& cap, std::vector<std::pair<void**, s
 void launch_conv(const ConvArgs& a, int cout_p, hipStream_t st);
 void launch_prep(const mrs_net* net, int64_t nhr, int64_t nlr, const float* hr, const float* aux,
                  const float* lr, uint16_t* xh, uint16_t* xl, hipStream_t st);
-void launch_pack(const float* wm, const NetLayer& L, uint16_t* wp, hipStream_t st);
 void launch_init(float* dst, const NetLayer& L, uint64_t seed, hipStream_t st);
 void launch_dgrad(const ConvArgs& a, const BwdEpi& e, int cout_p, hipStream_t st);
 void launch_wgrad(const WgradArgs& a, int splits, hipStream_t st);
 void launch_grad_reduce(const float* part, const float* bpart, int splits, const NetLayer& L,
                         float* g, hipStream_t st);
-void launch_pack_t(const float* wm, const NetLayer& L, uint16_t* wt, hipStream_t st);
+void launch_pack_all(const float* wm, const PackJob* jobs, int njobs, int64_t total,
+                     uint16_t* packed, uint16_t* packed_t, hipStream_t st);
 void launch_out_grad(const OutGrad& o, const float* y, int64_t npix, uint16_t* g8,
                      hipStream_t st);
 void launch_sgd(float* w, const float* g, int64_t n, float lr, hipStream_t st);
@@ -203,6 +214,10 @@ struct mrs_net {
   float* d_wpart = nullptr;
   size_t wpart_floats = 0;
   float* d_bpart = nullptr;
+  // packing jobs of every layer (forward layouts, then transposed), on device
+  mrs::PackJob* d_packjobs = nullptr;
+  int packjobs_fwd = 0, packjobs_all = 0;
+  int64_t pack_total_fwd = 0, pack_total_all = 0;
   // views of the last forward's activations (debug)
   int last_B = 0, last_H = 0, last_W = 0;
   float* last_f0 = nullptr;

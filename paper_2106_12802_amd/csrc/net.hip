@@ -310,23 +310,58 @@ mrs_status net_forward(mrs_net* net, int B, int H, int W, const float* hr, const
   return MRS_OK;
 }
 
-mrs_status net_refresh_packed(mrs_net* net, hipStream_t st) {
-  for (const NetLayer& L : net->layers) {
-    launch_pack(net->d_master + L.w_off, L, net->d_packed + L.pk_off, st);
-    if (L.pkt_off >= 0 && net->d_packed_t)
-      launch_pack_t(net->d_master + L.w_off, L, net->d_packed_t + L.pkt_off, st);
+// The table of packing jobs (built once: forward layouts of every layer, then
+// the transposed layouts of those with a data-gradient conv).
+mrs_status ensure_pack_jobs(mrs_net* net) {
+  if (net->d_packjobs) return MRS_OK;
+  std::vector<PackJob> jobs;
+  int64_t at = 0;
+  for (int t = 0; t < 2; ++t) {
+    for (const NetLayer& L : net->layers) {
+      if (t == 1 && L.pkt_off < 0) continue;
+      PackJob j;
+      j.begin = at;
+      j.w_off = L.w_off;
+      j.out_off = t ? L.pkt_off : L.pk_off;
+      j.cout = L.cout;
+      j.cin = L.cin;
+      j.ksz = L.k;
+      j.cinp = t ? L.cinp_t : L.cin_p;
+      j.kp = t ? L.kp_t : L.kp;
+      j.coutp = t ? L.coutp_t : L.cout_p;
+      j.t = t;
+      jobs.push_back(j);
+      at += (int64_t)j.coutp * j.kp;
+    }
+    if (t == 0) {
+      net->packjobs_fwd = (int)jobs.size();
+      net->pack_total_fwd = at;
+    }
   }
+  net->packjobs_all = (int)jobs.size();
+  net->pack_total_all = at;
+  if (hipMalloc(&net->d_packjobs, sizeof(PackJob) * jobs.size()) != hipSuccess) {
+    (void)hipGetLastError();
+    net->d_packjobs = nullptr;
+    return fail(MRS_ERR_OUT_OF_MEMORY, "packing table allocation failed");
+  }
+  MRS_TRY_HIP(hipMemcpy(net->d_packjobs, jobs.data(), sizeof(PackJob) * jobs.size(),
+                        hipMemcpyHostToDevice));
+  return MRS_OK;
+}
+
+mrs_status net_refresh_packed(mrs_net* net, hipStream_t st) {
+  mrs_status rc = ensure_pack_jobs(net);
+  if (rc != MRS_OK) return rc;
+  const bool with_t = net->d_packed_t != nullptr;
+  launch_pack_all(net->d_master, net->d_packjobs, with_t ? net->packjobs_all : net->packjobs_fwd,
+                  with_t ? net->pack_total_all : net->pack_total_fwd, net->d_packed,
+                  net->d_packed_t, st);
   MRS_TRY_HIP(hipGetLastError());
   return MRS_OK;
 }
 
 // ------------------------------------------------------------------ training
-
-int wgrad_splits(int64_t npix, int& chunk) {
-  int s = (int)std::min<int64_t>(256, std::max<int64_t>(1, npix / 256));
-  chunk = (int)(((npix + s - 1) / s + 31) / 32 * 32);
-  return (int)((npix + chunk - 1) / chunk);
-}
 
 // Split-K partial buffers for the weight gradients of every layer at batch
 // size B x H x W (pixel count per layer from its resolution level).
@@ -334,7 +369,7 @@ mrs_status ensure_wpart(mrs_net* net, int64_t P, hipStream_t st) {
   size_t need_w = 0, need_b = 0;
   for (const NetLayer& L : net->layers) {
     int chunk;
-    const int sp = wgrad_splits(P >> (2 * L.level), chunk);
+    const int sp = wgrad_splits(P >> (2 * L.level), L.kp, L.cout_p, chunk);
     need_w = std::max(need_w, (size_t)sp * L.cout_p * L.kp);
     need_b = std::max(need_b, (size_t)sp * L.cout);
   }
@@ -366,7 +401,7 @@ void wgrad(mrs_net* net, const NetLayer& L, const ConvArgs& x, const uint16_t* d
   w.dy_stride = dy_stride;
   w.cout_p = L.cout_p;
   w.npix = x.B * x.H * x.W;
-  const int splits = wgrad_splits(w.npix, w.chunk);
+  const int splits = wgrad_splits(w.npix, L.kp, L.cout_p, w.chunk);
   w.part = net->d_wpart;
   w.cout = L.cout;
   w.bpart = net->d_bpart;
@@ -794,7 +829,7 @@ mrs_status mrs_net_destroy(mrs_net* n) {
   if (n->d_arena) (void)hipFree(n->d_arena);
   for (void* p : {(void*)n->d_packed_t, (void*)n->d_grad, (void*)n->d_m, (void*)n->d_v,
                   (void*)n->d_train, (void*)n->d_loss, (void*)n->d_lpart, (void*)n->d_wpart,
-                  (void*)n->d_bpart})
+                  (void*)n->d_bpart, (void*)n->d_packjobs})
     if (p) (void)hipFree(p);
   delete n;
   return MRS_OK;
