@@ -901,6 +901,12 @@ def main():
                     help="tuning: traverse the quantized 64-byte BVH4 nodes")
     ap.add_argument("--queue-sort", type=int, default=None, choices=(0, 1),
                     help="tuning: order appended rays by octant / shadow rays by light")
+    ap.add_argument("--frames-in-flight", type=int, default=2, choices=(1, 2),
+                    help="frames the timed frame stream keeps in flight")
+    ap.add_argument("--wave-extend", type=int, default=None,
+                    help="tuning: bounces below this trace closest-hit rays a wave at a time")
+    ap.add_argument("--wave-shadow", type=int, default=None,
+                    help="tuning: bounces below this trace shadow rays a wave at a time")
     ap.add_argument("--bvh-builder", default=None, choices=("lbvh", "ploc"),
                     help="tuning: BVH builder of the scenes (default ploc)")
     ap.add_argument("--leaf-max", type=int, default=None,
@@ -929,6 +935,7 @@ def main():
     import torch
 
     import paper_2106_12802_amd as mrs
+    from paper_2106_12802_amd import hybrid as HY
     from paper_2106_12802_amd import tracer as R
     from mrs_inputs import scenes as S
 
@@ -938,7 +945,8 @@ def main():
         copy_calibration()
     R.set_tuning(args.chunk_paths, args.trace_blocks, args.schedule, args.leaf_max, args.streams,
                  args.tail_bounce, args.bvh_builder, queue_sort=args.queue_sort,
-                 bvh_quantized=args.bvh_quantized)
+                 bvh_quantized=args.bvh_quantized, wave_extend=args.wave_extend,
+                 wave_shadow=args.wave_shadow)
     tuning = R.get_tuning()
     log(f"[bench] tuning {tuning}")
     scene = S.procedural(SCENE_SEED)
@@ -970,17 +978,23 @@ def main():
         frame_batch.render()
         net.fuse(hr_rgb, hr_aux, lr_rgb, out=out)
 
-    def frames(first, k):
-        # k frames pipelined on the stream: frame i's fusion runs while frame i+1
-        # renders (the render is enqueued in two halves around the fusion)
-        frame_batch.set_seeds([2 * first, 2 * first + 1])
-        frame_batch.render_begin()
-        for i in range(first, first + k):
-            frame_batch.render_end()
-            if i + 1 < first + k:
-                frame_batch.set_seeds([2 * i + 2, 2 * i + 3])
-                frame_batch.render_begin()
-            net.fuse(hr_rgb, hr_aux, lr_rgb, out=out)
+    # a second frame in flight: its own batch (path workspace) and images
+    hr_rgb2, hr_aux2 = torch.empty_like(hr_rgb), torch.empty_like(hr_aux)
+    lr_rgb2 = torch.empty_like(lr_rgb)
+    frame_batch2 = mrs.Batch([
+        dict(scene=gs, W=Wh, H=Hh, spp=sh, max_depth=MAX_DEPTH, seed=0, out_rgb=hr_rgb2,
+             out_aux=hr_aux2),
+        dict(scene=gs, W=Wl, H=Hl, spp=sl, max_depth=MAX_DEPTH, seed=1, out_rgb=lr_rgb2,
+             want_aux=False)])
+    in_flight = ([frame_batch, frame_batch2], [
+        lambda: net.fuse(hr_rgb, hr_aux, lr_rgb, out=out),
+        lambda: net.fuse(hr_rgb2, hr_aux2, lr_rgb2, out=out)])
+
+    def frames(first, k, n=args.frames_in_flight):
+        # k frames pipelined on the stream, n in flight: frame i+1 renders while
+        # frame i's last paths finish and while frame i is fused
+        HY.pipeline_frames(in_flight[0][:n], lambda i: [2 * i, 2 * i + 1], in_flight[1][:n],
+                           range(first, first + k))
 
     def step_calls(i):
         R.render_ex(gs, Wh, Hh, sh, MAX_DEPTH, 2 * i, hr_rgb, hr_aux)
@@ -1092,8 +1106,9 @@ def main():
                                "textured Lambert+GGX, 3 quad lights, env 0.2), HRLS 1280x720@4spp "
                                "+ LRHS 320x180@64spp (max depth 8, RR from vertex 3; both renders as one "
                                "two-job batch, new seeds every frame) + BF16 fusion network "
-                               "(175.7 GFLOP); frames pipelined on one stream (frame i's fusion "
-                               "runs while frame i+1 renders)",
+                               "(175.7 GFLOP); frames pipelined on one stream with "
+                               f"{args.frames_in_flight} in flight (frame i+1 renders while frame i's "
+                               "last paths finish and while frame i is fused)",
                    "paths_per_frame": paths, "triangles": scene.num_tris,
                    "weights": "trained (paper_2106_12802_amd/weights)" if trained else "untrained",
                    "tuning": tuning},

@@ -259,6 +259,18 @@ mrs_status mrs_batch_render(mrs_batch* batch);
  * bitwise.  No allocation, no host synchronisation. */
 mrs_status mrs_batch_render_begin(mrs_batch* batch);
 mrs_status mrs_batch_render_end(mrs_batch* batch);
+/* The start of the batch's next render, marked ahead of its launches, for frame
+ * pipelines: on the current stream, clears the batch's per-pixel sums and marks
+ * the point the render's sub-chunk streams start from.  The next
+ * mrs_batch_render_begin (or mrs_batch_render) on the same stream then starts
+ * its wavefront from that point, so work enqueued on the stream between the two
+ * calls (e.g. the fusion of the previous frame, enqueued before the ~50
+ * launches of the wavefront) runs beside the render instead of before it.
+ * Seeds set after the fork undo it (the next begin forks again); a begin on
+ * another stream ignores it.  Same results, no allocation, no host
+ * synchronisation.  Error (MRS_ERR_INVALID_ARGUMENT, no effect): a render of the
+ * batch begun and not ended. */
+mrs_status mrs_batch_render_fork(mrs_batch* batch);
 /* Replaces the seed of every job (seeds[i] for job i, as many as the batch
  * has jobs): enqueues a small update of the device job table on the current
  * stream, ordered before later renders of the batch.  No allocation. */
@@ -342,6 +354,12 @@ typedef struct mrs_tuning {
                            node whose child boxes are 8-bit steps from the node's
                            origin, rounded outward with a margin; 0 (default):
                            the 128-byte nodes with FP32 boxes.  Same hits */
+  int32_t wave_extend;  /* 0..65 (default 1): closest-hit rays of the bounces
+                           below this one are traced a wave at a time (the 64
+                           rays of a wave walk one tree order together; node
+                           loads, stack and child order shared by the wave),
+                           the rest lane by lane.  Same hits */
+  int32_t wave_shadow;  /* 0..65 (default 0): the same for shadow rays */
 } mrs_tuning;
 mrs_status mrs_get_tuning(mrs_tuning* out);
 mrs_status mrs_set_tuning(const mrs_tuning* t);

@@ -82,7 +82,8 @@ class Tuning(C.Structure):
     _fields_ = [("chunk_paths", C.c_int32), ("trace_blocks", C.c_int32), ("schedule", C.c_int32),
                 ("bvh_leaf_max", C.c_int32), ("streams", C.c_int32), ("tail_bounce", C.c_int32),
                 ("bvh_builder", C.c_int32), ("conv_small_tiles", C.c_int32),
-                ("queue_sort", C.c_int32), ("bvh_quantized", C.c_int32)]
+                ("queue_sort", C.c_int32), ("bvh_quantized", C.c_int32),
+                ("wave_extend", C.c_int32), ("wave_shadow", C.c_int32)]
 
 
 assert C.sizeof(Material) == 32 and C.sizeof(QuadLight) == 56
@@ -137,6 +138,7 @@ def lib():
         "mrs_batch_create": ([C.POINTER(Job), I32, C.POINTER(P)], I32),
         "mrs_batch_render": ([P], I32),
         "mrs_batch_render_begin": ([P], I32),
+        "mrs_batch_render_fork": ([P], I32),
         "mrs_scene_bvh_builder": ([P, P], I32),
         "mrs_batch_render_end": ([P], I32),
         "mrs_batch_destroy": ([P], I32),
@@ -181,7 +183,7 @@ def exported_symbols():
         "mrs_batch_destroy", "mrs_release_workspaces", "mrs_batch_set_seeds",
         "mrs_debug_bvh4", "mrs_net_arch_num_params", "mrs_net_create_arch",
         "mrs_net_loss_grad_ex", "mrs_train_step_ex", "mrs_net_backward",
-        "mrs_batch_render_begin", "mrs_batch_render_end", "mrs_scene_bvh_builder",
+        "mrs_batch_render_begin", "mrs_batch_render_end", "mrs_batch_render_fork", "mrs_scene_bvh_builder",
         "mrs_profile_select", "mrs_debug_conv_launches", "mrs_net_save", "mrs_net_load",
         "mrs_render_ex_noalloc", "mrs_net_bind_layers",
     ]

@@ -394,6 +394,11 @@ mrs_status mrs_batch_render_begin(mrs_batch* b) {
   return batch_render_begin(b, current_stream());
 }
 
+mrs_status mrs_batch_render_fork(mrs_batch* b) {
+  if (!b) return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_batch_render_fork: batch is NULL");
+  return batch_render_fork(b, current_stream());
+}
+
 mrs_status mrs_batch_render_end(mrs_batch* b) {
   if (!b) return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_batch_render_end: batch is NULL");
   return batch_render_end(b, current_stream());

@@ -164,6 +164,7 @@ mrs_status batch_create(const std::vector<DevJob>& jobs, mrs_batch** out);
 mrs_status batch_render(mrs_batch* b, hipStream_t st);
 mrs_status batch_render_begin(mrs_batch* b, hipStream_t st);
 mrs_status batch_render_end(mrs_batch* b, hipStream_t st);
+mrs_status batch_render_fork(mrs_batch* b, hipStream_t st);
 mrs_status batch_set_seeds(mrs_batch* b, const uint64_t* seeds, hipStream_t st);
 void batch_destroy(mrs_batch* b);
 // frees the per-stream workspaces (synchronises the device)

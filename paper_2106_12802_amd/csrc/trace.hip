@@ -198,14 +198,14 @@ struct TraceView {
   int32_t ntris;
 };
 
-// Moller-Trumbore against one leaf; edges inclusive, t > 0, three excluded
-// primitives.  any: accept any t < ts.t (shadow rays).  Otherwise accept a
-// closer hit, or an equal t with a smaller primitive id.
-__device__ __forceinline__ bool isect_leaf(const gfloat4* __restrict__ leaf_tri, uint32_t leaf,
-                                           f3 o, f3 d, uint32_t x0, uint32_t x1, uint32_t x2,
-                                           bool any, TraceState& ts) {
-  const float4 A = ld4(leaf_tri + 3 * leaf), B = ld4(leaf_tri + 3 * leaf + 1),
-               C = ld4(leaf_tri + 3 * leaf + 2);
+// Moller-Trumbore on one triangle given as three float4 (v0 and the primitive
+// id, edge 1, edge 2); edges inclusive, t > 0, three excluded primitives.
+// any: accept any t < ts.t (shadow rays).  Otherwise accept a closer hit, or an
+// equal t with a smaller primitive id.  Both traversals (lane by lane and wave
+// by wave) call it, so their hits are bitwise alike.
+__device__ __forceinline__ bool isect_tri(const float4 A, const float4 B, const float4 C, f3 o,
+                                          f3 d, uint32_t x0, uint32_t x1, uint32_t x2, bool any,
+                                          TraceState& ts) {
   const uint32_t prim = __float_as_uint(A.w);
   const f3 e1 = xyz(B), e2 = xyz(C);
   const f3 pv = cross(d, e2);
@@ -230,6 +230,14 @@ __device__ __forceinline__ bool isect_leaf(const gfloat4* __restrict__ leaf_tri,
     }
   }
   return ok;
+}
+// The same on triangle `leaf` of the leaf-ordered triangle array.
+__device__ __forceinline__ bool isect_leaf(const gfloat4* __restrict__ leaf_tri, uint32_t leaf,
+                                           f3 o, f3 d, uint32_t x0, uint32_t x1, uint32_t x2,
+                                           bool any, TraceState& ts) {
+  const float4 A = ld4(leaf_tri + 3 * leaf), B = ld4(leaf_tri + 3 * leaf + 1),
+               C = ld4(leaf_tri + 3 * leaf + 2);
+  return isect_tri(A, B, C, o, d, x0, x1, x2, any, ts);
 }
 
 typedef __attribute__((address_space(3))) uint32_t lds_u32;
@@ -484,6 +492,214 @@ __device__ void trace_stream(IO& io, uint32_t first, uint32_t stride, uint32_t n
   }
 }
 
+
+// ------------------------------------------------------------ wave traversal
+
+// Coherent rays (camera rays: the 64 paths of a wave start in one pixel at 64
+// spp, in 16 neighbouring pixels at 4 spp; their shadow rays) are traced a wave
+// at a time: the wave walks one tree order together, each lane testing its own
+// ray against every node some lane of the wave still needs (Wald et al.,
+// "Interactive rendering with coherent ray tracing", 2001, on 64-wide SIMD).
+// The node and triangle loads, the stack and the child order are wave-uniform:
+// nodes come through the scalar data cache, the stack lives in VGPR lanes, and
+// no lane waits on another lane's branch.  A stack entry carries the lanes that
+// entered the node's box.  Culling stays per lane and conservative (slab), and
+// the triangle test is isect_tri, so each lane's hit is bitwise the one the
+// lane-by-lane traversal finds.
+
+typedef __attribute__((address_space(4))) const vfloat4 kfloat4;
+
+// A wave-uniform float4 through the scalar data cache (the address must be
+// uniform: it is built from readlane / scalar-load values only).
+__device__ __forceinline__ float4 sld4(const kfloat4* p) {
+  const vfloat4 v = *p;
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ uint32_t rdlane(uint32_t v, uint32_t lane) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)lane);
+}
+__device__ __forceinline__ uint64_t rdlane64(uint64_t v, uint32_t lane) {
+  return ((uint64_t)rdlane((uint32_t)(v >> 32), lane) << 32) | rdlane((uint32_t)v, lane);
+}
+
+constexpr uint32_t WAVE_STACK = 128;  // entries; as MAX_STACK4 for one lane
+
+// The stack of a wave: entry k = (reference, lane mask) in lane k % 64 of the
+// register set k / 64.  sp is wave-uniform.
+struct WaveStack {
+  uint32_t ref0, lo0, hi0, ref1, lo1, hi1;
+  uint32_t sp;
+  bool overflow;
+  // branch-free over the two register sets (a branch per set makes the
+  // compiler keep them in scratch memory)
+  __device__ __forceinline__ void push(uint32_t r, uint64_t m) {
+    if (sp >= WAVE_STACK) {
+      overflow = true;
+      return;
+    }
+    const bool me = __lane_id() == (sp & 63u), s0 = me && sp < 64, s1 = me && sp >= 64;
+    const uint32_t mlo = (uint32_t)m, mhi = (uint32_t)(m >> 32);
+    ref0 = s0 ? r : ref0;
+    lo0 = s0 ? mlo : lo0;
+    hi0 = s0 ? mhi : hi0;
+    ref1 = s1 ? r : ref1;
+    lo1 = s1 ? mlo : lo1;
+    hi1 = s1 ? mhi : hi1;
+    ++sp;
+  }
+  __device__ __forceinline__ void pop(uint32_t& r, uint64_t& m) {
+    --sp;
+    const uint32_t l = sp & 63u;
+    const bool first = sp < 64;
+    const uint32_t ra = rdlane(ref0, l), rb = rdlane(ref1, l);
+    const uint32_t la = rdlane(lo0, l), lb = rdlane(lo1, l);
+    const uint32_t ha = rdlane(hi0, l), hb = rdlane(hi1, l);
+    r = first ? ra : rb;
+    m = ((uint64_t)(first ? ha : hb) << 32) | (first ? la : lb);
+  }
+};
+
+// Orders two children (entry key, reference, lane mask) by key.
+__device__ __forceinline__ void wswap(uint32_t& ka, uint32_t& ra, uint64_t& ma, uint32_t& kb,
+                                      uint32_t& rb, uint64_t& mb) {
+  if (kb < ka) {
+    const uint32_t k = ka, r = ra;
+    const uint64_t m = ma;
+    ka = kb;
+    ra = rb;
+    ma = mb;
+    kb = k;
+    rb = r;
+    mb = m;
+  }
+}
+
+// The lanes `grp` (rays of one scene) walk the tree of `sc` together.  Children
+// are entered nearest first as seen by the first lane that enters any of them;
+// a child no lane enters is skipped.  ANY: a lane stops at its first occluder,
+// and the walk ends when every lane of grp has one.  Visits are bounded by the
+// node and triangle counts (each node is entered at most once per walk).
+template <bool ANY>
+__device__ __forceinline__ void wave_walk(const TraceView& sc, uint64_t grp, const RayIn& r,
+                                          f3 inv, f3 oi, TraceState& ts, bool& occluded,
+                                          WaveStack& ws) {
+  const uint32_t lane = __lane_id();
+  const kfloat4* nodes = (const kfloat4*)(uintptr_t)sc.nodes;
+  const kfloat4* tris = (const kfloat4*)(uintptr_t)sc.leaf_tri;
+  uint32_t node = sc.root;
+  uint64_t m = grp, done = 0;
+  int32_t budget = (int32_t)sc.nnodes + sc.ntris + 2;
+  ws.sp = 0;
+  while (--budget > 0) {
+    if (!(node & LEAF_BIT)) {
+      if (node < sc.nnodes) {
+        const bool act = ((m >> lane) & 1ull) != 0;
+        const kfloat4* nd = nodes + 8 * node;
+        const float4 lx = sld4(nd), ly = sld4(nd + 1), lz = sld4(nd + 2);
+        const float4 hx = sld4(nd + 3), hy = sld4(nd + 4), hz = sld4(nd + 5);
+        const float4 rf = sld4(nd + 6);
+        uint32_t r0 = __float_as_uint(rf.x), r1 = __float_as_uint(rf.y),
+                 r2 = __float_as_uint(rf.z), r3 = __float_as_uint(rf.w);
+        float t0, t1, t2, t3;
+        const bool h0 = act & (r0 != EMPTY4) &
+                        slab(lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, oi, inv, ts.t, t0);
+        const bool h1 = act & (r1 != EMPTY4) &
+                        slab(lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, oi, inv, ts.t, t1);
+        const bool h2 = act & (r2 != EMPTY4) &
+                        slab(lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, oi, inv, ts.t, t2);
+        const bool h3 = act & (r3 != EMPTY4) &
+                        slab(lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, oi, inv, ts.t, t3);
+        uint64_t m0 = __ballot(h0), m1 = __ballot(h1), m2 = __ballot(h2), m3 = __ballot(h3);
+        const uint64_t any_m = m0 | m1 | m2 | m3;
+        if (any_m) {
+          // keys: the entry distance of the first entering lane (its non-negative
+          // float bits order like the floats); children it misses after the rest
+          const uint32_t rl = (uint32_t)__builtin_ctzll(any_m);
+          const uint32_t FAR = 0x7f800000u, NONE = 0xffffffffu;
+          uint32_t k0 = m0 ? rdlane(h0 ? __float_as_uint(t0) & 0x7fffffffu : FAR, rl) : NONE;
+          uint32_t k1 = m1 ? rdlane(h1 ? __float_as_uint(t1) & 0x7fffffffu : FAR, rl) : NONE;
+          uint32_t k2 = m2 ? rdlane(h2 ? __float_as_uint(t2) & 0x7fffffffu : FAR, rl) : NONE;
+          uint32_t k3 = m3 ? rdlane(h3 ? __float_as_uint(t3) & 0x7fffffffu : FAR, rl) : NONE;
+          wswap(k0, r0, m0, k1, r1, m1);
+          wswap(k2, r2, m2, k3, r3, m3);
+          wswap(k0, r0, m0, k2, r2, m2);
+          wswap(k1, r1, m1, k3, r3, m3);
+          wswap(k1, r1, m1, k2, r2, m2);
+          // entered children first (keys below NONE), far ones pushed first
+          if (m3) ws.push(r3, m3);
+          if (m2) ws.push(r2, m2);
+          if (m1) ws.push(r1, m1);
+          node = r0;
+          m = m0;
+          continue;
+        }
+      }
+    } else {
+      const uint32_t f = node & 0x00ffffffu, cnt = ((node >> 24) & 3u) + 1u;
+      if (f + cnt <= (uint32_t)sc.ntris) {  // keeps a corrupt reference harmless
+        const bool act = ((m >> lane) & 1ull) != 0;
+        for (uint32_t k = 0; k < cnt; ++k) {
+          const kfloat4* tp = tris + 3 * (f + k);
+          const float4 A = sld4(tp), B = sld4(tp + 1), C = sld4(tp + 2);
+          if (act && !occluded) {
+            if (isect_tri(A, B, C, r.o, r.d, r.x0, r.x1, r.x2, ANY, ts) && ANY) occluded = true;
+          }
+        }
+        if (ANY) {
+          done |= __ballot(occluded);
+          if (!(grp & ~done)) break;
+        }
+      }
+    }
+    // next entry with a lane left in it
+    bool more = false;
+    while (ws.sp) {
+      ws.pop(node, m);
+      if (ANY) m &= ~done;
+      if (m) {
+        more = true;
+        break;
+      }
+    }
+    if (!more) break;
+  }
+}
+
+// The 64 queue entries base .. base + 63 (below n) as one wave: each lane
+// loads its ray, the lanes of each scene walk its tree together, and each lane
+// stores its result.  IO as for trace_stream (store's continuation is not used).
+template <bool ANY, class IO>
+__device__ __forceinline__ void trace_wave(IO& io, uint32_t base, uint32_t n, WaveStack& ws) {
+  const uint32_t qi = base + __lane_id();
+  const bool live = qi < n;
+  RayIn r{};
+  TraceState ts{INFINITY, NO_PRIM, 0.0f, 0.0f};
+  f3 inv = F3(1.0f, 1.0f, 1.0f), oi = F3(0.0f, 0.0f, 0.0f);
+  bool occluded = false;
+  if (live) {
+    io.load(qi, r);
+    ts.t = r.tmax;
+    inv = F3(safe_rcp(r.d.x), safe_rcp(r.d.y), safe_rcp(r.d.z));
+    oi = mul(r.o, inv);
+  }
+  uint64_t todo = __ballot(live && r.sc.ntris > 0);
+  while (todo) {
+    // the scene of the first lane left (lanes of a wave may trace different scenes)
+    const uint32_t l0 = (uint32_t)__builtin_ctzll(todo);
+    TraceView sc;
+    sc.nodes = (const gfloat4*)(uintptr_t)rdlane64((uint64_t)(uintptr_t)r.sc.nodes, l0);
+    sc.nodes_q = nullptr;
+    sc.leaf_tri = (const gfloat4*)(uintptr_t)rdlane64((uint64_t)(uintptr_t)r.sc.leaf_tri, l0);
+    sc.root = rdlane(r.sc.root, l0);
+    sc.nnodes = rdlane(r.sc.nnodes, l0);
+    sc.ntris = (int32_t)rdlane((uint32_t)r.sc.ntris, l0);
+    const uint64_t grp = __ballot(live && r.sc.nodes == sc.nodes) & todo;
+    todo &= ~grp;
+    wave_walk<ANY>(sc, grp, r, inv, oi, ts, occluded, ws);
+  }
+  RayIn next;
+  if (live) (void)io.store(qi, ts, occluded, next);
+}
 
 // ------------------------------------------------------------------ jobs
 
@@ -1033,6 +1249,36 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(7))) void k_
   if (COUNT && wc.max_steps) atomicMax(stats + 11, (unsigned long long)wc.max_steps);
 }
 
+// Closest hits and shadow rays of bounce b with the wave traversal (trace_wave):
+// a wave takes 64 consecutive queue entries at a time, grid-stride or (dyn)
+// from the device counter.  Same inputs, outputs and results as k_extend and
+// k_shadow.
+__global__ __launch_bounds__(TB) void k_extend_wave(const DevJob* __restrict__ jobs, int b,
+                                                    int dyn, const float4* __restrict__ rays,
+                                                    uint32_t* __restrict__ q,
+                                                    float4* __restrict__ hits,
+                                                    unsigned long long* __restrict__ stats) {
+  const uint32_t n = q[Q_RAYS + b];
+  ExtendIO io{jobs, rays, hits};
+  WaveStack ws{};
+  for (WaveQueue wq(q + Q_FETCH_EXT + b, dyn != 0); wq.base < n; wq.next())
+    trace_wave<false>(io, wq.base, n, ws);
+  if (ws.overflow && __lane_id() == 0) atomicAdd(stats + 5, 1ull);
+}
+
+__global__ __launch_bounds__(TB) void k_shadow_wave(const DevJob* __restrict__ jobs, int b,
+                                                    int dyn, const float4* __restrict__ shadow,
+                                                    uint32_t* __restrict__ q,
+                                                    float4* __restrict__ L_buf,
+                                                    unsigned long long* __restrict__ stats) {
+  const uint32_t n = q[Q_SHADOW + b];
+  ShadowIO io{jobs, shadow, L_buf};
+  WaveStack ws{};
+  for (WaveQueue wq(q + Q_FETCH_SHD + b, dyn != 0); wq.base < n; wq.next())
+    trace_wave<true>(io, wq.base, n, ws);
+  if (ws.overflow && __lane_id() == 0) atomicAdd(stats + 5, 1ull);
+}
+
 // Path tail: the paths still alive at bounce b0 are finished here one by one
 // (closest hit, shading, shadow ray, next segment, ...) in a single launch, so
 // that the last bounces -- few rays, each launch bounded below by its slowest
@@ -1236,7 +1482,19 @@ __global__ __launch_bounds__(256) void k_accumulate(const DevJob* __restrict__ j
                                                     const float4* __restrict__ aux_buf,
                                                     const float4* __restrict__ lay_buf,
                                                     char* __restrict__ acc_base,
-                                                    unsigned long long* __restrict__ stats) {
+                                                    unsigned long long* __restrict__ stats,
+                                                    const uint32_t* __restrict__ qc, int nb) {
+  // the chunk's ray counts, once (bounces 0 .. nb-1; the path tail counts its own)
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    unsigned long long r = 0, s = 0;
+    for (int b = 0; b < nb; ++b) {
+      r += qc[Q_RAYS + b];
+      s += qc[Q_SHADOW + b];
+    }
+    atomicAdd(stats + 1, r);
+    atomicAdd(stats + 2, s);
+    atomicAdd(stats + 4, (unsigned long long)n);
+  }
   // i runs over pixels in path order (the chunk's pixels are one range of it)
   const int64_t i = pix_lo + (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= pix_hi) return;
@@ -1294,21 +1552,6 @@ __global__ __launch_bounds__(256) void k_resolve(const DevJob* __restrict__ jobs
   const uint32_t pl = (uint32_t)(i - J.pix_first);
   if (J.fp64) resolve_pixel<double>(J, acc, pl, npix);
   else resolve_pixel<float>(J, acc, pl, npix);
-}
-
-__global__ __launch_bounds__(64) void k_tally(const uint32_t* __restrict__ q, int nb,
-                                              unsigned long long* __restrict__ stats,
-                                              uint32_t paths) {
-  if (threadIdx.x == 0) {
-    unsigned long long r = 0, s = 0;
-    for (int b = 0; b < nb; ++b) {
-      r += q[Q_RAYS + b];
-      s += q[Q_SHADOW + b];
-    }
-    atomicAdd(stats + 1, r);
-    atomicAdd(stats + 2, s);
-    atomicAdd(stats + 4, (unsigned long long)paths);
-  }
 }
 
 struct DebugHitIO {
@@ -1414,6 +1657,11 @@ struct Workspace {
   hipEvent_t ev_fork = nullptr;
   hipEvent_t ev_join[MAX_SUB] = {};
   Pending pend;  // a render begun and not yet ended
+  // a render fork not yet used (on stream fork_st, which may be the null
+  // stream): its zeroing of the sums and its ev_fork stand for those of the
+  // next render begun on that stream
+  bool forked = false;
+  hipStream_t fork_st = nullptr;
 };
 
 // How a render's path space is cut: super-chunks of K * Cs paths; the K
@@ -1448,7 +1696,7 @@ hipStream_t g_sub[MAX_SUB] = {};
 int g_nsub = 0;
 unsigned long long* g_stats = nullptr;  // device counters shared by every stream
 // defaults: the fastest hybrid 720p frame measured with the clustered BVH
-mrs_tuning g_tune = {1 << 23, 8192, 0, 3, 3, 3, MRS_BVH_PLOC, 128, 1, 0};
+mrs_tuning g_tune = {1 << 23, 8192, 0, 3, 3, 3, MRS_BVH_PLOC, 128, 1, 0, 1, 0};
 std::atomic<int> g_conv_small{128};  // g_tune.conv_small_tiles, read without the lock
 std::atomic<bool> g_count_work{false};
 
@@ -1600,9 +1848,8 @@ mrs_status sum_chunk(Workspace& ws, const DevJob* d_jobs, const std::vector<DevJ
         jobs[jhi].pix_first + (u.lo + (int64_t)u.n - 1 - jobs[jhi].first) / jobs[jhi].spp + 1;
     prof_begin(KID_ACCUMULATE, st);
     k_accumulate<<<cdiv((size_t)(pix_hi - pix_lo), 256), 256, 0, st>>>(
-        d_jobs, nj, u.lo, u.n, pix_lo, pix_hi, u.L, u.aux, u.lay, acc, ws.stats);
+        d_jobs, nj, u.lo, u.n, pix_lo, pix_hi, u.L, u.aux, u.lay, acc, ws.stats, u.q, nwave);
     prof_end(KID_ACCUMULATE, st);
-    k_tally<<<1, 64, 0, st>>>(u.q, nwave, ws.stats, u.n);
   }
   // the next super-chunk (or render) reuses the slices once these sums have read them
   if (used > 0 && sub[0].s != st) MRS_TRY_HIP(hipEventRecord(ws.ev_fork, st));
@@ -1632,9 +1879,13 @@ mrs_status begin_batch(Workspace& ws, const mrs_tuning& tu, const DevJob* d_jobs
   const bool count = g_count_work.load();
   unsigned long long* stats = ws.stats;
   const size_t spill_k = (size_t)P.blocks_k * TB * (MAX_STACK4 - LDS_STACK);
-  k_zero_words<<<std::min(4096u, cdiv(acc_bytes / 4, 256)), 256, 0, st>>>((uint32_t*)acc,
-                                                                          acc_bytes / 4);
-  if (P.K > 1) MRS_TRY_HIP(hipEventRecord(ws.ev_fork, st));
+  const bool forked = ws.forked && ws.fork_st == st;
+  ws.forked = false;
+  if (!forked) {
+    k_zero_words<<<std::min(4096u, cdiv(acc_bytes / 4, 256)), 256, 0, st>>>((uint32_t*)acc,
+                                                                            acc_bytes / 4);
+    if (P.K > 1) MRS_TRY_HIP(hipEventRecord(ws.ev_fork, st));
+  }
   for (int64_t g0 = 0; g0 < total; g0 += P.K * P.Cs) {
     Sub sub[MAX_SUB];
     int used = 0;
@@ -1670,9 +1921,13 @@ mrs_status begin_batch(Workspace& ws, const mrs_tuning& tu, const DevJob* d_jobs
       for (int k = 0; k < used; ++k) {
         Sub& u = sub[k];
         prof_begin(KID_EXTEND, u.s);
-        auto ext = count ? (qn ? k_extend<true, true> : k_extend<true, false>)
-                         : (qn ? k_extend<false, true> : k_extend<false, false>);
-        ext<<<u.gb, TB, 0, u.s>>>(d_jobs, b, dyn, u.rays[b & 1], u.q, u.hits, u.spill, stats);
+        if (!count && b < tu.wave_extend) {
+          k_extend_wave<<<u.gb, TB, 0, u.s>>>(d_jobs, b, dyn, u.rays[b & 1], u.q, u.hits, stats);
+        } else {
+          auto ext = count ? (qn ? k_extend<true, true> : k_extend<true, false>)
+                           : (qn ? k_extend<false, true> : k_extend<false, false>);
+          ext<<<u.gb, TB, 0, u.s>>>(d_jobs, b, dyn, u.rays[b & 1], u.q, u.hits, u.spill, stats);
+        }
         prof_end(KID_EXTEND, u.s);
       }
       for (int k = 0; k < used; ++k) {
@@ -1692,9 +1947,13 @@ mrs_status begin_batch(Workspace& ws, const mrs_tuning& tu, const DevJob* d_jobs
         for (int k = 0; k < used; ++k) {
           Sub& u = sub[k];
           prof_begin(KID_SHADOW, u.s);
-          auto shd = count ? (qn ? k_shadow<true, true> : k_shadow<true, false>)
-                           : (qn ? k_shadow<false, true> : k_shadow<false, false>);
-          shd<<<u.gb, TB, 0, u.s>>>(d_jobs, b, dyn, u.shadow, u.q, u.L, u.spill, stats);
+          if (!count && b < tu.wave_shadow) {
+            k_shadow_wave<<<u.gb, TB, 0, u.s>>>(d_jobs, b, dyn, u.shadow, u.q, u.L, stats);
+          } else {
+            auto shd = count ? (qn ? k_shadow<true, true> : k_shadow<true, false>)
+                             : (qn ? k_shadow<false, true> : k_shadow<false, false>);
+            shd<<<u.gb, TB, 0, u.s>>>(d_jobs, b, dyn, u.shadow, u.q, u.L, u.spill, stats);
+          }
           prof_end(KID_SHADOW, u.s);
         }
       }
@@ -2024,6 +2283,24 @@ mrs_status batch_render_begin(mrs_batch* b, hipStream_t st) {
   return rc;
 }
 
+// The first part of begin_batch on its own: clear the sums and record the
+// point the sub-chunk streams start from.
+mrs_status batch_render_fork(mrs_batch* b, hipStream_t st) {
+  if (b->ws.pend.active)
+    return fail(MRS_ERR_INVALID_ARGUMENT,
+                "mrs_batch_render_fork: the batch's previous render is not ended");
+  int64_t total = 0;
+  for (const DevJob& J : b->jobs) total += (int64_t)J.spp * J.ww * J.wh;
+  const Plan P = make_plan(b->tune, total);
+  k_zero_words<<<std::min(4096u, cdiv(b->acc_bytes / 4, 256)), 256, 0, st>>>(
+      (uint32_t*)b->d_acc, b->acc_bytes / 4);
+  if (P.K > 1) MRS_TRY_HIP(hipEventRecord(b->ws.ev_fork, st));
+  MRS_TRY_HIP(hipGetLastError());
+  b->ws.forked = true;
+  b->ws.fork_st = st;
+  return MRS_OK;
+}
+
 mrs_status batch_render_end(mrs_batch* b, hipStream_t st) {
   if (!b->ws.pend.active)
     return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_batch_render_end: no render of the batch begun");
@@ -2034,6 +2311,7 @@ mrs_status batch_render_end(mrs_batch* b, hipStream_t st) {
 }
 
 mrs_status batch_set_seeds(mrs_batch* b, const uint64_t* seeds, hipStream_t st) {
+  b->ws.forked = false;  // the generate kernels must see the new seeds
   SeedTable t;
   std::memset(&t, 0, sizeof t);
   t.n = (uint32_t)b->jobs.size();
@@ -2121,6 +2399,9 @@ mrs_status set_tuning(const mrs_tuning* t) {
     return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_set_tuning: queue_sort must be 0 or 1");
   if (t->bvh_quantized != 0 && t->bvh_quantized != 1)
     return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_set_tuning: bvh_quantized must be 0 or 1");
+  if (t->wave_extend < 0 || t->wave_extend > 65 || t->wave_shadow < 0 || t->wave_shadow > 65)
+    return fail(MRS_ERR_INVALID_ARGUMENT,
+                "mrs_set_tuning: wave_extend and wave_shadow must be in [0, 65]");
   std::lock_guard<std::mutex> lk(g_mu);
   g_tune = *t;
   g_conv_small = t->conv_small_tiles;

@@ -55,30 +55,69 @@ def fallback_spp(spp_h=4, spp_l=64):
     return max(1, spp_h + spp_l // (SCALE * SCALE))
 
 
-class HybridFrame:
-    """Reusable hybrid frame of one scene: HRLS and LRHS rendered as one two-job batch
-    (one wavefront over both renders), then fused.  Buffers and the batch are made
-    once; render(seed) takes seeds 2 seed and 2 seed + 1 as hybrid_frame does.
-    Without a ready network (None, or no parameters) the frame falls back to a plain
-    render with the same number of paths (fallback_spp), seed 2 seed.  layers=True also
-    keeps the HRLS render layers of Sec. 3.1 (hr_layers [H, W, 9]: emission, diffuse,
-    glossy) and its per-pixel sums of squares (hr_sumsq, the variance layer)."""
+def pipeline_frames(batches, seeds_of, fuses, seeds, on_frame=None):
+    """Renders and fuses the frames of `seeds` on the current stream with
+    n = len(batches) frames in flight: frame k renders with batches[k % n] (a
+    batch owns its path workspace and outputs) and fuses with fuses[k % n]().
 
-    def __init__(self, gs, net: FusionNet | None, W, H, spp_h=4, spp_l=64, depth=DEPTH,
-                 layers=False):
-        self.net = net
-        self.out = _empty((H, W, 3))
-        self.fallback = net is None or not net.ready
-        self.spp_h = spp_h
-        if not self.fallback and net.has_layers:
-            layers = True  # the network reads them
-        if self.fallback:
-            self.batch = T.Batch([dict(scene=gs, W=W, H=H, spp=fallback_spp(spp_h, spp_l),
-                                       max_depth=depth, seed=0, out_rgb=self.out,
-                                       want_aux=False)])
-            return
+    n = 1: per frame k, render_end (frame k's per-pixel sums and outputs), the
+    seeds and render_fork of frame k+1 (the point its sub-chunk streams start
+    from), fuse() on frame k's outputs, then render_begin of frame k+1: the
+    fusion's launches queue ahead of the next wavefront's and run beside it.
+
+    n = 2: frame k+1 is begun (on the other batch) before frame k is ended.  Its
+    sub-chunks queue on the library's sub-chunk streams behind frame k's and start
+    as each of frame k's sub-chunks finishes, so frame k's last path tails share
+    the GPU with frame k+1's first bounces instead of running alone; frame k's
+    sums, outputs and fusion follow on the stream.  A batch is begun again only
+    after its previous frame was ended and fused (stream order), so frame k+2's
+    outputs are written after frame k's fusion has read them.  (Forking frame k+2
+    right after frame k's sums, ahead of frame k's fusion, measured slower: with
+    two frames queued on the sub-chunk streams the stream's sums and fusions fall
+    behind.)
+
+    Every frame is bitwise what render + fuse of its seeds gives.  on_frame(k)
+    runs right after frame k's fusion is enqueued (work it enqueues on the stream
+    sees that frame)."""
+    seeds = list(seeds)
+    n = len(batches)
+    if not seeds:
+        return
+    if n not in (1, 2):
+        raise ValueError("pipeline_frames: 1 or 2 frames in flight")
+    batches[0].set_seeds(seeds_of(seeds[0]))
+    batches[0].render_begin()
+    for k in range(len(seeds)):
+        cur = batches[k % n]
+        more = k + 1 < len(seeds)
+        if n == 1:
+            cur.render_end()
+            if more:
+                cur.set_seeds(seeds_of(seeds[k + 1]))
+                cur.render_fork()
+            fuses[0]()
+            if on_frame is not None:
+                on_frame(k)
+            if more:
+                cur.render_begin()
+        else:
+            if more:
+                nxt = batches[(k + 1) % n]
+                nxt.set_seeds(seeds_of(seeds[k + 1]))
+                nxt.render_begin()
+            cur.render_end()
+            fuses[k % n]()
+            if on_frame is not None:
+                on_frame(k)
+
+
+class _Slot:
+    """One frame in flight: its two-job batch and the images it writes."""
+
+    def __init__(self, gs, W, H, spp_h, spp_l, depth, layers):
         self.hr_rgb, self.hr_aux = _empty((H, W, 3)), _empty((H, W, 7))
         self.lr_rgb = _empty((H // SCALE, W // SCALE, 3))
+        self.hr_layers = self.hr_sumsq = None
         extra = {}
         if layers:
             self.hr_layers, self.hr_sumsq = _empty((H, W, 9)), _empty((H, W, 3))
@@ -89,48 +128,90 @@ class HybridFrame:
             dict(scene=gs, W=W // SCALE, H=H // SCALE, spp=spp_l, max_depth=depth, seed=1,
                  out_rgb=self.lr_rgb, want_aux=False)])
 
+
+class HybridFrame:
+    """HRLS + LRHS rendered as one two-job batch (one wavefront launch sequence over
+    both renders), then fused.  Buffers and the batch are made once; render(seed)
+    takes seeds 2 seed and 2 seed + 1 as hybrid_frame does.  Without a ready network
+    (None, or no parameters) the frame falls back to a plain render with the same
+    number of paths (fallback_spp), seed 2 seed.  layers=True also keeps the HRLS
+    render layers of Sec. 3.1 (hr_layers [H, W, 9]: emission, diffuse, glossy) and
+    its per-pixel sums of squares (hr_sumsq, the variance layer).  hr_rgb, hr_aux,
+    lr_rgb, hr_layers and hr_sumsq are the images of the last render()."""
+
+    def __init__(self, gs, net: FusionNet | None, W, H, spp_h=4, spp_l=64, depth=DEPTH,
+                 layers=False):
+        self.net = net
+        self.out = _empty((H, W, 3))
+        self.fallback = net is None or not net.ready
+        self.spp_h = spp_h
+        self._args = (gs, W, H, spp_h, spp_l, depth)
+        if not self.fallback and net.has_layers:
+            layers = True  # the network reads them
+        self.layers = layers
+        if self.fallback:
+            self.batch = T.Batch([dict(scene=gs, W=W, H=H, spp=fallback_spp(spp_h, spp_l),
+                                       max_depth=depth, seed=0, out_rgb=self.out,
+                                       want_aux=False)])
+            return
+        self.slots = [_Slot(*self._args, layers)]
+        self._use(self.slots[0])
+
+    def _use(self, sl):
+        self.batch = sl.batch
+        self.hr_rgb, self.hr_aux, self.lr_rgb = sl.hr_rgb, sl.hr_aux, sl.lr_rgb
+        if self.layers:
+            self.hr_layers, self.hr_sumsq = sl.hr_layers, sl.hr_sumsq
+
     def render(self, seed):
         if self.fallback:
             self.batch.set_seeds([2 * seed])
             self.batch.render()
             return self.out
-        self.batch.set_seeds([2 * seed, 2 * seed + 1])
-        self.batch.render()
-        return self._fuse()
+        sl = self.slots[0]
+        self._use(sl)
+        sl.batch.set_seeds([2 * seed, 2 * seed + 1])
+        sl.batch.render()
+        return self._fuse(sl)
 
-    def _fuse(self):
-        lay = (self.hr_layers, self.hr_sumsq, self.spp_h) if self.net.has_layers else None
-        return self.net.fuse(self.hr_rgb, self.hr_aux, self.lr_rgb, out=self.out, layers=lay)
+    def _fuse(self, sl):
+        lay = (sl.hr_layers, sl.hr_sumsq, self.spp_h) if self.net.has_layers else None
+        return self.net.fuse(sl.hr_rgb, sl.hr_aux, sl.lr_rgb, out=self.out, layers=lay)
 
     def _seeds(self, seed):
         return [2 * seed] if self.fallback else [2 * seed, 2 * seed + 1]
 
-    def render_stream(self, seeds, on_frame=None):
-        """The frames of `seeds` in order, pipelined on the current stream: frame i's
-        fusion runs while frame i+1 renders (the render is enqueued in two halves,
-        Batch.render_begin / render_end, and the fusion goes between them).  Each
-        frame equals render(seed) bitwise.  on_frame(k, out) is called once frame k's
+    def render_stream(self, seeds, on_frame=None, in_flight=2):
+        """The frames of `seeds` in order, pipelined on the current stream
+        (pipeline_frames): with in_flight=2 (a second batch, made on first use)
+        frame k+1 renders while frame k's last paths finish and while frame k is
+        fused; with 1, frame k's fusion runs while frame k+1 renders.  Each frame
+        equals render(seed) bitwise.  on_frame(k, out) is called once frame k's
         output is enqueued (work it enqueues on the stream sees that frame)."""
         seeds = list(seeds)
-        if not seeds:
+        if self.fallback:  # no fusion: plain renders one after the other
+            for k, sd in enumerate(seeds):
+                self.render(sd)
+                if on_frame is not None:
+                    on_frame(k, self.out)
             return self.out
-        self.batch.set_seeds(self._seeds(seeds[0]))
-        self.batch.render_begin()
-        for k in range(len(seeds)):
-            self.batch.render_end()
-            if k + 1 < len(seeds):
-                # frame k+1's wavefront starts now; it writes the batch's outputs
-                # only at its render_end, after the fusion below has read them
-                self.batch.set_seeds(self._seeds(seeds[k + 1]))
-                self.batch.render_begin()
-            if not self.fallback:
-                self._fuse()
-            if on_frame is not None:
-                on_frame(k, self.out)
+        while len(self.slots) < in_flight:
+            self.slots.append(_Slot(*self._args, self.layers))
+        slots = self.slots[:in_flight]
+        pipeline_frames([sl.batch for sl in slots], self._seeds,
+                        [lambda sl=sl: self._fuse(sl) for sl in slots], seeds,
+                        on_frame=None if on_frame is None else
+                        (lambda k: on_frame(k, self.out)))
+        if seeds:
+            self._use(slots[(len(seeds) - 1) % len(slots)])
         return self.out
 
     def close(self):
-        self.batch.close()
+        if self.fallback:
+            self.batch.close()
+            return
+        for sl in self.slots:
+            sl.batch.close()
 
 
 def hybrid_frame(gs, net: FusionNet | None, W, H, seed, spp_h=4, spp_l=64, depth=DEPTH,

@@ -173,7 +173,8 @@ def profile_read():
 
 
 TUNING_KEYS = ("chunk_paths", "trace_blocks", "schedule", "bvh_leaf_max", "streams", "tail_bounce",
-               "bvh_builder", "conv_small_tiles", "queue_sort", "bvh_quantized")
+               "bvh_builder", "conv_small_tiles", "queue_sort", "bvh_quantized", "wave_extend",
+               "wave_shadow")
 BVH_BUILDERS = {"lbvh": 0, "ploc": 1}
 
 
@@ -185,17 +186,19 @@ def get_tuning():
 
 def set_tuning(chunk_paths=None, trace_blocks=None, schedule=None, bvh_leaf_max=None,
                streams=None, tail_bounce=None, bvh_builder=None, conv_small_tiles=None,
-               queue_sort=None, bvh_quantized=None):
+               queue_sort=None, bvh_quantized=None, wave_extend=None, wave_shadow=None):
     """bvh_builder: 0 / "lbvh" (Karras) or 1 / "ploc" (clustering, the default);
     conv_small_tiles: the network's 3x3 convs with fewer 16x16 output tiles than
-    this run on the small-tile plan (0: never)."""
+    this run on the small-tile plan (0: never); wave_extend / wave_shadow: the
+    bounces below these trace their closest-hit / shadow rays a wave at a time."""
     cur = get_tuning()
     if isinstance(bvh_builder, str):
         bvh_builder = BVH_BUILDERS[bvh_builder]
     new = dict(chunk_paths=chunk_paths, trace_blocks=trace_blocks, schedule=schedule,
                bvh_leaf_max=bvh_leaf_max, streams=streams, tail_bounce=tail_bounce,
                bvh_builder=bvh_builder, conv_small_tiles=conv_small_tiles,
-               queue_sort=queue_sort, bvh_quantized=bvh_quantized)
+               queue_sort=queue_sort, bvh_quantized=bvh_quantized, wave_extend=wave_extend,
+               wave_shadow=wave_shadow)
     t = L.Tuning()
     for k in TUNING_KEYS:
         setattr(t, k, int(new[k] if new[k] is not None else cur[k]))
@@ -293,6 +296,13 @@ class Batch:
         hold the previous render's values until render_end() (same stream)."""
         L.use_current_stream()
         L.check(L.lib().mrs_batch_render_begin(self.handle))
+
+    def render_fork(self):
+        """Marks the start of the next render on the current stream ahead of its
+        launches (mrs_batch_render_fork): work enqueued before the following
+        render_begin runs beside that render.  Set seeds before forking."""
+        L.use_current_stream()
+        L.check(L.lib().mrs_batch_render_fork(self.handle))
 
     def render_end(self):
         L.use_current_stream()

@@ -64,6 +64,34 @@ def test_batch_matches_single_renders_bitwise(torch_cuda, chunk, schedule):
         mrs.set_tuning(**old)
 
 
+
+@pytest.mark.parametrize("schedule", [0, 1])
+def test_wave_traversal_batch_matches_lane_traversal(torch_cuda, schedule):
+    """Every bounce's closest-hit and shadow rays traced a wave at a time: the
+    batch's outputs equal single renders traced lane by lane, bitwise.  The jobs'
+    path counts put waves across two scenes (lanes of a wave walk different trees),
+    and the later bounces hold incoherent rays (waves whose lanes enter few common
+    nodes)."""
+    import paper_2106_12802_amd as mrs
+    old = mrs.get_tuning()
+    try:
+        jobs = _jobs(mrs)
+        mrs.set_tuning(wave_extend=0, wave_shadow=0, schedule=schedule)
+        singles = [_single(mrs, j) for j in jobs]
+        mrs.counters(reset=True)
+        mrs.set_tuning(wave_extend=65, wave_shadow=65, tail_bounce=65)
+        b = mrs.Batch(jobs)
+        b.render()
+        torch_cuda.cuda.synchronize()
+        for j, (rgb, aux), (r1, a1) in zip(jobs, b.outputs, singles):
+            assert torch_cuda.equal(rgb, r1), j
+            if aux is not None:
+                assert torch_cuda.equal(aux, a1), j
+        c = mrs.counters(reset=True)
+        assert c["overflows"] == 0 and c["nonfinite"] == 0
+    finally:
+        mrs.set_tuning(**old)
+
 def test_batch_set_seeds_matches_single_renders(torch_cuda):
     import paper_2106_12802_amd as mrs
     jobs = _jobs(mrs)[:3]
@@ -172,8 +200,9 @@ def test_concurrent_streams_and_batch_tuning_snapshot(torch_cuda):
 
 def test_full_size_render_invariant_to_tuning(torch_cuda):
     """A 1280x720x4 render of the 101k-triangle scene is bitwise the same for every
-    sub-chunk count, chunk size, grid size, schedule and path-tail bounce (the result
-    must not depend on which rays share a wave, nor on which kernel traces a bounce)."""
+    sub-chunk count, chunk size, grid size, schedule, path-tail bounce and wave
+    traversal (the result must not depend on which rays share a wave, nor on which
+    kernel traces a bounce)."""
     import paper_2106_12802_amd as mrs
     torch = torch_cuda
     gs = mrs.GpuScene(S.procedural(7))
@@ -185,7 +214,9 @@ def test_full_size_render_invariant_to_tuning(torch_cuda):
         for tune in (dict(streams=3), dict(streams=2, chunk_paths=1 << 20),
                      dict(streams=3, trace_blocks=1000, schedule=1),
                      dict(streams=1, chunk_paths=777777, trace_blocks=3000),
-                     dict(tail_bounce=1), dict(tail_bounce=2), dict(tail_bounce=65)):
+                     dict(tail_bounce=1), dict(tail_bounce=2), dict(tail_bounce=65),
+                     dict(wave_extend=1, wave_shadow=1),
+                     dict(wave_extend=3, wave_shadow=3, schedule=1, trace_blocks=700)):
             mrs.set_tuning(**dict(old, **tune))
             img, aux = mrs.render(gs, 1280, 720, 4, 8, 99)
             torch.cuda.synchronize()
@@ -315,24 +346,79 @@ def test_split_render_matches_render(torch_cuda, chunk):
     b.close()
 
 
-def test_pipelined_frames_equal_single_frames(torch_cuda):
-    """HybridFrame.render_stream (frame k's fusion overlapping frame k+1's render)
-    gives every frame bitwise as render(seed); also for the no-network fallback."""
+
+@pytest.mark.parametrize("chunk", [None, 3000])
+def test_render_fork_keeps_results(torch_cuda, chunk):
+    """render_fork marks the next render's start ahead of its launches: fork, other
+    work on the stream, begin, end equals render bitwise (one super-chunk or
+    several); seeds set after a fork undo it; a fork while a render is begun is an
+    error with no effect."""
+    import paper_2106_12802_amd as mrs
+    from paper_2106_12802_amd._lib import MrsError
+    torch = torch_cuda
+    old = mrs.get_tuning()
+    try:
+        if chunk:
+            mrs.set_tuning(chunk_paths=chunk, trace_blocks=16)
+        jobs = _jobs(mrs)[:3]
+        b = mrs.Batch(jobs)
+    finally:
+        mrs.set_tuning(**old)
+    seeds_a, seeds_b = [31, 32, 33], [41, (1 << 35) + 42, 43]
+    b.set_seeds(seeds_a)
+    b.render()
+    torch.cuda.synchronize()
+    ref_a = [o[0].clone() for o in b.outputs]
+    b.set_seeds(seeds_b)
+    b.render()
+    torch.cuda.synchronize()
+    ref_b = [o[0].clone() for o in b.outputs]
+    # fork, unrelated work on the stream, begin, end
+    b.set_seeds(seeds_a)
+    b.render_fork()
+    scratch = torch.randn(1 << 20, device="cuda")
+    scratch.mul_(2.0)
+    b.render_begin()
+    with pytest.raises(MrsError, match="not ended"):
+        b.render_fork()
+    b.render_end()
+    torch.cuda.synchronize()
+    for got, r in zip(b.outputs, ref_a):
+        assert torch.equal(got[0], r)
+    # seeds after the fork: the render uses them
+    b.render_fork()
+    b.set_seeds(seeds_b)
+    b.render()
+    torch.cuda.synchronize()
+    for got, r in zip(b.outputs, ref_b):
+        assert torch.equal(got[0], r)
+    b.close()
+
+@pytest.mark.parametrize("in_flight", [1, 2])
+def test_pipelined_frames_equal_single_frames(torch_cuda, in_flight):
+    """HybridFrame.render_stream (frame k+1 rendering while frame k finishes and is
+    fused; one or two frames in flight) gives every frame bitwise as render(seed);
+    also for the network that reads the render layers and for the no-network
+    fallback.  Afterwards the frame's images are the last frame's."""
     import paper_2106_12802_amd as mrs
     from paper_2106_12802_amd import hybrid as HY
     torch = torch_cuda
     gs = mrs.GpuScene(S.procedural(7, spheres=((2, 4),), n_boxes=5, n_lights=2))
     seeds = [3, 11, 5, 8, 2]
-    for net in (mrs.FusionNet(seed=4), None):
+    for net in (mrs.FusionNet(seed=4), mrs.FusionNet(seed=6, arch="res16_layers"), None):
         fr = HY.HybridFrame(gs, net, 320, 192)
         refs = [fr.render(sd).clone() for sd in seeds]
+        last_hr = None if net is None else fr.hr_rgb.clone()
         got = []
-        fr.render_stream(seeds, on_frame=lambda k, out: got.append(out.clone()))
+        fr.render_stream(seeds, on_frame=lambda k, out: got.append(out.clone()),
+                         in_flight=in_flight)
         torch.cuda.synchronize()
         assert len(got) == len(seeds)
         for k, (a, r) in enumerate(zip(got, refs)):
             assert torch.equal(a, r), (net is None, k)
-        fr.render_stream([])
+        if net is not None:
+            assert torch.equal(fr.hr_rgb, last_hr)
+        fr.render_stream([], in_flight=in_flight)
         fr.close()
 
 

@@ -450,15 +450,18 @@ def test_window_is_crop_and_chunking_invariant(mrs, torch_cuda):
 
 def test_queue_order_and_node_format_do_not_change_the_image(mrs, torch_cuda):
     """Ordering each block's appended rays by direction octant and its shadow rays by
-    light (queue_sort) changes which rays share a wave, and the quantized BVH4 nodes
-    (bvh_quantized) which boxes a ray visits, not any result: the full HRLS render of
-    the bench scene, with features and render layers, is bitwise the same."""
+    light (queue_sort) changes which rays share a wave, the quantized BVH4 nodes
+    (bvh_quantized) which boxes a ray visits, and the wave traversal (wave_extend,
+    wave_shadow) the order and company in which rays walk the tree, not any result:
+    the full HRLS render of the bench scene, with features and render layers, is
+    bitwise the same."""
     gs = mrs.GpuScene(S.procedural(7))
     old = mrs.get_tuning()
     outs = []
     try:
-        for qs, qn in ((0, 0), (1, 0), (0, 1), (1, 1)):
-            mrs.set_tuning(queue_sort=qs, bvh_quantized=qn)
+        for qs, qn, we, wsh in ((0, 0, 0, 0), (1, 0, 0, 0), (0, 1, 0, 0), (1, 1, 0, 0),
+                                (1, 0, 1, 1), (1, 1, 3, 0), (0, 0, 0, 3)):
+            mrs.set_tuning(queue_sort=qs, bvh_quantized=qn, wave_extend=we, wave_shadow=wsh)
             lay = torch_cuda.empty(720, 1280, 9, device="cuda")
             rgb, aux = mrs.render(gs, 1280, 720, 4, 8, 14, out_layers=lay)
             torch_cuda.cuda.synchronize()
