@@ -317,6 +317,7 @@ __device__ __forceinline__ TraceView lane_view(const SceneView& sv) {
 // One ray as handed to the traversal.
 struct RayIn {
   TraceView sc;
+  uint32_t job;  // the ray's job (its scene is the job's)
   f3 o, d;
   uint32_t x0, x1, x2;  // excluded primitives
   float tmax;           // shadow rays: distance to the light point; else infinity
@@ -682,20 +683,22 @@ __device__ __forceinline__ void trace_wave(IO& io, uint32_t base, uint32_t n, Wa
     inv = F3(safe_rcp(r.d.x), safe_rcp(r.d.y), safe_rcp(r.d.z));
     oi = mul(r.o, inv);
   }
-  uint64_t todo = __ballot(live && r.sc.ntris > 0);
+  uint64_t todo = __ballot(live);
   while (todo) {
-    // the scene of the first lane left (lanes of a wave may trace different scenes)
-    const uint32_t l0 = (uint32_t)__builtin_ctzll(todo);
-    TraceView sc;
-    sc.nodes = (const gfloat4*)(uintptr_t)rdlane64((uint64_t)(uintptr_t)r.sc.nodes, l0);
-    sc.nodes_q = nullptr;
-    sc.leaf_tri = (const gfloat4*)(uintptr_t)rdlane64((uint64_t)(uintptr_t)r.sc.leaf_tri, l0);
-    sc.root = rdlane(r.sc.root, l0);
-    sc.nnodes = rdlane(r.sc.nnodes, l0);
-    sc.ntris = (int32_t)rdlane((uint32_t)r.sc.ntris, l0);
-    const uint64_t grp = __ballot(live && r.sc.nodes == sc.nodes) & todo;
+    // the lanes of the first lane's job (lanes of a wave may trace different
+    // scenes); the scene is read from the job table with wave-uniform loads
+    const uint32_t j0 = rdlane(r.job, (uint32_t)__builtin_ctzll(todo));
+    const uint64_t grp = __ballot(live && r.job == j0) & todo;
     todo &= ~grp;
-    wave_walk<ANY>(sc, grp, r, inv, oi, ts, occluded, ws);
+    const SceneView& sv = io.jobs[j0].sv;
+    TraceView sc;
+    sc.nodes = (const gfloat4*)(uintptr_t)sv.nodes;
+    sc.nodes_q = nullptr;
+    sc.leaf_tri = (const gfloat4*)(uintptr_t)sv.leaf_tri;
+    sc.root = sv.root;
+    sc.nnodes = sv.nnodes;
+    sc.ntris = sv.ntris;
+    if (sc.ntris > 0) wave_walk<ANY>(sc, grp, r, inv, oi, ts, occluded, ws);
   }
   RayIn next;
   if (live) (void)io.store(qi, ts, occluded, next);
@@ -860,7 +863,8 @@ struct ExtendIO {
   __device__ __forceinline__ void load(uint32_t qi, RayIn& r) const {
     const float4 R0 = rays[2 * qi], R1 = rays[2 * qi + 1];
     const uint32_t tag = __float_as_uint(R1.w);
-    r.sc = lane_view(jobs[job_of(tag)].sv);
+    r.job = job_of(tag);
+    r.sc = lane_view(jobs[r.job].sv);
     r.o = xyz(R0);
     r.d = xyz(R1);
     r.x0 = unpack_prim(tag);
@@ -1202,7 +1206,8 @@ struct ShadowIO {
     const float4 S0 = shadow[3 * qi], S1 = shadow[3 * qi + 1];
     const uint32_t li = __float_as_uint(S0.w) >> 24;
     const uint32_t ptag = __float_as_uint(shadow[3 * qi + 2].w);
-    const SceneView& sv = jobs[job_of(ptag)].sv;
+    r.job = job_of(ptag);
+    const SceneView& sv = jobs[r.job].sv;
     const DevLight& lt = sv.lights[li];
     r.sc = lane_view(sv);
     r.o = xyz(S0);
@@ -1305,6 +1310,7 @@ struct PathIO {
   bool cont, in_shadow;
 
   __device__ __forceinline__ void closest(RayIn& r, f3 ro, f3 rd, uint32_t origin) {
+    r.job = j;
     r.sc = lane_view(jobs[j].sv);
     r.o = o = ro;
     r.d = d = rd;
@@ -1343,6 +1349,7 @@ struct PathIO {
       next_prim = v.prim;
       if (v.shad) {
         const DevLight& lt = jobs[j].sv.lights[v.li];
+        r.job = j;
         r.sc = lane_view(jobs[j].sv);
         r.o = v.x;
         r.d = v.swi;
