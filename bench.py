@@ -903,6 +903,8 @@ def main():
                     help="tuning: order appended rays by octant / shadow rays by light")
     ap.add_argument("--conv-small-tiles", type=int, default=None,
                     help="tuning: 3x3 convs with fewer 16x16 output tiles run the small-tile plan")
+    ap.add_argument("--net-fused-blocks", type=int, default=None, choices=(0, 1),
+                    help="tuning: the network trunk's residual blocks as one kernel each")
     ap.add_argument("--frames-in-flight", type=int, default=2, choices=(1, 2),
                     help="frames the timed frame stream keeps in flight")
     ap.add_argument("--wave-extend", type=int, default=None,
@@ -948,7 +950,8 @@ def main():
     R.set_tuning(args.chunk_paths, args.trace_blocks, args.schedule, args.leaf_max, args.streams,
                  args.tail_bounce, args.bvh_builder, queue_sort=args.queue_sort,
                  bvh_quantized=args.bvh_quantized, wave_extend=args.wave_extend,
-                 wave_shadow=args.wave_shadow, conv_small_tiles=args.conv_small_tiles)
+                 wave_shadow=args.wave_shadow, conv_small_tiles=args.conv_small_tiles,
+                 net_fused_blocks=args.net_fused_blocks)
     tuning = R.get_tuning()
     log(f"[bench] tuning {tuning}")
     scene = S.procedural(SCENE_SEED)

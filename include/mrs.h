@@ -360,6 +360,10 @@ typedef struct mrs_tuning {
                            loads, stack and child order shared by the wave),
                            the rest lane by lane.  Same hits */
   int32_t wave_shadow;  /* 0..65 (default 0): the same for shadow rays */
+  int32_t net_fused_blocks; /* 1 (default): each residual block of the 16-block
+                           network's trunk runs as one kernel (both convs, the
+                           intermediate kept in LDS); 0: two conv launches.
+                           Bitwise the same */
 } mrs_tuning;
 mrs_status mrs_get_tuning(mrs_tuning* out);
 mrs_status mrs_set_tuning(const mrs_tuning* t);
@@ -579,9 +583,10 @@ mrs_status mrs_debug_net_activation(const mrs_net* net, int32_t which, float* ou
  * reconstruction convs); [6] / [7] the direct implicit-GEMM conv (64 / 16
  * output channels per block: the 1x1 fuse conv and shapes the LDS kernels do
  * not take); [8] / [9] the data-gradient convs of training on the LDS conv
- * (16x8 / 16x16 tiles; the others run a direct implicit GEMM, not counted).
- * reset != 0 clears the counts after reading them. */
-#define MRS_NUM_CONV_KINDS 10
+ * (16x8 / 16x16 tiles; the others run a direct implicit GEMM, not counted);
+ * [10] a residual block of the trunk as one kernel (two 3x3 convs, counted
+ * once).  reset != 0 clears the counts after reading them. */
+#define MRS_NUM_CONV_KINDS 11
 mrs_status mrs_debug_conv_launches(int64_t out[MRS_NUM_CONV_KINDS], int32_t reset);
 
 /* Philox4x32-10 on the device: out_dev[4i..4i+3] = philox(ctr_dev[4i..4i+3],

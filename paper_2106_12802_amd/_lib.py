@@ -83,7 +83,8 @@ class Tuning(C.Structure):
                 ("bvh_leaf_max", C.c_int32), ("streams", C.c_int32), ("tail_bounce", C.c_int32),
                 ("bvh_builder", C.c_int32), ("conv_small_tiles", C.c_int32),
                 ("queue_sort", C.c_int32), ("bvh_quantized", C.c_int32),
-                ("wave_extend", C.c_int32), ("wave_shadow", C.c_int32)]
+                ("wave_extend", C.c_int32), ("wave_shadow", C.c_int32),
+                ("net_fused_blocks", C.c_int32)]
 
 
 assert C.sizeof(Material) == 32 and C.sizeof(QuadLight) == 56

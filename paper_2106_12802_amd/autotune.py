@@ -7,7 +7,8 @@ without measuring.  The search is a grid over the primary launch shape
 (resident paths x traversal grid x queue schedule) followed by one pass over
 each secondary knob with the rest held at the best so far: sub-chunk streams,
 the first bounce traced path by path, the ordering of appended rays, the BVH
-node format, the bounces traced a wave at a time, and the network conv tile plan.
+node format, the bounces traced a wave at a time, the network conv tile plan
+and the fused residual blocks.
 """
 from __future__ import annotations
 
@@ -23,9 +24,9 @@ SCHEDULES = (0, 1)
 SECONDARY = (("streams", (1, 2, 3, 4)), ("tail_bounce", (2, 3, 4, 5)),
              ("queue_sort", (0, 1)), ("bvh_quantized", (0, 1)),
              ("wave_extend", (0, 1, 2)), ("wave_shadow", (0, 1, 2)),
-             ("conv_small_tiles", (0, 64, 128, 256)))
+             ("conv_small_tiles", (0, 64, 128, 256)), ("net_fused_blocks", (0, 1)))
 KEYS = ("chunk_paths", "trace_blocks", "schedule", "streams", "tail_bounce", "queue_sort",
-        "bvh_quantized", "wave_extend", "wave_shadow", "conv_small_tiles")
+        "bvh_quantized", "wave_extend", "wave_shadow", "conv_small_tiles", "net_fused_blocks")
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "mrs_autotune.json")
 
 

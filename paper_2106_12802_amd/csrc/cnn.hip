@@ -443,6 +443,167 @@ __global__ __launch_bounds__(32 * TH) void k_conv3_lds(ConvArgs p, int cout_p, i
   }
 }
 
+// One residual block of the trunk in one launch: for a 16 x 16 output tile,
+// y = res + res_scale convB(ReLU(convA(x))) (+ res2), convA and convB 3x3 convs
+// of 64 channels.  The block stages x with a halo of 2, computes convA on the
+// 18 x 18 pixels convB needs (halo recompute: 21 M tiles of 16 pixels instead
+// of 16), keeps ReLU(convA) as BF16 in LDS -- zero outside the image, which is
+// convB's zero padding -- and runs convB on it; convB's weights are loaded into
+// registers during convA.  The intermediate is rounded to BF16 as the two-conv
+// path stores it and every output element sums its K in the same order, so the
+// result is bitwise that of convA then convB as two k_conv3_lds launches, less
+// one launch and the intermediate's round trip through memory.
+constexpr int RB_T = 16;          // output tile
+constexpr int RB_IN = RB_T + 4;   // input tile rows / columns (halo of both convs)
+constexpr int RB_MID = RB_T + 2;  // convA outputs = convB's input tile
+constexpr int RB_C = 64;          // channels in and out of both convs
+constexpr int RB_PITCH = RB_C + 8;
+constexpr int RB_KP = 9 * RB_C;
+constexpr int RB_WPITCH = RB_C + 1;  // 16-byte chunks per weight row
+constexpr int RB_MIDT = (RB_MID * RB_MID + 15) / 16;  // convA's M tiles (21)
+constexpr int RB_THREADS = 512;                      // 8 waves
+constexpr int RB_MQ = (RB_MIDT + 7) / 8;             // convA M tiles per wave (3)
+
+__global__ __launch_bounds__(RB_THREADS) void k_res_block(ConvArgs pa, ConvArgs pb) {
+  __shared__ __attribute__((aligned(16))) uint16_t tile[RB_IN * RB_IN * RB_PITCH];
+  __shared__ __attribute__((aligned(16))) uint16_t wts[(RB_KP / 8) * RB_WPITCH * 8];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int kq = lane >> 4, li = lane & 15;
+  const int x0 = blockIdx.x * RB_T, y0 = blockIdx.y * RB_T, b = blockIdx.z;
+  constexpr int TCH = RB_IN * RB_IN * (RB_C / 8), WCH = RB_C * (RB_KP / 8);
+  constexpr int WPT = WCH / RB_THREADS;  // weight chunks per thread (9)
+  static_assert(WCH % RB_THREADS == 0, "weights split evenly over the threads");
+  // input tile, 4 chunks in flight per thread
+  for (int i = tid; i < TCH; i += 4 * RB_THREADS) {
+    bf16x8 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int ii = i + u * RB_THREADS, px = ii >> 3, c = (ii & 7) * 8;
+      const int ty = px / RB_IN, tx = px - ty * RB_IN;
+      v[u] = ii < TCH ? view_chunk(pa, b, y0 - 2 + ty, x0 - 2 + tx, c) : zero8();
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int ii = i + u * RB_THREADS;
+      if (ii < TCH) *reinterpret_cast<bf16x8*>(tile + (ii >> 3) * RB_PITCH + (ii & 7) * 8) = v[u];
+    }
+  }
+  // weights of chunk i: row n = i / (KP / 8), 16-byte chunk kc; LDS [kc][n][8]
+  auto w_load = [&](const ConvArgs& p, int i) -> uint4 {
+    const int n = i / (RB_KP / 8), kc = i - n * (RB_KP / 8);
+    return *reinterpret_cast<const uint4*>(p.w + (size_t)n * p.kp + kc * 8);
+  };
+  auto w_store = [&](int i, uint4 v) {
+    const int n = i / (RB_KP / 8), kc = i - n * (RB_KP / 8);
+    *reinterpret_cast<uint4*>(wts + (kc * RB_WPITCH + n) * 8) = v;
+  };
+  {
+    uint4 v[WPT];
+#pragma unroll
+    for (int u = 0; u < WPT; ++u) v[u] = w_load(pa, tid + u * RB_THREADS);
+#pragma unroll
+    for (int u = 0; u < WPT; ++u) w_store(tid + u * RB_THREADS, v[u]);
+  }
+  __syncthreads();
+  // convB's weights, in flight while convA runs
+  uint4 wb[WPT];
+#pragma unroll
+  for (int u = 0; u < WPT; ++u) wb[u] = w_load(pb, tid + u * RB_THREADS);
+  // convA: wave w takes M tiles w, w + 8, w + 16 of the 18 x 18 intermediate
+  // pixels in row-major order; lane li holds pixel 16 t + li of the A operand
+  f32x4 acc[RB_MQ][4];
+  int pofs[RB_MQ];
+#pragma unroll
+  for (int q = 0; q < RB_MQ; ++q) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[q][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int pix = 16 * (wave + 8 * q) + li;
+    const int iy = pix / RB_MID, ix = pix - iy * RB_MID;
+    pofs[q] = pix < RB_MID * RB_MID ? (iy * RB_IN + ix) * RB_PITCH : -1;
+  }
+  for (int ks = 0; ks < RB_KP; ks += 32) {
+    const int k = ks + kq * 8;
+    const int tap = k / RB_C, c = k - tap * RB_C;
+    const int dy = tap / 3, dx = tap - dy * 3;
+    const int tofs = (dy * RB_IN + dx) * RB_PITCH + c;
+    bf16x8 Bv[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) Bv[j] = ld8(wts + (((ks >> 3) + kq) * RB_WPITCH + j * 16 + li) * 8);
+#pragma unroll
+    for (int q = 0; q < RB_MQ; ++q) {
+      if (wave + 8 * q >= RB_MIDT) continue;  // wave-uniform
+      const bf16x8 A = pofs[q] >= 0 ? ld8(tile + pofs[q] + tofs) : zero8();
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        acc[q][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, Bv[j], acc[q][j], 0, 0, 0);
+    }
+  }
+  // ReLU(convA + bias) as BF16, zero outside the image and past the 18 x 18
+  uint16_t hv[RB_MQ][4][4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const float bias = pa.bias[j * 16 + li];
+#pragma unroll
+    for (int q = 0; q < RB_MQ; ++q)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int pix = 16 * (wave + 8 * q) + kq * 4 + v;
+        const int iy = pix / RB_MID, ix = pix - iy * RB_MID;
+        const int y = y0 - 1 + iy, x = x0 - 1 + ix;
+        const bool in = pix < RB_MID * RB_MID && y >= 0 && y < pa.H && x >= 0 && x < pa.W;
+        hv[q][j][v] = in ? f2bf(fmaxf(acc[q][j][v] + bias, 0.0f)) : (uint16_t)0;
+      }
+  }
+  __syncthreads();  // convA's operands are no longer read
+#pragma unroll
+  for (int q = 0; q < RB_MQ; ++q) {
+    if (wave + 8 * q >= RB_MIDT) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int pix = 16 * (wave + 8 * q) + kq * 4 + v;
+      if (pix >= RB_MID * RB_MID) continue;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) tile[pix * RB_PITCH + j * 16 + li] = hv[q][j][v];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < WPT; ++u) w_store(tid + u * RB_THREADS, wb[u]);
+  __syncthreads();
+  // convB on the 16 x 16 tile: wave w computes rows 2w and 2w + 1
+  f32x4 acc2[2][4];
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc2[r][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int ks = 0; ks < RB_KP; ks += 32) {
+    const int k = ks + kq * 8;
+    const int tap = k / RB_C, c = k - tap * RB_C;
+    const int dy = tap / 3, dx = tap - dy * 3;
+    bf16x8 A[2], Bv[4];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+      A[r] = ld8(tile + ((2 * wave + r + dy) * RB_MID + li + dx) * RB_PITCH + c);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) Bv[j] = ld8(wts + (((ks >> 3) + kq) * RB_WPITCH + j * 16 + li) * 8);
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        acc2[r][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[r], Bv[j], acc2[r][j], 0, 0, 0);
+  }
+  int64_t m[2][4];
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int y = y0 + 2 * wave + r, x = x0 + kq * 4 + v;
+      m[r][v] = (y < pb.H && x < pb.W) ? ((int64_t)b * pb.H + y) * pb.W + x : -1;
+    }
+  EpiIn<4> in;
+  epi_load<4>(pb, m, 0, li, in);
+  conv_epilogue<4>(pb, acc2, m, 0, li, in);
+}
+
 // Runs the conv on k_conv3_lds<CINP, NT, TH> if its shape fits: cin_p == CINP,
 // or (CINP = 64) a multiple of it taken in chunks; packed K = 9 cin_p rounded up
 // to 32; cout_p a multiple of nsplit channel groups of 16 NT.  The output
@@ -1126,6 +1287,20 @@ void launch_adam(float* w, const float* g, float* m, float* v, int64_t n, float 
 void conv_launch_counts(int64_t* out, bool reset) {
   for (int i = 0; i < MRS_NUM_CONV_KINDS; ++i)
     out[i] = reset ? g_conv_launches[i].exchange(0) : g_conv_launches[i].load();
+}
+
+bool launch_res_block(const ConvArgs& a, const ConvArgs& b, hipStream_t st) {
+  const auto fits = [](const ConvArgs& p) {
+    return p.mode == VIEW_PLAIN && p.taps == 9 && p.cin_p == RB_C && p.kp == RB_KP &&
+           p.cout == RB_C;
+  };
+  if (!fits(a) || !fits(b) || a.ca < RB_C || !a.relu || a.B != b.B || a.H != b.H ||
+      a.W != b.W)
+    return false;
+  k_res_block<<<dim3((a.W + RB_T - 1) / RB_T, (a.H + RB_T - 1) / RB_T, a.B), RB_THREADS, 0,
+                st>>>(a, b);
+  count_conv(10);
+  return true;
 }
 
 void launch_conv(const ConvArgs& a, int cout_p, hipStream_t st) {

@@ -168,6 +168,10 @@ mrs_status arena_carve(char*& base, size_t& cap, std::vector<std::pair<void**, s
                        hipStream_t st, const char* what);
 
 void launch_conv(const ConvArgs& a, int cout_p, hipStream_t st);
+// a then b as one residual block (k_res_block) when both are 3x3 64 -> 64
+// convs over the same plain BF16 input grid and a has the ReLU; false (nothing
+// launched) otherwise.
+bool launch_res_block(const ConvArgs& a, const ConvArgs& b, hipStream_t st);
 void launch_prep(const mrs_net* net, int64_t nhr, int64_t nlr, const float* hr, const float* aux,
                  const float* lr, uint16_t* xh, uint16_t* xl, hipStream_t st);
 void launch_init(float* dst, const NetLayer& L, uint64_t seed, hipStream_t st);

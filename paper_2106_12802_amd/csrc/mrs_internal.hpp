@@ -178,6 +178,7 @@ mrs_status get_counters(int64_t* out, bool reset, hipStream_t st);
 void get_tuning(mrs_tuning* t);
 mrs_status set_tuning(const mrs_tuning* t);
 int conv_small_tiles();  // mrs_tuning.conv_small_tiles in force
+int net_fused_blocks();  // mrs_tuning.net_fused_blocks in force
 // Launches of each network conv kernel instance since the last reset (host
 // counters, in the order of mrs_debug_conv_launches).
 void conv_launch_counts(int64_t* out, bool reset);

@@ -259,7 +259,6 @@ mrs_status net_forward(mrs_net* net, int B, int H, int W, const float* hr, const
     a.relu = 1;
     a.out_h = A.th;
     a.out_h_stride = NET_FEAT;
-    launch_conv(a, La.cout_p, st);
     ConvArgs bb = base_args(net, Lb, B, h, w);
     bb.a = A.th;
     bb.ca = NET_FEAT;
@@ -270,7 +269,12 @@ mrs_status net_forward(mrs_net* net, int B, int H, int W, const float* hr, const
     bb.out_f_stride = NET_FEAT;
     bb.out_h = A.rh[i & 1];
     bb.out_h_stride = NET_FEAT;
-    launch_conv(bb, Lb.cout_p, st);
+    // both convs in one launch (bitwise the same), or one after the other
+    // through the BF16 intermediate A.th
+    if (!(net_fused_blocks() && launch_res_block(a, bb, st))) {
+      launch_conv(a, La.cout_p, st);
+      launch_conv(bb, Lb.cout_p, st);
+    }
     cur_f = A.rf[i & 1];
     cur_h = A.rh[i & 1];
   }

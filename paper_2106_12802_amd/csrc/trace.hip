@@ -1703,8 +1703,9 @@ hipStream_t g_sub[MAX_SUB] = {};
 int g_nsub = 0;
 unsigned long long* g_stats = nullptr;  // device counters shared by every stream
 // defaults: the fastest hybrid 720p frame measured with the clustered BVH
-mrs_tuning g_tune = {1 << 23, 8192, 0, 3, 3, 3, MRS_BVH_PLOC, 128, 1, 0, 1, 0};
+mrs_tuning g_tune = {1 << 23, 8192, 0, 3, 3, 3, MRS_BVH_PLOC, 128, 1, 0, 1, 0, 1};
 std::atomic<int> g_conv_small{128};  // g_tune.conv_small_tiles, read without the lock
+std::atomic<int> g_net_fused{1};      // g_tune.net_fused_blocks, read without the lock
 std::atomic<bool> g_count_work{false};
 
 template <typename T>
@@ -2409,12 +2410,16 @@ mrs_status set_tuning(const mrs_tuning* t) {
   if (t->wave_extend < 0 || t->wave_extend > 65 || t->wave_shadow < 0 || t->wave_shadow > 65)
     return fail(MRS_ERR_INVALID_ARGUMENT,
                 "mrs_set_tuning: wave_extend and wave_shadow must be in [0, 65]");
+  if (t->net_fused_blocks != 0 && t->net_fused_blocks != 1)
+    return fail(MRS_ERR_INVALID_ARGUMENT, "mrs_set_tuning: net_fused_blocks must be 0 or 1");
   std::lock_guard<std::mutex> lk(g_mu);
   g_tune = *t;
   g_conv_small = t->conv_small_tiles;
+  g_net_fused = t->net_fused_blocks;
   return MRS_OK;
 }
 
 int conv_small_tiles() { return g_conv_small.load(std::memory_order_relaxed); }
+int net_fused_blocks() { return g_net_fused.load(std::memory_order_relaxed); }
 
 }  // namespace mrs

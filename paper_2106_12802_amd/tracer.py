@@ -174,7 +174,7 @@ def profile_read():
 
 TUNING_KEYS = ("chunk_paths", "trace_blocks", "schedule", "bvh_leaf_max", "streams", "tail_bounce",
                "bvh_builder", "conv_small_tiles", "queue_sort", "bvh_quantized", "wave_extend",
-               "wave_shadow")
+               "wave_shadow", "net_fused_blocks")
 BVH_BUILDERS = {"lbvh": 0, "ploc": 1}
 
 
@@ -186,11 +186,13 @@ def get_tuning():
 
 def set_tuning(chunk_paths=None, trace_blocks=None, schedule=None, bvh_leaf_max=None,
                streams=None, tail_bounce=None, bvh_builder=None, conv_small_tiles=None,
-               queue_sort=None, bvh_quantized=None, wave_extend=None, wave_shadow=None):
+               queue_sort=None, bvh_quantized=None, wave_extend=None, wave_shadow=None,
+               net_fused_blocks=None):
     """bvh_builder: 0 / "lbvh" (Karras) or 1 / "ploc" (clustering, the default);
     conv_small_tiles: the network's 3x3 convs with fewer 16x16 output tiles than
     this run on the small-tile plan (0: never); wave_extend / wave_shadow: the
-    bounces below these trace their closest-hit / shadow rays a wave at a time."""
+    bounces below these trace their closest-hit / shadow rays a wave at a time;
+    net_fused_blocks: the network trunk's residual blocks run as one kernel each."""
     cur = get_tuning()
     if isinstance(bvh_builder, str):
         bvh_builder = BVH_BUILDERS[bvh_builder]
@@ -198,7 +200,7 @@ def set_tuning(chunk_paths=None, trace_blocks=None, schedule=None, bvh_leaf_max=
                bvh_leaf_max=bvh_leaf_max, streams=streams, tail_bounce=tail_bounce,
                bvh_builder=bvh_builder, conv_small_tiles=conv_small_tiles,
                queue_sort=queue_sort, bvh_quantized=bvh_quantized, wave_extend=wave_extend,
-               wave_shadow=wave_shadow)
+               wave_shadow=wave_shadow, net_fused_blocks=net_fused_blocks)
     t = L.Tuning()
     for k in TUNING_KEYS:
         setattr(t, k, int(new[k] if new[k] is not None else cur[k]))
@@ -206,7 +208,7 @@ def set_tuning(chunk_paths=None, trace_blocks=None, schedule=None, bvh_leaf_max=
 
 
 CONV_KINDS = ("lds64_small", "lds64_large", "lds16", "lds8", "lds80_narrow", "lds64_narrow",
-              "direct64", "direct16", "dgrad_lds_small", "dgrad_lds_large")
+              "direct64", "direct16", "dgrad_lds_small", "dgrad_lds_large", "res_block")
 
 
 def conv_launches(reset=False):

@@ -17,7 +17,8 @@ def test_grid_then_secondary_knobs(monkeypatch, tmp_path):
     searched with the others held; the result is applied and cached."""
     state = {"chunk_paths": 1 << 23, "trace_blocks": 8192, "schedule": 0, "bvh_leaf_max": 3,
              "streams": 3, "tail_bounce": 3, "bvh_builder": 1, "conv_small_tiles": 128,
-             "queue_sort": 1, "bvh_quantized": 0, "wave_extend": 0, "wave_shadow": 0}
+             "queue_sort": 1, "bvh_quantized": 0, "wave_extend": 0, "wave_shadow": 0,
+             "net_fused_blocks": 1}
     monkeypatch.setattr(autotune.T, "get_tuning", lambda: dict(state))
     monkeypatch.setattr(autotune.T, "set_tuning", lambda **kw: state.update(kw))
     monkeypatch.setattr(autotune, "_device_key", lambda: "fake")

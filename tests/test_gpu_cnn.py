@@ -99,6 +99,7 @@ def test_forward_parity_large_tile_plan(net, tuning_restored, B, H, W, small):
     from paper_2106_12802_amd.tracer import conv_launches
     mrs = tuning_restored
     import torch
+    mrs.set_tuning(net_fused_blocks=0)  # every trunk conv on its own (the fused blocks below)
     if small is not None:
         mrs.set_tuning(conv_small_tiles=small)
     lr_tiles = B * ((W // 4 + 15) // 16) * ((H // 4 + 15) // 16)
@@ -129,6 +130,16 @@ def test_forward_parity_large_tile_plan(net, tuning_restored, B, H, W, small):
     ran = conv_launches(reset=True)
     assert ran["lds64_small"] == 33 and ran["lds64_large"] == 0, ran
     assert torch.equal(out_small, out)
+    # each residual block as one kernel: the same sums, bitwise
+    mrs.set_tuning(net_fused_blocks=1)
+    out_fused = net.fuse(*t)
+    torch.cuda.synchronize()
+    ran = conv_launches(reset=True)
+    _log(f"  fused: conv instances {ran}")
+    assert ran["res_block"] == 16 and ran["lds64_large"] + ran["lds64_small"] == 1, ran
+    assert torch.equal(out_fused, out)
+    fdf_fused = net.activation(1, (B, H // 4, W // 4, 64))
+    assert np.array_equal(fdf_fused, fdf)
 
 
 def test_fuse_not_ready_and_validation(torch_cuda):
