@@ -329,15 +329,40 @@ __device__ __forceinline__ void dgrad_epilogue_plain(const BwdEpi& e, int cout,
       }
 }
 
+// LDS pitch of a tile pixel (BF16 channels): 16-byte reads of 8 consecutive
+// lanes (pixels) at this stride hit distinct banks; a multiple of 32 channels
+// needs 8 more (64: 72), other widths do not (80: 80, 16: 16, 8: 8).
+template <int CINP>
+constexpr int c3_pitch() {
+  return CINP % 32 == 0 ? CINP + 8 : CINP;
+}
+// LDS bytes of a k_conv3_lds instance (input tile and weights).
+template <int CINP, int NT, int TH>
+constexpr int c3_lds_bytes() {
+  constexpr int KP = (9 * CINP + 31) / 32 * 32;
+  return 2 * ((TH + 2) * (C3_W + 2) * c3_pitch<CINP>() + (KP / 8) * (16 * NT + 1) * 8);
+}
+// Waves per SIMD the compiler must leave registers for (a block of TH / 2
+// waves puts TH / 8 on each SIMD): two blocks per CU for the narrow convs (16
+// output channels: the reconstruction convs) when the LDS allows it -- they fit
+// in 128 VGPRs --, one block otherwise (the 64-channel instances need more
+// registers than two blocks leave them, and spill when forced).
+template <int CINP, int NT, int TH>
+constexpr int c3_min_waves() {
+  return (NT == 1 && c3_lds_bytes<CINP, NT, TH>() <= 80 * 1024 ? 2 : 1) *
+         (TH / 8 > 0 ? TH / 8 : 1);
+}
+
 template <int CINP, int NT, int TH, bool DG = false>
-__global__ __launch_bounds__(32 * TH) void k_conv3_lds(ConvArgs p, int cout_p, int nsplit,
-                                                       BwdEpi be) {
+__global__ __launch_bounds__(32 * TH, (c3_min_waves<CINP, NT, TH>())) void k_conv3_lds(
+    ConvArgs p, int cout_p, int nsplit, BwdEpi be) {
   constexpr int THREADS = 32 * TH;  // TH / 2 waves, two tile rows each
   constexpr int TILE = (TH + 2) * (C3_W + 2);
-  constexpr int PITCH = CINP + 8;
+  constexpr int PITCH = c3_pitch<CINP>();
   constexpr int KP = (9 * CINP + 31) / 32 * 32;
   constexpr int NG = 16 * NT;
   constexpr int WPITCH = NG + 1;  // 16-byte chunks per weight row (pad: conflict-free stores)
+  constexpr int LDS_ALL = c3_lds_bytes<CINP, NT, TH>();
   __shared__ __attribute__((aligned(16))) uint16_t tile[TILE * PITCH];
   __shared__ __attribute__((aligned(16))) uint16_t wts[(KP / 8) * WPITCH * 8];
   const int tid = threadIdx.x;
@@ -354,9 +379,8 @@ __global__ __launch_bounds__(32 * TH) void k_conv3_lds(ConvArgs p, int cout_p, i
   // A block whose LDS leaves room for no second block on its CU (more than
   // 80 KB) has 2 waves per SIMD, so registers are plentiful: 6 tile and 9
   // weight chunks in flight per thread; otherwise 3 and 3.
-  constexpr int LDS_BYTES = 2 * (TILE * PITCH + (KP / 8) * WPITCH * 8);
-  constexpr int C3_BATCH_T = LDS_BYTES > 80 * 1024 ? 6 : 3;
-  constexpr int C3_BATCH_W = LDS_BYTES > 80 * 1024 ? 9 : 3;
+  constexpr int C3_BATCH_T = LDS_ALL > 80 * 1024 ? 6 : 3;
+  constexpr int C3_BATCH_W = LDS_ALL > 80 * 1024 ? 9 : 3;
   for (int n0 = part * nper; n0 < (part + 1) * nper; n0 += NG) {
     f32x4 acc[2][NT];
 #pragma unroll
@@ -432,10 +456,9 @@ __global__ __launch_bounds__(32 * TH) void k_conv3_lds(ConvArgs p, int cout_p, i
         const int y = y0 + 2 * wave + r, x = x0 + kq * 4 + v;
         m[r][v] = (y < p.H && x < p.W) ? ((int64_t)b * p.H + y) * p.W + x : -1;
       }
-    if (DG)
+    if (DG) {
       dgrad_epilogue_plain<NT>(be, p.cout, acc, m, n0, li);
-    else
-    {
+    } else {
       EpiIn<NT> in;
       epi_load<NT>(p, m, n0, li, in);
       conv_epilogue<NT>(p, acc, m, n0, li, in);
