@@ -141,15 +141,17 @@ def pmc_summary(fetch_path, write_path, out_path):
     cf, cw = copy_value(fetch), copy_value(write)
     fs = COPY_BYTES / (cf * 1024.0) if cf else None
     ws = COPY_BYTES / (cw * 1024.0) if cw else None
-    ext = [k for k in fetch if "k_extend<false>" in k]
+    ext = [k for k in fetch if is_extend(k)]
     if not ext or fs is None or ws is None:
         raise SystemExit(f"pmc summary: missing kernels (extend {ext}, copy {cf}, {cw})")
-    k = ext[0]
-    f_kib = sum(fetch[k]) / len(fetch[k])
-    w_kib = sum(write.get(k, [0.0])) / max(len(write.get(k, [])), 1)
+    fv = [x for k in ext for x in fetch[k]]
+    wv = [x for k in ext for x in write.get(k, [])]
+    f_kib = sum(fv) / len(fv)
+    w_kib = sum(wv) / max(len(wv), 1)
     hbm = f_kib * 1024.0 * fs + w_kib * 1024.0 * ws
     lines = [
-        "# HBM traffic of k_extend<false> (closest-hit traversal), procedural scene seed 7",
+        "# HBM traffic per closest-hit launch (k_extend_wave at bounce 0 and k_extend<false,",
+        "# false> at bounces 1-2, averaged over their dispatches), procedural scene seed 7",
         "# (101,446 triangles, textured), 720p hybrid frame HRLS 1280x720@4 + LRHS 320x180@64",
         "# (max depth 8) + fusion network.",
         "# Made by (each pass its own process, run from the repository root):",
@@ -167,7 +169,7 @@ def pmc_summary(fetch_path, write_path, out_path):
         f"copy_write_kib = {cw:.1f}",
         f"fetch_scale = {fs:.4f}",
         f"write_scale = {ws:.4f}",
-        f"extend_dispatches = {len(fetch[k])}",
+        f"extend_dispatches = {len(fv)}",
         f"extend_fetch_kib_per_dispatch = {f_kib:.1f}",
         f"extend_write_kib_per_dispatch = {w_kib:.1f}",
         f"hbm_bytes_per_launch = {hbm:.0f}",
@@ -193,13 +195,24 @@ COUNTER_PASSES = {
             "SQ_BUSY_CYCLES GRBM_GUI_ACTIVE",
 }
 # kernel (a prefix of its demangled name, after the namespace) -> short name
-COUNTER_KERNELS = [("k_extend<false>", "k_extend"), ("k_shadow<false>", "k_shadow"),
-                   ("k_tail<false>", "k_tail"), ("k_shade", "k_shade"),
-                   ("k_conv3_lds<64, 4, 16>", "k_conv3_lds<64,4,16>"),
-                   ("k_conv3_lds<16, 4, 16>", "k_conv3_lds<16,4,16>"),
-                   ("k_conv3_lds<8, 4, 16>", "k_conv3_lds<8,4,16>"),
-                   ("k_conv3_lds<80, 1, 16>", "k_conv3_lds<80,1,16>"),
+# (rocprofv3 name prefix once "void ", "mrs::" and the anonymous namespace are
+# dropped; short name)
+COUNTER_KERNELS = [("k_extend_wave", "k_extend_wave"), ("k_extend<false,", "k_extend"),
+                   ("k_shadow<false,", "k_shadow"), ("k_tail<false,", "k_tail"),
+                   ("k_shade", "k_shade"), ("k_res_block", "k_res_block"),
+                   ("k_conv3_lds<64, 4, 16, false>", "k_conv3_lds<64,4,16>"),
+                   ("k_conv3_lds<16, 4, 16, false>", "k_conv3_lds<16,4,16>"),
+                   ("k_conv3_lds<8, 4, 16, false>", "k_conv3_lds<8,4,16>"),
+                   ("k_conv3_lds<80, 1, 16, false>", "k_conv3_lds<80,1,16>"),
                    ("k_conv<4>", "k_conv<4>")]
+# the closest-hit launches bench.py times as "extend": bounce 0 a wave at a time,
+# the other wavefront bounces lane by lane (k_extend<true, ..> is the counting pass)
+EXTEND_KERNELS = ("k_extend_wave", "k_extend<false,")
+
+
+def is_extend(name):
+    n = name.replace("void ", "").replace("(anonymous namespace)::", "").replace("mrs::", "")
+    return any(n.startswith(pre) for pre in EXTEND_KERNELS)
 
 
 def counter_source_hash() -> str:
@@ -330,8 +343,8 @@ def stats_summary(prof_dir, out_path):
     lines = ["# 720p hybrid frame (procedural 101,446 triangles, textured; HRLS 1280x720@4 + LRHS "
              "320x180@64 as one two-job batch, depth 8; BF16 fusion network): 1 counting frame "
              "(k_*<true>) + 1 warmup + 5 timed frames, pipelined, then the network 5 times "
-             "alone (k_extend<false>: the launches of the warmup and timed frames, whose "
-             "extend average bench.py reports)",
+             "alone (k_extend_wave and k_extend<false, false>: the launches of the warmup and "
+             "timed frames, whose extend average bench.py reports)",
              f"# command (from the repository root): {STATS_CMD}",
              "#   then: python bench.py --stats-summary gpurun_out/prof",
              "# rocprofv3 kernel stats: name | calls | total ms | average us | percent", ""]
@@ -339,6 +352,13 @@ def stats_summary(prof_dir, out_path):
         lines.append(f"{short(r['Name']):34s} | {int(r['Calls']):5d} | "
                      f"{int(r['TotalDurationNs']) / 1e6:9.3f} | {float(r['AverageNs']) / 1e3:10.2f} | "
                      f"{float(r['Percentage']):6.2f}")
+    ext = [r for r in rows if is_extend(r["Name"])]
+    if ext:
+        calls = sum(int(r["Calls"]) for r in ext)
+        tot = sum(int(r["TotalDurationNs"]) for r in ext)
+        lines += ["", "# the launches bench.py's roofline averages (k_extend_wave + k_extend<false, false>):",
+                  f"{'extend (all timed launches)':34s} | {calls:5d} | {tot / 1e6:9.3f} | "
+                  f"{tot / max(calls, 1) / 1e3:10.2f} |"]
     with open(out_path, "w") as f:
         f.write("\n".join(lines) + "\n")
     print("\n".join(lines))
@@ -1098,9 +1118,9 @@ def main():
     # hardware counters of the committed profile, if it belongs to these kernel sources
     ctr = read_counters()
     roofline["counters"] = None if ctr is None else {
-        k: ctr[k] for k in ("k_extend", "k_shadow", "k_tail") if k in ctr}
+        k: ctr[k] for k in ("k_extend_wave", "k_extend", "k_shadow", "k_tail") if k in ctr}
     cnn_roof["counters"] = None if ctr is None else {
-        k: ctr[k] for k in ctr if k.startswith("k_conv")}
+        k: ctr[k] for k in ctr if k.startswith("k_conv") or k == "k_res_block"}
     kernel_ms = {k: round(v[0] / args.steps, 4) for k, v in prof.items()}
     result = {
         "metric": METRIC, "value": round(value, 3), "unit": "Mpaths/s", "n_gpus": 1,
