@@ -878,22 +878,25 @@ struct ExtendIO {
   }
 };
 
-// Static schedule: lane sequences gtid, gtid + threads, ...  Dynamic: a wave
-// takes 64 consecutive entries per fetch from a device counter.
-template <int MODE, bool COUNT, bool Q, class IO>
-__device__ __forceinline__ void trace_queue(IO& io, uint32_t n, int dyn, uint32_t* fetch,
-                                            Stack& st, WorkCount& wc) {
-  if (!dyn) {
+// SCHED 0, static: lane sequences gtid, gtid + threads, ...  1, dynamic: a wave
+// takes 64 consecutive entries per fetch from a device counter.  One
+// instantiation per schedule, so that each kernel holds only its own queue code
+// (fewer registers for the static one).
+template <int MODE, bool COUNT, bool Q, int SCHED, class IO>
+__device__ __forceinline__ void trace_queue(IO& io, uint32_t n, uint32_t* fetch, Stack& st,
+                                            WorkCount& wc) {
+  if (SCHED == 0) {
     trace_stream<MODE, COUNT, Q>(io, blockIdx.x * TB + threadIdx.x, gridDim.x * TB, n, st, wc);
-    return;
+  } else {
+    WaveQueue wq(fetch, true);
+    for (; wq.base < n; wq.next())
+      trace_stream<MODE, COUNT, Q>(io, wq.base + __lane_id(), 64u, min(n, wq.base + 64u), st,
+                                   wc);
   }
-  WaveQueue wq(fetch, true);
-  for (; wq.base < n; wq.next())
-    trace_stream<MODE, COUNT, Q>(io, wq.base + __lane_id(), 64u, min(n, wq.base + 64u), st, wc);
 }
 
-template <bool COUNT, bool Q>
-__global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(7))) void k_extend(const DevJob* __restrict__ jobs, int b, int dyn,
+template <bool COUNT, bool Q, int SCHED>
+__global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(7))) void k_extend(const DevJob* __restrict__ jobs, int b,
                                                const float4* __restrict__ rays,
                                                uint32_t* __restrict__ q,
                                                float4* __restrict__ hits,
@@ -905,7 +908,7 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(7))) void k_
   Stack st{(lds_u32*)stk + threadIdx.x, spill + gtid, gridDim.x * TB, 0, 0u, false};
   WorkCount wc;
   ExtendIO io{jobs, rays, hits};
-  trace_queue<CLOSEST, COUNT, Q>(io, n, dyn, q + Q_FETCH_EXT + b, st, wc);
+  trace_queue<CLOSEST, COUNT, Q, SCHED>(io, n, q + Q_FETCH_EXT + b, st, wc);
   if (st.spills) atomicAdd(stats + 3, (unsigned long long)st.spills);
   if (st.overflow) atomicAdd(stats + 5, 1ull);
   if (COUNT && wc.visits) atomicAdd(stats + 6, (unsigned long long)wc.visits);
@@ -1233,8 +1236,8 @@ struct ShadowIO {
   }
 };
 
-template <bool COUNT, bool Q>
-__global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(7))) void k_shadow(const DevJob* __restrict__ jobs, int b, int dyn,
+template <bool COUNT, bool Q, int SCHED>
+__global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(7))) void k_shadow(const DevJob* __restrict__ jobs, int b,
                                                const float4* __restrict__ shadow,
                                                uint32_t* __restrict__ q,
                                                float4* __restrict__ L_buf,
@@ -1246,7 +1249,7 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(7))) void k_
   Stack st{(lds_u32*)stk + threadIdx.x, spill + gtid, gridDim.x * TB, 0, 0u, false};
   WorkCount wc;
   ShadowIO io{jobs, shadow, L_buf};
-  trace_queue<ANY_HIT, COUNT, Q>(io, n, dyn, q + Q_FETCH_SHD + b, st, wc);
+  trace_queue<ANY_HIT, COUNT, Q, SCHED>(io, n, q + Q_FETCH_SHD + b, st, wc);
   if (st.spills) atomicAdd(stats + 3, (unsigned long long)st.spills);
   if (st.overflow) atomicAdd(stats + 5, 1ull);
   if (COUNT && wc.visits) atomicAdd(stats + 8, (unsigned long long)wc.visits);
@@ -1864,6 +1867,16 @@ mrs_status sum_chunk(Workspace& ws, const DevJob* d_jobs, const std::vector<DevJ
   return MRS_OK;
 }
 
+// The traversal kernels of a queue schedule (mrs_tuning.schedule).
+template <bool COUNT, bool Q>
+auto extend_kernel(int sched) {
+  return sched == 1 ? k_extend<COUNT, Q, 1> : k_extend<COUNT, Q, 0>;
+}
+template <bool COUNT, bool Q>
+auto shadow_kernel(int sched) {
+  return sched == 1 ? k_shadow<COUNT, Q, 1> : k_shadow<COUNT, Q, 0>;
+}
+
 // The launch sequence of a batch whose job table is on the device: chunks of at
 // most chunk_paths paths over the concatenated path space; per chunk, generate,
 // then extend / shade / shadow per bounce, then accumulate; finally resolve.
@@ -1932,9 +1945,9 @@ mrs_status begin_batch(Workspace& ws, const mrs_tuning& tu, const DevJob* d_jobs
         if (!count && b < tu.wave_extend) {
           k_extend_wave<<<u.gb, TB, 0, u.s>>>(d_jobs, b, dyn, u.rays[b & 1], u.q, u.hits, stats);
         } else {
-          auto ext = count ? (qn ? k_extend<true, true> : k_extend<true, false>)
-                           : (qn ? k_extend<false, true> : k_extend<false, false>);
-          ext<<<u.gb, TB, 0, u.s>>>(d_jobs, b, dyn, u.rays[b & 1], u.q, u.hits, u.spill, stats);
+          auto ext = count ? (qn ? extend_kernel<true, true>(dyn) : extend_kernel<true, false>(dyn))
+                           : (qn ? extend_kernel<false, true>(dyn) : extend_kernel<false, false>(dyn));
+          ext<<<u.gb, TB, 0, u.s>>>(d_jobs, b, u.rays[b & 1], u.q, u.hits, u.spill, stats);
         }
         prof_end(KID_EXTEND, u.s);
       }
@@ -1958,9 +1971,9 @@ mrs_status begin_batch(Workspace& ws, const mrs_tuning& tu, const DevJob* d_jobs
           if (!count && b < tu.wave_shadow) {
             k_shadow_wave<<<u.gb, TB, 0, u.s>>>(d_jobs, b, dyn, u.shadow, u.q, u.L, stats);
           } else {
-            auto shd = count ? (qn ? k_shadow<true, true> : k_shadow<true, false>)
-                             : (qn ? k_shadow<false, true> : k_shadow<false, false>);
-            shd<<<u.gb, TB, 0, u.s>>>(d_jobs, b, dyn, u.shadow, u.q, u.L, u.spill, stats);
+            auto shd = count ? (qn ? shadow_kernel<true, true>(dyn) : shadow_kernel<true, false>(dyn))
+                             : (qn ? shadow_kernel<false, true>(dyn) : shadow_kernel<false, false>(dyn));
+            shd<<<u.gb, TB, 0, u.s>>>(d_jobs, b, u.shadow, u.q, u.L, u.spill, stats);
           }
           prof_end(KID_SHADOW, u.s);
         }

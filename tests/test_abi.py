@@ -69,11 +69,15 @@ def test_tuning_validation():
     assert (t.chunk_paths, t.trace_blocks, t.schedule, t.bvh_leaf_max, t.streams,
             t.tail_bounce, t.bvh_builder) == (1 << 23, 8192, 0, 3, 3, 3, 1)
     for bad in (_lib.Tuning(1, 10, 0, 4, 1, 3), _lib.Tuning(1 << 22, 0, 0, 4, 1, 3),
-                _lib.Tuning(1 << 22, 2048, 2, 4, 1, 3), _lib.Tuning(1 << 22, 2048, 0, 0, 1, 3),
+                _lib.Tuning(1 << 22, 2048, 2, 4, 1, 3), _lib.Tuning(1 << 22, 2048, -1, 4, 1, 3),
+                _lib.Tuning(1 << 22, 2048, 0, 0, 1, 3),
                 _lib.Tuning(1 << 22, 2048, 0, 5, 1, 3), _lib.Tuning(1 << 22, 2048, 0, 4, 0, 3),
                 _lib.Tuning(1 << 22, 2048, 0, 4, 5, 3), _lib.Tuning(1 << 22, 2048, 0, 4, 1, 0),
                 _lib.Tuning(1 << 22, 2048, 0, 4, 1, 66), _lib.Tuning(1 << 22, 2048, 0, 4, 1, 3, 2),
-                _lib.Tuning(1 << 22, 2048, 0, 4, 1, 3, -1)):
+                _lib.Tuning(1 << 22, 2048, 0, 4, 1, 3, -1),
+                _lib.Tuning(1 << 22, 2048, 0, 4, 1, 3, 1, 0, 0, 0, 66),
+                _lib.Tuning(1 << 22, 2048, 0, 4, 1, 3, 1, 0, 0, 0, 0, -1),
+                _lib.Tuning(1 << 22, 2048, 0, 4, 1, 3, 1, 0, 0, 0, 0, 0, 2)):
         assert L.mrs_set_tuning(C.byref(bad)) == 1
     assert L.mrs_set_tuning(C.byref(t)) == 0
 
