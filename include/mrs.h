@@ -362,8 +362,9 @@ typedef struct mrs_tuning {
   int32_t wave_shadow;  /* 0..65 (default 0): the same for shadow rays */
   int32_t net_fused_blocks; /* 1 (default): each residual block of the 16-block
                            network's trunk runs as one kernel (both convs, the
-                           intermediate kept in LDS); 0: two conv launches.
-                           Bitwise the same */
+                           intermediate kept in LDS) when the LR image has at
+                           least conv_small_tiles 16x16 tiles; 0: two conv
+                           launches.  Bitwise the same */
 } mrs_tuning;
 mrs_status mrs_get_tuning(mrs_tuning* out);
 mrs_status mrs_set_tuning(const mrs_tuning* t);

@@ -270,8 +270,11 @@ mrs_status net_forward(mrs_net* net, int B, int H, int W, const float* hr, const
     bb.out_h = A.rh[i & 1];
     bb.out_h_stride = NET_FEAT;
     // both convs in one launch (bitwise the same), or one after the other
-    // through the BF16 intermediate A.th
-    if (!(net_fused_blocks() && launch_res_block(a, bb, st))) {
+    // through the BF16 intermediate A.th; small images (fewer 16x16 tiles than
+    // the small-tile threshold) keep the two convs, whose small-tile plan
+    // spreads them over more blocks
+    const int64_t tiles = (int64_t)B * ((h + 15) / 16) * ((w + 15) / 16);
+    if (!(net_fused_blocks() && tiles >= conv_small_tiles() && launch_res_block(a, bb, st))) {
       launch_conv(a, La.cout_p, st);
       launch_conv(bb, Lb.cout_p, st);
     }

@@ -130,8 +130,9 @@ def test_forward_parity_large_tile_plan(net, tuning_restored, B, H, W, small):
     ran = conv_launches(reset=True)
     assert ran["lds64_small"] == 33 and ran["lds64_large"] == 0, ran
     assert torch.equal(out_small, out)
-    # each residual block as one kernel: the same sums, bitwise
-    mrs.set_tuning(net_fused_blocks=1)
+    # each residual block as one kernel: the same sums, bitwise (fused at any
+    # tile count once the small-tile threshold is 0)
+    mrs.set_tuning(net_fused_blocks=1, conv_small_tiles=0)
     out_fused = net.fuse(*t)
     torch.cuda.synchronize()
     ran = conv_launches(reset=True)
