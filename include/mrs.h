@@ -335,7 +335,7 @@ typedef struct mrs_tuning {
                            this many sub-chunks, traced concurrently on internal
                            streams shared by the library (joined back into the
                            caller's stream before the per-pixel sums) */
-  int32_t tail_bounce;  /* 1..65 (default 4): bounces from this one on are traced
+  int32_t tail_bounce;  /* 1..65 (default 3): bounces from this one on are traced
                            path by path in one launch (65: never) */
   int32_t bvh_builder;  /* MRS_BVH_PLOC (default) or MRS_BVH_LBVH; applies to
                            scenes built afterwards */

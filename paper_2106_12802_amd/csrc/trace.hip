@@ -1706,7 +1706,7 @@ hipStream_t g_sub[MAX_SUB] = {};
 int g_nsub = 0;
 unsigned long long* g_stats = nullptr;  // device counters shared by every stream
 // defaults: the fastest hybrid 720p frame measured with the clustered BVH
-mrs_tuning g_tune = {1 << 23, 8192, 0, 3, 3, 4, MRS_BVH_PLOC, 128, 1, 0, 1, 0, 1};
+mrs_tuning g_tune = {1 << 23, 8192, 0, 3, 3, 3, MRS_BVH_PLOC, 128, 1, 0, 1, 0, 1};
 std::atomic<int> g_conv_small{128};  // g_tune.conv_small_tiles, read without the lock
 std::atomic<int> g_net_fused{1};      // g_tune.net_fused_blocks, read without the lock
 std::atomic<bool> g_count_work{false};

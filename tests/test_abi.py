@@ -67,7 +67,7 @@ def test_tuning_validation():
     t = _lib.Tuning()
     assert L.mrs_get_tuning(C.byref(t)) == 0
     assert (t.chunk_paths, t.trace_blocks, t.schedule, t.bvh_leaf_max, t.streams,
-            t.tail_bounce, t.bvh_builder) == (1 << 23, 8192, 0, 3, 3, 4, 1)
+            t.tail_bounce, t.bvh_builder) == (1 << 23, 8192, 0, 3, 3, 3, 1)
     for bad in (_lib.Tuning(1, 10, 0, 4, 1, 3), _lib.Tuning(1 << 22, 0, 0, 4, 1, 3),
                 _lib.Tuning(1 << 22, 2048, 2, 4, 1, 3), _lib.Tuning(1 << 22, 2048, -1, 4, 1, 3),
                 _lib.Tuning(1 << 22, 2048, 0, 0, 1, 3),
