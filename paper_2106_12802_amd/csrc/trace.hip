@@ -794,13 +794,13 @@ __global__ __launch_bounds__(256) void k_reset(uint32_t* q, uint32_t n) {
   for (int i = threadIdx.x; i < Q_WORDS; i += blockDim.x) q[i] = (i == Q_RAYS) ? n : 0u;
 }
 
-__global__ __launch_bounds__(256) void k_generate(const DevJob* __restrict__ jobs, int njobs,
-                                                  int64_t g0, uint32_t n,
-                                                  float4* __restrict__ rays) {
-  const uint32_t slot = blockIdx.x * 256 + threadIdx.x;
-  if (slot >= n) return;
-  const int64_t g = g0 + slot;
-  const uint32_t j = find_job(jobs, njobs, g);
+// The camera ray of global path g: its job j, origin o and direction d.
+// k_generate stores it; the bounce-0 kernels that skip the stored queue
+// (wave traversal and shading, when generation is fused into them) call the
+// same function, so every path starts from bitwise the same ray.
+__device__ __forceinline__ void camera_ray(const DevJob* __restrict__ jobs, int njobs, int64_t g,
+                                           uint32_t& j, f3& o, f3& d) {
+  j = find_job(jobs, njobs, g);
   const DevJob& J = jobs[j];
   const SceneView& sc = J.sv;
   uint32_t P, s;
@@ -814,8 +814,8 @@ __global__ __launch_bounds__(256) void k_generate(const DevJob* __restrict__ job
   const float cy = (1.0f - 2.0f * sy) * sc.cam_tan_half;
   const f3 f = F3(sc.cam_fx, sc.cam_fy, sc.cam_fz), rr = F3(sc.cam_rx, sc.cam_ry, sc.cam_rz),
            vv = F3(sc.cam_vx, sc.cam_vy, sc.cam_vz);
-  f3 d = normalize(f + rr * cx + vv * cy);
-  f3 o = F3(sc.cam_px, sc.cam_py, sc.cam_pz);
+  d = normalize(f + rr * cx + vv * cy);
+  o = F3(sc.cam_px, sc.cam_py, sc.cam_pz);
   // camera effects: translation over the shutter (time from its own Philox
   // block), thin lens (lens sample from words 2, 3, aimed at the point where
   // the pinhole ray meets the focal plane)
@@ -832,6 +832,16 @@ __global__ __launch_bounds__(256) void k_generate(const DevJob* __restrict__ job
     o = o + rr * (rho * cp) + vv * (rho * sp);
     d = normalize(Fp - o);
   }
+}
+
+__global__ __launch_bounds__(256) void k_generate(const DevJob* __restrict__ jobs, int njobs,
+                                                  int64_t g0, uint32_t n,
+                                                  float4* __restrict__ rays) {
+  const uint32_t slot = blockIdx.x * 256 + threadIdx.x;
+  if (slot >= n) return;
+  uint32_t j;
+  f3 o, d;
+  camera_ray(jobs, njobs, g0 + slot, j, o, d);
   rays[2 * slot] = make_float4(o.x, o.y, o.z, __uint_as_float(slot));
   rays[2 * slot + 1] = make_float4(d.x, d.y, d.z, __uint_as_float((j << 24) | PRIM24));
 }
@@ -856,11 +866,25 @@ struct WaveQueue {
   __device__ __forceinline__ void next() { base = dyn ? fetch() : base + step; }
 };
 
+// GEN: bounce 0 with generation fused in -- queue entry qi is path slot qi and
+// its camera ray is computed here instead of read from the queue.
+template <bool GEN = false>
 struct ExtendIO {
   const DevJob* __restrict__ jobs;
   const float4* __restrict__ rays;
   float4* __restrict__ hits;
+  int njobs = 0;
+  int64_t g0 = 0;
   __device__ __forceinline__ void load(uint32_t qi, RayIn& r) const {
+    r.x1 = r.x2 = NO_PRIM;
+    r.tmax = INFINITY;
+    r.any = false;
+    if (GEN) {
+      camera_ray(jobs, njobs, g0 + qi, r.job, r.o, r.d);
+      r.sc = lane_view(jobs[r.job].sv);
+      r.x0 = NO_PRIM;
+      return;
+    }
     const float4 R0 = rays[2 * qi], R1 = rays[2 * qi + 1];
     const uint32_t tag = __float_as_uint(R1.w);
     r.job = job_of(tag);
@@ -868,9 +892,6 @@ struct ExtendIO {
     r.o = xyz(R0);
     r.d = xyz(R1);
     r.x0 = unpack_prim(tag);
-    r.x1 = r.x2 = NO_PRIM;
-    r.tmax = INFINITY;
-    r.any = false;
   }
   __device__ __forceinline__ bool store(uint32_t qi, const TraceState& ts, bool, RayIn&) const {
     hits[qi] = make_float4(ts.t, __uint_as_float(ts.prim), ts.b1, ts.b2);
@@ -907,7 +928,7 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(7))) void k_
   const uint32_t gtid = blockIdx.x * TB + threadIdx.x;
   Stack st{(lds_u32*)stk + threadIdx.x, spill + gtid, gridDim.x * TB, 0, 0u, false};
   WorkCount wc;
-  ExtendIO io{jobs, rays, hits};
+  ExtendIO<> io{jobs, rays, hits};
   trace_queue<CLOSEST, COUNT, Q, SCHED>(io, n, q + Q_FETCH_EXT + b, st, wc);
   if (st.spills) atomicAdd(stats + 3, (unsigned long long)st.spills);
   if (st.overflow) atomicAdd(stats + 5, 1ull);
@@ -1142,8 +1163,11 @@ __device__ __forceinline__ void shade_vertex(const DevJob& J, int64_t g, int b, 
   v.L = L;
 }
 
-template <bool SORT>
-__global__ __launch_bounds__(256) void k_shade(const DevJob* __restrict__ jobs, int64_t g0, int b,
+// GEN: bounce 0 with generation fused in (queue entry qi is path slot qi; its
+// camera ray is recomputed rather than read from the queue).
+template <bool SORT, bool GEN>
+__global__ __launch_bounds__(256) void k_shade(const DevJob* __restrict__ jobs, int njobs,
+                                               int64_t g0, int b,
                                                const float4* __restrict__ rays_in,
                                                const float4* __restrict__ hits,
                                                uint32_t* __restrict__ q,
@@ -1166,15 +1190,23 @@ __global__ __launch_bounds__(256) void k_shade(const DevJob* __restrict__ jobs, 
     v.wi = F3(0.0f, 0.0f, 0.0f);
     uint32_t slot = 0, j = 0;
     if (qi < n) {
-      const float4 R0 = rays_in[2 * qi], R1 = rays_in[2 * qi + 1];
-      slot = __float_as_uint(R0.w);
-      j = job_of(__float_as_uint(R1.w));
+      f3 o, d;
+      if (GEN) {
+        slot = qi;
+        camera_ray(jobs, njobs, g0 + qi, j, o, d);
+      } else {
+        const float4 R0 = rays_in[2 * qi], R1 = rays_in[2 * qi + 1];
+        slot = __float_as_uint(R0.w);
+        j = job_of(__float_as_uint(R1.w));
+        o = xyz(R0);
+        d = xyz(R1);
+      }
       // a path starts with beta = 1, L = 0 and zero features (nothing is stored
       // for it before its first vertex)
       const float4 Bt = b == 0 ? make_float4(1.0f, 1.0f, 1.0f, 0.0f) : beta_buf[slot];
       const f3 L = b == 0 ? F3(0.0f, 0.0f, 0.0f) : xyz(L_buf[slot]);
       // first-hit features only for jobs that output them
-      shade_vertex(jobs[j], g0 + slot, b, xyz(R0), xyz(R1), hits[qi], xyz(Bt), L, Bt.w,
+      shade_vertex(jobs[j], g0 + slot, b, o, d, hits[qi], xyz(Bt), L, Bt.w,
                    (b == 0 && jobs[j].out_aux) ? aux_buf + 2 * slot : nullptr, v);
       if (v.cont) beta_buf[slot] = make_float4(v.beta.x, v.beta.y, v.beta.z, v.pdf);
       L_buf[slot] = make_float4(v.L.x, v.L.y, v.L.z, 0.0f);
@@ -1261,13 +1293,15 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(7))) void k_
 // a wave takes 64 consecutive queue entries at a time, grid-stride or (dyn)
 // from the device counter.  Same inputs, outputs and results as k_extend and
 // k_shadow.
-__global__ __launch_bounds__(TB) void k_extend_wave(const DevJob* __restrict__ jobs, int b,
-                                                    int dyn, const float4* __restrict__ rays,
+template <bool GEN>
+__global__ __launch_bounds__(TB) void k_extend_wave(const DevJob* __restrict__ jobs, int njobs,
+                                                    int64_t g0, int b, int dyn,
+                                                    const float4* __restrict__ rays,
                                                     uint32_t* __restrict__ q,
                                                     float4* __restrict__ hits,
                                                     unsigned long long* __restrict__ stats) {
   const uint32_t n = q[Q_RAYS + b];
-  ExtendIO io{jobs, rays, hits};
+  ExtendIO<GEN> io{jobs, rays, hits, njobs, g0};
   WaveStack ws{};
   for (WaveQueue wq(q + Q_FETCH_EXT + b, dyn != 0); wq.base < n; wq.next())
     trace_wave<false>(io, wq.base, n, ws);
@@ -1898,6 +1932,9 @@ mrs_status begin_batch(Workspace& ws, const mrs_tuning& tu, const DevJob* d_jobs
   const int dyn = tu.schedule;
   const bool qn = tu.bvh_quantized != 0;
   const bool count = g_count_work.load();
+  // bounce 0 by the wave traversal: camera rays are computed where they are
+  // used (wave traversal, shading) and never stored
+  const bool gen_fused = !count && tu.wave_extend > 0;
   unsigned long long* stats = ws.stats;
   const size_t spill_k = (size_t)P.blocks_k * TB * (MAX_STACK4 - LDS_STACK);
   const bool forked = ws.forked && ws.fork_st == st;
@@ -1934,16 +1971,19 @@ mrs_status begin_batch(Workspace& ws, const mrs_tuning& tu, const DevJob* d_jobs
       Sub& u = sub[k];
       if (P.K > 1) MRS_TRY_HIP(hipStreamWaitEvent(u.s, ws.ev_fork, 0));
       k_reset<<<1, 256, 0, u.s>>>(u.q, u.n);
-      prof_begin(KID_GENERATE, u.s);
-      k_generate<<<cdiv(u.n, 256), 256, 0, u.s>>>(d_jobs, nj, u.lo, u.n, u.rays[0]);
-      prof_end(KID_GENERATE, u.s);
+      if (!gen_fused) {
+        prof_begin(KID_GENERATE, u.s);
+        k_generate<<<cdiv(u.n, 256), 256, 0, u.s>>>(d_jobs, nj, u.lo, u.n, u.rays[0]);
+        prof_end(KID_GENERATE, u.s);
+      }
     }
     for (int b = 0; b < nwave; ++b) {
       for (int k = 0; k < used; ++k) {
         Sub& u = sub[k];
         prof_begin(KID_EXTEND, u.s);
         if (!count && b < tu.wave_extend) {
-          k_extend_wave<<<u.gb, TB, 0, u.s>>>(d_jobs, b, dyn, u.rays[b & 1], u.q, u.hits, stats);
+          auto wext = b == 0 && gen_fused ? k_extend_wave<true> : k_extend_wave<false>;
+          wext<<<u.gb, TB, 0, u.s>>>(d_jobs, nj, u.lo, b, dyn, u.rays[b & 1], u.q, u.hits, stats);
         } else {
           auto ext = count ? (qn ? extend_kernel<true, true>(dyn) : extend_kernel<true, false>(dyn))
                            : (qn ? extend_kernel<false, true>(dyn) : extend_kernel<false, false>(dyn));
@@ -1954,14 +1994,11 @@ mrs_status begin_batch(Workspace& ws, const mrs_tuning& tu, const DevJob* d_jobs
       for (int k = 0; k < used; ++k) {
         Sub& u = sub[k];
         prof_begin(KID_SHADE, u.s);
-        if (tu.queue_sort)
-          k_shade<true><<<u.gb, 256, 0, u.s>>>(d_jobs, u.lo, b, u.rays[b & 1], u.hits, u.q,
-                                               u.rays[(b + 1) & 1], u.shadow, u.beta, u.L,
-                                               u.aux, u.lay);
-        else
-          k_shade<false><<<u.gb, 256, 0, u.s>>>(d_jobs, u.lo, b, u.rays[b & 1], u.hits, u.q,
-                                                u.rays[(b + 1) & 1], u.shadow, u.beta, u.L,
-                                                u.aux, u.lay);
+        const bool gen = b == 0 && gen_fused;
+        auto shd = tu.queue_sort ? (gen ? k_shade<true, true> : k_shade<true, false>)
+                                 : (gen ? k_shade<false, true> : k_shade<false, false>);
+        shd<<<u.gb, 256, 0, u.s>>>(d_jobs, nj, u.lo, b, u.rays[b & 1], u.hits, u.q,
+                                   u.rays[(b + 1) & 1], u.shadow, u.beta, u.L, u.aux, u.lay);
         prof_end(KID_SHADE, u.s);
       }
       if (b < max_depth) {

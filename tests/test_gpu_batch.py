@@ -424,11 +424,15 @@ def test_pipelined_frames_equal_single_frames(torch_cuda, in_flight):
 
 def test_profile_records_selected_kernels(torch_cuda):
     """HIP-event kernel timing: every launch by default, only the selected kernels
-    after profile_select; the counts follow the launch structure of a render."""
+    after profile_select; the counts follow the launch structure of a render.  With
+    bounce 0 on the wave traversal (the default) camera rays are generated inside
+    the bounce-0 kernels, so no generate launch is recorded; with the lane-by-lane
+    traversal at bounce 0 the generate kernel runs."""
     import paper_2106_12802_amd as mrs
     from paper_2106_12802_amd import tracer as R
     torch = torch_cuda
     gs = mrs.GpuScene(S.procedural(7, spheres=((2, 4),), n_boxes=5, n_lights=2))
+    old = mrs.get_tuning()
     try:
         R.profile_select(None)
         R.profile_enable(True)
@@ -438,12 +442,20 @@ def test_profile_records_selected_kernels(torch_cuda):
         R.profile_enable(True)
         mrs.render(gs, 128, 96, 4, 8, 3)
         only = R.profile_read()
+        mrs.set_tuning(wave_extend=0)
+        R.profile_select(None)
+        R.profile_enable(True)
+        mrs.render(gs, 128, 96, 4, 8, 3)
+        lane0 = R.profile_read()
     finally:
         R.profile_enable(False)
         R.profile_select(None)
+        mrs.set_tuning(**old)
     torch.cuda.synchronize()
     assert set(only) == {"extend"}
     assert only["extend"][1] == everything["extend"][1] > 0
-    assert {"generate", "extend", "shade", "shadow", "accumulate", "resolve"} <= set(everything)
+    assert old["wave_extend"] > 0 and "generate" not in everything
+    assert {"extend", "shade", "shadow", "accumulate", "resolve"} <= set(everything)
+    assert {"generate", "extend", "shade", "shadow", "accumulate", "resolve"} <= set(lane0)
     with pytest.raises(ValueError):
         R.profile_select(["no_such_kernel"])
