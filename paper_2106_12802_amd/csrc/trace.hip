@@ -3,8 +3,13 @@
 //
 // A chunk of paths -- contiguous (sample, pixel) pairs -- is advanced one
 // bounce at a time by separate kernels:
-//   generate   camera rays (the path state starts at its first shade) (per path)
-//   extend     closest-hit LBVH traversal, LDS short stack      (per live ray)
+//   generate   camera rays (the path state starts at its first shade); skipped
+//              when bounce 0 runs the wave traversal, whose kernels compute
+//              each camera ray where they need it                 (per path)
+//   extend     closest-hit traversal of the BVH4: a wave at a time for the
+//              coherent camera rays (scalar node loads, wave-uniform stack),
+//              lane by lane for the later bounces (streaming lanes, LDS short
+//              stack with a global spill)                     (per live ray)
 //   shade      emission, first-hit features, next-event estimation sample,
 //              BSDF sample, Russian roulette; appends the surviving rays and
 //              the shadow rays to dense queues with one atomic per queue per
@@ -12,11 +17,12 @@
 //              over the block's waves)                          (per live ray)
 //   shadow     any-hit traversal; an unoccluded sample adds its contribution
 //              to its own path's radiance                       (per shadow ray)
+//   tail       the bounces from tail_bounce on, path by path in one launch
 //   accumulate per-pixel sums in sample order                   (per pixel)
 // Queue sizes stay on the device, so the host enqueues a fixed sequence of
 // launches with no read-back.  Each path owns its state slot, and each pixel
 // sums its samples in order, so results do not depend on queue order, chunk
-// size or grid size.
+// size, grid size or traversal kind.
 #include <algorithm>
 #include <atomic>
 #include <cstring>
@@ -1912,8 +1918,9 @@ auto shadow_kernel(int sched) {
 }
 
 // The launch sequence of a batch whose job table is on the device: chunks of at
-// most chunk_paths paths over the concatenated path space; per chunk, generate,
-// then extend / shade / shadow per bounce, then accumulate; finally resolve.
+// most chunk_paths paths over the concatenated path space; per chunk, generate
+// (unless bounce 0 computes the camera rays itself), then extend / shade /
+// shadow per bounce, then accumulate; finally resolve.
 // This enqueues everything but the last super-chunk's sums and the resolve,
 // which end_batch enqueues (render_batch does both).
 mrs_status begin_batch(Workspace& ws, const mrs_tuning& tu, const DevJob* d_jobs,
@@ -2369,7 +2376,9 @@ mrs_status batch_render_end(mrs_batch* b, hipStream_t st) {
 }
 
 mrs_status batch_set_seeds(mrs_batch* b, const uint64_t* seeds, hipStream_t st) {
-  b->ws.forked = false;  // the generate kernels must see the new seeds
+  // a fork recorded before the new seeds would let the sub-chunk streams start
+  // without them: the next render records its own
+  b->ws.forked = false;
   SeedTable t;
   std::memset(&t, 0, sizeof t);
   t.n = (uint32_t)b->jobs.size();
