@@ -82,3 +82,24 @@ def test_camera_effects_invariances(mrs, torch_cuda):
     r2, _ = mrs.render(gs, 64, 64, 2, 5, 9)
     torch.cuda.synchronize()
     assert torch.equal(b.outputs[0][0], full) and torch.equal(b.outputs[1][0], r2)
+
+
+def test_camera_rays_computed_in_place_equal_stored(mrs, torch_cuda):
+    """With bounce 0 on the wave traversal the camera rays (lens and motion
+    included) are computed inside the bounce-0 kernels; with the lane-by-lane
+    traversal at bounce 0 they are stored by the generate kernel.  Both give
+    bitwise the same image and features."""
+    torch = torch_cuda
+    _log("camera rays computed in place vs stored")
+    gs = mrs.GpuScene(S.procedural(7, spheres=((2, 4),), n_boxes=5, n_lights=2))
+    fx = dict(lens_radius=0.1, focus_dist=8.0, cam_motion=(0.2, 0.1, 0.0))
+    old = mrs.get_tuning()
+    try:
+        mrs.set_tuning(wave_extend=1)
+        a, aa = mrs.render(gs, 160, 96, 4, 5, 8, **fx)
+        mrs.set_tuning(wave_extend=0)
+        b, ba = mrs.render(gs, 160, 96, 4, 5, 8, **fx)
+        torch.cuda.synchronize()
+    finally:
+        mrs.set_tuning(**old)
+    assert torch.equal(a, b) and torch.equal(aa, ba)
